@@ -1,0 +1,225 @@
+/*
+ * tn.h -- C interface of libtn, exact inference on probabilistic graphical
+ * models by tensor-network contraction on one MI355X (gfx950).
+ *
+ * The library contracts the network of factor tensors of a model along a
+ * binary contraction tree (paper: definition of a tensor network and
+ * eq. contraction-definition; contraction orders as binary trees).  Each tree
+ * node is one pairwise contraction executed by hand-written HIP kernels.
+ *
+ *   tn_logZ       probability of evidence / partition function (eq. pr),
+ *   tn_marginals  all single-variable marginals (eq. mar-prob) through the
+ *                 unity-vector adjoint pass (theorem thm:diff, eq. einback),
+ *   tn_map        most probable explanation by max-plus contraction
+ *                 (eq. tropical, eq. log-map) and argmax readout,
+ *   tn_mmap       maximum marginal a posteriori by the two-phase method
+ *                 (eq. mmap and the partition procedure after it),
+ *   tn_sample     unbiased samples by back-tracing the tree (eq. sample,
+ *                 eq. condition-prob).
+ *
+ * Conventions
+ *   - Every call returns a tn_status; no C++ exception crosses this
+ *     interface.  On a non-OK status the outputs are unspecified and
+ *     tn_last_error() returns a thread-local message.
+ *   - Input arrays are copied before the call returns; the caller keeps
+ *     ownership.  Host outputs are caller-allocated.  Pointers named *_dev
+ *     are device pointers owned by the caller (e.g. torch tensors); the
+ *     library never frees them.
+ *   - Variables are numbered 0..n_vars-1 with domain sizes card[v] >= 1.
+ *     A factor's table is row-major over its scope in the order given,
+ *     last variable fastest.
+ *   - Evidence arrays hold one int32 per variable: -1 = unobserved,
+ *     otherwise the observed value (0 <= e < card).
+ *   - A plan owns device memory and one HIP stream (its own, or one the
+ *     caller lends); calls on one plan are not re-entrant.  Different plans
+ *     may be used from different threads.
+ */
+#ifndef TN_H
+#define TN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tn_net tn_net;
+typedef struct tn_plan_impl tn_plan_t;  /* created by tn_plan() */
+
+typedef enum {
+  TN_OK = 0,
+  TN_E_INVALID = 1,        /* malformed input (message says which) */
+  TN_E_NOMEM = 2,          /* host or device allocation failed */
+  TN_E_DEVICE = 3,         /* a HIP call failed */
+  TN_E_TOO_LARGE = 4,      /* an intermediate exceeds the size limits */
+  TN_E_ZERO_EVIDENCE = 5,  /* p(e) = 0 for some instance */
+  TN_E_UNSUPPORTED = 6     /* task not enabled in this plan / mode */
+} tn_status;
+
+typedef enum { TN_F32 = 0, TN_BF16 = 1, TN_F16 = 2 } tn_dtype;
+
+/* Semiring bits for tn_plan_opts.semiring_mask. */
+#define TN_SUM_PRODUCT 1   /* log Z, marginals, sampling */
+#define TN_MAX_PLUS 2      /* MAP */
+
+/* Evidence modes for tn_plan_opts.evidence_mode. */
+#define TN_EVIDENCE_NONE 0       /* no evidence; batch must be 1 */
+#define TN_EVIDENCE_SLICED 1     /* observed set fixed at plan time, values per
+                                    call; factors are sliced (paper: the sliced
+                                    tensor set of eq. pr) */
+#define TN_EVIDENCE_INDICATOR 2  /* per-instance observed sets; every variable
+                                    gets an indicator vector (one-hot when
+                                    observed) and instances run as one batch */
+
+/* Planner choices for tn_plan_opts.planner. */
+#define TN_PLANNER_BEST 0        /* best of all strategies below */
+#define TN_PLANNER_GREEDY 1      /* pairwise greedy on output size */
+#define TN_PLANNER_MINFILL 2     /* bucket elimination, min-fill order */
+#define TN_PLANNER_NATURAL 3     /* bucket elimination in variable-id order */
+#define TN_PLANNER_MINDEG 4      /* bucket elimination, min-degree order */
+
+typedef struct {
+  int32_t semiring_mask;     /* TN_SUM_PRODUCT | TN_MAX_PLUS */
+  int32_t evidence_mode;     /* TN_EVIDENCE_* */
+  const int32_t *observed;   /* mode SLICED: observed variable ids */
+  int32_t n_observed;
+  const int32_t *query;      /* MMAP max variables (Q); NULL if no MMAP */
+  int32_t n_query;
+  int32_t planner;           /* TN_PLANNER_* */
+  int32_t restarts;          /* randomised restarts per strategy */
+  uint64_t seed;             /* planner tie-break seed */
+  double max_log2_size;      /* slicing cap on log2(elements) of any
+                                intermediate; 0 = no slicing */
+  int32_t dtype;             /* tn_dtype of stored intermediates (sum-product) */
+  int32_t max_batch;         /* mode INDICATOR: instances per call */
+  int32_t use_graph;         /* capture each task's launches in a hipGraph */
+  void *hip_stream;          /* borrowed hipStream_t; NULL = library-owned */
+  const int32_t *tree_pairs; /* optional precomputed contraction tree:
+                                n_tree_pairs pairs (l, r) in post-order over
+                                the leaf ids described at tn_plan() */
+  int32_t n_tree_pairs;
+  int32_t want_factor_grad;  /* keep factor adjoints (tn_logZ_dev grads) */
+} tn_plan_opts;
+
+/* Summary of a plan (tn_plan_info). */
+typedef struct {
+  int32_t n_leaves, n_nodes;     /* main tree */
+  int32_t n_kernels_fwd;         /* launches of one sum-product forward */
+  int32_t n_kernels_bwd;         /* launches of the adjoint pass */
+  int32_t n_kernels_max;         /* launches of the max-plus pass */
+  double sc;                     /* log2 elements of the largest node output */
+  double sc_union;               /* log2 of the largest node label union */
+  double tc;                     /* log2 of sum over nodes of union sizes */
+  double flops_fwd;              /* algorithmic flops of one sum-product
+                                    forward: 2 x sum of union sizes, per instance */
+  double bytes_fwd;              /* algorithmic bytes of one forward */
+  int32_t n_sliced;              /* sliced labels */
+  int32_t planner_used;          /* TN_PLANNER_* that won */
+  int64_t device_bytes;          /* device memory held by the plan */
+} tn_plan_info;
+
+/* Fill *o with defaults: sum-product + max-plus, no evidence, best planner,
+ * 4 restarts, no slicing, FP32, batch 1, graphs on, own stream. */
+void tn_plan_opts_default(tn_plan_opts *o);
+
+/*
+ * Copy a factorised model.  scope_ptr has n_factors+1 entries (CSR into
+ * scope_vars); values are concatenated per factor (row-major over the scope
+ * order, last fastest), linear potentials >= 0 or, if values_are_log,
+ * log-potentials (finite or -inf).  Scope variables of one factor must be
+ * distinct.  Errors: TN_E_INVALID.
+ */
+tn_status tn_load_network(int32_t n_vars, const int32_t *card, int32_t n_factors,
+                          const int64_t *scope_ptr, const int32_t *scope_vars,
+                          const double *values, int32_t values_are_log, tn_net **out);
+void tn_free_network(tn_net *net);
+
+/*
+ * Build a plan: leaves, contraction tree, per-node kernel descriptors,
+ * device buffers.  Leaf ids (for tree_pairs): factors 0..n_factors-1 in
+ * load order, then one unity vector per variable in increasing id order --
+ * all variables for modes NONE and INDICATOR, only unobserved ones for mode
+ * SLICED.  (paper: MAR algorithm step 1 adds one unity tensor per query
+ * variable; with batched evidence it doubles as the evidence indicator.)
+ * With a query set, the plan holds the two MMAP phases instead.
+ * Errors: TN_E_INVALID (bad options or tree), TN_E_TOO_LARGE, TN_E_NOMEM,
+ * TN_E_DEVICE.
+ */
+tn_status tn_plan(const tn_net *net, const tn_plan_opts *opts, tn_plan_t **out);
+void tn_free_plan(tn_plan_t *plan);
+tn_status tn_plan_info_get(const tn_plan_t *plan, tn_plan_info *info);
+
+/* Copy the main contraction tree: writes up to cap pairs (post-order) and
+ * returns the count in *n_pairs and the leaf count in *n_leaves. */
+tn_status tn_plan_tree(const tn_plan_t *plan, int32_t *pairs, int32_t cap, int32_t *n_pairs,
+                       int32_t *n_leaves);
+
+/*
+ * Planning only (host, no device): contraction tree and complexity of the
+ * network under the given options, for inspection and testing.
+ * pairs: caller buffer of at least 2*(n_leaves-1) int32 (n_leaves as
+ * described at tn_plan); stats: optional.
+ */
+tn_status tn_plan_tree_host(const tn_net *net, const tn_plan_opts *opts, int32_t *pairs,
+                            int32_t cap, int32_t *n_pairs, int32_t *n_leaves,
+                            tn_plan_info *stats);
+
+/*
+ * log p(e) per instance (eq. pr).  evidence: [batch][n_vars] (may be NULL
+ * for mode NONE).  batch: 1 for modes NONE/SLICED (SLICED may pass several
+ * instances; they run one after another), <= max_batch for INDICATOR.
+ * logz: [batch] FP64.  TN_E_ZERO_EVIDENCE if some p(e) = 0.
+ */
+tn_status tn_logZ(tn_plan_t *plan, int32_t batch, const int32_t *evidence, double *logz);
+
+/*
+ * log p(e) and p(v = x | e) for every variable (eq. mar-prob via the
+ * adjoint pass of theorem thm:diff).  marg: [batch][sum_v card[v]] FP64,
+ * variable-major; observed variables get a one-hot row.
+ */
+tn_status tn_marginals(tn_plan_t *plan, int32_t batch, const int32_t *evidence, double *logz,
+                       double *marg);
+
+/*
+ * MPE (eq. log-map): assign [batch][n_vars] (evidence copied in), logp
+ * [batch] = max log p(x, e) as computed in FP32.  Ties keep the smallest
+ * row-major index over each node's eliminated variables (sorted by id).
+ */
+tn_status tn_map(tn_plan_t *plan, int32_t batch, const int32_t *evidence, int32_t *assign,
+                 double *logp);
+
+/*
+ * MMAP (eq. mmap) for the plan's query set: assign_q [n_query] in the
+ * order of the sorted query ids, log_value = max_q log sum_m p(q, m, e).
+ */
+tn_status tn_mmap(tn_plan_t *plan, const int32_t *evidence, int32_t *assign_q, double *log_value);
+
+/*
+ * n samples from p(x | e) (eq. sample / eq. condition-prob), Philox4x32-10
+ * uniforms with key = seed and counter (sample, node, slot).
+ * samples: [n][n_vars].
+ */
+tn_status tn_sample(tn_plan_t *plan, const int32_t *evidence, int64_t n, uint64_t seed,
+                    int32_t *samples);
+
+/*
+ * Device-side sum-product for differentiation (theorem thm:diff): factor
+ * tables come from values_dev (FP32, linear, laid out as in
+ * tn_load_network), log Z goes to logz_dev (FP64, one value), and if
+ * grad_dev is not NULL it receives d logZ / d T_f for every factor entry
+ * (FP32, same layout; requires want_factor_grad).  Modes NONE and SLICED
+ * (evidence as in tn_logZ, one instance).  Runs on the plan's stream.
+ */
+tn_status tn_logZ_dev(tn_plan_t *plan, const int32_t *evidence, const float *values_dev,
+                      double *logz_dev, float *grad_dev);
+
+/* Synchronise the plan's stream; TN_E_DEVICE on error. */
+tn_status tn_sync(tn_plan_t *plan);
+
+/* Thread-local message for the last non-OK status. */
+const char *tn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TN_H */

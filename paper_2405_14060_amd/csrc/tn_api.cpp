@@ -1,0 +1,1380 @@
+// libtn: C interface, plan construction and execution on one gfx950 GPU.
+//
+// A plan binds the model's leaves (factor tables, sliced by fixed evidence
+// -- paper eq. pr -- plus one unity / indicator vector per variable, the
+// auxiliary tensors of the MAR and MPE algorithms) to a binary contraction
+// tree, assigns every tensor a slice of one device arena, and lowers every
+// tree node to one launch of the generic contraction kernel:
+//   forward sum-product  C = sum over eliminated labels of A * B
+//   reverse pass         Abar = con(Cbar, B -> Va), Bbar = con(A, Cbar -> Vb)
+//                        (eq. einback; leaves' adjoints give the marginals)
+//   max-plus             private eliminated labels reduced first, then
+//                        C = max_K (A' + B') with argmax indices, read out
+//                        top-down (the tropical back-propagation of the MPE
+//                        algorithm, realised as argmax backtracking).
+// Every call's launches can be captured once into a hipGraph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+
+#include "tn_plan.h"
+
+using namespace tn;
+
+static thread_local std::string g_err;
+
+extern "C" const char *tn_last_error(void) { return g_err.c_str(); }
+
+template <class F>
+static tn_status guard(F &&f) {
+  try {
+    f();
+    return TN_OK;
+  } catch (const TnError &e) {
+    g_err = e.what();
+    return e.st;
+  } catch (const std::bad_alloc &) {
+    g_err = "host allocation failed";
+    return TN_E_NOMEM;
+  } catch (const std::exception &e) {
+    g_err = e.what();
+    return TN_E_INVALID;
+  }
+}
+
+static void hip_check(hipError_t e, const char *what) {
+  if (e != hipSuccess) {
+    if (e == hipErrorOutOfMemory) throw TnError(TN_E_NOMEM, std::string(what) + ": out of device memory");
+    throw TnError(TN_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// network
+// ---------------------------------------------------------------------------
+extern "C" tn_status tn_load_network(int32_t n_vars, const int32_t *card, int32_t n_factors,
+                                     const int64_t *scope_ptr, const int32_t *scope_vars,
+                                     const double *values, int32_t values_are_log, tn_net **out) {
+  return guard([&] {
+    if (!out) throw TnError(TN_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n_vars < 0 || n_factors < 0) throw TnError(TN_E_INVALID, "negative sizes");
+    if (n_vars > 0 && !card) throw TnError(TN_E_INVALID, "card is NULL");
+    if (n_factors > 0 && (!scope_ptr || !values)) throw TnError(TN_E_INVALID, "factor arrays are NULL");
+    auto net = std::make_unique<tn_net>();
+    net->n_vars = n_vars;
+    net->card.assign(card, card + n_vars);
+    for (int v = 0; v < n_vars; ++v)
+      if (card[v] < 1) throw TnError(TN_E_INVALID, "domain size of variable " + std::to_string(v) + " < 1");
+    net->is_log = values_are_log != 0;
+    if (n_factors > 0 && scope_ptr[0] != 0) throw TnError(TN_E_INVALID, "scope_ptr[0] must be 0");
+    int64_t voff = 0;
+    for (int f = 0; f < n_factors; ++f) {
+      if (scope_ptr[f + 1] < scope_ptr[f]) throw TnError(TN_E_INVALID, "scope_ptr not monotone");
+      std::vector<int> s(scope_vars + scope_ptr[f], scope_vars + scope_ptr[f + 1]);
+      int64_t sz = 1;
+      std::vector<char> seen(n_vars, 0);
+      for (int v : s) {
+        if (v < 0 || v >= n_vars) throw TnError(TN_E_INVALID, "factor " + std::to_string(f) + " has a variable out of range");
+        if (seen[v]) throw TnError(TN_E_INVALID, "factor " + std::to_string(f) + " repeats a variable");
+        seen[v] = 1;
+        sz *= card[v];
+        if (sz > (int64_t(1) << 31)) throw TnError(TN_E_TOO_LARGE, "factor table too large");
+      }
+      std::vector<double> vals(values + voff, values + voff + sz);
+      for (double x : vals) {
+        if (std::isnan(x)) throw TnError(TN_E_INVALID, "factor " + std::to_string(f) + " has NaN");
+        if (net->is_log ? (x == INFINITY) : (x < 0 || !std::isfinite(x)))
+          throw TnError(TN_E_INVALID, "factor " + std::to_string(f) +
+                                          (net->is_log ? " has +inf log-potential" : " has a negative or non-finite value"));
+      }
+      net->val_off.push_back(voff);
+      voff += sz;
+      net->scope.push_back(std::move(s));
+      net->vals.push_back(std::move(vals));
+    }
+    net->n_values = voff;
+    *out = net.release();
+  });
+}
+
+extern "C" void tn_free_network(tn_net *net) { delete net; }
+
+extern "C" void tn_plan_opts_default(tn_plan_opts *o) {
+  std::memset(o, 0, sizeof *o);
+  o->semiring_mask = TN_SUM_PRODUCT | TN_MAX_PLUS;
+  o->evidence_mode = TN_EVIDENCE_NONE;
+  o->planner = TN_PLANNER_BEST;
+  o->restarts = 4;
+  o->seed = 0;
+  o->max_log2_size = 0;
+  o->dtype = TN_F32;
+  o->max_batch = 1;
+  o->use_graph = 1;
+}
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+static int64_t numel(const Labels &l, const std::vector<int> &card) {
+  int64_t s = 1;
+  for (int v : l) s *= card[v];
+  return s;
+}
+static bool has(const Labels &l, int v) { return std::binary_search(l.begin(), l.end(), v); }
+static Labels inter(const Labels &a, const Labels &b) {
+  Labels o;
+  std::set_intersection(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(o));
+  return o;
+}
+static Labels minus(const Labels &a, const Labels &b) {
+  Labels o;
+  std::set_difference(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(o));
+  return o;
+}
+static Labels unite(const Labels &a, const Labels &b) {
+  Labels o;
+  std::set_union(a.begin(), a.end(), b.begin(), b.end(), std::back_inserter(o));
+  return o;
+}
+// row-major stride of v in a tensor with sorted labels L (0 if absent)
+static int64_t stride_in(const Labels &L, int v, const std::vector<int> &card) {
+  int64_t s = 1;
+  for (int i = (int)L.size() - 1; i >= 0; --i) {
+    if (L[i] == v) return s;
+    s *= card[L[i]];
+  }
+  return 0;
+}
+
+static int new_tensor(tn_plan_t *p, const Labels &lab, bool batched, bool scaled) {
+  TensorBuf t;
+  t.lab = lab;
+  t.size = numel(lab, p->card);
+  if (t.size >= (int64_t(1) << 31))
+    throw TnError(TN_E_TOO_LARGE, "an intermediate tensor has 2^" +
+                                      std::to_string(std::log2((double)t.size)) +
+                                      " elements; set max_log2_size to slice the network");
+  t.batched = batched;
+  t.slot = scaled ? 0 : -1;  // real slot assigned at allocation
+  p->T.push_back(t);
+  return (int)p->T.size() - 1;
+}
+static int new_intbuf(tn_plan_t *p, int64_t size, bool batched) {
+  IntBuf b;
+  b.size = size;
+  b.batched = batched;
+  p->IB.push_back(b);
+  return (int)p->IB.size() - 1;
+}
+
+// split point of a class: trailing labels whose product is <= 1024
+static size_t lo_split(const Labels &L, const std::vector<int> &card) {
+  size_t s = L.size();
+  int64_t prod = 1;
+  while (s > 0 && prod * card[L[s - 1]] <= 1024) {
+    prod *= card[L[s - 1]];
+    --s;
+  }
+  if (s == L.size() && !L.empty()) s = L.size() - 1;  // a single label larger than 1024
+  return s;
+}
+
+// append offset tables of class L (split at `split`) for tensor TL
+static void add_tabs(tn_plan_t *p, const Labels &L, size_t split, const Labels &TL, int64_t out[2]) {
+  const auto &card = p->card;
+  Labels hi(L.begin(), L.begin() + split), lo(L.begin() + split, L.end());
+  for (int part = 0; part < 2; ++part) {
+    const Labels &P = part ? lo : hi;
+    std::vector<int64_t> st(P.size());
+    for (size_t j = 0; j < P.size(); ++j) st[j] = stride_in(TL, P[j], card);
+    int64_t n = numel(P, card);
+    out[part] = (int64_t)p->tabs.size();
+    std::vector<int> d(P.size(), 0);
+    int64_t off = 0;
+    for (int64_t i = 0; i < n; ++i) {
+      p->tabs.push_back((int32_t)off);
+      for (int j = (int)P.size() - 1; j >= 0; --j) {
+        if (++d[j] < card[P[j]]) {
+          off += st[j];
+          break;
+        }
+        off -= st[j] * (card[P[j]] - 1);
+        d[j] = 0;
+      }
+    }
+  }
+}
+
+// Lower one contraction Z = X (x) Y to a kernel descriptor.
+static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
+  Op op;
+  op.semi = semi;
+  op.X = X;
+  op.Y = Y;
+  op.Z = Z;
+  op.I = I;
+  const auto &card = p->card;
+  const Labels &LX = p->T[X].lab, &LZ = p->T[Z].lab;
+  const Labels LY = Y >= 0 ? p->T[Y].lab : Labels{};
+  const Labels R = inter(LZ, LX), C = minus(LZ, LX), S = minus(unite(LX, LY), LZ);
+  if (semi == SEMI_MAX && !minus(C, LY).empty()) throw TnError(TN_E_INVALID, "internal: broadcast in max-plus node");
+  const size_t rs = lo_split(R, card), cs = lo_split(C, card), ss = lo_split(S, card);
+  for (auto *t : {op.t_rX, op.t_rY, op.t_rZ, op.t_cY, op.t_cZ, op.t_sX, op.t_sY}) t[0] = t[1] = -1;
+  add_tabs(p, R, rs, LX, op.t_rX);
+  add_tabs(p, R, rs, LZ, op.t_rZ);
+  add_tabs(p, C, cs, LZ, op.t_cZ);
+  add_tabs(p, S, ss, LX, op.t_sX);
+  if (Y >= 0) {
+    add_tabs(p, R, rs, LY, op.t_rY);
+    add_tabs(p, C, cs, LY, op.t_cY);
+    add_tabs(p, S, ss, LY, op.t_sY);
+  }
+  ContractArgs &a = op.a;
+  a.nR = (uint32_t)numel(R, card);
+  a.nRl = (uint32_t)numel(Labels(R.begin() + rs, R.end()), card);
+  a.nC = (uint32_t)numel(C, card);
+  a.nCl = (uint32_t)numel(Labels(C.begin() + cs, C.end()), card);
+  a.nS = (uint32_t)numel(S, card);
+  a.nSl = (uint32_t)numel(Labels(S.begin() + ss, S.end()), card);
+  a.col_fastest = (!LZ.empty() && !C.empty() && LZ.back() == C.back()) ? 1 : 0;
+  const bool zb = p->T[Z].batched;
+  op.nb = zb ? p->max_batch : 1;
+  const uint64_t n_out = (uint64_t)a.nR * a.nC;
+  const uint32_t nSh = a.nS / a.nSl;
+  if (n_out * (uint64_t)op.nb < 8192 && a.nS >= 4096 && nSh >= 2) {
+    op.split = true;
+    uint32_t want = std::max<uint32_t>(1, 4096u / (uint32_t)op.nb);
+    a.n_chunks = std::min<uint32_t>(nSh, want);
+    p->part_floats = std::max<int64_t>(p->part_floats, (int64_t)op.nb * a.n_chunks * n_out);
+  }
+  op.flops = 2.0 * (double)n_out * (double)a.nS;
+  op.bytes = 4.0 * (double)(p->T[X].size + (Y >= 0 ? p->T[Y].size : 0) + p->T[Z].size);
+  return op;
+}
+
+// ---------------------------------------------------------------------------
+// plan construction
+// ---------------------------------------------------------------------------
+
+// leaves of the main tree for the plan's evidence mode
+static void build_leaves(tn_plan_t *p, const tn_net *net) {
+  const int n = p->n_vars;
+  for (int f = 0; f < (int)net->scope.size(); ++f) {
+    Labels lab;
+    for (int v : net->scope[f])
+      if (!p->is_obs[v]) lab.push_back(v);
+    std::sort(lab.begin(), lab.end());
+    p->leaf_lab.push_back(lab);
+    p->leaf_kind.push_back(0);
+    p->leaf_var.push_back(-1);
+    p->leaf_factor.push_back(f);
+  }
+  for (int v = 0; v < n; ++v) {
+    if (p->mode == TN_EVIDENCE_SLICED && p->is_obs[v]) continue;
+    p->leaf_lab.push_back(Labels{v});
+    p->leaf_kind.push_back(p->mode == TN_EVIDENCE_INDICATOR ? 2 : 1);
+    p->leaf_var.push_back(v);
+    p->leaf_factor.push_back(-1);
+  }
+}
+
+// gather map of factor f restricted to its unobserved variables (sorted),
+// and (var, stride) pairs of its observed variables, strides in load order
+static void factor_gather(tn_plan_t *p, const tn_net *net, int f, const std::vector<char> &fixed,
+                          int32_t &gmap_off, int32_t &obs_b, int32_t &obs_e) {
+  const auto &sc = net->scope[f];
+  std::vector<int64_t> st(sc.size());
+  int64_t s = 1;
+  for (int i = (int)sc.size() - 1; i >= 0; --i) {
+    st[i] = s;
+    s *= p->card[sc[i]];
+  }
+  Labels lab;
+  for (int v : sc)
+    if (!fixed[v]) lab.push_back(v);
+  std::sort(lab.begin(), lab.end());
+  std::vector<int64_t> ls(lab.size());
+  for (size_t j = 0; j < lab.size(); ++j)
+    for (size_t i = 0; i < sc.size(); ++i)
+      if (sc[i] == lab[j]) ls[j] = st[i];
+  gmap_off = (int32_t)p->gmap.size();
+  int64_t n = numel(lab, p->card);
+  std::vector<int> d(lab.size(), 0);
+  int64_t off = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    p->gmap.push_back((int32_t)off);
+    for (int j = (int)lab.size() - 1; j >= 0; --j) {
+      if (++d[j] < p->card[lab[j]]) {
+        off += ls[j];
+        break;
+      }
+      off -= ls[j] * (p->card[lab[j]] - 1);
+      d[j] = 0;
+    }
+  }
+  obs_b = (int32_t)(p->obs.size() / 2);
+  for (size_t i = 0; i < sc.size(); ++i)
+    if (fixed[sc[i]]) {
+      p->obs.push_back(sc[i]);
+      p->obs.push_back((int32_t)st[i]);
+    }
+  obs_e = (int32_t)(p->obs.size() / 2);
+}
+
+// Forward ops of a tree whose leaf tensors exist: creates node tensors.
+// For max-plus, labels eliminated at a node that only one child holds are
+// reduced in that child first (with their own argmax), so that the node
+// itself maximises over the shared labels only.
+static void build_forward(tn_plan_t *p, TreeExec &t, int semi) {
+  const int L = (int)t.leaf_tensor.size();
+  t.node_tensor = t.leaf_tensor;
+  t.node_tensor.resize(L + t.pairs.size(), -1);
+  t.node_ops.assign(t.pairs.size(), {});
+  t.root_op = -1;
+  const bool sum = semi == SEMI_SUM;
+  for (size_t q = 0; q < t.pairs.size(); ++q) {
+    const int c = L + (int)q, l = t.pairs[q][0], r = t.pairs[q][1];
+    int tl = t.node_tensor[l], tr = t.node_tensor[r];
+    const Labels &Lc = t.lab[c];
+    if (!sum) {
+      for (int side = 0; side < 2; ++side) {
+        int &tc = side ? tr : tl;
+        const Labels mine = p->T[tc].lab, other = p->T[side ? tl : tr].lab;
+        Labels keep;
+        for (int v : mine)
+          if (has(other, v) || has(Lc, v)) keep.push_back(v);
+        if (keep.size() == mine.size()) continue;
+        int red = new_tensor(p, keep, p->T[tc].batched, false);
+        int ib = new_intbuf(p, p->T[red].size, p->T[red].batched);
+        t.node_ops[q].push_back((int)t.ops.size());
+        t.ops.push_back(make_op(p, SEMI_MAX, tc, -1, red, ib));
+        tc = red;
+      }
+    }
+    const bool bat = p->T[tl].batched || p->T[tr].batched;
+    int z = new_tensor(p, Lc, bat, sum);
+    int X = tl, Y = tr;
+    const int64_t wl = p->T[tl].size * (p->T[tl].batched ? 2 : 1), wr = p->T[tr].size * (p->T[tr].batched ? 2 : 1);
+    if (wr > wl) std::swap(X, Y);
+    int ib = sum ? -1 : new_intbuf(p, p->T[z].size, bat);
+    t.node_ops[q].push_back((int)t.ops.size());
+    t.ops.push_back(make_op(p, semi, X, Y, z, ib));
+    t.node_tensor[c] = z;
+  }
+  const int root_node = L + (int)t.pairs.size() - 1;
+  const int rt = t.node_tensor[root_node];
+  if (p->T[rt].lab != t.out) {
+    // single leaf (or labels left at the root): reduce to the output labels
+    int z = new_tensor(p, t.out, p->T[rt].batched, sum);
+    int ib = sum ? -1 : new_intbuf(p, p->T[z].size, p->T[z].batched);
+    t.root_op = (int)t.ops.size();
+    t.ops.push_back(make_op(p, semi, rt, -1, z, ib));
+    t.root = z;
+  } else {
+    t.root = rt;
+  }
+}
+
+// Readout steps for a max-plus tree: top-down, each node's main argmax
+// first, then the argmax of its children's private reductions.
+static void build_backtrack(tn_plan_t *p, TreeExec &t) {
+  t.back.clear();
+  t.back_meta.clear();
+  auto add_step = [&](const Op &op) {
+    BackStep s{};
+    s.arg = op.I;  // IntBuf id; converted to an offset at allocation
+    const Labels &LZ = p->T[op.Z].lab;
+    s.in_begin = (int32_t)(t.back_meta.size() / 2);
+    for (int v : LZ) {
+      t.back_meta.push_back(v);
+      t.back_meta.push_back((int32_t)stride_in(LZ, v, p->card));
+    }
+    s.in_end = (int32_t)(t.back_meta.size() / 2);
+    Labels U = p->T[op.X].lab;
+    if (op.Y >= 0) U = unite(U, p->T[op.Y].lab);
+    s.out_begin = s.in_end;
+    for (int v : minus(U, LZ)) {
+      t.back_meta.push_back(v);
+      t.back_meta.push_back(p->card[v]);
+    }
+    s.out_end = (int32_t)(t.back_meta.size() / 2);
+    t.back.push_back(s);
+  };
+  if (t.root_op >= 0) add_step(t.ops[t.root_op]);
+  for (int q = (int)t.pairs.size() - 1; q >= 0; --q) {
+    const auto &ids = t.node_ops[q];
+    add_step(t.ops[ids.back()]);
+    for (size_t k = 0; k + 1 < ids.size(); ++k) add_step(t.ops[ids[k]]);
+  }
+}
+
+static void build_sampling(tn_plan_t *p, const TreeExec &t) {
+  p->samp.clear();
+  p->samp_meta.clear();
+  const int L = (int)t.leaf_tensor.size();
+  auto quad = [&](int v, int c, int64_t sa, int64_t sb) {
+    p->samp_meta.push_back(v);
+    p->samp_meta.push_back(c);
+    p->samp_meta.push_back((int32_t)sa);
+    p->samp_meta.push_back((int32_t)sb);
+  };
+  if (t.pairs.empty()) {
+    SampleStep st{};
+    st.A = t.leaf_tensor[0];
+    st.B = -1;
+    st.node = L;
+    st.aIn_b = st.aIn_e = st.bIn_b = st.bIn_e = st.k_b = st.k_e = st.pb_b = st.pb_e = 0;
+    const Labels &la = p->T[t.leaf_tensor[0]].lab;
+    st.pa_b = (int32_t)(p->samp_meta.size() / 4);
+    for (int v : la) quad(v, p->card[v], stride_in(la, v, p->card), 0);
+    st.pa_e = (int32_t)(p->samp_meta.size() / 4);
+    p->samp.push_back(st);
+    return;
+  }
+  for (int q = (int)t.pairs.size() - 1; q >= 0; --q) {
+    const int c = L + q, l = t.pairs[q][0], r = t.pairs[q][1];
+    const Labels &La = t.lab[l], &Lb = t.lab[r], &Lc = t.lab[c];
+    SampleStep st{};
+    st.A = t.node_tensor[l];
+    st.B = t.node_tensor[r];
+    st.node = c;
+    auto beg = [&] { return (int32_t)(p->samp_meta.size() / 4); };
+    st.aIn_b = beg();
+    for (int v : inter(La, Lc)) quad(v, p->card[v], stride_in(La, v, p->card), 0);
+    st.aIn_e = beg();
+    st.bIn_b = beg();
+    for (int v : inter(Lb, Lc)) quad(v, p->card[v], 0, stride_in(Lb, v, p->card));
+    st.bIn_e = beg();
+    st.k_b = beg();
+    for (int v : minus(inter(La, Lb), Lc)) quad(v, p->card[v], stride_in(La, v, p->card), stride_in(Lb, v, p->card));
+    st.k_e = beg();
+    st.pa_b = beg();
+    for (int v : minus(minus(La, Lb), Lc)) quad(v, p->card[v], stride_in(La, v, p->card), 0);
+    st.pa_e = beg();
+    st.pb_b = beg();
+    for (int v : minus(minus(Lb, La), Lc)) quad(v, p->card[v], 0, stride_in(Lb, v, p->card));
+    st.pb_e = beg();
+    p->samp.push_back(st);
+  }
+}
+
+template <class T>
+static T *dalloc(tn_plan_t *p, size_t n) {
+  if (n == 0) n = 1;
+  void *ptr = nullptr;
+  hip_check(hipMalloc(&ptr, n * sizeof(T)), "hipMalloc");
+  p->allocs.push_back(ptr);
+  p->device_bytes += (int64_t)(n * sizeof(T));
+  return (T *)ptr;
+}
+template <class T>
+static T *dupload(tn_plan_t *p, const std::vector<T> &v) {
+  T *d = dalloc<T>(p, v.size());
+  if (!v.empty()) hip_check(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "upload");
+  return d;
+}
+
+static void fill_args(tn_plan_t *p, Op &op) {
+  ContractArgs &a = op.a;
+  auto tab = [&](const int64_t t[2]) {
+    Tab2 r;
+    if (t[0] >= 0) {
+      r.hi = p->d_tabs + t[0];
+      r.lo = p->d_tabs + t[1];
+    }
+    return r;
+  };
+  a.rX = tab(op.t_rX);
+  a.rY = tab(op.t_rY);
+  a.rZ = tab(op.t_rZ);
+  a.cY = tab(op.t_cY);
+  a.cZ = tab(op.t_cZ);
+  a.sX = tab(op.t_sX);
+  a.sY = tab(op.t_sY);
+  const TensorBuf &X = p->T[op.X], &Z = p->T[op.Z];
+  a.X = p->arena + X.off;
+  a.bsX = X.batched ? X.size : 0;
+  if (op.Y >= 0) {
+    const TensorBuf &Y = p->T[op.Y];
+    a.Y = p->arena + Y.off;
+    a.bsY = Y.batched ? Y.size : 0;
+    a.slotY = Y.slot;
+    a.batY = Y.batched;
+  }
+  a.Z = p->arena + Z.off;
+  a.bsZ = Z.batched ? Z.size : 0;
+  a.I = op.I >= 0 ? p->iarena + p->IB[op.I].off : nullptr;
+  a.mx = p->mx;
+  a.ex = p->ex;
+  a.slotX = X.slot;
+  a.batX = X.batched;
+  a.slotZ = Z.slot;
+  a.batZ = Z.batched;
+  a.part = p->d_part;
+  a.parti = p->d_parti;
+}
+
+tn_plan_impl::~tn_plan_impl() {
+  for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
+  if (stream) (void)hipStreamSynchronize(stream);
+  for (void *ptr : allocs) (void)hipFree(ptr);
+  if (own_stream && stream) (void)hipStreamDestroy(stream);
+}
+
+static void build_mmap(tn_plan_t *p, const tn_net *net);
+static void allocate_mmap(tn_plan_t *p);
+
+static void allocate(tn_plan_t *p, const tn_net *net) {
+  // device work starts here: everything above is host-side planning
+  if (p->opts.hip_stream) {
+    p->stream = (hipStream_t)p->opts.hip_stream;
+  } else {
+    hip_check(hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking), "hipStreamCreate");
+    p->own_stream = true;
+  }
+  // slots: prepared leaves first, then constants, then everything reset per solve
+  int slot = 0;
+  std::vector<char> prepared(p->T.size(), 0), constant(p->T.size(), 0);
+  for (auto &d : p->leaves_sum) prepared[d.slot] = 1;  // d.slot holds the tensor id here
+  for (auto &gl : p->group_leaves)
+    for (auto &d : gl) prepared[d.slot] = 1;
+  if (p->seed_tensor >= 0) constant[p->seed_tensor] = 1;
+  auto give = [&](int i) {
+    p->T[i].slot = slot;
+    slot += p->T[i].batched ? p->max_batch : 1;
+  };
+  for (size_t i = 0; i < p->T.size(); ++i)
+    if (p->T[i].slot >= 0 && prepared[i]) give((int)i);
+  for (size_t i = 0; i < p->T.size(); ++i)
+    if (p->T[i].slot >= 0 && constant[i]) give((int)i);
+  p->reset_begin = slot;
+  for (size_t i = 0; i < p->T.size(); ++i)
+    if (p->T[i].slot >= 0 && !prepared[i] && !constant[i]) give((int)i);
+  p->reset_end = slot;
+  p->n_slots = slot;
+  for (auto &d : p->leaves_sum) d.slot = p->T[d.slot].slot;
+  for (auto &gl : p->group_leaves)
+    for (auto &d : gl) d.slot = p->T[d.slot].slot;
+  // arena: factor stores, then tensors (256-byte aligned)
+  int64_t off = 0;
+  auto take = [&](int64_t n) {
+    int64_t o = off;
+    off += (n + 63) / 64 * 64;
+    return o;
+  };
+  const int64_t fs_lin = take(net->n_values), fs_log = take(net->n_values);
+  for (auto &t : p->T) t.off = take(t.size * (t.batched ? p->max_batch : 1));
+  p->arena_floats = off;
+  int64_t ioff = 0;
+  for (auto &b : p->IB) {
+    b.off = ioff;
+    ioff += (b.size * (b.batched ? p->max_batch : 1) + 63) / 64 * 64;
+  }
+  p->iarena_ints = ioff;
+  p->arena = dalloc<float>(p, (size_t)p->arena_floats);
+  p->iarena = dalloc<int32_t>(p, (size_t)p->iarena_ints + 64);
+  p->mx = dalloc<uint32_t>(p, (size_t)std::max(1, p->n_slots));
+  p->ex = dalloc<int32_t>(p, (size_t)std::max(1, p->n_slots));
+  hip_check(hipMemset(p->mx, 0, sizeof(uint32_t) * std::max(1, p->n_slots)), "memset");
+  hip_check(hipMemset(p->ex, 0, sizeof(int32_t) * std::max(1, p->n_slots)), "memset");
+  // factor stores: linear FP32 and log FP32 (host FP64 conversion, rounded once)
+  std::vector<float> lin(net->n_values), lg(net->n_values);
+  for (size_t f = 0; f < net->vals.size(); ++f)
+    for (size_t i = 0; i < net->vals[f].size(); ++i) {
+      const double x = net->vals[f][i];
+      const int64_t o = net->val_off[f] + (int64_t)i;
+      if (net->is_log) {
+        lin[o] = (float)std::exp(x);
+        lg[o] = (float)x;
+      } else {
+        lin[o] = (float)x;
+        lg[o] = x > 0 ? (float)std::log(x) : -INFINITY;
+      }
+    }
+  if (!lin.empty()) {
+    hip_check(hipMemcpy(p->arena + fs_lin, lin.data(), lin.size() * 4, hipMemcpyHostToDevice), "upload");
+    hip_check(hipMemcpy(p->arena + fs_log, lg.data(), lg.size() * 4, hipMemcpyHostToDevice), "upload");
+  }
+  auto fix_leaf = [&](LeafDesc &d, int tensor, bool maxdom) {
+    d.dst = p->T[tensor].off;
+    if (d.kind == 0) d.src += maxdom ? fs_log : fs_lin;
+  };
+  // leaf descriptors carry the tensor id in dst until here
+  for (auto &d : p->leaves_sum) fix_leaf(d, (int)d.dst, false);
+  for (auto &d : p->leaves_max) fix_leaf(d, (int)d.dst, true);
+  for (auto &gl : p->group_leaves)
+    for (auto &d : gl) fix_leaf(d, (int)d.dst, false);
+  for (auto &d : p->qleaves) fix_leaf(d, (int)d.dst, true);
+  p->d_tabs = dupload(p, p->tabs);
+  p->d_gmap = dupload(p, p->gmap);
+  p->d_obs = dupload(p, p->obs);
+  p->d_evidence = dalloc<int32_t>(p, (size_t)p->max_batch * std::max(1, p->n_vars));
+  p->d_assign = dalloc<int32_t>(p, (size_t)p->max_batch * std::max(1, p->n_vars));
+  p->d_out = dalloc<double>(p, (size_t)p->max_batch);
+  p->d_part = dalloc<float>(p, (size_t)std::max<int64_t>(1, p->part_floats));
+  p->d_parti = dalloc<int32_t>(p, (size_t)std::max<int64_t>(1, p->part_floats));
+  for (auto &op : p->sum_tree.ops) fill_args(p, op);
+  for (auto &op : p->max_tree.ops) fill_args(p, op);
+  for (auto &op : p->bwd) fill_args(p, op);
+  for (auto &g : p->groups)
+    for (auto &op : g.ops) fill_args(p, op);
+  for (auto &op : p->qtree.ops) fill_args(p, op);
+  p->d_leaves_sum = dupload(p, p->leaves_sum);
+  p->d_leaves_max = dupload(p, p->leaves_max);
+  p->d_qleaves = dupload(p, p->qleaves);
+  for (auto &gl : p->group_leaves) p->d_group_leaves.push_back(dupload(p, gl));
+  // seed of the reverse pass: ones, maximum 1, exponent 0
+  if (p->seed_tensor >= 0) {
+    const TensorBuf &s = p->T[p->seed_tensor];
+    const int64_t n = s.size * (s.batched ? p->max_batch : 1);
+    std::vector<float> ones(n, 1.f);
+    hip_check(hipMemcpy(p->arena + s.off, ones.data(), n * 4, hipMemcpyHostToDevice), "upload");
+    const int ns = s.batched ? p->max_batch : 1;
+    std::vector<uint32_t> m(ns, 0x3f800000u);
+    hip_check(hipMemcpy(p->mx + s.slot, m.data(), ns * 4, hipMemcpyHostToDevice), "upload");
+  }
+  // marginal / gradient descriptors
+  for (auto &m : p->marg) {
+    const TensorBuf &A = p->T[(int)m.adj], &Lf = p->T[(int)m.leaf];
+    m.adj = A.off;
+    m.leaf = Lf.off;
+    m.adj_batched = A.batched;
+    m.leaf_batched = Lf.batched;
+    m.adj_bs = A.size;
+    m.leaf_bs = Lf.size;
+  }
+  p->d_marg_desc = dupload(p, p->marg);
+  p->d_marg = dalloc<double>(p, (size_t)p->max_batch * std::max(1, p->marg_row));
+  for (auto &g : p->grads) {
+    const TensorBuf &A = p->T[(int)g.adj];
+    g.slot = A.slot;
+    g.adj = A.off;
+  }
+  p->d_grad_desc = dupload(p, p->grads);
+  auto fix_back = [&](TreeExec &t) {
+    for (auto &s : t.back) {
+      const IntBuf &b = p->IB[(int)s.arg];
+      s.arg = b.off;
+      s.bs = b.batched ? b.size : 0;
+    }
+  };
+  fix_back(p->max_tree);
+  fix_back(p->qtree);
+  p->d_back = dupload(p, p->max_tree.back);
+  p->d_back_meta = dupload(p, p->max_tree.back_meta);
+  p->d_qback = dupload(p, p->qtree.back);
+  p->d_qback_meta = dupload(p, p->qtree.back_meta);
+  for (auto &s : p->samp) {
+    s.A = p->T[(int)s.A].off;
+    if (s.B >= 0) s.B = p->T[(int)s.B].off;
+  }
+  p->d_samp = dupload(p, p->samp);
+  p->d_samp_meta = dupload(p, p->samp_meta);
+  if (p->is_mmap) allocate_mmap(p);
+}
+
+static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
+  p->opts = *o;
+  p->n_vars = net->n_vars;
+  p->card = net->card;
+  p->mode = o->evidence_mode;
+  if (p->mode < 0 || p->mode > 2) throw TnError(TN_E_INVALID, "unknown evidence mode");
+  p->max_batch = p->mode == TN_EVIDENCE_INDICATOR ? std::max(1, o->max_batch) : 1;
+  p->want_sum = (o->semiring_mask & TN_SUM_PRODUCT) != 0;
+  p->want_max = (o->semiring_mask & TN_MAX_PLUS) != 0;
+  p->want_grad = o->want_factor_grad != 0;
+  if (o->dtype != TN_F32) throw TnError(TN_E_UNSUPPORTED, "only FP32 storage is built in this version");
+  p->is_obs.assign(p->n_vars, 0);
+  if (p->mode == TN_EVIDENCE_SLICED) {
+    for (int i = 0; i < o->n_observed; ++i) {
+      int v = o->observed[i];
+      if (v < 0 || v >= p->n_vars) throw TnError(TN_E_INVALID, "observed variable out of range");
+      if (p->is_obs[v]) throw TnError(TN_E_INVALID, "observed variable listed twice");
+      p->is_obs[v] = 1;
+      p->observed.push_back(v);
+    }
+  }
+  if (o->query && o->n_query > 0) {
+    p->is_mmap = true;
+    if (p->mode == TN_EVIDENCE_INDICATOR) throw TnError(TN_E_UNSUPPORTED, "MMAP with batched evidence");
+    build_mmap(p, net);
+    allocate(p, net);
+    return;
+  }
+  // stream
+  build_leaves(p, net);
+  const int L = (int)p->leaf_lab.size();
+  if (o->tree_pairs && o->n_tree_pairs > 0) {
+    for (int i = 0; i < o->n_tree_pairs; ++i) p->pairs.push_back({o->tree_pairs[2 * i], o->tree_pairs[2 * i + 1]});
+    validate_tree(L, p->pairs);
+    p->stats = tree_stats(p->leaf_lab, p->pairs, {}, p->card);
+    p->planner_used = -1;
+  } else {
+    PlanChoice pc = plan_tree(p->leaf_lab, p->card, {}, o->planner, o->restarts, o->seed);
+    p->pairs = pc.pairs;
+    p->stats = pc.stats;
+    p->planner_used = pc.planner;
+  }
+  auto lab = node_labels(p->leaf_lab, p->pairs, {}, p->n_vars);
+  if (o->max_log2_size > 0 && p->stats.sc > o->max_log2_size + 1e-9)
+    throw TnError(TN_E_UNSUPPORTED, "slicing is available for MMAP plans; increase max_log2_size");
+  // leaf tensors and descriptors
+  std::vector<char> fixed = p->is_obs;
+  std::vector<int> leaf_sum(L, -1), leaf_max(L, -1);
+  for (int i = 0; i < L; ++i) {
+    const bool bat = p->leaf_kind[i] == 2;
+    LeafDesc d{};
+    d.kind = p->leaf_kind[i];
+    d.var = p->leaf_var[i];
+    d.batched = bat;
+    d.size = (int32_t)numel(p->leaf_lab[i], p->card);
+    if (d.kind == 0) {
+      const int f = p->leaf_factor[i];
+      factor_gather(p, net, f, fixed, d.gmap, d.obs_begin, d.obs_end);
+      d.src = net->val_off[f];
+    }
+    if (p->want_sum) {
+      leaf_sum[i] = new_tensor(p, p->leaf_lab[i], bat, true);
+      LeafDesc s = d;
+      s.dst = leaf_sum[i];
+      s.slot = leaf_sum[i];
+      s.maxdom = 0;
+      p->leaves_sum.push_back(s);
+    }
+    if (p->want_max) {
+      leaf_max[i] = new_tensor(p, p->leaf_lab[i], bat, false);
+      LeafDesc m = d;
+      m.dst = leaf_max[i];
+      m.slot = -1;
+      m.maxdom = 1;
+      p->leaves_max.push_back(m);
+    }
+  }
+  if (p->want_sum) {
+    TreeExec &t = p->sum_tree;
+    t.leaf_tensor = leaf_sum;
+    t.pairs = p->pairs;
+    t.lab = lab;
+    build_forward(p, t, SEMI_SUM);
+    // reverse pass
+    std::vector<char> need(L + p->pairs.size(), 0);
+    for (int i = 0; i < L; ++i) need[i] = p->leaf_kind[i] != 0 || p->want_grad;
+    for (size_t q = 0; q < p->pairs.size(); ++q)
+      need[L + q] = need[p->pairs[q][0]] || need[p->pairs[q][1]];
+    p->adj_tensor.assign(L + p->pairs.size(), -1);
+    const int rootn = L + (int)p->pairs.size() - 1;
+    p->seed_tensor = new_tensor(p, p->T[t.root].lab, p->mode == TN_EVIDENCE_INDICATOR, true);
+    if (t.root != t.node_tensor[rootn]) {
+      // root reduction: its adjoint is a broadcast of the seed
+      int a = new_tensor(p, p->T[t.node_tensor[rootn]].lab, p->T[p->seed_tensor].batched, true);
+      p->bwd.push_back(make_op(p, SEMI_SUM, p->seed_tensor, -1, a, -1));
+      p->adj_tensor[rootn] = a;
+    } else {
+      p->adj_tensor[rootn] = p->seed_tensor;
+    }
+    for (int q = (int)p->pairs.size() - 1; q >= 0; --q) {
+      const int c = L + q;
+      if (!need[c]) continue;
+      for (int side = 0; side < 2; ++side) {
+        const int ch = p->pairs[q][side], sib = p->pairs[q][1 - side];
+        if (!need[ch]) continue;
+        const int cbar = p->adj_tensor[c], sbt = t.node_tensor[sib];
+        const bool bat = p->T[cbar].batched || p->T[sbt].batched;
+        int a = new_tensor(p, lab[ch], bat, true);
+        int X = cbar, Y = sbt;
+        if (p->T[Y].size > p->T[X].size) std::swap(X, Y);
+        p->bwd.push_back(make_op(p, SEMI_SUM, X, Y, a, -1));
+        p->adj_tensor[ch] = a;
+      }
+    }
+    int col = 0;
+    p->marg_col.assign(p->n_vars, 0);
+    for (int v = 0; v < p->n_vars; ++v) {
+      p->marg_col[v] = col;
+      col += p->card[v];
+    }
+    p->marg_row = col;
+    for (int i = 0; i < L; ++i) {
+      if (p->leaf_kind[i] != 0) {
+        MargDesc m{};
+        m.adj = p->adj_tensor[i];
+        m.leaf = leaf_sum[i];
+        m.card = p->card[p->leaf_var[i]];
+        m.out = p->marg_col[p->leaf_var[i]];
+        p->marg.push_back(m);
+      } else if (p->want_grad) {
+        GradDesc g{};
+        g.adj = p->adj_tensor[i];
+        g.size = (int32_t)numel(p->leaf_lab[i], p->card);
+        const int f = p->leaf_factor[i];
+        g.dst = net->val_off[f];
+        const LeafDesc &ld = p->leaves_sum[i];
+        g.gmap = ld.gmap;
+        g.obs_begin = ld.obs_begin;
+        g.obs_end = ld.obs_end;
+        p->grads.push_back(g);
+      }
+    }
+    if (p->mode != TN_EVIDENCE_INDICATOR) build_sampling(p, t);
+  }
+  if (p->want_max) {
+    TreeExec &t = p->max_tree;
+    t.leaf_tensor = leaf_max;
+    t.pairs = p->pairs;
+    t.lab = lab;
+    build_forward(p, t, SEMI_MAX);
+    build_backtrack(p, t);
+  }
+  allocate(p, net);
+}
+
+extern "C" tn_status tn_plan(const tn_net *net, const tn_plan_opts *opts, tn_plan_t **out) {
+  return guard([&] {
+    if (!net || !out) throw TnError(TN_E_INVALID, "NULL argument");
+    *out = nullptr;
+    tn_plan_opts o;
+    if (opts) o = *opts;
+    else tn_plan_opts_default(&o);
+    auto p = std::make_unique<tn_plan_impl>();
+    p->net_src = net;
+    make_plan(p.get(), net, &o);
+    hip_check(hipDeviceSynchronize(), "plan upload");
+    *out = p.release();
+  });
+}
+
+extern "C" void tn_free_plan(tn_plan_t *p) { delete p; }
+
+extern "C" tn_status tn_plan_info_get(const tn_plan_t *p, tn_plan_info *info) {
+  return guard([&] {
+    if (!p || !info) throw TnError(TN_E_INVALID, "NULL argument");
+    std::memset(info, 0, sizeof *info);
+    info->n_leaves = (int32_t)p->leaf_lab.size();
+    info->n_nodes = (int32_t)(p->leaf_lab.size() + p->pairs.size());
+    info->n_kernels_fwd = (int32_t)p->sum_tree.ops.size();
+    info->n_kernels_bwd = (int32_t)p->bwd.size();
+    info->n_kernels_max = (int32_t)p->max_tree.ops.size();
+    info->sc = p->stats.sc;
+    info->sc_union = p->stats.sc_union;
+    info->tc = p->stats.tc;
+    info->flops_fwd = p->stats.flops;
+    info->bytes_fwd = p->stats.bytes;
+    info->n_sliced = (int32_t)p->sliced.size();
+    info->planner_used = p->planner_used;
+    info->device_bytes = p->device_bytes;
+  });
+}
+
+extern "C" tn_status tn_plan_tree(const tn_plan_t *p, int32_t *pairs, int32_t cap, int32_t *n_pairs,
+                                  int32_t *n_leaves) {
+  return guard([&] {
+    if (!p) throw TnError(TN_E_INVALID, "NULL plan");
+    if (n_pairs) *n_pairs = (int32_t)p->pairs.size();
+    if (n_leaves) *n_leaves = (int32_t)p->leaf_lab.size();
+    for (int i = 0; i < (int)p->pairs.size() && i < cap; ++i) {
+      pairs[2 * i] = p->pairs[i][0];
+      pairs[2 * i + 1] = p->pairs[i][1];
+    }
+  });
+}
+
+extern "C" tn_status tn_plan_tree_host(const tn_net *net, const tn_plan_opts *opts, int32_t *pairs,
+                                       int32_t cap, int32_t *n_pairs, int32_t *n_leaves,
+                                       tn_plan_info *stats) {
+  return guard([&] {
+    if (!net) throw TnError(TN_E_INVALID, "NULL network");
+    tn_plan_opts o;
+    if (opts) o = *opts;
+    else tn_plan_opts_default(&o);
+    tn_plan_impl p;
+    p.n_vars = net->n_vars;
+    p.card = net->card;
+    p.mode = o.evidence_mode;
+    p.is_obs.assign(p.n_vars, 0);
+    if (p.mode == TN_EVIDENCE_SLICED)
+      for (int i = 0; i < o.n_observed; ++i) {
+        if (o.observed[i] < 0 || o.observed[i] >= p.n_vars) throw TnError(TN_E_INVALID, "observed variable out of range");
+        p.is_obs[o.observed[i]] = 1;
+      }
+    build_leaves(&p, net);
+    PlanChoice pc = plan_tree(p.leaf_lab, p.card, {}, o.planner, o.restarts, o.seed);
+    if (n_pairs) *n_pairs = (int32_t)pc.pairs.size();
+    if (n_leaves) *n_leaves = (int32_t)p.leaf_lab.size();
+    for (int i = 0; i < (int)pc.pairs.size() && i < cap; ++i) {
+      pairs[2 * i] = pc.pairs[i][0];
+      pairs[2 * i + 1] = pc.pairs[i][1];
+    }
+    if (stats) {
+      std::memset(stats, 0, sizeof *stats);
+      stats->n_leaves = (int32_t)p.leaf_lab.size();
+      stats->n_nodes = (int32_t)(p.leaf_lab.size() + pc.pairs.size());
+      stats->sc = pc.stats.sc;
+      stats->sc_union = pc.stats.sc_union;
+      stats->tc = pc.stats.tc;
+      stats->flops_fwd = pc.stats.flops;
+      stats->bytes_fwd = pc.stats.bytes;
+      stats->planner_used = pc.planner;
+      if (o.max_log2_size > 0) {
+        Labels sl = choose_slices(p.leaf_lab, pc.pairs, {}, p.card, o.max_log2_size);
+        stats->n_sliced = (int32_t)sl.size();
+      }
+    }
+  });
+}
+
+// ---------------------------------------------------------------------------
+// execution
+// ---------------------------------------------------------------------------
+namespace tn {
+
+void run_ops(tn_plan_t *p, const std::vector<Op> &ops) {
+  for (const Op &op : ops) launch_contract(op.semi, op.Y >= 0, op.split, op.a, op.nb, p->stream);
+}
+
+static PrepareArgs prep_args(tn_plan_t *p, const std::vector<LeafDesc> &h, const LeafDesc *d, bool reset) {
+  PrepareArgs a;
+  a.arena = p->arena;
+  a.leaves = d;
+  a.n_leaves = (int)h.size();
+  a.gmap = p->d_gmap;
+  a.obs = p->d_obs;
+  a.evidence = p->d_evidence;
+  a.n_vars = p->n_vars;
+  a.mx = p->mx;
+  a.ex = p->ex;
+  a.reset_begin = reset ? p->reset_begin : 0;
+  a.reset_end = reset ? p->reset_end : 0;
+  a.batch = p->max_batch;
+  a.max_batch = p->max_batch;
+  return a;
+}
+
+void launch_prepare_set(tn_plan_t *p, const std::vector<LeafDesc> &h, const LeafDesc *d, bool reset) {
+  launch_prepare(prep_args(p, h, d, reset), p->stream);
+}
+
+// Run `body` directly, or replay its captured graph.
+template <class F>
+void run_graph(tn_plan_t *p, const std::string &key, F &&body) {
+  if (!p->opts.use_graph) {
+    body();
+    hip_check(hipGetLastError(), "kernel launch");
+    return;
+  }
+  auto it = p->graphs.find(key);
+  if (it == p->graphs.end()) {
+    hipGraph_t g = nullptr;
+    hip_check(hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    body();
+    hipError_t le = hipGetLastError();
+    hip_check(hipStreamEndCapture(p->stream, &g), "end capture");
+    hip_check(le, "kernel launch during capture");
+    hipGraphExec_t ge = nullptr;
+    hip_check(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0), "graph instantiate");
+    (void)hipGraphDestroy(g);
+    it = p->graphs.emplace(key, ge).first;
+  }
+  hip_check(hipGraphLaunch(it->second, p->stream), "graph launch");
+}
+
+}  // namespace tn
+
+static void upload_evidence(tn_plan_t *p, int batch, const int32_t *ev) {
+  std::vector<int32_t> h((size_t)p->max_batch * p->n_vars, -1);
+  for (int b = 0; b < batch; ++b)
+    for (int v = 0; v < p->n_vars; ++v) {
+      int e = ev ? ev[(int64_t)b * p->n_vars + v] : -1;
+      if (e < -1 || e >= p->card[v]) throw TnError(TN_E_INVALID, "evidence value out of range");
+      if (p->mode == TN_EVIDENCE_NONE && e >= 0) throw TnError(TN_E_INVALID, "plan has no evidence; pass -1");
+      if (p->mode == TN_EVIDENCE_SLICED && (e >= 0) != (bool)p->is_obs[v])
+        throw TnError(TN_E_INVALID, "evidence must give exactly the plan's observed variables");
+      h[(size_t)b * p->n_vars + v] = e;
+    }
+  hip_check(hipMemcpyAsync(p->d_evidence, h.data(), h.size() * 4, hipMemcpyHostToDevice, p->stream), "evidence upload");
+  hip_check(hipStreamSynchronize(p->stream), "evidence upload");
+}
+
+static void check_batch(tn_plan_t *p, int batch) {
+  if (batch < 1) throw TnError(TN_E_INVALID, "batch must be >= 1");
+  if (p->mode == TN_EVIDENCE_INDICATOR && batch > p->max_batch) throw TnError(TN_E_INVALID, "batch exceeds max_batch");
+  if (p->mode == TN_EVIDENCE_NONE && batch != 1) throw TnError(TN_E_INVALID, "mode NONE takes batch 1");
+}
+
+static void forward_sum(tn_plan_t *p, bool with_bwd) {
+  run_graph(p, with_bwd ? "sum+bwd" : "sum", [&] {
+    launch_prepare_set(p, p->leaves_sum, p->d_leaves_sum, true);
+    run_ops(p, p->sum_tree.ops);
+    const TensorBuf &r = p->T[p->sum_tree.root];
+    launch_logz(p->arena + r.off, r.batched ? r.size : 0, p->ex, r.slot, r.batched, p->max_batch, p->d_out, p->stream);
+    if (with_bwd) {
+      run_ops(p, p->bwd);
+      launch_marg(p->arena, p->d_marg_desc, (int)p->marg.size(), p->max_batch, p->marg_row, p->d_marg, p->stream);
+    }
+  });
+}
+
+template <class F>
+static void per_instance(tn_plan_t *p, int batch, const int32_t *ev, F &&f) {
+  // modes NONE / INDICATOR: one pass over the batch; SLICED: one pass each
+  if (p->mode == TN_EVIDENCE_SLICED) {
+    for (int b = 0; b < batch; ++b) f(b, 1, ev ? ev + (int64_t)b * p->n_vars : nullptr);
+  } else {
+    f(0, batch, ev);
+  }
+}
+
+extern "C" tn_status tn_logZ(tn_plan_t *p, int32_t batch, const int32_t *evidence, double *logz) {
+  return guard([&] {
+    if (!p || !logz) throw TnError(TN_E_INVALID, "NULL argument");
+    if (!p->want_sum || p->is_mmap) throw TnError(TN_E_UNSUPPORTED, "plan has no sum-product pass");
+    check_batch(p, batch);
+    per_instance(p, batch, evidence, [&](int b0, int nb, const int32_t *ev) {
+      upload_evidence(p, nb, ev);
+      forward_sum(p, false);
+      hip_check(hipMemcpyAsync(logz + b0, p->d_out, nb * sizeof(double), hipMemcpyDeviceToHost, p->stream), "D2H");
+      hip_check(hipStreamSynchronize(p->stream), "logZ");
+    });
+    for (int b = 0; b < batch; ++b)
+      if (!(logz[b] > -INFINITY)) throw TnError(TN_E_ZERO_EVIDENCE, "p(e) = 0 for instance " + std::to_string(b));
+  });
+}
+
+extern "C" tn_status tn_marginals(tn_plan_t *p, int32_t batch, const int32_t *evidence, double *logz,
+                                  double *marg) {
+  return guard([&] {
+    if (!p || !marg) throw TnError(TN_E_INVALID, "NULL argument");
+    if (!p->want_sum || p->is_mmap) throw TnError(TN_E_UNSUPPORTED, "plan has no sum-product pass");
+    check_batch(p, batch);
+    std::vector<double> lz(batch);
+    per_instance(p, batch, evidence, [&](int b0, int nb, const int32_t *ev) {
+      upload_evidence(p, nb, ev);
+      forward_sum(p, true);
+      hip_check(hipMemcpyAsync(lz.data() + b0, p->d_out, nb * sizeof(double), hipMemcpyDeviceToHost, p->stream), "D2H");
+      hip_check(hipMemcpyAsync(marg + (int64_t)b0 * p->marg_row, p->d_marg, (size_t)nb * p->marg_row * sizeof(double),
+                               hipMemcpyDeviceToHost, p->stream), "D2H");
+      hip_check(hipStreamSynchronize(p->stream), "marginals");
+      if (p->mode == TN_EVIDENCE_SLICED)
+        for (int v : p->observed) {
+          double *row = marg + (int64_t)b0 * p->marg_row + p->marg_col[v];
+          for (int x = 0; x < p->card[v]; ++x) row[x] = x == ev[v] ? 1.0 : 0.0;
+        }
+    });
+    if (logz) std::copy(lz.begin(), lz.end(), logz);
+    for (int b = 0; b < batch; ++b)
+      if (!(lz[b] > -INFINITY)) throw TnError(TN_E_ZERO_EVIDENCE, "p(e) = 0 for instance " + std::to_string(b));
+  });
+}
+
+extern "C" tn_status tn_map(tn_plan_t *p, int32_t batch, const int32_t *evidence, int32_t *assign, double *logp) {
+  return guard([&] {
+    if (!p || !assign) throw TnError(TN_E_INVALID, "NULL argument");
+    if (!p->want_max || p->is_mmap) throw TnError(TN_E_UNSUPPORTED, "plan has no max-plus pass");
+    check_batch(p, batch);
+    per_instance(p, batch, evidence, [&](int b0, int nb, const int32_t *ev) {
+      upload_evidence(p, nb, ev);
+      hip_check(hipMemcpyAsync(p->d_assign, p->d_evidence, (size_t)p->max_batch * p->n_vars * 4,
+                               hipMemcpyDeviceToDevice, p->stream), "init");
+      run_graph(p, "max", [&] {
+        launch_prepare_set(p, p->leaves_max, p->d_leaves_max, false);
+        run_ops(p, p->max_tree.ops);
+        launch_backtrack(p->iarena, p->d_back, (int)p->max_tree.back.size(), p->d_back_meta, p->n_vars,
+                         p->max_batch, p->d_assign, p->stream);
+      });
+      hip_check(hipMemcpyAsync(assign + (int64_t)b0 * p->n_vars, p->d_assign, (size_t)nb * p->n_vars * 4,
+                               hipMemcpyDeviceToHost, p->stream), "D2H");
+      const TensorBuf &r = p->T[p->max_tree.root];
+      std::vector<float> rv(nb);
+      for (int b = 0; b < nb; ++b)
+        hip_check(hipMemcpyAsync(&rv[b], p->arena + r.off + (r.batched ? (int64_t)b * r.size : 0), 4,
+                                 hipMemcpyDeviceToHost, p->stream), "D2H");
+      hip_check(hipStreamSynchronize(p->stream), "map");
+      if (logp)
+        for (int b = 0; b < nb; ++b) logp[b0 + b] = (double)rv[b];
+    });
+  });
+}
+
+extern "C" tn_status tn_sample(tn_plan_t *p, const int32_t *evidence, int64_t n, uint64_t seed, int32_t *samples) {
+  return guard([&] {
+    if (!p || (!samples && n > 0)) throw TnError(TN_E_INVALID, "NULL argument");
+    if (n < 0) throw TnError(TN_E_INVALID, "negative sample count");
+    if (!p->want_sum || p->is_mmap || p->mode == TN_EVIDENCE_INDICATOR)
+      throw TnError(TN_E_UNSUPPORTED, "sampling needs a sum-product plan without batched evidence");
+    upload_evidence(p, 1, evidence);
+    forward_sum(p, false);
+    std::vector<double> lz(1);
+    hip_check(hipMemcpyAsync(lz.data(), p->d_out, sizeof(double), hipMemcpyDeviceToHost, p->stream), "D2H");
+    hip_check(hipStreamSynchronize(p->stream), "sample forward");
+    if (!(lz[0] > -INFINITY)) throw TnError(TN_E_ZERO_EVIDENCE, "p(e) = 0");
+    if (n == 0) return;
+    if (n > p->samp_cap) {
+      if (p->d_samp_out) {
+        hip_check(hipFree(p->d_samp_out), "hipFree");
+        p->allocs.erase(std::find(p->allocs.begin(), p->allocs.end(), (void *)p->d_samp_out));
+      }
+      p->d_samp_out = dalloc<int32_t>(p, (size_t)n * p->n_vars);
+      p->samp_cap = n;
+    }
+    launch_sample(p->arena, p->d_samp, (int)p->samp.size(), p->d_samp_meta, p->n_vars, n, seed, p->d_evidence,
+                  p->d_samp_out, p->stream);
+    hip_check(hipGetLastError(), "sample launch");
+    hip_check(hipMemcpyAsync(samples, p->d_samp_out, (size_t)n * p->n_vars * 4, hipMemcpyDeviceToHost, p->stream), "D2H");
+    hip_check(hipStreamSynchronize(p->stream), "sample");
+  });
+}
+
+extern "C" tn_status tn_logZ_dev(tn_plan_t *p, const int32_t *evidence, const float *values_dev, double *logz_dev,
+                                 float *grad_dev) {
+  return guard([&] {
+    if (!p || !values_dev || !logz_dev) throw TnError(TN_E_INVALID, "NULL argument");
+    if (!p->want_sum || p->is_mmap || p->mode == TN_EVIDENCE_INDICATOR)
+      throw TnError(TN_E_UNSUPPORTED, "tn_logZ_dev needs a sum-product plan in mode NONE or SLICED");
+    if (grad_dev && !p->want_grad) throw TnError(TN_E_UNSUPPORTED, "plan built without want_factor_grad");
+    const tn_net *net = p->net_src;
+    upload_evidence(p, 1, evidence);
+    // factor store (linear) lives at arena offset 0
+    hip_check(hipMemcpyAsync(p->arena, values_dev, (size_t)net->n_values * 4, hipMemcpyDeviceToDevice, p->stream), "values");
+    forward_sum(p, grad_dev != nullptr);
+    hip_check(hipMemcpyAsync(logz_dev, p->d_out, sizeof(double), hipMemcpyDeviceToDevice, p->stream), "logz");
+    if (grad_dev) {
+      hip_check(hipMemsetAsync(grad_dev, 0, (size_t)net->n_values * 4, p->stream), "grad clear");
+      const TensorBuf &r = p->T[p->sum_tree.root];
+      launch_factor_grad(p->arena, p->d_grad_desc, (int)p->grads.size(), p->d_gmap, p->d_obs, p->d_evidence, p->ex,
+                         p->arena + r.off, r.slot, net->n_values, grad_dev, p->stream);
+      hip_check(hipGetLastError(), "grad launch");
+    }
+  });
+}
+
+extern "C" tn_status tn_sync(tn_plan_t *p) {
+  return guard([&] {
+    if (!p) throw TnError(TN_E_INVALID, "NULL plan");
+    hip_check(hipStreamSynchronize(p->stream), "sync");
+  });
+}
+
+// ---------------------------------------------------------------------------
+// MMAP (paper: section on maximum marginal a posteriori, eq. mmap)
+//   1. partition the factor tables so that every summed variable has all of
+//      its tables in one group (union-find over summed variables);
+//   2. contract every group with its query variables left open (sliced when
+//      an intermediate would exceed the size cap; slice results are summed);
+//   3. solve the MPE of the network of group results and query-only tables.
+// ---------------------------------------------------------------------------
+static int uf_find(std::vector<int> &u, int x) {
+  while (u[x] != x) x = u[x] = u[u[x]];
+  return x;
+}
+
+static void build_mmap(tn_plan_t *p, const tn_net *net) {
+  const tn_plan_opts &o = p->opts;
+  std::vector<char> isq(p->n_vars, 0);
+  for (int i = 0; i < o.n_query; ++i) {
+    int v = o.query[i];
+    if (v < 0 || v >= p->n_vars) throw TnError(TN_E_INVALID, "query variable out of range");
+    if (isq[v]) throw TnError(TN_E_INVALID, "query variable listed twice");
+    if (p->is_obs[v]) throw TnError(TN_E_INVALID, "query and evidence variables must be disjoint");
+    isq[v] = 1;
+  }
+  for (int v = 0; v < p->n_vars; ++v)
+    if (isq[v]) p->query.push_back(v);
+  const int F = (int)net->scope.size();
+  std::vector<int> uf(F);
+  std::iota(uf.begin(), uf.end(), 0);
+  std::vector<int> first(p->n_vars, -1);
+  std::vector<char> summed_in_factor(p->n_vars, 0);
+  for (int f = 0; f < F; ++f)
+    for (int v : net->scope[f]) {
+      if (isq[v] || p->is_obs[v]) continue;
+      summed_in_factor[v] = 1;
+      if (first[v] < 0) first[v] = f;
+      else uf[uf_find(uf, f)] = uf_find(uf, first[v]);
+    }
+  for (int v = 0; v < p->n_vars; ++v)
+    if (!isq[v] && !p->is_obs[v] && !summed_in_factor[v]) p->mmap_const += std::log((double)p->card[v]);
+  std::map<int, std::vector<int>> comp;
+  std::vector<int> qonly;
+  for (int f = 0; f < F; ++f) {
+    bool has_summed = false;
+    for (int v : net->scope[f])
+      if (!isq[v] && !p->is_obs[v]) has_summed = true;
+    if (has_summed) comp[uf_find(uf, f)].push_back(f);
+    else qonly.push_back(f);
+  }
+  std::vector<int> qleaf_tensor;
+  std::vector<Labels> qleaf_lab;
+  p->stats = TreeStats{};
+  for (auto &kv : comp) {
+    const std::vector<int> &fs = kv.second;
+    TreeExec t;
+    std::vector<Labels> labs;
+    Labels outq;
+    for (int f : fs) {
+      Labels l;
+      for (int v : net->scope[f])
+        if (!p->is_obs[v]) l.push_back(v);
+      std::sort(l.begin(), l.end());
+      for (int v : l)
+        if (isq[v]) outq.push_back(v);
+      labs.push_back(l);
+    }
+    std::sort(outq.begin(), outq.end());
+    outq.erase(std::unique(outq.begin(), outq.end()), outq.end());
+    PlanChoice pc = plan_tree(labs, p->card, outq, o.planner, o.restarts, o.seed);
+    Labels sl;
+    if (o.max_log2_size > 0 && pc.stats.sc > o.max_log2_size + 1e-9)
+      sl = choose_slices(labs, pc.pairs, outq, p->card, o.max_log2_size);
+    std::vector<char> fixed = p->is_obs;
+    for (int v : sl) fixed[v] = 1;
+    p->group_sliced_ptr.push_back((int)p->group_sliced_vars.size());
+    for (int v : sl) p->group_sliced_vars.push_back(v);
+    for (int v : sl) p->sliced.push_back(v);
+    std::vector<Labels> slabs;
+    std::vector<LeafDesc> gl;
+    for (size_t i = 0; i < fs.size(); ++i) {
+      Labels l;
+      for (int v : labs[i])
+        if (!fixed[v]) l.push_back(v);
+      slabs.push_back(l);
+      int tid = new_tensor(p, l, false, true);
+      LeafDesc d{};
+      d.kind = 0;
+      d.var = -1;
+      d.size = (int32_t)numel(l, p->card);
+      factor_gather(p, net, fs[i], fixed, d.gmap, d.obs_begin, d.obs_end);
+      d.src = net->val_off[fs[i]];
+      d.dst = tid;
+      d.slot = tid;
+      gl.push_back(d);
+      t.leaf_tensor.push_back(tid);
+    }
+    t.pairs = pc.pairs;
+    t.out = outq;
+    t.lab = node_labels(slabs, t.pairs, outq, p->n_vars);
+    TreeStats st = tree_stats(slabs, t.pairs, outq, p->card);
+    p->stats.sc = std::max(p->stats.sc, st.sc);
+    p->stats.sc_union = std::max(p->stats.sc_union, st.sc_union);
+    const double nsl = std::exp2(std::accumulate(sl.begin(), sl.end(), 0.0,
+                                                 [&](double a, int v) { return a + std::log2((double)p->card[v]); }));
+    p->stats.flops += st.flops * nsl;
+    p->stats.bytes += st.bytes * nsl;
+    build_forward(p, t, SEMI_SUM);
+    // log-domain copy of the group result: a leaf of the max phase
+    int lg = new_tensor(p, outq, false, false);
+    p->group_log.push_back(lg);
+    qleaf_tensor.push_back(lg);
+    qleaf_lab.push_back(outq);
+    p->groups.push_back(std::move(t));
+    p->group_leaves.push_back(std::move(gl));
+  }
+  p->group_sliced_ptr.push_back((int)p->group_sliced_vars.size());
+  p->stats.tc = p->stats.flops > 0 ? std::log2(p->stats.flops / 2) : 0;
+  // max phase leaves: query-only tables, then one zero vector per query
+  // variable so that every query variable is read out
+  for (int f : qonly) {
+    Labels l;
+    for (int v : net->scope[f])
+      if (!p->is_obs[v]) l.push_back(v);
+    std::sort(l.begin(), l.end());
+    int tid = new_tensor(p, l, false, false);
+    LeafDesc d{};
+    d.kind = 0;
+    d.size = (int32_t)numel(l, p->card);
+    factor_gather(p, net, f, p->is_obs, d.gmap, d.obs_begin, d.obs_end);
+    d.src = net->val_off[f];
+    d.dst = tid;
+    d.slot = -1;
+    d.maxdom = 1;
+    p->qleaves.push_back(d);
+    qleaf_tensor.push_back(tid);
+    qleaf_lab.push_back(l);
+  }
+  for (int v : p->query) {
+    int tid = new_tensor(p, Labels{v}, false, false);
+    LeafDesc d{};
+    d.kind = 1;
+    d.var = v;
+    d.size = p->card[v];
+    d.dst = tid;
+    d.slot = -1;
+    d.maxdom = 1;
+    p->qleaves.push_back(d);
+    qleaf_tensor.push_back(tid);
+    qleaf_lab.push_back(Labels{v});
+  }
+  TreeExec &q = p->qtree;
+  q.leaf_tensor = qleaf_tensor;
+  PlanChoice qc = plan_tree(qleaf_lab, p->card, {}, o.planner, o.restarts, o.seed);
+  q.pairs = qc.pairs;
+  q.out = {};
+  q.lab = node_labels(qleaf_lab, q.pairs, {}, p->n_vars);
+  build_forward(p, q, SEMI_MAX);
+  build_backtrack(p, q);
+}
+
+static void allocate_mmap(tn_plan_t *p) {
+  int64_t mx = 1;
+  for (size_t g = 0; g < p->groups.size(); ++g) mx = std::max(mx, p->T[p->groups[g].root].size);
+  p->d_acc = dalloc<double>(p, (size_t)mx + 64);
+}
+
+static void run_mmap(tn_plan_t *p, const int32_t *evidence, int32_t *assign_q, double *value) {
+  std::vector<int32_t> row(p->n_vars, -1);
+  for (int v = 0; v < p->n_vars; ++v) {
+    int e = evidence ? evidence[v] : -1;
+    if (e < -1 || e >= p->card[v]) throw TnError(TN_E_INVALID, "evidence value out of range");
+    if ((e >= 0) != (bool)p->is_obs[v]) throw TnError(TN_E_INVALID, "evidence must give exactly the plan's observed variables");
+    row[v] = e;
+  }
+  int32_t *acc_ex = p->iarena + p->iarena_ints;  // one int past the index arena
+  for (size_t g = 0; g < p->groups.size(); ++g) {
+    const TreeExec &t = p->groups[g];
+    const int sb = p->group_sliced_ptr[g], se = p->group_sliced_ptr[g + 1];
+    int64_t n_slices = 1;
+    for (int i = sb; i < se; ++i) n_slices *= p->card[p->group_sliced_vars[i]];
+    const TensorBuf &r = p->T[t.root];
+    for (int64_t s = 0; s < n_slices; ++s) {
+      int64_t k = s;
+      for (int i = se - 1; i >= sb; --i) {
+        const int v = p->group_sliced_vars[i];
+        row[v] = (int32_t)(k % p->card[v]);
+        k /= p->card[v];
+      }
+      hip_check(hipMemcpyAsync(p->d_evidence, row.data(), row.size() * 4, hipMemcpyHostToDevice, p->stream), "slice");
+      launch_prepare_set(p, p->group_leaves[g], p->d_group_leaves[g], true);
+      run_ops(p, t.ops);
+      launch_slice_acc(p->arena + r.off, p->mx, p->ex, r.slot, p->d_acc, acc_ex, r.size, s == 0 ? 1 : 0, p->stream);
+      hip_check(hipStreamSynchronize(p->stream), "slice");
+    }
+    for (int i = sb; i < se; ++i) row[p->group_sliced_vars[i]] = -1;
+    launch_acc_tolog(p->d_acc, acc_ex, r.size, p->arena + p->T[p->group_log[g]].off, p->stream);
+  }
+  hip_check(hipMemcpyAsync(p->d_evidence, row.data(), row.size() * 4, hipMemcpyHostToDevice, p->stream), "evidence");
+  hip_check(hipMemcpyAsync(p->d_assign, row.data(), row.size() * 4, hipMemcpyHostToDevice, p->stream), "init");
+  launch_prepare_set(p, p->qleaves, p->d_qleaves, false);
+  run_ops(p, p->qtree.ops);
+  launch_backtrack(p->iarena, p->d_qback, (int)p->qtree.back.size(), p->d_qback_meta, p->n_vars, 1, p->d_assign,
+                   p->stream);
+  hip_check(hipGetLastError(), "mmap launch");
+  std::vector<int32_t> a(p->n_vars);
+  float rv = 0;
+  hip_check(hipMemcpyAsync(a.data(), p->d_assign, a.size() * 4, hipMemcpyDeviceToHost, p->stream), "D2H");
+  hip_check(hipMemcpyAsync(&rv, p->arena + p->T[p->qtree.root].off, 4, hipMemcpyDeviceToHost, p->stream), "D2H");
+  hip_check(hipStreamSynchronize(p->stream), "mmap");
+  for (size_t i = 0; i < p->query.size(); ++i) assign_q[i] = a[p->query[i]];
+  if (value) *value = (double)rv + p->mmap_const;
+}
+
+extern "C" tn_status tn_mmap(tn_plan_t *p, const int32_t *evidence, int32_t *assign_q, double *log_value) {
+  return guard([&] {
+    if (!p || !assign_q) throw TnError(TN_E_INVALID, "NULL argument");
+    if (!p->is_mmap) throw TnError(TN_E_UNSUPPORTED, "plan has no query set");
+    run_mmap(p, evidence, assign_q, log_value);
+    if (!(*log_value > -INFINITY)) throw TnError(TN_E_ZERO_EVIDENCE, "p(e) = 0");
+  });
+}

@@ -1,0 +1,196 @@
+// Internal declarations shared by the host planner, the runtime and the
+// kernel launchers of libtn.
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/tn.h"
+
+struct TnError : std::runtime_error {
+  tn_status st;
+  TnError(tn_status s, const std::string &m) : std::runtime_error(m), st(s) {}
+};
+
+struct tn_net {
+  int n_vars = 0;
+  std::vector<int> card;
+  std::vector<std::vector<int>> scope;   // scope order as loaded
+  std::vector<std::vector<double>> vals; // linear or log, as loaded
+  std::vector<int64_t> val_off;          // offset of each factor in the flat store
+  int64_t n_values = 0;
+  bool is_log = false;
+};
+
+namespace tn {
+
+using Labels = std::vector<int>;  // variable ids, sorted ascending
+using Pair = std::array<int, 2>;
+
+// ---------------------------------------------------------------------------
+// Trees and planning (tn_planner.cpp)
+// ---------------------------------------------------------------------------
+
+// Output labels of every node of a binary tree (leaves first, then pairs in
+// post-order): a node keeps the labels of its children that still occur in a
+// leaf outside its subtree or in the requested output set.
+std::vector<Labels> node_labels(const std::vector<Labels> &leaves, const std::vector<Pair> &pairs,
+                                const Labels &out, int n_vars);
+
+struct TreeStats {
+  double sc = 0, sc_union = 0, tc = 0;  // log2
+  double flops = 0;                     // 2 * sum of union sizes
+  double bytes = 0;                     // 4 * sum over nodes (|A| + |B| + |C|)
+};
+TreeStats tree_stats(const std::vector<Labels> &leaves, const std::vector<Pair> &pairs,
+                     const Labels &out, const std::vector<int> &card);
+
+void validate_tree(int n_leaves, const std::vector<Pair> &pairs);
+
+struct PlanChoice {
+  std::vector<Pair> pairs;
+  TreeStats stats;
+  int planner = 0;
+};
+
+// Choose a contraction tree over the leaves; labels in `out` are never
+// eliminated.  `strategy` is a TN_PLANNER_* value.
+PlanChoice plan_tree(const std::vector<Labels> &leaves, const std::vector<int> &card,
+                     const Labels &out, int strategy, int restarts, uint64_t seed);
+
+// Pick labels to slice (fix per slice) so that every node output and every
+// node label union is at most 2^cap elements.
+Labels choose_slices(const std::vector<Labels> &leaves, const std::vector<Pair> &pairs,
+                     const Labels &out, const std::vector<int> &card, double cap);
+
+// ---------------------------------------------------------------------------
+// Kernel launch descriptors (tn_kernels.hip)
+// ---------------------------------------------------------------------------
+
+// Offset tables of one index class (rows, columns or summed labels) for one
+// tensor: offset(i) = hi[i / nlo] + lo[i % nlo].
+struct Tab2 {
+  const int32_t *hi = nullptr, *lo = nullptr;
+};
+
+struct ContractArgs {
+  const float *X = nullptr, *Y = nullptr;
+  float *Z = nullptr;
+  int32_t *I = nullptr;  // argmax output (max-plus)
+  int64_t bsX = 0, bsY = 0, bsZ = 0;
+  Tab2 rX, rY, rZ;  // rows: labels of Z that X holds
+  Tab2 cY, cZ;      // columns: labels of Z that X lacks
+  Tab2 sX, sY;      // summed: labels of X or Y not in Z
+  uint32_t nR = 1, nRl = 1, nC = 1, nCl = 1, nS = 1, nSl = 1;
+  int col_fastest = 0;
+  // power-of-two scaling slots (sum-product)
+  uint32_t *mx = nullptr;
+  int32_t *ex = nullptr;
+  int32_t slotX = -1, slotY = -1, slotZ = -1;
+  int32_t batX = 0, batY = 0, batZ = 0;  // 1 if the slot is per instance
+  // split reduction scratch
+  float *part = nullptr;
+  int32_t *parti = nullptr;
+  uint32_t n_chunks = 1;
+};
+
+enum Semiring { SEMI_SUM = 0, SEMI_MAX = 1 };
+
+void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, int nb,
+                     void *stream);
+
+struct LeafDesc {
+  int32_t kind;      // 0 factor gather, 1 constant one-vector, 2 indicator
+  int32_t var;       // indicator variable
+  int32_t size;      // elements per instance
+  int32_t batched;   // 1: one copy per instance
+  int64_t dst;       // float offset of the leaf tensor in the arena
+  int64_t src;       // float offset of the factor table in the arena
+  int32_t gmap;      // int32 offset of the gather map (size entries)
+  int32_t obs_begin, obs_end;  // (var, stride) pairs in the observation list
+  int32_t slot;      // mx slot (ex slot is the same index)
+  int32_t maxdom;    // 1: log domain (zero = -inf, one = 0)
+};
+
+struct PrepareArgs {
+  float *arena = nullptr;
+  const LeafDesc *leaves = nullptr;
+  int n_leaves = 0;
+  const int32_t *gmap = nullptr;
+  const int32_t *obs = nullptr;      // pairs (var, stride)
+  const int32_t *evidence = nullptr; // [batch][n_vars]
+  int n_vars = 0;
+  uint32_t *mx = nullptr;
+  int32_t *ex = nullptr;
+  int reset_begin = 0, reset_end = 0;  // slots zeroed each solve
+  int batch = 1;
+  int max_batch = 1;
+};
+void launch_prepare(const PrepareArgs &a, void *stream);
+
+void launch_logz(const float *root, int64_t bs, const int32_t *ex, int slot, int batched,
+                 int batch, double *out, void *stream);
+
+struct MargDesc {
+  int64_t adj;    // float offset of the unity/indicator adjoint
+  int64_t leaf;   // float offset of the unity/indicator leaf
+  int32_t card;
+  int32_t out;    // column offset in the marginal row
+  int32_t adj_batched, leaf_batched;
+  int64_t adj_bs, leaf_bs;
+};
+void launch_marg(const float *arena, const MargDesc *d, int n, int batch, int row, double *out,
+                 void *stream);
+
+struct GradDesc {
+  int64_t adj;       // float offset of the factor-leaf adjoint
+  int32_t size;      // leaf elements
+  int32_t slot;      // adjoint slot (exponent)
+  int64_t dst;       // offset of the factor in the gradient array
+  int32_t gmap;      // gather map of the leaf (leaf element -> table entry)
+  int32_t obs_begin, obs_end;
+};
+void launch_factor_grad(const float *arena, const GradDesc *d, int n, const int32_t *gmap,
+                        const int32_t *obs, const int32_t *evidence, const int32_t *ex,
+                        const float *root, int root_slot, int64_t n_values, float *grad,
+                        void *stream);
+
+// Argmax readout: steps run in order; each reads x at its input labels,
+// fetches an argmax index and decodes it into its output labels.
+struct BackStep {
+  int64_t arg;       // int32 offset of the argmax array in the index arena
+  int64_t bs;        // per-instance stride of the argmax array (0 = shared)
+  int32_t in_begin, in_end;    // (var, stride) pairs
+  int32_t out_begin, out_end;  // (var, card) pairs, last fastest
+};
+void launch_backtrack(const int32_t *iarena, const BackStep *steps, int n_steps,
+                      const int32_t *pairs, int n_vars, int batch, int32_t *assign,
+                      void *stream);
+
+// Top-down sampling steps (see tn_sample).
+struct SampleStep {
+  int64_t A, B;        // float offsets of the two children (B < 0: none)
+  int32_t node;        // tree node id (Philox counter word 2)
+  int32_t aIn_b, aIn_e;    // (var, stride in A) for A's labels already drawn
+  int32_t bIn_b, bIn_e;    // (var, stride in B)
+  int32_t k_b, k_e;        // (var, card, strideA, strideB): shared eliminated
+  int32_t pa_b, pa_e;      // (var, card, strideA, 0): A-private eliminated
+  int32_t pb_b, pb_e;      // (var, card, 0, strideB): B-private eliminated
+};
+void launch_sample(const float *arena, const SampleStep *steps, int n_steps, const int32_t *meta,
+                   int n_vars, int64_t n, uint64_t seed, const int32_t *init, int32_t *out,
+                   void *stream);
+
+void launch_tolog(const float *src, const int32_t *ex, int slot, int64_t n, float *dst,
+                  void *stream);
+
+// Accumulate a sliced partial result into an accumulator with exponent
+// alignment: acc = acc + src (both raw tables with exponents).
+void launch_slice_acc(const float *src, const uint32_t *mx, const int32_t *ex, int slot_src,
+                      double *acc, int32_t *acc_ex, int64_t n, int first, void *stream);
+void launch_acc_tolog(const double *acc, const int32_t *acc_ex, int64_t n, float *dst, void *stream);
+
+}  // namespace tn

@@ -1,0 +1,721 @@
+// HIP kernels of libtn for gfx950 (CDNA4, 64-wide wavefronts).
+//
+// One generic pairwise-contraction kernel family carries every tree node
+// (paper: eq. contraction-definition applied to two tensors; eq. tropical
+// for the max-plus algebra) and every adjoint contraction of the reverse
+// pass (eq. einback).  A contraction is described by index classes of the
+// output Z relative to the larger operand X and the smaller Y:
+//   rows    labels of Z held by X          (offsets in X, Y, Z)
+//   columns labels of Z not held by X      (offsets in Y, Z; broadcast when
+//                                           Y lacks them too)
+//   summed  labels of X or Y not in Z      (offsets in X, Y)
+// Each class owns split offset tables, offset(i) = hi[i / nlo] + lo[i % nlo],
+// so any interleaving of labels in the operands' layouts is a gather and no
+// separate transpose pass is needed; the row order follows the canonical
+// (sorted-label) layout so consecutive lanes touch consecutive addresses of
+// the operand that owns the fastest label.
+//   k_map    one lane per output element, summed labels looped in order;
+//   k_split  outputs few, summed set large: each workgroup reduces one chunk
+//            of the summed index for every output, k_split_finish combines
+//            the chunks in a fixed order (deterministic, no atomics on data).
+// Sum-product operands are rescaled on load by 2^-k with k the exponent of
+// the operand's recorded maximum; each launch records the maximum of its
+// output (atomicMax on the IEEE bits of non-negative floats) and its
+// exponent, so the value of a tensor is raw * 2^ex (per instance).
+// Max-plus keeps the first maximiser in canonical order of the summed
+// labels, and every candidate is exactly one FP32 addition.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "tn_internal.h"
+
+namespace tn {
+
+static constexpr int kBlock = 256;
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// exponent k of the recorded maximum m (m = f * 2^k, f in [0.5, 1)),
+// clamped so that 2^-k is a normal float
+__device__ __forceinline__ int max_exponent(uint32_t bits) {
+  float m = __uint_as_float(bits);
+  if (!(m > 0.f)) return 0;
+  int k;
+  frexpf(m, &k);
+  return k < -126 ? -126 : (k > 126 ? 126 : k);
+}
+
+__device__ __forceinline__ int32_t tab_off(const Tab2 &t, uint32_t i, uint32_t nlo) {
+  uint32_t h = i / nlo;
+  return t.hi[h] + t.lo[i - h * nlo];
+}
+
+// --------------------------------------------------------------------------
+// generic contraction, one lane per output element
+// --------------------------------------------------------------------------
+template <int SEMI, bool HASY>
+__global__ __launch_bounds__(kBlock) void k_map(ContractArgs a) {
+  const int b = blockIdx.y;
+  const float *__restrict__ X = a.X + (int64_t)b * a.bsX;
+  const float *__restrict__ Y = HASY ? a.Y + (int64_t)b * a.bsY : nullptr;
+  float *__restrict__ Z = a.Z + (int64_t)b * a.bsZ;
+  int32_t *__restrict__ I = SEMI == SEMI_MAX ? a.I + (int64_t)b * a.bsZ : nullptr;
+  float sx = 1.f, sy = 1.f;
+  int kx = 0, ky = 0;
+  if (SEMI == SEMI_SUM) {
+    kx = max_exponent(a.mx[a.slotX + (a.batX ? b : 0)]);
+    sx = ldexpf(1.f, -kx);
+    if (HASY) {
+      ky = max_exponent(a.mx[a.slotY + (a.batY ? b : 0)]);
+      sy = ldexpf(1.f, -ky);
+    }
+  }
+  const uint32_t n_out = a.nR * a.nC;
+  const uint32_t nSh = a.nS / a.nSl;
+  float lmax = 0.f;
+  for (uint32_t o = blockIdx.x * kBlock + threadIdx.x; o < n_out; o += gridDim.x * kBlock) {
+    uint32_t r, c;
+    if (a.col_fastest) {
+      r = o / a.nC;
+      c = o - r * a.nC;
+    } else {
+      c = o / a.nR;
+      r = o - c * a.nR;
+    }
+    const uint32_t rh = r / a.nRl, rl = r - rh * a.nRl;
+    const int32_t xo = a.rX.hi[rh] + a.rX.lo[rl];
+    int32_t zo = a.rZ.hi[rh] + a.rZ.lo[rl];
+    int32_t yo = HASY ? a.rY.hi[rh] + a.rY.lo[rl] : 0;
+    if (a.nC > 1) {
+      const uint32_t ch = c / a.nCl, cl = c - ch * a.nCl;
+      zo += a.cZ.hi[ch] + a.cZ.lo[cl];
+      if (HASY) yo += a.cY.hi[ch] + a.cY.lo[cl];
+    }
+    if (SEMI == SEMI_SUM) {
+      float acc = 0.f;
+      for (uint32_t sh = 0; sh < nSh; ++sh) {
+        const int32_t xs = xo + a.sX.hi[sh];
+        const int32_t ys = HASY ? yo + a.sY.hi[sh] : 0;
+        for (uint32_t sl = 0; sl < a.nSl; ++sl) {
+          const float xv = X[xs + a.sX.lo[sl]] * sx;
+          if (HASY)
+            acc = fmaf(xv, Y[ys + a.sY.lo[sl]] * sy, acc);
+          else
+            acc += xv;
+        }
+      }
+      Z[zo] = acc;
+      lmax = fmaxf(lmax, acc);
+    } else {
+      float best = -INFINITY;
+      int32_t bi = 0;
+      uint32_t s = 0;
+      for (uint32_t sh = 0; sh < nSh; ++sh) {
+        const int32_t xs = xo + a.sX.hi[sh];
+        const int32_t ys = HASY ? yo + a.sY.hi[sh] : 0;
+        for (uint32_t sl = 0; sl < a.nSl; ++sl, ++s) {
+          float v = X[xs + a.sX.lo[sl]];
+          if (HASY) v = v + Y[ys + a.sY.lo[sl]];
+          if (s == 0 || v > best) {
+            best = v;
+            bi = (int32_t)s;
+          }
+        }
+      }
+      Z[zo] = best;
+      I[zo] = bi;
+    }
+  }
+  if (SEMI == SEMI_SUM) {
+    lmax = wave_max(lmax);
+    if ((threadIdx.x & 63) == 0 && lmax > 0.f)
+      atomicMax(a.mx + a.slotZ + (a.batZ ? b : 0), __float_as_uint(lmax));
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      int e = a.ex[a.slotX + (a.batX ? b : 0)] + kx;
+      if (HASY) e += a.ex[a.slotY + (a.batY ? b : 0)] + ky;
+      a.ex[a.slotZ + (a.batZ ? b : 0)] = e;
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// generic contraction, summed index split across workgroups
+// --------------------------------------------------------------------------
+template <int SEMI, bool HASY>
+__global__ __launch_bounds__(kBlock) void k_split(ContractArgs a) {
+  const int b = blockIdx.y;
+  const uint32_t chunk = blockIdx.x;
+  const float *__restrict__ X = a.X + (int64_t)b * a.bsX;
+  const float *__restrict__ Y = HASY ? a.Y + (int64_t)b * a.bsY : nullptr;
+  float sx = 1.f, sy = 1.f;
+  if (SEMI == SEMI_SUM) {
+    sx = ldexpf(1.f, -max_exponent(a.mx[a.slotX + (a.batX ? b : 0)]));
+    if (HASY) sy = ldexpf(1.f, -max_exponent(a.mx[a.slotY + (a.batY ? b : 0)]));
+  }
+  const uint32_t nSh = a.nS / a.nSl;
+  const uint32_t per = (nSh + a.n_chunks - 1) / a.n_chunks;
+  const uint32_t h0 = chunk * per, h1 = min(nSh, h0 + per);
+  const uint32_t n_out = a.nR * a.nC;
+  __shared__ float sv[kBlock / 64];
+  __shared__ int32_t si[kBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (uint32_t o = 0; o < n_out; ++o) {
+    uint32_t r, c;
+    if (a.col_fastest) {
+      r = o / a.nC;
+      c = o - r * a.nC;
+    } else {
+      c = o / a.nR;
+      r = o - c * a.nR;
+    }
+    const uint32_t rh = r / a.nRl, rl = r - rh * a.nRl;
+    const int32_t xo = a.rX.hi[rh] + a.rX.lo[rl];
+    int32_t yo = HASY ? a.rY.hi[rh] + a.rY.lo[rl] : 0;
+    if (HASY && a.nC > 1) yo += tab_off(a.cY, c, a.nCl);
+    const size_t pidx = ((size_t)b * a.n_chunks + chunk) * n_out + o;
+    if (SEMI == SEMI_SUM) {
+      float acc = 0.f;
+      for (uint32_t sh = h0; sh < h1; ++sh) {
+        const int32_t xs = xo + a.sX.hi[sh];
+        const int32_t ys = HASY ? yo + a.sY.hi[sh] : 0;
+        for (uint32_t sl = threadIdx.x; sl < a.nSl; sl += kBlock) {
+          const float xv = X[xs + a.sX.lo[sl]] * sx;
+          if (HASY)
+            acc = fmaf(xv, Y[ys + a.sY.lo[sl]] * sy, acc);
+          else
+            acc += xv;
+        }
+      }
+      acc = wave_sum(acc);
+      if (lane == 0) sv[wid] = acc;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        float t = 0.f;
+        for (int w = 0; w < kBlock / 64; ++w) t += sv[w];
+        a.part[pidx] = t;
+      }
+      __syncthreads();
+    } else {
+      float best = -INFINITY;
+      int32_t bi = -1;
+      for (uint32_t sh = h0; sh < h1; ++sh) {
+        const int32_t xs = xo + a.sX.hi[sh];
+        const int32_t ys = HASY ? yo + a.sY.hi[sh] : 0;
+        for (uint32_t sl = threadIdx.x; sl < a.nSl; sl += kBlock) {
+          float v = X[xs + a.sX.lo[sl]];
+          if (HASY) v = v + Y[ys + a.sY.lo[sl]];
+          const int32_t s = (int32_t)(sh * a.nSl + sl);
+          if (bi < 0 || v > best) {
+            best = v;
+            bi = s;
+          }
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        float ov = __shfl_xor(best, off, 64);
+        int32_t oi = __shfl_xor(bi, off, 64);
+        if (oi >= 0 && (bi < 0 || ov > best || (ov == best && oi < bi))) {
+          best = ov;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        sv[wid] = best;
+        si[wid] = bi;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        float bv = sv[0];
+        int32_t bj = si[0];
+        for (int w = 1; w < kBlock / 64; ++w)
+          if (si[w] >= 0 && (bj < 0 || sv[w] > bv || (sv[w] == bv && si[w] < bj))) {
+            bv = sv[w];
+            bj = si[w];
+          }
+        a.part[pidx] = bv;
+        a.parti[pidx] = bj;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <int SEMI, bool HASY>
+__global__ __launch_bounds__(kBlock) void k_split_finish(ContractArgs a) {
+  const int b = blockIdx.y;
+  float *__restrict__ Z = a.Z + (int64_t)b * a.bsZ;
+  int32_t *__restrict__ I = SEMI == SEMI_MAX ? a.I + (int64_t)b * a.bsZ : nullptr;
+  const uint32_t n_out = a.nR * a.nC;
+  float lmax = 0.f;
+  for (uint32_t o = blockIdx.x * kBlock + threadIdx.x; o < n_out; o += gridDim.x * kBlock) {
+    uint32_t r, c;
+    if (a.col_fastest) {
+      r = o / a.nC;
+      c = o - r * a.nC;
+    } else {
+      c = o / a.nR;
+      r = o - c * a.nR;
+    }
+    int32_t zo = tab_off(a.rZ, r, a.nRl);
+    if (a.nC > 1) zo += tab_off(a.cZ, c, a.nCl);
+    const size_t base = (size_t)b * a.n_chunks * n_out + o;
+    if (SEMI == SEMI_SUM) {
+      float acc = 0.f;
+      for (uint32_t ch = 0; ch < a.n_chunks; ++ch) acc += a.part[base + (size_t)ch * n_out];
+      Z[zo] = acc;
+      lmax = fmaxf(lmax, acc);
+    } else {
+      float bv = -INFINITY;
+      int32_t bj = -1;
+      for (uint32_t ch = 0; ch < a.n_chunks; ++ch) {
+        const float v = a.part[base + (size_t)ch * n_out];
+        const int32_t i = a.parti[base + (size_t)ch * n_out];
+        if (i >= 0 && (bj < 0 || v > bv)) {
+          bv = v;
+          bj = i;
+        }
+      }
+      Z[zo] = bv;
+      I[zo] = bj < 0 ? 0 : bj;
+    }
+  }
+  if (SEMI == SEMI_SUM) {
+    lmax = wave_max(lmax);
+    if ((threadIdx.x & 63) == 0 && lmax > 0.f)
+      atomicMax(a.mx + a.slotZ + (a.batZ ? b : 0), __float_as_uint(lmax));
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      const int kx = max_exponent(a.mx[a.slotX + (a.batX ? b : 0)]);
+      int e = a.ex[a.slotX + (a.batX ? b : 0)] + kx;
+      if (HASY) e += a.ex[a.slotY + (a.batY ? b : 0)] + max_exponent(a.mx[a.slotY + (a.batY ? b : 0)]);
+      a.ex[a.slotZ + (a.batZ ? b : 0)] = e;
+    }
+  }
+}
+
+void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, int nb, void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  const uint32_t n_out = a.nR * a.nC;
+  if (!split) {
+    uint32_t blocks = (n_out + kBlock - 1) / kBlock;
+    if (blocks > 65535u) blocks = 65535u;
+    dim3 g(blocks, nb);
+    if (semi == SEMI_SUM) {
+      if (has_y) k_map<SEMI_SUM, true><<<g, kBlock, 0, s>>>(a);
+      else k_map<SEMI_SUM, false><<<g, kBlock, 0, s>>>(a);
+    } else {
+      if (has_y) k_map<SEMI_MAX, true><<<g, kBlock, 0, s>>>(a);
+      else k_map<SEMI_MAX, false><<<g, kBlock, 0, s>>>(a);
+    }
+    return;
+  }
+  dim3 g(a.n_chunks, nb);
+  uint32_t fb = (n_out + kBlock - 1) / kBlock;
+  dim3 gf(fb > 65535u ? 65535u : fb, nb);
+  if (semi == SEMI_SUM) {
+    if (has_y) {
+      k_split<SEMI_SUM, true><<<g, kBlock, 0, s>>>(a);
+      k_split_finish<SEMI_SUM, true><<<gf, kBlock, 0, s>>>(a);
+    } else {
+      k_split<SEMI_SUM, false><<<g, kBlock, 0, s>>>(a);
+      k_split_finish<SEMI_SUM, false><<<gf, kBlock, 0, s>>>(a);
+    }
+  } else {
+    if (has_y) {
+      k_split<SEMI_MAX, true><<<g, kBlock, 0, s>>>(a);
+      k_split_finish<SEMI_MAX, true><<<gf, kBlock, 0, s>>>(a);
+    } else {
+      k_split<SEMI_MAX, false><<<g, kBlock, 0, s>>>(a);
+      k_split_finish<SEMI_MAX, false><<<gf, kBlock, 0, s>>>(a);
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// leaf preparation: evidence slicing (gather), indicator vectors, maxima;
+// extra blocks clear the maxima of the tensors produced in this solve
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_prepare(PrepareArgs a) {
+  const int b = blockIdx.y;
+  if ((int)blockIdx.x >= a.n_leaves) {
+    if (b != 0) return;
+    const int n = a.reset_end - a.reset_begin;
+    for (int i = (blockIdx.x - a.n_leaves) * kBlock + threadIdx.x; i < n;
+         i += (gridDim.x - a.n_leaves) * kBlock)
+      a.mx[a.reset_begin + i] = 0u;
+    return;
+  }
+  const LeafDesc d = a.leaves[blockIdx.x];
+  if (!d.batched && b > 0) return;
+  const int row = d.batched ? b : 0;
+  float *dst = a.arena + d.dst + (d.batched ? (int64_t)b * d.size : 0);
+  const float one = d.maxdom ? 0.f : 1.f;
+  const float zero = d.maxdom ? -INFINITY : 0.f;
+  float lmax = 0.f;
+  if (d.kind == 0) {
+    int64_t base = 0;
+    for (int o = d.obs_begin; o < d.obs_end; ++o)
+      base += (int64_t)a.evidence[(int64_t)row * a.n_vars + a.obs[2 * o]] * a.obs[2 * o + 1];
+    const float *src = a.arena + d.src + base;
+    for (int i = threadIdx.x; i < d.size; i += kBlock) {
+      const float v = src[a.gmap[d.gmap + i]];
+      dst[i] = v;
+      lmax = fmaxf(lmax, fabsf(v));
+    }
+  } else if (d.kind == 1) {
+    for (int i = threadIdx.x; i < d.size; i += kBlock) dst[i] = one;
+    lmax = 1.f;
+  } else {
+    const int e = a.evidence[(int64_t)row * a.n_vars + d.var];
+    for (int i = threadIdx.x; i < d.size; i += kBlock) dst[i] = (e < 0 || e == i) ? one : zero;
+    lmax = 1.f;
+  }
+  __shared__ float sm[kBlock / 64];
+  lmax = wave_max(lmax);
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = lmax;
+  __syncthreads();
+  if (threadIdx.x == 0 && d.slot >= 0) {
+    float m = sm[0];
+    for (int w = 1; w < kBlock / 64; ++w) m = fmaxf(m, sm[w]);
+    a.mx[d.slot + (d.batched ? b : 0)] = __float_as_uint(m);
+    a.ex[d.slot + (d.batched ? b : 0)] = 0;
+  }
+}
+
+void launch_prepare(const PrepareArgs &a, void *stream) {
+  const int reset_blocks = (a.reset_end - a.reset_begin + kBlock - 1) / kBlock;
+  dim3 g(a.n_leaves + (reset_blocks > 0 ? (reset_blocks > 1024 ? 1024 : reset_blocks) : 0),
+         a.batch);
+  if (g.x == 0) return;
+  k_prepare<<<g, kBlock, 0, (hipStream_t)stream>>>(a);
+}
+
+// --------------------------------------------------------------------------
+// log Z per instance, in FP64: ln(root) + ex * ln 2
+// --------------------------------------------------------------------------
+__global__ void k_logz(const float *root, int64_t bs, const int32_t *ex, int slot, int batched,
+                       int batch, double *out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  const float z = root[(int64_t)b * bs];
+  const int e = ex[slot + (batched ? b : 0)];
+  out[b] = z > 0.f ? log((double)z) + (double)e * 0.69314718055994530942 : -INFINITY;
+}
+
+void launch_logz(const float *root, int64_t bs, const int32_t *ex, int slot, int batched, int batch,
+                 double *out, void *stream) {
+  k_logz<<<(batch + 63) / 64, 64, 0, (hipStream_t)stream>>>(root, bs, ex, slot, batched, batch, out);
+}
+
+// --------------------------------------------------------------------------
+// marginals: p(v = x | e) = adj(x) * lambda(x) / sum (MAR algorithm step 3)
+// --------------------------------------------------------------------------
+__global__ void k_marg(const float *arena, const MargDesc *d, int n, int batch, int row,
+                       double *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int b = blockIdx.y;
+  if (i >= n || b >= batch) return;
+  const MargDesc m = d[i];
+  const float *adj = arena + m.adj + (m.adj_batched ? (int64_t)b * m.adj_bs : 0);
+  const float *lam = arena + m.leaf + (m.leaf_batched ? (int64_t)b * m.leaf_bs : 0);
+  double tot = 0.0;
+  for (int x = 0; x < m.card; ++x) tot += (double)adj[x] * (double)lam[x];
+  for (int x = 0; x < m.card; ++x)
+    out[(int64_t)b * row + m.out + x] = tot > 0.0 ? (double)adj[x] * (double)lam[x] / tot : 0.0;
+}
+
+void launch_marg(const float *arena, const MargDesc *d, int n, int batch, int row, double *out,
+                 void *stream) {
+  if (n <= 0) return;
+  dim3 g((n + 63) / 64, batch);
+  k_marg<<<g, 64, 0, (hipStream_t)stream>>>(arena, d, n, batch, row, out);
+}
+
+// --------------------------------------------------------------------------
+// d logZ / d T_f = adjoint / Z, scattered back through the leaf gather map
+// --------------------------------------------------------------------------
+__global__ void k_factor_grad(const float *arena, const GradDesc *d, int n, const int32_t *gmap,
+                              const int32_t *obs, const int32_t *evidence, const int32_t *ex,
+                              const float *root, int root_slot, float *grad) {
+  const int f = blockIdx.x;
+  if (f >= n) return;
+  const GradDesc g = d[f];
+  const double z = (double)root[0];
+  const int er = ex[root_slot];
+  int64_t base = 0;
+  for (int o = g.obs_begin; o < g.obs_end; ++o) base += (int64_t)evidence[obs[2 * o]] * obs[2 * o + 1];
+  const double sc = ldexp(1.0, ex[g.slot] - er) / z;
+  for (int i = threadIdx.x; i < g.size; i += blockDim.x)
+    grad[g.dst + base + gmap[g.gmap + i]] = (float)((double)arena[g.adj + i] * sc);
+}
+
+void launch_factor_grad(const float *arena, const GradDesc *d, int n, const int32_t *gmap,
+                        const int32_t *obs, const int32_t *evidence, const int32_t *ex,
+                        const float *root, int root_slot, int64_t n_values, float *grad,
+                        void *stream) {
+  (void)n_values;
+  if (n <= 0) return;
+  k_factor_grad<<<n, 256, 0, (hipStream_t)stream>>>(arena, d, n, gmap, obs, evidence, ex, root,
+                                                    root_slot, grad);
+}
+
+// --------------------------------------------------------------------------
+// argmax readout (MPE configuration), one lane per instance
+// --------------------------------------------------------------------------
+__global__ void k_backtrack(const int32_t *iarena, const BackStep *steps, int n_steps,
+                            const int32_t *pairs, int n_vars, int batch, int32_t *assign) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  int32_t *x = assign + (int64_t)b * n_vars;
+  for (int st = 0; st < n_steps; ++st) {
+    const BackStep s = steps[st];
+    int64_t off = 0;
+    bool ok = true;
+    for (int i = s.in_begin; i < s.in_end; ++i) {
+      const int32_t xv = x[pairs[2 * i]];
+      ok = ok && xv >= 0;
+      off += (int64_t)xv * pairs[2 * i + 1];
+    }
+    if (!ok) continue;  // an input left unassigned: leave this step's outputs unset
+    int32_t k = iarena[s.arg + (int64_t)b * s.bs + off];
+    for (int j = s.out_end - 1; j >= s.out_begin; --j) {
+      const int c = pairs[2 * j + 1];
+      x[pairs[2 * j]] = k % c;
+      k /= c;
+    }
+  }
+}
+
+void launch_backtrack(const int32_t *iarena, const BackStep *steps, int n_steps, const int32_t *pairs,
+                      int n_vars, int batch, int32_t *assign, void *stream) {
+  k_backtrack<<<(batch + 63) / 64, 64, 0, (hipStream_t)stream>>>(iarena, steps, n_steps, pairs,
+                                                                 n_vars, batch, assign);
+}
+
+// --------------------------------------------------------------------------
+// sampling along the tree (eq. sample / eq. condition-prob)
+// --------------------------------------------------------------------------
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplications with the Weyl-sequence key schedule.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    c[1] = (uint32_t)p1;
+    c[3] = (uint32_t)p0;
+    c[0] = n0;
+    c[2] = n2;
+  }
+}
+
+__device__ __forceinline__ double uniform53(uint64_t sample, uint32_t node, uint32_t slot,
+                                            uint64_t seed) {
+  uint32_t c[4] = {(uint32_t)sample, (uint32_t)(sample >> 32), node, slot};
+  philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  return ((double)(c[0] >> 5) * 67108864.0 + (double)(c[1] >> 6)) * (1.0 / 9007199254740992.0);
+}
+
+// meta quadruples (var, card, strideA, strideB)
+__device__ __forceinline__ void decode_offsets(int64_t k, const int32_t *q, int qb, int qe,
+                                               int64_t &oa, int64_t &ob) {
+  oa = 0;
+  ob = 0;
+  for (int j = qe - 1; j >= qb; --j) {
+    const int c = q[4 * j + 1];
+    const int64_t d = k % c;
+    k /= c;
+    oa += d * q[4 * j + 2];
+    ob += d * q[4 * j + 3];
+  }
+}
+__device__ __forceinline__ void decode_assign(int64_t k, const int32_t *q, int qb, int qe, int32_t *x) {
+  for (int j = qe - 1; j >= qb; --j) {
+    const int c = q[4 * j + 1];
+    x[q[4 * j]] = (int32_t)(k % c);
+    k /= c;
+  }
+}
+__device__ __forceinline__ int64_t count_of(const int32_t *q, int qb, int qe) {
+  int64_t n = 1;
+  for (int j = qb; j < qe; ++j) n *= q[4 * j + 1];
+  return n;
+}
+
+__global__ void k_sample(const float *arena, const SampleStep *steps, int n_steps, const int32_t *q,
+                         int n_vars, int64_t n, uint64_t seed, const int32_t *init, int32_t *out) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  int32_t *x = out + s * n_vars;
+  for (int v = 0; v < n_vars; ++v) x[v] = init[v];
+  for (int t = 0; t < n_steps; ++t) {
+    const SampleStep st = steps[t];
+    const float *A = arena + st.A;
+    const float *B = st.B >= 0 ? arena + st.B : nullptr;
+    int64_t oa = 0, ob = 0;
+    bool ok = true;
+    for (int i = st.aIn_b; i < st.aIn_e; ++i) {
+      ok = ok && x[q[4 * i]] >= 0;
+      oa += (int64_t)x[q[4 * i]] * q[4 * i + 2];
+    }
+    for (int i = st.bIn_b; i < st.bIn_e; ++i) {
+      ok = ok && x[q[4 * i]] >= 0;
+      ob += (int64_t)x[q[4 * i]] * q[4 * i + 3];
+    }
+    if (!ok) continue;  // an input left unassigned: leave this step's outputs unset
+    // shared eliminated labels: w(k) = (sum_pa A) * (sum_pb B)
+    if (st.k_e > st.k_b) {
+      const int64_t nK = count_of(q, st.k_b, st.k_e);
+      const int64_t nPa = count_of(q, st.pa_b, st.pa_e), nPb = count_of(q, st.pb_b, st.pb_e);
+      auto weight = [&](int64_t k) {
+        int64_t ka, kb;
+        decode_offsets(k, q, st.k_b, st.k_e, ka, kb);
+        double wa = 0.0, wb = 0.0;
+        for (int64_t p = 0; p < nPa; ++p) {
+          int64_t pa, dummy;
+          decode_offsets(p, q, st.pa_b, st.pa_e, pa, dummy);
+          wa += (double)A[oa + ka + pa];
+        }
+        if (B) {
+          for (int64_t p = 0; p < nPb; ++p) {
+            int64_t dummy, pb;
+            decode_offsets(p, q, st.pb_b, st.pb_e, dummy, pb);
+            wb += (double)B[ob + kb + pb];
+          }
+        } else {
+          wb = 1.0;
+        }
+        return wa * wb;
+      };
+      double tot = 0.0;
+      for (int64_t k = 0; k < nK; ++k) tot += weight(k);
+      const double target = uniform53((uint64_t)s, (uint32_t)st.node, 0u, seed) * tot;
+      double cum = 0.0;
+      int64_t pick = -1, last = 0;
+      for (int64_t k = 0; k < nK; ++k) {
+        const double w = weight(k);
+        if (w > 0.0) last = k;
+        cum += w;
+        if (w > 0.0 && cum > target) {
+          pick = k;
+          break;
+        }
+      }
+      if (pick < 0) pick = last;
+      int64_t ka, kb;
+      decode_offsets(pick, q, st.k_b, st.k_e, ka, kb);
+      decode_assign(pick, q, st.k_b, st.k_e, x);
+      oa += ka;
+      ob += kb;
+    }
+    // private labels of each child, drawn from the child itself
+    for (int side = 0; side < 2; ++side) {
+      const int pb = side ? st.pb_b : st.pa_b, pe = side ? st.pb_e : st.pa_e;
+      if (pe <= pb) continue;
+      const float *T = side ? B : A;
+      const int64_t base = side ? ob : oa;
+      const int64_t nP = count_of(q, pb, pe);
+      double tot = 0.0;
+      for (int64_t p = 0; p < nP; ++p) {
+        int64_t da, db;
+        decode_offsets(p, q, pb, pe, da, db);
+        tot += (double)T[base + (side ? db : da)];
+      }
+      const double target = uniform53((uint64_t)s, (uint32_t)st.node, 1u + side, seed) * tot;
+      double cum = 0.0;
+      int64_t pick = -1, last = 0;
+      for (int64_t p = 0; p < nP; ++p) {
+        int64_t da, db;
+        decode_offsets(p, q, pb, pe, da, db);
+        const double w = (double)T[base + (side ? db : da)];
+        if (w > 0.0) last = p;
+        cum += w;
+        if (w > 0.0 && cum > target) {
+          pick = p;
+          break;
+        }
+      }
+      if (pick < 0) pick = last;
+      decode_assign(pick, q, pb, pe, x);
+    }
+  }
+}
+
+void launch_sample(const float *arena, const SampleStep *steps, int n_steps, const int32_t *meta,
+                   int n_vars, int64_t n, uint64_t seed, const int32_t *init, int32_t *out,
+                   void *stream) {
+  if (n <= 0) return;
+  const int64_t blocks = (n + 63) / 64;
+  k_sample<<<(unsigned)blocks, 64, 0, (hipStream_t)stream>>>(arena, steps, n_steps, meta, n_vars, n,
+                                                            seed, init, out);
+}
+
+// --------------------------------------------------------------------------
+// domain conversion for the MMAP max phase: log(raw) + ex * ln 2 (FP64 math)
+// --------------------------------------------------------------------------
+__global__ void k_tolog(const float *src, const int32_t *ex, int slot, int64_t n, float *dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float v = src[i];
+  dst[i] = v > 0.f ? (float)(log((double)v) + (double)ex[slot] * 0.69314718055994530942) : -INFINITY;
+}
+
+void launch_tolog(const float *src, const int32_t *ex, int slot, int64_t n, float *dst, void *stream) {
+  if (n <= 0) return;
+  k_tolog<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(src, ex, slot, n, dst);
+}
+
+// --------------------------------------------------------------------------
+// slice accumulation (FP64): acc = sum over slices of raw * 2^ex; the first
+// slice fixes the reference exponent acc_ex
+// --------------------------------------------------------------------------
+__global__ void k_slice_acc(const float *src, const int32_t *ex, int slot, double *acc,
+                            int32_t *acc_ex, int64_t n, int first) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int es = ex[slot];
+  if (first) {
+    if (i == 0) acc_ex[0] = es;
+    if (i < n) acc[i] = (double)src[i];
+  } else if (i < n) {
+    acc[i] += ldexp((double)src[i], es - acc_ex[0]);
+  }
+}
+
+void launch_slice_acc(const float *src, const uint32_t *mx, const int32_t *ex, int slot_src, double *acc,
+                      int32_t *acc_ex, int64_t n, int first, void *stream) {
+  (void)mx;
+  k_slice_acc<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(src, ex, slot_src, acc, acc_ex, n,
+                                                                             first);
+}
+
+__global__ void k_acc_tolog(const double *acc, const int32_t *acc_ex, int64_t n, float *dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = acc[i];
+  dst[i] = v > 0.0 ? (float)(log(v) + (double)acc_ex[0] * 0.69314718055994530942) : -INFINITY;
+}
+
+void launch_acc_tolog(const double *acc, const int32_t *acc_ex, int64_t n, float *dst, void *stream) {
+  if (n <= 0) return;
+  k_acc_tolog<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(acc, acc_ex, n, dst);
+}
+
+}  // namespace tn

@@ -1,0 +1,147 @@
+// Plan structures of libtn (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "tn_internal.h"
+
+namespace tn {
+
+// A tensor resident in the float arena.  Values are row-major over the
+// sorted labels (last label fastest); batched tensors hold one copy per
+// instance (instance outermost).  Sum-product tensors carry a scaling slot:
+// value = raw * 2^ex[slot (+ instance)].
+struct TensorBuf {
+  Labels lab;
+  int64_t size = 1;      // elements per instance
+  bool batched = false;
+  int64_t off = -1;      // float offset in the arena
+  int slot = -1;         // first scaling slot, -1 for max-plus tensors
+};
+
+struct IntBuf {
+  int64_t size = 1;
+  bool batched = false;
+  int64_t off = -1;      // int32 offset in the index arena
+};
+
+// One launch of the generic contraction kernel.
+struct Op {
+  int semi = SEMI_SUM;
+  int X = -1, Y = -1, Z = -1, I = -1;  // tensor ids; I = argmax IntBuf id
+  bool split = false;
+  int nb = 1;
+  ContractArgs a;                     // pointers filled after allocation
+  // table offsets into the host table store (-1 = unused)
+  int64_t t_rX[2], t_rY[2], t_rZ[2], t_cY[2], t_cZ[2], t_sX[2], t_sY[2];
+  double flops = 0, bytes = 0;        // algorithmic, per instance
+};
+
+// A contraction tree bound to tensors.
+struct TreeExec {
+  std::vector<int> leaf_tensor;       // tensor id of every leaf
+  std::vector<Pair> pairs;
+  Labels out;
+  std::vector<Labels> lab;            // node labels (leaves, then pairs)
+  std::vector<int> node_tensor;       // tensor id of every node
+  int root = -1;                      // tensor holding the result over `out`
+  std::vector<Op> ops;
+  std::vector<std::vector<int>> node_ops;  // op indices per pair (reductions, then main)
+  int root_op = -1;                   // op reducing the root to `out`, if any
+  // max-plus only: readout steps
+  std::vector<BackStep> back;
+  std::vector<int32_t> back_meta;
+};
+
+}  // namespace tn
+
+struct tn_plan_impl {
+  tn_plan_opts opts{};
+  const tn_net *net_src = nullptr;     // not owned; copied fields below
+  int n_vars = 0;
+  std::vector<int> card;
+  int mode = 0;
+  int max_batch = 1;
+  bool want_sum = false, want_max = false, want_grad = false, is_mmap = false;
+  std::vector<int> observed;           // mode SLICED
+  std::vector<char> is_obs;
+
+  // leaves of the main tree
+  std::vector<tn::Labels> leaf_lab;
+  std::vector<int> leaf_kind;          // 0 factor, 1 unity, 2 indicator
+  std::vector<int> leaf_var, leaf_factor;
+  std::vector<tn::Pair> pairs;
+  tn::TreeStats stats;
+  int planner_used = 0;
+  std::vector<int> sliced;
+
+  // tensors
+  std::vector<tn::TensorBuf> T;
+  std::vector<tn::IntBuf> IB;
+  int n_slots = 0;
+  int reset_begin = 0, reset_end = 0;
+  std::vector<int32_t> tabs;           // host copy of offset tables
+  std::vector<int32_t> gmap;           // leaf gather maps
+  std::vector<int32_t> obs;            // (var, stride) pairs
+  std::vector<tn::LeafDesc> leaves_sum, leaves_max;
+
+  // executable pieces
+  tn::TreeExec sum_tree, max_tree;
+  std::vector<tn::Op> bwd;
+  int seed_tensor = -1;                // adjoint of the root (ones)
+  std::vector<int> adj_tensor;         // per node of sum_tree, -1 = none
+  std::vector<tn::MargDesc> marg;
+  std::vector<tn::GradDesc> grads;
+  std::vector<tn::SampleStep> samp;
+  std::vector<int32_t> samp_meta;
+  std::vector<int> marg_col;           // column offset of each variable
+  int marg_row = 0;
+
+  // MMAP
+  std::vector<tn::TreeExec> groups;    // sum phase, one tree per group
+  std::vector<std::vector<tn::LeafDesc>> group_leaves;
+  std::vector<int> group_log;          // tensor id of the log-domain copy of each group root
+  tn::TreeExec qtree;                  // max phase over the query variables
+  std::vector<tn::LeafDesc> qleaves;
+  std::vector<int> query;              // sorted
+  double mmap_const = 0.0;             // log of summed variables in no factor
+  std::vector<int> group_sliced_vars;  // per group: sliced variables (flattened)
+  std::vector<int> group_sliced_ptr;
+
+  // device
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  float *arena = nullptr;
+  int32_t *iarena = nullptr;
+  uint32_t *mx = nullptr;
+  int32_t *ex = nullptr;
+  int32_t *d_tabs = nullptr, *d_gmap = nullptr, *d_obs = nullptr;
+  int32_t *d_evidence = nullptr;       // [max_batch][n_vars]
+  int32_t *d_assign = nullptr;         // [max_batch][n_vars]
+  double *d_out = nullptr;             // logz [max_batch]
+  double *d_marg = nullptr;            // [max_batch][marg_row]
+  tn::LeafDesc *d_leaves_sum = nullptr, *d_leaves_max = nullptr, *d_qleaves = nullptr;
+  std::vector<tn::LeafDesc *> d_group_leaves;
+  tn::MargDesc *d_marg_desc = nullptr;
+  tn::GradDesc *d_grad_desc = nullptr;
+  tn::BackStep *d_back = nullptr, *d_qback = nullptr;
+  int32_t *d_back_meta = nullptr, *d_qback_meta = nullptr;
+  tn::SampleStep *d_samp = nullptr;
+  int32_t *d_samp_meta = nullptr;
+  int32_t *d_samp_out = nullptr;
+  int64_t samp_cap = 0;
+  float *d_part = nullptr;
+  int32_t *d_parti = nullptr;
+  double *d_acc = nullptr;             // MMAP slice accumulator
+  int64_t arena_floats = 0, iarena_ints = 0, part_floats = 0;
+  int64_t device_bytes = 0;
+  std::vector<void *> allocs;
+
+  std::map<std::string, hipGraphExec_t> graphs;
+  ~tn_plan_impl();
+};

@@ -1,0 +1,79 @@
+"""Host-side checks of libtn (no GPU needed): exports, validation, planner."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_14060_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def T():
+    import paper_2405_14060_amd as T
+    if not os.path.exists(os.path.join(ROOT, "paper_2405_14060_amd", "libtn.so")):
+        from paper_2405_14060_amd import build
+        build.build()
+    T.lib()
+    return T
+
+
+def test_exports_every_declared_symbol(T):
+    hdr = open(os.path.join(ROOT, "include", "tn.h")).read()
+    names = set(re.findall(r"\b(tn_[a-z_A-Z0-9]+)\s*\(", hdr))
+    assert {"tn_load_network", "tn_plan", "tn_logZ", "tn_marginals", "tn_map", "tn_mmap", "tn_sample"} <= names
+    L = T.lib()
+    for n in sorted(names):
+        assert hasattr(L, n), n
+
+
+def test_load_network_validation(T):
+    with pytest.raises(T.TNError):
+        T.Network(W.Network(np.array([2, 0], np.int32), [np.array([0], np.int32)], [np.ones(2)], False))
+    with pytest.raises(T.TNError):
+        T.Network(W.Network(np.array([2], np.int32), [np.array([0], np.int32)], [np.array([1.0, np.nan])], False))
+    with pytest.raises(T.TNError):
+        T.Network(W.Network(np.array([2], np.int32), [np.array([0], np.int32)], [np.array([1.0, -1.0])], False))
+    with pytest.raises(T.TNError):
+        T.Network(W.Network(np.array([2], np.int32), [np.array([3], np.int32)], [np.ones(2)], False))
+
+
+@pytest.mark.parametrize("planner", [0, 1, 2, 3, 4])
+def test_planner_tree_is_valid_and_stats_agree(T, planner):
+    net = W.random_small_mrf(20, 30, seed=planner, cards=(2, 3))
+    pairs, L, info = T.plan_tree_host(T.Network(net), planner=planner, restarts=2)
+    lv = oracle.build_leaves(net)
+    assert L == len(lv)
+    assert pairs.shape == (L - 1, 2)
+    used = np.bincount(pairs.ravel(), minlength=2 * L - 1)
+    assert np.all(used[:-1] == 1) and used[-1] == 0
+    for i, (a, b) in enumerate(pairs):
+        assert a < L + i and b < L + i
+    st = oracle.tree_stats(lv.labels, pairs, lv.card)
+    assert abs(st["sc"] - info["sc"]) < 1e-9
+    assert abs(st["tc"] - info["tc"]) < 1e-9
+
+
+def test_planner_grid20_reaches_sweep_width(T):
+    pairs, L, info = T.plan_tree_host(T.Network(W.grid_mrf(20, 20, 0)), restarts=2)
+    assert info["sc"] <= 21
+
+
+def test_planner_slicing_cap(T):
+    c = W.config(4, seed=0, small=True)
+    pairs, L, info = T.plan_tree_host(T.Network(c["net"]), max_log2_size=6)
+    if info["sc"] > 6:
+        assert info["n_sliced"] > 0
+
+
+def test_plan_tree_rejects_bad_tree_on_host(T):
+    """Tree validation happens before any device work."""
+    from paper_2405_14060_amd._capi import TN_E_INVALID
+    net = W.grid_mrf(2, 2, 0)
+    N = T.Network(net)
+    with pytest.raises(T.TNError) as ei:
+        T.Plan(N, tree=np.array([[0, 1]], np.int32))
+    assert ei.value.status == TN_E_INVALID

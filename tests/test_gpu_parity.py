@@ -1,0 +1,366 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances: log Z relative error <= 1e-5 * max(1, |log Z|) for FP32 storage;
+marginals max-abs error <= 1e-5; MAP assignments and values bit-exact against
+the oracle's FP32 emulation on the same tree, and equal to the FP64 optimum
+unless the oracle certifies a near-tie.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.brute as bf
+from paper_2405_14060_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def T(gpu):
+    import paper_2405_14060_amd as T
+    T.lib()
+    return T
+
+
+def rel(a, b):
+    return abs(a - b) / max(1.0, abs(b))
+
+
+def oracle_tree(net, evidence=None, mode="slice", order=None):
+    lv = oracle.build_leaves(net, evidence, mode)
+    if order is None:
+        order = oracle.min_degree_order(lv.labels, net.n_vars)
+    return lv, oracle.elimination_tree(lv.labels, lv.card, order)
+
+
+# ---------------------------------------------------------------------------
+# log Z and marginals
+# ---------------------------------------------------------------------------
+
+def test_grid4x4_against_brute_force(T):
+    net = W.grid_mrf(4, 4, 0)
+    P = T.Plan(T.Network(net))
+    lz = P.log_z()[0]
+    want = bf.log_z(net)
+    assert rel(lz, want) <= 1e-5
+    lz2, m = P.marginals()
+    bm = bf.marginals(net)
+    got = P.split_marginals(m[0])
+    assert max(np.abs(a - b).max() for a, b in zip(got, bm)) <= 1e-5
+    lp, x = P.map()
+    best, sols, gap = bf.map_set(net)
+    assert any(np.array_equal(x[0], s) for s in sols)
+    assert abs(lp[0] - best) < 1e-4
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("explicit_tree", [False, True])
+def test_small_random_models(T, seed, explicit_tree):
+    net = W.random_small_mrf(12, 18, seed=seed, cards=(2, 3, 4))
+    kw = {}
+    if explicit_tree:
+        lv, pairs = oracle_tree(net)
+        kw["tree"] = pairs
+    P = T.Plan(T.Network(net), **kw)
+    want = bf.log_z(net)
+    lz, m = P.marginals()
+    assert rel(lz[0], want) <= 1e-5
+    bm = bf.marginals(net)
+    err = max(np.abs(a - b).max() for a, b in zip(P.split_marginals(m[0]), bm))
+    assert err <= 1e-5, err
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_sliced_evidence(T, seed):
+    bn = W.random_bn(60, seed=seed)
+    obs, ev = W.bn_evidence(bn, seed=seed + 50, frac=0.15)
+    P = T.Plan(T.Network(bn), evidence_mode=T.EVIDENCE_SLICED, observed=obs)
+    lz, m = P.marginals(ev)
+    want_lz, want_m, *_ = oracle.marginals(bn, ev)
+    assert rel(lz[0], want_lz) <= 1e-5
+    got = P.split_marginals(m[0])
+    assert max(np.abs(a - b).max() for a, b in zip(got, want_m)) <= 1e-5
+    # several instances of the same observed set, one call
+    ev2 = np.stack([ev, ev])
+    for v in obs[:3]:
+        ev2[1, v] = (ev2[1, v] + 1) % bn.card[v]
+    lz2 = P.log_z(ev2, batch=2)
+    assert rel(lz2[0], want_lz) <= 1e-5
+    assert rel(lz2[1], oracle.log_z(bn, ev2[1])) <= 1e-5
+
+
+def test_bn_without_evidence_has_unit_partition_function(T):
+    bn = W.random_bn(150, seed=3)
+    P = T.Plan(T.Network(bn), semirings=T.SUM_PRODUCT)
+    assert abs(P.log_z()[0]) <= 1e-5
+
+
+def test_batched_indicators_small(T):
+    c = W.config(3, seed=1, small=True)
+    bn, ev = c["net"], c["evidence"]
+    B = ev.shape[0]
+    P = T.Plan(T.Network(bn), evidence_mode=T.EVIDENCE_INDICATOR, max_batch=B, semirings=T.SUM_PRODUCT)
+    lz, m = P.marginals(ev, batch=B)
+    for b in range(B):
+        want_lz, want_m, *_ = oracle.marginals(bn, ev[b], mode="indicator")
+        assert rel(lz[b], want_lz) <= 1e-5, b
+        got = P.split_marginals(m[b])
+        assert max(np.abs(x - y).max() for x, y in zip(got, want_m)) <= 1e-5, b
+    # fewer instances than max_batch
+    lz3 = P.log_z(ev[:3], batch=3)
+    assert np.allclose(lz3, lz[:3], rtol=0, atol=1e-9)
+
+
+def test_grid20x20_full_size_against_oracle(T):
+    ref = json.load(open(os.path.join(GOLDEN, "oracle_grid20x20_seed0.json")))
+    net = W.grid_mrf(20, 20, 0)
+    P = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT)
+    info = P.info()
+    assert info["sc"] <= 22
+    lz, m = P.marginals()
+    assert rel(lz[0], ref["log_z"]) <= 1e-5 * abs(ref["log_z"]) / max(1, abs(ref["log_z"])) * 1.0 + 1e-5
+    assert abs(lz[0] - ref["log_z"]) / abs(ref["log_z"]) <= 1e-5
+    got = np.array([r[1] for r in P.split_marginals(m[0])])
+    err = np.abs(got - np.array(ref["p1"])).max()
+    assert err <= 1e-5, err
+    # sums to one for every variable
+    assert np.allclose([r.sum() for r in P.split_marginals(m[0])], 1.0, atol=1e-12)
+
+
+def test_unity_identity_and_invariants(T):
+    """Marginal rows sum to one and observed variables are one-hot."""
+    bn = W.random_bn(40, seed=9)
+    obs, ev = W.bn_evidence(bn, seed=10, frac=0.2)
+    P = T.Plan(T.Network(bn), evidence_mode=T.EVIDENCE_SLICED, observed=obs)
+    lz, m = P.marginals(ev)
+    rows = P.split_marginals(m[0])
+    for v in range(bn.n_vars):
+        assert abs(rows[v].sum() - 1) < 1e-9
+        if ev[v] >= 0:
+            assert rows[v][ev[v]] == 1.0
+
+
+# ---------------------------------------------------------------------------
+# MAP: bit-exact against the oracle's FP32 emulation on the same tree
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(3))
+def test_map_bit_exact_small(T, seed):
+    net = W.random_small_mrf(14, 20, seed=30 + seed, cards=(2, 3))
+    lv = oracle.build_leaves(net, domain="log")
+    pairs = oracle.default_tree(lv)
+    P = T.Plan(T.Network(net), tree=pairs)
+    lp, x = P.map()
+    v32, x32 = oracle.max_forward(lv, pairs, fp32=True)
+    assert np.array_equal(x[0], x32)
+    assert np.float32(lp[0]) == np.float32(v32)
+
+
+def test_map_bn300_bit_exact(T):
+    c = W.config(2, seed=0)
+    bn, obs, ev = c["net"], c["observed"], c["evidence"]
+    lv = oracle.build_leaves(bn, ev, domain="log")
+    pairs = oracle.default_tree(lv)
+    P = T.Plan(T.Network(bn), evidence_mode=T.EVIDENCE_SLICED, observed=obs, tree=pairs,
+               semirings=T.MAX_PLUS)
+    lp, x = P.map(ev)
+    v32, x32 = oracle.max_forward(lv, pairs, fp32=True)
+    x32 = np.where(ev >= 0, ev, x32)
+    assert np.array_equal(x[0], x32)
+    assert np.float32(lp[0]) == np.float32(v32)
+    # own planner: equal to the FP64 optimum unless the FP64 gap is below
+    # the FP32 error bound of the tree
+    P2 = T.Plan(T.Network(bn), evidence_mode=T.EVIDENCE_SLICED, observed=obs, semirings=T.MAX_PLUS)
+    lp2, x2 = P2.map(ev)
+    v64, x64 = oracle.map_assignment(bn, ev)
+    if not np.array_equal(x2[0], x64):
+        gap = v64 - oracle.log_joint(bn, x2[0])
+        assert gap <= 1e-3 * max(1.0, abs(v64))
+    assert abs(oracle.log_joint(bn, x2[0]) - lp2[0]) <= 1e-3 * max(1.0, abs(v64))
+
+
+def test_map_batched_indicators(T):
+    bn = W.random_bn(50, seed=4)
+    ev = W.bn_evidence_batch(bn, 6, seed=5)
+    lvs = [oracle.build_leaves(bn, ev[b], "indicator", domain="log") for b in range(6)]
+    pairs = oracle.default_tree(lvs[0])
+    P = T.Plan(T.Network(bn), evidence_mode=T.EVIDENCE_INDICATOR, max_batch=6, tree=pairs,
+               semirings=T.MAX_PLUS)
+    lp, x = P.map(ev, batch=6)
+    for b in range(6):
+        v32, x32 = oracle.max_forward(lvs[b], pairs, fp32=True)
+        assert np.array_equal(x[b], x32), b
+        assert np.float32(lp[b]) == np.float32(v32)
+
+
+def test_map_ferromagnetic_tie(T):
+    net = W.chain_mrf(np.full(40, 0.7))
+    lv = oracle.build_leaves(net, domain="log")
+    pairs = oracle.default_tree(lv)
+    P = T.Plan(T.Network(net), tree=pairs)
+    lp, x = P.map()
+    v32, x32 = oracle.max_forward(lv, pairs, fp32=True)
+    assert np.array_equal(x[0], x32)
+    assert np.all(x[0] == 0) or np.all(x[0] == 1)
+
+
+# ---------------------------------------------------------------------------
+# MMAP and sampling
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(3))
+def test_mmap_small(T, seed):
+    net = W.random_regular3(16, seed=seed, n_query=5)
+    q = net.meta["query"]
+    P = T.Plan(T.Network(net), query=q)
+    val, x = P.mmap()
+    bv, bx, gap = bf.mmap(net, q)
+    if gap > 1e-4:
+        assert np.array_equal(x, bx)
+    assert abs(val - bv) <= 1e-4 * max(1, abs(bv))
+
+
+def test_mmap_sliced(T):
+    c = W.config(4, seed=0, small=True)
+    net, q = c["net"], c["query"]
+    ov, ox, ogap = oracle.mmap(net, q)
+    P = T.Plan(T.Network(net), query=q, max_log2_size=10)
+    assert P.info()["n_sliced"] > 0
+    val, x = P.mmap()
+    if ogap > 1e-4:
+        assert np.array_equal(x, ox)
+    assert abs(val - ov) <= 1e-5 * max(1, abs(ov))
+    P0 = T.Plan(T.Network(net), query=q)
+    val0, x0 = P0.mmap()
+    assert abs(val0 - ov) <= 1e-5 * max(1, abs(ov))
+
+
+def test_sampling_same_rng_as_oracle(T):
+    net = W.grid_mrf(4, 5, 11)
+    lv = oracle.build_leaves(net)
+    pairs = oracle.default_tree(lv)
+    P = T.Plan(T.Network(net), tree=pairs, semirings=T.SUM_PRODUCT)
+    n = 4000
+    s = P.sample(n, seed=1234)
+    so = oracle.sample_tree(lv, pairs, n, seed=1234)
+    agree = np.mean(np.all(s == so, axis=1))
+    assert agree >= 0.99, agree
+
+
+def test_sampling_marginals(T):
+    bn = W.random_bn(40, seed=12)
+    obs, ev = W.bn_evidence(bn, seed=13, frac=0.2)
+    P = T.Plan(T.Network(bn), evidence_mode=T.EVIDENCE_SLICED, observed=obs, semirings=T.SUM_PRODUCT)
+    n = 20000
+    s = P.sample(n, seed=7, evidence=ev)
+    assert np.all(s[:, ev >= 0] == ev[ev >= 0])
+    _, exact, *_ = oracle.marginals(bn, ev)
+    for v in np.nonzero(ev < 0)[0]:
+        emp = np.bincount(s[:, v], minlength=bn.card[v]) / n
+        sig = np.sqrt(exact[v] * (1 - exact[v]) / n)
+        assert np.all(np.abs(emp - exact[v]) <= 4.5 * sig + 1e-9), v
+
+
+# ---------------------------------------------------------------------------
+# Differentiation through torch.autograd
+# ---------------------------------------------------------------------------
+
+def test_autograd_theorem_and_finite_differences(T):
+    import torch
+    from paper_2405_14060_amd.autograd import log_z
+    net = W.random_small_mrf(10, 14, seed=21)
+    N = T.Network(net)
+    P = T.Plan(N, semirings=T.SUM_PRODUCT, want_factor_grad=True,
+               stream=torch.cuda.current_stream().cuda_stream)
+    _, _, _, vals = net.flat()
+    v = torch.tensor(vals, dtype=torch.float32, device="cuda", requires_grad=True)
+    lz = log_z(P, v)
+    lz.sum().backward()
+    g = v.grad.double().cpu().numpy()
+    lzo, marg, adj, aexp, lv = oracle.marginals(net)
+    assert rel(float(lz.item()), lzo) <= 1e-5
+    z = math.exp(lzo)
+    off = N.value_offsets
+    for i, k in enumerate(lv.kind):
+        if k != "factor":
+            continue
+        f = lv.factor_of[i]
+        s = np.asarray(net.scopes[f])
+        perm = np.argsort(s)
+        want = (adj[i] * 2.0 ** aexp[i] / z).reshape([net.card[u] for u in s[perm]])
+        want = np.transpose(want, np.argsort(perm)).ravel()
+        got = g[off[f]:off[f + 1]]
+        assert np.allclose(got, want, rtol=1e-4, atol=1e-7), f
+    # central finite differences of the GPU log Z itself
+    with torch.no_grad():
+        for j in [0, 5, 17]:
+            e = 1e-2 * float(v[j])
+            vp = v.detach().clone()
+            vp[j] += e
+            vm = v.detach().clone()
+            vm[j] -= e
+            fd = (log_z(P, vp).item() - log_z(P, vm).item()) / (2 * e)
+            assert abs(fd - g[j]) <= 2e-3 * max(1.0, abs(g[j]))
+
+
+# ---------------------------------------------------------------------------
+# Edge cases and errors
+# ---------------------------------------------------------------------------
+
+def test_edge_isolated_variables_and_single_factor(T):
+    # variable 2 in no factor: Z gains a factor |D_2| and a uniform marginal
+    net = W.Network(np.array([2, 3, 4], np.int32), [np.array([1, 0], np.int32)],
+                    [np.arange(1, 7, dtype=np.float64)], False)
+    P = T.Plan(T.Network(net))
+    lz, m = P.marginals()
+    assert rel(lz[0], math.log(21.0 * 4)) <= 1e-6
+    rows = P.split_marginals(m[0])
+    assert np.allclose(rows[2], 0.25)
+    lp, x = P.map()
+    assert x[0][2] == 0 and x[0][1] == 2 and x[0][0] == 1
+
+
+def test_edge_card_one_and_zero_evidence(T):
+    net = W.Network(np.array([1, 2, 2], np.int32),
+                    [np.array([0, 1], np.int32), np.array([1, 2], np.int32)],
+                    [np.array([1.0, 0.0]), np.array([0.5, 0.5, 0.0, 1.0])], False)
+    P = T.Plan(T.Network(net), evidence_mode=T.EVIDENCE_SLICED, observed=[1])
+    assert rel(P.log_z([-1, 0, -1])[0], math.log(1.0)) <= 1e-6
+    with pytest.raises(T.TNError) as ei:
+        P.log_z([-1, 1, -1])
+    assert ei.value.status == 5
+    with pytest.raises(T.TNError) as ei:
+        P.log_z([-1, 2, -1])
+    assert ei.value.status == 1
+
+
+def test_invalid_inputs_raise(T):
+    bad = W.Network(np.array([2, 2], np.int32), [np.array([0, 0], np.int32)], [np.ones(4)], False)
+    with pytest.raises(T.TNError):
+        T.Network(bad)
+    net = W.grid_mrf(2, 2, 0)
+    with pytest.raises(T.TNError):
+        T.Plan(T.Network(net), tree=np.array([[0, 0]], np.int32))
+
+
+def test_graph_replay_matches_eager(T):
+    """Captured graphs are replayed several times with eager work between
+    the replays; every replay matches the eager result."""
+    bn = W.random_bn(60, seed=2)
+    ev = W.bn_evidence_batch(bn, 8, seed=3)
+    Pg = T.Plan(T.Network(bn), evidence_mode=T.EVIDENCE_INDICATOR, max_batch=8, use_graph=True)
+    Pe = T.Plan(T.Network(bn), evidence_mode=T.EVIDENCE_INDICATOR, max_batch=8, use_graph=False)
+    lz_e, m_e = Pe.marginals(ev, batch=8)
+    for rep in range(4):
+        lz_g, m_g = Pg.marginals(ev, batch=8)
+        assert np.array_equal(lz_g, lz_e) and np.array_equal(m_g, m_e), rep
+        lp_g, x_g = Pg.map(ev, batch=8)
+        lp_e, x_e = Pe.map(ev, batch=8)
+        assert np.array_equal(x_g, x_e)
+        Pe.log_z(ev, batch=8)
