@@ -116,6 +116,9 @@ typedef struct {
   int32_t n_sliced;              /* sliced labels */
   int32_t planner_used;          /* TN_PLANNER_* that won */
   int64_t device_bytes;          /* device memory held by the plan */
+  int32_t n_launches_fwd;        /* kernel launches after stage grouping */
+  int32_t n_launches_bwd;
+  int32_t n_launches_max;
 } tn_plan_info;
 
 /* Fill *o with defaults: sum-product + max-plus, no evidence, best planner,
@@ -212,6 +215,22 @@ tn_status tn_sample(tn_plan_t *plan, const int32_t *evidence, int64_t n, uint64_
  */
 tn_status tn_logZ_dev(tn_plan_t *plan, const int32_t *evidence, const float *values_dev,
                       double *logz_dev, float *grad_dev);
+
+/* Per-launch timing of one task (for roofline reports).  kind: 0/1 generic
+ * contraction (sum / max), 2/3 split-reduction contraction (sum / max),
+ * 4 leaf preparation, 5 other.  flops and bytes are algorithmic
+ * (2 x output x summed elements; 4 bytes x (|X| + |Y| + |Z|) per instance,
+ * times the instances of the launch).  ms is the launch's duration from
+ * HIP events recorded around it on the plan's stream, averaged over reps. */
+typedef struct {
+  int32_t kind;
+  double flops, bytes, ms;
+} tn_op_profile;
+
+/* task: 0 log Z, 1 log Z + marginals, 2 MAP.  Runs the task reps times
+ * without graph capture and fills out[0..min(cap, n)-1]; *n_ops = n. */
+tn_status tn_profile(tn_plan_t *plan, int32_t task, int32_t batch, const int32_t *evidence,
+                     int32_t reps, tn_op_profile *out, int32_t cap, int32_t *n_ops);
 
 /* Synchronise the plan's stream; TN_E_DEVICE on error. */
 tn_status tn_sync(tn_plan_t *plan);

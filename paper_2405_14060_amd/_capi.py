@@ -31,7 +31,7 @@ PLANNER_BEST, PLANNER_GREEDY, PLANNER_MINFILL, PLANNER_NATURAL, PLANNER_MINDEG =
 
 EXPORTS = ["tn_plan_opts_default", "tn_load_network", "tn_free_network", "tn_plan", "tn_free_plan",
            "tn_plan_info_get", "tn_plan_tree", "tn_plan_tree_host", "tn_logZ", "tn_marginals",
-           "tn_map", "tn_mmap", "tn_sample", "tn_logZ_dev", "tn_sync", "tn_last_error"]
+           "tn_map", "tn_mmap", "tn_sample", "tn_logZ_dev", "tn_sync", "tn_profile", "tn_last_error"]
 
 i32p = ctypes.POINTER(ctypes.c_int32)
 i64p = ctypes.POINTER(ctypes.c_int64)
@@ -58,10 +58,16 @@ class PlanInfo(ctypes.Structure):
                 ("sc_union", ctypes.c_double), ("tc", ctypes.c_double),
                 ("flops_fwd", ctypes.c_double), ("bytes_fwd", ctypes.c_double),
                 ("n_sliced", ctypes.c_int32), ("planner_used", ctypes.c_int32),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("n_launches_fwd", ctypes.c_int32),
+                ("n_launches_bwd", ctypes.c_int32), ("n_launches_max", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class OpProfile(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("ms", ctypes.c_double)]
 
 
 class TNError(RuntimeError):
@@ -104,8 +110,11 @@ def lib():
     L.tn_sample.argtypes = [vp, i32p, ctypes.c_int64, ctypes.c_uint64, i32p]
     L.tn_logZ_dev.argtypes = [vp, i32p, vp, vp, vp]
     L.tn_sync.argtypes = [vp]
+    L.tn_profile.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, i32p, ctypes.c_int32,
+                             ctypes.POINTER(OpProfile), ctypes.c_int32, i32p]
     for name in ("tn_load_network", "tn_plan", "tn_plan_info_get", "tn_plan_tree", "tn_plan_tree_host",
-                 "tn_logZ", "tn_marginals", "tn_map", "tn_mmap", "tn_sample", "tn_logZ_dev", "tn_sync"):
+                 "tn_logZ", "tn_marginals", "tn_map", "tn_mmap", "tn_sample", "tn_logZ_dev", "tn_sync",
+                 "tn_profile"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -276,6 +285,15 @@ class Plan:
         _check(lib().tn_logZ_dev(self.h, _ptr(ev, ctypes.c_int32), ctypes.c_void_p(values_ptr),
                                  ctypes.c_void_p(logz_ptr),
                                  ctypes.c_void_p(grad_ptr) if grad_ptr else None))
+
+    def profile(self, task, reps=3, evidence=None, batch=1):
+        """Per-launch (kind, flops, bytes, ms) of one task: 0 log Z, 1 marginals, 2 MAP."""
+        ev = self._ev(evidence, batch)
+        cap = 1 << 16
+        buf = (OpProfile * cap)()
+        n = ctypes.c_int32()
+        _check(lib().tn_profile(self.h, task, batch, _ptr(ev, ctypes.c_int32), reps, buf, cap, ctypes.byref(n)))
+        return [(buf[i].kind, buf[i].flops, buf[i].bytes, buf[i].ms) for i in range(min(n.value, cap))]
 
     def sync(self):
         _check(lib().tn_sync(self.h))

@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <numeric>
 #include <string>
 
@@ -248,9 +249,14 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
   const uint32_t nSh = a.nS / a.nSl;
   if (n_out * (uint64_t)op.nb < 8192 && a.nS >= 4096 && nSh >= 2) {
     op.split = true;
-    uint32_t want = std::max<uint32_t>(1, 4096u / (uint32_t)op.nb);
+    // about 1024 workgroups in total, each reducing at least 1K summed entries
+    uint32_t want = std::max<uint32_t>(1, 1024u / (uint32_t)op.nb);
+    want = std::min<uint32_t>(want, std::max<uint32_t>(1, a.nS / 1024u));
     a.n_chunks = std::min<uint32_t>(nSh, want);
-    p->part_floats = std::max<int64_t>(p->part_floats, (int64_t)op.nb * a.n_chunks * n_out);
+    // every split contraction owns its partial-sum region: contractions of
+    // one stage run concurrently in a grouped launch
+    op.part_off = p->part_floats;
+    p->part_floats += ((int64_t)op.nb * a.n_chunks * n_out + 63) / 64 * 64;
   }
   op.flops = 2.0 * (double)n_out * (double)a.nS;
   op.bytes = 4.0 * (double)(p->T[X].size + (Y >= 0 ? p->T[Y].size : 0) + p->T[Z].size);
@@ -479,6 +485,11 @@ static T *dupload(tn_plan_t *p, const std::vector<T> &v) {
   return d;
 }
 
+template <class T>
+static T *dalloc_vec(tn_plan_t *p, const std::vector<T> &v) {
+  return dupload(p, v);
+}
+
 static void fill_args(tn_plan_t *p, Op &op) {
   ContractArgs &a = op.a;
   auto tab = [&](const int64_t t[2]) {
@@ -515,8 +526,88 @@ static void fill_args(tn_plan_t *p, Op &op) {
   a.batX = X.batched;
   a.slotZ = Z.slot;
   a.batZ = Z.batched;
-  a.part = p->d_part;
-  a.parti = p->d_parti;
+  a.part = p->d_part + (op.part_off >= 0 ? op.part_off : 0);
+  a.parti = p->d_parti + (op.part_off >= 0 ? op.part_off : 0);
+}
+
+
+// ---------------------------------------------------------------------------
+// schedules (stages of independent contractions)
+// ---------------------------------------------------------------------------
+static Schedule build_schedule(tn_plan_t *p, const std::vector<Op> &ops, bool alap) {
+  Schedule sc;
+  const int n = (int)ops.size();
+  if (n == 0) return sc;
+  std::map<int, int> producer;  // tensor id -> op index
+  for (int i = 0; i < n; ++i) producer[ops[i].Z] = i;
+  std::vector<int> stage(n, 0);
+  std::vector<std::vector<int>> consumers(n);
+  for (int i = 0; i < n; ++i) {
+    int st = 0;
+    for (int t : {ops[i].X, ops[i].Y}) {
+      if (t < 0) continue;
+      auto it = producer.find(t);
+      if (it != producer.end() && it->second < i) {
+        st = std::max(st, stage[it->second] + 1);
+        consumers[it->second].push_back(i);
+      }
+    }
+    stage[i] = st;
+  }
+  int smax = *std::max_element(stage.begin(), stage.end());
+  if (alap) {
+    for (int i = n - 1; i >= 0; --i) {
+      int st = smax;
+      for (int c : consumers[i]) st = std::min(st, stage[c] - 1);
+      stage[i] = st;
+    }
+  }
+  sc.n_stages = smax + 1;
+  // launches: per stage, map ops of each semiring together, split ops together
+  for (int st = 0; st <= smax; ++st)
+    for (int semi = 0; semi < 2; ++semi)
+      for (int spl = 0; spl < 2; ++spl) {
+        Launch L;
+        L.semi = semi;
+        L.split = spl != 0;
+        for (int i = 0; i < n; ++i)
+          if (stage[i] == st && ops[i].semi == semi && ops[i].split == (spl != 0)) L.ops.push_back(i);
+        if (!L.ops.empty()) sc.launches.push_back(std::move(L));
+      }
+  (void)p;
+  return sc;
+}
+
+static void upload_schedule(tn_plan_t *p, Schedule &sc, const std::vector<Op> &ops) {
+  for (Launch &L : sc.launches) {
+    if (L.ops.size() < 2) continue;
+    std::vector<ContractArgs> args;
+    std::vector<uint32_t> st, nb, st2, nb2;
+    uint32_t tot = 0, tot2 = 0;
+    for (int i : L.ops) {
+      const Op &op = ops[i];
+      args.push_back(op.a);
+      const uint32_t per = L.split ? op.a.n_chunks : map_blocks(op.a);
+      st.push_back(tot);
+      nb.push_back(per);
+      tot += per * (uint32_t)op.nb;
+      if (L.split) {
+        const uint32_t per2 = op.a.nR * op.a.nC;
+        st2.push_back(tot2);
+        nb2.push_back(per2);
+        tot2 += per2 * (uint32_t)op.nb;
+      }
+    }
+    L.total = tot;
+    L.total2 = tot2;
+    L.d_args = dalloc_vec(p, args);
+    L.d_start = dalloc_vec(p, st);
+    L.d_nblk = dalloc_vec(p, nb);
+    if (L.split) {
+      L.d_start2 = dalloc_vec(p, st2);
+      L.d_nblk2 = dalloc_vec(p, nb2);
+    }
+  }
 }
 
 tn_plan_impl::~tn_plan_impl() {
@@ -624,6 +715,18 @@ static void allocate(tn_plan_t *p, const tn_net *net) {
   for (auto &g : p->groups)
     for (auto &op : g.ops) fill_args(p, op);
   for (auto &op : p->qtree.ops) fill_args(p, op);
+  p->sched_fwd = build_schedule(p, p->sum_tree.ops, false);
+  p->sched_bwd = build_schedule(p, p->bwd, true);
+  p->sched_max = build_schedule(p, p->max_tree.ops, false);
+  p->sched_q = build_schedule(p, p->qtree.ops, false);
+  upload_schedule(p, p->sched_fwd, p->sum_tree.ops);
+  upload_schedule(p, p->sched_bwd, p->bwd);
+  upload_schedule(p, p->sched_max, p->max_tree.ops);
+  upload_schedule(p, p->sched_q, p->qtree.ops);
+  for (auto &g : p->groups) {
+    p->sched_groups.push_back(build_schedule(p, g.ops, false));
+    upload_schedule(p, p->sched_groups.back(), g.ops);
+  }
   p->d_leaves_sum = dupload(p, p->leaves_sum);
   p->d_leaves_max = dupload(p, p->leaves_max);
   p->d_qleaves = dupload(p, p->qleaves);
@@ -867,6 +970,14 @@ extern "C" tn_status tn_plan_info_get(const tn_plan_t *p, tn_plan_info *info) {
     info->n_sliced = (int32_t)p->sliced.size();
     info->planner_used = p->planner_used;
     info->device_bytes = p->device_bytes;
+    auto count = [](const Schedule &sc) {
+      int n = 0;
+      for (const Launch &L : sc.launches) n += L.split ? 2 : 1;
+      return n;
+    };
+    info->n_launches_fwd = count(p->sched_fwd);
+    info->n_launches_bwd = count(p->sched_bwd);
+    info->n_launches_max = count(p->sched_max);
   });
 }
 
@@ -934,6 +1045,20 @@ namespace tn {
 
 void run_ops(tn_plan_t *p, const std::vector<Op> &ops) {
   for (const Op &op : ops) launch_contract(op.semi, op.Y >= 0, op.split, op.a, op.nb, p->stream);
+}
+
+void run_sched(tn_plan_t *p, const std::vector<Op> &ops, const Schedule &sc) {
+  for (const Launch &L : sc.launches) {
+    if (L.ops.size() == 1) {
+      const Op &op = ops[L.ops[0]];
+      launch_contract(op.semi, op.Y >= 0, op.split, op.a, op.nb, p->stream);
+    } else if (!L.split) {
+      launch_group(L.semi, 0, L.d_args, L.d_start, L.d_nblk, (int)L.ops.size(), L.total, p->stream);
+    } else {
+      launch_group(L.semi, 1, L.d_args, L.d_start, L.d_nblk, (int)L.ops.size(), L.total, p->stream);
+      launch_group(L.semi, 2, L.d_args, L.d_start2, L.d_nblk2, (int)L.ops.size(), L.total2, p->stream);
+    }
+  }
 }
 
 static PrepareArgs prep_args(tn_plan_t *p, const std::vector<LeafDesc> &h, const LeafDesc *d, bool reset) {
@@ -1008,11 +1133,11 @@ static void check_batch(tn_plan_t *p, int batch) {
 static void forward_sum(tn_plan_t *p, bool with_bwd) {
   run_graph(p, with_bwd ? "sum+bwd" : "sum", [&] {
     launch_prepare_set(p, p->leaves_sum, p->d_leaves_sum, true);
-    run_ops(p, p->sum_tree.ops);
+    run_sched(p, p->sum_tree.ops, p->sched_fwd);
     const TensorBuf &r = p->T[p->sum_tree.root];
     launch_logz(p->arena + r.off, r.batched ? r.size : 0, p->ex, r.slot, r.batched, p->max_batch, p->d_out, p->stream);
     if (with_bwd) {
-      run_ops(p, p->bwd);
+      run_sched(p, p->bwd, p->sched_bwd);
       launch_marg(p->arena, p->d_marg_desc, (int)p->marg.size(), p->max_batch, p->marg_row, p->d_marg, p->stream);
     }
   });
@@ -1081,7 +1206,7 @@ extern "C" tn_status tn_map(tn_plan_t *p, int32_t batch, const int32_t *evidence
                                hipMemcpyDeviceToDevice, p->stream), "init");
       run_graph(p, "max", [&] {
         launch_prepare_set(p, p->leaves_max, p->d_leaves_max, false);
-        run_ops(p, p->max_tree.ops);
+        run_sched(p, p->max_tree.ops, p->sched_max);
         launch_backtrack(p->iarena, p->d_back, (int)p->max_tree.back.size(), p->d_back_meta, p->n_vars,
                          p->max_batch, p->d_assign, p->stream);
       });
@@ -1347,7 +1472,7 @@ static void run_mmap(tn_plan_t *p, const int32_t *evidence, int32_t *assign_q, d
       }
       hip_check(hipMemcpyAsync(p->d_evidence, row.data(), row.size() * 4, hipMemcpyHostToDevice, p->stream), "slice");
       launch_prepare_set(p, p->group_leaves[g], p->d_group_leaves[g], true);
-      run_ops(p, t.ops);
+      run_sched(p, t.ops, p->sched_groups[g]);
       launch_slice_acc(p->arena + r.off, p->mx, p->ex, r.slot, p->d_acc, acc_ex, r.size, s == 0 ? 1 : 0, p->stream);
       hip_check(hipStreamSynchronize(p->stream), "slice");
     }
@@ -1357,7 +1482,7 @@ static void run_mmap(tn_plan_t *p, const int32_t *evidence, int32_t *assign_q, d
   hip_check(hipMemcpyAsync(p->d_evidence, row.data(), row.size() * 4, hipMemcpyHostToDevice, p->stream), "evidence");
   hip_check(hipMemcpyAsync(p->d_assign, row.data(), row.size() * 4, hipMemcpyHostToDevice, p->stream), "init");
   launch_prepare_set(p, p->qleaves, p->d_qleaves, false);
-  run_ops(p, p->qtree.ops);
+  run_sched(p, p->qtree.ops, p->sched_q);
   launch_backtrack(p->iarena, p->d_qback, (int)p->qtree.back.size(), p->d_qback_meta, p->n_vars, 1, p->d_assign,
                    p->stream);
   hip_check(hipGetLastError(), "mmap launch");
@@ -1376,5 +1501,83 @@ extern "C" tn_status tn_mmap(tn_plan_t *p, const int32_t *evidence, int32_t *ass
     if (!p->is_mmap) throw TnError(TN_E_UNSUPPORTED, "plan has no query set");
     run_mmap(p, evidence, assign_q, log_value);
     if (!(*log_value > -INFINITY)) throw TnError(TN_E_ZERO_EVIDENCE, "p(e) = 0");
+  });
+}
+
+// ---------------------------------------------------------------------------
+// per-launch profile (events around every launch of one task)
+// ---------------------------------------------------------------------------
+extern "C" tn_status tn_profile(tn_plan_t *p, int32_t task, int32_t batch, const int32_t *evidence, int32_t reps,
+                                tn_op_profile *out, int32_t cap, int32_t *n_ops) {
+  return guard([&] {
+    if (!p || reps < 1) throw TnError(TN_E_INVALID, "bad argument");
+    if (p->is_mmap) throw TnError(TN_E_UNSUPPORTED, "profile of MMAP plans");
+    if ((task <= 1 && !p->want_sum) || (task == 2 && !p->want_max)) throw TnError(TN_E_UNSUPPORTED, "task not in plan");
+    check_batch(p, batch);
+    if (p->mode == TN_EVIDENCE_SLICED && batch != 1) throw TnError(TN_E_INVALID, "profile one instance at a time");
+    upload_evidence(p, batch, evidence);
+    // launch list: (kind, flops, bytes, launcher)
+    struct L {
+      int kind;
+      double flops, bytes;
+      std::function<void()> go;
+    };
+    std::vector<L> ls;
+    auto add_ops = [&](const std::vector<Op> &ops) {
+      for (const Op &op : ops) {
+        const int kind = (op.split ? 2 : 0) + (op.semi == SEMI_MAX ? 1 : 0);
+        double by = op.bytes + (op.semi == SEMI_MAX ? 4.0 * p->T[op.Z].size : 0.0);
+        ls.push_back({kind, op.flops * op.nb, by * op.nb,
+                      [p, &op] { launch_contract(op.semi, op.Y >= 0, op.split, op.a, op.nb, p->stream); }});
+      }
+    };
+    if (task <= 1) {
+      ls.push_back({4, 0, 0, [p] { launch_prepare_set(p, p->leaves_sum, p->d_leaves_sum, true); }});
+      add_ops(p->sum_tree.ops);
+      ls.push_back({5, 0, 0, [p] {
+                      const TensorBuf &r = p->T[p->sum_tree.root];
+                      launch_logz(p->arena + r.off, r.batched ? r.size : 0, p->ex, r.slot, r.batched, p->max_batch,
+                                  p->d_out, p->stream);
+                    }});
+      if (task == 1) {
+        add_ops(p->bwd);
+        ls.push_back({5, 0, 0, [p] {
+                        launch_marg(p->arena, p->d_marg_desc, (int)p->marg.size(), p->max_batch, p->marg_row,
+                                    p->d_marg, p->stream);
+                      }});
+      }
+    } else {
+      ls.push_back({4, 0, 0, [p] { launch_prepare_set(p, p->leaves_max, p->d_leaves_max, false); }});
+      add_ops(p->max_tree.ops);
+      ls.push_back({5, 0, 0, [p] {
+                      launch_backtrack(p->iarena, p->d_back, (int)p->max_tree.back.size(), p->d_back_meta, p->n_vars,
+                                       p->max_batch, p->d_assign, p->stream);
+                    }});
+    }
+    std::vector<hipEvent_t> ev(ls.size() + 1);
+    for (auto &e : ev) hip_check(hipEventCreate(&e), "event");
+    std::vector<double> acc(ls.size(), 0.0);
+    for (int r = 0; r < reps; ++r) {
+      hip_check(hipEventRecord(ev[0], p->stream), "event");
+      for (size_t i = 0; i < ls.size(); ++i) {
+        ls[i].go();
+        hip_check(hipEventRecord(ev[i + 1], p->stream), "event");
+      }
+      hip_check(hipEventSynchronize(ev.back()), "event sync");
+      hip_check(hipGetLastError(), "profile launch");
+      for (size_t i = 0; i < ls.size(); ++i) {
+        float ms = 0;
+        hip_check(hipEventElapsedTime(&ms, ev[i], ev[i + 1]), "elapsed");
+        acc[i] += ms;
+      }
+    }
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (n_ops) *n_ops = (int32_t)ls.size();
+    for (size_t i = 0; i < ls.size() && (int)i < cap; ++i) {
+      out[i].kind = ls[i].kind;
+      out[i].flops = ls[i].flops;
+      out[i].bytes = ls[i].bytes;
+      out[i].ms = acc[i] / reps;
+    }
   });
 }

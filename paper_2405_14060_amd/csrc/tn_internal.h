@@ -101,6 +101,11 @@ enum Semiring { SEMI_SUM = 0, SEMI_MAX = 1 };
 
 void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, int nb,
                      void *stream);
+// blocks per instance of a one-lane-per-output launch
+uint32_t map_blocks(const ContractArgs &a);
+// phase 0: map, 1: split partials, 2: split finish
+void launch_group(int semi, int phase, const ContractArgs *ops, const uint32_t *start,
+                  const uint32_t *nblk, int n, uint32_t total_blocks, void *stream);
 
 struct LeafDesc {
   int32_t kind;      // 0 factor gather, 1 constant one-vector, 2 indicator

@@ -56,6 +56,22 @@ __device__ __forceinline__ int max_exponent(uint32_t bits) {
   return k < -126 ? -126 : (k > 126 ? 126 : k);
 }
 
+// Record the block's maximum in *slot.  One candidate per block; the atomic
+// is skipped when the stored value is already larger (maxima only grow
+// within a launch, so a stale read only costs an unneeded atomic).
+__device__ __forceinline__ void block_record_max(float v, uint32_t *slot) {
+  __shared__ float red[kBlock / 64];
+  v = wave_max(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float m = red[0];
+#pragma unroll
+    for (int w = 1; w < kBlock / 64; ++w) m = fmaxf(m, red[w]);
+    if (m > 0.f && __uint_as_float(*(volatile uint32_t *)slot) < m) atomicMax(slot, __float_as_uint(m));
+  }
+}
+
 __device__ __forceinline__ int32_t tab_off(const Tab2 &t, uint32_t i, uint32_t nlo) {
   uint32_t h = i / nlo;
   return t.hi[h] + t.lo[i - h * nlo];
@@ -65,8 +81,8 @@ __device__ __forceinline__ int32_t tab_off(const Tab2 &t, uint32_t i, uint32_t n
 // generic contraction, one lane per output element
 // --------------------------------------------------------------------------
 template <int SEMI, bool HASY>
-__global__ __launch_bounds__(kBlock) void k_map(ContractArgs a) {
-  const int b = blockIdx.y;
+__device__ __forceinline__ void map_body(const ContractArgs &a, const int b, const uint32_t blk,
+                                         const uint32_t nblk) {
   const float *__restrict__ X = a.X + (int64_t)b * a.bsX;
   const float *__restrict__ Y = HASY ? a.Y + (int64_t)b * a.bsY : nullptr;
   float *__restrict__ Z = a.Z + (int64_t)b * a.bsZ;
@@ -84,7 +100,7 @@ __global__ __launch_bounds__(kBlock) void k_map(ContractArgs a) {
   const uint32_t n_out = a.nR * a.nC;
   const uint32_t nSh = a.nS / a.nSl;
   float lmax = 0.f;
-  for (uint32_t o = blockIdx.x * kBlock + threadIdx.x; o < n_out; o += gridDim.x * kBlock) {
+  for (uint32_t o = blk * kBlock + threadIdx.x; o < n_out; o += nblk * kBlock) {
     uint32_t r, c;
     if (a.col_fastest) {
       r = o / a.nC;
@@ -138,10 +154,8 @@ __global__ __launch_bounds__(kBlock) void k_map(ContractArgs a) {
     }
   }
   if (SEMI == SEMI_SUM) {
-    lmax = wave_max(lmax);
-    if ((threadIdx.x & 63) == 0 && lmax > 0.f)
-      atomicMax(a.mx + a.slotZ + (a.batZ ? b : 0), __float_as_uint(lmax));
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    block_record_max(lmax, a.mx + a.slotZ + (a.batZ ? b : 0));
+    if (blk == 0 && threadIdx.x == 0) {
       int e = a.ex[a.slotX + (a.batX ? b : 0)] + kx;
       if (HASY) e += a.ex[a.slotY + (a.batY ? b : 0)] + ky;
       a.ex[a.slotZ + (a.batZ ? b : 0)] = e;
@@ -152,10 +166,13 @@ __global__ __launch_bounds__(kBlock) void k_map(ContractArgs a) {
 // --------------------------------------------------------------------------
 // generic contraction, summed index split across workgroups
 // --------------------------------------------------------------------------
+// Outputs are processed in groups of kSplitOuts kept in registers, so that
+// each lane streams its share of the summed index once per group and every
+// element of the operands is read once per group.
+static constexpr int kSplitOuts = 16;
+
 template <int SEMI, bool HASY>
-__global__ __launch_bounds__(kBlock) void k_split(ContractArgs a) {
-  const int b = blockIdx.y;
-  const uint32_t chunk = blockIdx.x;
+__device__ __forceinline__ void split_body(const ContractArgs &a, const int b, const uint32_t chunk) {
   const float *__restrict__ X = a.X + (int64_t)b * a.bsX;
   const float *__restrict__ Y = HASY ? a.Y + (int64_t)b * a.bsY : nullptr;
   float sx = 1.f, sy = 1.f;
@@ -167,150 +184,263 @@ __global__ __launch_bounds__(kBlock) void k_split(ContractArgs a) {
   const uint32_t per = (nSh + a.n_chunks - 1) / a.n_chunks;
   const uint32_t h0 = chunk * per, h1 = min(nSh, h0 + per);
   const uint32_t n_out = a.nR * a.nC;
-  __shared__ float sv[kBlock / 64];
-  __shared__ int32_t si[kBlock / 64];
+  __shared__ float sv[kBlock / 64][kSplitOuts];
+  __shared__ int32_t si[kBlock / 64][kSplitOuts];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (uint32_t o = 0; o < n_out; ++o) {
-    uint32_t r, c;
-    if (a.col_fastest) {
-      r = o / a.nC;
-      c = o - r * a.nC;
-    } else {
-      c = o / a.nR;
-      r = o - c * a.nR;
-    }
-    const uint32_t rh = r / a.nRl, rl = r - rh * a.nRl;
-    const int32_t xo = a.rX.hi[rh] + a.rX.lo[rl];
-    int32_t yo = HASY ? a.rY.hi[rh] + a.rY.lo[rl] : 0;
-    if (HASY && a.nC > 1) yo += tab_off(a.cY, c, a.nCl);
-    const size_t pidx = ((size_t)b * a.n_chunks + chunk) * n_out + o;
-    if (SEMI == SEMI_SUM) {
-      float acc = 0.f;
-      for (uint32_t sh = h0; sh < h1; ++sh) {
-        const int32_t xs = xo + a.sX.hi[sh];
-        const int32_t ys = HASY ? yo + a.sY.hi[sh] : 0;
-        for (uint32_t sl = threadIdx.x; sl < a.nSl; sl += kBlock) {
-          const float xv = X[xs + a.sX.lo[sl]] * sx;
-          if (HASY)
-            acc = fmaf(xv, Y[ys + a.sY.lo[sl]] * sy, acc);
-          else
-            acc += xv;
+  for (uint32_t o0 = 0; o0 < n_out; o0 += kSplitOuts) {
+    const int no = (int)min((uint32_t)kSplitOuts, n_out - o0);
+    int32_t xo[kSplitOuts], yo[kSplitOuts];
+    float acc[kSplitOuts];
+    int32_t arg[kSplitOuts];
+#pragma unroll
+    for (int j = 0; j < kSplitOuts; ++j) {
+      xo[j] = 0;
+      yo[j] = 0;
+      acc[j] = SEMI == SEMI_SUM ? 0.f : -INFINITY;
+      arg[j] = -1;
+      if (j < no) {
+        const uint32_t o = o0 + j;
+        uint32_t r, c;
+        if (a.col_fastest) {
+          r = o / a.nC;
+          c = o - r * a.nC;
+        } else {
+          c = o / a.nR;
+          r = o - c * a.nR;
+        }
+        xo[j] = tab_off(a.rX, r, a.nRl);
+        if (HASY) {
+          yo[j] = tab_off(a.rY, r, a.nRl);
+          if (a.nC > 1) yo[j] += tab_off(a.cY, c, a.nCl);
         }
       }
-      acc = wave_sum(acc);
-      if (lane == 0) sv[wid] = acc;
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        float t = 0.f;
-        for (int w = 0; w < kBlock / 64; ++w) t += sv[w];
-        a.part[pidx] = t;
-      }
-      __syncthreads();
-    } else {
-      float best = -INFINITY;
-      int32_t bi = -1;
-      for (uint32_t sh = h0; sh < h1; ++sh) {
-        const int32_t xs = xo + a.sX.hi[sh];
-        const int32_t ys = HASY ? yo + a.sY.hi[sh] : 0;
-        for (uint32_t sl = threadIdx.x; sl < a.nSl; sl += kBlock) {
-          float v = X[xs + a.sX.lo[sl]];
-          if (HASY) v = v + Y[ys + a.sY.lo[sl]];
-          const int32_t s = (int32_t)(sh * a.nSl + sl);
-          if (bi < 0 || v > best) {
-            best = v;
-            bi = s;
+    }
+    for (uint32_t sh = h0; sh < h1; ++sh) {
+      const int32_t xs0 = a.sX.hi[sh];
+      const int32_t ys0 = HASY ? a.sY.hi[sh] : 0;
+      for (uint32_t sl = threadIdx.x; sl < a.nSl; sl += kBlock) {
+        const int32_t xs = xs0 + a.sX.lo[sl];
+        const int32_t ys = HASY ? ys0 + a.sY.lo[sl] : 0;
+        const int32_t sidx = (int32_t)(sh * a.nSl + sl);
+#pragma unroll
+        for (int j = 0; j < kSplitOuts; ++j) {
+          if (j >= no) break;
+          if (SEMI == SEMI_SUM) {
+            const float xv = X[xo[j] + xs] * sx;
+            acc[j] = HASY ? fmaf(xv, Y[yo[j] + ys] * sy, acc[j]) : acc[j] + xv;
+          } else {
+            float v = X[xo[j] + xs];
+            if (HASY) v = v + Y[yo[j] + ys];
+            if (arg[j] < 0 || v > acc[j]) {
+              acc[j] = v;
+              arg[j] = sidx;
+            }
           }
         }
       }
+    }
+    // reduce every output over the block, fixed shape
 #pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        float ov = __shfl_xor(best, off, 64);
-        int32_t oi = __shfl_xor(bi, off, 64);
-        if (oi >= 0 && (bi < 0 || ov > best || (ov == best && oi < bi))) {
-          best = ov;
-          bi = oi;
+    for (int j = 0; j < kSplitOuts; ++j) {
+      if (j >= no) break;
+      float v = acc[j];
+      int32_t i = arg[j];
+      if (SEMI == SEMI_SUM) {
+        v = wave_sum(v);
+      } else {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          const float ov = __shfl_xor(v, off, 64);
+          const int32_t oi = __shfl_xor(i, off, 64);
+          if (oi >= 0 && (i < 0 || ov > v || (ov == v && oi < i))) {
+            v = ov;
+            i = oi;
+          }
         }
       }
       if (lane == 0) {
-        sv[wid] = best;
-        si[wid] = bi;
+        sv[wid][j] = v;
+        si[wid][j] = i;
       }
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        float bv = sv[0];
-        int32_t bj = si[0];
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)no) {
+      const int j = threadIdx.x;
+      const size_t pidx = ((size_t)b * a.n_chunks + chunk) * n_out + o0 + j;
+      if (SEMI == SEMI_SUM) {
+        float t = 0.f;
+        for (int w = 0; w < kBlock / 64; ++w) t += sv[w][j];
+        a.part[pidx] = t;
+      } else {
+        float v = sv[0][j];
+        int32_t i = si[0][j];
         for (int w = 1; w < kBlock / 64; ++w)
-          if (si[w] >= 0 && (bj < 0 || sv[w] > bv || (sv[w] == bv && si[w] < bj))) {
-            bv = sv[w];
-            bj = si[w];
+          if (si[w][j] >= 0 && (i < 0 || sv[w][j] > v || (sv[w][j] == v && si[w][j] < i))) {
+            v = sv[w][j];
+            i = si[w][j];
           }
-        a.part[pidx] = bv;
-        a.parti[pidx] = bj;
+        a.part[pidx] = v;
+        a.parti[pidx] = i;
       }
-      __syncthreads();
+    }
+    __syncthreads();
+  }
+}
+
+template <int SEMI, bool HASY>
+__device__ __forceinline__ void finish_body(const ContractArgs &a, const int b, const uint32_t o) {
+  // one block per output element: lanes stride over the chunks, then a
+  // fixed-shape tree reduction (deterministic)
+  float *__restrict__ Z = a.Z + (int64_t)b * a.bsZ;
+  const uint32_t n_out = a.nR * a.nC;
+  uint32_t r, c;
+  if (a.col_fastest) {
+    r = o / a.nC;
+    c = o - r * a.nC;
+  } else {
+    c = o / a.nR;
+    r = o - c * a.nR;
+  }
+  int32_t zo = tab_off(a.rZ, r, a.nRl);
+  if (a.nC > 1) zo += tab_off(a.cZ, c, a.nCl);
+  const size_t base = (size_t)b * a.n_chunks * n_out + o;
+  __shared__ float sv[kBlock / 64];
+  __shared__ int32_t si[kBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (SEMI == SEMI_SUM) {
+    float acc = 0.f;
+    for (uint32_t ch = threadIdx.x; ch < a.n_chunks; ch += kBlock) acc += a.part[base + (size_t)ch * n_out];
+    acc = wave_sum(acc);
+    if (lane == 0) sv[wid] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float t = 0.f;
+      for (int w = 0; w < kBlock / 64; ++w) t += sv[w];
+      Z[zo] = t;
+      if (t > 0.f) atomicMax(a.mx + a.slotZ + (a.batZ ? b : 0), __float_as_uint(t));
+      if (o == 0) {
+        const int kx = max_exponent(a.mx[a.slotX + (a.batX ? b : 0)]);
+        int e = a.ex[a.slotX + (a.batX ? b : 0)] + kx;
+        if (HASY) e += a.ex[a.slotY + (a.batY ? b : 0)] + max_exponent(a.mx[a.slotY + (a.batY ? b : 0)]);
+        a.ex[a.slotZ + (a.batZ ? b : 0)] = e;
+      }
+    }
+  } else {
+    int32_t *__restrict__ I = a.I + (int64_t)b * a.bsZ;
+    float bv = -INFINITY;
+    int32_t bj = -1;
+    for (uint32_t ch = threadIdx.x; ch < a.n_chunks; ch += kBlock) {
+      const float v = a.part[base + (size_t)ch * n_out];
+      const int32_t i = a.parti[base + (size_t)ch * n_out];
+      if (i >= 0 && (bj < 0 || v > bv || (v == bv && i < bj))) {
+        bv = v;
+        bj = i;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const float ov = __shfl_xor(bv, off, 64);
+      const int32_t oi = __shfl_xor(bj, off, 64);
+      if (oi >= 0 && (bj < 0 || ov > bv || (ov == bv && oi < bj))) {
+        bv = ov;
+        bj = oi;
+      }
+    }
+    if (lane == 0) {
+      sv[wid] = bv;
+      si[wid] = bj;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float v = sv[0];
+      int32_t j = si[0];
+      for (int w = 1; w < kBlock / 64; ++w)
+        if (si[w] >= 0 && (j < 0 || sv[w] > v || (sv[w] == v && si[w] < j))) {
+          v = sv[w];
+          j = si[w];
+        }
+      Z[zo] = v;
+      I[zo] = j < 0 ? 0 : j;
     }
   }
 }
 
 template <int SEMI, bool HASY>
+__global__ __launch_bounds__(kBlock) void k_map(ContractArgs a) {
+  map_body<SEMI, HASY>(a, blockIdx.y, blockIdx.x, gridDim.x);
+}
+template <int SEMI, bool HASY>
+__global__ __launch_bounds__(kBlock) void k_split(ContractArgs a) {
+  split_body<SEMI, HASY>(a, blockIdx.y, blockIdx.x);
+}
+template <int SEMI, bool HASY>
 __global__ __launch_bounds__(kBlock) void k_split_finish(ContractArgs a) {
-  const int b = blockIdx.y;
-  float *__restrict__ Z = a.Z + (int64_t)b * a.bsZ;
-  int32_t *__restrict__ I = SEMI == SEMI_MAX ? a.I + (int64_t)b * a.bsZ : nullptr;
+  finish_body<SEMI, HASY>(a, blockIdx.y, blockIdx.x);
+}
+
+// Several independent contractions in one launch (one stage of the tree
+// schedule).  Block ranges: op i owns blocks [start[i], start[i+1]), split
+// as instance-major (b, blk) with nblk[i] blocks per instance.
+__device__ __forceinline__ int find_op(const uint32_t *start, int n, uint32_t x) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= x) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int SEMI, int PHASE>
+__global__ __launch_bounds__(kBlock) void k_group(const ContractArgs *__restrict__ ops,
+                                                  const uint32_t *__restrict__ start,
+                                                  const uint32_t *__restrict__ nblk, int n) {
+  const int i = find_op(start, n, blockIdx.x);
+  const ContractArgs a = ops[i];
+  const uint32_t local = blockIdx.x - start[i];
+  const uint32_t per = nblk[i];
+  const int b = (int)(local / per);
+  const uint32_t blk = local - (uint32_t)b * per;
+  const bool hy = a.Y != nullptr;
+  if (PHASE == 0) {
+    if (hy) map_body<SEMI, true>(a, b, blk, per);
+    else map_body<SEMI, false>(a, b, blk, per);
+  } else if (PHASE == 1) {
+    if (hy) split_body<SEMI, true>(a, b, blk);
+    else split_body<SEMI, false>(a, b, blk);
+  } else {
+    if (hy) finish_body<SEMI, true>(a, b, blk);
+    else finish_body<SEMI, false>(a, b, blk);
+  }
+}
+
+void launch_group(int semi, int phase, const ContractArgs *ops, const uint32_t *start, const uint32_t *nblk,
+                  int n, uint32_t total_blocks, void *stream) {
+  if (n <= 0 || total_blocks == 0) return;
+  hipStream_t s = (hipStream_t)stream;
+  dim3 g(total_blocks);
+  if (semi == SEMI_SUM) {
+    if (phase == 0) k_group<SEMI_SUM, 0><<<g, kBlock, 0, s>>>(ops, start, nblk, n);
+    else if (phase == 1) k_group<SEMI_SUM, 1><<<g, kBlock, 0, s>>>(ops, start, nblk, n);
+    else k_group<SEMI_SUM, 2><<<g, kBlock, 0, s>>>(ops, start, nblk, n);
+  } else {
+    if (phase == 0) k_group<SEMI_MAX, 0><<<g, kBlock, 0, s>>>(ops, start, nblk, n);
+    else if (phase == 1) k_group<SEMI_MAX, 1><<<g, kBlock, 0, s>>>(ops, start, nblk, n);
+    else k_group<SEMI_MAX, 2><<<g, kBlock, 0, s>>>(ops, start, nblk, n);
+  }
+}
+
+uint32_t map_blocks(const ContractArgs &a) {
   const uint32_t n_out = a.nR * a.nC;
-  float lmax = 0.f;
-  for (uint32_t o = blockIdx.x * kBlock + threadIdx.x; o < n_out; o += gridDim.x * kBlock) {
-    uint32_t r, c;
-    if (a.col_fastest) {
-      r = o / a.nC;
-      c = o - r * a.nC;
-    } else {
-      c = o / a.nR;
-      r = o - c * a.nR;
-    }
-    int32_t zo = tab_off(a.rZ, r, a.nRl);
-    if (a.nC > 1) zo += tab_off(a.cZ, c, a.nCl);
-    const size_t base = (size_t)b * a.n_chunks * n_out + o;
-    if (SEMI == SEMI_SUM) {
-      float acc = 0.f;
-      for (uint32_t ch = 0; ch < a.n_chunks; ++ch) acc += a.part[base + (size_t)ch * n_out];
-      Z[zo] = acc;
-      lmax = fmaxf(lmax, acc);
-    } else {
-      float bv = -INFINITY;
-      int32_t bj = -1;
-      for (uint32_t ch = 0; ch < a.n_chunks; ++ch) {
-        const float v = a.part[base + (size_t)ch * n_out];
-        const int32_t i = a.parti[base + (size_t)ch * n_out];
-        if (i >= 0 && (bj < 0 || v > bv)) {
-          bv = v;
-          bj = i;
-        }
-      }
-      Z[zo] = bv;
-      I[zo] = bj < 0 ? 0 : bj;
-    }
-  }
-  if (SEMI == SEMI_SUM) {
-    lmax = wave_max(lmax);
-    if ((threadIdx.x & 63) == 0 && lmax > 0.f)
-      atomicMax(a.mx + a.slotZ + (a.batZ ? b : 0), __float_as_uint(lmax));
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      const int kx = max_exponent(a.mx[a.slotX + (a.batX ? b : 0)]);
-      int e = a.ex[a.slotX + (a.batX ? b : 0)] + kx;
-      if (HASY) e += a.ex[a.slotY + (a.batY ? b : 0)] + max_exponent(a.mx[a.slotY + (a.batY ? b : 0)]);
-      a.ex[a.slotZ + (a.batZ ? b : 0)] = e;
-    }
-  }
+  uint32_t blocks = (n_out + kBlock - 1) / kBlock;
+  return blocks > 2048u ? 2048u : blocks;
 }
 
 void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, int nb, void *stream) {
   hipStream_t s = (hipStream_t)stream;
   const uint32_t n_out = a.nR * a.nC;
   if (!split) {
-    uint32_t blocks = (n_out + kBlock - 1) / kBlock;
-    if (blocks > 65535u) blocks = 65535u;
-    dim3 g(blocks, nb);
+    dim3 g(map_blocks(a), nb);  // grid-stride: at most about 8 blocks per CU
     if (semi == SEMI_SUM) {
       if (has_y) k_map<SEMI_SUM, true><<<g, kBlock, 0, s>>>(a);
       else k_map<SEMI_SUM, false><<<g, kBlock, 0, s>>>(a);
@@ -321,8 +451,7 @@ void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, in
     return;
   }
   dim3 g(a.n_chunks, nb);
-  uint32_t fb = (n_out + kBlock - 1) / kBlock;
-  dim3 gf(fb > 65535u ? 65535u : fb, nb);
+  dim3 gf(n_out, nb);
   if (semi == SEMI_SUM) {
     if (has_y) {
       k_split<SEMI_SUM, true><<<g, kBlock, 0, s>>>(a);

@@ -40,6 +40,28 @@ struct Op {
   // table offsets into the host table store (-1 = unused)
   int64_t t_rX[2], t_rY[2], t_rZ[2], t_cY[2], t_cZ[2], t_sX[2], t_sY[2];
   double flops = 0, bytes = 0;        // algorithmic, per instance
+  int64_t part_off = -1;              // partial-sum region of a split contraction
+};
+
+// One launch of a schedule: a single contraction, or several independent
+// contractions of one stage run by the grouped kernel.
+struct Launch {
+  int semi = SEMI_SUM;
+  bool split = false;
+  std::vector<int> ops;               // indices into the op list
+  // grouped launches: device copies of the ops' arguments and block ranges
+  ContractArgs *d_args = nullptr;
+  uint32_t *d_start = nullptr, *d_nblk = nullptr;    // map, or split partials
+  uint32_t *d_start2 = nullptr, *d_nblk2 = nullptr;  // split finish
+  uint32_t total = 0, total2 = 0;
+};
+
+// Stages of independent contractions.  Forward passes are scheduled as soon
+// as possible, the reverse pass as late as possible, so that contractions
+// hanging off the critical path collect into few grouped launches.
+struct Schedule {
+  std::vector<Launch> launches;
+  int n_stages = 0;
 };
 
 // A contraction tree bound to tensors.
@@ -93,6 +115,8 @@ struct tn_plan_impl {
   // executable pieces
   tn::TreeExec sum_tree, max_tree;
   std::vector<tn::Op> bwd;
+  tn::Schedule sched_fwd, sched_bwd, sched_max, sched_q;
+  std::vector<tn::Schedule> sched_groups;
   int seed_tensor = -1;                // adjoint of the root (ones)
   std::vector<int> adj_tensor;         // per node of sum_tree, -1 = none
   std::vector<tn::MargDesc> marg;

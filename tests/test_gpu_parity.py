@@ -124,7 +124,6 @@ def test_grid20x20_full_size_against_oracle(T):
     info = P.info()
     assert info["sc"] <= 22
     lz, m = P.marginals()
-    assert rel(lz[0], ref["log_z"]) <= 1e-5 * abs(ref["log_z"]) / max(1, abs(ref["log_z"])) * 1.0 + 1e-5
     assert abs(lz[0] - ref["log_z"]) / abs(ref["log_z"]) <= 1e-5
     got = np.array([r[1] for r in P.split_marginals(m[0])])
     err = np.abs(got - np.array(ref["p1"])).max()
@@ -227,18 +226,23 @@ def test_mmap_small(T, seed):
 
 
 def test_mmap_sliced(T):
-    c = W.config(4, seed=0, small=True)
-    net, q = c["net"], c["query"]
+    """Slicing the sum phase (cap below the group's largest intermediate)
+    gives the same MMAP as the unsliced plan and the oracle."""
+    net = W.random_regular3(40, seed=0, n_query=4)
+    q = net.meta["query"]
     ov, ox, ogap = oracle.mmap(net, q)
-    P = T.Plan(T.Network(net), query=q, max_log2_size=10)
-    assert P.info()["n_sliced"] > 0
-    val, x = P.mmap()
-    if ogap > 1e-4:
-        assert np.array_equal(x, ox)
-    assert abs(val - ov) <= 1e-5 * max(1, abs(ov))
     P0 = T.Plan(T.Network(net), query=q)
+    sc0 = P0.info()["sc"]
     val0, x0 = P0.mmap()
     assert abs(val0 - ov) <= 1e-5 * max(1, abs(ov))
+    cap = max(float(len(q)), sc0 - 2)
+    P = T.Plan(T.Network(net), query=q, max_log2_size=cap)
+    info = P.info()
+    assert info["n_sliced"] > 0 and info["sc"] <= cap
+    val, x = P.mmap()
+    if ogap > 1e-4:
+        assert np.array_equal(x, ox) and np.array_equal(x0, ox)
+    assert abs(val - ov) <= 1e-5 * max(1, abs(ov))
 
 
 def test_sampling_same_rng_as_oracle(T):
