@@ -258,6 +258,34 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
     op.part_off = p->part_floats;
     p->part_floats += ((int64_t)op.nb * a.n_chunks * n_out + 63) / 64 * 64;
   }
+  // row form for skinny contractions: few summed entries and columns
+  if (!op.split && a.nS <= (uint32_t)kRowMax && a.nC <= (uint32_t)kRowMax && a.nS * a.nC <= 64) {
+    a.kind = 1;
+    a.ns = (int32_t)a.nS;
+    a.nc = (int32_t)a.nC;
+    auto offsets = [&](const Labels &L, const Labels &TL, int32_t *dst) {
+      const int64_t n = numel(L, card);
+      std::vector<int> d(L.size(), 0);
+      for (int64_t i = 0; i < n; ++i) {
+        int64_t off = 0;
+        for (size_t j = 0; j < L.size(); ++j) off += (int64_t)d[j] * stride_in(TL, L[j], card);
+        dst[i] = (int32_t)off;
+        for (int j = (int)L.size() - 1; j >= 0; --j) {
+          if (++d[j] < card[L[j]]) break;
+          d[j] = 0;
+        }
+      }
+    };
+    offsets(S, LX, a.sx);
+    offsets(S, LY, a.sy);
+    offsets(C, LY, a.cy);
+    offsets(C, LZ, a.cz);
+    if ((a.nRl & (a.nRl - 1)) == 0) {
+      int sh = 0;
+      while ((1u << sh) < a.nRl) ++sh;
+      a.rl_shift = sh;
+    }
+  }
   op.flops = 2.0 * (double)n_out * (double)a.nS;
   op.bytes = 4.0 * (double)(p->T[X].size + (Y >= 0 ? p->T[Y].size : 0) + p->T[Z].size);
   return op;
@@ -522,6 +550,7 @@ static void fill_args(tn_plan_t *p, Op &op) {
   a.I = op.I >= 0 ? p->iarena + p->IB[op.I].off : nullptr;
   a.mx = p->mx;
   a.ex = p->ex;
+  a.mx_stride = std::max(1, p->n_slots);
   a.slotX = X.slot;
   a.batX = X.batched;
   a.slotZ = Z.slot;
@@ -669,9 +698,9 @@ static void allocate(tn_plan_t *p, const tn_net *net) {
   p->iarena_ints = ioff;
   p->arena = dalloc<float>(p, (size_t)p->arena_floats);
   p->iarena = dalloc<int32_t>(p, (size_t)p->iarena_ints + 64);
-  p->mx = dalloc<uint32_t>(p, (size_t)std::max(1, p->n_slots));
+  p->mx = dalloc<uint32_t>(p, (size_t)kMaxSubSlots * std::max(1, p->n_slots));
   p->ex = dalloc<int32_t>(p, (size_t)std::max(1, p->n_slots));
-  hip_check(hipMemset(p->mx, 0, sizeof(uint32_t) * std::max(1, p->n_slots)), "memset");
+  hip_check(hipMemset(p->mx, 0, sizeof(uint32_t) * kMaxSubSlots * std::max(1, p->n_slots)), "memset");
   hip_check(hipMemset(p->ex, 0, sizeof(int32_t) * std::max(1, p->n_slots)), "memset");
   // factor stores: linear FP32 and log FP32 (host FP64 conversion, rounded once)
   std::vector<float> lin(net->n_values), lg(net->n_values);
@@ -715,6 +744,19 @@ static void allocate(tn_plan_t *p, const tn_net *net) {
   for (auto &g : p->groups)
     for (auto &op : g.ops) fill_args(p, op);
   for (auto &op : p->qtree.ops) fill_args(p, op);
+  {
+    std::vector<Op *> all;
+    for (auto &op : p->sum_tree.ops) all.push_back(&op);
+    for (auto &op : p->max_tree.ops) all.push_back(&op);
+    for (auto &op : p->bwd) all.push_back(&op);
+    for (auto &g : p->groups)
+      for (auto &op : g.ops) all.push_back(&op);
+    for (auto &op : p->qtree.ops) all.push_back(&op);
+    std::vector<ContractArgs> host;
+    for (Op *op : all) host.push_back(op->a);
+    ContractArgs *d = dupload(p, host);
+    for (size_t i = 0; i < all.size(); ++i) all[i]->d_a = d + i;
+  }
   p->sched_fwd = build_schedule(p, p->sum_tree.ops, false);
   p->sched_bwd = build_schedule(p, p->bwd, true);
   p->sched_max = build_schedule(p, p->max_tree.ops, false);
@@ -1044,14 +1086,14 @@ extern "C" tn_status tn_plan_tree_host(const tn_net *net, const tn_plan_opts *op
 namespace tn {
 
 void run_ops(tn_plan_t *p, const std::vector<Op> &ops) {
-  for (const Op &op : ops) launch_contract(op.semi, op.Y >= 0, op.split, op.a, op.nb, p->stream);
+  for (const Op &op : ops) launch_contract(op.semi, op.Y >= 0, op.split, op.a, op.d_a, op.nb, p->stream);
 }
 
 void run_sched(tn_plan_t *p, const std::vector<Op> &ops, const Schedule &sc) {
   for (const Launch &L : sc.launches) {
     if (L.ops.size() == 1) {
       const Op &op = ops[L.ops[0]];
-      launch_contract(op.semi, op.Y >= 0, op.split, op.a, op.nb, p->stream);
+      launch_contract(op.semi, op.Y >= 0, op.split, op.a, op.d_a, op.nb, p->stream);
     } else if (!L.split) {
       launch_group(L.semi, 0, L.d_args, L.d_start, L.d_nblk, (int)L.ops.size(), L.total, p->stream);
     } else {
@@ -1072,6 +1114,7 @@ static PrepareArgs prep_args(tn_plan_t *p, const std::vector<LeafDesc> &h, const
   a.n_vars = p->n_vars;
   a.mx = p->mx;
   a.ex = p->ex;
+  a.mx_stride = std::max(1, p->n_slots);
   a.reset_begin = reset ? p->reset_begin : 0;
   a.reset_end = reset ? p->reset_end : 0;
   a.batch = p->max_batch;
@@ -1528,7 +1571,7 @@ extern "C" tn_status tn_profile(tn_plan_t *p, int32_t task, int32_t batch, const
         const int kind = (op.split ? 2 : 0) + (op.semi == SEMI_MAX ? 1 : 0);
         double by = op.bytes + (op.semi == SEMI_MAX ? 4.0 * p->T[op.Z].size : 0.0);
         ls.push_back({kind, op.flops * op.nb, by * op.nb,
-                      [p, &op] { launch_contract(op.semi, op.Y >= 0, op.split, op.a, op.nb, p->stream); }});
+                      [p, &op] { launch_contract(op.semi, op.Y >= 0, op.split, op.a, op.d_a, op.nb, p->stream); }});
       }
     };
     if (task <= 1) {

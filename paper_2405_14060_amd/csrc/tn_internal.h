@@ -76,6 +76,9 @@ struct Tab2 {
   const int32_t *hi = nullptr, *lo = nullptr;
 };
 
+static constexpr int kRowMax = 16;
+static constexpr int kMaxSubSlots = 64;  // sub-slots per recorded maximum
+
 struct ContractArgs {
   const float *X = nullptr, *Y = nullptr;
   float *Z = nullptr;
@@ -89,17 +92,26 @@ struct ContractArgs {
   // power-of-two scaling slots (sum-product)
   uint32_t *mx = nullptr;
   int32_t *ex = nullptr;
+  int32_t mx_stride = 0;  // sub-slot stride of mx (number of slots)
   int32_t slotX = -1, slotY = -1, slotZ = -1;
   int32_t batX = 0, batY = 0, batZ = 0;  // 1 if the slot is per instance
   // split reduction scratch
   float *part = nullptr;
   int32_t *parti = nullptr;
   uint32_t n_chunks = 1;
+  // row form (kind 1): one lane per row, all summed entries and columns in
+  // registers; offsets of the summed entries in X, Y and of the columns in
+  // Y, Z, in canonical order
+  int32_t kind = 0;  // 0 generic, 1 row form
+  int32_t ns = 0, nc = 0;
+  int32_t rl_shift = -1;  // log2(nRl) when nRl is a power of two
+  int32_t sx[kRowMax], sy[kRowMax], cy[kRowMax], cz[kRowMax];
 };
 
 enum Semiring { SEMI_SUM = 0, SEMI_MAX = 1 };
 
-void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, int nb,
+// a: host copy (grid shape); d_a: the same arguments in device memory
+void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, const ContractArgs *d_a, int nb,
                      void *stream);
 // blocks per instance of a one-lane-per-output launch
 uint32_t map_blocks(const ContractArgs &a);
@@ -130,6 +142,7 @@ struct PrepareArgs {
   int n_vars = 0;
   uint32_t *mx = nullptr;
   int32_t *ex = nullptr;
+  int32_t mx_stride = 0;
   int reset_begin = 0, reset_end = 0;  // slots zeroed each solve
   int batch = 1;
   int max_batch = 1;

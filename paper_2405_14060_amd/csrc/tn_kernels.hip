@@ -56,6 +56,18 @@ __device__ __forceinline__ int max_exponent(uint32_t bits) {
   return k < -126 ? -126 : (k > 126 ? 126 : k);
 }
 
+// Maxima live in kMaxSub sub-slots per tensor, sub-slot-major
+// (mx[sub * stride + slot]) so that the sub-slots of one tensor sit on
+// different cache lines: the workgroups of a launch spread their atomics
+// over them instead of serialising on one address.  A reader takes the
+// maximum over the sub-slots with one wave-wide load.
+static constexpr int kMaxSub = kMaxSubSlots;
+
+__device__ __forceinline__ uint32_t read_max(const uint32_t *mx, int stride, int slot) {
+  const uint32_t v = mx[(threadIdx.x & 63) * stride + slot];
+  return __float_as_uint(wave_max(__uint_as_float(v)));
+}
+
 // Record the block's maximum in *slot.  One candidate per block; the atomic
 // is skipped when the stored value is already larger (maxima only grow
 // within a launch, so a stale read only costs an unneeded atomic).
@@ -90,10 +102,10 @@ __device__ __forceinline__ void map_body(const ContractArgs &a, const int b, con
   float sx = 1.f, sy = 1.f;
   int kx = 0, ky = 0;
   if (SEMI == SEMI_SUM) {
-    kx = max_exponent(a.mx[a.slotX + (a.batX ? b : 0)]);
+    kx = max_exponent(read_max(a.mx, a.mx_stride, a.slotX + (a.batX ? b : 0)));
     sx = ldexpf(1.f, -kx);
     if (HASY) {
-      ky = max_exponent(a.mx[a.slotY + (a.batY ? b : 0)]);
+      ky = max_exponent(read_max(a.mx, a.mx_stride, a.slotY + (a.batY ? b : 0)));
       sy = ldexpf(1.f, -ky);
     }
   }
@@ -154,7 +166,7 @@ __device__ __forceinline__ void map_body(const ContractArgs &a, const int b, con
     }
   }
   if (SEMI == SEMI_SUM) {
-    block_record_max(lmax, a.mx + a.slotZ + (a.batZ ? b : 0));
+    block_record_max(lmax, a.mx + (blk % kMaxSub) * a.mx_stride + a.slotZ + (a.batZ ? b : 0));
     if (blk == 0 && threadIdx.x == 0) {
       int e = a.ex[a.slotX + (a.batX ? b : 0)] + kx;
       if (HASY) e += a.ex[a.slotY + (a.batY ? b : 0)] + ky;
@@ -177,8 +189,8 @@ __device__ __forceinline__ void split_body(const ContractArgs &a, const int b, c
   const float *__restrict__ Y = HASY ? a.Y + (int64_t)b * a.bsY : nullptr;
   float sx = 1.f, sy = 1.f;
   if (SEMI == SEMI_SUM) {
-    sx = ldexpf(1.f, -max_exponent(a.mx[a.slotX + (a.batX ? b : 0)]));
-    if (HASY) sy = ldexpf(1.f, -max_exponent(a.mx[a.slotY + (a.batY ? b : 0)]));
+    sx = ldexpf(1.f, -max_exponent(read_max(a.mx, a.mx_stride, a.slotX + (a.batX ? b : 0))));
+    if (HASY) sy = ldexpf(1.f, -max_exponent(read_max(a.mx, a.mx_stride, a.slotY + (a.batY ? b : 0))));
   }
   const uint32_t nSh = a.nS / a.nSl;
   const uint32_t per = (nSh + a.n_chunks - 1) / a.n_chunks;
@@ -224,7 +236,7 @@ __device__ __forceinline__ void split_body(const ContractArgs &a, const int b, c
         const int32_t sidx = (int32_t)(sh * a.nSl + sl);
 #pragma unroll
         for (int j = 0; j < kSplitOuts; ++j) {
-          if (j >= no) break;
+          if (j >= no) continue;
           if (SEMI == SEMI_SUM) {
             const float xv = X[xo[j] + xs] * sx;
             acc[j] = HASY ? fmaf(xv, Y[yo[j] + ys] * sy, acc[j]) : acc[j] + xv;
@@ -242,7 +254,7 @@ __device__ __forceinline__ void split_body(const ContractArgs &a, const int b, c
     // reduce every output over the block, fixed shape
 #pragma unroll
     for (int j = 0; j < kSplitOuts; ++j) {
-      if (j >= no) break;
+      if (j >= no) continue;
       float v = acc[j];
       int32_t i = arg[j];
       if (SEMI == SEMI_SUM) {
@@ -307,6 +319,11 @@ __device__ __forceinline__ void finish_body(const ContractArgs &a, const int b, 
   __shared__ float sv[kBlock / 64];
   __shared__ int32_t si[kBlock / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int kx = 0, ky = 0;
+  if (SEMI == SEMI_SUM && o == 0) {  // whole-block branch: every wave reads
+    kx = max_exponent(read_max(a.mx, a.mx_stride, a.slotX + (a.batX ? b : 0)));
+    if (HASY) ky = max_exponent(read_max(a.mx, a.mx_stride, a.slotY + (a.batY ? b : 0)));
+  }
   if (SEMI == SEMI_SUM) {
     float acc = 0.f;
     for (uint32_t ch = threadIdx.x; ch < a.n_chunks; ch += kBlock) acc += a.part[base + (size_t)ch * n_out];
@@ -317,11 +334,10 @@ __device__ __forceinline__ void finish_body(const ContractArgs &a, const int b, 
       float t = 0.f;
       for (int w = 0; w < kBlock / 64; ++w) t += sv[w];
       Z[zo] = t;
-      if (t > 0.f) atomicMax(a.mx + a.slotZ + (a.batZ ? b : 0), __float_as_uint(t));
+      if (t > 0.f) atomicMax(a.mx + (o % kMaxSub) * a.mx_stride + a.slotZ + (a.batZ ? b : 0), __float_as_uint(t));
       if (o == 0) {
-        const int kx = max_exponent(a.mx[a.slotX + (a.batX ? b : 0)]);
         int e = a.ex[a.slotX + (a.batX ? b : 0)] + kx;
-        if (HASY) e += a.ex[a.slotY + (a.batY ? b : 0)] + max_exponent(a.mx[a.slotY + (a.batY ? b : 0)]);
+        if (HASY) e += a.ex[a.slotY + (a.batY ? b : 0)] + ky;
         a.ex[a.slotZ + (a.batZ ? b : 0)] = e;
       }
     }
@@ -365,17 +381,108 @@ __device__ __forceinline__ void finish_body(const ContractArgs &a, const int b, 
   }
 }
 
+// --------------------------------------------------------------------------
+// row form: one lane per row of the output; the summed entries (<= B) are
+// loaded once into registers and every column (<= B) is produced from them
+// --------------------------------------------------------------------------
+template <int SEMI, bool HASY, int B>
+__device__ __forceinline__ void rows_body(const ContractArgs &a, const int b, const uint32_t blk,
+                                          const uint32_t nblk) {
+  const float *__restrict__ X = a.X + (int64_t)b * a.bsX;
+  const float *__restrict__ Y = HASY ? a.Y + (int64_t)b * a.bsY : nullptr;
+  float *__restrict__ Z = a.Z + (int64_t)b * a.bsZ;
+  int32_t *__restrict__ I = SEMI == SEMI_MAX ? a.I + (int64_t)b * a.bsZ : nullptr;
+  float sx = 1.f, sy = 1.f;
+  int kx = 0, ky = 0;
+  if (SEMI == SEMI_SUM) {
+    kx = max_exponent(read_max(a.mx, a.mx_stride, a.slotX + (a.batX ? b : 0)));
+    sx = ldexpf(1.f, -kx);
+    if (HASY) {
+      ky = max_exponent(read_max(a.mx, a.mx_stride, a.slotY + (a.batY ? b : 0)));
+      sy = ldexpf(1.f, -ky);
+    }
+  }
+  const int ns = a.ns, nc = a.nc;
+  float lmax = 0.f;
+  for (uint32_t r = blk * kBlock + threadIdx.x; r < a.nR; r += nblk * kBlock) {
+    uint32_t rh, rl;
+    if (a.rl_shift >= 0) {
+      rh = r >> a.rl_shift;
+      rl = r & (a.nRl - 1);
+    } else {
+      rh = r / a.nRl;
+      rl = r - rh * a.nRl;
+    }
+    const int32_t xo = a.rX.hi[rh] + a.rX.lo[rl];
+    const int32_t zo = a.rZ.hi[rh] + a.rZ.lo[rl];
+    const int32_t yo = HASY ? a.rY.hi[rh] + a.rY.lo[rl] : 0;
+    float xv[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+      if (k < ns) xv[k] = SEMI == SEMI_SUM ? X[xo + a.sx[k]] * sx : X[xo + a.sx[k]];
+#pragma unroll
+    for (int c = 0; c < B; ++c) {
+      if (c >= nc) continue;
+      const int32_t yc = yo + a.cy[c];
+      if (SEMI == SEMI_SUM) {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+          if (k < ns) acc = HASY ? fmaf(xv[k], Y[yc + a.sy[k]] * sy, acc) : acc + xv[k];
+        Z[zo + a.cz[c]] = acc;
+        lmax = fmaxf(lmax, acc);
+      } else {
+        float best = -INFINITY;
+        int32_t bi = 0;
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+          if (k < ns) {
+            float v = xv[k];
+            if (HASY) v = v + Y[yc + a.sy[k]];
+            if (k == 0 || v > best) {
+              best = v;
+              bi = k;
+            }
+          }
+        Z[zo + a.cz[c]] = best;
+        I[zo + a.cz[c]] = bi;
+      }
+    }
+  }
+  if (SEMI == SEMI_SUM) {
+    block_record_max(lmax, a.mx + (blk % kMaxSub) * a.mx_stride + a.slotZ + (a.batZ ? b : 0));
+    if (blk == 0 && threadIdx.x == 0) {
+      int e = a.ex[a.slotX + (a.batX ? b : 0)] + kx;
+      if (HASY) e += a.ex[a.slotY + (a.batY ? b : 0)] + ky;
+      a.ex[a.slotZ + (a.batZ ? b : 0)] = e;
+    }
+  }
+}
+
 template <int SEMI, bool HASY>
-__global__ __launch_bounds__(kBlock) void k_map(ContractArgs a) {
-  map_body<SEMI, HASY>(a, blockIdx.y, blockIdx.x, gridDim.x);
+__device__ __forceinline__ void any_map_body(const ContractArgs &a, const int b, const uint32_t blk,
+                                             const uint32_t nblk) {
+  if (a.kind == 1) {
+    if (a.ns <= 4 && a.nc <= 4) rows_body<SEMI, HASY, 4>(a, b, blk, nblk);
+    else rows_body<SEMI, HASY, kRowMax>(a, b, blk, nblk);
+  } else {
+    map_body<SEMI, HASY>(a, b, blk, nblk);
+  }
+}
+
+// Arguments live in device memory (a pointer is the only kernel argument):
+// large by-value argument blocks cost microseconds per launch.
+template <int SEMI, bool HASY>
+__global__ __launch_bounds__(kBlock) void k_map(const ContractArgs *__restrict__ ap) {
+  any_map_body<SEMI, HASY>(*ap, blockIdx.y, blockIdx.x, gridDim.x);
 }
 template <int SEMI, bool HASY>
-__global__ __launch_bounds__(kBlock) void k_split(ContractArgs a) {
-  split_body<SEMI, HASY>(a, blockIdx.y, blockIdx.x);
+__global__ __launch_bounds__(kBlock) void k_split(const ContractArgs *__restrict__ ap) {
+  split_body<SEMI, HASY>(*ap, blockIdx.y, blockIdx.x);
 }
 template <int SEMI, bool HASY>
-__global__ __launch_bounds__(kBlock) void k_split_finish(ContractArgs a) {
-  finish_body<SEMI, HASY>(a, blockIdx.y, blockIdx.x);
+__global__ __launch_bounds__(kBlock) void k_split_finish(const ContractArgs *__restrict__ ap) {
+  finish_body<SEMI, HASY>(*ap, blockIdx.y, blockIdx.x);
 }
 
 // Several independent contractions in one launch (one stage of the tree
@@ -396,15 +503,15 @@ __global__ __launch_bounds__(kBlock) void k_group(const ContractArgs *__restrict
                                                   const uint32_t *__restrict__ start,
                                                   const uint32_t *__restrict__ nblk, int n) {
   const int i = find_op(start, n, blockIdx.x);
-  const ContractArgs a = ops[i];
+  const ContractArgs &a = ops[i];
   const uint32_t local = blockIdx.x - start[i];
   const uint32_t per = nblk[i];
   const int b = (int)(local / per);
   const uint32_t blk = local - (uint32_t)b * per;
   const bool hy = a.Y != nullptr;
   if (PHASE == 0) {
-    if (hy) map_body<SEMI, true>(a, b, blk, per);
-    else map_body<SEMI, false>(a, b, blk, per);
+    if (hy) any_map_body<SEMI, true>(a, b, blk, per);
+    else any_map_body<SEMI, false>(a, b, blk, per);
   } else if (PHASE == 1) {
     if (hy) split_body<SEMI, true>(a, b, blk);
     else split_body<SEMI, false>(a, b, blk);
@@ -431,22 +538,23 @@ void launch_group(int semi, int phase, const ContractArgs *ops, const uint32_t *
 }
 
 uint32_t map_blocks(const ContractArgs &a) {
-  const uint32_t n_out = a.nR * a.nC;
+  const uint32_t n_out = a.kind == 1 ? a.nR : a.nR * a.nC;
   uint32_t blocks = (n_out + kBlock - 1) / kBlock;
   return blocks > 2048u ? 2048u : blocks;
 }
 
-void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, int nb, void *stream) {
+void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, const ContractArgs *d_a, int nb,
+                     void *stream) {
   hipStream_t s = (hipStream_t)stream;
   const uint32_t n_out = a.nR * a.nC;
   if (!split) {
     dim3 g(map_blocks(a), nb);  // grid-stride: at most about 8 blocks per CU
     if (semi == SEMI_SUM) {
-      if (has_y) k_map<SEMI_SUM, true><<<g, kBlock, 0, s>>>(a);
-      else k_map<SEMI_SUM, false><<<g, kBlock, 0, s>>>(a);
+      if (has_y) k_map<SEMI_SUM, true><<<g, kBlock, 0, s>>>(d_a);
+      else k_map<SEMI_SUM, false><<<g, kBlock, 0, s>>>(d_a);
     } else {
-      if (has_y) k_map<SEMI_MAX, true><<<g, kBlock, 0, s>>>(a);
-      else k_map<SEMI_MAX, false><<<g, kBlock, 0, s>>>(a);
+      if (has_y) k_map<SEMI_MAX, true><<<g, kBlock, 0, s>>>(d_a);
+      else k_map<SEMI_MAX, false><<<g, kBlock, 0, s>>>(d_a);
     }
     return;
   }
@@ -454,19 +562,19 @@ void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, in
   dim3 gf(n_out, nb);
   if (semi == SEMI_SUM) {
     if (has_y) {
-      k_split<SEMI_SUM, true><<<g, kBlock, 0, s>>>(a);
-      k_split_finish<SEMI_SUM, true><<<gf, kBlock, 0, s>>>(a);
+      k_split<SEMI_SUM, true><<<g, kBlock, 0, s>>>(d_a);
+      k_split_finish<SEMI_SUM, true><<<gf, kBlock, 0, s>>>(d_a);
     } else {
-      k_split<SEMI_SUM, false><<<g, kBlock, 0, s>>>(a);
-      k_split_finish<SEMI_SUM, false><<<gf, kBlock, 0, s>>>(a);
+      k_split<SEMI_SUM, false><<<g, kBlock, 0, s>>>(d_a);
+      k_split_finish<SEMI_SUM, false><<<gf, kBlock, 0, s>>>(d_a);
     }
   } else {
     if (has_y) {
-      k_split<SEMI_MAX, true><<<g, kBlock, 0, s>>>(a);
-      k_split_finish<SEMI_MAX, true><<<gf, kBlock, 0, s>>>(a);
+      k_split<SEMI_MAX, true><<<g, kBlock, 0, s>>>(d_a);
+      k_split_finish<SEMI_MAX, true><<<gf, kBlock, 0, s>>>(d_a);
     } else {
-      k_split<SEMI_MAX, false><<<g, kBlock, 0, s>>>(a);
-      k_split_finish<SEMI_MAX, false><<<gf, kBlock, 0, s>>>(a);
+      k_split<SEMI_MAX, false><<<g, kBlock, 0, s>>>(d_a);
+      k_split_finish<SEMI_MAX, false><<<gf, kBlock, 0, s>>>(d_a);
     }
   }
 }
@@ -480,9 +588,9 @@ __global__ __launch_bounds__(kBlock) void k_prepare(PrepareArgs a) {
   if ((int)blockIdx.x >= a.n_leaves) {
     if (b != 0) return;
     const int n = a.reset_end - a.reset_begin;
-    for (int i = (blockIdx.x - a.n_leaves) * kBlock + threadIdx.x; i < n;
+    for (int i = (blockIdx.x - a.n_leaves) * kBlock + threadIdx.x; i < n * kMaxSub;
          i += (gridDim.x - a.n_leaves) * kBlock)
-      a.mx[a.reset_begin + i] = 0u;
+      a.mx[(i / n) * a.mx_stride + a.reset_begin + i % n] = 0u;
     return;
   }
   const LeafDesc d = a.leaves[blockIdx.x];

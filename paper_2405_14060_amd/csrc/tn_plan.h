@@ -41,6 +41,7 @@ struct Op {
   int64_t t_rX[2], t_rY[2], t_rZ[2], t_cY[2], t_cZ[2], t_sX[2], t_sY[2];
   double flops = 0, bytes = 0;        // algorithmic, per instance
   int64_t part_off = -1;              // partial-sum region of a split contraction
+  ContractArgs *d_a = nullptr;        // device copy of `a`
 };
 
 // One launch of a schedule: a single contraction, or several independent
