@@ -99,6 +99,10 @@ typedef struct {
                                 the leaf ids described at tn_plan() */
   int32_t n_tree_pairs;
   int32_t want_factor_grad;  /* keep factor adjoints (tn_logZ_dev grads) */
+  int32_t host_only;         /* build host structures only (no device memory);
+                                only tn_plan_info_get / tn_plan_tree / tn_free_plan
+                                may then be called */
+  int32_t no_fuse;           /* keep every tree node a separate contraction */
 } tn_plan_opts;
 
 /* Summary of a plan (tn_plan_info). */
@@ -119,6 +123,8 @@ typedef struct {
   int32_t n_launches_fwd;        /* kernel launches after stage grouping */
   int32_t n_launches_bwd;
   int32_t n_launches_max;
+  int32_t n_segments;            /* fused chain segments */
+  int32_t n_fused_nodes;         /* tree nodes inside fused segments */
 } tn_plan_info;
 
 /* Fill *o with defaults: sum-product + max-plus, no evidence, best planner,

@@ -48,7 +48,8 @@ class PlanOpts(ctypes.Structure):
                 ("dtype", ctypes.c_int32), ("max_batch", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("hip_stream", ctypes.c_void_p),
                 ("tree_pairs", i32p), ("n_tree_pairs", ctypes.c_int32),
-                ("want_factor_grad", ctypes.c_int32)]
+                ("want_factor_grad", ctypes.c_int32), ("host_only", ctypes.c_int32),
+                ("no_fuse", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -59,7 +60,8 @@ class PlanInfo(ctypes.Structure):
                 ("flops_fwd", ctypes.c_double), ("bytes_fwd", ctypes.c_double),
                 ("n_sliced", ctypes.c_int32), ("planner_used", ctypes.c_int32),
                 ("device_bytes", ctypes.c_int64), ("n_launches_fwd", ctypes.c_int32),
-                ("n_launches_bwd", ctypes.c_int32), ("n_launches_max", ctypes.c_int32)]
+                ("n_launches_bwd", ctypes.c_int32), ("n_launches_max", ctypes.c_int32),
+                ("n_segments", ctypes.c_int32), ("n_fused_nodes", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -155,7 +157,7 @@ class Network:
 def make_opts(semirings=SUM_PRODUCT | MAX_PLUS, evidence_mode=EVIDENCE_NONE, observed=None,
               query=None, planner=PLANNER_BEST, restarts=4, seed=0, max_log2_size=0.0,
               dtype=TN_F32, max_batch=1, use_graph=True, stream=None, tree=None,
-              want_factor_grad=False):
+              want_factor_grad=False, host_only=False, fuse=True):
     o = PlanOpts()
     lib().tn_plan_opts_default(ctypes.byref(o))
     keep = []
@@ -185,6 +187,8 @@ def make_opts(semirings=SUM_PRODUCT | MAX_PLUS, evidence_mode=EVIDENCE_NONE, obs
         o.tree_pairs = _ptr(t, ctypes.c_int32)
         o.n_tree_pairs = int(t.shape[0])
     o.want_factor_grad = 1 if want_factor_grad else 0
+    o.host_only = 1 if host_only else 0
+    o.no_fuse = 0 if fuse else 1
     return o, keep
 
 

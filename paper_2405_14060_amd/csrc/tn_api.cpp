@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <numeric>
@@ -568,12 +569,18 @@ static Schedule build_schedule(tn_plan_t *p, const std::vector<Op> &ops, bool al
   const int n = (int)ops.size();
   if (n == 0) return sc;
   std::map<int, int> producer;  // tensor id -> op index
-  for (int i = 0; i < n; ++i) producer[ops[i].Z] = i;
+  for (int i = 0; i < n; ++i) {
+    producer[ops[i].Z] = i;
+    for (int t : ops[i].outs) producer[t] = i;
+  }
   std::vector<int> stage(n, 0);
   std::vector<std::vector<int>> consumers(n);
   for (int i = 0; i < n; ++i) {
     int st = 0;
-    for (int t : {ops[i].X, ops[i].Y}) {
+    std::vector<int> inputs = ops[i].ins;
+    inputs.push_back(ops[i].X);
+    inputs.push_back(ops[i].Y);
+    for (int t : inputs) {
       if (t < 0) continue;
       auto it = producer.find(t);
       if (it != producer.end() && it->second < i) {
@@ -592,24 +599,34 @@ static Schedule build_schedule(tn_plan_t *p, const std::vector<Op> &ops, bool al
     }
   }
   sc.n_stages = smax + 1;
-  // launches: per stage, map ops of each semiring together, split ops together
-  for (int st = 0; st <= smax; ++st)
+  // launches: per stage, map ops of each semiring together, split ops
+  // together, fused segments alone
+  for (int st = 0; st <= smax; ++st) {
+    for (int i = 0; i < n; ++i)
+      if (stage[i] == st && ops[i].seg >= 0) {
+        Launch L;
+        L.seg = true;
+        L.ops.push_back(i);
+        sc.launches.push_back(std::move(L));
+      }
     for (int semi = 0; semi < 2; ++semi)
       for (int spl = 0; spl < 2; ++spl) {
         Launch L;
         L.semi = semi;
         L.split = spl != 0;
         for (int i = 0; i < n; ++i)
-          if (stage[i] == st && ops[i].semi == semi && ops[i].split == (spl != 0)) L.ops.push_back(i);
+          if (stage[i] == st && ops[i].seg < 0 && ops[i].semi == semi && ops[i].split == (spl != 0))
+            L.ops.push_back(i);
         if (!L.ops.empty()) sc.launches.push_back(std::move(L));
       }
+  }
   (void)p;
   return sc;
 }
 
 static void upload_schedule(tn_plan_t *p, Schedule &sc, const std::vector<Op> &ops) {
   for (Launch &L : sc.launches) {
-    if (L.ops.size() < 2) continue;
+    if (L.seg || L.ops.size() < 2) continue;
     std::vector<ContractArgs> args;
     std::vector<uint32_t> st, nb, st2, nb2;
     uint32_t tot = 0, tot2 = 0;
@@ -648,6 +665,7 @@ tn_plan_impl::~tn_plan_impl() {
 
 static void build_mmap(tn_plan_t *p, const tn_net *net);
 static void allocate_mmap(tn_plan_t *p);
+static void upload_segments(tn_plan_t *p);
 
 static void allocate(tn_plan_t *p, const tn_net *net) {
   // device work starts here: everything above is host-side planning
@@ -769,6 +787,26 @@ static void allocate(tn_plan_t *p, const tn_net *net) {
     p->sched_groups.push_back(build_schedule(p, g.ops, false));
     upload_schedule(p, p->sched_groups.back(), g.ops);
   }
+  if (p->fused) {
+    for (auto &op : p->ffwd)
+      if (op.seg < 0) fill_args(p, op);
+    for (auto &op : p->fbwd)
+      if (op.seg < 0) fill_args(p, op);
+    std::vector<Op *> all;
+    for (auto &op : p->ffwd)
+      if (op.seg < 0) all.push_back(&op);
+    for (auto &op : p->fbwd)
+      if (op.seg < 0) all.push_back(&op);
+    std::vector<ContractArgs> host;
+    for (Op *op : all) host.push_back(op->a);
+    ContractArgs *d = dupload(p, host);
+    for (size_t i = 0; i < all.size(); ++i) all[i]->d_a = d + i;
+    upload_segments(p);
+    p->sched_ffwd = build_schedule(p, p->ffwd, false);
+    p->sched_fbwd = build_schedule(p, p->fbwd, true);
+    upload_schedule(p, p->sched_ffwd, p->ffwd);
+    upload_schedule(p, p->sched_fbwd, p->fbwd);
+  }
   p->d_leaves_sum = dupload(p, p->leaves_sum);
   p->d_leaves_max = dupload(p, p->leaves_max);
   p->d_qleaves = dupload(p, p->qleaves);
@@ -821,6 +859,346 @@ static void allocate(tn_plan_t *p, const tn_net *net) {
   p->d_samp = dupload(p, p->samp);
   p->d_samp_meta = dupload(p, p->samp_meta);
   if (p->is_mmap) allocate_mmap(p);
+}
+
+
+// ---------------------------------------------------------------------------
+// fused chain segments
+// ---------------------------------------------------------------------------
+static int64_t index_in(const Labels &L, const std::vector<int> &val, const std::vector<int> &card) {
+  int64_t k = 0;
+  for (int v : L) k = k * card[v] + val[v];
+  return k;
+}
+
+// Try to describe ops[first..] (chain order) as one segment; fills sp and
+// returns true if all size limits hold.
+static bool describe_segment(tn_plan_t *p, const std::vector<Op> &ops, const std::vector<int> &chain, SegPlan &sp,
+                             bool commit) {
+  const auto &card = p->card;
+  const int L = (int)chain.size();
+  std::vector<Labels> V(L + 1), U(L);
+  V[0] = p->T[ops[chain[0]].X].lab;
+  for (int j = 0; j < L; ++j) {
+    U[j] = p->T[ops[chain[j]].Y].lab;
+    V[j + 1] = p->T[ops[chain[j]].Z].lab;
+  }
+  Labels T;
+  for (int j = 0; j < L; ++j) {
+    Labels E = minus(unite(V[j], U[j]), V[j + 1]);
+    T = unite(T, unite(U[j], E));
+    Labels d1 = minus(V[j], V[j + 1]), d2 = minus(V[j + 1], V[j]);
+    T = unite(T, unite(d1, d2));
+  }
+  const Labels O = minus(V[0], T);
+  if (minus(O, V[L]).size()) return false;  // outer labels must survive
+  std::vector<Labels> Loc(L + 1);
+  for (int j = 0; j <= L; ++j) Loc[j] = inter(V[j], T);
+  const int te = 32;
+  for (int j = 0; j <= L; ++j)
+    if (numel(Loc[j], card) > te) return false;
+  int64_t n_sb = 0;
+  for (int j = 0; j < L; ++j) {
+    const Labels W = unite(Loc[j], U[j]);
+    if (numel(W, card) > 128) return false;
+    n_sb += numel(U[j], card);
+  }
+  const int64_t nO = numel(O, card);
+  if (nO < 256 || n_sb > 64) return false;
+  // LDS: lists (about 6 entries per triple plus pointers), coefficients and
+  // tiles; the reverse pass holds L + 2 tiles for one wave
+  {
+    int64_t nnz = 0, ptrs = 0;
+    for (int j = 0; j < L; ++j) {
+      nnz += numel(unite(Loc[j], U[j]), card);
+      ptrs += numel(Loc[j], card) + numel(Loc[j + 1], card) + numel(U[j], card) + 3;
+    }
+    const int64_t lists = 6 * nnz + ptrs;
+    // slabs of 32 outer assignments, rows padded to 33
+    if ((lists + 64 * L + 2 * nnz + (int64_t)(L + 2) * te * 33 + n_sb) * 4 > 64 * 1024) return false;
+    if ((lists + 64 * L + nnz + 2 * te * 33) * 4 > 64 * 1024) return false;
+  }
+  if (!commit) return true;
+  sp.ops = chain;
+  sp.c0 = ops[chain[0]].X;
+  sp.cL = ops[chain[L - 1]].Z;
+  sp.te = te;
+  sp.nO = (uint32_t)nO;
+  const size_t os = lo_split(O, card);
+  sp.nOl = (uint32_t)numel(Labels(O.begin() + os, O.end()), card);
+  add_tabs(p, O, os, V[0], sp.oX);
+  add_tabs(p, O, os, V[L], sp.oZ);
+  auto local_tab = [&](const Labels &Lc, const Labels &TL) {
+    int64_t off = (int64_t)p->tabs.size();
+    const int64_t n = numel(Lc, card);
+    std::vector<int> d(Lc.size(), 0);
+    for (int64_t i = 0; i < n; ++i) {
+      int64_t o = 0;
+      for (size_t k = 0; k < Lc.size(); ++k) o += (int64_t)d[k] * stride_in(TL, Lc[k], card);
+      p->tabs.push_back((int32_t)o);
+      for (int k = (int)Lc.size() - 1; k >= 0; --k) {
+        if (++d[k] < card[Lc[k]]) break;
+        d[k] = 0;
+      }
+    }
+    return off;
+  };
+  sp.in_outer_fast = (!V[0].empty() && !O.empty() && V[0].back() == O.back()) ? 1 : 0;
+  sp.out_outer_fast = (!V[L].empty() && !O.empty() && V[L].back() == O.back()) ? 1 : 0;
+  sp.inX = local_tab(Loc[0], V[0]);
+  sp.outZ = local_tab(Loc[L], V[L]);
+  sp.n_in0 = (int32_t)numel(Loc[0], card);
+  sp.n_outL = (int32_t)numel(Loc[L], card);
+  sp.n_sb = 0;
+  sp.steps.clear();
+  std::vector<int32_t> blk;  // the segment's lists, offsets relative to its start
+  int32_t c_off = 0;
+  std::vector<int> val(p->n_vars, 0);
+  for (int j = 0; j < L; ++j) {
+    SegStep st{};
+    st.y = ops[chain[j]].Y;  // tensor id until allocation
+    st.ny = (int32_t)numel(U[j], card);
+    st.n_in = (int32_t)numel(Loc[j], card);
+    st.n_out = (int32_t)numel(Loc[j + 1], card);
+    const Labels W = unite(Loc[j], U[j]);
+    const int64_t nW = numel(W, card);
+    std::vector<std::array<int32_t, 3>> tri;  // (in, out, s), enumeration order
+    std::vector<int> d(W.size(), 0);
+    for (int64_t w = 0; w < nW; ++w) {
+      for (size_t k = 0; k < W.size(); ++k) val[W[k]] = d[k];
+      int64_t so = 0;
+      for (int v : U[j]) so += (int64_t)val[v] * stride_in(U[j], v, card);
+      tri.push_back({(int32_t)index_in(Loc[j], val, card), (int32_t)index_in(Loc[j + 1], val, card), (int32_t)so});
+      for (int k = (int)W.size() - 1; k >= 0; --k) {
+        if (++d[k] < card[W[k]]) break;
+        d[k] = 0;
+      }
+    }
+    st.nnz = (int32_t)tri.size();
+    st.c_off = c_off;
+    c_off += st.nnz;
+    // CSR lists grouped by key (stable: enumeration order within a group,
+    // so every sum runs in a fixed order)
+    auto csr = [&](int key, int n, int a1, int a2, int32_t &ptr, int32_t &l1, int32_t &l2) {
+      std::vector<int32_t> cnt(n + 1, 0);
+      for (auto &t : tri) cnt[t[key] + 1]++;
+      for (int i = 0; i < n; ++i) cnt[i + 1] += cnt[i];
+      ptr = (int32_t)blk.size();
+      blk.insert(blk.end(), cnt.begin(), cnt.end());
+      std::vector<int32_t> x1(tri.size()), x2(tri.size()), pos(cnt.begin(), cnt.end() - 1);
+      for (auto &t : tri) {
+        const int32_t q = pos[t[key]]++;
+        x1[q] = t[a1];
+        x2[q] = t[a2];
+      }
+      l1 = (int32_t)blk.size();
+      blk.insert(blk.end(), x1.begin(), x1.end());
+      l2 = (int32_t)blk.size();
+      blk.insert(blk.end(), x2.begin(), x2.end());
+    };
+    csr(1, st.n_out, 0, 2, st.fo_ptr, st.fo_in, st.fo_s);
+    csr(0, st.n_in, 1, 2, st.bi_ptr, st.bi_out, st.bi_s);
+    csr(2, st.ny, 0, 1, st.bs_ptr, st.bs_in, st.bs_out);
+    sp.steps.push_back(st);
+  }
+  sp.list_off = (int64_t)p->tabs.size();
+  sp.list_len = (int32_t)blk.size();
+  sp.nnz_total = c_off;
+  p->tabs.insert(p->tabs.end(), blk.begin(), blk.end());
+  double b = 4.0 * (double)(p->T[sp.c0].size + p->T[sp.cL].size);
+  sp.bytes_fwd = b;
+  sp.bytes_bwd = 4.0 * (double)(2 * p->T[sp.c0].size + p->T[sp.cL].size);
+  for (int i : chain) sp.flops += ops[i].flops;
+  return true;
+}
+
+static void build_fusion(tn_plan_t *p, std::vector<char> &need, int L_leaves) {
+  const std::vector<Op> &ops = p->sum_tree.ops;
+  const int n = (int)ops.size();
+  std::map<int, int> prod;
+  for (int i = 0; i < n; ++i) prod[ops[i].Z] = i;
+  std::vector<char> chainable(n, 0);
+  for (int i = 0; i < n; ++i) {
+    const Op &op = ops[i];
+    chainable[i] = op.semi == SEMI_SUM && op.Y >= 0 && !op.split && p->T[op.Y].size <= 64 &&
+                   p->T[op.X].size >= 4096 && !p->T[op.X].batched && !p->T[op.Y].batched;
+  }
+  std::map<int, int> node_of;  // node of the sum tree that holds each tensor
+  for (size_t c = 0; c < p->sum_tree.node_tensor.size(); ++c) node_of[p->sum_tree.node_tensor[c]] = (int)c;
+  for (int i = 0; i < n; ++i)  // the reverse segment needs the carriers' adjoints
+    if (chainable[i] && !need[node_of.at(ops[i].X)]) chainable[i] = 0;
+  std::vector<int> next(n, -1), has_prev(n, 0);
+  for (int i = 0; i < n; ++i) {
+    if (!chainable[i]) continue;
+    auto it = prod.find(ops[i].X);
+    if (it != prod.end() && chainable[it->second]) {
+      next[it->second] = i;
+      has_prev[i] = 1;
+    }
+  }
+  std::vector<int> seg_of(n, -1);
+  for (int s0 = 0; s0 < n; ++s0) {
+    if (!chainable[s0] || has_prev[s0]) continue;
+    int cur = s0;
+    while (cur >= 0) {
+      std::vector<int> chain{cur};
+      SegPlan probe;
+      while (next[chain.back()] >= 0 && chain.size() < 8) {
+        chain.push_back(next[chain.back()]);
+        if (!describe_segment(p, ops, chain, probe, false)) {
+          chain.pop_back();
+          break;
+        }
+      }
+      int after = next[chain.back()];
+      if (chain.size() >= 2 && describe_segment(p, ops, chain, probe, false)) {
+        SegPlan sp;
+        describe_segment(p, ops, chain, sp, true);
+        for (int i : chain) seg_of[i] = (int)p->segs.size();
+        p->segs.push_back(std::move(sp));
+      }
+      cur = after;
+    }
+  }
+  if (p->segs.empty()) return;
+  p->fused = true;
+  // forward list: segment op at the position of its last node
+  for (int i = 0; i < n; ++i) {
+    if (seg_of[i] < 0) {
+      p->ffwd.push_back(ops[i]);
+      continue;
+    }
+    SegPlan &sp = p->segs[seg_of[i]];
+    if (i != sp.ops.back()) continue;
+    Op op;
+    op.seg = seg_of[i];
+    op.seg_kind = 1;
+    op.X = sp.c0;
+    op.Z = sp.cL;
+    for (int j : sp.ops) op.ins.push_back(ops[j].Y);
+    op.flops = sp.flops;
+    op.bytes = sp.bytes_fwd;
+    p->ffwd.push_back(op);
+  }
+  // reverse list: the two adjoint contractions of every fused node are
+  // replaced by one reverse segment at the position of the first of them
+  std::map<int, int> adj_to_seg;  // adjoint tensor produced by a replaced op -> segment
+  for (size_t si = 0; si < p->segs.size(); ++si) {
+    SegPlan &sp = p->segs[si];
+    sp.g = p->adj_tensor[node_of.at(sp.cL)];
+    sp.c0bar = p->adj_tensor[node_of.at(sp.c0)];
+    int32_t sb = 0;
+    for (size_t j = 0; j < sp.ops.size(); ++j) {
+      const Op &fo = ops[sp.ops[j]];
+      const int ynode = node_of.at(fo.Y), xnode = node_of.at(fo.X);
+      const int ybar = need[ynode] ? p->adj_tensor[ynode] : -1;
+      sp.ybar_tensor.push_back(ybar);
+      SegStep &st = sp.steps[j];
+      if (ybar >= 0) {
+        st.sb_off = sb;
+        sb += st.ny;
+        adj_to_seg[ybar] = (int)si;
+      }
+      if (p->adj_tensor[xnode] >= 0) adj_to_seg[p->adj_tensor[xnode]] = (int)si;
+    }
+    sp.n_sb = sb;
+    const int64_t blocks = (sp.nO + 31) / 32;
+    sp.part_off = p->part_floats;
+    p->part_floats += (blocks * std::max(1, sb) + 63) / 64 * 64;
+  }
+  std::vector<char> emitted(p->segs.size(), 0);
+  for (const Op &op : p->bwd) {
+    auto it = adj_to_seg.find(op.Z);
+    if (it == adj_to_seg.end()) {
+      p->fbwd.push_back(op);
+      continue;
+    }
+    const int si = it->second;
+    if (emitted[si]) continue;
+    emitted[si] = 1;
+    SegPlan &sp = p->segs[si];
+    Op b;
+    b.seg = si;
+    b.seg_kind = 2;
+    b.X = sp.g;
+    b.Z = sp.c0bar;
+    b.ins.push_back(sp.c0);
+    for (size_t j = 0; j < sp.ops.size(); ++j) {
+      b.ins.push_back(ops[sp.ops[j]].Y);
+      if (sp.ybar_tensor[j] >= 0) b.outs.push_back(sp.ybar_tensor[j]);
+    }
+    b.flops = 2 * sp.flops;
+    b.bytes = sp.bytes_bwd;
+    p->fbwd.push_back(b);
+  }
+  (void)L_leaves;
+}
+
+static void upload_segments(tn_plan_t *p) {
+  for (SegPlan &sp : p->segs) {
+    for (size_t j = 0; j < sp.steps.size(); ++j) {
+      SegStep &st = sp.steps[j];
+      const int yt = (int)st.y;
+      st.y = p->T[yt].off;
+      st.yslot = p->T[yt].slot;
+      if (sp.ybar_tensor[j] >= 0) {
+        st.ybar = p->T[sp.ybar_tensor[j]].off;
+        st.ybar_slot = p->T[sp.ybar_tensor[j]].slot;
+      }
+    }
+  }
+  for (int kind = 0; kind < 2; ++kind) {
+    std::vector<SegArgs> &H = kind ? p->seg_bwd_h : p->seg_fwd_h;
+    for (SegPlan &sp : p->segs) {
+      SegArgs a;
+      a.arena = p->arena;
+      a.mx = p->mx;
+      a.ex = p->ex;
+      a.mx_stride = std::max(1, p->n_slots);
+      a.nO = sp.nO;
+      a.nOl = sp.nOl;
+      if ((sp.nOl & (sp.nOl - 1)) == 0) {
+        int sh = 0;
+        while ((1u << sh) < sp.nOl) ++sh;
+        a.ol_shift = sh;
+      }
+      a.oX = Tab2{p->d_tabs + sp.oX[0], p->d_tabs + sp.oX[1]};
+      a.oZ = Tab2{p->d_tabs + sp.oZ[0], p->d_tabs + sp.oZ[1]};
+      a.inX = p->d_tabs + sp.inX;
+      a.outZ = p->d_tabs + sp.outZ;
+      a.n_in0 = sp.n_in0;
+      a.n_outL = sp.n_outL;
+      a.in_outer_fast = sp.in_outer_fast;
+      a.out_outer_fast = sp.out_outer_fast;
+      a.lists = p->d_tabs + sp.list_off;
+      a.list_len = sp.list_len;
+      a.nnz_total = sp.nnz_total;
+      a.te = sp.te;
+      a.n_steps = (int32_t)sp.steps.size();
+      std::vector<SegStep> st = sp.steps;
+      if (!kind) {
+        for (auto &x : st) x.sb_off = -1;
+        a.X = p->T[sp.c0].off;
+        a.slotX = p->T[sp.c0].slot;
+        a.Z = p->T[sp.cL].off;
+        a.slotZ = p->T[sp.cL].slot;
+      } else {
+        a.X = p->T[sp.c0].off;
+        a.slotX = p->T[sp.c0].slot;
+        a.G = p->T[sp.g].off;
+        a.slotG = p->T[sp.g].slot;
+        a.Z = p->T[sp.c0bar].off;
+        a.slotZ = p->T[sp.c0bar].slot;
+        a.n_sb = sp.n_sb;
+        a.part = p->d_part + sp.part_off;
+      }
+      a.steps = dupload(p, st);
+      H.push_back(a);
+    }
+    SegArgs *d = dupload(p, H);
+    if (kind) p->d_seg_bwd = d;
+    else p->d_seg_fwd = d;
+  }
 }
 
 static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
@@ -966,6 +1344,7 @@ static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
       }
     }
     if (p->mode != TN_EVIDENCE_INDICATOR) build_sampling(p, t);
+    if (!p->opts.no_fuse && p->mode != TN_EVIDENCE_INDICATOR) build_fusion(p, need, L);
   }
   if (p->want_max) {
     TreeExec &t = p->max_tree;
@@ -975,6 +1354,7 @@ static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
     build_forward(p, t, SEMI_MAX);
     build_backtrack(p, t);
   }
+  if (o->host_only) return;
   allocate(p, net);
 }
 
@@ -988,7 +1368,7 @@ extern "C" tn_status tn_plan(const tn_net *net, const tn_plan_opts *opts, tn_pla
     auto p = std::make_unique<tn_plan_impl>();
     p->net_src = net;
     make_plan(p.get(), net, &o);
-    hip_check(hipDeviceSynchronize(), "plan upload");
+    if (!o.host_only) hip_check(hipDeviceSynchronize(), "plan upload");
     *out = p.release();
   });
 }
@@ -1020,6 +1400,15 @@ extern "C" tn_status tn_plan_info_get(const tn_plan_t *p, tn_plan_info *info) {
     info->n_launches_fwd = count(p->sched_fwd);
     info->n_launches_bwd = count(p->sched_bwd);
     info->n_launches_max = count(p->sched_max);
+    if (p->opts.host_only) {  // schedules are built at allocation: count ops
+      info->n_launches_fwd = (int32_t)(p->fused ? p->ffwd.size() : p->sum_tree.ops.size());
+      info->n_launches_bwd = (int32_t)(p->fused ? p->fbwd.size() : p->bwd.size());
+    } else if (p->fused) {
+      info->n_launches_fwd = count(p->sched_ffwd);
+      info->n_launches_bwd = count(p->sched_fbwd);
+    }
+    info->n_segments = (int32_t)p->segs.size();
+    for (const auto &sp : p->segs) info->n_fused_nodes += (int32_t)sp.ops.size();
   });
 }
 
@@ -1091,7 +1480,11 @@ void run_ops(tn_plan_t *p, const std::vector<Op> &ops) {
 
 void run_sched(tn_plan_t *p, const std::vector<Op> &ops, const Schedule &sc) {
   for (const Launch &L : sc.launches) {
-    if (L.ops.size() == 1) {
+    if (L.seg) {
+      const Op &op = ops[L.ops[0]];
+      if (op.seg_kind == 1) launch_seg_fwd(p->seg_fwd_h[op.seg], p->d_seg_fwd + op.seg, p->stream);
+      else launch_seg_bwd(p->seg_bwd_h[op.seg], p->d_seg_bwd + op.seg, p->stream);
+    } else if (L.ops.size() == 1) {
       const Op &op = ops[L.ops[0]];
       launch_contract(op.semi, op.Y >= 0, op.split, op.a, op.d_a, op.nb, p->stream);
     } else if (!L.split) {
@@ -1173,14 +1566,19 @@ static void check_batch(tn_plan_t *p, int batch) {
   if (p->mode == TN_EVIDENCE_NONE && batch != 1) throw TnError(TN_E_INVALID, "mode NONE takes batch 1");
 }
 
-static void forward_sum(tn_plan_t *p, bool with_bwd) {
-  run_graph(p, with_bwd ? "sum+bwd" : "sum", [&] {
+// Sum-product forward (and reverse pass).  Fused chain segments skip the
+// intermediate carriers; sampling reads every node, so it runs unfused.
+static void forward_sum(tn_plan_t *p, bool with_bwd, bool allow_fused = true) {
+  const bool fz = p->fused && allow_fused;
+  run_graph(p, std::string(with_bwd ? "sum+bwd" : "sum") + (fz ? "" : "-unfused"), [&] {
     launch_prepare_set(p, p->leaves_sum, p->d_leaves_sum, true);
-    run_sched(p, p->sum_tree.ops, p->sched_fwd);
+    if (fz) run_sched(p, p->ffwd, p->sched_ffwd);
+    else run_sched(p, p->sum_tree.ops, p->sched_fwd);
     const TensorBuf &r = p->T[p->sum_tree.root];
     launch_logz(p->arena + r.off, r.batched ? r.size : 0, p->ex, r.slot, r.batched, p->max_batch, p->d_out, p->stream);
     if (with_bwd) {
-      run_sched(p, p->bwd, p->sched_bwd);
+      if (fz) run_sched(p, p->fbwd, p->sched_fbwd);
+      else run_sched(p, p->bwd, p->sched_bwd);
       launch_marg(p->arena, p->d_marg_desc, (int)p->marg.size(), p->max_batch, p->marg_row, p->d_marg, p->stream);
     }
   });
@@ -1274,7 +1672,7 @@ extern "C" tn_status tn_sample(tn_plan_t *p, const int32_t *evidence, int64_t n,
     if (!p->want_sum || p->is_mmap || p->mode == TN_EVIDENCE_INDICATOR)
       throw TnError(TN_E_UNSUPPORTED, "sampling needs a sum-product plan without batched evidence");
     upload_evidence(p, 1, evidence);
-    forward_sum(p, false);
+    forward_sum(p, false, false);
     std::vector<double> lz(1);
     hip_check(hipMemcpyAsync(lz.data(), p->d_out, sizeof(double), hipMemcpyDeviceToHost, p->stream), "D2H");
     hip_check(hipStreamSynchronize(p->stream), "sample forward");

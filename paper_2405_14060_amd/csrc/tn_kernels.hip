@@ -71,15 +71,16 @@ __device__ __forceinline__ uint32_t read_max(const uint32_t *mx, int stride, int
 // Record the block's maximum in *slot.  One candidate per block; the atomic
 // is skipped when the stored value is already larger (maxima only grow
 // within a launch, so a stale read only costs an unneeded atomic).
+template <int NT = kBlock>
 __device__ __forceinline__ void block_record_max(float v, uint32_t *slot) {
-  __shared__ float red[kBlock / 64];
+  __shared__ float red[NT / 64];
   v = wave_max(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
     float m = red[0];
 #pragma unroll
-    for (int w = 1; w < kBlock / 64; ++w) m = fmaxf(m, red[w]);
+    for (int w = 1; w < NT / 64; ++w) m = fmaxf(m, red[w]);
     if (m > 0.f && __uint_as_float(*(volatile uint32_t *)slot) < m) atomicMax(slot, __float_as_uint(m));
   }
 }
@@ -109,36 +110,39 @@ __device__ __forceinline__ void map_body(const ContractArgs &a, const int b, con
       sy = ldexpf(1.f, -ky);
     }
   }
-  const uint32_t n_out = a.nR * a.nC;
-  const uint32_t nSh = a.nS / a.nSl;
+  const uint32_t nR = a.nR, nC = a.nC, nRl = a.nRl, nCl = a.nCl, nSl = a.nSl;
+  const uint32_t n_out = nR * nC;
+  const uint32_t nSh = a.nS / nSl;
+  const bool colf = a.col_fastest != 0;
+  const Tab2 rX = a.rX, rY = a.rY, rZ = a.rZ, cY = a.cY, cZ = a.cZ, sXt = a.sX, sYt = a.sY;
   float lmax = 0.f;
   for (uint32_t o = blk * kBlock + threadIdx.x; o < n_out; o += nblk * kBlock) {
     uint32_t r, c;
-    if (a.col_fastest) {
-      r = o / a.nC;
-      c = o - r * a.nC;
+    if (colf) {
+      r = o / nC;
+      c = o - r * nC;
     } else {
-      c = o / a.nR;
-      r = o - c * a.nR;
+      c = o / nR;
+      r = o - c * nR;
     }
-    const uint32_t rh = r / a.nRl, rl = r - rh * a.nRl;
-    const int32_t xo = a.rX.hi[rh] + a.rX.lo[rl];
-    int32_t zo = a.rZ.hi[rh] + a.rZ.lo[rl];
-    int32_t yo = HASY ? a.rY.hi[rh] + a.rY.lo[rl] : 0;
-    if (a.nC > 1) {
-      const uint32_t ch = c / a.nCl, cl = c - ch * a.nCl;
-      zo += a.cZ.hi[ch] + a.cZ.lo[cl];
-      if (HASY) yo += a.cY.hi[ch] + a.cY.lo[cl];
+    const uint32_t rh = r / nRl, rl = r - rh * nRl;
+    const int32_t xo = rX.hi[rh] + rX.lo[rl];
+    int32_t zo = rZ.hi[rh] + rZ.lo[rl];
+    int32_t yo = HASY ? rY.hi[rh] + rY.lo[rl] : 0;
+    if (nC > 1) {
+      const uint32_t ch = c / nCl, cl = c - ch * nCl;
+      zo += cZ.hi[ch] + cZ.lo[cl];
+      if (HASY) yo += cY.hi[ch] + cY.lo[cl];
     }
     if (SEMI == SEMI_SUM) {
       float acc = 0.f;
       for (uint32_t sh = 0; sh < nSh; ++sh) {
-        const int32_t xs = xo + a.sX.hi[sh];
-        const int32_t ys = HASY ? yo + a.sY.hi[sh] : 0;
-        for (uint32_t sl = 0; sl < a.nSl; ++sl) {
-          const float xv = X[xs + a.sX.lo[sl]] * sx;
+        const int32_t xs = xo + sXt.hi[sh];
+        const int32_t ys = HASY ? yo + sYt.hi[sh] : 0;
+        for (uint32_t sl = 0; sl < nSl; ++sl) {
+          const float xv = X[xs + sXt.lo[sl]] * sx;
           if (HASY)
-            acc = fmaf(xv, Y[ys + a.sY.lo[sl]] * sy, acc);
+            acc = fmaf(xv, Y[ys + sYt.lo[sl]] * sy, acc);
           else
             acc += xv;
         }
@@ -150,11 +154,11 @@ __device__ __forceinline__ void map_body(const ContractArgs &a, const int b, con
       int32_t bi = 0;
       uint32_t s = 0;
       for (uint32_t sh = 0; sh < nSh; ++sh) {
-        const int32_t xs = xo + a.sX.hi[sh];
-        const int32_t ys = HASY ? yo + a.sY.hi[sh] : 0;
-        for (uint32_t sl = 0; sl < a.nSl; ++sl, ++s) {
-          float v = X[xs + a.sX.lo[sl]];
-          if (HASY) v = v + Y[ys + a.sY.lo[sl]];
+        const int32_t xs = xo + sXt.hi[sh];
+        const int32_t ys = HASY ? yo + sYt.hi[sh] : 0;
+        for (uint32_t sl = 0; sl < nSl; ++sl, ++s) {
+          float v = X[xs + sXt.lo[sl]];
+          if (HASY) v = v + Y[ys + sYt.lo[sl]];
           if (s == 0 || v > best) {
             best = v;
             bi = (int32_t)s;
@@ -388,48 +392,63 @@ __device__ __forceinline__ void finish_body(const ContractArgs &a, const int b, 
 template <int SEMI, bool HASY, int B>
 __device__ __forceinline__ void rows_body(const ContractArgs &a, const int b, const uint32_t blk,
                                           const uint32_t nblk) {
+  // every argument is copied to registers before the loop: the arguments
+  // live in device memory and stores to Z would otherwise force reloads
   const float *__restrict__ X = a.X + (int64_t)b * a.bsX;
   const float *__restrict__ Y = HASY ? a.Y + (int64_t)b * a.bsY : nullptr;
   float *__restrict__ Z = a.Z + (int64_t)b * a.bsZ;
   int32_t *__restrict__ I = SEMI == SEMI_MAX ? a.I + (int64_t)b * a.bsZ : nullptr;
-  float sx = 1.f, sy = 1.f;
+  const int32_t *__restrict__ rXh = a.rX.hi, *__restrict__ rXl = a.rX.lo;
+  const int32_t *__restrict__ rZh = a.rZ.hi, *__restrict__ rZl = a.rZ.lo;
+  const int32_t *__restrict__ rYh = a.rY.hi, *__restrict__ rYl = a.rY.lo;
+  const uint32_t nR = a.nR, nRl = a.nRl;
+  const int rls = a.rl_shift;
+  const int ns = a.ns, nc = a.nc;
+  int32_t sx[B], sy[B], cy[B], cz[B];
+#pragma unroll
+  for (int k = 0; k < B; ++k) {
+    sx[k] = k < ns ? a.sx[k] : 0;
+    sy[k] = k < ns ? a.sy[k] : 0;
+    cy[k] = k < nc ? a.cy[k] : 0;
+    cz[k] = k < nc ? a.cz[k] : 0;
+  }
+  float fx = 1.f, fy = 1.f;
   int kx = 0, ky = 0;
   if (SEMI == SEMI_SUM) {
     kx = max_exponent(read_max(a.mx, a.mx_stride, a.slotX + (a.batX ? b : 0)));
-    sx = ldexpf(1.f, -kx);
+    fx = ldexpf(1.f, -kx);
     if (HASY) {
       ky = max_exponent(read_max(a.mx, a.mx_stride, a.slotY + (a.batY ? b : 0)));
-      sy = ldexpf(1.f, -ky);
+      fy = ldexpf(1.f, -ky);
     }
   }
-  const int ns = a.ns, nc = a.nc;
   float lmax = 0.f;
-  for (uint32_t r = blk * kBlock + threadIdx.x; r < a.nR; r += nblk * kBlock) {
+  for (uint32_t r = blk * kBlock + threadIdx.x; r < nR; r += nblk * kBlock) {
     uint32_t rh, rl;
-    if (a.rl_shift >= 0) {
-      rh = r >> a.rl_shift;
-      rl = r & (a.nRl - 1);
+    if (rls >= 0) {
+      rh = r >> rls;
+      rl = r & (nRl - 1);
     } else {
-      rh = r / a.nRl;
-      rl = r - rh * a.nRl;
+      rh = r / nRl;
+      rl = r - rh * nRl;
     }
-    const int32_t xo = a.rX.hi[rh] + a.rX.lo[rl];
-    const int32_t zo = a.rZ.hi[rh] + a.rZ.lo[rl];
-    const int32_t yo = HASY ? a.rY.hi[rh] + a.rY.lo[rl] : 0;
+    const int32_t xo = rXh[rh] + rXl[rl];
+    const int32_t zo = rZh[rh] + rZl[rl];
+    const int32_t yo = HASY ? rYh[rh] + rYl[rl] : 0;
     float xv[B];
 #pragma unroll
     for (int k = 0; k < B; ++k)
-      if (k < ns) xv[k] = SEMI == SEMI_SUM ? X[xo + a.sx[k]] * sx : X[xo + a.sx[k]];
+      if (k < ns) xv[k] = SEMI == SEMI_SUM ? X[xo + sx[k]] * fx : X[xo + sx[k]];
 #pragma unroll
     for (int c = 0; c < B; ++c) {
       if (c >= nc) continue;
-      const int32_t yc = yo + a.cy[c];
+      const int32_t yc = yo + cy[c];
       if (SEMI == SEMI_SUM) {
         float acc = 0.f;
 #pragma unroll
         for (int k = 0; k < B; ++k)
-          if (k < ns) acc = HASY ? fmaf(xv[k], Y[yc + a.sy[k]] * sy, acc) : acc + xv[k];
-        Z[zo + a.cz[c]] = acc;
+          if (k < ns) acc = HASY ? fmaf(xv[k], Y[yc + sy[k]] * fy, acc) : acc + xv[k];
+        Z[zo + cz[c]] = acc;
         lmax = fmaxf(lmax, acc);
       } else {
         float best = -INFINITY;
@@ -438,14 +457,14 @@ __device__ __forceinline__ void rows_body(const ContractArgs &a, const int b, co
         for (int k = 0; k < B; ++k)
           if (k < ns) {
             float v = xv[k];
-            if (HASY) v = v + Y[yc + a.sy[k]];
+            if (HASY) v = v + Y[yc + sy[k]];
             if (k == 0 || v > best) {
               best = v;
               bi = k;
             }
           }
-        Z[zo + a.cz[c]] = best;
-        I[zo + a.cz[c]] = bi;
+        Z[zo + cz[c]] = best;
+        I[zo + cz[c]] = bi;
       }
     }
   }
@@ -577,6 +596,233 @@ void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, co
       k_split_finish<SEMI_MAX, false><<<gf, kBlock, 0, s>>>(d_a);
     }
   }
+}
+
+
+// --------------------------------------------------------------------------
+// fused chain segments
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int32_t outer_off(const Tab2 &t, uint32_t o, uint32_t nlo) {
+  const uint32_t h = o / nlo;
+  return t.hi[h] + t.lo[o - h * nlo];
+}
+
+static constexpr int kSegBlock = 256;
+static constexpr int kSegOB = 32;       // outer assignments per block (one 128-byte line of floats)
+static constexpr int kSegOBP = kSegOB + 1;  // padded tile row (no LDS bank conflicts in either mapping)
+
+// LDS (floats) of a segment launch: index lists, per-triple coefficients,
+// then the tiles (entry-major rows of kSegOBP).
+size_t seg_fwd_lds(const SegArgs &a) {
+  return ((size_t)a.list_len + 64 * a.n_steps + 2 * (size_t)a.te * kSegOBP) * sizeof(float);
+}
+size_t seg_bwd_lds(const SegArgs &a) {
+  return ((size_t)a.list_len + 64 * a.n_steps + (size_t)(a.n_steps + 2) * a.te * kSegOBP + a.n_sb) *
+         sizeof(float);
+}
+// one slab of kSegOB outer assignments per block
+static unsigned seg_blocks(const SegArgs &a) { return (a.nO + kSegOB - 1) / kSegOB; }
+unsigned seg_grid(const SegArgs &a) { return seg_blocks(a); }
+
+// Stage the segment's constants in LDS in one phase: the index lists and
+// the small operands' raw values.  Inside a segment the small operands are
+// used unscaled (their exponents add to the output's); only the carrier is
+// renormalised.  Returns the sum of the small operands' exponents.
+__device__ __forceinline__ int seg_stage(const SegArgs &a, int32_t *li, float *yv) {
+  for (int e = threadIdx.x; e < a.list_len; e += kSegBlock) li[e] = a.lists[e];
+  int ey = 0;
+  for (int i = 0; i < a.n_steps; ++i) {
+    const SegStep &st = a.steps[i];
+    ey += a.ex[st.yslot];
+    for (int e = threadIdx.x; e < st.ny; e += kSegBlock) yv[i * 64 + e] = a.arena[st.y + e];
+  }
+  __syncthreads();
+  return ey;
+}
+
+__device__ __forceinline__ int32_t seg_outer(const SegArgs &a, const Tab2 &ot, uint32_t og) {
+  if (a.ol_shift >= 0) return ot.hi[og >> a.ol_shift] + ot.lo[og & (a.nOl - 1)];
+  return outer_off(ot, og, a.nOl);
+}
+
+// Move a slab (n entries x kSegOB outer assignments) between a carrier in
+// global memory and an LDS tile.  The thread mapping puts consecutive
+// threads on consecutive addresses of the carrier: outer-fastest when the
+// carrier's stride-1 label is an outer label, entry-fastest otherwise.
+template <bool LOAD>
+__device__ __forceinline__ float seg_slab(const SegArgs &a, const float *src, float *dst, const Tab2 &ot,
+                                          const int32_t *loc, int n, bool outer_fast, uint32_t o0, float *tile,
+                                          float scale) {
+  float lmax = 0.f;
+  const int tasks = n * kSegOB;
+  for (int t = threadIdx.x; t < tasks; t += kSegBlock) {
+    int j, o;
+    if (outer_fast) {
+      j = t / kSegOB;
+      o = t - j * kSegOB;
+    } else {
+      o = t / n;
+      j = t - o * n;
+    }
+    const uint32_t og = o0 + o;
+    if (LOAD) {
+      tile[j * kSegOBP + o] = og < a.nO ? src[seg_outer(a, ot, og) + loc[j]] * scale : 0.f;
+    } else if (og < a.nO) {
+      const float v = tile[j * kSegOBP + o];
+      dst[seg_outer(a, ot, og) + loc[j]] = v;
+      lmax = fmaxf(lmax, v);
+    }
+  }
+  return lmax;
+}
+
+// One step on the tiles: out[j][o] = sum over the triples of entry j of
+// in[i][o] * coef.  All threads share the (entry, outer) tasks.
+__device__ __forceinline__ void seg_apply(const int32_t *pp, const int32_t *ix, const int32_t *sx, const float *yv,
+                                          int n_out, const float *tin, float *tout) {
+  const int tasks = n_out * kSegOB;
+  for (int t = threadIdx.x; t < tasks; t += kSegBlock) {
+    const int j = t / kSegOB, o = t - j * kSegOB;
+    float acc = 0.f;
+    for (int e = pp[j]; e < pp[j + 1]; ++e) acc = fmaf(tin[ix[e] * kSegOBP + o], yv[sx[e]], acc);
+    tout[j * kSegOBP + o] = acc;
+  }
+}
+
+// Forward: input carrier slab -> steps -> output carrier slab, one slab of
+// kSegOB outer assignments per block.
+__global__ __launch_bounds__(kSegBlock) void k_seg_fwd(const SegArgs *__restrict__ ap) {
+  const SegArgs &a = *ap;
+  extern __shared__ float lds[];
+  int32_t *li = (int32_t *)lds;
+  float *yv = lds + a.list_len;
+  float *t0 = yv + 64 * a.n_steps;
+  float *t1 = t0 + (size_t)a.te * kSegOBP;
+  const int kx = max_exponent(read_max(a.mx, a.mx_stride, a.slotX));
+  const uint32_t o0 = blockIdx.x * kSegOB;
+  seg_slab<true>(a, a.arena + a.X, nullptr, a.oX, a.inX, a.n_in0, a.in_outer_fast, o0, t0, ldexpf(1.f, -kx));
+  const int esum = a.ex[a.slotX] + kx + seg_stage(a, li, yv);
+  for (int i = 0; i < a.n_steps; ++i) {
+    const SegStep &st = a.steps[i];
+    seg_apply(li + st.fo_ptr, li + st.fo_in, li + st.fo_s, yv + i * 64, st.n_out, t0, t1);
+    __syncthreads();
+    float *tmp = t0;
+    t0 = t1;
+    t1 = tmp;
+  }
+  const float lmax =
+      seg_slab<false>(a, nullptr, a.arena + a.Z, a.oZ, a.outZ, a.n_outL, a.out_outer_fast, o0, t0, 1.f);
+  block_record_max<kSegBlock>(lmax, a.mx + (blockIdx.x % kMaxSub) * a.mx_stride + a.slotZ);
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.ex[a.slotZ] = esum;
+}
+
+// Reverse pass of a segment: recompute the carrier tiles of the slab from
+// the input carrier, then run the steps backwards (eq. einback per step).
+// The adjoint tile flows to the input carrier's adjoint (triples grouped by
+// input entry); every small operand's adjoint entry is a sum over its
+// triples (grouped by small entry) and over the slab, written per block to
+// `part` and summed in a fixed order by k_seg_bwd_finish.
+__global__ __launch_bounds__(kSegBlock) void k_seg_bwd(const SegArgs *__restrict__ ap) {
+  const SegArgs &a = *ap;
+  extern __shared__ float lds[];
+  const int te = a.te, L = a.n_steps;
+  int32_t *li = (int32_t *)lds;
+  float *yv = lds + a.list_len;
+  float *T = yv + 64 * L;                            // L tiles: input tile of every step
+  float *g0 = T + (size_t)L * te * kSegOBP;
+  float *g1 = g0 + (size_t)te * kSegOBP;
+  float *sbw = g1 + (size_t)te * kSegOBP;            // n_sb block totals
+  const int kx = max_exponent(read_max(a.mx, a.mx_stride, a.slotX));
+  const int kg = max_exponent(read_max(a.mx, a.mx_stride, a.slotG));
+  const uint32_t o0 = blockIdx.x * kSegOB;
+  seg_slab<true>(a, a.arena + a.X, nullptr, a.oX, a.inX, a.n_in0, a.in_outer_fast, o0, T, ldexpf(1.f, -kx));
+  seg_slab<true>(a, a.arena + a.G, nullptr, a.oZ, a.outZ, a.n_outL, a.out_outer_fast, o0, g0, ldexpf(1.f, -kg));
+  for (int k = threadIdx.x; k < a.n_sb; k += kSegBlock) sbw[k] = 0.f;
+  const int ey = seg_stage(a, li, yv);
+  for (int i = 0; i + 1 < L; ++i) {
+    const SegStep &st = a.steps[i];
+    seg_apply(li + st.fo_ptr, li + st.fo_in, li + st.fo_s, yv + i * 64, st.n_out, T + (size_t)i * te * kSegOBP,
+              T + (size_t)(i + 1) * te * kSegOBP);
+    __syncthreads();
+  }
+  for (int i = L - 1; i >= 0; --i) {
+    const SegStep &st = a.steps[i];
+    const float *tin = T + (size_t)i * te * kSegOBP;
+    if (st.sb_off >= 0) {
+      // (small entry, outer) tasks; the 32 outer assignments of one entry
+      // are 32 consecutive lanes, summed with shuffles
+      const int32_t *pp = li + st.bs_ptr, *xi = li + st.bs_in, *xo = li + st.bs_out;
+      const int tasks = st.ny * kSegOB;
+      for (int t0 = 0; t0 < tasks; t0 += kSegBlock) {
+        const int t = t0 + threadIdx.x;
+        float acc = 0.f;
+        int s2 = 0;
+        if (t < tasks) {
+          s2 = t / kSegOB;
+          const int o = t - s2 * kSegOB;
+          for (int e = pp[s2]; e < pp[s2 + 1]; ++e)
+            acc = fmaf(g0[xo[e] * kSegOBP + o], tin[xi[e] * kSegOBP + o], acc);
+        }
+#pragma unroll
+        for (int off = 16; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (t < tasks && (t & (kSegOB - 1)) == 0) sbw[st.sb_off + s2] += acc;
+      }
+    }
+    seg_apply(li + st.bi_ptr, li + st.bi_out, li + st.bi_s, yv + i * 64, st.n_in, g0, g1);
+    __syncthreads();
+    float *tmp = g0;
+    g0 = g1;
+    g1 = tmp;
+  }
+  const float lmax =
+      seg_slab<false>(a, nullptr, a.arena + a.Z, a.oX, a.inX, a.n_in0, a.in_outer_fast, o0, g0, 1.f);
+  block_record_max<kSegBlock>(lmax, a.mx + (blockIdx.x % kMaxSub) * a.mx_stride + a.slotZ);
+  for (int k = threadIdx.x; k < a.n_sb; k += kSegBlock) a.part[(size_t)blockIdx.x * a.n_sb + k] = sbw[k];
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.ex[a.slotZ] = a.ex[a.slotG] + kg + ey;
+}
+
+// Sum the per-block partials of every small-operand adjoint entry (fixed
+// order) and record maxima and exponents.
+__global__ __launch_bounds__(256) void k_seg_bwd_finish(const SegArgs *__restrict__ ap, int n_blocks) {
+  const SegArgs &a = *ap;
+  const int k = blockIdx.x;
+  float acc = 0.f;
+  for (int w = threadIdx.x; w < n_blocks; w += 256) acc += a.part[(size_t)w * a.n_sb + k];
+  __shared__ float red[4];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  const int kx = max_exponent(read_max(a.mx, a.mx_stride, a.slotX));
+  const int kg = max_exponent(read_max(a.mx, a.mx_stride, a.slotG));
+  int ey = 0, step = -1, sidx = 0, ei = 0;
+  for (int i = 0; i < a.n_steps; ++i) {
+    const SegStep &st = a.steps[i];
+    const int e = a.ex[st.yslot];
+    ey += e;
+    if (st.sb_off >= 0 && k >= st.sb_off && k < st.sb_off + st.ny) {
+      step = i;
+      sidx = k - st.sb_off;
+      ei = e;
+    }
+  }
+  if (threadIdx.x == 0 && step >= 0) {
+    const SegStep &st = a.steps[step];
+    const float t = red[0] + red[1] + red[2] + red[3];
+    a.arena[st.ybar + sidx] = t;
+    if (t > 0.f) atomicMax(a.mx + (sidx % kMaxSub) * a.mx_stride + st.ybar_slot, __float_as_uint(t));
+    if (sidx == 0) a.ex[st.ybar_slot] = (a.ex[a.slotG] + kg) + (a.ex[a.slotX] + kx) + (ey - ei);
+  }
+}
+
+void launch_seg_fwd(const SegArgs &a, const SegArgs *d_a, void *stream) {
+  const unsigned blocks = seg_blocks(a);
+  k_seg_fwd<<<blocks, kSegBlock, seg_fwd_lds(a), (hipStream_t)stream>>>(d_a);
+}
+
+void launch_seg_bwd(const SegArgs &a, const SegArgs *d_a, void *stream) {
+  const unsigned blocks = seg_blocks(a);
+  k_seg_bwd<<<blocks, kSegBlock, seg_bwd_lds(a), (hipStream_t)stream>>>(d_a);
+  if (a.n_sb > 0) k_seg_bwd_finish<<<a.n_sb, 256, 0, (hipStream_t)stream>>>(d_a, (int)blocks);
 }
 
 // --------------------------------------------------------------------------

@@ -42,6 +42,28 @@ struct Op {
   double flops = 0, bytes = 0;        // algorithmic, per instance
   int64_t part_off = -1;              // partial-sum region of a split contraction
   ContractArgs *d_a = nullptr;        // device copy of `a`
+  // fused chain segment (seg >= 0): 1 forward, 2 reverse; extra tensors
+  // read / written, for scheduling
+  int seg = -1, seg_kind = 0;
+  std::vector<int> ins, outs;
+};
+
+// Host description of a fused segment (tables as offsets into the plan's
+// int32 table store).
+struct SegPlan {
+  std::vector<int> ops;               // forward op indices, in order
+  int c0 = -1, cL = -1;               // input / output carrier tensors
+  int64_t oX[2], oZ[2], inX = 0, outZ = 0;
+  uint32_t nO = 1, nOl = 1;
+  int32_t n_in0 = 0, n_outL = 0, te = 32, n_sb = 0;
+  int64_t list_off = 0;               // the steps' CSR lists in the table store
+  int32_t list_len = 0, nnz_total = 0;
+  int32_t in_outer_fast = 0, out_outer_fast = 0;
+  std::vector<SegStep> steps;
+  std::vector<int> ybar_tensor;       // reverse: adjoint tensor of each small operand (-1)
+  int g = -1, c0bar = -1;             // reverse: adjoint tensors of C_L and C_0
+  int64_t part_off = 0;               // reverse: partial region
+  double bytes_fwd = 0, bytes_bwd = 0, flops = 0;
 };
 
 // One launch of a schedule: a single contraction, or several independent
@@ -49,6 +71,7 @@ struct Op {
 struct Launch {
   int semi = SEMI_SUM;
   bool split = false;
+  bool seg = false;                   // a fused segment (always alone)
   std::vector<int> ops;               // indices into the op list
   // grouped launches: device copies of the ops' arguments and block ranges
   ContractArgs *d_args = nullptr;
@@ -117,6 +140,13 @@ struct tn_plan_impl {
   tn::TreeExec sum_tree, max_tree;
   std::vector<tn::Op> bwd;
   tn::Schedule sched_fwd, sched_bwd, sched_max, sched_q;
+  // fused variants of the sum-product passes (log Z / marginals)
+  bool fused = false;
+  std::vector<tn::SegPlan> segs;
+  std::vector<tn::Op> ffwd, fbwd;
+  tn::Schedule sched_ffwd, sched_fbwd;
+  tn::SegArgs *d_seg_fwd = nullptr, *d_seg_bwd = nullptr;
+  std::vector<tn::SegArgs> seg_fwd_h, seg_bwd_h;
   std::vector<tn::Schedule> sched_groups;
   int seed_tensor = -1;                // adjoint of the root (ones)
   std::vector<int> adj_tensor;         // per node of sum_tree, -1 = none
