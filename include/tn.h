@@ -224,10 +224,15 @@ tn_status tn_logZ_dev(tn_plan_t *plan, const int32_t *evidence, const float *val
 
 /* Per-launch timing of one task (for roofline reports).  kind: 0/1 generic
  * contraction (sum / max), 2/3 split-reduction contraction (sum / max),
- * 4 leaf preparation, 5 other.  flops and bytes are algorithmic
- * (2 x output x summed elements; 4 bytes x (|X| + |Y| + |Z|) per instance,
- * times the instances of the launch).  ms is the launch's duration from
- * HIP events recorded around it on the plan's stream, averaged over reps. */
+ * 4 leaf preparation, 5 other, 6/7 fused chain segment (forward / reverse,
+ * the reverse including its partial-sum finish).  flops and bytes are
+ * algorithmic: 2 x output x summed elements; 4 bytes x (|X| + |Y| + |Z|)
+ * per instance times the instances of the launch; for a forward segment
+ * 4 bytes x (|input carrier| + |output carrier|), for a reverse segment
+ * 4 bytes x (2 |input carrier| + |output carrier|) (it reads the input
+ * carrier and the output's adjoint and writes the input's adjoint).  ms is
+ * the launch's duration from HIP events recorded around it on the plan's
+ * stream, averaged over reps. */
 typedef struct {
   int32_t kind;
   double flops, bytes, ms;
@@ -237,6 +242,14 @@ typedef struct {
  * without graph capture and fills out[0..min(cap, n)-1]; *n_ops = n. */
 tn_status tn_profile(tn_plan_t *plan, int32_t task, int32_t batch, const int32_t *evidence,
                      int32_t reps, tn_op_profile *out, int32_t cap, int32_t *n_ops);
+
+/* Average over the launches of one kind of one task, timed back to back
+ * (all launches of that kind in task order, reps times) between two HIP
+ * events on the plan's stream: avg->ms per launch, avg->flops and
+ * avg->bytes per launch; *n_launches = launches of that kind per task. */
+tn_status tn_profile_kind(tn_plan_t *plan, int32_t task, int32_t kind, int32_t batch,
+                          const int32_t *evidence, int32_t reps, tn_op_profile *avg,
+                          int32_t *n_launches);
 
 /* Synchronise the plan's stream; TN_E_DEVICE on error. */
 tn_status tn_sync(tn_plan_t *plan);

@@ -31,7 +31,7 @@ PLANNER_BEST, PLANNER_GREEDY, PLANNER_MINFILL, PLANNER_NATURAL, PLANNER_MINDEG =
 
 EXPORTS = ["tn_plan_opts_default", "tn_load_network", "tn_free_network", "tn_plan", "tn_free_plan",
            "tn_plan_info_get", "tn_plan_tree", "tn_plan_tree_host", "tn_logZ", "tn_marginals",
-           "tn_map", "tn_mmap", "tn_sample", "tn_logZ_dev", "tn_sync", "tn_profile", "tn_last_error"]
+           "tn_map", "tn_mmap", "tn_sample", "tn_logZ_dev", "tn_sync", "tn_profile", "tn_profile_kind", "tn_last_error"]
 
 i32p = ctypes.POINTER(ctypes.c_int32)
 i64p = ctypes.POINTER(ctypes.c_int64)
@@ -114,9 +114,11 @@ def lib():
     L.tn_sync.argtypes = [vp]
     L.tn_profile.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, i32p, ctypes.c_int32,
                              ctypes.POINTER(OpProfile), ctypes.c_int32, i32p]
+    L.tn_profile_kind.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, i32p, ctypes.c_int32,
+                                  ctypes.POINTER(OpProfile), i32p]
     for name in ("tn_load_network", "tn_plan", "tn_plan_info_get", "tn_plan_tree", "tn_plan_tree_host",
                  "tn_logZ", "tn_marginals", "tn_map", "tn_mmap", "tn_sample", "tn_logZ_dev", "tn_sync",
-                 "tn_profile"):
+                 "tn_profile", "tn_profile_kind"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -298,6 +300,16 @@ class Plan:
         n = ctypes.c_int32()
         _check(lib().tn_profile(self.h, task, batch, _ptr(ev, ctypes.c_int32), reps, buf, cap, ctypes.byref(n)))
         return [(buf[i].kind, buf[i].flops, buf[i].bytes, buf[i].ms) for i in range(min(n.value, cap))]
+
+    def profile_kind(self, task, kind, reps=5, evidence=None, batch=1):
+        """Launches of one kind timed back to back: (ms per launch, flops per
+        launch, bytes per launch, launches per task)."""
+        ev = self._ev(evidence, batch)
+        o = OpProfile()
+        n = ctypes.c_int32()
+        _check(lib().tn_profile_kind(self.h, task, kind, batch, _ptr(ev, ctypes.c_int32), reps,
+                                     ctypes.byref(o), ctypes.byref(n)))
+        return o.ms, o.flops, o.bytes, n.value
 
     def sync(self):
         _check(lib().tn_sync(self.h))

@@ -1948,8 +1948,8 @@ extern "C" tn_status tn_mmap(tn_plan_t *p, const int32_t *evidence, int32_t *ass
 // ---------------------------------------------------------------------------
 // per-launch profile (events around every launch of one task)
 // ---------------------------------------------------------------------------
-extern "C" tn_status tn_profile(tn_plan_t *p, int32_t task, int32_t batch, const int32_t *evidence, int32_t reps,
-                                tn_op_profile *out, int32_t cap, int32_t *n_ops) {
+static tn_status profile_impl(tn_plan_t *p, int32_t task, int32_t batch, const int32_t *evidence, int32_t reps,
+                              tn_op_profile *out, int32_t cap, int32_t *n_ops, int32_t kind_only) {
   return guard([&] {
     if (!p || reps < 1) throw TnError(TN_E_INVALID, "bad argument");
     if (p->is_mmap) throw TnError(TN_E_UNSUPPORTED, "profile of MMAP plans");
@@ -1964,24 +1964,41 @@ extern "C" tn_status tn_profile(tn_plan_t *p, int32_t task, int32_t batch, const
       std::function<void()> go;
     };
     std::vector<L> ls;
-    auto add_ops = [&](const std::vector<Op> &ops) {
-      for (const Op &op : ops) {
-        const int kind = (op.split ? 2 : 0) + (op.semi == SEMI_MAX ? 1 : 0);
-        double by = op.bytes + (op.semi == SEMI_MAX ? 4.0 * p->T[op.Z].size : 0.0);
-        ls.push_back({kind, op.flops * op.nb, by * op.nb,
-                      [p, &op] { launch_contract(op.semi, op.Y >= 0, op.split, op.a, op.d_a, op.nb, p->stream); }});
+    // one entry per launch of the schedule actually run by the task (grouped
+    // stages included), with the algorithmic work of the ops it covers
+    auto add_ops = [&](const std::vector<Op> &ops, const Schedule &sc) {
+      for (const Launch &L : sc.launches) {
+        double fl = 0, by = 0;
+        for (int i : L.ops) {
+          const Op &op = ops[i];
+          fl += op.seg >= 0 ? op.flops : op.flops * op.nb;
+          by += op.seg >= 0 ? op.bytes : (op.bytes + (op.semi == SEMI_MAX ? 4.0 * p->T[op.Z].size : 0.0)) * op.nb;
+        }
+        const Op &o0 = ops[L.ops[0]];
+        int kind;
+        if (L.seg) kind = o0.seg_kind == 1 ? 6 : 7;
+        else kind = (L.split ? 2 : 0) + (L.semi == SEMI_MAX ? 1 : 0);
+        const Launch *lp = &L;
+        const std::vector<Op> *opsp = &ops;
+        ls.push_back({kind, fl, by, [p, lp, opsp] {
+                        Schedule one;
+                        one.launches.push_back(*lp);
+                        run_sched(p, *opsp, one);
+                      }});
       }
     };
     if (task <= 1) {
       ls.push_back({4, 0, 0, [p] { launch_prepare_set(p, p->leaves_sum, p->d_leaves_sum, true); }});
-      add_ops(p->sum_tree.ops);
+      if (p->fused) add_ops(p->ffwd, p->sched_ffwd);
+      else add_ops(p->sum_tree.ops, p->sched_fwd);
       ls.push_back({5, 0, 0, [p] {
                       const TensorBuf &r = p->T[p->sum_tree.root];
                       launch_logz(p->arena + r.off, r.batched ? r.size : 0, p->ex, r.slot, r.batched, p->max_batch,
                                   p->d_out, p->stream);
                     }});
       if (task == 1) {
-        add_ops(p->bwd);
+        if (p->fused) add_ops(p->fbwd, p->sched_fbwd);
+        else add_ops(p->bwd, p->sched_bwd);
         ls.push_back({5, 0, 0, [p] {
                         launch_marg(p->arena, p->d_marg_desc, (int)p->marg.size(), p->max_batch, p->marg_row,
                                     p->d_marg, p->stream);
@@ -1989,11 +2006,45 @@ extern "C" tn_status tn_profile(tn_plan_t *p, int32_t task, int32_t batch, const
       }
     } else {
       ls.push_back({4, 0, 0, [p] { launch_prepare_set(p, p->leaves_max, p->d_leaves_max, false); }});
-      add_ops(p->max_tree.ops);
+      add_ops(p->max_tree.ops, p->sched_max);
       ls.push_back({5, 0, 0, [p] {
                       launch_backtrack(p->iarena, p->d_back, (int)p->max_tree.back.size(), p->d_back_meta, p->n_vars,
                                        p->max_batch, p->d_assign, p->stream);
                     }});
+    }
+    if (kind_only >= 0) {
+      // the launches of one kind back to back, bracketed by two events
+      std::vector<size_t> sel;
+      for (size_t i = 0; i < ls.size(); ++i)
+        if (ls[i].kind == kind_only) sel.push_back(i);
+      hipEvent_t e0, e1;
+      hip_check(hipEventCreate(&e0), "event");
+      hip_check(hipEventCreate(&e1), "event");
+      for (size_t i : sel) ls[i].go();  // warm
+      hip_check(hipEventRecord(e0, p->stream), "event");
+      for (int r = 0; r < reps; ++r)
+        for (size_t i : sel) ls[i].go();
+      hip_check(hipEventRecord(e1, p->stream), "event");
+      hip_check(hipEventSynchronize(e1), "event sync");
+      hip_check(hipGetLastError(), "profile launch");
+      float ms = 0;
+      hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      if (n_ops) *n_ops = (int32_t)sel.size();
+      if (cap > 0 && !sel.empty()) {
+        out[0].kind = kind_only;
+        out[0].flops = 0;
+        out[0].bytes = 0;
+        for (size_t i : sel) {
+          out[0].flops += ls[i].flops;
+          out[0].bytes += ls[i].bytes;
+        }
+        out[0].ms = ms / reps / (double)sel.size();
+        out[0].flops /= (double)sel.size();
+        out[0].bytes /= (double)sel.size();
+      }
+      return;
     }
     std::vector<hipEvent_t> ev(ls.size() + 1);
     for (auto &e : ev) hip_check(hipEventCreate(&e), "event");
@@ -2021,4 +2072,18 @@ extern "C" tn_status tn_profile(tn_plan_t *p, int32_t task, int32_t batch, const
       out[i].ms = acc[i] / reps;
     }
   });
+}
+
+extern "C" tn_status tn_profile(tn_plan_t *p, int32_t task, int32_t batch, const int32_t *evidence, int32_t reps,
+                                tn_op_profile *out, int32_t cap, int32_t *n_ops) {
+  return profile_impl(p, task, batch, evidence, reps, out, cap, n_ops, -1);
+}
+
+extern "C" tn_status tn_profile_kind(tn_plan_t *p, int32_t task, int32_t kind, int32_t batch, const int32_t *evidence,
+                                     int32_t reps, tn_op_profile *avg, int32_t *n_launches) {
+  if (kind < 0) {
+    g_err = "kind must be >= 0";
+    return TN_E_INVALID;
+  }
+  return profile_impl(p, task, batch, evidence, reps, avg, 1, n_launches, kind);
 }
