@@ -24,11 +24,13 @@ sys.path.insert(0, ROOT)
 METRIC = "TN-contraction TFLOP/s; logZ+marginal solves/s vs FP64 path at err<=1e-5"
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
+KIND_NAMES = {0: "contract_map_sum", 1: "contract_map_max", 2: "contract_split_sum",
+              3: "contract_split_max", 4: "prepare", 5: "other", 6: "seg_carrier_fwd",
+              7: "seg_carrier_bwd", 8: "seg_maps", 9: "seg_adjoint_sweeps"}
 
 
 def kernel_summary(prof):
-    names = {0: "contract_map_sum", 1: "contract_map_max", 2: "contract_split_sum",
-             3: "contract_split_max", 4: "prepare", 5: "other", 6: "seg_fwd", 7: "seg_bwd"}
+    names = KIND_NAMES
     agg = {}
     for kind, fl, by, ms in prof:
         a = agg.setdefault(names[kind], dict(n=0, flops=0.0, bytes=0.0, ms=0.0))
@@ -96,9 +98,7 @@ def main():
     agg = kernel_summary(prof)
     flops_solve = sum(fl for _, fl, _, _ in prof)
     dom_name, dom = max(agg.items(), key=lambda kv: kv[1]["ms"])
-    kind_of = {v: k for k, v in {0: "contract_map_sum", 1: "contract_map_max", 2: "contract_split_sum",
-                                  3: "contract_split_max", 4: "prepare", 5: "other", 6: "seg_fwd",
-                                  7: "seg_bwd"}.items()}
+    kind_of = {v: k for k, v in KIND_NAMES.items()}
     # the dominant kernel's launches timed back to back between two events
     avg_ms, fl_launch, by_launch, n_launch = plan.profile_kind(1, kind_of[dom_name], reps=5)
     achieved_gbs = by_launch / (avg_ms * 1e-3) / 1e9

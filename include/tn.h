@@ -224,15 +224,17 @@ tn_status tn_logZ_dev(tn_plan_t *plan, const int32_t *evidence, const float *val
 
 /* Per-launch timing of one task (for roofline reports).  kind: 0/1 generic
  * contraction (sum / max), 2/3 split-reduction contraction (sum / max),
- * 4 leaf preparation, 5 other, 6/7 fused chain segment (forward / reverse,
- * the reverse including its partial-sum finish).  flops and bytes are
- * algorithmic: 2 x output x summed elements; 4 bytes x (|X| + |Y| + |Z|)
- * per instance times the instances of the launch; for a forward segment
- * 4 bytes x (|input carrier| + |output carrier|), for a reverse segment
- * 4 bytes x (2 |input carrier| + |output carrier|) (it reads the input
- * carrier and the output's adjoint and writes the input's adjoint).  ms is
- * the launch's duration from HIP events recorded around it on the plan's
- * stream, averaged over reps. */
+ * 4 leaf preparation, 5 other, and the kernels of fused chain segments:
+ * 6 carrier forward (C_L = M C_0 over the outer labels), 7 carrier reverse
+ * (adjoint of C_0 and partial sums of Gbar C_0^T), 8 composed maps M of a
+ * stage's segments, 9 adjoint sweeps (small operands' adjoints) of a
+ * stage's segments.  flops and bytes are algorithmic: 2 x output x summed
+ * elements; 4 bytes x (|X| + |Y| + |Z|) per instance times the instances of
+ * the launch; for a carrier forward 4 bytes x (|input carrier| + |output
+ * carrier|), for a carrier reverse 4 bytes x (2 |input carrier| + |output
+ * carrier|) (it reads the input carrier and the output's adjoint and writes
+ * the input's adjoint).  ms is the launch's duration from HIP events
+ * recorded around it on the plan's stream, averaged over reps. */
 typedef struct {
   int32_t kind;
   double flops, bytes, ms;

@@ -166,6 +166,14 @@ static int new_tensor(tn_plan_t *p, const Labels &lab, bool batched, bool scaled
   p->T.push_back(t);
   return (int)p->T.size() - 1;
 }
+// a tensor without labels (per-solve scratch of fused segments)
+static int new_raw_tensor(tn_plan_t *p, int64_t size, bool scaled) {
+  TensorBuf t;
+  t.size = size;
+  t.slot = scaled ? 0 : -1;
+  p->T.push_back(t);
+  return (int)p->T.size() - 1;
+}
 static int new_intbuf(tn_plan_t *p, int64_t size, bool batched) {
   IntBuf b;
   b.size = size;
@@ -600,12 +608,21 @@ static Schedule build_schedule(tn_plan_t *p, const std::vector<Op> &ops, bool al
   }
   sc.n_stages = smax + 1;
   // launches: per stage, map ops of each semiring together, split ops
-  // together, fused segments alone
+  // together, segment sweeps of one kind together, carrier transforms alone
   for (int st = 0; st <= smax; ++st) {
+    for (int kind = 3; kind <= 4; ++kind) {  // composed maps / adjoint sweeps of a stage together
+      Launch L;
+      L.seg = true;
+      L.seg_kind = kind;
+      for (int i = 0; i < n; ++i)
+        if (stage[i] == st && ops[i].seg >= 0 && ops[i].seg_kind == kind) L.ops.push_back(i);
+      if (!L.ops.empty()) sc.launches.push_back(std::move(L));
+    }
     for (int i = 0; i < n; ++i)
-      if (stage[i] == st && ops[i].seg >= 0) {
+      if (stage[i] == st && ops[i].seg >= 0 && ops[i].seg_kind <= 2) {
         Launch L;
         L.seg = true;
+        L.seg_kind = ops[i].seg_kind;
         L.ops.push_back(i);
         sc.launches.push_back(std::move(L));
       }
@@ -626,6 +643,16 @@ static Schedule build_schedule(tn_plan_t *p, const std::vector<Op> &ops, bool al
 
 static void upload_schedule(tn_plan_t *p, Schedule &sc, const std::vector<Op> &ops) {
   for (Launch &L : sc.launches) {
+    if (L.seg && L.seg_kind >= 3) {
+      std::vector<int32_t> ids;
+      L.lds = 0;
+      for (int i : L.ops) {
+        ids.push_back(ops[i].seg);
+        L.lds = std::max(L.lds, L.seg_kind == 3 ? 2 * 1024 : p->segs[ops[i].seg].sweep_lds);
+      }
+      L.d_ids = dalloc_vec(p, ids);
+      continue;
+    }
     if (L.seg || L.ops.size() < 2) continue;
     std::vector<ContractArgs> args;
     std::vector<uint32_t> st, nb, st2, nb2;
@@ -894,36 +921,23 @@ static bool describe_segment(tn_plan_t *p, const std::vector<Op> &ops, const std
   if (minus(O, V[L]).size()) return false;  // outer labels must survive
   std::vector<Labels> Loc(L + 1);
   for (int j = 0; j <= L; ++j) Loc[j] = inter(V[j], T);
-  const int te = 32;
   for (int j = 0; j <= L; ++j)
-    if (numel(Loc[j], card) > te) return false;
-  int64_t n_sb = 0;
-  for (int j = 0; j < L; ++j) {
-    const Labels W = unite(Loc[j], U[j]);
-    if (numel(W, card) > 128) return false;
-    n_sb += numel(U[j], card);
-  }
+    if (numel(Loc[j], card) > kSegMaxLocal) return false;
+  for (int j = 0; j < L; ++j)
+    if (numel(unite(Loc[j], U[j]), card) > 1024) return false;  // triples of a step
   const int64_t nO = numel(O, card);
-  if (nO < 256 || n_sb > 64) return false;
-  // LDS: lists (about 6 entries per triple plus pointers), coefficients and
-  // tiles; the reverse pass holds L + 2 tiles for one wave
-  {
-    int64_t nnz = 0, ptrs = 0;
-    for (int j = 0; j < L; ++j) {
-      nnz += numel(unite(Loc[j], U[j]), card);
-      ptrs += numel(Loc[j], card) + numel(Loc[j + 1], card) + numel(U[j], card) + 3;
-    }
-    const int64_t lists = 6 * nnz + ptrs;
-    // slabs of 32 outer assignments, rows padded to 33
-    if ((lists + 64 * L + 2 * nnz + (int64_t)(L + 2) * te * 33 + n_sb) * 4 > 64 * 1024) return false;
-    if ((lists + 64 * L + nnz + 2 * te * 33) * 4 > 64 * 1024) return false;
-  }
+  if (nO < 256) return false;
+  // LDS of the adjoint sweep: three 32 x 32 work areas and P_0 .. P_{L-1}
+  const int64_t n_in0 = numel(Loc[0], card);
+  int64_t lds = 3 * 1024;
+  for (int j = 0; j < L; ++j) lds += numel(Loc[j], card) * n_in0;
+  if (lds > 15 * 1024) return false;
   if (!commit) return true;
   sp.ops = chain;
   sp.c0 = ops[chain[0]].X;
   sp.cL = ops[chain[L - 1]].Z;
-  sp.te = te;
   sp.nO = (uint32_t)nO;
+  sp.sweep_lds = (int32_t)lds;
   const size_t os = lo_split(O, card);
   sp.nOl = (uint32_t)numel(Labels(O.begin() + os, O.end()), card);
   add_tabs(p, O, os, V[0], sp.oX);
@@ -949,10 +963,8 @@ static bool describe_segment(tn_plan_t *p, const std::vector<Op> &ops, const std
   sp.outZ = local_tab(Loc[L], V[L]);
   sp.n_in0 = (int32_t)numel(Loc[0], card);
   sp.n_outL = (int32_t)numel(Loc[L], card);
-  sp.n_sb = 0;
   sp.steps.clear();
   std::vector<int32_t> blk;  // the segment's lists, offsets relative to its start
-  int32_t c_off = 0;
   std::vector<int> val(p->n_vars, 0);
   for (int j = 0; j < L; ++j) {
     SegStep st{};
@@ -975,8 +987,6 @@ static bool describe_segment(tn_plan_t *p, const std::vector<Op> &ops, const std
       }
     }
     st.nnz = (int32_t)tri.size();
-    st.c_off = c_off;
-    c_off += st.nnz;
     // CSR lists grouped by key (stable: enumeration order within a group,
     // so every sum runs in a fixed order)
     auto csr = [&](int key, int n, int a1, int a2, int32_t &ptr, int32_t &l1, int32_t &l2) {
@@ -1002,8 +1012,6 @@ static bool describe_segment(tn_plan_t *p, const std::vector<Op> &ops, const std
     sp.steps.push_back(st);
   }
   sp.list_off = (int64_t)p->tabs.size();
-  sp.list_len = (int32_t)blk.size();
-  sp.nnz_total = c_off;
   p->tabs.insert(p->tabs.end(), blk.begin(), blk.end());
   double b = 4.0 * (double)(p->T[sp.c0].size + p->T[sp.cL].size);
   sp.bytes_fwd = b;
@@ -1043,7 +1051,7 @@ static void build_fusion(tn_plan_t *p, std::vector<char> &need, int L_leaves) {
     while (cur >= 0) {
       std::vector<int> chain{cur};
       SegPlan probe;
-      while (next[chain.back()] >= 0 && chain.size() < 8) {
+      while (next[chain.back()] >= 0 && (int)chain.size() < kSegMaxSteps) {
         chain.push_back(next[chain.back()]);
         if (!describe_segment(p, ops, chain, probe, false)) {
           chain.pop_back();
@@ -1062,7 +1070,13 @@ static void build_fusion(tn_plan_t *p, std::vector<char> &need, int L_leaves) {
   }
   if (p->segs.empty()) return;
   p->fused = true;
-  // forward list: segment op at the position of its last node
+  // forward list: at the position of a segment's last node, the composed
+  // map (it reads the small operands only, so the schedule hoists it) and
+  // the carrier transform
+  for (size_t si = 0; si < p->segs.size(); ++si) {
+    SegPlan &sp = p->segs[si];
+    sp.mt = new_raw_tensor(p, (int64_t)sp.n_outL * sp.n_in0, true);
+  }
   for (int i = 0; i < n; ++i) {
     if (seg_of[i] < 0) {
       p->ffwd.push_back(ops[i]);
@@ -1070,12 +1084,20 @@ static void build_fusion(tn_plan_t *p, std::vector<char> &need, int L_leaves) {
     }
     SegPlan &sp = p->segs[seg_of[i]];
     if (i != sp.ops.back()) continue;
+    Op m;
+    m.seg = seg_of[i];
+    m.seg_kind = 3;
+    m.Z = sp.mt;
+    for (int j : sp.ops) m.ins.push_back(ops[j].Y);
+    for (int j : sp.ops) m.flops += 2.0 * p->T[ops[j].Y].size * sp.n_in0;
+    m.bytes = 4.0 * sp.n_outL * sp.n_in0;
+    p->ffwd.push_back(m);
     Op op;
     op.seg = seg_of[i];
     op.seg_kind = 1;
     op.X = sp.c0;
     op.Z = sp.cL;
-    for (int j : sp.ops) op.ins.push_back(ops[j].Y);
+    op.ins.push_back(sp.mt);
     op.flops = sp.flops;
     op.bytes = sp.bytes_fwd;
     p->ffwd.push_back(op);
@@ -1087,24 +1109,22 @@ static void build_fusion(tn_plan_t *p, std::vector<char> &need, int L_leaves) {
     SegPlan &sp = p->segs[si];
     sp.g = p->adj_tensor[node_of.at(sp.cL)];
     sp.c0bar = p->adj_tensor[node_of.at(sp.c0)];
-    int32_t sb = 0;
+    bool any = false;
     for (size_t j = 0; j < sp.ops.size(); ++j) {
       const Op &fo = ops[sp.ops[j]];
       const int ynode = node_of.at(fo.Y), xnode = node_of.at(fo.X);
       const int ybar = need[ynode] ? p->adj_tensor[ynode] : -1;
       sp.ybar_tensor.push_back(ybar);
-      SegStep &st = sp.steps[j];
       if (ybar >= 0) {
-        st.sb_off = sb;
-        sb += st.ny;
+        any = true;
         adj_to_seg[ybar] = (int)si;
       }
       if (p->adj_tensor[xnode] >= 0) adj_to_seg[p->adj_tensor[xnode]] = (int)si;
     }
-    sp.n_sb = sb;
-    const int64_t blocks = (sp.nO + 31) / 32;
-    sp.part_off = p->part_floats;
-    p->part_floats += (blocks * std::max(1, sb) + 63) / 64 * 64;
+    if (any) {
+      sp.n_part = (int32_t)((sp.nO + kSegOuterBlock - 1) / kSegOuterBlock);
+      sp.spt = new_raw_tensor(p, (int64_t)sp.n_part * sp.n_outL * sp.n_in0, true);
+    }
   }
   std::vector<char> emitted(p->segs.size(), 0);
   for (const Op &op : p->bwd) {
@@ -1123,13 +1143,26 @@ static void build_fusion(tn_plan_t *p, std::vector<char> &need, int L_leaves) {
     b.X = sp.g;
     b.Z = sp.c0bar;
     b.ins.push_back(sp.c0);
-    for (size_t j = 0; j < sp.ops.size(); ++j) {
-      b.ins.push_back(ops[sp.ops[j]].Y);
-      if (sp.ybar_tensor[j] >= 0) b.outs.push_back(sp.ybar_tensor[j]);
-    }
+    b.ins.push_back(sp.mt);
+    if (sp.spt >= 0) b.outs.push_back(sp.spt);
     b.flops = 2 * sp.flops;
     b.bytes = sp.bytes_bwd;
     p->fbwd.push_back(b);
+    if (sp.spt < 0) continue;
+    Op f;
+    f.seg = si;
+    f.seg_kind = 4;
+    f.X = sp.spt;
+    for (size_t j = 0; j < sp.ops.size(); ++j) {
+      f.ins.push_back(ops[sp.ops[j]].Y);
+      if (sp.ybar_tensor[j] >= 0) {
+        if (f.Z < 0) f.Z = sp.ybar_tensor[j];
+        f.outs.push_back(sp.ybar_tensor[j]);
+      }
+    }
+    f.bytes = 4.0 * (double)sp.n_part * sp.n_outL * sp.n_in0;
+    f.flops = 2.0 * (double)sp.n_part * sp.n_outL * sp.n_in0;
+    p->fbwd.push_back(f);
   }
   (void)L_leaves;
 }
@@ -1171,26 +1204,27 @@ static void upload_segments(tn_plan_t *p) {
       a.in_outer_fast = sp.in_outer_fast;
       a.out_outer_fast = sp.out_outer_fast;
       a.lists = p->d_tabs + sp.list_off;
-      a.list_len = sp.list_len;
-      a.nnz_total = sp.nnz_total;
-      a.te = sp.te;
       a.n_steps = (int32_t)sp.steps.size();
+      a.sweep_lds = sp.sweep_lds;
+      a.M = p->T[sp.mt].off;
+      a.slotM = p->T[sp.mt].slot;
+      a.X = p->T[sp.c0].off;
+      a.slotX = p->T[sp.c0].slot;
       std::vector<SegStep> st = sp.steps;
       if (!kind) {
-        for (auto &x : st) x.sb_off = -1;
-        a.X = p->T[sp.c0].off;
-        a.slotX = p->T[sp.c0].slot;
+        for (auto &x : st) x.ybar = -1;
         a.Z = p->T[sp.cL].off;
         a.slotZ = p->T[sp.cL].slot;
       } else {
-        a.X = p->T[sp.c0].off;
-        a.slotX = p->T[sp.c0].slot;
         a.G = p->T[sp.g].off;
         a.slotG = p->T[sp.g].slot;
         a.Z = p->T[sp.c0bar].off;
         a.slotZ = p->T[sp.c0bar].slot;
-        a.n_sb = sp.n_sb;
-        a.part = p->d_part + sp.part_off;
+        if (sp.spt >= 0) {
+          a.Sp = p->T[sp.spt].off;
+          a.slotSp = p->T[sp.spt].slot;
+          a.n_part = sp.n_part;
+        }
       }
       a.steps = dupload(p, st);
       H.push_back(a);
@@ -1482,8 +1516,12 @@ void run_sched(tn_plan_t *p, const std::vector<Op> &ops, const Schedule &sc) {
   for (const Launch &L : sc.launches) {
     if (L.seg) {
       const Op &op = ops[L.ops[0]];
-      if (op.seg_kind == 1) launch_seg_fwd(p->seg_fwd_h[op.seg], p->d_seg_fwd + op.seg, p->stream);
-      else launch_seg_bwd(p->seg_bwd_h[op.seg], p->d_seg_bwd + op.seg, p->stream);
+      switch (L.seg_kind) {
+        case 1: launch_seg_fwd(p->seg_fwd_h[op.seg], p->d_seg_fwd + op.seg, p->stream); break;
+        case 2: launch_seg_bwd(p->seg_bwd_h[op.seg], p->d_seg_bwd + op.seg, p->stream); break;
+        case 3: launch_seg_mat(p->d_seg_fwd, L.d_ids, (int)L.ops.size(), L.lds, p->stream); break;
+        default: launch_seg_fin(p->d_seg_bwd, L.d_ids, (int)L.ops.size(), L.lds, p->stream); break;
+      }
     } else if (L.ops.size() == 1) {
       const Op &op = ops[L.ops[0]];
       launch_contract(op.semi, op.Y >= 0, op.split, op.a, op.d_a, op.nb, p->stream);
@@ -1974,9 +2012,8 @@ static tn_status profile_impl(tn_plan_t *p, int32_t task, int32_t batch, const i
           fl += op.seg >= 0 ? op.flops : op.flops * op.nb;
           by += op.seg >= 0 ? op.bytes : (op.bytes + (op.semi == SEMI_MAX ? 4.0 * p->T[op.Z].size : 0.0)) * op.nb;
         }
-        const Op &o0 = ops[L.ops[0]];
         int kind;
-        if (L.seg) kind = o0.seg_kind == 1 ? 6 : 7;
+        if (L.seg) kind = 5 + L.seg_kind;  // 6 carrier forward, 7 carrier reverse, 8 composed maps, 9 adjoint sweeps
         else kind = (L.split ? 2 : 0) + (L.semi == SEMI_MAX ? 1 : 0);
         const Launch *lp = &L;
         const std::vector<Op> *opsp = &ops;

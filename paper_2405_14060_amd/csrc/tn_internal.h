@@ -120,29 +120,38 @@ void launch_group(int semi, int phase, const ContractArgs *ops, const uint32_t *
                   const uint32_t *nblk, int n, uint32_t total_blocks, void *stream);
 
 // Fused chain segment: consecutive tree nodes that each contract the
-// previous node's output (the carrier) with a small tensor.  Every lane owns
-// one assignment of the labels the segment never touches (outer labels) and
-// keeps its local tile (the touched labels) in LDS; each step applies the
-// node's contraction to the tile through a list of index triples
-// (in | out << 8 | s << 16): out-tile entry += in-tile entry * small[s].
+// previous node's output (the carrier) with a small tensor.  The labels the
+// chain touches (local labels) are few; on them the chain is a product of
+// small linear maps, one per step, and the labels it never touches (outer
+// labels) are carried along.  The composed map M (local entries of the
+// output carrier x local entries of the input carrier, at most 32 x 32) is
+// built once per solve from the small operands (k_seg_mat), and the carrier
+// is transformed by one batched matrix product per segment on the matrix
+// cores: C_L[:, o] = M C_0[:, o] for every outer assignment o.  The reverse
+// pass applies M^T to the output adjoint and accumulates
+// S = sum_o Gbar[:, o] C_0[:, o]^T, from which every small operand's adjoint
+// follows by sweeps over the steps (k_seg_fin, eq. einback per step).
+// A step's triples (in, out, s) say: out-entry += in-entry * small[s].
 struct SegStep {
   int64_t y = -1;         // float offset of the small operand
   int32_t yslot = -1;     // its scaling slot
   int32_t ny = 0;         // its elements
-  int32_t n_in = 0, n_out = 0;   // local tile sizes before / after the step
+  int32_t n_in = 0, n_out = 0;   // local entries before / after the step
   int32_t nnz = 0;        // index triples of the step
-  // the step's triples in three orders (int32 offsets into the table store):
+  // the step's triples in three orders (int32 offsets into the lists):
   // by output entry (CSR: ptr[n_out + 1], in[], s[]), by input entry
   // (ptr[n_in + 1], out[], s[]) and by small-operand entry (ptr[ny + 1],
   // in[], out[])
   int32_t fo_ptr = 0, fo_in = 0, fo_s = 0;
   int32_t bi_ptr = 0, bi_out = 0, bi_s = 0;
   int32_t bs_ptr = 0, bs_in = 0, bs_out = 0;
-  int32_t c_off = 0;      // offset of the step's triples in the staged coefficient lists
   int64_t ybar = -1;      // reverse pass: adjoint of the small operand (-1 = not needed)
   int32_t ybar_slot = -1;
-  int32_t sb_off = -1;    // reverse pass: first accumulator entry of this step
 };
+
+static constexpr int kSegMaxLocal = 32;   // local entries of a carrier in a segment
+static constexpr int kSegOuterBlock = 128; // outer assignments per workgroup (4 waves x 32)
+static constexpr int kSegMaxSteps = 16;    // steps of a segment
 
 struct SegArgs {
   float *arena = nullptr;
@@ -153,28 +162,30 @@ struct SegArgs {
                                  // reverse: G = adjoint of the output carrier,
                                  //          X = input carrier, Z = its adjoint
   int32_t slotX = -1, slotZ = -1, slotG = -1;
+  int64_t M = 0;                 // composed map, n_outL x n_in0 row-major (raw, max in [0.5, 1))
+  int32_t slotM = -1;            // its exponent slot
+  int64_t Sp = 0;                // reverse: per-workgroup partials of S (n_part x n_outL x n_in0)
+  int32_t slotSp = -1;           // exponent of S
+  int32_t n_part = 0;            // reverse: workgroups of the carrier kernel
   uint32_t nO = 1, nOl = 1;      // outer assignments; split of the outer tables
   int32_t ol_shift = -1;         // log2(nOl) when nOl is a power of two
   Tab2 oX, oZ;                   // outer offsets in the input / output carrier
-  const int32_t *inX = nullptr;  // local offsets of the input tile
-  const int32_t *outZ = nullptr; // local offsets of the output tile
+  const int32_t *inX = nullptr;  // local offsets of the input carrier
+  const int32_t *outZ = nullptr; // local offsets of the output carrier
   int32_t n_in0 = 0, n_outL = 0;
   const SegStep *steps = nullptr;
   int32_t n_steps = 0;
   const int32_t *lists = nullptr;  // the steps' CSR lists (offsets in SegStep are relative)
-  int32_t list_len = 0;            // int32 entries of the lists
-  int32_t nnz_total = 0;           // sum of the steps' triples
-  int32_t te = 32;               // tile capacity (local entries)
   int32_t in_outer_fast = 0;     // the input carrier's stride-1 label is an outer label
   int32_t out_outer_fast = 0;    // same for the output carrier
-  int32_t n_sb = 0;              // reverse: accumulator entries per lane
-  float *part = nullptr;         // reverse: per-wave sums of the accumulators
+  int32_t sweep_lds = 0;         // floats of LDS of the sweep kernels (k_seg_mat, k_seg_fin)
 };
 void launch_seg_fwd(const SegArgs &a, const SegArgs *d_a, void *stream);
 void launch_seg_bwd(const SegArgs &a, const SegArgs *d_a, void *stream);
-size_t seg_fwd_lds(const SegArgs &a);
-size_t seg_bwd_lds(const SegArgs &a);
-unsigned seg_grid(const SegArgs &a);  // blocks of a segment launch
+// one workgroup per listed segment; lds_floats = the largest sweep_lds of them
+void launch_seg_mat(const SegArgs *d_base, const int32_t *d_ids, int n, int lds_floats, void *stream);
+void launch_seg_fin(const SegArgs *d_base, const int32_t *d_ids, int n, int lds_floats, void *stream);
+unsigned seg_blocks(const SegArgs &a);  // workgroups of a carrier launch
 
 struct LeafDesc {
   int32_t kind;      // 0 factor gather, 1 constant one-vector, 2 indicator

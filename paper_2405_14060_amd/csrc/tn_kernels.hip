@@ -71,7 +71,9 @@ __device__ __forceinline__ uint32_t read_max(const uint32_t *mx, int stride, int
 // Record the block's maximum in *slot.  One candidate per block; the atomic
 // is skipped when the stored value is already larger (maxima only grow
 // within a launch, so a stale read only costs an unneeded atomic).
-template <int NT = kBlock>
+// GUARD = false skips the read (one memory round trip less at the end of a
+// launch) where few workgroups share a sub-slot.
+template <int NT = kBlock, bool GUARD = true>
 __device__ __forceinline__ void block_record_max(float v, uint32_t *slot) {
   __shared__ float red[NT / 64];
   v = wave_max(v);
@@ -81,7 +83,8 @@ __device__ __forceinline__ void block_record_max(float v, uint32_t *slot) {
     float m = red[0];
 #pragma unroll
     for (int w = 1; w < NT / 64; ++w) m = fmaxf(m, red[w]);
-    if (m > 0.f && __uint_as_float(*(volatile uint32_t *)slot) < m) atomicMax(slot, __float_as_uint(m));
+    if (m > 0.f && (!GUARD || __uint_as_float(*(volatile uint32_t *)slot) < m))
+      atomicMax(slot, __float_as_uint(m));
   }
 }
 
@@ -602,227 +605,432 @@ void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, co
 // --------------------------------------------------------------------------
 // fused chain segments
 // --------------------------------------------------------------------------
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+static constexpr int kSegThreads = 256;           // 4 waves
+static constexpr int kSegOB = kSegOuterBlock;     // outer assignments per workgroup (32 per wave)
+static constexpr int kSegRow = kSegOB + 1;        // padded LDS tile row: conflict-free in both directions
+
+unsigned seg_blocks(const SegArgs &a) { return (a.nO + kSegOB - 1) / kSegOB; }
+
 __device__ __forceinline__ int32_t outer_off(const Tab2 &t, uint32_t o, uint32_t nlo) {
   const uint32_t h = o / nlo;
   return t.hi[h] + t.lo[o - h * nlo];
 }
-
-static constexpr int kSegBlock = 256;
-static constexpr int kSegOB = 32;       // outer assignments per block (one 128-byte line of floats)
-static constexpr int kSegOBP = kSegOB + 1;  // padded tile row (no LDS bank conflicts in either mapping)
-
-// LDS (floats) of a segment launch: index lists, per-triple coefficients,
-// then the tiles (entry-major rows of kSegOBP).
-size_t seg_fwd_lds(const SegArgs &a) {
-  return ((size_t)a.list_len + 64 * a.n_steps + 2 * (size_t)a.te * kSegOBP) * sizeof(float);
-}
-size_t seg_bwd_lds(const SegArgs &a) {
-  return ((size_t)a.list_len + 64 * a.n_steps + (size_t)(a.n_steps + 2) * a.te * kSegOBP + a.n_sb) *
-         sizeof(float);
-}
-// one slab of kSegOB outer assignments per block
-static unsigned seg_blocks(const SegArgs &a) { return (a.nO + kSegOB - 1) / kSegOB; }
-unsigned seg_grid(const SegArgs &a) { return seg_blocks(a); }
-
-// Stage the segment's constants in LDS in one phase: the index lists and
-// the small operands' raw values.  Inside a segment the small operands are
-// used unscaled (their exponents add to the output's); only the carrier is
-// renormalised.  Returns the sum of the small operands' exponents.
-__device__ __forceinline__ int seg_stage(const SegArgs &a, int32_t *li, float *yv) {
-  for (int e = threadIdx.x; e < a.list_len; e += kSegBlock) li[e] = a.lists[e];
-  int ey = 0;
-  for (int i = 0; i < a.n_steps; ++i) {
-    const SegStep &st = a.steps[i];
-    ey += a.ex[st.yslot];
-    for (int e = threadIdx.x; e < st.ny; e += kSegBlock) yv[i * 64 + e] = a.arena[st.y + e];
-  }
-  __syncthreads();
-  return ey;
-}
-
 __device__ __forceinline__ int32_t seg_outer(const SegArgs &a, const Tab2 &ot, uint32_t og) {
   if (a.ol_shift >= 0) return ot.hi[og >> a.ol_shift] + ot.lo[og & (a.nOl - 1)];
   return outer_off(ot, og, a.nOl);
 }
 
-// Move a slab (n entries x kSegOB outer assignments) between a carrier in
-// global memory and an LDS tile.  The thread mapping puts consecutive
-// threads on consecutive addresses of the carrier: outer-fastest when the
-// carrier's stride-1 label is an outer label, entry-fastest otherwise.
-template <bool LOAD>
-__device__ __forceinline__ float seg_slab(const SegArgs &a, const float *src, float *dst, const Tab2 &ot,
-                                          const int32_t *loc, int n, bool outer_fast, uint32_t o0, float *tile,
-                                          float scale) {
+// Offsets of the workgroup's outer assignments in the input and output
+// carriers (-1 past nO) and of the local entries, staged in LDS once so that
+// every element move below is a single independent global access.
+static_assert(kSegThreads == 2 * kSegOB, "one thread per outer offset of each carrier");
+struct SegOffs {
+  int32_t oo, lx, lz;
+  uint32_t og;
+};
+// issue the table reads (clamped, valid indices; out-of-range results are
+// replaced when staged) ...
+__device__ __forceinline__ SegOffs seg_fetch_offsets(const SegArgs &a, uint32_t o0) {
+  typedef __attribute__((address_space(1))) const int32_t gint;
+  const int t = threadIdx.x;
+  const bool lowh = __builtin_amdgcn_readfirstlane(t) < kSegOB;  // uniform per wave
+  const uint32_t og = o0 + (lowh ? t : t - kSegOB);
+  const uint32_t oc = min(og, a.nO - 1);
+  gint *hi = (gint *)(lowh ? a.oX.hi : a.oZ.hi), *lo = (gint *)(lowh ? a.oX.lo : a.oZ.lo);
+  SegOffs r;
+  if (a.ol_shift >= 0) r.oo = hi[oc >> a.ol_shift] + lo[oc & (a.nOl - 1)];
+  else r.oo = hi[oc / a.nOl] + lo[oc % a.nOl];
+  r.lx = ((gint *)a.inX)[min(t, a.n_in0 - 1)];
+  r.lz = ((gint *)a.outZ)[min(t, a.n_outL - 1)];
+  r.og = og;
+  return r;
+}
+// ... and stage them in LDS once they have arrived
+__device__ __forceinline__ void seg_stage_offsets(const SegArgs &a, const SegOffs &r, int32_t *offX, int32_t *offZ,
+                                                  int32_t *locX, int32_t *locZ) {
+  const int t = threadIdx.x;
+  if (t < kSegOB) offX[t] = r.og < a.nO ? r.oo : -1;
+  else offZ[t - kSegOB] = r.og < a.nO ? r.oo : -1;
+  if (t < a.n_in0) locX[t] = r.lx;
+  if (t < a.n_outL) locZ[t] = r.lz;
+}
+__device__ __forceinline__ uint32_t seg_fetch_max(const SegArgs &a, int slot) {
+  typedef __attribute__((address_space(1))) const uint32_t gu32;
+  return ((gu32 *)a.mx)[(threadIdx.x & 63) * a.mx_stride + slot];
+}
+__device__ __forceinline__ int seg_max_exponent(uint32_t fetched) {
+  return max_exponent(__float_as_uint(wave_max(__uint_as_float(fetched))));
+}
+
+// Move a tile (kSegMaxLocal entries x kSegOB outer assignments) between a
+// carrier in global memory and LDS.  Consecutive threads take consecutive
+// addresses of the carrier: outer-fastest when the carrier's stride-1 label
+// is an outer label, entry-fastest otherwise.  Every thread issues all of
+// its kSegIter accesses before using them.  Loads fill entries past n and
+// outer assignments past nO with zeros; stores return the largest value
+// written by the thread.
+static constexpr int kSegIter = kSegMaxLocal * kSegOB / kSegThreads;
+
+// carriers are read and written through global-address-space pointers
+typedef __attribute__((address_space(1))) float gfloat;
+
+// (entry, outer assignment) of task t
+template <bool OUTER_FAST>
+__device__ __forceinline__ int2 seg_task(int t) {
+  if (OUTER_FAST) return make_int2(t / kSegOB, t % kSegOB);
+  return make_int2(t % kSegMaxLocal, t / kSegMaxLocal);
+}
+
+template <bool OUTER_FAST>
+__device__ __forceinline__ void seg_load_t(const float *src, const int32_t *off, const int32_t *loc, int n,
+                                           float *tile, float scale) {
+  const gfloat *g = (const gfloat *)src;
+  float v[kSegIter];
+#pragma unroll
+  for (int k = 0; k < kSegIter; ++k) {
+    const int2 jo = seg_task<OUTER_FAST>(threadIdx.x + k * kSegThreads);
+    const int32_t oo = off[jo.y];
+    v[k] = (jo.x < n && oo >= 0) ? g[(uint32_t)(oo + loc[jo.x])] : 0.f;
+  }
+#pragma unroll
+  for (int k = 0; k < kSegIter; ++k) {
+    const int2 jo = seg_task<OUTER_FAST>(threadIdx.x + k * kSegThreads);
+    tile[jo.x * kSegRow + jo.y] = v[k] * scale;
+  }
+}
+
+template <bool OUTER_FAST>
+__device__ __forceinline__ float seg_store_t(float *dst, const int32_t *off, const int32_t *loc, int n,
+                                             const float *tile) {
+  gfloat *g = (gfloat *)dst;
   float lmax = 0.f;
-  const int tasks = n * kSegOB;
-  for (int t = threadIdx.x; t < tasks; t += kSegBlock) {
-    int j, o;
-    if (outer_fast) {
-      j = t / kSegOB;
-      o = t - j * kSegOB;
-    } else {
-      o = t / n;
-      j = t - o * n;
-    }
-    const uint32_t og = o0 + o;
-    if (LOAD) {
-      tile[j * kSegOBP + o] = og < a.nO ? src[seg_outer(a, ot, og) + loc[j]] * scale : 0.f;
-    } else if (og < a.nO) {
-      const float v = tile[j * kSegOBP + o];
-      dst[seg_outer(a, ot, og) + loc[j]] = v;
-      lmax = fmaxf(lmax, v);
+#pragma unroll
+  for (int k = 0; k < kSegIter; ++k) {
+    const int2 jo = seg_task<OUTER_FAST>(threadIdx.x + k * kSegThreads);
+    const int32_t oo = off[jo.y];
+    if (jo.x < n && oo >= 0) {
+      const float x = tile[jo.x * kSegRow + jo.y];
+      g[(uint32_t)(oo + loc[jo.x])] = x;
+      lmax = fmaxf(lmax, x);
     }
   }
   return lmax;
 }
 
-// One step on the tiles: out[j][o] = sum over the triples of entry j of
-// in[i][o] * coef.  All threads share the (entry, outer) tasks.
-__device__ __forceinline__ void seg_apply(const int32_t *pp, const int32_t *ix, const int32_t *sx, const float *yv,
-                                          int n_out, const float *tin, float *tout) {
-  const int tasks = n_out * kSegOB;
-  for (int t = threadIdx.x; t < tasks; t += kSegBlock) {
-    const int j = t / kSegOB, o = t - j * kSegOB;
-    float acc = 0.f;
-    for (int e = pp[j]; e < pp[j + 1]; ++e) acc = fmaf(tin[ix[e] * kSegOBP + o], yv[sx[e]], acc);
-    tout[j * kSegOBP + o] = acc;
-  }
+__device__ __forceinline__ void seg_load(const float *src, const int32_t *off, const int32_t *loc, int n,
+                                         bool outer_fast, float *tile, float scale) {
+  if (outer_fast) seg_load_t<true>(src, off, loc, n, tile, scale);
+  else seg_load_t<false>(src, off, loc, n, tile, scale);
+}
+__device__ __forceinline__ float seg_store(float *dst, const int32_t *off, const int32_t *loc, int n, bool outer_fast,
+                                           const float *tile) {
+  return outer_fast ? seg_store_t<true>(dst, off, loc, n, tile) : seg_store_t<false>(dst, off, loc, n, tile);
 }
 
-// Forward: input carrier slab -> steps -> output carrier slab, one slab of
-// kSegOB outer assignments per block.
-__global__ __launch_bounds__(kSegBlock) void k_seg_fwd(const SegArgs *__restrict__ ap) {
-  const SegArgs &a = *ap;
-  extern __shared__ float lds[];
-  int32_t *li = (int32_t *)lds;
-  float *yv = lds + a.list_len;
-  float *t0 = yv + 64 * a.n_steps;
-  float *t1 = t0 + (size_t)a.te * kSegOBP;
-  const int kx = max_exponent(read_max(a.mx, a.mx_stride, a.slotX));
-  const uint32_t o0 = blockIdx.x * kSegOB;
-  seg_slab<true>(a, a.arena + a.X, nullptr, a.oX, a.inX, a.n_in0, a.in_outer_fast, o0, t0, ldexpf(1.f, -kx));
-  const int esum = a.ex[a.slotX] + kx + seg_stage(a, li, yv);
-  for (int i = 0; i < a.n_steps; ++i) {
-    const SegStep &st = a.steps[i];
-    seg_apply(li + st.fo_ptr, li + st.fo_in, li + st.fo_s, yv + i * 64, st.n_out, t0, t1);
-    __syncthreads();
-    float *tmp = t0;
-    t0 = t1;
-    t1 = tmp;
-  }
-  const float lmax =
-      seg_slab<false>(a, nullptr, a.arena + a.Z, a.oZ, a.outZ, a.n_outL, a.out_outer_fast, o0, t0, 1.f);
-  block_record_max<kSegBlock>(lmax, a.mx + (blockIdx.x % kMaxSub) * a.mx_stride + a.slotZ);
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.ex[a.slotZ] = esum;
-}
-
-// Reverse pass of a segment: recompute the carrier tiles of the slab from
-// the input carrier, then run the steps backwards (eq. einback per step).
-// The adjoint tile flows to the input carrier's adjoint (triples grouped by
-// input entry); every small operand's adjoint entry is a sum over its
-// triples (grouped by small entry) and over the slab, written per block to
-// `part` and summed in a fixed order by k_seg_bwd_finish.
-__global__ __launch_bounds__(kSegBlock) void k_seg_bwd(const SegArgs *__restrict__ ap) {
-  const SegArgs &a = *ap;
-  extern __shared__ float lds[];
-  const int te = a.te, L = a.n_steps;
-  int32_t *li = (int32_t *)lds;
-  float *yv = lds + a.list_len;
-  float *T = yv + 64 * L;                            // L tiles: input tile of every step
-  float *g0 = T + (size_t)L * te * kSegOBP;
-  float *g1 = g0 + (size_t)te * kSegOBP;
-  float *sbw = g1 + (size_t)te * kSegOBP;            // n_sb block totals
-  const int kx = max_exponent(read_max(a.mx, a.mx_stride, a.slotX));
-  const int kg = max_exponent(read_max(a.mx, a.mx_stride, a.slotG));
-  const uint32_t o0 = blockIdx.x * kSegOB;
-  seg_slab<true>(a, a.arena + a.X, nullptr, a.oX, a.inX, a.n_in0, a.in_outer_fast, o0, T, ldexpf(1.f, -kx));
-  seg_slab<true>(a, a.arena + a.G, nullptr, a.oZ, a.outZ, a.n_outL, a.out_outer_fast, o0, g0, ldexpf(1.f, -kg));
-  for (int k = threadIdx.x; k < a.n_sb; k += kSegBlock) sbw[k] = 0.f;
-  const int ey = seg_stage(a, li, yv);
-  for (int i = 0; i + 1 < L; ++i) {
-    const SegStep &st = a.steps[i];
-    seg_apply(li + st.fo_ptr, li + st.fo_in, li + st.fo_s, yv + i * 64, st.n_out, T + (size_t)i * te * kSegOBP,
-              T + (size_t)(i + 1) * te * kSegOBP);
-    __syncthreads();
-  }
-  for (int i = L - 1; i >= 0; --i) {
-    const SegStep &st = a.steps[i];
-    const float *tin = T + (size_t)i * te * kSegOBP;
-    if (st.sb_off >= 0) {
-      // (small entry, outer) tasks; the 32 outer assignments of one entry
-      // are 32 consecutive lanes, summed with shuffles
-      const int32_t *pp = li + st.bs_ptr, *xi = li + st.bs_in, *xo = li + st.bs_out;
-      const int tasks = st.ny * kSegOB;
-      for (int t0 = 0; t0 < tasks; t0 += kSegBlock) {
-        const int t = t0 + threadIdx.x;
-        float acc = 0.f;
-        int s2 = 0;
-        if (t < tasks) {
-          s2 = t / kSegOB;
-          const int o = t - s2 * kSegOB;
-          for (int e = pp[s2]; e < pp[s2 + 1]; ++e)
-            acc = fmaf(g0[xo[e] * kSegOBP + o], tin[xi[e] * kSegOBP + o], acc);
-        }
+// One wave: D (32 x 32) = A (32 x 32) * B (32 x 32) on the matrix cores
+// (sixteen v_mfma_f32_32x32x2_f32).  A is held in registers,
+// av[q] = A[lane % 32][2q + lane / 32]; B is read from LDS rows of kSegRow
+// starting at b.  Result: d[r] = D[8 (r / 4) + 4 (lane / 32) + r % 4][lane % 32].
+__device__ __forceinline__ f32x16 seg_mfma(const float (&av)[16], const float *b) {
+  f32x16 acc = {};
+  const int l = threadIdx.x & 63;
+  const float *bp = b + (l >> 5) * kSegRow + (l & 31);
 #pragma unroll
-        for (int off = 16; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-        if (t < tasks && (t & (kSegOB - 1)) == 0) sbw[st.sb_off + s2] += acc;
+  for (int q = 0; q < 16; ++q) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q], bp[2 * q * kSegRow], acc, 0, 0, 0);
+  return acc;
+}
+// A operand from a row-major matrix with `rows` x `cols` entries (zero
+// outside), transposed when TRANS: av[q] = A[lane % 32][2q + lane / 32]
+template <bool TRANS>
+__device__ __forceinline__ void seg_load_a(const float *m, int rows, int cols, float (&av)[16]) {
+  const gfloat *g = (const gfloat *)m;
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int i = l & 31, k = 2 * q + (l >> 5);
+    const int r = TRANS ? k : i, c = TRANS ? i : k;
+    // every lane loads (a clamped, valid entry) so that the sixteen loads are
+    // in flight together; entries outside the matrix are masked to zero
+    const float x = g[min(r, rows - 1) * cols + min(c, cols - 1)];
+    av[q] = x * ((r < rows && c < cols) ? 1.f : 0.f);
+  }
+}
+__device__ __forceinline__ int seg_drow(int r) { return 8 * (r >> 2) + 4 * ((threadIdx.x & 63) >> 5) + (r & 3); }
+
+// Forward: C_L[:, o] = M C_0[:, o] for the workgroup's kSegOB outer
+// assignments (one 32-wide column block per wave).
+__global__ __launch_bounds__(kSegThreads) void k_seg_fwd(const SegArgs *__restrict__ ap) {
+  const SegArgs &a = *ap;
+  __shared__ float tile[kSegMaxLocal * kSegRow];
+  __shared__ int32_t offX[kSegOB], offZ[kSegOB], locX[kSegMaxLocal], locZ[kSegMaxLocal];
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t o0 = blockIdx.x * kSegOB;
+  const int n_in = a.n_in0, n_out = a.n_outL;
+  // every prologue read is in flight before the first is used
+  const uint32_t mxX = seg_fetch_max(a, a.slotX);
+  float av[16];
+  seg_load_a<false>(a.arena + a.M, n_out, n_in, av);
+  const SegOffs so = seg_fetch_offsets(a, o0);
+  const int kx = seg_max_exponent(mxX);
+  seg_stage_offsets(a, so, offX, offZ, locX, locZ);
+  __syncthreads();
+  seg_load(a.arena + a.X, offX, locX, n_in, a.in_outer_fast, tile, ldexpf(1.f, -kx));
+  __syncthreads();
+  const f32x16 d = seg_mfma(av, tile + 32 * w);
+  // the wave's columns are its own: overwrite them in place
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    if (seg_drow(r) < n_out) tile[seg_drow(r) * kSegRow + 32 * w + (l & 31)] = d[r];
+  __syncthreads();
+  const float lmax = seg_store(a.arena + a.Z, offZ, locZ, n_out, a.out_outer_fast, tile);
+  block_record_max<kSegThreads, false>(lmax, a.mx + (blockIdx.x % kMaxSub) * a.mx_stride + a.slotZ);
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.ex[a.slotZ] = a.ex[a.slotX] + kx + a.ex[a.slotM];
+}
+
+// Reverse: Cbar_0[:, o] = M^T Gbar[:, o], and the workgroup's partial of
+// S = sum_o Gbar[:, o] C_0[:, o]^T (fixed order over the four waves).
+__global__ __launch_bounds__(kSegThreads) void k_seg_bwd(const SegArgs *__restrict__ ap) {
+  const SegArgs &a = *ap;
+  __shared__ float tg[kSegMaxLocal * kSegRow];  // output adjoint; later the waves' S partials
+  __shared__ float tx[kSegMaxLocal * kSegRow];  // input carrier; later its adjoint
+  __shared__ int32_t offX[kSegOB], offZ[kSegOB], locX[kSegMaxLocal], locZ[kSegMaxLocal];
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t o0 = blockIdx.x * kSegOB;
+  const int n_in = a.n_in0, n_out = a.n_outL;
+  const bool want_s = a.n_part > 0;
+  // every prologue read is in flight before the first is used
+  const uint32_t mxX = seg_fetch_max(a, a.slotX), mxG = seg_fetch_max(a, a.slotG);
+  float av[16];  // A = M^T
+  seg_load_a<true>(a.arena + a.M, n_out, n_in, av);
+  const SegOffs so = seg_fetch_offsets(a, o0);
+  const int kx = seg_max_exponent(mxX), kg = seg_max_exponent(mxG);
+  seg_stage_offsets(a, so, offX, offZ, locX, locZ);
+  __syncthreads();
+  seg_load(a.arena + a.G, offZ, locZ, n_out, a.out_outer_fast, tg, ldexpf(1.f, -kg));
+  if (want_s) seg_load(a.arena + a.X, offX, locX, n_in, a.in_outer_fast, tx, ldexpf(1.f, -kx));
+  __syncthreads();
+  const f32x16 xb = seg_mfma(av, tg + 32 * w);
+  f32x16 s = {};
+  if (want_s) {
+    // S (n_out x n_in) += Gbar (n_out x 32 outer) * C_0^T (32 outer x n_in)
+    const float *ga = tg + (l & 31) * kSegRow + 32 * w + (l >> 5);
+    const float *xa = tx + (l & 31) * kSegRow + 32 * w + (l >> 5);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) s = __builtin_amdgcn_mfma_f32_32x32x2f32(ga[2 * q], xa[2 * q], s, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    if (seg_drow(r) < n_in) tx[seg_drow(r) * kSegRow + 32 * w + (l & 31)] = xb[r];
+  __syncthreads();
+  const float lmax = seg_store(a.arena + a.Z, offX, locX, n_in, a.in_outer_fast, tx);
+  if (want_s && w > 0) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) tg[(w - 1) * 1024 + r * 64 + l] = s[r];
+  }
+  block_record_max<kSegThreads, false>(lmax, a.mx + (blockIdx.x % kMaxSub) * a.mx_stride + a.slotZ);
+  if (want_s && w == 0) {
+    const int nS = n_out * n_in;
+    float *part = a.arena + a.Sp + (size_t)blockIdx.x * nS;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const float v = ((s[r] + tg[r * 64 + l]) + tg[1024 + r * 64 + l]) + tg[2048 + r * 64 + l];
+      const int j = seg_drow(r), i = l & 31;
+      if (j < n_out && i < n_in) part[j * n_in + i] = v;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.ex[a.slotZ] = a.ex[a.slotG] + kg + a.ex[a.slotM];
+    if (want_s) a.ex[a.slotSp] = (a.ex[a.slotG] + kg) + (a.ex[a.slotX] + kx);
+  }
+}
+
+// --- sweeps over the steps (one workgroup per segment) ---------------------
+__device__ __forceinline__ float seg_block_max(float v, float *red) {
+  v = wave_max(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+// Scale v[0, n) so that its maximum lies in [0.5, 1); returns the exponent
+// taken out (values are non-negative).
+__device__ int seg_normalize(float *v, int n, float *red) {
+  float m = 0.f;
+  for (int t = threadIdx.x; t < n; t += kSegThreads) m = fmaxf(m, v[t]);
+  m = seg_block_max(m, red);
+  const int k = max_exponent(__float_as_uint(m));
+  if (k != 0) {
+    const float sc = ldexpf(1.f, -k);
+    for (int t = threadIdx.x; t < n; t += kSegThreads) v[t] *= sc;
+  }
+  __syncthreads();
+  return k;
+}
+
+// out = (step's map) in, column by column: out[j][c] = sum over the triples
+// of output entry j of in[i][c] * y[s]; rows of nc columns.
+__device__ void seg_step_fwd(const SegArgs &a, const SegStep &st, const float *in, float *out, int nc) {
+  const int32_t *ptr = a.lists + st.fo_ptr, *xi = a.lists + st.fo_in, *xs = a.lists + st.fo_s;
+  const float *y = a.arena + st.y;
+  for (int t = threadIdx.x; t < st.n_out * nc; t += kSegThreads) {
+    const int j = t / nc, c = t - j * nc;
+    float acc = 0.f;
+    for (int e = ptr[j]; e < ptr[j + 1]; ++e) acc = fmaf(in[xi[e] * nc + c], y[xs[e]], acc);
+    out[t] = acc;
+  }
+}
+
+// out = (step's map)^T in: out[i][c] = sum over the triples of input entry i
+// of in[j][c] * y[s].
+__device__ void seg_step_bwd(const SegArgs &a, const SegStep &st, const float *in, float *out, int nc) {
+  const int32_t *ptr = a.lists + st.bi_ptr, *xo = a.lists + st.bi_out, *xs = a.lists + st.bi_s;
+  const float *y = a.arena + st.y;
+  for (int t = threadIdx.x; t < st.n_in * nc; t += kSegThreads) {
+    const int i = t / nc, c = t - i * nc;
+    float acc = 0.f;
+    for (int e = ptr[i]; e < ptr[i + 1]; ++e) acc = fmaf(in[xo[e] * nc + c], y[xs[e]], acc);
+    out[t] = acc;
+  }
+}
+
+// M = (last step's map) ... (first step's map), applied to the identity,
+// renormalised after every step.
+__global__ __launch_bounds__(kSegThreads) void k_seg_mat(const SegArgs *__restrict__ base,
+                                                         const int32_t *__restrict__ ids) {
+  const SegArgs &a = base[ids[blockIdx.x]];
+  extern __shared__ float lds[];
+  __shared__ float red[4];
+  const int nc = a.n_in0;
+  float *A = lds, *B = lds + kSegMaxLocal * kSegMaxLocal;
+  for (int t = threadIdx.x; t < nc * nc; t += kSegThreads) A[t] = (t / nc == t % nc) ? 1.f : 0.f;
+  __syncthreads();
+  int e = 0;
+  for (int k = 0; k < a.n_steps; ++k) {
+    const SegStep &st = a.steps[k];
+    seg_step_fwd(a, st, A, B, nc);
+    __syncthreads();
+    e += a.ex[st.yslot] + seg_normalize(B, st.n_out * nc, red);
+    float *tmp = A;
+    A = B;
+    B = tmp;
+  }
+  for (int t = threadIdx.x; t < a.n_outL * nc; t += kSegThreads) a.arena[a.M + t] = A[t];
+  if (threadIdx.x == 0) a.ex[a.slotM] = e;
+}
+
+// Adjoints of the small operands.  With P_k the map of the first k steps
+// (P_0 = I) and G_k = (steps k..L-1)^T S (G_L = S), the adjoint of step k's
+// map is W_k = G_{k+1} P_k^T (eq. einback summed over the outer labels), and
+// the small operand's adjoint entry s sums W_k over the triples of s.
+__global__ __launch_bounds__(kSegThreads) void k_seg_fin(const SegArgs *__restrict__ base,
+                                                         const int32_t *__restrict__ ids) {
+  const SegArgs &a = base[ids[blockIdx.x]];
+  extern __shared__ float lds[];
+  __shared__ float red[4];
+  __shared__ int eP[kSegMaxSteps], poff[kSegMaxSteps];
+  const int nc = a.n_in0, L = a.n_steps, nS = a.n_outL * nc;
+  float *G0 = lds, *G1 = lds + 1024, *W = lds + 2048, *P = lds + 3072;
+  // S (summed by k_seg_sred into the first partial)
+  for (int t = threadIdx.x; t < nS; t += kSegThreads) G0[t] = a.arena[a.Sp + t];
+  // P_0 .. P_{L-1}
+  if (threadIdx.x == 0) {
+    int off = 0;
+    for (int k = 0; k < L; ++k) {
+      poff[k] = off;
+      off += a.steps[k].n_in * nc;
+    }
+    eP[0] = 0;
+  }
+  for (int t = threadIdx.x; t < nc * nc; t += kSegThreads) P[t] = (t / nc == t % nc) ? 1.f : 0.f;
+  __syncthreads();
+  for (int k = 0; k + 1 < L; ++k) {
+    const SegStep &st = a.steps[k];
+    float *nxt = P + poff[k + 1];
+    seg_step_fwd(a, st, P + poff[k], nxt, nc);
+    __syncthreads();
+    const int sh = seg_normalize(nxt, st.n_out * nc, red);
+    if (threadIdx.x == 0) eP[k + 1] = eP[k] + a.ex[st.yslot] + sh;
+  }
+  int eG = a.ex[a.slotSp] + seg_normalize(G0, nS, red);
+  for (int k = L - 1; k >= 0; --k) {
+    const SegStep &st = a.steps[k];
+    if (st.ybar >= 0) {
+      const float *Pk = P + poff[k];
+      for (int t = threadIdx.x; t < st.n_out * st.n_in; t += kSegThreads) {
+        const int j = t / st.n_in, i = t - j * st.n_in;
+        float acc = 0.f;
+        for (int c = 0; c < nc; ++c) acc = fmaf(G0[j * nc + c], Pk[i * nc + c], acc);
+        W[t] = acc;
+      }
+      __syncthreads();
+      const int32_t *ptr = a.lists + st.bs_ptr, *xi = a.lists + st.bs_in, *xo = a.lists + st.bs_out;
+      float m = 0.f;
+      for (int sidx = threadIdx.x; sidx < st.ny; sidx += kSegThreads) {
+        float acc = 0.f;
+        for (int e = ptr[sidx]; e < ptr[sidx + 1]; ++e) acc += W[xo[e] * st.n_in + xi[e]];
+        a.arena[st.ybar + sidx] = acc;
+        m = fmaxf(m, acc);
+      }
+      m = seg_block_max(m, red);
+      if (threadIdx.x == 0) {
+        a.mx[st.ybar_slot] = __float_as_uint(m);
+        a.ex[st.ybar_slot] = eG + eP[k];
       }
     }
-    seg_apply(li + st.bi_ptr, li + st.bi_out, li + st.bi_s, yv + i * 64, st.n_in, g0, g1);
-    __syncthreads();
-    float *tmp = g0;
-    g0 = g1;
-    g1 = tmp;
-  }
-  const float lmax =
-      seg_slab<false>(a, nullptr, a.arena + a.Z, a.oX, a.inX, a.n_in0, a.in_outer_fast, o0, g0, 1.f);
-  block_record_max<kSegBlock>(lmax, a.mx + (blockIdx.x % kMaxSub) * a.mx_stride + a.slotZ);
-  for (int k = threadIdx.x; k < a.n_sb; k += kSegBlock) a.part[(size_t)blockIdx.x * a.n_sb + k] = sbw[k];
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.ex[a.slotZ] = a.ex[a.slotG] + kg + ey;
-}
-
-// Sum the per-block partials of every small-operand adjoint entry (fixed
-// order) and record maxima and exponents.
-__global__ __launch_bounds__(256) void k_seg_bwd_finish(const SegArgs *__restrict__ ap, int n_blocks) {
-  const SegArgs &a = *ap;
-  const int k = blockIdx.x;
-  float acc = 0.f;
-  for (int w = threadIdx.x; w < n_blocks; w += 256) acc += a.part[(size_t)w * a.n_sb + k];
-  __shared__ float red[4];
-  acc = wave_sum(acc);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  const int kx = max_exponent(read_max(a.mx, a.mx_stride, a.slotX));
-  const int kg = max_exponent(read_max(a.mx, a.mx_stride, a.slotG));
-  int ey = 0, step = -1, sidx = 0, ei = 0;
-  for (int i = 0; i < a.n_steps; ++i) {
-    const SegStep &st = a.steps[i];
-    const int e = a.ex[st.yslot];
-    ey += e;
-    if (st.sb_off >= 0 && k >= st.sb_off && k < st.sb_off + st.ny) {
-      step = i;
-      sidx = k - st.sb_off;
-      ei = e;
+    if (k > 0) {
+      seg_step_bwd(a, st, G0, G1, nc);
+      __syncthreads();
+      eG += a.ex[st.yslot] + seg_normalize(G1, st.n_in * nc, red);
+      float *tmp = G0;
+      G0 = G1;
+      G1 = tmp;
     }
   }
-  if (threadIdx.x == 0 && step >= 0) {
-    const SegStep &st = a.steps[step];
-    const float t = red[0] + red[1] + red[2] + red[3];
-    a.arena[st.ybar + sidx] = t;
-    if (t > 0.f) atomicMax(a.mx + (sidx % kMaxSub) * a.mx_stride + st.ybar_slot, __float_as_uint(t));
-    if (sidx == 0) a.ex[st.ybar_slot] = (a.ex[a.slotG] + kg) + (a.ex[a.slotX] + kx) + (ey - ei);
+}
+
+// S = sum of the carrier kernel's partials, in a fixed order, written over
+// the first partial.  Workgroup (segment, chunk) owns kSredEntries entries;
+// four lanes per entry take every fourth partial, combined in lane order.
+static constexpr int kSredEntries = 64;
+static constexpr int kSredChunks = kSegMaxLocal * kSegMaxLocal / kSredEntries;
+
+__global__ __launch_bounds__(kSegThreads) void k_seg_sred(const SegArgs *__restrict__ base,
+                                                          const int32_t *__restrict__ ids) {
+  const SegArgs &a = base[ids[blockIdx.x / kSredChunks]];
+  __shared__ float red[kSegThreads];
+  const int nS = a.n_outL * a.n_in0;
+  const int e = (blockIdx.x % kSredChunks) * kSredEntries + (threadIdx.x & (kSredEntries - 1));
+  const int g = threadIdx.x / kSredEntries;
+  float *part = a.arena + a.Sp;
+  float acc = 0.f;
+  if (e < nS) {
+#pragma unroll 8
+    for (int b = g; b < a.n_part; b += kSegThreads / kSredEntries) acc += part[(size_t)b * nS + e];
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (g == 0 && e < nS) {
+    float t = red[threadIdx.x];
+    for (int q = 1; q < kSegThreads / kSredEntries; ++q) t += red[q * kSredEntries + threadIdx.x];
+    part[e] = t;
   }
 }
 
 void launch_seg_fwd(const SegArgs &a, const SegArgs *d_a, void *stream) {
-  const unsigned blocks = seg_blocks(a);
-  k_seg_fwd<<<blocks, kSegBlock, seg_fwd_lds(a), (hipStream_t)stream>>>(d_a);
+  k_seg_fwd<<<seg_blocks(a), kSegThreads, 0, (hipStream_t)stream>>>(d_a);
 }
-
 void launch_seg_bwd(const SegArgs &a, const SegArgs *d_a, void *stream) {
-  const unsigned blocks = seg_blocks(a);
-  k_seg_bwd<<<blocks, kSegBlock, seg_bwd_lds(a), (hipStream_t)stream>>>(d_a);
-  if (a.n_sb > 0) k_seg_bwd_finish<<<a.n_sb, 256, 0, (hipStream_t)stream>>>(d_a, (int)blocks);
+  k_seg_bwd<<<seg_blocks(a), kSegThreads, 0, (hipStream_t)stream>>>(d_a);
+}
+void launch_seg_mat(const SegArgs *d_base, const int32_t *d_ids, int n, int lds_floats, void *stream) {
+  k_seg_mat<<<n, kSegThreads, (size_t)lds_floats * sizeof(float), (hipStream_t)stream>>>(d_base, d_ids);
+}
+void launch_seg_fin(const SegArgs *d_base, const int32_t *d_ids, int n, int lds_floats, void *stream) {
+  k_seg_sred<<<n * kSredChunks, kSegThreads, 0, (hipStream_t)stream>>>(d_base, d_ids);
+  k_seg_fin<<<n, kSegThreads, (size_t)lds_floats * sizeof(float), (hipStream_t)stream>>>(d_base, d_ids);
 }
 
 // --------------------------------------------------------------------------

@@ -42,8 +42,9 @@ struct Op {
   double flops = 0, bytes = 0;        // algorithmic, per instance
   int64_t part_off = -1;              // partial-sum region of a split contraction
   ContractArgs *d_a = nullptr;        // device copy of `a`
-  // fused chain segment (seg >= 0): 1 forward, 2 reverse; extra tensors
-  // read / written, for scheduling
+  // fused chain segment (seg >= 0): 1 carrier forward, 2 carrier reverse,
+  // 3 composed map, 4 small operands' adjoints; extra tensors read /
+  // written, for scheduling
   int seg = -1, seg_kind = 0;
   std::vector<int> ins, outs;
 };
@@ -55,14 +56,16 @@ struct SegPlan {
   int c0 = -1, cL = -1;               // input / output carrier tensors
   int64_t oX[2], oZ[2], inX = 0, outZ = 0;
   uint32_t nO = 1, nOl = 1;
-  int32_t n_in0 = 0, n_outL = 0, te = 32, n_sb = 0;
+  int32_t n_in0 = 0, n_outL = 0;
   int64_t list_off = 0;               // the steps' CSR lists in the table store
-  int32_t list_len = 0, nnz_total = 0;
   int32_t in_outer_fast = 0, out_outer_fast = 0;
   std::vector<SegStep> steps;
+  int mt = -1;                        // tensor holding the composed map M
+  int spt = -1;                       // reverse: tensor holding the partials of S (-1 = none)
+  int32_t n_part = 0;                 // reverse: workgroups of the carrier kernel
+  int32_t sweep_lds = 0;              // floats of LDS of the sweep kernels
   std::vector<int> ybar_tensor;       // reverse: adjoint tensor of each small operand (-1)
   int g = -1, c0bar = -1;             // reverse: adjoint tensors of C_L and C_0
-  int64_t part_off = 0;               // reverse: partial region
   double bytes_fwd = 0, bytes_bwd = 0, flops = 0;
 };
 
@@ -71,8 +74,11 @@ struct SegPlan {
 struct Launch {
   int semi = SEMI_SUM;
   bool split = false;
-  bool seg = false;                   // a fused segment (always alone)
+  bool seg = false;                   // fused-segment kernels (carrier kinds alone)
+  int seg_kind = 0;
   std::vector<int> ops;               // indices into the op list
+  int32_t *d_ids = nullptr;           // segment kinds 3 / 4: device list of segment indices
+  int lds = 0;                        // segment kinds 3 / 4: LDS floats
   // grouped launches: device copies of the ops' arguments and block ranges
   ContractArgs *d_args = nullptr;
   uint32_t *d_start = nullptr, *d_nblk = nullptr;    // map, or split partials

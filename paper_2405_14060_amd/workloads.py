@@ -60,31 +60,32 @@ class Network:
 # ---------------------------------------------------------------------------
 
 def grid_mrf(rows: int, cols: int, seed: int, unary_sd: float = 0.5,
-             pair_sd: float = 1.0) -> Network:
-    """Binary pairwise grid MRF with Gaussian log-potentials.
+             pair_sd: float = 1.0, card: int = 2) -> Network:
+    """Pairwise grid MRF with Gaussian log-potentials (binary by default).
 
     Variable (r, c) has id r*cols + c.  Factors, in this order: one unary
-    table per variable (2 entries ~ N(0, unary_sd)), one 2x2 table per
-    horizontal edge (r,c)-(r,c+1), then one per vertical edge (r,c)-(r+1,c)
-    (4 i.i.d. entries ~ N(0, pair_sd)).  ``unary_sd`` is a standard deviation.
+    table per variable (``card`` entries ~ N(0, unary_sd)), one card x card
+    table per horizontal edge (r,c)-(r,c+1), then one per vertical edge
+    (r,c)-(r+1,c) (i.i.d. entries ~ N(0, pair_sd)).  ``unary_sd`` is a
+    standard deviation.
     """
     rng = np.random.default_rng(seed)
     n = rows * cols
     scopes, values = [], []
     for v in range(n):
         scopes.append(np.array([v], np.int32))
-        values.append(rng.normal(0.0, unary_sd, 2))
+        values.append(rng.normal(0.0, unary_sd, card))
     for r in range(rows):
         for c in range(cols - 1):
             scopes.append(np.array([r * cols + c, r * cols + c + 1], np.int32))
-            values.append(rng.normal(0.0, pair_sd, 4))
+            values.append(rng.normal(0.0, pair_sd, card * card))
     for r in range(rows - 1):
         for c in range(cols):
             scopes.append(np.array([r * cols + c, (r + 1) * cols + c], np.int32))
-            values.append(rng.normal(0.0, pair_sd, 4))
-    return Network(np.full(n, 2, np.int32), scopes, values, True,
+            values.append(rng.normal(0.0, pair_sd, card * card))
+    return Network(np.full(n, card, np.int32), scopes, values, True,
                    dict(kind="grid", rows=rows, cols=cols, seed=seed,
-                        unary_sd=unary_sd, pair_sd=pair_sd))
+                        unary_sd=unary_sd, pair_sd=pair_sd, card=card))
 
 
 def random_regular3(n: int, seed: int, pair_sd: float = 1.0,

@@ -132,6 +132,63 @@ def test_grid20x20_full_size_against_oracle(T):
     assert np.allclose([r.sum() for r in P.split_marginals(m[0])], 1.0, atol=1e-12)
 
 
+@pytest.mark.parametrize("rows,cols,card", [(12, 12, 2), (9, 9, 3), (7, 7, 4)])
+def test_fused_segments_against_oracle(T, rows, cols, card):
+    """Grids whose planned trees hold fused chain segments (composed maps on
+    the matrix cores), including odd local sizes (card 3: 27 entries)."""
+    net = W.grid_mrf(rows, cols, 1, card=card)
+    P = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT)
+    info = P.info()
+    assert info["n_segments"] > 0
+    lz, m = P.marginals()
+    pairs, _ = P.tree()
+    lzo, marg, *_ = oracle.marginals(net, pairs=pairs.astype(np.int64))
+    assert rel(lz[0], lzo) <= 1e-5
+    got = P.split_marginals(m[0])
+    err = max(np.abs(a - b).max() for a, b in zip(got, marg))
+    assert err <= 1e-5, err
+    # the unfused plan of the same tree agrees closely
+    U = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, fuse=False,
+               tree=pairs)
+    assert U.info()["n_segments"] == 0
+    lzu, mu = U.marginals()
+    assert rel(lz[0], lzu[0]) <= 2e-6
+    assert np.abs(m[0] - mu[0]).max() <= 2e-6
+
+
+def test_fused_segments_factor_gradients(T):
+    """d log Z / dT of every factor (thm. diff) through fused segments: the
+    small operands' adjoints come from the segments' adjoint sweeps."""
+    import torch
+    from paper_2405_14060_amd.autograd import log_z
+    g0 = W.grid_mrf(12, 12, 2)
+    net = W.Network(g0.card, g0.scopes, [np.exp(v) for v in g0.values], False, dict(g0.meta))
+    N = T.Network(net)
+    P = T.Plan(N, semirings=T.SUM_PRODUCT, want_factor_grad=True,
+               stream=torch.cuda.current_stream().cuda_stream)
+    assert P.info()["n_segments"] > 0
+    _, _, _, vals = net.flat()
+    v = torch.tensor(vals, dtype=torch.float32, device="cuda", requires_grad=True)
+    lz = log_z(P, v)
+    lz.sum().backward()
+    g = v.grad.double().cpu().numpy()
+    lzo, marg, adj, aexp, lv = oracle.marginals(net, pairs=P.tree()[0].astype(np.int64))
+    assert rel(float(lz.item()), lzo) <= 1e-5
+    off = N.value_offsets
+    worst = 0.0
+    for i, k in enumerate(lv.kind):
+        if k != "factor":
+            continue
+        f = lv.factor_of[i]
+        s = np.asarray(net.scopes[f])
+        perm = np.argsort(s)
+        want = (adj[i] * 2.0 ** (aexp[i] - lzo / math.log(2.0))).reshape([net.card[u] for u in s[perm]])
+        want = np.transpose(want, np.argsort(perm)).ravel()
+        got = g[off[f]:off[f + 1]]
+        worst = max(worst, float(np.max(np.abs(got - want) / np.maximum(np.abs(want), 1e-3))))
+    assert worst <= 1e-4, worst
+
+
 def test_unity_identity_and_invariants(T):
     """Marginal rows sum to one and observed variables are one-hot."""
     bn = W.random_bn(40, seed=9)
