@@ -256,7 +256,9 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
   op.nb = zb ? p->max_batch : 1;
   const uint64_t n_out = (uint64_t)a.nR * a.nC;
   const uint32_t nSh = a.nS / a.nSl;
-  if (n_out * (uint64_t)op.nb < 8192 && a.nS >= 4096 && nSh >= 2) {
+  // few outputs, each a long sum: workgroups reduce chunks of the summed
+  // index cooperatively instead of one lane looping over all of it
+  if (n_out * (uint64_t)op.nb < 8192 && a.nS >= 256) {
     op.split = true;
     // about 1024 workgroups in total, each reducing at least 1K summed entries
     uint32_t want = std::max<uint32_t>(1, 1024u / (uint32_t)op.nb);
@@ -648,7 +650,8 @@ static void upload_schedule(tn_plan_t *p, Schedule &sc, const std::vector<Op> &o
       L.lds = 0;
       for (int i : L.ops) {
         ids.push_back(ops[i].seg);
-        L.lds = std::max(L.lds, L.seg_kind == 3 ? 2 * 1024 : p->segs[ops[i].seg].sweep_lds);
+        const SegPlan &sp = p->segs[ops[i].seg];
+        L.lds = std::max(L.lds, L.seg_kind == 3 ? sp.mat_lds : sp.fin_lds);
       }
       L.d_ids = dalloc_vec(p, ids);
       continue;
@@ -927,17 +930,25 @@ static bool describe_segment(tn_plan_t *p, const std::vector<Op> &ops, const std
     if (numel(unite(Loc[j], U[j]), card) > 1024) return false;  // triples of a step
   const int64_t nO = numel(O, card);
   if (nO < 256) return false;
-  // LDS of the adjoint sweep: three 32 x 32 work areas and P_0 .. P_{L-1}
+  // LDS of the sweeps: 32 x 32 work areas (two for the composed map, three
+  // for the adjoints), P_0 .. P_{L-1} (adjoints), 64 floats of small operand
+  // per step and the index lists (three CSR orders of every step's triples)
   const int64_t n_in0 = numel(Loc[0], card);
-  int64_t lds = 3 * 1024;
-  for (int j = 0; j < L; ++j) lds += numel(Loc[j], card) * n_in0;
-  if (lds > 15 * 1024) return false;
+  int64_t lists = 0, pstore = 0;
+  for (int j = 0; j < L; ++j) {
+    const int64_t nnz = numel(unite(Loc[j], U[j]), card);
+    lists += numel(Loc[j + 1], card) + numel(Loc[j], card) + numel(U[j], card) + 3 + 6 * nnz;
+    pstore += numel(Loc[j], card) * n_in0;
+  }
+  const int64_t fin_lds = 3 * 1024 + pstore + 64 * L + lists;
+  if (fin_lds > 15 * 1024) return false;
   if (!commit) return true;
   sp.ops = chain;
   sp.c0 = ops[chain[0]].X;
   sp.cL = ops[chain[L - 1]].Z;
   sp.nO = (uint32_t)nO;
-  sp.sweep_lds = (int32_t)lds;
+  sp.fin_lds = (int32_t)fin_lds;
+  sp.mat_lds = (int32_t)(2 * 1024 + 64 * L + lists);
   const size_t os = lo_split(O, card);
   sp.nOl = (uint32_t)numel(Labels(O.begin() + os, O.end()), card);
   add_tabs(p, O, os, V[0], sp.oX);
@@ -1012,6 +1023,8 @@ static bool describe_segment(tn_plan_t *p, const std::vector<Op> &ops, const std
     sp.steps.push_back(st);
   }
   sp.list_off = (int64_t)p->tabs.size();
+  sp.list_len = (int32_t)blk.size();
+  if (sp.list_len != lists) throw TnError(TN_E_INVALID, "internal: segment list size");
   p->tabs.insert(p->tabs.end(), blk.begin(), blk.end());
   double b = 4.0 * (double)(p->T[sp.c0].size + p->T[sp.cL].size);
   sp.bytes_fwd = b;
@@ -1205,7 +1218,9 @@ static void upload_segments(tn_plan_t *p) {
       a.out_outer_fast = sp.out_outer_fast;
       a.lists = p->d_tabs + sp.list_off;
       a.n_steps = (int32_t)sp.steps.size();
-      a.sweep_lds = sp.sweep_lds;
+      a.list_len = sp.list_len;
+      a.mat_lds = sp.mat_lds;
+      a.fin_lds = sp.fin_lds;
       a.M = p->T[sp.mt].off;
       a.slotM = p->T[sp.mt].slot;
       a.X = p->T[sp.c0].off;

@@ -176,13 +176,14 @@ struct SegArgs {
   const SegStep *steps = nullptr;
   int32_t n_steps = 0;
   const int32_t *lists = nullptr;  // the steps' CSR lists (offsets in SegStep are relative)
+  int32_t list_len = 0;            // int32 entries of the lists
   int32_t in_outer_fast = 0;     // the input carrier's stride-1 label is an outer label
   int32_t out_outer_fast = 0;    // same for the output carrier
-  int32_t sweep_lds = 0;         // floats of LDS of the sweep kernels (k_seg_mat, k_seg_fin)
+  int32_t mat_lds = 0, fin_lds = 0;  // floats of LDS of the sweep kernels
 };
 void launch_seg_fwd(const SegArgs &a, const SegArgs *d_a, void *stream);
 void launch_seg_bwd(const SegArgs &a, const SegArgs *d_a, void *stream);
-// one workgroup per listed segment; lds_floats = the largest sweep_lds of them
+// one workgroup per listed segment; lds_floats = the largest mat_lds / fin_lds of them
 void launch_seg_mat(const SegArgs *d_base, const int32_t *d_ids, int n, int lds_floats, void *stream);
 void launch_seg_fin(const SegArgs *d_base, const int32_t *d_ids, int n, int lds_floats, void *stream);
 unsigned seg_blocks(const SegArgs &a);  // workgroups of a carrier launch

@@ -605,9 +605,9 @@ void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, co
 // --------------------------------------------------------------------------
 // fused chain segments
 // --------------------------------------------------------------------------
-typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-static constexpr int kSegThreads = 256;           // 4 waves
+static constexpr int kSegThreads = 1024;          // 16 waves: enough in flight per CU to cover latency
+static constexpr int kSweepThreads = 256;         // sweep kernels (one workgroup per segment)
 static constexpr int kSegOB = kSegOuterBlock;     // outer assignments per workgroup (32 per wave)
 static constexpr int kSegRow = kSegOB + 1;        // padded LDS tile row: conflict-free in both directions
 
@@ -625,43 +625,68 @@ __device__ __forceinline__ int32_t seg_outer(const SegArgs &a, const Tab2 &ot, u
 // Offsets of the workgroup's outer assignments in the input and output
 // carriers (-1 past nO) and of the local entries, staged in LDS once so that
 // every element move below is a single independent global access.
-static_assert(kSegThreads == 2 * kSegOB, "one thread per outer offset of each carrier");
-struct SegOffs {
-  int32_t oo, lx, lz;
-  uint32_t og;
+static_assert(kSegThreads >= 2 * kSegOB, "one thread per outer offset of each carrier");
+// Per-workgroup constants of a carrier kernel, staged in LDS by a prologue
+// in which every thread makes at most two global reads and no location is
+// read by more than one wave of the workgroup (a location read by every wave
+// of every workgroup would serialise in one L2 channel): outer offsets of
+// both carriers, local offsets, the composed map M (zero-padded to 32 x 32)
+// and the exponents of the operands' maxima.
+struct SegShared {
+  int32_t offX[kSegOB], offZ[kSegOB], locX[kSegMaxLocal], locZ[kSegMaxLocal];
+  float m[kSegMaxLocal * (kSegMaxLocal + 1)];
+  int32_t kx, kg;
 };
-// issue the table reads (clamped, valid indices; out-of-range results are
-// replaced when staged) ...
-__device__ __forceinline__ SegOffs seg_fetch_offsets(const SegArgs &a, uint32_t o0) {
-  typedef __attribute__((address_space(1))) const int32_t gint;
+typedef __attribute__((address_space(1))) const int32_t gint;
+typedef __attribute__((address_space(1))) const uint32_t gu32;
+typedef __attribute__((address_space(1))) const float gcfloat;
+
+__device__ __forceinline__ void seg_prologue(const SegArgs &a, uint32_t o0, bool want_g, SegShared &sh) {
   const int t = threadIdx.x;
-  const bool lowh = __builtin_amdgcn_readfirstlane(t) < kSegOB;  // uniform per wave
-  const uint32_t og = o0 + (lowh ? t : t - kSegOB);
-  const uint32_t oc = min(og, a.nO - 1);
-  gint *hi = (gint *)(lowh ? a.oX.hi : a.oZ.hi), *lo = (gint *)(lowh ? a.oX.lo : a.oZ.lo);
-  SegOffs r;
-  if (a.ol_shift >= 0) r.oo = hi[oc >> a.ol_shift] + lo[oc & (a.nOl - 1)];
-  else r.oo = hi[oc / a.nOl] + lo[oc % a.nOl];
-  r.lx = ((gint *)a.inX)[min(t, a.n_in0 - 1)];
-  r.lz = ((gint *)a.outZ)[min(t, a.n_outL - 1)];
-  r.og = og;
-  return r;
+  const int wv = __builtin_amdgcn_readfirstlane(t) >> 6;  // wave index, uniform
+  const int l = t & 63;
+  // M, one entry per thread
+  {
+    const int r = t >> 5, c = t & 31;
+    const float x = ((gcfloat *)(a.arena + a.M))[min(r, a.n_outL - 1) * a.n_in0 + min(c, a.n_in0 - 1)];
+    sh.m[r * (kSegMaxLocal + 1) + c] = (r < a.n_outL && c < a.n_in0) ? x : 0.f;
+  }
+  if (wv < 4) {  // outer offsets: waves 0-1 the input carrier, 2-3 the output carrier
+    const bool in = wv < 2;
+    const int tt = t & (kSegOB - 1);
+    const uint32_t og = o0 + tt, oc = min(og, a.nO - 1);
+    gint *hi = (gint *)(in ? a.oX.hi : a.oZ.hi), *lo = (gint *)(in ? a.oX.lo : a.oZ.lo);
+    int32_t oo;
+    if (a.ol_shift >= 0) oo = hi[oc >> a.ol_shift] + lo[oc & (a.nOl - 1)];
+    else oo = hi[oc / a.nOl] + lo[oc % a.nOl];
+    (in ? sh.offX : sh.offZ)[tt] = og < a.nO ? oo : -1;
+  } else if (wv == 4) {  // local offsets: lanes 0-31 input, 32-63 output
+    const int j = l & 31;
+    if (l < 32) {
+      const int32_t v = ((gint *)a.inX)[min(j, a.n_in0 - 1)];
+      if (j < a.n_in0) sh.locX[j] = v;
+    } else {
+      const int32_t v = ((gint *)a.outZ)[min(j, a.n_outL - 1)];
+      if (j < a.n_outL) sh.locZ[j] = v;
+    }
+  } else if (wv == 5 || (wv == 6 && want_g)) {  // maxima of the operands (64 sub-slots)
+    const int slot = wv == 5 ? a.slotX : a.slotG;
+    const uint32_t v = ((gu32 *)a.mx)[l * a.mx_stride + slot];
+    const int k = max_exponent(__float_as_uint(wave_max(__uint_as_float(v))));
+    if (l == 0) (wv == 5 ? sh.kx : sh.kg) = k;
+  }
 }
-// ... and stage them in LDS once they have arrived
-__device__ __forceinline__ void seg_stage_offsets(const SegArgs &a, const SegOffs &r, int32_t *offX, int32_t *offZ,
-                                                  int32_t *locX, int32_t *locZ) {
-  const int t = threadIdx.x;
-  if (t < kSegOB) offX[t] = r.og < a.nO ? r.oo : -1;
-  else offZ[t - kSegOB] = r.og < a.nO ? r.oo : -1;
-  if (t < a.n_in0) locX[t] = r.lx;
-  if (t < a.n_outL) locZ[t] = r.lz;
-}
-__device__ __forceinline__ uint32_t seg_fetch_max(const SegArgs &a, int slot) {
-  typedef __attribute__((address_space(1))) const uint32_t gu32;
-  return ((gu32 *)a.mx)[(threadIdx.x & 63) * a.mx_stride + slot];
-}
-__device__ __forceinline__ int seg_max_exponent(uint32_t fetched) {
-  return max_exponent(__float_as_uint(wave_max(__uint_as_float(fetched))));
+
+// A operand for the wave's row half from the staged M:
+// av[q] = A[16 (w % 2) + l % 16][4q + l / 16] with A = M, or A = M^T when TRANS
+template <bool TRANS>
+__device__ __forceinline__ void seg_load_a(const SegShared &sh, float (&av)[8]) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int i = 16 * (w & 1) + (l & 15), k = 4 * q + (l >> 4);
+    av[q] = TRANS ? sh.m[k * (kSegMaxLocal + 1) + i] : sh.m[i * (kSegMaxLocal + 1) + k];
+  }
 }
 
 // Move a tile (kSegMaxLocal entries x kSegOB outer assignments) between a
@@ -729,117 +754,107 @@ __device__ __forceinline__ float seg_store(float *dst, const int32_t *off, const
   return outer_fast ? seg_store_t<true>(dst, off, loc, n, tile) : seg_store_t<false>(dst, off, loc, n, tile);
 }
 
-// One wave: D (32 x 32) = A (32 x 32) * B (32 x 32) on the matrix cores
-// (sixteen v_mfma_f32_32x32x2_f32).  A is held in registers,
-// av[q] = A[lane % 32][2q + lane / 32]; B is read from LDS rows of kSegRow
-// starting at b.  Result: d[r] = D[8 (r / 4) + 4 (lane / 32) + r % 4][lane % 32].
-__device__ __forceinline__ f32x16 seg_mfma(const float (&av)[16], const float *b) {
-  f32x16 acc = {};
-  const int l = threadIdx.x & 63;
-  const float *bp = b + (l >> 5) * kSegRow + (l & 31);
+// Matrix-core tiles: v_mfma_f32_16x16x4_f32, D (16 x 16) += A (16 x 4) B (4 x 16)
+// with lane l holding A[l % 16][l / 16], B[l / 16][l % 16] and
+// D[4 (l / 16) + r][l % 16] in register r.  A workgroup's 32 x kSegOB output
+// is 2 x 8 tiles, one per wave: rows 16 (w % 2), columns 16 (w / 2).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// D tile of the wave = A (its 16 rows x 32) * B (32 x its 16 columns of `b`)
+__device__ __forceinline__ f32x4 seg_mfma(const float (&av)[8], const float *b) {
+  f32x4 acc = {};
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const float *bp = b + (l >> 4) * kSegRow + 16 * (w >> 1) + (l & 15);
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q], bp[2 * q * kSegRow], acc, 0, 0, 0);
+  for (int q = 0; q < 8; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], bp[4 * q * kSegRow], acc, 0, 0, 0);
   return acc;
 }
-// A operand from a row-major matrix with `rows` x `cols` entries (zero
-// outside), transposed when TRANS: av[q] = A[lane % 32][2q + lane / 32]
-template <bool TRANS>
-__device__ __forceinline__ void seg_load_a(const float *m, int rows, int cols, float (&av)[16]) {
-  const gfloat *g = (const gfloat *)m;
-  const int l = threadIdx.x & 63;
+// write the wave's D tile into rows < n of a tile
+__device__ __forceinline__ void seg_put(const f32x4 &d, int n, float *tile) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int i = l & 31, k = 2 * q + (l >> 5);
-    const int r = TRANS ? k : i, c = TRANS ? i : k;
-    // every lane loads (a clamped, valid entry) so that the sixteen loads are
-    // in flight together; entries outside the matrix are masked to zero
-    const float x = g[min(r, rows - 1) * cols + min(c, cols - 1)];
-    av[q] = x * ((r < rows && c < cols) ? 1.f : 0.f);
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * (w & 1) + 4 * (l >> 4) + r;
+    if (row < n) tile[row * kSegRow + 16 * (w >> 1) + (l & 15)] = d[r];
   }
 }
-__device__ __forceinline__ int seg_drow(int r) { return 8 * (r >> 2) + 4 * ((threadIdx.x & 63) >> 5) + (r & 3); }
 
 // Forward: C_L[:, o] = M C_0[:, o] for the workgroup's kSegOB outer
 // assignments (one 32-wide column block per wave).
 __global__ __launch_bounds__(kSegThreads) void k_seg_fwd(const SegArgs *__restrict__ ap) {
   const SegArgs &a = *ap;
   __shared__ float tile[kSegMaxLocal * kSegRow];
-  __shared__ int32_t offX[kSegOB], offZ[kSegOB], locX[kSegMaxLocal], locZ[kSegMaxLocal];
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __shared__ SegShared sh;
   const uint32_t o0 = blockIdx.x * kSegOB;
   const int n_in = a.n_in0, n_out = a.n_outL;
-  // every prologue read is in flight before the first is used
-  const uint32_t mxX = seg_fetch_max(a, a.slotX);
-  float av[16];
-  seg_load_a<false>(a.arena + a.M, n_out, n_in, av);
-  const SegOffs so = seg_fetch_offsets(a, o0);
-  const int kx = seg_max_exponent(mxX);
-  seg_stage_offsets(a, so, offX, offZ, locX, locZ);
+  seg_prologue(a, o0, false, sh);
   __syncthreads();
-  seg_load(a.arena + a.X, offX, locX, n_in, a.in_outer_fast, tile, ldexpf(1.f, -kx));
+  const int kx = sh.kx;
+  seg_load(a.arena + a.X, sh.offX, sh.locX, n_in, a.in_outer_fast, tile, ldexpf(1.f, -kx));
+  float av[8];
+  seg_load_a<false>(sh, av);
   __syncthreads();
-  const f32x16 d = seg_mfma(av, tile + 32 * w);
-  // the wave's columns are its own: overwrite them in place
-#pragma unroll
-  for (int r = 0; r < 16; ++r)
-    if (seg_drow(r) < n_out) tile[seg_drow(r) * kSegRow + 32 * w + (l & 31)] = d[r];
+  const f32x4 d = seg_mfma(av, tile);
   __syncthreads();
-  const float lmax = seg_store(a.arena + a.Z, offZ, locZ, n_out, a.out_outer_fast, tile);
+  seg_put(d, n_out, tile);
+  __syncthreads();
+  const float lmax = seg_store(a.arena + a.Z, sh.offZ, sh.locZ, n_out, a.out_outer_fast, tile);
   block_record_max<kSegThreads, false>(lmax, a.mx + (blockIdx.x % kMaxSub) * a.mx_stride + a.slotZ);
   if (blockIdx.x == 0 && threadIdx.x == 0) a.ex[a.slotZ] = a.ex[a.slotX] + kx + a.ex[a.slotM];
 }
 
 // Reverse: Cbar_0[:, o] = M^T Gbar[:, o], and the workgroup's partial of
-// S = sum_o Gbar[:, o] C_0[:, o]^T (fixed order over the four waves).
+// S = sum_o Gbar[:, o] C_0[:, o]^T: wave w computes the 16 x 16 quadrant
+// w % 4 of S over the outer quarter w / 4; quarters are added in order.
 __global__ __launch_bounds__(kSegThreads) void k_seg_bwd(const SegArgs *__restrict__ ap) {
   const SegArgs &a = *ap;
   __shared__ float tg[kSegMaxLocal * kSegRow];  // output adjoint; later the waves' S partials
   __shared__ float tx[kSegMaxLocal * kSegRow];  // input carrier; later its adjoint
-  __shared__ int32_t offX[kSegOB], offZ[kSegOB], locX[kSegMaxLocal], locZ[kSegMaxLocal];
+  __shared__ SegShared sh;
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint32_t o0 = blockIdx.x * kSegOB;
   const int n_in = a.n_in0, n_out = a.n_outL;
   const bool want_s = a.n_part > 0;
-  // every prologue read is in flight before the first is used
-  const uint32_t mxX = seg_fetch_max(a, a.slotX), mxG = seg_fetch_max(a, a.slotG);
-  float av[16];  // A = M^T
-  seg_load_a<true>(a.arena + a.M, n_out, n_in, av);
-  const SegOffs so = seg_fetch_offsets(a, o0);
-  const int kx = seg_max_exponent(mxX), kg = seg_max_exponent(mxG);
-  seg_stage_offsets(a, so, offX, offZ, locX, locZ);
+  seg_prologue(a, o0, true, sh);
   __syncthreads();
-  seg_load(a.arena + a.G, offZ, locZ, n_out, a.out_outer_fast, tg, ldexpf(1.f, -kg));
-  if (want_s) seg_load(a.arena + a.X, offX, locX, n_in, a.in_outer_fast, tx, ldexpf(1.f, -kx));
+  const int kx = sh.kx, kg = sh.kg;
+  seg_load(a.arena + a.G, sh.offZ, sh.locZ, n_out, a.out_outer_fast, tg, ldexpf(1.f, -kg));
+  if (want_s) seg_load(a.arena + a.X, sh.offX, sh.locX, n_in, a.in_outer_fast, tx, ldexpf(1.f, -kx));
+  float av[8];  // A = M^T
+  seg_load_a<true>(sh, av);
   __syncthreads();
-  const f32x16 xb = seg_mfma(av, tg + 32 * w);
-  f32x16 s = {};
+  const f32x4 xb = seg_mfma(av, tg);
+  f32x4 s = {};
   if (want_s) {
-    // S (n_out x n_in) += Gbar (n_out x 32 outer) * C_0^T (32 outer x n_in)
-    const float *ga = tg + (l & 31) * kSegRow + 32 * w + (l >> 5);
-    const float *xa = tx + (l & 31) * kSegRow + 32 * w + (l >> 5);
+    // S quadrant (rows 16 qr of Gbar's entries, columns 16 qc of C_0's) over
+    // the outer quarter kq: A = Gbar (16 x 32 outer), B = C_0^T (32 outer x 16)
+    const int qr = w & 1, qc = (w >> 1) & 1, kq = w >> 2;
+    const float *ga = tg + (16 * qr + (l & 15)) * kSegRow + 32 * kq + (l >> 4);
+    const float *xa = tx + (16 * qc + (l & 15)) * kSegRow + 32 * kq + (l >> 4);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) s = __builtin_amdgcn_mfma_f32_32x32x2f32(ga[2 * q], xa[2 * q], s, 0, 0, 0);
+    for (int q = 0; q < 8; ++q) s = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[4 * q], xa[4 * q], s, 0, 0, 0);
   }
-#pragma unroll
-  for (int r = 0; r < 16; ++r)
-    if (seg_drow(r) < n_in) tx[seg_drow(r) * kSegRow + 32 * w + (l & 31)] = xb[r];
   __syncthreads();
-  const float lmax = seg_store(a.arena + a.Z, offX, locX, n_in, a.in_outer_fast, tx);
-  if (want_s && w > 0) {
+  seg_put(xb, n_in, tx);
+  if (want_s && w >= 4) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) tg[(w - 1) * 1024 + r * 64 + l] = s[r];
+    for (int r = 0; r < 4; ++r) tg[(w - 4) * 256 + r * 64 + l] = s[r];
   }
-  block_record_max<kSegThreads, false>(lmax, a.mx + (blockIdx.x % kMaxSub) * a.mx_stride + a.slotZ);
-  if (want_s && w == 0) {
+  __syncthreads();
+  const float lmax = seg_store(a.arena + a.Z, sh.offX, sh.locX, n_in, a.in_outer_fast, tx);
+  if (want_s && w < 4) {
     const int nS = n_out * n_in;
     float *part = a.arena + a.Sp + (size_t)blockIdx.x * nS;
+    const int qr = w & 1, qc = w >> 1;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const float v = ((s[r] + tg[r * 64 + l]) + tg[1024 + r * 64 + l]) + tg[2048 + r * 64 + l];
-      const int j = seg_drow(r), i = l & 31;
+    for (int r = 0; r < 4; ++r) {
+      const float v = ((s[r] + tg[w * 256 + r * 64 + l]) + tg[(w + 4) * 256 + r * 64 + l]) +
+                      tg[(w + 8) * 256 + r * 64 + l];
+      const int j = 16 * qr + 4 * (l >> 4) + r, i = 16 * qc + (l & 15);
       if (j < n_out && i < n_in) part[j * n_in + i] = v;
     }
   }
+  block_record_max<kSegThreads, false>(lmax, a.mx + (blockIdx.x % kMaxSub) * a.mx_stride + a.slotZ);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.ex[a.slotZ] = a.ex[a.slotG] + kg + a.ex[a.slotM];
     if (want_s) a.ex[a.slotSp] = (a.ex[a.slotG] + kg) + (a.ex[a.slotX] + kx);
@@ -859,23 +874,34 @@ __device__ __forceinline__ float seg_block_max(float v, float *red) {
 // taken out (values are non-negative).
 __device__ int seg_normalize(float *v, int n, float *red) {
   float m = 0.f;
-  for (int t = threadIdx.x; t < n; t += kSegThreads) m = fmaxf(m, v[t]);
+  for (int t = threadIdx.x; t < n; t += kSweepThreads) m = fmaxf(m, v[t]);
   m = seg_block_max(m, red);
   const int k = max_exponent(__float_as_uint(m));
   if (k != 0) {
     const float sc = ldexpf(1.f, -k);
-    for (int t = threadIdx.x; t < n; t += kSegThreads) v[t] *= sc;
+    for (int t = threadIdx.x; t < n; t += kSweepThreads) v[t] *= sc;
   }
   __syncthreads();
   return k;
 }
 
+// The sweep kernels stage the segment's index lists and small operands in
+// LDS first (one round of global reads), so that every step below reads
+// LDS only.
+__device__ __forceinline__ void seg_stage_lists(const SegArgs &a, int32_t *li, float *yv) {
+  for (int t = threadIdx.x; t < a.list_len; t += kSweepThreads) li[t] = a.lists[t];
+  for (int k = 0; k < a.n_steps; ++k) {
+    const SegStep &st = a.steps[k];
+    for (int t = threadIdx.x; t < st.ny; t += kSweepThreads) yv[k * 64 + t] = a.arena[st.y + t];
+  }
+}
+
 // out = (step's map) in, column by column: out[j][c] = sum over the triples
 // of output entry j of in[i][c] * y[s]; rows of nc columns.
-__device__ void seg_step_fwd(const SegArgs &a, const SegStep &st, const float *in, float *out, int nc) {
-  const int32_t *ptr = a.lists + st.fo_ptr, *xi = a.lists + st.fo_in, *xs = a.lists + st.fo_s;
-  const float *y = a.arena + st.y;
-  for (int t = threadIdx.x; t < st.n_out * nc; t += kSegThreads) {
+__device__ void seg_step_fwd(const SegStep &st, const int32_t *li, const float *y, const float *in, float *out,
+                             int nc) {
+  const int32_t *ptr = li + st.fo_ptr, *xi = li + st.fo_in, *xs = li + st.fo_s;
+  for (int t = threadIdx.x; t < st.n_out * nc; t += kSweepThreads) {
     const int j = t / nc, c = t - j * nc;
     float acc = 0.f;
     for (int e = ptr[j]; e < ptr[j + 1]; ++e) acc = fmaf(in[xi[e] * nc + c], y[xs[e]], acc);
@@ -885,10 +911,10 @@ __device__ void seg_step_fwd(const SegArgs &a, const SegStep &st, const float *i
 
 // out = (step's map)^T in: out[i][c] = sum over the triples of input entry i
 // of in[j][c] * y[s].
-__device__ void seg_step_bwd(const SegArgs &a, const SegStep &st, const float *in, float *out, int nc) {
-  const int32_t *ptr = a.lists + st.bi_ptr, *xo = a.lists + st.bi_out, *xs = a.lists + st.bi_s;
-  const float *y = a.arena + st.y;
-  for (int t = threadIdx.x; t < st.n_in * nc; t += kSegThreads) {
+__device__ void seg_step_bwd(const SegStep &st, const int32_t *li, const float *y, const float *in, float *out,
+                             int nc) {
+  const int32_t *ptr = li + st.bi_ptr, *xo = li + st.bi_out, *xs = li + st.bi_s;
+  for (int t = threadIdx.x; t < st.n_in * nc; t += kSweepThreads) {
     const int i = t / nc, c = t - i * nc;
     float acc = 0.f;
     for (int e = ptr[i]; e < ptr[i + 1]; ++e) acc = fmaf(in[xo[e] * nc + c], y[xs[e]], acc);
@@ -897,27 +923,30 @@ __device__ void seg_step_bwd(const SegArgs &a, const SegStep &st, const float *i
 }
 
 // M = (last step's map) ... (first step's map), applied to the identity,
-// renormalised after every step.
-__global__ __launch_bounds__(kSegThreads) void k_seg_mat(const SegArgs *__restrict__ base,
-                                                         const int32_t *__restrict__ ids) {
+// renormalised after every step.  LDS: two 32 x 32 work areas, the lists,
+// 64 floats of small operand per step.
+__global__ __launch_bounds__(kSweepThreads) void k_seg_mat(const SegArgs *__restrict__ base,
+                                                           const int32_t *__restrict__ ids) {
   const SegArgs &a = base[ids[blockIdx.x]];
   extern __shared__ float lds[];
   __shared__ float red[4];
   const int nc = a.n_in0;
-  float *A = lds, *B = lds + kSegMaxLocal * kSegMaxLocal;
-  for (int t = threadIdx.x; t < nc * nc; t += kSegThreads) A[t] = (t / nc == t % nc) ? 1.f : 0.f;
+  float *A = lds, *B = lds + 1024, *yv = lds + 2048;
+  int32_t *li = (int32_t *)(yv + 64 * a.n_steps);
+  seg_stage_lists(a, li, yv);
+  for (int t = threadIdx.x; t < nc * nc; t += kSweepThreads) A[t] = (t / nc == t % nc) ? 1.f : 0.f;
   __syncthreads();
   int e = 0;
   for (int k = 0; k < a.n_steps; ++k) {
     const SegStep &st = a.steps[k];
-    seg_step_fwd(a, st, A, B, nc);
+    seg_step_fwd(st, li, yv + 64 * k, A, B, nc);
     __syncthreads();
     e += a.ex[st.yslot] + seg_normalize(B, st.n_out * nc, red);
     float *tmp = A;
     A = B;
     B = tmp;
   }
-  for (int t = threadIdx.x; t < a.n_outL * nc; t += kSegThreads) a.arena[a.M + t] = A[t];
+  for (int t = threadIdx.x; t < a.n_outL * nc; t += kSweepThreads) a.arena[a.M + t] = A[t];
   if (threadIdx.x == 0) a.ex[a.slotM] = e;
 }
 
@@ -925,31 +954,36 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_mat(const SegArgs *__restri
 // (P_0 = I) and G_k = (steps k..L-1)^T S (G_L = S), the adjoint of step k's
 // map is W_k = G_{k+1} P_k^T (eq. einback summed over the outer labels), and
 // the small operand's adjoint entry s sums W_k over the triples of s.
-__global__ __launch_bounds__(kSegThreads) void k_seg_fin(const SegArgs *__restrict__ base,
-                                                         const int32_t *__restrict__ ids) {
+// LDS: three 32 x 32 work areas, P_0 .. P_{L-1}, the small operands, the lists.
+__global__ __launch_bounds__(kSweepThreads) void k_seg_fin(const SegArgs *__restrict__ base,
+                                                           const int32_t *__restrict__ ids) {
   const SegArgs &a = base[ids[blockIdx.x]];
   extern __shared__ float lds[];
   __shared__ float red[4];
-  __shared__ int eP[kSegMaxSteps], poff[kSegMaxSteps];
+  __shared__ int eP[kSegMaxSteps], poff[kSegMaxSteps + 1];
   const int nc = a.n_in0, L = a.n_steps, nS = a.n_outL * nc;
   float *G0 = lds, *G1 = lds + 1024, *W = lds + 2048, *P = lds + 3072;
-  // S (summed by k_seg_sred into the first partial)
-  for (int t = threadIdx.x; t < nS; t += kSegThreads) G0[t] = a.arena[a.Sp + t];
-  // P_0 .. P_{L-1}
   if (threadIdx.x == 0) {
     int off = 0;
     for (int k = 0; k < L; ++k) {
       poff[k] = off;
       off += a.steps[k].n_in * nc;
     }
+    poff[L] = off;
     eP[0] = 0;
   }
-  for (int t = threadIdx.x; t < nc * nc; t += kSegThreads) P[t] = (t / nc == t % nc) ? 1.f : 0.f;
+  __syncthreads();
+  float *yv = P + poff[L];
+  int32_t *li = (int32_t *)(yv + 64 * L);
+  seg_stage_lists(a, li, yv);
+  // S (summed by k_seg_sred into the first partial)
+  for (int t = threadIdx.x; t < nS; t += kSweepThreads) G0[t] = a.arena[a.Sp + t];
+  for (int t = threadIdx.x; t < nc * nc; t += kSweepThreads) P[t] = (t / nc == t % nc) ? 1.f : 0.f;
   __syncthreads();
   for (int k = 0; k + 1 < L; ++k) {
     const SegStep &st = a.steps[k];
     float *nxt = P + poff[k + 1];
-    seg_step_fwd(a, st, P + poff[k], nxt, nc);
+    seg_step_fwd(st, li, yv + 64 * k, P + poff[k], nxt, nc);
     __syncthreads();
     const int sh = seg_normalize(nxt, st.n_out * nc, red);
     if (threadIdx.x == 0) eP[k + 1] = eP[k] + a.ex[st.yslot] + sh;
@@ -959,16 +993,16 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_fin(const SegArgs *__restri
     const SegStep &st = a.steps[k];
     if (st.ybar >= 0) {
       const float *Pk = P + poff[k];
-      for (int t = threadIdx.x; t < st.n_out * st.n_in; t += kSegThreads) {
+      for (int t = threadIdx.x; t < st.n_out * st.n_in; t += kSweepThreads) {
         const int j = t / st.n_in, i = t - j * st.n_in;
         float acc = 0.f;
         for (int c = 0; c < nc; ++c) acc = fmaf(G0[j * nc + c], Pk[i * nc + c], acc);
         W[t] = acc;
       }
       __syncthreads();
-      const int32_t *ptr = a.lists + st.bs_ptr, *xi = a.lists + st.bs_in, *xo = a.lists + st.bs_out;
+      const int32_t *ptr = li + st.bs_ptr, *xi = li + st.bs_in, *xo = li + st.bs_out;
       float m = 0.f;
-      for (int sidx = threadIdx.x; sidx < st.ny; sidx += kSegThreads) {
+      for (int sidx = threadIdx.x; sidx < st.ny; sidx += kSweepThreads) {
         float acc = 0.f;
         for (int e = ptr[sidx]; e < ptr[sidx + 1]; ++e) acc += W[xo[e] * st.n_in + xi[e]];
         a.arena[st.ybar + sidx] = acc;
@@ -981,7 +1015,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_fin(const SegArgs *__restri
       }
     }
     if (k > 0) {
-      seg_step_bwd(a, st, G0, G1, nc);
+      seg_step_bwd(st, li, yv + 64 * k, G0, G1, nc);
       __syncthreads();
       eG += a.ex[st.yslot] + seg_normalize(G1, st.n_in * nc, red);
       float *tmp = G0;
@@ -997,10 +1031,10 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_fin(const SegArgs *__restri
 static constexpr int kSredEntries = 64;
 static constexpr int kSredChunks = kSegMaxLocal * kSegMaxLocal / kSredEntries;
 
-__global__ __launch_bounds__(kSegThreads) void k_seg_sred(const SegArgs *__restrict__ base,
+__global__ __launch_bounds__(kSweepThreads) void k_seg_sred(const SegArgs *__restrict__ base,
                                                           const int32_t *__restrict__ ids) {
   const SegArgs &a = base[ids[blockIdx.x / kSredChunks]];
-  __shared__ float red[kSegThreads];
+  __shared__ float red[kSweepThreads];
   const int nS = a.n_outL * a.n_in0;
   const int e = (blockIdx.x % kSredChunks) * kSredEntries + (threadIdx.x & (kSredEntries - 1));
   const int g = threadIdx.x / kSredEntries;
@@ -1008,13 +1042,13 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_sred(const SegArgs *__restr
   float acc = 0.f;
   if (e < nS) {
 #pragma unroll 8
-    for (int b = g; b < a.n_part; b += kSegThreads / kSredEntries) acc += part[(size_t)b * nS + e];
+    for (int b = g; b < a.n_part; b += kSweepThreads / kSredEntries) acc += part[(size_t)b * nS + e];
   }
   red[threadIdx.x] = acc;
   __syncthreads();
   if (g == 0 && e < nS) {
     float t = red[threadIdx.x];
-    for (int q = 1; q < kSegThreads / kSredEntries; ++q) t += red[q * kSredEntries + threadIdx.x];
+    for (int q = 1; q < kSweepThreads / kSredEntries; ++q) t += red[q * kSredEntries + threadIdx.x];
     part[e] = t;
   }
 }
@@ -1026,11 +1060,11 @@ void launch_seg_bwd(const SegArgs &a, const SegArgs *d_a, void *stream) {
   k_seg_bwd<<<seg_blocks(a), kSegThreads, 0, (hipStream_t)stream>>>(d_a);
 }
 void launch_seg_mat(const SegArgs *d_base, const int32_t *d_ids, int n, int lds_floats, void *stream) {
-  k_seg_mat<<<n, kSegThreads, (size_t)lds_floats * sizeof(float), (hipStream_t)stream>>>(d_base, d_ids);
+  k_seg_mat<<<n, kSweepThreads, (size_t)lds_floats * sizeof(float), (hipStream_t)stream>>>(d_base, d_ids);
 }
 void launch_seg_fin(const SegArgs *d_base, const int32_t *d_ids, int n, int lds_floats, void *stream) {
-  k_seg_sred<<<n * kSredChunks, kSegThreads, 0, (hipStream_t)stream>>>(d_base, d_ids);
-  k_seg_fin<<<n, kSegThreads, (size_t)lds_floats * sizeof(float), (hipStream_t)stream>>>(d_base, d_ids);
+  k_seg_sred<<<n * kSredChunks, kSweepThreads, 0, (hipStream_t)stream>>>(d_base, d_ids);
+  k_seg_fin<<<n, kSweepThreads, (size_t)lds_floats * sizeof(float), (hipStream_t)stream>>>(d_base, d_ids);
 }
 
 // --------------------------------------------------------------------------

@@ -63,7 +63,8 @@ struct SegPlan {
   int mt = -1;                        // tensor holding the composed map M
   int spt = -1;                       // reverse: tensor holding the partials of S (-1 = none)
   int32_t n_part = 0;                 // reverse: workgroups of the carrier kernel
-  int32_t sweep_lds = 0;              // floats of LDS of the sweep kernels
+  int32_t list_len = 0;               // int32 entries of the lists
+  int32_t mat_lds = 0, fin_lds = 0;   // floats of LDS of the sweep kernels
   std::vector<int> ybar_tensor;       // reverse: adjoint tensor of each small operand (-1)
   int g = -1, c0bar = -1;             // reverse: adjoint tensors of C_L and C_0
   double bytes_fwd = 0, bytes_bwd = 0, flops = 0;
