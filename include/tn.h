@@ -125,6 +125,7 @@ typedef struct {
   int32_t n_launches_max;
   int32_t n_segments;            /* fused chain segments */
   int32_t n_fused_nodes;         /* tree nodes inside fused segments */
+  int32_t n_dense;               /* contractions (forward and reverse) in the dense matrix-core form */
 } tn_plan_info;
 
 /* Fill *o with defaults: sum-product + max-plus, no evidence, best planner,
@@ -228,7 +229,8 @@ tn_status tn_logZ_dev(tn_plan_t *plan, const int32_t *evidence, const float *val
  * 6 carrier forward (C_L = M C_0 over the outer labels), 7 carrier reverse
  * (adjoint of C_0 and partial sums of Gbar C_0^T), 8 composed maps M of a
  * stage's segments, 9 adjoint sweeps (small operands' adjoints) of a
- * stage's segments.  flops and bytes are algorithmic: 2 x output x summed
+ * stage's segments, 10 dense-form contractions on the matrix cores
+ * (sum-product).  flops and bytes are algorithmic: 2 x output x summed
  * elements; 4 bytes x (|X| + |Y| + |Z|) per instance times the instances of
  * the launch; for a carrier forward 4 bytes x (|input carrier| + |output
  * carrier|), for a carrier reverse 4 bytes x (2 |input carrier| + |output

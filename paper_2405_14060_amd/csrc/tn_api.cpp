@@ -234,7 +234,9 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
   const Labels R = inter(LZ, LX), C = minus(LZ, LX), S = minus(unite(LX, LY), LZ);
   if (semi == SEMI_MAX && !minus(C, LY).empty()) throw TnError(TN_E_INVALID, "internal: broadcast in max-plus node");
   const size_t rs = lo_split(R, card), cs = lo_split(C, card), ss = lo_split(S, card);
-  for (auto *t : {op.t_rX, op.t_rY, op.t_rZ, op.t_cY, op.t_cZ, op.t_sX, op.t_sY}) t[0] = t[1] = -1;
+  for (auto *t : {op.t_rX, op.t_rY, op.t_rZ, op.t_cY, op.t_cZ, op.t_sX, op.t_sY, op.t_gbX, op.t_gbY, op.t_gbZ,
+                  op.t_gmX, op.t_gmZ})
+    t[0] = t[1] = -1;
   add_tabs(p, R, rs, LX, op.t_rX);
   add_tabs(p, R, rs, LZ, op.t_rZ);
   add_tabs(p, C, cs, LZ, op.t_cZ);
@@ -269,8 +271,31 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
     op.part_off = p->part_floats;
     p->part_floats += ((int64_t)op.nb * a.n_chunks * n_out + 63) / 64 * 64;
   }
+  // dense form on the matrix cores: sum-product with wide row and column
+  // sets and a summed set of at least one MFMA step
+  if (!op.split && semi == SEMI_SUM && Y >= 0) {
+    const Labels Bl = inter(R, LY), Ml = minus(R, LY);
+    const int64_t nB = numel(Bl, card), nM = numel(Ml, card);
+    if (nM >= 16 && a.nC >= 8 && a.nS >= 8 && nB * ((nM + kGemmTile - 1) / kGemmTile) *
+                                                      (((int64_t)a.nC + kGemmTile - 1) / kGemmTile) < (1LL << 31)) {
+      a.kind = 2;
+      const size_t bs = lo_split(Bl, card), ms = lo_split(Ml, card);
+      add_tabs(p, Bl, bs, LX, op.t_gbX);
+      add_tabs(p, Bl, bs, LY, op.t_gbY);
+      add_tabs(p, Bl, bs, LZ, op.t_gbZ);
+      add_tabs(p, Ml, ms, LX, op.t_gmX);
+      add_tabs(p, Ml, ms, LZ, op.t_gmZ);
+      a.nB = (uint32_t)nB;
+      a.nBl = (uint32_t)numel(Labels(Bl.begin() + bs, Bl.end()), card);
+      a.nM = (uint32_t)nM;
+      a.nMl = (uint32_t)numel(Labels(Ml.begin() + ms, Ml.end()), card);
+      a.x_s_fast = (!LX.empty() && has(S, LX.back())) ? 1 : 0;
+      a.y_n_fast = (!LY.empty() && has(C, LY.back())) ? 1 : 0;
+      a.z_n_fast = (!LZ.empty() && has(C, LZ.back())) ? 1 : 0;
+    }
+  }
   // row form for skinny contractions: few summed entries and columns
-  if (!op.split && a.nS <= (uint32_t)kRowMax && a.nC <= (uint32_t)kRowMax && a.nS * a.nC <= 64) {
+  if (!op.split && a.kind == 0 && a.nS <= (uint32_t)kRowMax && a.nC <= (uint32_t)kRowMax && a.nS * a.nC <= 64) {
     a.kind = 1;
     a.ns = (int32_t)a.nS;
     a.nc = (int32_t)a.nC;
@@ -546,6 +571,11 @@ static void fill_args(tn_plan_t *p, Op &op) {
   a.cZ = tab(op.t_cZ);
   a.sX = tab(op.t_sX);
   a.sY = tab(op.t_sY);
+  a.gbX = tab(op.t_gbX);
+  a.gbY = tab(op.t_gbY);
+  a.gbZ = tab(op.t_gbZ);
+  a.gmX = tab(op.t_gmX);
+  a.gmZ = tab(op.t_gmZ);
   const TensorBuf &X = p->T[op.X], &Z = p->T[op.Z];
   a.X = p->arena + X.off;
   a.bsX = X.batched ? X.size : 0;
@@ -629,13 +659,16 @@ static Schedule build_schedule(tn_plan_t *p, const std::vector<Op> &ops, bool al
         sc.launches.push_back(std::move(L));
       }
     for (int semi = 0; semi < 2; ++semi)
-      for (int spl = 0; spl < 2; ++spl) {
+      for (int cls = 0; cls < 3; ++cls) {  // one-lane-per-output forms, split reductions, dense form
         Launch L;
         L.semi = semi;
-        L.split = spl != 0;
-        for (int i = 0; i < n; ++i)
-          if (stage[i] == st && ops[i].seg < 0 && ops[i].semi == semi && ops[i].split == (spl != 0))
-            L.ops.push_back(i);
+        L.split = cls == 1;
+        L.gemm = cls == 2;
+        for (int i = 0; i < n; ++i) {
+          const Op &op = ops[i];
+          const int c = op.split ? 1 : (op.a.kind == 2 ? 2 : 0);
+          if (stage[i] == st && op.seg < 0 && op.semi == semi && c == cls) L.ops.push_back(i);
+        }
         if (!L.ops.empty()) sc.launches.push_back(std::move(L));
       }
   }
@@ -1458,6 +1491,10 @@ extern "C" tn_status tn_plan_info_get(const tn_plan_t *p, tn_plan_info *info) {
     }
     info->n_segments = (int32_t)p->segs.size();
     for (const auto &sp : p->segs) info->n_fused_nodes += (int32_t)sp.ops.size();
+    for (const auto *L : {&p->sum_tree.ops, &p->bwd, &p->qtree.ops})
+      for (const Op &op : *L) info->n_dense += op.a.kind == 2 ? 1 : 0;
+    for (const auto &g : p->groups)
+      for (const Op &op : g.ops) info->n_dense += op.a.kind == 2 ? 1 : 0;
   });
 }
 
@@ -1540,6 +1577,8 @@ void run_sched(tn_plan_t *p, const std::vector<Op> &ops, const Schedule &sc) {
     } else if (L.ops.size() == 1) {
       const Op &op = ops[L.ops[0]];
       launch_contract(op.semi, op.Y >= 0, op.split, op.a, op.d_a, op.nb, p->stream);
+    } else if (L.gemm) {
+      launch_group(L.semi, 3, L.d_args, L.d_start, L.d_nblk, (int)L.ops.size(), L.total, p->stream);
     } else if (!L.split) {
       launch_group(L.semi, 0, L.d_args, L.d_start, L.d_nblk, (int)L.ops.size(), L.total, p->stream);
     } else {
@@ -2029,6 +2068,7 @@ static tn_status profile_impl(tn_plan_t *p, int32_t task, int32_t batch, const i
         }
         int kind;
         if (L.seg) kind = 5 + L.seg_kind;  // 6 carrier forward, 7 carrier reverse, 8 composed maps, 9 adjoint sweeps
+        else if (L.gemm) kind = 10;
         else kind = (L.split ? 2 : 0) + (L.semi == SEMI_MAX ? 1 : 0);
         const Launch *lp = &L;
         const std::vector<Op> *opsp = &ops;

@@ -102,11 +102,22 @@ struct ContractArgs {
   // row form (kind 1): one lane per row, all summed entries and columns in
   // registers; offsets of the summed entries in X, Y and of the columns in
   // Y, Z, in canonical order
-  int32_t kind = 0;  // 0 generic, 1 row form
+  int32_t kind = 0;  // 0 generic, 1 row form, 2 dense matrix-core form
   int32_t ns = 0, nc = 0;
   int32_t rl_shift = -1;  // log2(nRl) when nRl is a power of two
   int32_t sx[kRowMax], sy[kRowMax], cy[kRowMax], cz[kRowMax];
+  // dense form (kind 2, sum-product): the rows split into batch labels
+  // (held by Y too) and M labels (not held by Y); for every batch
+  // assignment Z[M, N] = sum_S X[M, S] Y[S, N] with N the columns, as
+  // 64 x 64 output tiles on the matrix cores
+  Tab2 gbX, gbY, gbZ;       // batch labels in X, Y, Z
+  Tab2 gmX, gmZ;            // M labels in X, Z
+  uint32_t nB = 1, nBl = 1, nM = 1, nMl = 1;
+  int32_t x_s_fast = 0;     // X's stride-1 label is summed (else an M or batch label)
+  int32_t y_n_fast = 0;     // Y's stride-1 label is a column label
+  int32_t z_n_fast = 0;     // Z's stride-1 label is a column label
 };
+static constexpr int kGemmTile = 64;  // output tile edge of the dense form
 
 enum Semiring { SEMI_SUM = 0, SEMI_MAX = 1 };
 
@@ -115,7 +126,7 @@ void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, co
                      void *stream);
 // blocks per instance of a one-lane-per-output launch
 uint32_t map_blocks(const ContractArgs &a);
-// phase 0: map, 1: split partials, 2: split finish
+// phase 0: map, 1: split partials, 2: split finish, 3: dense form
 void launch_group(int semi, int phase, const ContractArgs *ops, const uint32_t *start,
                   const uint32_t *nblk, int n, uint32_t total_blocks, void *stream);
 

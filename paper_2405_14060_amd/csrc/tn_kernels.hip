@@ -34,6 +34,7 @@
 namespace tn {
 
 static constexpr int kBlock = 256;
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
@@ -492,6 +493,122 @@ __device__ __forceinline__ void any_map_body(const ContractArgs &a, const int b,
   }
 }
 
+// --------------------------------------------------------------------------
+// dense form on the matrix cores (sum-product): for one batch assignment,
+// a 64 x 64 tile of Z[M, N] = sum_S X[M, S] Y[S, N], FP32 operands on
+// v_mfma_f32_16x16x4_f32 (lane l holds A[l % 16][l / 16], B[l / 16][l % 16],
+// D[4 (l / 16) + r][l % 16]).  Operands are gathered through the offset
+// tables into LDS chunks of 16 summed entries (consecutive threads on the
+// operand's stride-1 label), scaled on load; each wave owns a 32 x 32
+// quarter of the tile (2 x 2 MFMA tiles); the tile leaves through LDS with
+// consecutive threads on Z's stride-1 label.
+// --------------------------------------------------------------------------
+static constexpr int kGT = kGemmTile;   // 64
+static constexpr int kGK = 16;          // summed entries per chunk
+static constexpr int kGKP = kGT + 16;   // chunk row pitch: conflict-free MFMA operand reads
+static constexpr int kGCP = kGT + 1;    // epilogue tile pitch
+
+__device__ __forceinline__ void gemm_body(const ContractArgs &a, const int b, const uint32_t blk) {
+  __shared__ int32_t oMX[kGT], oMZ[kGT], oNY[kGT], oNZ[kGT];
+  __shared__ float As[kGK * kGKP], Bs[kGK * kGKP];
+  __shared__ float Cs[kGT * kGCP];
+  __shared__ int ksh[2];
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
+  const uint32_t tm = (a.nM + kGT - 1) / kGT, tn = (a.nC + kGT - 1) / kGT;
+  const uint32_t bt = blk / (tm * tn), rem = blk - bt * tm * tn;
+  const uint32_t mt = rem / tn, nt = rem - mt * tn;
+  const uint32_t m0 = mt * kGT, n0 = nt * kGT;
+  const int32_t xb = tab_off(a.gbX, bt, a.nBl), yb = tab_off(a.gbY, bt, a.nBl), zb = tab_off(a.gbZ, bt, a.nBl);
+  const float *__restrict__ X = a.X + (int64_t)b * a.bsX + xb;
+  const float *__restrict__ Y = a.Y + (int64_t)b * a.bsY + yb;
+  float *__restrict__ Z = a.Z + (int64_t)b * a.bsZ + zb;
+  // prologue: row / column offsets and the operands' exponents, one read each
+  if (w == 0) {
+    const uint32_t m = m0 + l;
+    oMX[l] = m < a.nM ? tab_off(a.gmX, m, a.nMl) : -1;
+    oMZ[l] = m < a.nM ? tab_off(a.gmZ, m, a.nMl) : -1;
+  } else if (w == 1) {
+    const uint32_t n = n0 + l;
+    oNY[l] = n < a.nC ? (a.nC > 1 ? tab_off(a.cY, n, a.nCl) : 0) : -1;
+    oNZ[l] = n < a.nC ? (a.nC > 1 ? tab_off(a.cZ, n, a.nCl) : 0) : -1;
+  } else {
+    const int slot = w == 2 ? a.slotX + (a.batX ? b : 0) : a.slotY + (a.batY ? b : 0);
+    const int k = max_exponent(read_max(a.mx, a.mx_stride, slot));
+    if (l == 0) ksh[w - 2] = k;
+  }
+  __syncthreads();
+  const int kx = ksh[0], ky = ksh[1];
+  const float sx = ldexpf(1.f, -kx), sy = ldexpf(1.f, -ky);
+  f32x4 acc[2][2] = {};
+  const int wm = w & 1, wn = w >> 1;
+  for (uint32_t s0 = 0; s0 < a.nS; s0 += kGK) {
+    // gather the chunk: A^T as As[k][m], B as Bs[k][n]
+    float va[4], vb[4];
+    int da[4], db[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + q * kBlock;
+      int m, k;
+      if (a.x_s_fast) { k = e % kGK; m = e / kGK; } else { m = e % kGT; k = e / kGT; }
+      const uint32_t s = s0 + k;
+      const int32_t om = oMX[m];
+      va[q] = (om >= 0 && s < a.nS) ? X[om + tab_off(a.sX, s, a.nSl)] : 0.f;
+      da[q] = k * kGKP + m;
+      int n, k2;
+      if (a.y_n_fast) { n = e % kGT; k2 = e / kGT; } else { k2 = e % kGK; n = e / kGK; }
+      const uint32_t s2 = s0 + k2;
+      const int32_t on = oNY[n];
+      vb[q] = (on >= 0 && s2 < a.nS) ? Y[on + tab_off(a.sY, s2, a.nSl)] : 0.f;
+      db[q] = k2 * kGKP + n;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      As[da[q]] = va[q] * sx;
+      Bs[db[q]] = vb[q] * sy;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGK; kk += 4) {
+      const int r = (kk + (l >> 4)) * kGKP + (l & 15);
+      const float a0 = As[r + 32 * wm], a1 = As[r + 32 * wm + 16];
+      const float b0 = Bs[r + 32 * wn], b1 = Bs[r + 32 * wn + 16];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        Cs[(32 * wm + 16 * i + 4 * (l >> 4) + r) * kGCP + 32 * wn + 16 * j + (l & 15)] = acc[i][j][r];
+  __syncthreads();
+  float lmax = 0.f;
+#pragma unroll 4
+  for (int q = 0; q < kGT * kGT / kBlock; ++q) {
+    const int e = t + q * kBlock;
+    int m, n;
+    if (a.z_n_fast) { n = e % kGT; m = e / kGT; } else { m = e % kGT; n = e / kGT; }
+    const int32_t om = oMZ[m], on = oNZ[n];
+    if (om >= 0 && on >= 0) {
+      const float v = Cs[m * kGCP + n];
+      Z[om + on] = v;
+      lmax = fmaxf(lmax, v);
+    }
+  }
+  block_record_max(lmax, a.mx + (blk % kMaxSub) * a.mx_stride + a.slotZ + (a.batZ ? b : 0));
+  if (blk == 0 && threadIdx.x == 0)
+    a.ex[a.slotZ + (a.batZ ? b : 0)] = a.ex[a.slotX + (a.batX ? b : 0)] + kx + a.ex[a.slotY + (a.batY ? b : 0)] + ky;
+}
+
+__global__ __launch_bounds__(kBlock) void k_gemm(const ContractArgs *__restrict__ ap) {
+  gemm_body(*ap, blockIdx.y, blockIdx.x);
+}
+
 // Arguments live in device memory (a pointer is the only kernel argument):
 // large by-value argument blocks cost microseconds per launch.
 template <int SEMI, bool HASY>
@@ -537,6 +654,8 @@ __global__ __launch_bounds__(kBlock) void k_group(const ContractArgs *__restrict
   } else if (PHASE == 1) {
     if (hy) split_body<SEMI, true>(a, b, blk);
     else split_body<SEMI, false>(a, b, blk);
+  } else if (PHASE == 3) {
+    gemm_body(a, b, blk);
   } else {
     if (hy) finish_body<SEMI, true>(a, b, blk);
     else finish_body<SEMI, false>(a, b, blk);
@@ -548,6 +667,10 @@ void launch_group(int semi, int phase, const ContractArgs *ops, const uint32_t *
   if (n <= 0 || total_blocks == 0) return;
   hipStream_t s = (hipStream_t)stream;
   dim3 g(total_blocks);
+  if (phase == 3) {  // dense form: sum-product only
+    k_group<SEMI_SUM, 3><<<g, kBlock, 0, s>>>(ops, start, nblk, n);
+    return;
+  }
   if (semi == SEMI_SUM) {
     if (phase == 0) k_group<SEMI_SUM, 0><<<g, kBlock, 0, s>>>(ops, start, nblk, n);
     else if (phase == 1) k_group<SEMI_SUM, 1><<<g, kBlock, 0, s>>>(ops, start, nblk, n);
@@ -560,6 +683,8 @@ void launch_group(int semi, int phase, const ContractArgs *ops, const uint32_t *
 }
 
 uint32_t map_blocks(const ContractArgs &a) {
+  if (a.kind == 2)  // one 64 x 64 tile per workgroup
+    return a.nB * ((a.nM + kGT - 1) / kGT) * ((a.nC + kGT - 1) / kGT);
   const uint32_t n_out = a.kind == 1 ? a.nR : a.nR * a.nC;
   uint32_t blocks = (n_out + kBlock - 1) / kBlock;
   return blocks > 2048u ? 2048u : blocks;
@@ -569,6 +694,10 @@ void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, co
                      void *stream) {
   hipStream_t s = (hipStream_t)stream;
   const uint32_t n_out = a.nR * a.nC;
+  if (a.kind == 2) {
+    k_gemm<<<dim3(map_blocks(a), nb), kBlock, 0, s>>>(d_a);
+    return;
+  }
   if (!split) {
     dim3 g(map_blocks(a), nb);  // grid-stride: at most about 8 blocks per CU
     if (semi == SEMI_SUM) {
@@ -758,7 +887,6 @@ __device__ __forceinline__ float seg_store(float *dst, const int32_t *off, const
 // with lane l holding A[l % 16][l / 16], B[l / 16][l % 16] and
 // D[4 (l / 16) + r][l % 16] in register r.  A workgroup's 32 x kSegOB output
 // is 2 x 8 tiles, one per wave: rows 16 (w % 2), columns 16 (w / 2).
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // D tile of the wave = A (its 16 rows x 32) * B (32 x its 16 columns of `b`)
 __device__ __forceinline__ f32x4 seg_mfma(const float (&av)[8], const float *b) {

@@ -39,6 +39,7 @@ struct Op {
   ContractArgs a;                     // pointers filled after allocation
   // table offsets into the host table store (-1 = unused)
   int64_t t_rX[2], t_rY[2], t_rZ[2], t_cY[2], t_cZ[2], t_sX[2], t_sY[2];
+  int64_t t_gbX[2], t_gbY[2], t_gbZ[2], t_gmX[2], t_gmZ[2];  // dense form
   double flops = 0, bytes = 0;        // algorithmic, per instance
   int64_t part_off = -1;              // partial-sum region of a split contraction
   ContractArgs *d_a = nullptr;        // device copy of `a`
@@ -75,6 +76,7 @@ struct SegPlan {
 struct Launch {
   int semi = SEMI_SUM;
   bool split = false;
+  bool gemm = false;                  // dense-form contractions (matrix cores)
   bool seg = false;                   // fused-segment kernels (carrier kinds alone)
   int seg_kind = 0;
   std::vector<int> ops;               // indices into the op list

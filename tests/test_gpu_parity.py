@@ -117,6 +117,32 @@ def test_batched_indicators_small(T):
     assert np.allclose(lz3, lz[:3], rtol=0, atol=1e-9)
 
 
+@pytest.mark.parametrize("seed", [0, 4])
+def test_dense_form_against_oracle(T, seed):
+    """Bayesian networks whose trees hold dense contractions (matrix-core
+    form), unbatched and with batched indicator evidence."""
+    bn = W.random_bn(200, seed)
+    P = T.Plan(T.Network(bn), semirings=T.SUM_PRODUCT)
+    assert P.info()["n_dense"] > 0
+    lz, m = P.marginals()
+    pairs, _ = P.tree()
+    lzo, marg, *_ = oracle.marginals(bn, pairs=pairs.astype(np.int64))
+    assert abs(lz[0] - lzo) <= 1e-5 * max(1.0, abs(lzo))
+    got = P.split_marginals(m[0])
+    assert max(np.abs(a - b).max() for a, b in zip(got, marg)) <= 1e-5
+    c = W.config(3, seed=seed, small=True)
+    bn, ev = c["net"], c["evidence"]
+    B = ev.shape[0]
+    P = T.Plan(T.Network(bn), evidence_mode=T.EVIDENCE_INDICATOR, max_batch=B, semirings=T.SUM_PRODUCT)
+    assert P.info()["n_dense"] > 0
+    lz, m = P.marginals(ev, batch=B)
+    for b in (0, B // 2, B - 1):
+        want_lz, want_m, *_ = oracle.marginals(bn, ev[b], mode="indicator")
+        assert rel(lz[b], want_lz) <= 1e-5, b
+        got = P.split_marginals(m[b])
+        assert max(np.abs(x - y).max() for x, y in zip(got, want_m)) <= 1e-5, b
+
+
 def test_grid20x20_full_size_against_oracle(T):
     ref = json.load(open(os.path.join(GOLDEN, "oracle_grid20x20_seed0.json")))
     net = W.grid_mrf(20, 20, 0)
