@@ -90,7 +90,12 @@ typedef struct {
   uint64_t seed;             /* planner tie-break seed */
   double max_log2_size;      /* slicing cap on log2(elements) of any
                                 intermediate; 0 = no slicing */
-  int32_t dtype;             /* tn_dtype of stored intermediates (sum-product) */
+  int32_t dtype;             /* tn_dtype of the matrix-core operands of the
+                                sum-product contractions (dense form and fused
+                                segments): TN_F32, or TN_BF16 / TN_F16 (operands
+                                rounded to nearest, FP32 accumulation).  Every
+                                stored tensor stays FP32 with its power-of-two
+                                scale; the other kernels compute in FP32. */
   int32_t max_batch;         /* mode INDICATOR: instances per call */
   int32_t use_graph;         /* capture each task's launches in a hipGraph */
   void *hip_stream;          /* borrowed hipStream_t; NULL = library-owned */

@@ -598,6 +598,7 @@ static void fill_args(tn_plan_t *p, Op &op) {
   a.batZ = Z.batched;
   a.part = p->d_part + (op.part_off >= 0 ? op.part_off : 0);
   a.parti = p->d_parti + (op.part_off >= 0 ? op.part_off : 0);
+  a.prec = a.kind == 2 ? p->opts.dtype : 0;
 }
 
 
@@ -1252,6 +1253,7 @@ static void upload_segments(tn_plan_t *p) {
       a.lists = p->d_tabs + sp.list_off;
       a.n_steps = (int32_t)sp.steps.size();
       a.list_len = sp.list_len;
+      a.prec = p->opts.dtype;
       a.mat_lds = sp.mat_lds;
       a.fin_lds = sp.fin_lds;
       a.M = p->T[sp.mt].off;
@@ -1293,7 +1295,7 @@ static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
   p->want_sum = (o->semiring_mask & TN_SUM_PRODUCT) != 0;
   p->want_max = (o->semiring_mask & TN_MAX_PLUS) != 0;
   p->want_grad = o->want_factor_grad != 0;
-  if (o->dtype != TN_F32) throw TnError(TN_E_UNSUPPORTED, "only FP32 storage is built in this version");
+  if (o->dtype < TN_F32 || o->dtype > TN_F16) throw TnError(TN_E_INVALID, "unknown dtype");
   p->is_obs.assign(p->n_vars, 0);
   if (p->mode == TN_EVIDENCE_SLICED) {
     for (int i = 0; i < o->n_observed; ++i) {

@@ -116,6 +116,7 @@ struct ContractArgs {
   int32_t x_s_fast = 0;     // X's stride-1 label is summed (else an M or batch label)
   int32_t y_n_fast = 0;     // Y's stride-1 label is a column label
   int32_t z_n_fast = 0;     // Z's stride-1 label is a column label
+  int32_t prec = 0;         // matrix-core operands: 0 FP32, 1 BF16, 2 FP16 (FP32 accumulation)
 };
 static constexpr int kGemmTile = 64;  // output tile edge of the dense form
 
@@ -191,6 +192,7 @@ struct SegArgs {
   int32_t in_outer_fast = 0;     // the input carrier's stride-1 label is an outer label
   int32_t out_outer_fast = 0;    // same for the output carrier
   int32_t mat_lds = 0, fin_lds = 0;  // floats of LDS of the sweep kernels
+  int32_t prec = 0;              // matrix-core operands: 0 FP32, 1 BF16, 2 FP16 (FP32 accumulation)
 };
 void launch_seg_fwd(const SegArgs &a, const SegArgs *d_a, void *stream);
 void launch_seg_bwd(const SegArgs &a, const SegArgs *d_a, void *stream);

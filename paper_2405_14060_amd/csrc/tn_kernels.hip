@@ -35,6 +35,30 @@ namespace tn {
 
 static constexpr int kBlock = 256;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16, round to nearest even (operands are finite)
+__device__ __forceinline__ short bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+// One 16 x 16 x 16 matrix-core step with operands rounded to BF16 (PREC 1)
+// or FP16 (PREC 2), FP32 accumulation: lane l supplies A[l % 16][4 (l / 16) + j]
+// and B[4 (l / 16) + j][l % 16], j = 0..3.
+template <int PREC>
+__device__ __forceinline__ f32x4 mfma16_lp(const float (&a)[4], const float (&b)[4], f32x4 c) {
+  if (PREC == 1) {
+    const bf16x4 av = {bf16_rne(a[0]), bf16_rne(a[1]), bf16_rne(a[2]), bf16_rne(a[3])};
+    const bf16x4 bv = {bf16_rne(b[0]), bf16_rne(b[1]), bf16_rne(b[2]), bf16_rne(b[3])};
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, c, 0, 0, 0);
+  } else {
+    const f16x4 av = {(_Float16)a[0], (_Float16)a[1], (_Float16)a[2], (_Float16)a[3]};
+    const f16x4 bv = {(_Float16)b[0], (_Float16)b[1], (_Float16)b[2], (_Float16)b[3]};
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(av, bv, c, 0, 0, 0);
+  }
+}
 
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
@@ -508,6 +532,7 @@ static constexpr int kGK = 16;          // summed entries per chunk
 static constexpr int kGKP = kGT + 16;   // chunk row pitch: conflict-free MFMA operand reads
 static constexpr int kGCP = kGT + 1;    // epilogue tile pitch
 
+template <int PREC>
 __device__ __forceinline__ void gemm_body(const ContractArgs &a, const int b, const uint32_t blk) {
   __shared__ int32_t oMX[kGT], oMZ[kGT], oNY[kGT], oNZ[kGT];
   __shared__ float As[kGK * kGKP], Bs[kGK * kGKP];
@@ -567,15 +592,31 @@ __device__ __forceinline__ void gemm_body(const ContractArgs &a, const int b, co
       Bs[db[q]] = vb[q] * sy;
     }
     __syncthreads();
+    if (PREC == 0) {
 #pragma unroll
-    for (int kk = 0; kk < kGK; kk += 4) {
-      const int r = (kk + (l >> 4)) * kGKP + (l & 15);
-      const float a0 = As[r + 32 * wm], a1 = As[r + 32 * wm + 16];
-      const float b0 = Bs[r + 32 * wn], b1 = Bs[r + 32 * wn + 16];
-      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+      for (int kk = 0; kk < kGK; kk += 4) {
+        const int r = (kk + (l >> 4)) * kGKP + (l & 15);
+        const float a0 = As[r + 32 * wm], a1 = As[r + 32 * wm + 16];
+        const float b0 = Bs[r + 32 * wn], b1 = Bs[r + 32 * wn + 16];
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+      }
+    } else {  // the whole chunk (16 summed entries) in one low-precision step
+      float a0[4], a1[4], b0[4], b1[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = (4 * (l >> 4) + j) * kGKP + (l & 15);
+        a0[j] = As[r + 32 * wm];
+        a1[j] = As[r + 32 * wm + 16];
+        b0[j] = Bs[r + 32 * wn];
+        b1[j] = Bs[r + 32 * wn + 16];
+      }
+      acc[0][0] = mfma16_lp<PREC>(a0, b0, acc[0][0]);
+      acc[0][1] = mfma16_lp<PREC>(a0, b1, acc[0][1]);
+      acc[1][0] = mfma16_lp<PREC>(a1, b0, acc[1][0]);
+      acc[1][1] = mfma16_lp<PREC>(a1, b1, acc[1][1]);
     }
     __syncthreads();
   }
@@ -605,8 +646,13 @@ __device__ __forceinline__ void gemm_body(const ContractArgs &a, const int b, co
     a.ex[a.slotZ + (a.batZ ? b : 0)] = a.ex[a.slotX + (a.batX ? b : 0)] + kx + a.ex[a.slotY + (a.batY ? b : 0)] + ky;
 }
 
+__device__ __forceinline__ void gemm_any(const ContractArgs &a, const int b, const uint32_t blk) {
+  if (a.prec == 1) gemm_body<1>(a, b, blk);
+  else if (a.prec == 2) gemm_body<2>(a, b, blk);
+  else gemm_body<0>(a, b, blk);
+}
 __global__ __launch_bounds__(kBlock) void k_gemm(const ContractArgs *__restrict__ ap) {
-  gemm_body(*ap, blockIdx.y, blockIdx.x);
+  gemm_any(*ap, blockIdx.y, blockIdx.x);
 }
 
 // Arguments live in device memory (a pointer is the only kernel argument):
@@ -655,7 +701,7 @@ __global__ __launch_bounds__(kBlock) void k_group(const ContractArgs *__restrict
     if (hy) split_body<SEMI, true>(a, b, blk);
     else split_body<SEMI, false>(a, b, blk);
   } else if (PHASE == 3) {
-    gemm_body(a, b, blk);
+    gemm_any(a, b, blk);
   } else {
     if (hy) finish_body<SEMI, true>(a, b, blk);
     else finish_body<SEMI, false>(a, b, blk);
@@ -806,18 +852,6 @@ __device__ __forceinline__ void seg_prologue(const SegArgs &a, uint32_t o0, bool
   }
 }
 
-// A operand for the wave's row half from the staged M:
-// av[q] = A[16 (w % 2) + l % 16][4q + l / 16] with A = M, or A = M^T when TRANS
-template <bool TRANS>
-__device__ __forceinline__ void seg_load_a(const SegShared &sh, float (&av)[8]) {
-  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int i = 16 * (w & 1) + (l & 15), k = 4 * q + (l >> 4);
-    av[q] = TRANS ? sh.m[k * (kSegMaxLocal + 1) + i] : sh.m[i * (kSegMaxLocal + 1) + k];
-  }
-}
-
 // Move a tile (kSegMaxLocal entries x kSegOB outer assignments) between a
 // carrier in global memory and LDS.  Consecutive threads take consecutive
 // addresses of the carrier: outer-fastest when the carrier's stride-1 label
@@ -888,13 +922,34 @@ __device__ __forceinline__ float seg_store(float *dst, const int32_t *off, const
 // D[4 (l / 16) + r][l % 16] in register r.  A workgroup's 32 x kSegOB output
 // is 2 x 8 tiles, one per wave: rows 16 (w % 2), columns 16 (w / 2).
 
-// D tile of the wave = A (its 16 rows x 32) * B (32 x its 16 columns of `b`)
-__device__ __forceinline__ f32x4 seg_mfma(const float (&av)[8], const float *b) {
+// D tile of the wave = A (its 16 rows x 32) * B (32 x its 16 columns of `b`);
+// the A operand comes from the staged M (transposed when TRANS)
+template <int PREC, bool TRANS>
+__device__ __forceinline__ f32x4 seg_mfma(const SegShared &sh, const float *b) {
   f32x4 acc = {};
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const float *bp = b + (l >> 4) * kSegRow + 16 * (w >> 1) + (l & 15);
+  const int i = 16 * (w & 1) + (l & 15);
+  const float *bp = b + 16 * (w >> 1) + (l & 15);
+  auto A = [&](int k) { return TRANS ? sh.m[k * (kSegMaxLocal + 1) + i] : sh.m[i * (kSegMaxLocal + 1) + k]; };
+  if (PREC == 0) {
 #pragma unroll
-  for (int q = 0; q < 8; ++q) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q], bp[4 * q * kSegRow], acc, 0, 0, 0);
+    for (int q = 0; q < 8; ++q) {
+      const int k = 4 * q + (l >> 4);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A(k), bp[k * kSegRow], acc, 0, 0, 0);
+    }
+  } else {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      float av[4], bv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = 16 * h + 4 * (l >> 4) + j;
+        av[j] = A(k);
+        bv[j] = bp[k * kSegRow];
+      }
+      acc = mfma16_lp<PREC>(av, bv, acc);
+    }
+  }
   return acc;
 }
 // write the wave's D tile into rows < n of a tile
@@ -909,6 +964,7 @@ __device__ __forceinline__ void seg_put(const f32x4 &d, int n, float *tile) {
 
 // Forward: C_L[:, o] = M C_0[:, o] for the workgroup's kSegOB outer
 // assignments (one 32-wide column block per wave).
+template <int PREC>
 __global__ __launch_bounds__(kSegThreads) void k_seg_fwd(const SegArgs *__restrict__ ap) {
   const SegArgs &a = *ap;
   __shared__ float tile[kSegMaxLocal * kSegRow];
@@ -919,10 +975,8 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_fwd(const SegArgs *__restri
   __syncthreads();
   const int kx = sh.kx;
   seg_load(a.arena + a.X, sh.offX, sh.locX, n_in, a.in_outer_fast, tile, ldexpf(1.f, -kx));
-  float av[8];
-  seg_load_a<false>(sh, av);
   __syncthreads();
-  const f32x4 d = seg_mfma(av, tile);
+  const f32x4 d = seg_mfma<PREC, false>(sh, tile);
   __syncthreads();
   seg_put(d, n_out, tile);
   __syncthreads();
@@ -934,6 +988,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_fwd(const SegArgs *__restri
 // Reverse: Cbar_0[:, o] = M^T Gbar[:, o], and the workgroup's partial of
 // S = sum_o Gbar[:, o] C_0[:, o]^T: wave w computes the 16 x 16 quadrant
 // w % 4 of S over the outer quarter w / 4; quarters are added in order.
+template <int PREC>
 __global__ __launch_bounds__(kSegThreads) void k_seg_bwd(const SegArgs *__restrict__ ap) {
   const SegArgs &a = *ap;
   __shared__ float tg[kSegMaxLocal * kSegRow];  // output adjoint; later the waves' S partials
@@ -948,19 +1003,31 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_bwd(const SegArgs *__restri
   const int kx = sh.kx, kg = sh.kg;
   seg_load(a.arena + a.G, sh.offZ, sh.locZ, n_out, a.out_outer_fast, tg, ldexpf(1.f, -kg));
   if (want_s) seg_load(a.arena + a.X, sh.offX, sh.locX, n_in, a.in_outer_fast, tx, ldexpf(1.f, -kx));
-  float av[8];  // A = M^T
-  seg_load_a<true>(sh, av);
   __syncthreads();
-  const f32x4 xb = seg_mfma(av, tg);
+  const f32x4 xb = seg_mfma<PREC, true>(sh, tg);  // A = M^T
   f32x4 s = {};
   if (want_s) {
     // S quadrant (rows 16 qr of Gbar's entries, columns 16 qc of C_0's) over
     // the outer quarter kq: A = Gbar (16 x 32 outer), B = C_0^T (32 outer x 16)
     const int qr = w & 1, qc = (w >> 1) & 1, kq = w >> 2;
-    const float *ga = tg + (16 * qr + (l & 15)) * kSegRow + 32 * kq + (l >> 4);
-    const float *xa = tx + (16 * qc + (l & 15)) * kSegRow + 32 * kq + (l >> 4);
+    const float *ga = tg + (16 * qr + (l & 15)) * kSegRow + 32 * kq;
+    const float *xa = tx + (16 * qc + (l & 15)) * kSegRow + 32 * kq;
+    if (PREC == 0) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) s = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[4 * q], xa[4 * q], s, 0, 0, 0);
+      for (int q = 0; q < 8; ++q)
+        s = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[4 * q + (l >> 4)], xa[4 * q + (l >> 4)], s, 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        float av[4], bv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          av[j] = ga[16 * h + 4 * (l >> 4) + j];
+          bv[j] = xa[16 * h + 4 * (l >> 4) + j];
+        }
+        s = mfma16_lp<PREC>(av, bv, s);
+      }
+    }
   }
   __syncthreads();
   seg_put(xb, n_in, tx);
@@ -1182,10 +1249,16 @@ __global__ __launch_bounds__(kSweepThreads) void k_seg_sred(const SegArgs *__res
 }
 
 void launch_seg_fwd(const SegArgs &a, const SegArgs *d_a, void *stream) {
-  k_seg_fwd<<<seg_blocks(a), kSegThreads, 0, (hipStream_t)stream>>>(d_a);
+  hipStream_t s = (hipStream_t)stream;
+  if (a.prec == 1) k_seg_fwd<1><<<seg_blocks(a), kSegThreads, 0, s>>>(d_a);
+  else if (a.prec == 2) k_seg_fwd<2><<<seg_blocks(a), kSegThreads, 0, s>>>(d_a);
+  else k_seg_fwd<0><<<seg_blocks(a), kSegThreads, 0, s>>>(d_a);
 }
 void launch_seg_bwd(const SegArgs &a, const SegArgs *d_a, void *stream) {
-  k_seg_bwd<<<seg_blocks(a), kSegThreads, 0, (hipStream_t)stream>>>(d_a);
+  hipStream_t s = (hipStream_t)stream;
+  if (a.prec == 1) k_seg_bwd<1><<<seg_blocks(a), kSegThreads, 0, s>>>(d_a);
+  else if (a.prec == 2) k_seg_bwd<2><<<seg_blocks(a), kSegThreads, 0, s>>>(d_a);
+  else k_seg_bwd<0><<<seg_blocks(a), kSegThreads, 0, s>>>(d_a);
 }
 void launch_seg_mat(const SegArgs *d_base, const int32_t *d_ids, int n, int lds_floats, void *stream) {
   k_seg_mat<<<n, kSweepThreads, (size_t)lds_floats * sizeof(float), (hipStream_t)stream>>>(d_base, d_ids);

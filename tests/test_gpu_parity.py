@@ -143,6 +143,37 @@ def test_dense_form_against_oracle(T, seed):
         assert max(np.abs(x - y).max() for x, y in zip(got, want_m)) <= 1e-5, b
 
 
+@pytest.mark.parametrize("dtype,tol_lz,tol_m", [("bf16", 1e-3, 5e-3), ("f16", 1e-3, 5e-3)])
+def test_low_precision_matrix_cores(T, dtype, tol_lz, tol_m):
+    """BF16 / FP16 operands on the matrix cores (FP32 accumulation, FP32
+    storage with power-of-two scales): fused segments (grid) and dense
+    contractions (batched BN), error against the FP64 oracle within the
+    stated bounds: |dlog Z| <= 1e-3 max(1, |log Z|), marginals max-abs."""
+    dt = dict(bf16=T.TN_BF16, f16=T.TN_F16)[dtype]
+    net = W.grid_mrf(12, 12, 1)
+    P = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, dtype=dt)
+    assert P.info()["n_segments"] > 0
+    lz, m = P.marginals()
+    pairs, _ = P.tree()
+    lzo, marg, *_ = oracle.marginals(net, pairs=pairs.astype(np.int64))
+    assert rel(lz[0], lzo) <= tol_lz
+    got = P.split_marginals(m[0])
+    err = max(np.abs(a - b).max() for a, b in zip(got, marg))
+    assert err <= tol_m, err
+    c = W.config(3, seed=0, small=True)
+    bn, ev = c["net"], c["evidence"]
+    B = ev.shape[0]
+    P = T.Plan(T.Network(bn), evidence_mode=T.EVIDENCE_INDICATOR, max_batch=B, semirings=T.SUM_PRODUCT,
+               dtype=dt)
+    assert P.info()["n_dense"] > 0
+    lz, m = P.marginals(ev, batch=B)
+    for b in (0, B - 1):
+        want_lz, want_m, *_ = oracle.marginals(bn, ev[b], mode="indicator")
+        assert rel(lz[b], want_lz) <= tol_lz, b
+        got = P.split_marginals(m[b])
+        assert max(np.abs(x - y).max() for x, y in zip(got, want_m)) <= tol_m, b
+
+
 def test_grid20x20_full_size_against_oracle(T):
     ref = json.load(open(os.path.join(GOLDEN, "oracle_grid20x20_seed0.json")))
     net = W.grid_mrf(20, 20, 0)
