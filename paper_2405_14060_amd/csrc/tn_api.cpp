@@ -1580,7 +1580,7 @@ void run_sched(tn_plan_t *p, const std::vector<Op> &ops, const Schedule &sc) {
       const Op &op = ops[L.ops[0]];
       launch_contract(op.semi, op.Y >= 0, op.split, op.a, op.d_a, op.nb, p->stream);
     } else if (L.gemm) {
-      launch_group(L.semi, 3, L.d_args, L.d_start, L.d_nblk, (int)L.ops.size(), L.total, p->stream);
+      launch_group(L.semi, 3 + p->opts.dtype, L.d_args, L.d_start, L.d_nblk, (int)L.ops.size(), L.total, p->stream);
     } else if (!L.split) {
       launch_group(L.semi, 0, L.d_args, L.d_start, L.d_nblk, (int)L.ops.size(), L.total, p->stream);
     } else {

@@ -127,7 +127,7 @@ void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, co
                      void *stream);
 // blocks per instance of a one-lane-per-output launch
 uint32_t map_blocks(const ContractArgs &a);
-// phase 0: map, 1: split partials, 2: split finish, 3: dense form
+// phase 0: map, 1: split partials, 2: split finish, 3 + p: dense form with operand precision p
 void launch_group(int semi, int phase, const ContractArgs *ops, const uint32_t *start,
                   const uint32_t *nblk, int n, uint32_t total_blocks, void *stream);
 

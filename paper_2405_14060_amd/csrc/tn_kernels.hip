@@ -646,13 +646,11 @@ __device__ __forceinline__ void gemm_body(const ContractArgs &a, const int b, co
     a.ex[a.slotZ + (a.batZ ? b : 0)] = a.ex[a.slotX + (a.batX ? b : 0)] + kx + a.ex[a.slotY + (a.batY ? b : 0)] + ky;
 }
 
-__device__ __forceinline__ void gemm_any(const ContractArgs &a, const int b, const uint32_t blk) {
-  if (a.prec == 1) gemm_body<1>(a, b, blk);
-  else if (a.prec == 2) gemm_body<2>(a, b, blk);
-  else gemm_body<0>(a, b, blk);
-}
+// one kernel per operand precision (a runtime switch inside one kernel would
+// size its registers for the largest variant)
+template <int PREC>
 __global__ __launch_bounds__(kBlock) void k_gemm(const ContractArgs *__restrict__ ap) {
-  gemm_any(*ap, blockIdx.y, blockIdx.x);
+  gemm_body<PREC>(*ap, blockIdx.y, blockIdx.x);
 }
 
 // Arguments live in device memory (a pointer is the only kernel argument):
@@ -700,8 +698,8 @@ __global__ __launch_bounds__(kBlock) void k_group(const ContractArgs *__restrict
   } else if (PHASE == 1) {
     if (hy) split_body<SEMI, true>(a, b, blk);
     else split_body<SEMI, false>(a, b, blk);
-  } else if (PHASE == 3) {
-    gemm_any(a, b, blk);
+  } else if (PHASE >= 3) {  // dense form, operand precision PHASE - 3
+    gemm_body<PHASE - 3>(a, b, blk);
   } else {
     if (hy) finish_body<SEMI, true>(a, b, blk);
     else finish_body<SEMI, false>(a, b, blk);
@@ -713,8 +711,10 @@ void launch_group(int semi, int phase, const ContractArgs *ops, const uint32_t *
   if (n <= 0 || total_blocks == 0) return;
   hipStream_t s = (hipStream_t)stream;
   dim3 g(total_blocks);
-  if (phase == 3) {  // dense form: sum-product only
-    k_group<SEMI_SUM, 3><<<g, kBlock, 0, s>>>(ops, start, nblk, n);
+  if (phase >= 3) {  // dense form (sum-product), operand precision phase - 3
+    if (phase == 4) k_group<SEMI_SUM, 4><<<g, kBlock, 0, s>>>(ops, start, nblk, n);
+    else if (phase == 5) k_group<SEMI_SUM, 5><<<g, kBlock, 0, s>>>(ops, start, nblk, n);
+    else k_group<SEMI_SUM, 3><<<g, kBlock, 0, s>>>(ops, start, nblk, n);
     return;
   }
   if (semi == SEMI_SUM) {
@@ -741,7 +741,10 @@ void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, co
   hipStream_t s = (hipStream_t)stream;
   const uint32_t n_out = a.nR * a.nC;
   if (a.kind == 2) {
-    k_gemm<<<dim3(map_blocks(a), nb), kBlock, 0, s>>>(d_a);
+    const dim3 g(map_blocks(a), nb);
+    if (a.prec == 1) k_gemm<1><<<g, kBlock, 0, s>>>(d_a);
+    else if (a.prec == 2) k_gemm<2><<<g, kBlock, 0, s>>>(d_a);
+    else k_gemm<0><<<g, kBlock, 0, s>>>(d_a);
     return;
   }
   if (!split) {
