@@ -131,6 +131,7 @@ typedef struct {
   int32_t n_segments;            /* fused chain segments */
   int32_t n_fused_nodes;         /* tree nodes inside fused segments */
   int32_t n_dense;               /* contractions (forward and reverse) in the dense matrix-core form */
+  int32_t n_wave;                /* contractions in the wave-per-output form (all passes, both semirings) */
 } tn_plan_info;
 
 /* Fill *o with defaults: sum-product + max-plus, no evidence, best planner,

@@ -272,11 +272,12 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
     p->part_floats += ((int64_t)op.nb * a.n_chunks * n_out + 63) / 64 * 64;
   }
   // dense form on the matrix cores: sum-product with wide row and column
-  // sets and a summed set of at least one MFMA step
+  // sets and a summed set of at least 8 entries, or none (an outer product:
+  // its tiles still leave through LDS in the order of Z's layout)
   if (!op.split && semi == SEMI_SUM && Y >= 0) {
     const Labels Bl = inter(R, LY), Ml = minus(R, LY);
     const int64_t nB = numel(Bl, card), nM = numel(Ml, card);
-    if (nM >= 16 && a.nC >= 8 && a.nS >= 8 && nB * ((nM + kGemmTile - 1) / kGemmTile) *
+    if (nM >= 16 && a.nC >= 8 && (a.nS >= 8 || a.nS == 1) && nB * ((nM + kGemmTile - 1) / kGemmTile) *
                                                       (((int64_t)a.nC + kGemmTile - 1) / kGemmTile) < (1LL << 31)) {
       a.kind = 2;
       const size_t bs = lo_split(Bl, card), ms = lo_split(Ml, card);
@@ -294,6 +295,8 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
       a.z_n_fast = (!LZ.empty() && has(C, LZ.back())) ? 1 : 0;
     }
   }
+  // wave form: long sums over many outputs (one wavefront per output)
+  if (!op.split && a.kind == 0 && a.nS >= 64) a.kind = 3;
   // row form for skinny contractions: few summed entries and columns
   if (!op.split && a.kind == 0 && a.nS <= (uint32_t)kRowMax && a.nC <= (uint32_t)kRowMax && a.nS * a.nC <= 64) {
     a.kind = 1;
@@ -1493,10 +1496,16 @@ extern "C" tn_status tn_plan_info_get(const tn_plan_t *p, tn_plan_info *info) {
     }
     info->n_segments = (int32_t)p->segs.size();
     for (const auto &sp : p->segs) info->n_fused_nodes += (int32_t)sp.ops.size();
-    for (const auto *L : {&p->sum_tree.ops, &p->bwd, &p->qtree.ops})
-      for (const Op &op : *L) info->n_dense += op.a.kind == 2 ? 1 : 0;
+    for (const auto *L : {&p->sum_tree.ops, &p->bwd, &p->qtree.ops, &p->max_tree.ops})
+      for (const Op &op : *L) {
+        info->n_dense += op.a.kind == 2 ? 1 : 0;
+        info->n_wave += op.a.kind == 3 ? 1 : 0;
+      }
     for (const auto &g : p->groups)
-      for (const Op &op : g.ops) info->n_dense += op.a.kind == 2 ? 1 : 0;
+      for (const Op &op : g.ops) {
+        info->n_dense += op.a.kind == 2 ? 1 : 0;
+        info->n_wave += op.a.kind == 3 ? 1 : 0;
+      }
   });
 }
 

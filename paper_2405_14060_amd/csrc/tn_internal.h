@@ -102,7 +102,7 @@ struct ContractArgs {
   // row form (kind 1): one lane per row, all summed entries and columns in
   // registers; offsets of the summed entries in X, Y and of the columns in
   // Y, Z, in canonical order
-  int32_t kind = 0;  // 0 generic, 1 row form, 2 dense matrix-core form
+  int32_t kind = 0;  // 0 generic, 1 row form, 2 dense matrix-core form, 3 wave per output
   int32_t ns = 0, nc = 0;
   int32_t rl_shift = -1;  // log2(nRl) when nRl is a power of two
   int32_t sx[kRowMax], sy[kRowMax], cy[kRowMax], cz[kRowMax];

@@ -506,12 +506,109 @@ __device__ __forceinline__ void rows_body(const ContractArgs &a, const int b, co
   }
 }
 
+// --------------------------------------------------------------------------
+// wave form (kind 3): one wavefront per output element, the lanes striding
+// over the summed index (consecutive lanes on consecutive summed entries,
+// so the stride-1 summed label of X is read coalesced), combined with
+// wavefront shuffles.  Max-plus keeps (value, index) pairs: the larger
+// value wins, equal values keep the smaller index, so the result is the
+// first maximiser in canonical order whatever the lane that found it.
+// --------------------------------------------------------------------------
+static constexpr int kWaveOuts = kBlock / 64;  // outputs per workgroup pass
+
+template <int SEMI, bool HASY>
+__device__ __forceinline__ void wave_body(const ContractArgs &a, const int b, const uint32_t blk,
+                                          const uint32_t nblk) {
+  const float *__restrict__ X = a.X + (int64_t)b * a.bsX;
+  const float *__restrict__ Y = HASY ? a.Y + (int64_t)b * a.bsY : nullptr;
+  float *__restrict__ Z = a.Z + (int64_t)b * a.bsZ;
+  int32_t *__restrict__ I = SEMI == SEMI_MAX ? a.I + (int64_t)b * a.bsZ : nullptr;
+  float sx = 1.f, sy = 1.f;
+  int kx = 0, ky = 0;
+  if (SEMI == SEMI_SUM) {
+    kx = max_exponent(read_max(a.mx, a.mx_stride, a.slotX + (a.batX ? b : 0)));
+    sx = ldexpf(1.f, -kx);
+    if (HASY) {
+      ky = max_exponent(read_max(a.mx, a.mx_stride, a.slotY + (a.batY ? b : 0)));
+      sy = ldexpf(1.f, -ky);
+    }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const uint32_t n_out = a.nR * a.nC, nS = a.nS, nSl = a.nSl;
+  float lmax = 0.f;
+  for (uint32_t o = blk * kWaveOuts + wid; o < n_out; o += nblk * kWaveOuts) {
+    uint32_t r, c;
+    if (a.col_fastest) {
+      r = o / a.nC;
+      c = o - r * a.nC;
+    } else {
+      c = o / a.nR;
+      r = o - c * a.nR;
+    }
+    const int32_t xo = tab_off(a.rX, r, a.nRl);
+    int32_t zo = tab_off(a.rZ, r, a.nRl);
+    int32_t yo = HASY ? tab_off(a.rY, r, a.nRl) : 0;
+    if (a.nC > 1) {
+      zo += tab_off(a.cZ, c, a.nCl);
+      if (HASY) yo += tab_off(a.cY, c, a.nCl);
+    }
+    if (SEMI == SEMI_SUM) {
+      float acc = 0.f;
+      for (uint32_t sidx = lane; sidx < nS; sidx += 64) {
+        const uint32_t sh = sidx / nSl, sl = sidx - sh * nSl;
+        const float xv = X[xo + a.sX.hi[sh] + a.sX.lo[sl]] * sx;
+        acc = HASY ? fmaf(xv, Y[yo + a.sY.hi[sh] + a.sY.lo[sl]] * sy, acc) : acc + xv;
+      }
+      acc = wave_sum(acc);
+      if (lane == 0) {
+        Z[zo] = acc;
+        lmax = fmaxf(lmax, acc);
+      }
+    } else {
+      float best = -INFINITY;
+      int32_t bi = 0x7fffffff;
+      for (uint32_t sidx = lane; sidx < nS; sidx += 64) {
+        const uint32_t sh = sidx / nSl, sl = sidx - sh * nSl;
+        float v = X[xo + a.sX.hi[sh] + a.sX.lo[sl]];
+        if (HASY) v = v + Y[yo + a.sY.hi[sh] + a.sY.lo[sl]];
+        if (bi == 0x7fffffff || v > best) {  // first candidate of the lane, or strictly larger
+          best = v;
+          bi = (int32_t)sidx;
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const float ov = __shfl_xor(best, off, 64);
+        const int32_t oi = __shfl_xor(bi, off, 64);
+        if (oi != 0x7fffffff && (bi == 0x7fffffff || ov > best || (ov == best && oi < bi))) {
+          best = ov;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        Z[zo] = best;
+        I[zo] = bi;
+      }
+    }
+  }
+  if (SEMI == SEMI_SUM) {
+    block_record_max(lmax, a.mx + (blk % kMaxSub) * a.mx_stride + a.slotZ + (a.batZ ? b : 0));
+    if (blk == 0 && threadIdx.x == 0) {
+      int e = a.ex[a.slotX + (a.batX ? b : 0)] + kx;
+      if (HASY) e += a.ex[a.slotY + (a.batY ? b : 0)] + ky;
+      a.ex[a.slotZ + (a.batZ ? b : 0)] = e;
+    }
+  }
+}
+
 template <int SEMI, bool HASY>
 __device__ __forceinline__ void any_map_body(const ContractArgs &a, const int b, const uint32_t blk,
                                              const uint32_t nblk) {
   if (a.kind == 1) {
     if (a.ns <= 4 && a.nc <= 4) rows_body<SEMI, HASY, 4>(a, b, blk, nblk);
     else rows_body<SEMI, HASY, kRowMax>(a, b, blk, nblk);
+  } else if (a.kind == 3) {
+    wave_body<SEMI, HASY>(a, b, blk, nblk);
   } else {
     map_body<SEMI, HASY>(a, b, blk, nblk);
   }
@@ -732,6 +829,10 @@ uint32_t map_blocks(const ContractArgs &a) {
   if (a.kind == 2)  // one 64 x 64 tile per workgroup
     return a.nB * ((a.nM + kGT - 1) / kGT) * ((a.nC + kGT - 1) / kGT);
   const uint32_t n_out = a.kind == 1 ? a.nR : a.nR * a.nC;
+  if (a.kind == 3) {  // kWaveOuts outputs per workgroup pass
+    const uint32_t blocks = (n_out + kWaveOuts - 1) / kWaveOuts;
+    return blocks > 4096u ? 4096u : blocks;
+  }
   uint32_t blocks = (n_out + kBlock - 1) / kBlock;
   return blocks > 2048u ? 2048u : blocks;
 }
