@@ -1,19 +1,29 @@
 #!/usr/bin/env python
-"""Benchmark of the hot path: log Z + all single-variable marginals.
+"""Benchmark of the hot path (one GPU).
 
-Workload: the 20x20 binary grid MRF (400 variables, 400 unary + 760 pairwise
-Gaussian log-potential tables, seed 0), contracted along the library's
-planned tree (bucket elimination, largest intermediate 2^20 elements).  One
-step = one call of tn_marginals: leaf preparation, the forward sum-product
-over the tree, the reverse pass (two adjoint contractions per node) and the
-marginal normalisation, results copied back to the host.  Factor tables are
-resident in device memory before the timed region.
+Default workload (the metric's configuration): the 20x20 binary grid MRF
+(400 variables, 400 unary + 760 pairwise Gaussian log-potential tables,
+seed 0), contracted along the library's planned tree (bucket elimination,
+largest intermediate 2^20 elements).  One step = one call of tn_marginals:
+leaf preparation, the forward sum-product over the tree, the reverse pass and
+the marginal normalisation, results copied back to the host.  Factor tables
+are resident in device memory before the timed region.
 
-Prints one JSON line; see the design doc for the meaning of every field.
+Other workloads (--workload), each printed as the same kind of JSON line:
+  bn500x512   500-variable Bayesian network, 512 evidence sets in one batched
+              indicator pass (log Z + all marginals of every instance); the
+              plain FP32 per-instance form is timed beside it
+  bn300_map   300-variable Bayesian network, 30 observed: MAP (max-plus
+              contraction + argmax readout), checked bit for bit against the
+              oracle's FP32 emulation
+  grid20_map  MAP on the 20x20 grid (max-plus at the size of the sum-product
+              workload)
+
+Prints one JSON line.
 """
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -28,12 +38,22 @@ KIND_NAMES = {0: "contract_map_sum", 1: "contract_map_max", 2: "contract_split_s
               3: "contract_split_max", 4: "prepare", 5: "other", 6: "seg_carrier_fwd",
               7: "seg_carrier_bwd", 8: "seg_maps", 9: "seg_adjoint_sweeps", 10: "contract_mfma_sum"}
 
+# HBM bytes per launch of a kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# counter runs (scaled by the counts of a plain 256 MiB copy), valid only for
+# the kernel source they were taken from (sha256 prefix of tn_kernels.hip):
+# {(kernel, workload): {"src": sha, "bytes": B}}
+MEASURED_TRAFFIC = {}
+
+
+def kernel_src_sha():
+    with open(os.path.join(ROOT, "paper_2405_14060_amd", "csrc", "tn_kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
 
 def kernel_summary(prof):
-    names = KIND_NAMES
     agg = {}
     for kind, fl, by, ms in prof:
-        a = agg.setdefault(names[kind], dict(n=0, flops=0.0, bytes=0.0, ms=0.0))
+        a = agg.setdefault(KIND_NAMES[kind], dict(n=0, flops=0.0, bytes=0.0, ms=0.0))
         a["n"] += 1
         a["flops"] += fl
         a["bytes"] += by
@@ -41,17 +61,150 @@ def kernel_summary(prof):
     return agg
 
 
-def cpu_baseline(net, budget_s=40.0):
-    """The FP64 oracle on one solve of the same workload (log Z + marginals)."""
-    import oracle
-    lv = oracle.build_leaves(net)
-    pairs = oracle.elimination_tree(lv.labels, lv.card, list(range(net.n_vars)))
+def roofline(plan, task, workload, evidence=None, batch=1):
+    """Dominant kernel kind of one task by executed time; its launches timed
+    back to back between two HIP events on the plan's stream."""
+    prof = plan.profile(task, reps=3, evidence=evidence, batch=batch)
+    agg = kernel_summary(prof)
+    flops_task = sum(fl for _, fl, _, _ in prof)
+    dom_name, _ = max(agg.items(), key=lambda kv: kv[1]["ms"])
+    kind_of = {v: k for k, v in KIND_NAMES.items()}
+    avg_ms, fl_launch, by_launch, n_launch = plan.profile_kind(task, kind_of[dom_name], reps=5,
+                                                               evidence=evidence, batch=batch)
+    achieved_gbs = by_launch / (avg_ms * 1e-3) / 1e9
+    achieved_tf = fl_launch / (avg_ms * 1e-3) / 1e12
+    hbm_frac = achieved_gbs / HBM_PEAK_GBS
+    mfma_frac = achieved_tf / FP32_PEAK_TFLOPS
+    meas = MEASURED_TRAFFIC.get((dom_name, workload))
+    traffic = meas["bytes"] if meas and meas["src"] == kernel_src_sha() else None
+    if hbm_frac >= mfma_frac:
+        roof = dict(bound="hbm", achieved=round(achieved_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(hbm_frac, 4), traffic=traffic)
+    else:
+        roof = dict(bound="mfma", achieved=round(achieved_tf, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(mfma_frac, 4), traffic=traffic)
+    roof.update(kernel=dom_name, launches_per_solve=n_launch, avg_launch_us=round(avg_ms * 1e3, 3),
+                bytes_per_launch=round(by_launch), flops_per_launch=round(fl_launch))
+    kernels = {k: dict(n=v["n"], ms=round(v["ms"], 4)) for k, v in agg.items()}
+    return roof, kernels, flops_task
+
+
+def timed(fn, steps, warmup, sync):
+    for _ in range(warmup):
+        fn()
+    sync()
     t0 = time.perf_counter()
-    lz, marg, *_ = oracle.marginals(net, pairs=pairs)
-    dt = time.perf_counter() - t0
-    return dict(value=1.0 / dt, unit="solves/s", cores=1, kind="oracle",
-                sample="one full solve (log Z + all 400 marginals) of the same 20x20 grid, "
-                       "single-threaded FP64 loop nests, %.1f s" % dt), lz, marg
+    for _ in range(steps):
+        out = fn()
+    sync()
+    return (time.perf_counter() - t0) / steps, out
+
+
+def bench_grid20(args, T, W, np, sync):
+    net = W.grid_mrf(20, 20, 0)
+    dt = dict(f32=T.TN_F32, bf16=T.TN_BF16, f16=T.TN_F16)[args.dtype]
+    plan = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, use_graph=not args.no_graph, dtype=dt)
+    info = plan.info()
+    sec, (lz, m) = timed(plan.marginals, args.steps, args.warmup, lambda: (plan.sync(), sync()))
+    roof, kernels, flops = roofline(plan, 1, "grid20x20")
+    out = dict(value=round(1.0 / sec, 3), unit="solves/s", ms_per_step=round(sec * 1e3, 4),
+               dtype=args.dtype,
+               config=dict(workload="grid20x20_mrf logZ+all-marginals", seed=0, n_vars=400, n_factors=1160,
+                           tree_sc_log2=info["sc"], tree_tc_log2=round(info["tc"], 3),
+                           segments=info["n_segments"], launches_per_solve=info["n_launches_fwd"] +
+                           info["n_launches_bwd"] + 3, graph=not args.no_graph),
+               tflops=round(flops / sec / 1e12, 4), log_z=float(lz[0]), roofline=roof, kernels=kernels)
+    if not args.no_cpu_baseline:
+        import oracle
+        lv = oracle.build_leaves(net)
+        pairs = oracle.elimination_tree(lv.labels, lv.card, list(range(net.n_vars)))
+        t0 = time.perf_counter()
+        lz_o, marg_o, *_ = oracle.marginals(net, pairs=pairs)
+        d = time.perf_counter() - t0
+        out["cpu_baseline"] = dict(value=1.0 / d, unit="solves/s", cores=1, kind="oracle",
+                                   sample="one full solve (log Z + all 400 marginals) of the same 20x20 grid, "
+                                          "single-threaded FP64 loop nests, %.1f s" % d)
+        got = plan.split_marginals(m[0])
+        out["err_vs_oracle"] = dict(log_z_rel=abs(float(lz[0]) - lz_o) / abs(lz_o),
+                                    marginal_max_abs=float(max(np.abs(a - b).max() for a, b in zip(got, marg_o))))
+        out["speedup_vs_cpu_oracle"] = round(out["value"] / out["cpu_baseline"]["value"], 1)
+    return out
+
+
+def bench_bn500x512(args, T, W, np, sync):
+    c = W.config(3, 0)
+    net, ev = c["net"], c["evidence"]
+    B = ev.shape[0]
+    dt = dict(f32=T.TN_F32, bf16=T.TN_BF16, f16=T.TN_F16)[args.dtype]
+    plan = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, evidence_mode=T.EVIDENCE_INDICATOR, max_batch=B,
+                  use_graph=not args.no_graph, dtype=dt)
+    info = plan.info()
+    sec, (lz, m) = timed(lambda: plan.marginals(ev, batch=B), args.steps, args.warmup,
+                         lambda: (plan.sync(), sync()))
+    roof, kernels, flops = roofline(plan, 1, "bn500x512", evidence=ev, batch=B)
+    # the plain FP32 per-instance form: one instance per call, no batching
+    one = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, evidence_mode=T.EVIDENCE_INDICATOR, max_batch=1,
+                 use_graph=not args.no_graph)
+    n1 = 32
+    sec1, _ = timed(lambda: [one.marginals(ev[b:b + 1], batch=1) for b in range(n1)], 1, 1,
+                    lambda: (one.sync(), sync()))
+    lz1 = np.array([one.marginals(ev[b:b + 1], batch=1)[0][0] for b in range(4)])
+    out = dict(value=round(B / sec, 1), unit="instance-solves/s", ms_per_step=round(sec * 1e3, 4),
+               dtype=args.dtype,
+               config=dict(workload="bn500 x 512 evidence sets, logZ+all-marginals, batched indicator pass",
+                           seed=0, n_vars=500, batch=B, tree_sc_log2=round(info["sc"], 3),
+                           tree_tc_log2=round(info["tc"], 3), dense_nodes=info["n_dense"],
+                           wave_nodes=info["n_wave"], graph=not args.no_graph),
+               tflops=round(flops / sec / 1e12, 4), roofline=roof, kernels=kernels,
+               per_instance_fp32=dict(value=round(n1 / sec1, 2), unit="instance-solves/s",
+                                      max_log_z_diff_vs_batched=float(np.abs(lz1 - lz[:4]).max())))
+    if not args.no_cpu_baseline:
+        import oracle
+        n_o, t0 = 0, time.perf_counter()
+        errs = []
+        while n_o < 64 and time.perf_counter() - t0 < 20.0:
+            lz_o, marg_o, *_ = oracle.marginals(net, ev[n_o], mode="indicator")
+            got = plan.split_marginals(m[n_o])
+            errs.append((abs(lz[n_o] - lz_o) / max(1.0, abs(lz_o)),
+                         max(np.abs(a - b).max() for a, b in zip(got, marg_o))))
+            n_o += 1
+        d = time.perf_counter() - t0
+        out["cpu_baseline"] = dict(value=n_o / d, unit="instance-solves/s", cores=1, kind="oracle",
+                                   sample="first %d of the 512 evidence sets, single-threaded FP64, %.1f s" % (n_o, d))
+        out["err_vs_oracle"] = dict(log_z_rel=float(max(e[0] for e in errs)),
+                                    marginal_max_abs=float(max(e[1] for e in errs)), instances=n_o)
+    return out
+
+
+def bench_map(args, T, W, np, sync, which):
+    if which == "bn300_map":
+        c = W.config(2, 0)
+        net, obs, ev = c["net"], c["observed"], c["evidence"]
+        plan = T.Plan(T.Network(net), semirings=T.MAX_PLUS, evidence_mode=T.EVIDENCE_SLICED, observed=obs,
+                      use_graph=not args.no_graph)
+        evb = ev.reshape(1, -1)
+        wl = "bn300 MAP, 30 observed (max-plus + argmax readout)"
+    else:
+        net, ev, evb = W.grid_mrf(20, 20, 0), None, None
+        plan = T.Plan(T.Network(net), semirings=T.MAX_PLUS, use_graph=not args.no_graph)
+        wl = "grid20x20 MAP (max-plus + argmax readout)"
+    info = plan.info()
+    sec, (lp, x) = timed(lambda: plan.map(evb), args.steps, args.warmup, lambda: (plan.sync(), sync()))
+    roof, kernels, flops = roofline(plan, 2, which, evidence=evb)
+    out = dict(value=round(1.0 / sec, 3), unit="MAP solves/s", ms_per_step=round(sec * 1e3, 4), dtype="f32",
+               config=dict(workload=wl, seed=0, n_vars=int(net.n_vars), tree_sc_log2=round(info["sc"], 3),
+                           tree_tc_log2=round(info["tc"], 3), graph=not args.no_graph),
+               tflops=round(flops / sec / 1e12, 4), log_p=float(lp[0]), roofline=roof, kernels=kernels)
+    if not args.no_cpu_baseline:
+        import oracle
+        pairs, _ = plan.tree()
+        t0 = time.perf_counter()
+        val, asg = oracle.map_assignment(net, ev, pairs=pairs.astype(np.int64), fp32=True)
+        d = time.perf_counter() - t0
+        out["cpu_baseline"] = dict(value=1.0 / d, unit="MAP solves/s", cores=1, kind="oracle",
+                                   sample="one MAP solve on the plan's tree, FP32-emulating loops, %.1f s" % d)
+        out["bit_exact_vs_oracle_fp32"] = bool(np.array_equal(np.asarray(asg), x[0]) and np.float32(val) == np.float32(lp[0]))
+    return out
 
 
 def main():
@@ -59,6 +212,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="grid20", choices=["grid20", "bn500x512", "bn300_map", "grid20_map"])
+    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"],
+                    help="matrix-core operand precision of the sum-product workloads")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -76,67 +232,17 @@ def main():
     from paper_2405_14060_amd import workloads as W
 
     torch.cuda.set_device(0)
-    net = W.grid_mrf(20, 20, 0)
-    plan = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, use_graph=not args.no_graph)
-    info = plan.info()
-
-    for _ in range(args.warmup):
-        plan.marginals()
-    plan.sync()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        lz, m = plan.marginals()
-    plan.sync()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_per_step = dt / args.steps * 1e3
-    solves_per_s = args.steps / dt
-
-    # per-launch times (HIP events on the plan's stream) for the roofline
-    prof = plan.profile(1, reps=3)
-    agg = kernel_summary(prof)
-    flops_solve = sum(fl for _, fl, _, _ in prof)
-    dom_name, dom = max(agg.items(), key=lambda kv: kv[1]["ms"])
-    kind_of = {v: k for k, v in KIND_NAMES.items()}
-    # the dominant kernel's launches timed back to back between two events
-    avg_ms, fl_launch, by_launch, n_launch = plan.profile_kind(1, kind_of[dom_name], reps=5)
-    achieved_gbs = by_launch / (avg_ms * 1e-3) / 1e9
-    achieved_tf = fl_launch / (avg_ms * 1e-3) / 1e12
-    hbm_frac = achieved_gbs / HBM_PEAK_GBS
-    mfma_frac = achieved_tf / FP32_PEAK_TFLOPS
-    if hbm_frac >= mfma_frac:
-        roof = dict(bound="hbm", achieved=round(achieved_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(hbm_frac, 4), traffic=None)
+    sync = torch.cuda.synchronize
+    if args.workload == "grid20":
+        res = bench_grid20(args, T, W, np, sync)
+    elif args.workload == "bn500x512":
+        res = bench_bn500x512(args, T, W, np, sync)
     else:
-        roof = dict(bound="mfma", achieved=round(achieved_tf, 3), peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(mfma_frac, 4), traffic=None)
-    roof["kernel"] = dom_name
-    roof["launches_per_solve"] = n_launch
-    roof["avg_launch_us"] = round(avg_ms * 1e3, 3)
-    roof["bytes_per_launch"] = round(by_launch)
-    roof["flops_per_launch"] = round(fl_launch)
-
-    out = dict(metric=METRIC, value=round(solves_per_s, 3), unit="solves/s", n_gpus=1,
-               steps=args.steps, warmup=args.warmup, ms_per_step=round(ms_per_step, 4),
-               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
-               data="synthetic",
-               config=dict(workload="grid20x20_mrf logZ+all-marginals", seed=0, n_vars=400,
-                           n_factors=1160, tree_sc_log2=info["sc"], tree_tc_log2=round(info["tc"], 3),
-                           kernels_per_solve=len(prof),
-                           launches_per_solve=info["n_launches_fwd"] + info["n_launches_bwd"] + 3,
-                           graph=not args.no_graph),
-               tflops=round(flops_solve / (ms_per_step * 1e-3) / 1e12, 4),
-               log_z=float(lz[0]), roofline=roof,
-               kernels={k: dict(n=v["n"], ms=round(v["ms"], 4)) for k, v in agg.items()})
-    if not args.no_cpu_baseline:
-        cb, lz_o, marg_o = cpu_baseline(net)
-        out["cpu_baseline"] = cb
-        got = plan.split_marginals(m[0])
-        out["err_vs_oracle"] = dict(
-            log_z_rel=abs(float(lz[0]) - lz_o) / abs(lz_o),
-            marginal_max_abs=float(max(np.abs(a - b).max() for a, b in zip(got, marg_o))))
-        out["speedup_vs_cpu_oracle"] = round(solves_per_s / cb["value"], 1)
+        res = bench_map(args, T, W, np, sync, args.workload)
+    out = dict(metric=METRIC, value=res.pop("value"), unit=res.pop("unit"), n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=res.pop("ms_per_step"), higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype=res.pop("dtype"), data="synthetic", config=res.pop("config"))
+    out.update(res)
     if args.copy_probe:
         # 256 MiB source, then 2 GiB of other writes so the source is not
         # cache resident, then copies: each reads and writes 256 MiB
@@ -144,11 +250,11 @@ def main():
         y = torch.empty_like(x)
         flush = torch.empty(512 << 20, dtype=torch.float32, device="cuda")
         flush.fill_(2.0)
-        torch.cuda.synchronize()
+        sync()
         for _ in range(3):
             y.copy_(x)
             flush.fill_(3.0)
-        torch.cuda.synchronize()
+        sync()
         del flush
         out["copy_probe_bytes"] = 2 * x.numel() * 4
     print(json.dumps(out), flush=True)
