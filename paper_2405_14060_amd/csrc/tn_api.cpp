@@ -484,6 +484,28 @@ static void build_backtrack(tn_plan_t *p, TreeExec &t) {
     add_step(t.ops[ids.back()]);
     for (size_t k = 0; k + 1 < ids.size(); ++k) add_step(t.ops[ids[k]]);
   }
+  // Readout levels: a step needs the variables of its node's output, which
+  // earlier steps assign; level = 1 + the largest level among the steps that
+  // assigned them.  Steps of one level read only lower levels and write
+  // disjoint variables, so each level runs in parallel.
+  std::vector<int> lev_of_var(p->n_vars, -1), lev(t.back.size());
+  int n_lev = 0;
+  for (size_t i = 0; i < t.back.size(); ++i) {
+    const BackStep &s = t.back[i];
+    int l = 0;
+    for (int k = s.in_begin; k < s.in_end; ++k) l = std::max(l, lev_of_var[t.back_meta[2 * k]] + 1);
+    for (int k = s.out_begin; k < s.out_end; ++k) lev_of_var[t.back_meta[2 * k]] = l;
+    lev[i] = l;
+    n_lev = std::max(n_lev, l + 1);
+  }
+  std::vector<BackStep> sorted;
+  t.back_lev.assign(1, 0);
+  for (int l = 0; l < n_lev; ++l) {
+    for (size_t i = 0; i < t.back.size(); ++i)
+      if (lev[i] == l) sorted.push_back(t.back[i]);
+    t.back_lev.push_back((int32_t)sorted.size());
+  }
+  t.back = std::move(sorted);
 }
 
 static void build_sampling(tn_plan_t *p, const TreeExec &t) {
@@ -917,6 +939,8 @@ static void allocate(tn_plan_t *p, const tn_net *net) {
   fix_back(p->qtree);
   p->d_back = dupload(p, p->max_tree.back);
   p->d_back_meta = dupload(p, p->max_tree.back_meta);
+  p->d_back_lev = dupload(p, p->max_tree.back_lev);
+  p->d_qback_lev = dupload(p, p->qtree.back_lev);
   p->d_qback = dupload(p, p->qtree.back);
   p->d_qback_meta = dupload(p, p->qtree.back_meta);
   for (auto &s : p->samp) {
@@ -1751,8 +1775,8 @@ extern "C" tn_status tn_map(tn_plan_t *p, int32_t batch, const int32_t *evidence
       run_graph(p, "max", [&] {
         launch_prepare_set(p, p->leaves_max, p->d_leaves_max, false);
         run_sched(p, p->max_tree.ops, p->sched_max);
-        launch_backtrack(p->iarena, p->d_back, (int)p->max_tree.back.size(), p->d_back_meta, p->n_vars,
-                         p->max_batch, p->d_assign, p->stream);
+        launch_backtrack(p->iarena, p->d_back, p->d_back_lev, (int)p->max_tree.back_lev.size() - 1, p->d_back_meta,
+                         p->n_vars, p->max_batch, p->d_assign, p->stream);
       });
       hip_check(hipMemcpyAsync(assign + (int64_t)b0 * p->n_vars, p->d_assign, (size_t)nb * p->n_vars * 4,
                                hipMemcpyDeviceToHost, p->stream), "D2H");
@@ -2027,7 +2051,8 @@ static void run_mmap(tn_plan_t *p, const int32_t *evidence, int32_t *assign_q, d
   hip_check(hipMemcpyAsync(p->d_assign, row.data(), row.size() * 4, hipMemcpyHostToDevice, p->stream), "init");
   launch_prepare_set(p, p->qleaves, p->d_qleaves, false);
   run_sched(p, p->qtree.ops, p->sched_q);
-  launch_backtrack(p->iarena, p->d_qback, (int)p->qtree.back.size(), p->d_qback_meta, p->n_vars, 1, p->d_assign,
+  launch_backtrack(p->iarena, p->d_qback, p->d_qback_lev, (int)p->qtree.back_lev.size() - 1, p->d_qback_meta,
+                   p->n_vars, 1, p->d_assign,
                    p->stream);
   hip_check(hipGetLastError(), "mmap launch");
   std::vector<int32_t> a(p->n_vars);
@@ -2111,8 +2136,8 @@ static tn_status profile_impl(tn_plan_t *p, int32_t task, int32_t batch, const i
       ls.push_back({4, 0, 0, [p] { launch_prepare_set(p, p->leaves_max, p->d_leaves_max, false); }});
       add_ops(p->max_tree.ops, p->sched_max);
       ls.push_back({5, 0, 0, [p] {
-                      launch_backtrack(p->iarena, p->d_back, (int)p->max_tree.back.size(), p->d_back_meta, p->n_vars,
-                                       p->max_batch, p->d_assign, p->stream);
+                      launch_backtrack(p->iarena, p->d_back, p->d_back_lev, (int)p->max_tree.back_lev.size() - 1,
+                                       p->d_back_meta, p->n_vars, p->max_batch, p->d_assign, p->stream);
                     }});
     }
     if (kind_only >= 0) {

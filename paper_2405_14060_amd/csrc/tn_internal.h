@@ -258,17 +258,17 @@ void launch_factor_grad(const float *arena, const GradDesc *d, int n, const int3
                         const float *root, int root_slot, int64_t n_values, float *grad,
                         void *stream);
 
-// Argmax readout: steps run in order; each reads x at its input labels,
-// fetches an argmax index and decodes it into its output labels.
+// Argmax readout: steps run level by level (the steps of a level in
+// parallel); each reads x at its input labels, fetches an argmax index and
+// decodes it into its output labels.
 struct BackStep {
   int64_t arg;       // int32 offset of the argmax array in the index arena
   int64_t bs;        // per-instance stride of the argmax array (0 = shared)
   int32_t in_begin, in_end;    // (var, stride) pairs
   int32_t out_begin, out_end;  // (var, card) pairs, last fastest
 };
-void launch_backtrack(const int32_t *iarena, const BackStep *steps, int n_steps,
-                      const int32_t *pairs, int n_vars, int batch, int32_t *assign,
-                      void *stream);
+void launch_backtrack(const int32_t *iarena, const BackStep *steps, const int32_t *lev, int n_lev,
+                      const int32_t *pairs, int n_vars, int batch, int32_t *assign, void *stream);
 
 // Top-down sampling steps (see tn_sample).
 struct SampleStep {

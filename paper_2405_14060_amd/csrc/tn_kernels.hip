@@ -1503,34 +1503,58 @@ void launch_factor_grad(const float *arena, const GradDesc *d, int n, const int3
 // --------------------------------------------------------------------------
 // argmax readout (MPE configuration), one lane per instance
 // --------------------------------------------------------------------------
-__global__ void k_backtrack(const int32_t *iarena, const BackStep *steps, int n_steps,
-                            const int32_t *pairs, int n_vars, int batch, int32_t *assign) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= batch) return;
-  int32_t *x = assign + (int64_t)b * n_vars;
-  for (int st = 0; st < n_steps; ++st) {
-    const BackStep s = steps[st];
-    int64_t off = 0;
-    bool ok = true;
-    for (int i = s.in_begin; i < s.in_end; ++i) {
-      const int32_t xv = x[pairs[2 * i]];
-      ok = ok && xv >= 0;
-      off += (int64_t)xv * pairs[2 * i + 1];
-    }
-    if (!ok) continue;  // an input left unassigned: leave this step's outputs unset
-    int32_t k = iarena[s.arg + (int64_t)b * s.bs + off];
-    for (int j = s.out_end - 1; j >= s.out_begin; --j) {
-      const int c = pairs[2 * j + 1];
-      x[pairs[2 * j]] = k % c;
-      k /= c;
-    }
+// One workgroup per instance; the levels run in order, the steps of a level
+// spread over the threads.  The assignment lives in LDS when it fits (else in
+// global memory, fenced between levels).
+static constexpr int kBackLdsVars = 12288;
+
+__device__ __forceinline__ void back_step(const int32_t *__restrict__ iarena, const BackStep &s,
+                                          const int32_t *__restrict__ pairs, int b, int32_t *x) {
+  int64_t off = 0;
+  bool ok = true;
+  for (int i = s.in_begin; i < s.in_end; ++i) {
+    const int32_t xv = x[pairs[2 * i]];
+    ok = ok && xv >= 0;
+    off += (int64_t)xv * pairs[2 * i + 1];
+  }
+  if (!ok) return;  // an input left unassigned: leave this step's outputs unset
+  int32_t k = iarena[s.arg + (int64_t)b * s.bs + off];
+  for (int j = s.out_end - 1; j >= s.out_begin; --j) {
+    const int c = pairs[2 * j + 1];
+    x[pairs[2 * j]] = k % c;
+    k /= c;
   }
 }
 
-void launch_backtrack(const int32_t *iarena, const BackStep *steps, int n_steps, const int32_t *pairs,
-                      int n_vars, int batch, int32_t *assign, void *stream) {
-  k_backtrack<<<(batch + 63) / 64, 64, 0, (hipStream_t)stream>>>(iarena, steps, n_steps, pairs,
-                                                                 n_vars, batch, assign);
+template <bool LDS_X>
+__global__ __launch_bounds__(kBlock) void k_backtrack(const int32_t *iarena, const BackStep *steps, const int32_t *lev,
+                                                      int n_lev, const int32_t *pairs, int n_vars, int32_t *assign) {
+  extern __shared__ int32_t xs[];
+  const int b = blockIdx.x;
+  int32_t *xg = assign + (int64_t)b * n_vars;
+  int32_t *x = LDS_X ? xs : xg;
+  if (LDS_X) {
+    for (int i = threadIdx.x; i < n_vars; i += kBlock) xs[i] = xg[i];
+    __syncthreads();
+  }
+  for (int l = 0; l < n_lev; ++l) {
+    for (int st = lev[l] + threadIdx.x; st < lev[l + 1]; st += kBlock) back_step(iarena, steps[st], pairs, b, x);
+    if (!LDS_X) __threadfence();
+    __syncthreads();
+  }
+  if (LDS_X)
+    for (int i = threadIdx.x; i < n_vars; i += kBlock) xg[i] = xs[i];
+}
+
+void launch_backtrack(const int32_t *iarena, const BackStep *steps, const int32_t *lev, int n_lev,
+                      const int32_t *pairs, int n_vars, int batch, int32_t *assign, void *stream) {
+  if (n_lev <= 0) return;
+  hipStream_t s = (hipStream_t)stream;
+  if (n_vars <= kBackLdsVars)
+    k_backtrack<true><<<batch, kBlock, (size_t)n_vars * sizeof(int32_t), s>>>(iarena, steps, lev, n_lev, pairs,
+                                                                                n_vars, assign);
+  else
+    k_backtrack<false><<<batch, kBlock, 0, s>>>(iarena, steps, lev, n_lev, pairs, n_vars, assign);
 }
 
 // --------------------------------------------------------------------------

@@ -111,6 +111,7 @@ struct TreeExec {
   // max-plus only: readout steps
   std::vector<BackStep> back;
   std::vector<int32_t> back_meta;
+  std::vector<int32_t> back_lev;      // readout levels: steps [back_lev[l], back_lev[l + 1])
 };
 
 }  // namespace tn
@@ -195,6 +196,7 @@ struct tn_plan_impl {
   tn::GradDesc *d_grad_desc = nullptr;
   tn::BackStep *d_back = nullptr, *d_qback = nullptr;
   int32_t *d_back_meta = nullptr, *d_qback_meta = nullptr;
+  int32_t *d_back_lev = nullptr, *d_qback_lev = nullptr;
   tn::SampleStep *d_samp = nullptr;
   int32_t *d_samp_meta = nullptr;
   int32_t *d_samp_out = nullptr;
