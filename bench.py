@@ -36,7 +36,8 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 KIND_NAMES = {0: "contract_map_sum", 1: "contract_map_max", 2: "contract_split_sum",
               3: "contract_split_max", 4: "prepare", 5: "other", 6: "seg_carrier_fwd",
-              7: "seg_carrier_bwd", 8: "seg_maps", 9: "seg_adjoint_sweeps", 10: "contract_mfma_sum"}
+              7: "seg_carrier_bwd", 8: "seg_maps", 9: "seg_adjoint_sweeps", 10: "contract_mfma_sum",
+              11: "contract_tropical_dense"}
 
 # HBM bytes per launch of a kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # counter runs (scaled by the counts of a plain 256 MiB copy), valid only for

@@ -236,7 +236,7 @@ tn_status tn_logZ_dev(tn_plan_t *plan, const int32_t *evidence, const float *val
  * (adjoint of C_0 and partial sums of Gbar C_0^T), 8 composed maps M of a
  * stage's segments, 9 adjoint sweeps (small operands' adjoints) of a
  * stage's segments, 10 dense-form contractions on the matrix cores
- * (sum-product).  flops and bytes are algorithmic: 2 x output x summed
+ * (sum-product), 11 dense-form max-plus contractions (vector ALUs).  flops and bytes are algorithmic: 2 x output x summed
  * elements; 4 bytes x (|X| + |Y| + |Z|) per instance times the instances of
  * the launch; for a carrier forward 4 bytes x (|input carrier| + |output
  * carrier|), for a carrier reverse 4 bytes x (2 |input carrier| + |output

@@ -274,10 +274,12 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
   // dense form on the matrix cores: sum-product with wide row and column
   // sets and a summed set of at least 8 entries, or none (an outer product:
   // its tiles still leave through LDS in the order of Z's layout)
-  if (!op.split && semi == SEMI_SUM && Y >= 0) {
+  // (max-plus: the same tiles on the vector ALUs, summed set of at least 8)
+  if (!op.split && Y >= 0) {
     const Labels Bl = inter(R, LY), Ml = minus(R, LY);
     const int64_t nB = numel(Bl, card), nM = numel(Ml, card);
-    if (nM >= 16 && a.nC >= 8 && (a.nS >= 8 || a.nS == 1) && nB * ((nM + kGemmTile - 1) / kGemmTile) *
+    const bool s_ok = semi == SEMI_SUM ? (a.nS >= 8 || a.nS == 1) : a.nS >= 8;
+    if (nM >= 16 && a.nC >= 8 && s_ok && nB * ((nM + kGemmTile - 1) / kGemmTile) *
                                                       (((int64_t)a.nC + kGemmTile - 1) / kGemmTile) < (1LL << 31)) {
       a.kind = 2;
       const size_t bs = lo_split(Bl, card), ms = lo_split(Ml, card);
@@ -1613,7 +1615,8 @@ void run_sched(tn_plan_t *p, const std::vector<Op> &ops, const Schedule &sc) {
       const Op &op = ops[L.ops[0]];
       launch_contract(op.semi, op.Y >= 0, op.split, op.a, op.d_a, op.nb, p->stream);
     } else if (L.gemm) {
-      launch_group(L.semi, 3 + p->opts.dtype, L.d_args, L.d_start, L.d_nblk, (int)L.ops.size(), L.total, p->stream);
+      launch_group(L.semi, 3 + (L.semi == SEMI_SUM ? p->opts.dtype : 0), L.d_args, L.d_start, L.d_nblk,
+                   (int)L.ops.size(), L.total, p->stream);
     } else if (!L.split) {
       launch_group(L.semi, 0, L.d_args, L.d_start, L.d_nblk, (int)L.ops.size(), L.total, p->stream);
     } else {
@@ -2104,7 +2107,7 @@ static tn_status profile_impl(tn_plan_t *p, int32_t task, int32_t batch, const i
         }
         int kind;
         if (L.seg) kind = 5 + L.seg_kind;  // 6 carrier forward, 7 carrier reverse, 8 composed maps, 9 adjoint sweeps
-        else if (L.gemm) kind = 10;
+        else if (L.gemm) kind = L.semi == SEMI_MAX ? 11 : 10;
         else kind = (L.split ? 2 : 0) + (L.semi == SEMI_MAX ? 1 : 0);
         const Launch *lp = &L;
         const std::vector<Op> *opsp = &ops;

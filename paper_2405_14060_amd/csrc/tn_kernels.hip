@@ -743,6 +743,123 @@ __device__ __forceinline__ void gemm_body(const ContractArgs &a, const int b, co
     a.ex[a.slotZ + (a.batZ ? b : 0)] = a.ex[a.slotX + (a.batX ? b : 0)] + kx + a.ex[a.slotY + (a.batY ? b : 0)] + ky;
 }
 
+// --------------------------------------------------------------------------
+// dense form of a max-plus node on the vector ALUs: a 64 x 64 tile of
+// Z[M, N] = max_S (X[M, S] + Y[S, N]) with the argmax index over S.  Chunks
+// of 16 summed entries are gathered into LDS as in the sum-product form
+// (entries past nS read as -inf, so they never win); every thread keeps a
+// 4 x 4 block of (value, index) pairs in registers and scans the chunk in
+// canonical order with a strict comparison, so the first maximiser is kept
+// (every candidate one FP32 addition).
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void gemm_max_body(const ContractArgs &a, const int b, const uint32_t blk) {
+  __shared__ int32_t oMX[kGT], oMZ[kGT], oNY[kGT], oNZ[kGT];
+  __shared__ float As[kGK * kGKP], Bs[kGK * kGKP];
+  __shared__ float Cs[kGT * kGCP];
+  __shared__ int32_t Ci[kGT * kGCP];
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
+  const uint32_t tm = (a.nM + kGT - 1) / kGT, tn = (a.nC + kGT - 1) / kGT;
+  const uint32_t bt = blk / (tm * tn), rem = blk - bt * tm * tn;
+  const uint32_t mt = rem / tn, nt = rem - mt * tn;
+  const uint32_t m0 = mt * kGT, n0 = nt * kGT;
+  const int32_t xb = tab_off(a.gbX, bt, a.nBl), yb = tab_off(a.gbY, bt, a.nBl), zb = tab_off(a.gbZ, bt, a.nBl);
+  const float *__restrict__ X = a.X + (int64_t)b * a.bsX + xb;
+  const float *__restrict__ Y = a.Y + (int64_t)b * a.bsY + yb;
+  float *__restrict__ Z = a.Z + (int64_t)b * a.bsZ + zb;
+  int32_t *__restrict__ I = a.I + (int64_t)b * a.bsZ + zb;
+  if (w == 0) {
+    const uint32_t m = m0 + l;
+    oMX[l] = m < a.nM ? tab_off(a.gmX, m, a.nMl) : -1;
+    oMZ[l] = m < a.nM ? tab_off(a.gmZ, m, a.nMl) : -1;
+  } else if (w == 1) {
+    const uint32_t n = n0 + l;
+    oNY[l] = n < a.nC ? (a.nC > 1 ? tab_off(a.cY, n, a.nCl) : 0) : -1;
+    oNZ[l] = n < a.nC ? (a.nC > 1 ? tab_off(a.cZ, n, a.nCl) : 0) : -1;
+  }
+  __syncthreads();
+  // thread (ty, tx) owns rows ty + 16 i and columns tx + 16 j, i, j < 4
+  const int ty = t >> 4, tx = t & 15;
+  float best[4][4];
+  int32_t arg[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      best[i][j] = -INFINITY;
+      arg[i][j] = 0;
+    }
+  for (uint32_t s0 = 0; s0 < a.nS; s0 += kGK) {
+    float va[4], vb[4];
+    int da[4], db[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + q * kBlock;
+      int m, k;
+      if (a.x_s_fast) { k = e % kGK; m = e / kGK; } else { m = e % kGT; k = e / kGT; }
+      const uint32_t sa = s0 + k;
+      const int32_t om = oMX[m];
+      va[q] = (om >= 0 && sa < a.nS) ? X[om + tab_off(a.sX, sa, a.nSl)] : -INFINITY;
+      da[q] = k * kGKP + m;
+      int n, k2;
+      if (a.y_n_fast) { n = e % kGT; k2 = e / kGT; } else { k2 = e % kGK; n = e / kGK; }
+      const uint32_t sb = s0 + k2;
+      const int32_t on = oNY[n];
+      vb[q] = (on >= 0 && sb < a.nS) ? Y[on + tab_off(a.sY, sb, a.nSl)] : -INFINITY;
+      db[q] = k2 * kGKP + n;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      As[da[q]] = va[q];
+      Bs[db[q]] = vb[q];
+    }
+    __syncthreads();
+    const int kn = (int)min((uint32_t)kGK, a.nS - s0);
+    for (int k = 0; k < kn; ++k) {
+      float av[4], bv[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        av[i] = As[k * kGKP + ty + 16 * i];
+        bv[i] = Bs[k * kGKP + tx + 16 * i];
+      }
+      const int32_t sidx = (int32_t)(s0 + k);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float v = av[i] + bv[j];
+          if (v > best[i][j]) {
+            best[i][j] = v;
+            arg[i][j] = sidx;
+          }
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      Cs[(ty + 16 * i) * kGCP + tx + 16 * j] = best[i][j];
+      Ci[(ty + 16 * i) * kGCP + tx + 16 * j] = arg[i][j];
+    }
+  __syncthreads();
+#pragma unroll 4
+  for (int q = 0; q < kGT * kGT / kBlock; ++q) {
+    const int e = t + q * kBlock;
+    int m, n;
+    if (a.z_n_fast) { n = e % kGT; m = e / kGT; } else { m = e % kGT; n = e / kGT; }
+    const int32_t om = oMZ[m], on = oNZ[n];
+    if (om >= 0 && on >= 0) {
+      Z[om + on] = Cs[m * kGCP + n];
+      I[om + on] = Ci[m * kGCP + n];
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gemm_max(const ContractArgs *__restrict__ ap) {
+  gemm_max_body(*ap, blockIdx.y, blockIdx.x);
+}
+
 // one kernel per operand precision (a runtime switch inside one kernel would
 // size its registers for the largest variant)
 template <int PREC>
@@ -795,8 +912,9 @@ __global__ __launch_bounds__(kBlock) void k_group(const ContractArgs *__restrict
   } else if (PHASE == 1) {
     if (hy) split_body<SEMI, true>(a, b, blk);
     else split_body<SEMI, false>(a, b, blk);
-  } else if (PHASE >= 3) {  // dense form, operand precision PHASE - 3
-    gemm_body<PHASE - 3>(a, b, blk);
+  } else if (PHASE >= 3) {  // dense form (sum-product: operand precision PHASE - 3)
+    if (SEMI == SEMI_MAX) gemm_max_body(a, b, blk);
+    else gemm_body<PHASE - 3>(a, b, blk);
   } else {
     if (hy) finish_body<SEMI, true>(a, b, blk);
     else finish_body<SEMI, false>(a, b, blk);
@@ -808,6 +926,10 @@ void launch_group(int semi, int phase, const ContractArgs *ops, const uint32_t *
   if (n <= 0 || total_blocks == 0) return;
   hipStream_t s = (hipStream_t)stream;
   dim3 g(total_blocks);
+  if (phase >= 3 && semi == SEMI_MAX) {  // dense max-plus form
+    k_group<SEMI_MAX, 3><<<g, kBlock, 0, s>>>(ops, start, nblk, n);
+    return;
+  }
   if (phase >= 3) {  // dense form (sum-product), operand precision phase - 3
     if (phase == 4) k_group<SEMI_SUM, 4><<<g, kBlock, 0, s>>>(ops, start, nblk, n);
     else if (phase == 5) k_group<SEMI_SUM, 5><<<g, kBlock, 0, s>>>(ops, start, nblk, n);
@@ -843,7 +965,8 @@ void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, co
   const uint32_t n_out = a.nR * a.nC;
   if (a.kind == 2) {
     const dim3 g(map_blocks(a), nb);
-    if (a.prec == 1) k_gemm<1><<<g, kBlock, 0, s>>>(d_a);
+    if (semi == SEMI_MAX) k_gemm_max<<<g, kBlock, 0, s>>>(d_a);
+    else if (a.prec == 1) k_gemm<1><<<g, kBlock, 0, s>>>(d_a);
     else if (a.prec == 2) k_gemm<2><<<g, kBlock, 0, s>>>(d_a);
     else k_gemm<0><<<g, kBlock, 0, s>>>(d_a);
     return;

@@ -298,6 +298,21 @@ def test_map_bn300_bit_exact(T):
     assert abs(oracle.log_joint(bn, x2[0]) - lp2[0]) <= 1e-3 * max(1.0, abs(v64))
 
 
+@pytest.mark.parametrize("seed", [0, 4])
+def test_map_dense_tropical_bit_exact(T, seed):
+    """Trees with dense max-plus nodes (64 x 64 tiles on the vector ALUs):
+    value and assignment bit for bit against the oracle's FP32 emulation on
+    the same tree."""
+    bn = W.random_bn(200, seed)
+    P = T.Plan(T.Network(bn), semirings=T.MAX_PLUS)
+    assert P.info()["n_dense"] > 0
+    lp, x = P.map()
+    pairs, _ = P.tree()
+    v32, x32 = oracle.map_assignment(bn, None, pairs=pairs.astype(np.int64), fp32=True)
+    assert np.array_equal(x[0], np.asarray(x32))
+    assert np.float32(lp[0]) == np.float32(v32)
+
+
 def test_map_batched_indicators(T):
     bn = W.random_bn(50, seed=4)
     ev = W.bn_evidence_batch(bn, 6, seed=5)
