@@ -258,9 +258,9 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
   op.nb = zb ? p->max_batch : 1;
   const uint64_t n_out = (uint64_t)a.nR * a.nC;
   const uint32_t nSh = a.nS / a.nSl;
-  // few outputs, each a long sum: workgroups reduce chunks of the summed
-  // index cooperatively instead of one lane looping over all of it
-  if (n_out * (uint64_t)op.nb < 8192 && a.nS >= 256) {
+  // very few outputs, each a long sum: workgroups reduce chunks of the
+  // summed index cooperatively (more outputs go to the wave form below)
+  if (n_out * (uint64_t)op.nb <= 64 && a.nS >= 256) {
     op.split = true;
     // about 1024 workgroups in total, each reducing at least 1K summed entries
     uint32_t want = std::max<uint32_t>(1, 1024u / (uint32_t)op.nb);
