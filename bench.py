@@ -106,7 +106,8 @@ def timed(fn, steps, warmup, sync):
 def bench_grid20(args, T, W, np, sync):
     net = W.grid_mrf(20, 20, 0)
     dt = dict(f32=T.TN_F32, bf16=T.TN_BF16, f16=T.TN_F16)[args.dtype]
-    plan = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, use_graph=not args.no_graph, dtype=dt)
+    plan = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, use_graph=not args.no_graph, dtype=dt,
+                  autotune=args.autotune)
     info = plan.info()
     sec, (lz, m) = timed(plan.marginals, args.steps, args.warmup, lambda: (plan.sync(), sync()))
     roof, kernels, flops = roofline(plan, 1, "grid20x20")
@@ -115,7 +116,7 @@ def bench_grid20(args, T, W, np, sync):
                config=dict(workload="grid20x20_mrf logZ+all-marginals", seed=0, n_vars=400, n_factors=1160,
                            tree_sc_log2=info["sc"], tree_tc_log2=round(info["tc"], 3),
                            segments=info["n_segments"], launches_per_solve=info["n_launches_fwd"] +
-                           info["n_launches_bwd"] + 3, graph=not args.no_graph),
+                           info["n_launches_bwd"] + 3, graph=not args.no_graph, autotune=args.autotune),
                tflops=round(flops / sec / 1e12, 4), log_z=float(lz[0]), roofline=roof, kernels=kernels)
     if not args.no_cpu_baseline:
         import oracle
@@ -140,7 +141,7 @@ def bench_bn500x512(args, T, W, np, sync):
     B = ev.shape[0]
     dt = dict(f32=T.TN_F32, bf16=T.TN_BF16, f16=T.TN_F16)[args.dtype]
     plan = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, evidence_mode=T.EVIDENCE_INDICATOR, max_batch=B,
-                  use_graph=not args.no_graph, dtype=dt)
+                  use_graph=not args.no_graph, dtype=dt, autotune=args.autotune)
     info = plan.info()
     sec, (lz, m) = timed(lambda: plan.marginals(ev, batch=B), args.steps, args.warmup,
                          lambda: (plan.sync(), sync()))
@@ -157,7 +158,7 @@ def bench_bn500x512(args, T, W, np, sync):
                config=dict(workload="bn500 x 512 evidence sets, logZ+all-marginals, batched indicator pass",
                            seed=0, n_vars=500, batch=B, tree_sc_log2=round(info["sc"], 3),
                            tree_tc_log2=round(info["tc"], 3), dense_nodes=info["n_dense"],
-                           wave_nodes=info["n_wave"], graph=not args.no_graph),
+                           wave_nodes=info["n_wave"], graph=not args.no_graph, autotune=args.autotune),
                tflops=round(flops / sec / 1e12, 4), roofline=roof, kernels=kernels,
                per_instance_fp32=dict(value=round(n1 / sec1, 2), unit="instance-solves/s",
                                       max_log_z_diff_vs_batched=float(np.abs(lz1 - lz[:4]).max())))
@@ -218,6 +219,9 @@ def main():
     ap.add_argument("--workload", default="grid20", choices=["grid20", "bn500x512", "bn300_map", "grid20_map"])
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"],
                     help="matrix-core operand precision of the sum-product workloads")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="pick kernel forms by the fixed rules instead of timing the eligible forms of every "
+                         "contraction shape at plan time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",

@@ -108,6 +108,10 @@ typedef struct {
                                 only tn_plan_info_get / tn_plan_tree / tn_free_plan
                                 may then be called */
   int32_t no_fuse;           /* keep every tree node a separate contraction */
+  int32_t autotune;          /* 1: at plan time, time every eligible kernel form
+                                (generic, row, wave, dense) of each distinct
+                                contraction shape on the device and keep the
+                                fastest; 0: fixed rules */
 } tn_plan_opts;
 
 /* Summary of a plan (tn_plan_info). */

@@ -49,7 +49,7 @@ class PlanOpts(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("hip_stream", ctypes.c_void_p),
                 ("tree_pairs", i32p), ("n_tree_pairs", ctypes.c_int32),
                 ("want_factor_grad", ctypes.c_int32), ("host_only", ctypes.c_int32),
-                ("no_fuse", ctypes.c_int32)]
+                ("no_fuse", ctypes.c_int32), ("autotune", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -160,7 +160,7 @@ class Network:
 def make_opts(semirings=SUM_PRODUCT | MAX_PLUS, evidence_mode=EVIDENCE_NONE, observed=None,
               query=None, planner=PLANNER_BEST, restarts=4, seed=0, max_log2_size=0.0,
               dtype=TN_F32, max_batch=1, use_graph=True, stream=None, tree=None,
-              want_factor_grad=False, host_only=False, fuse=True):
+              want_factor_grad=False, host_only=False, fuse=True, autotune=False):
     o = PlanOpts()
     lib().tn_plan_opts_default(ctypes.byref(o))
     keep = []
@@ -192,6 +192,7 @@ def make_opts(semirings=SUM_PRODUCT | MAX_PLUS, evidence_mode=EVIDENCE_NONE, obs
     o.want_factor_grad = 1 if want_factor_grad else 0
     o.host_only = 1 if host_only else 0
     o.no_fuse = 0 if fuse else 1
+    o.autotune = 1 if autotune else 0
     return o, keep
 
 

@@ -115,6 +115,7 @@ extern "C" void tn_plan_opts_default(tn_plan_opts *o) {
   o->seed = 0;
   o->max_log2_size = 0;
   o->dtype = TN_F32;
+  o->autotune = 0;
   o->max_batch = 1;
   o->use_graph = 1;
 }
@@ -271,61 +272,69 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
     op.part_off = p->part_floats;
     p->part_floats += ((int64_t)op.nb * a.n_chunks * n_out + 63) / 64 * 64;
   }
-  // dense form on the matrix cores: sum-product with wide row and column
-  // sets and a summed set of at least 8 entries, or none (an outer product:
-  // its tiles still leave through LDS in the order of Z's layout)
-  // (max-plus: the same tiles on the vector ALUs, summed set of at least 8)
-  if (!op.split && Y >= 0) {
-    const Labels Bl = inter(R, LY), Ml = minus(R, LY);
-    const int64_t nB = numel(Bl, card), nM = numel(Ml, card);
-    const bool s_ok = semi == SEMI_SUM ? (a.nS >= 8 || a.nS == 1) : a.nS >= 8;
-    if (nM >= 16 && a.nC >= 8 && s_ok && nB * ((nM + kGemmTile - 1) / kGemmTile) *
-                                                      (((int64_t)a.nC + kGemmTile - 1) / kGemmTile) < (1LL << 31)) {
-      a.kind = 2;
-      const size_t bs = lo_split(Bl, card), ms = lo_split(Ml, card);
-      add_tabs(p, Bl, bs, LX, op.t_gbX);
-      add_tabs(p, Bl, bs, LY, op.t_gbY);
-      add_tabs(p, Bl, bs, LZ, op.t_gbZ);
-      add_tabs(p, Ml, ms, LX, op.t_gmX);
-      add_tabs(p, Ml, ms, LZ, op.t_gmZ);
-      a.nB = (uint32_t)nB;
-      a.nBl = (uint32_t)numel(Labels(Bl.begin() + bs, Bl.end()), card);
-      a.nM = (uint32_t)nM;
-      a.nMl = (uint32_t)numel(Labels(Ml.begin() + ms, Ml.end()), card);
-      a.x_s_fast = (!LX.empty() && has(S, LX.back())) ? 1 : 0;
-      a.y_n_fast = (!LY.empty() && has(C, LY.back())) ? 1 : 0;
-      a.z_n_fast = (!LZ.empty() && has(C, LZ.back())) ? 1 : 0;
-    }
-  }
-  // wave form: long sums over many outputs (one wavefront per output)
-  if (!op.split && a.kind == 0 && a.nS >= 64) a.kind = 3;
-  // row form for skinny contractions: few summed entries and columns
-  if (!op.split && a.kind == 0 && a.nS <= (uint32_t)kRowMax && a.nC <= (uint32_t)kRowMax && a.nS * a.nC <= 64) {
-    a.kind = 1;
-    a.ns = (int32_t)a.nS;
-    a.nc = (int32_t)a.nC;
-    auto offsets = [&](const Labels &L, const Labels &TL, int32_t *dst) {
-      const int64_t n = numel(L, card);
-      std::vector<int> d(L.size(), 0);
-      for (int64_t i = 0; i < n; ++i) {
-        int64_t off = 0;
-        for (size_t j = 0; j < L.size(); ++j) off += (int64_t)d[j] * stride_in(TL, L[j], card);
-        dst[i] = (int32_t)off;
-        for (int j = (int)L.size() - 1; j >= 0; --j) {
-          if (++d[j] < card[L[j]]) break;
-          d[j] = 0;
-        }
+  // Eligible forms (Op::forms bits: 1 generic, 2 row, 4 dense, 8 wave) and
+  // the rule-based choice; the autotuner may later pick another eligible one.
+  // dense form: wide row and column sets, a summed set of at least 8 entries
+  // (sum-product: or none, an outer product whose tiles still leave through
+  // LDS in the order of Z's layout); max-plus runs the same tiles on the
+  // vector ALUs
+  if (!op.split) {
+    op.forms = 1 | 8;
+    if (Y >= 0) {
+      const Labels Bl = inter(R, LY), Ml = minus(R, LY);
+      const int64_t nB = numel(Bl, card), nM = numel(Ml, card);
+      const bool s_ok = semi == SEMI_SUM ? (a.nS >= 8 || a.nS == 1) : a.nS >= 8;
+      if (nM >= 16 && a.nC >= 8 && s_ok &&
+          nB * ((nM + kGemmTile - 1) / kGemmTile) * (((int64_t)a.nC + kGemmTile - 1) / kGemmTile) < (1LL << 31)) {
+        op.forms |= 4;
+        const size_t bs = lo_split(Bl, card), ms = lo_split(Ml, card);
+        add_tabs(p, Bl, bs, LX, op.t_gbX);
+        add_tabs(p, Bl, bs, LY, op.t_gbY);
+        add_tabs(p, Bl, bs, LZ, op.t_gbZ);
+        add_tabs(p, Ml, ms, LX, op.t_gmX);
+        add_tabs(p, Ml, ms, LZ, op.t_gmZ);
+        a.nB = (uint32_t)nB;
+        a.nBl = (uint32_t)numel(Labels(Bl.begin() + bs, Bl.end()), card);
+        a.nM = (uint32_t)nM;
+        a.nMl = (uint32_t)numel(Labels(Ml.begin() + ms, Ml.end()), card);
+        a.x_s_fast = (!LX.empty() && has(S, LX.back())) ? 1 : 0;
+        a.y_n_fast = (!LY.empty() && has(C, LY.back())) ? 1 : 0;
+        a.z_n_fast = (!LZ.empty() && has(C, LZ.back())) ? 1 : 0;
       }
-    };
-    offsets(S, LX, a.sx);
-    offsets(S, LY, a.sy);
-    offsets(C, LY, a.cy);
-    offsets(C, LZ, a.cz);
-    if ((a.nRl & (a.nRl - 1)) == 0) {
-      int sh = 0;
-      while ((1u << sh) < a.nRl) ++sh;
-      a.rl_shift = sh;
     }
+    // row form for skinny contractions: few summed entries and columns
+    if (a.nS <= (uint32_t)kRowMax && a.nC <= (uint32_t)kRowMax && a.nS * a.nC <= 64) {
+      op.forms |= 2;
+      a.ns = (int32_t)a.nS;
+      a.nc = (int32_t)a.nC;
+      auto offsets = [&](const Labels &L, const Labels &TL, int32_t *dst) {
+        const int64_t n = numel(L, card);
+        std::vector<int> d(L.size(), 0);
+        for (int64_t i = 0; i < n; ++i) {
+          int64_t off = 0;
+          for (size_t j = 0; j < L.size(); ++j) off += (int64_t)d[j] * stride_in(TL, L[j], card);
+          dst[i] = (int32_t)off;
+          for (int j = (int)L.size() - 1; j >= 0; --j) {
+            if (++d[j] < card[L[j]]) break;
+            d[j] = 0;
+          }
+        }
+      };
+      offsets(S, LX, a.sx);
+      offsets(S, LY, a.sy);
+      offsets(C, LY, a.cy);
+      offsets(C, LZ, a.cz);
+      if ((a.nRl & (a.nRl - 1)) == 0) {
+        int sh = 0;
+        while ((1u << sh) < a.nRl) ++sh;
+        a.rl_shift = sh;
+      }
+    }
+    // rules: dense, else wave for long sums, else row, else generic
+    if (op.forms & 4) a.kind = 2;
+    else if (a.nS >= 64) a.kind = 3;
+    else if (op.forms & 2) a.kind = 1;
+    else a.kind = 0;
   }
   op.flops = 2.0 * (double)n_out * (double)a.nS;
   op.bytes = 4.0 * (double)(p->T[X].size + (Y >= 0 ? p->T[Y].size : 0) + p->T[Z].size);
@@ -754,6 +763,58 @@ tn_plan_impl::~tn_plan_impl() {
   if (own_stream && stream) (void)hipStreamDestroy(stream);
 }
 
+// Autotuner: for every distinct contraction shape with more than one
+// eligible kernel form, time each form on the device (its own arguments,
+// three launches between two events after a warm-up) and keep the fastest.
+// Decisions are cached by shape, so a tree with many equal nodes costs a few
+// timings.  Operand contents do not matter for the timing (every access is
+// at table offsets).
+static void autotune_ops(tn_plan_t *p, const std::vector<Op *> &ops) {
+  std::map<std::vector<int64_t>, int> cache;
+  hipEvent_t e0, e1;
+  hip_check(hipEventCreate(&e0), "event");
+  hip_check(hipEventCreate(&e1), "event");
+  static const int kForm[4][2] = {{1, 0}, {2, 1}, {4, 2}, {8, 3}};  // (bit, kind)
+  for (Op *op : ops) {
+    if (op->split || op->seg >= 0) continue;
+    std::vector<int> cands;
+    for (auto &f : kForm)
+      if (op->forms & f[0]) cands.push_back(f[1]);
+    if (cands.size() < 2) continue;
+    const ContractArgs &a = op->a;
+    const std::vector<int64_t> key = {op->semi, op->Y >= 0, op->nb, a.nR, a.nRl, a.nC, a.nCl, a.nS, a.nSl,
+                                      a.col_fastest, a.nB, a.nM, a.x_s_fast, a.y_n_fast, a.z_n_fast, op->forms};
+    auto it = cache.find(key);
+    int best = -1;
+    if (it != cache.end()) {
+      best = it->second;
+    } else {
+      float best_ms = 0.f;
+      for (int kind : cands) {
+        op->a.kind = kind;
+        hip_check(hipMemcpy(op->d_a, &op->a, sizeof(ContractArgs), hipMemcpyHostToDevice), "autotune");
+        launch_contract(op->semi, op->Y >= 0, false, op->a, op->d_a, op->nb, p->stream);
+        hip_check(hipEventRecord(e0, p->stream), "event");
+        for (int r = 0; r < 3; ++r) launch_contract(op->semi, op->Y >= 0, false, op->a, op->d_a, op->nb, p->stream);
+        hip_check(hipEventRecord(e1, p->stream), "event");
+        hip_check(hipEventSynchronize(e1), "autotune");
+        hip_check(hipGetLastError(), "autotune launch");
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+        if (best < 0 || ms < best_ms) {
+          best = kind;
+          best_ms = ms;
+        }
+      }
+      cache[key] = best;
+    }
+    op->a.kind = best;
+    hip_check(hipMemcpy(op->d_a, &op->a, sizeof(ContractArgs), hipMemcpyHostToDevice), "autotune");
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
 static void build_mmap(tn_plan_t *p, const tn_net *net);
 static void allocate_mmap(tn_plan_t *p);
 static void upload_segments(tn_plan_t *p);
@@ -865,6 +926,15 @@ static void allocate(tn_plan_t *p, const tn_net *net) {
     for (Op *op : all) host.push_back(op->a);
     ContractArgs *d = dupload(p, host);
     for (size_t i = 0; i < all.size(); ++i) all[i]->d_a = d + i;
+    if (p->opts.autotune) {
+      autotune_ops(p, all);
+      // the fused lists hold copies of the unfused contractions: same choice
+      std::map<int, int> kind_of;  // output tensor -> form
+      for (Op *op : all) kind_of[op->Z] = op->a.kind;
+      for (auto *L : {&p->ffwd, &p->fbwd})
+        for (Op &op : *L)
+          if (op.seg < 0 && kind_of.count(op.Z)) op.a.kind = kind_of[op.Z];
+    }
   }
   p->sched_fwd = build_schedule(p, p->sum_tree.ops, false);
   p->sched_bwd = build_schedule(p, p->bwd, true);
@@ -1339,7 +1409,7 @@ static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
     p->is_mmap = true;
     if (p->mode == TN_EVIDENCE_INDICATOR) throw TnError(TN_E_UNSUPPORTED, "MMAP with batched evidence");
     build_mmap(p, net);
-    allocate(p, net);
+    if (!o->host_only) allocate(p, net);
     return;
   }
   // stream

@@ -48,6 +48,7 @@ struct Op {
   // written, for scheduling
   int seg = -1, seg_kind = 0;
   std::vector<int> ins, outs;
+  int forms = 0;                      // eligible kernel forms: 1 generic, 2 row, 4 dense, 8 wave
 };
 
 // Host description of a fused segment (tables as offsets into the plan's

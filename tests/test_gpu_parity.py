@@ -174,6 +174,29 @@ def test_low_precision_matrix_cores(T, dtype, tol_lz, tol_m):
         assert max(np.abs(x - y).max() for x, y in zip(got, want_m)) <= tol_m, b
 
 
+def test_autotuned_plans_against_oracle(T):
+    """Plans whose kernel forms the autotuner picked by timing: same results
+    (sum-product on batched indicators, MAP bit for bit)."""
+    c = W.config(3, seed=4, small=True)
+    bn, ev = c["net"], c["evidence"]
+    B = ev.shape[0]
+    P = T.Plan(T.Network(bn), evidence_mode=T.EVIDENCE_INDICATOR, max_batch=B, semirings=T.SUM_PRODUCT,
+               autotune=True)
+    lz, m = P.marginals(ev, batch=B)
+    for b in (0, B - 1):
+        want_lz, want_m, *_ = oracle.marginals(bn, ev[b], mode="indicator")
+        assert rel(lz[b], want_lz) <= 1e-5, b
+        got = P.split_marginals(m[b])
+        assert max(np.abs(x - y).max() for x, y in zip(got, want_m)) <= 1e-5, b
+    bn = W.random_bn(200, 4)
+    P = T.Plan(T.Network(bn), semirings=T.MAX_PLUS, autotune=True)
+    lp, x = P.map()
+    pairs, _ = P.tree()
+    v32, x32 = oracle.map_assignment(bn, None, pairs=pairs.astype(np.int64), fp32=True)
+    assert np.array_equal(x[0], np.asarray(x32))
+    assert np.float32(lp[0]) == np.float32(v32)
+
+
 def test_grid20x20_full_size_against_oracle(T):
     ref = json.load(open(os.path.join(GOLDEN, "oracle_grid20x20_seed0.json")))
     net = W.grid_mrf(20, 20, 0)
