@@ -37,7 +37,7 @@ FP32_PEAK_TFLOPS = 157.3
 KIND_NAMES = {0: "contract_map_sum", 1: "contract_map_max", 2: "contract_split_sum",
               3: "contract_split_max", 4: "prepare", 5: "other", 6: "seg_carrier_fwd",
               7: "seg_carrier_bwd", 8: "seg_maps", 9: "seg_adjoint_sweeps", 10: "contract_mfma_sum",
-              11: "contract_tropical_dense"}
+              11: "contract_tropical_dense", 12: "contract_interleaved_sum", 13: "contract_interleaved_max"}
 
 # HBM bytes per launch of a kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # counter runs (scaled by the counts of a plain 256 MiB copy), valid only for
@@ -140,8 +140,10 @@ def bench_bn500x512(args, T, W, np, sync):
     net, ev = c["net"], c["evidence"]
     B = ev.shape[0]
     dt = dict(f32=T.TN_F32, bf16=T.TN_BF16, f16=T.TN_F16)[args.dtype]
+    layout = dict(auto=T.LAYOUT_AUTO, instance_major=T.LAYOUT_INSTANCE_MAJOR,
+                  interleaved=T.LAYOUT_INTERLEAVED)[args.batch_layout]
     plan = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, evidence_mode=T.EVIDENCE_INDICATOR, max_batch=B,
-                  use_graph=not args.no_graph, dtype=dt, autotune=args.autotune)
+                  use_graph=not args.no_graph, dtype=dt, autotune=args.autotune, batch_layout=layout)
     info = plan.info()
     sec, (lz, m) = timed(lambda: plan.marginals(ev, batch=B), args.steps, args.warmup,
                          lambda: (plan.sync(), sync()))
@@ -158,7 +160,9 @@ def bench_bn500x512(args, T, W, np, sync):
                config=dict(workload="bn500 x 512 evidence sets, logZ+all-marginals, batched indicator pass",
                            seed=0, n_vars=500, batch=B, tree_sc_log2=round(info["sc"], 3),
                            tree_tc_log2=round(info["tc"], 3), dense_nodes=info["n_dense"],
-                           wave_nodes=info["n_wave"], graph=not args.no_graph, autotune=args.autotune),
+                           wave_nodes=info["n_wave"], interleaved_nodes=info["n_interleaved"],
+                           batch_layout="interleaved" if info["batch_stride"] else "instance_major",
+                           graph=not args.no_graph, autotune=args.autotune),
                tflops=round(flops / sec / 1e12, 4), roofline=roof, kernels=kernels,
                per_instance_fp32=dict(value=round(n1 / sec1, 2), unit="instance-solves/s",
                                       max_log_z_diff_vs_batched=float(np.abs(lz1 - lz[:4]).max())))
@@ -219,6 +223,8 @@ def main():
     ap.add_argument("--workload", default="grid20", choices=["grid20", "bn500x512", "bn300_map", "grid20_map"])
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"],
                     help="matrix-core operand precision of the sum-product workloads")
+    ap.add_argument("--batch-layout", default="auto", choices=["auto", "instance_major", "interleaved"],
+                    help="batched workload: layout of the instances (auto: interleaved for f32)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="pick kernel forms by the fixed rules instead of timing the eligible forms of every "
                          "contraction shape at plan time")

@@ -109,9 +109,19 @@ typedef struct {
                                 may then be called */
   int32_t no_fuse;           /* keep every tree node a separate contraction */
   int32_t autotune;          /* 1: at plan time, time every eligible kernel form
-                                (generic, row, wave, dense) of each distinct
-                                contraction shape on the device and keep the
-                                fastest; 0: fixed rules */
+                                (generic, row, wave, dense; interleaved with or
+                                without the workgroup split of the summed
+                                range) of each distinct contraction shape on
+                                the device and keep the fastest; 0: fixed rules */
+  int32_t batch_layout;      /* batched evidence (mode INDICATOR, max_batch > 1):
+                                0 automatic (interleaved for dtype TN_F32),
+                                1 instance-major (each instance's tensor
+                                contiguous; all kernel forms, matrix cores),
+                                2 interleaved (element e of instance b at
+                                e * B + b with B = max_batch rounded up to a
+                                multiple of 64: one wavefront computes one
+                                output element for 64 instances, FP32 on the
+                                vector ALUs) */
 } tn_plan_opts;
 
 /* Summary of a plan (tn_plan_info). */
@@ -136,6 +146,9 @@ typedef struct {
   int32_t n_fused_nodes;         /* tree nodes inside fused segments */
   int32_t n_dense;               /* contractions (forward and reverse) in the dense matrix-core form */
   int32_t n_wave;                /* contractions in the wave-per-output form (all passes, both semirings) */
+  int32_t n_interleaved;         /* contractions in the interleaved-instance form */
+  int32_t batch_stride;          /* interleaved plans: instances held per element (max_batch
+                                    rounded up to a multiple of 64); 0 otherwise */
 } tn_plan_info;
 
 /* Fill *o with defaults: sum-product + max-plus, no evidence, best planner,
@@ -240,7 +253,8 @@ tn_status tn_logZ_dev(tn_plan_t *plan, const int32_t *evidence, const float *val
  * (adjoint of C_0 and partial sums of Gbar C_0^T), 8 composed maps M of a
  * stage's segments, 9 adjoint sweeps (small operands' adjoints) of a
  * stage's segments, 10 dense-form contractions on the matrix cores
- * (sum-product), 11 dense-form max-plus contractions (vector ALUs).  flops and bytes are algorithmic: 2 x output x summed
+ * (sum-product), 11 dense-form max-plus contractions (vector ALUs),
+ * 12 / 13 interleaved-form contractions (sum / max).  flops and bytes are algorithmic: 2 x output x summed
  * elements; 4 bytes x (|X| + |Y| + |Z|) per instance times the instances of
  * the launch; for a carrier forward 4 bytes x (|input carrier| + |output
  * carrier|), for a carrier reverse 4 bytes x (2 |input carrier| + |output

@@ -27,6 +27,7 @@ TN_OK, TN_E_INVALID, TN_E_NOMEM, TN_E_DEVICE, TN_E_TOO_LARGE, TN_E_ZERO_EVIDENCE
 TN_F32, TN_BF16, TN_F16 = 0, 1, 2
 SUM_PRODUCT, MAX_PLUS = 1, 2
 EVIDENCE_NONE, EVIDENCE_SLICED, EVIDENCE_INDICATOR = 0, 1, 2
+LAYOUT_AUTO, LAYOUT_INSTANCE_MAJOR, LAYOUT_INTERLEAVED = 0, 1, 2
 PLANNER_BEST, PLANNER_GREEDY, PLANNER_MINFILL, PLANNER_NATURAL, PLANNER_MINDEG = range(5)
 
 EXPORTS = ["tn_plan_opts_default", "tn_load_network", "tn_free_network", "tn_plan", "tn_free_plan",
@@ -49,7 +50,8 @@ class PlanOpts(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("hip_stream", ctypes.c_void_p),
                 ("tree_pairs", i32p), ("n_tree_pairs", ctypes.c_int32),
                 ("want_factor_grad", ctypes.c_int32), ("host_only", ctypes.c_int32),
-                ("no_fuse", ctypes.c_int32), ("autotune", ctypes.c_int32)]
+                ("no_fuse", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("batch_layout", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -62,7 +64,8 @@ class PlanInfo(ctypes.Structure):
                 ("device_bytes", ctypes.c_int64), ("n_launches_fwd", ctypes.c_int32),
                 ("n_launches_bwd", ctypes.c_int32), ("n_launches_max", ctypes.c_int32),
                 ("n_segments", ctypes.c_int32), ("n_fused_nodes", ctypes.c_int32),
-                ("n_dense", ctypes.c_int32), ("n_wave", ctypes.c_int32)]
+                ("n_dense", ctypes.c_int32), ("n_wave", ctypes.c_int32),
+                ("n_interleaved", ctypes.c_int32), ("batch_stride", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -160,7 +163,7 @@ class Network:
 def make_opts(semirings=SUM_PRODUCT | MAX_PLUS, evidence_mode=EVIDENCE_NONE, observed=None,
               query=None, planner=PLANNER_BEST, restarts=4, seed=0, max_log2_size=0.0,
               dtype=TN_F32, max_batch=1, use_graph=True, stream=None, tree=None,
-              want_factor_grad=False, host_only=False, fuse=True, autotune=False):
+              want_factor_grad=False, host_only=False, fuse=True, autotune=False, batch_layout=0):
     o = PlanOpts()
     lib().tn_plan_opts_default(ctypes.byref(o))
     keep = []
@@ -193,6 +196,7 @@ def make_opts(semirings=SUM_PRODUCT | MAX_PLUS, evidence_mode=EVIDENCE_NONE, obs
     o.host_only = 1 if host_only else 0
     o.no_fuse = 0 if fuse else 1
     o.autotune = 1 if autotune else 0
+    o.batch_layout = batch_layout
     return o, keep
 
 

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -116,6 +117,7 @@ extern "C" void tn_plan_opts_default(tn_plan_opts *o) {
   o->max_log2_size = 0;
   o->dtype = TN_F32;
   o->autotune = 0;
+  o->batch_layout = 0;
   o->max_batch = 1;
   o->use_graph = 1;
 }
@@ -257,8 +259,45 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
   a.col_fastest = (!LZ.empty() && !C.empty() && LZ.back() == C.back()) ? 1 : 0;
   const bool zb = p->T[Z].batched;
   op.nb = zb ? p->max_batch : 1;
+  op.inst = op.nb;
   const uint64_t n_out = (uint64_t)a.nR * a.nC;
   const uint32_t nSh = a.nS / a.nSl;
+  if (zb && p->inter) {
+    // interleaved plans: every batched contraction takes the interleaved
+    // form, rows split into batch labels (held by Y) and M labels
+    op.forms = 16;
+    a.kind = 4;
+    op.nb = p->max_batch / kInterLanes;
+    a.nslab = op.nb;
+    const Labels Bl = Y >= 0 ? inter(R, LY) : Labels{}, Ml = minus(R, Bl);
+    const size_t bs = lo_split(Bl, card), ms = lo_split(Ml, card);
+    add_tabs(p, Bl, bs, LX, op.t_gbX);
+    if (Y >= 0) add_tabs(p, Bl, bs, LY, op.t_gbY);
+    add_tabs(p, Bl, bs, LZ, op.t_gbZ);
+    add_tabs(p, Ml, ms, LX, op.t_gmX);
+    add_tabs(p, Ml, ms, LZ, op.t_gmZ);
+    a.nB = (uint32_t)numel(Bl, card);
+    a.nBl = (uint32_t)numel(Labels(Bl.begin() + bs, Bl.end()), card);
+    a.nM = (uint32_t)numel(Ml, card);
+    a.nMl = (uint32_t)numel(Labels(Ml.begin() + ms, Ml.end()), card);
+    // tiles of a wave (forms: 16 = 4 x 4, 32 = 4 x 4 with the summed range
+    // split over the workgroup, 64 = 8 x 8, 128 = 16 x 1; the larger tiles
+    // for sum-product only): 8 x 8 where rows and columns are wide, 16 x 1
+    // for (nearly) column-free contractions, else 4 x 4, split when long
+    // sums meet few tiles
+    const uint64_t waves = (uint64_t)a.nB * ((a.nM + kInterTile - 1) / kInterTile) *
+                           ((a.nC + kInterTile - 1) / kInterTile) * op.nb;
+    if (a.nS >= 8) op.forms |= 32;
+    if (semi == SEMI_SUM && Y >= 0 && a.nM >= 8 && a.nC >= 8) op.forms |= 64;
+    if (semi == SEMI_SUM && a.nM >= 16 && a.nC <= 2) op.forms |= 128;
+    a.ksplit = a.nS >= 64 && waves < 4096 ? 4 : 1;
+    a.tile = 0;
+    if (a.ksplit == 1 && (op.forms & 64)) a.tile = 1;
+    else if (a.ksplit == 1 && (op.forms & 128)) a.tile = 2;
+    op.flops = 2.0 * (double)n_out * (double)a.nS;
+    op.bytes = 4.0 * (double)(p->T[X].size + (Y >= 0 ? p->T[Y].size : 0) + p->T[Z].size);
+    return op;
+  }
   // very few outputs, each a long sum: workgroups reduce chunks of the
   // summed index cooperatively (more outputs go to the wave form below)
   if (n_out * (uint64_t)op.nb <= 64 && a.nS >= 256) {
@@ -613,17 +652,22 @@ static void fill_args(tn_plan_t *p, Op &op) {
   a.gmX = tab(op.t_gmX);
   a.gmZ = tab(op.t_gmZ);
   const TensorBuf &X = p->T[op.X], &Z = p->T[op.Z];
+  // instance stride bs and element stride es of an operand
+  auto strides = [&](const TensorBuf &t, int64_t &bs, int32_t &es) {
+    bs = t.batched ? (p->inter ? 1 : t.size) : 0;
+    es = t.batched && p->inter ? p->max_batch : 1;
+  };
   a.X = p->arena + X.off;
-  a.bsX = X.batched ? X.size : 0;
+  strides(X, a.bsX, a.esX);
   if (op.Y >= 0) {
     const TensorBuf &Y = p->T[op.Y];
     a.Y = p->arena + Y.off;
-    a.bsY = Y.batched ? Y.size : 0;
+    strides(Y, a.bsY, a.esY);
     a.slotY = Y.slot;
     a.batY = Y.batched;
   }
   a.Z = p->arena + Z.off;
-  a.bsZ = Z.batched ? Z.size : 0;
+  strides(Z, a.bsZ, a.esZ);
   a.I = op.I >= 0 ? p->iarena + p->IB[op.I].off : nullptr;
   a.mx = p->mx;
   a.ex = p->ex;
@@ -696,14 +740,15 @@ static Schedule build_schedule(tn_plan_t *p, const std::vector<Op> &ops, bool al
         sc.launches.push_back(std::move(L));
       }
     for (int semi = 0; semi < 2; ++semi)
-      for (int cls = 0; cls < 3; ++cls) {  // one-lane-per-output forms, split reductions, dense form
+      for (int cls = 0; cls < 4; ++cls) {  // one-lane-per-output forms, split reductions, dense, interleaved
         Launch L;
         L.semi = semi;
         L.split = cls == 1;
         L.gemm = cls == 2;
+        L.inter = cls == 3;
         for (int i = 0; i < n; ++i) {
           const Op &op = ops[i];
-          const int c = op.split ? 1 : (op.a.kind == 2 ? 2 : 0);
+          const int c = op.split ? 1 : (op.a.kind == 2 ? 2 : (op.a.kind == 4 ? 3 : 0));
           if (stage[i] == st && op.seg < 0 && op.semi == semi && c == cls) L.ops.push_back(i);
         }
         if (!L.ops.empty()) sc.launches.push_back(std::move(L));
@@ -770,28 +815,33 @@ tn_plan_impl::~tn_plan_impl() {
 // timings.  Operand contents do not matter for the timing (every access is
 // at table offsets).
 static void autotune_ops(tn_plan_t *p, const std::vector<Op *> &ops) {
-  std::map<std::vector<int64_t>, int> cache;
+  std::map<std::vector<int64_t>, std::array<int, 3>> cache;
   hipEvent_t e0, e1;
   hip_check(hipEventCreate(&e0), "event");
   hip_check(hipEventCreate(&e1), "event");
-  static const int kForm[4][2] = {{1, 0}, {2, 1}, {4, 2}, {8, 3}};  // (bit, kind)
+  // (form bit, kind, workgroup split of the summed range, interleaved tile)
+  static const int kForm[8][4] = {{1, 0, 1, 0},  {2, 1, 1, 0},  {4, 2, 1, 0},  {8, 3, 1, 0},
+                                  {16, 4, 1, 0}, {32, 4, 4, 0}, {64, 4, 1, 1}, {128, 4, 1, 2}};
   for (Op *op : ops) {
     if (op->split || op->seg >= 0) continue;
-    std::vector<int> cands;
+    std::vector<std::array<int, 3>> cands;
     for (auto &f : kForm)
-      if (op->forms & f[0]) cands.push_back(f[1]);
+      if (op->forms & f[0]) cands.push_back({f[1], f[2], f[3]});
     if (cands.size() < 2) continue;
     const ContractArgs &a = op->a;
     const std::vector<int64_t> key = {op->semi, op->Y >= 0, op->nb, a.nR, a.nRl, a.nC, a.nCl, a.nS, a.nSl,
-                                      a.col_fastest, a.nB, a.nM, a.x_s_fast, a.y_n_fast, a.z_n_fast, op->forms};
+                                      a.col_fastest, a.nB, a.nM, a.x_s_fast, a.y_n_fast, a.z_n_fast, op->forms,
+                                      a.batX, a.batY};
     auto it = cache.find(key);
-    int best = -1;
+    std::array<int, 3> best{-1, 1, 0};
     if (it != cache.end()) {
       best = it->second;
     } else {
       float best_ms = 0.f;
-      for (int kind : cands) {
-        op->a.kind = kind;
+      for (auto cand : cands) {
+        op->a.kind = cand[0];
+        op->a.ksplit = cand[1];
+        op->a.tile = cand[2];
         hip_check(hipMemcpy(op->d_a, &op->a, sizeof(ContractArgs), hipMemcpyHostToDevice), "autotune");
         launch_contract(op->semi, op->Y >= 0, false, op->a, op->d_a, op->nb, p->stream);
         hip_check(hipEventRecord(e0, p->stream), "event");
@@ -801,14 +851,16 @@ static void autotune_ops(tn_plan_t *p, const std::vector<Op *> &ops) {
         hip_check(hipGetLastError(), "autotune launch");
         float ms = 0.f;
         hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
-        if (best < 0 || ms < best_ms) {
-          best = kind;
+        if (best[0] < 0 || ms < best_ms) {
+          best = cand;
           best_ms = ms;
         }
       }
       cache[key] = best;
     }
-    op->a.kind = best;
+    op->a.kind = best[0];
+    op->a.ksplit = best[1];
+    op->a.tile = best[2];
     hip_check(hipMemcpy(op->d_a, &op->a, sizeof(ContractArgs), hipMemcpyHostToDevice), "autotune");
   }
   (void)hipEventDestroy(e0);
@@ -929,11 +981,15 @@ static void allocate(tn_plan_t *p, const tn_net *net) {
     if (p->opts.autotune) {
       autotune_ops(p, all);
       // the fused lists hold copies of the unfused contractions: same choice
-      std::map<int, int> kind_of;  // output tensor -> form
-      for (Op *op : all) kind_of[op->Z] = op->a.kind;
+      std::map<int, std::array<int, 3>> kind_of;  // output tensor -> form
+      for (Op *op : all) kind_of[op->Z] = {op->a.kind, op->a.ksplit, op->a.tile};
       for (auto *L : {&p->ffwd, &p->fbwd})
         for (Op &op : *L)
-          if (op.seg < 0 && kind_of.count(op.Z)) op.a.kind = kind_of[op.Z];
+          if (op.seg < 0 && kind_of.count(op.Z)) {
+            op.a.kind = kind_of[op.Z][0];
+            op.a.ksplit = kind_of[op.Z][1];
+            op.a.tile = kind_of[op.Z][2];
+          }
     }
   }
   p->sched_fwd = build_schedule(p, p->sum_tree.ops, false);
@@ -989,8 +1045,10 @@ static void allocate(tn_plan_t *p, const tn_net *net) {
     m.leaf = Lf.off;
     m.adj_batched = A.batched;
     m.leaf_batched = Lf.batched;
-    m.adj_bs = A.size;
-    m.leaf_bs = Lf.size;
+    m.adj_bs = p->inter ? 1 : A.size;
+    m.leaf_bs = p->inter ? 1 : Lf.size;
+    m.adj_es = A.batched && p->inter ? p->max_batch : 1;
+    m.leaf_es = Lf.batched && p->inter ? p->max_batch : 1;
   }
   p->d_marg_desc = dupload(p, p->marg);
   p->d_marg = dalloc<double>(p, (size_t)p->max_batch * std::max(1, p->marg_row));
@@ -1004,7 +1062,8 @@ static void allocate(tn_plan_t *p, const tn_net *net) {
     for (auto &s : t.back) {
       const IntBuf &b = p->IB[(int)s.arg];
       s.arg = b.off;
-      s.bs = b.batched ? b.size : 0;
+      s.bs = b.batched ? (p->inter ? 1 : b.size) : 0;
+      s.es = b.batched && p->inter ? p->max_batch : 1;
     }
   };
   fix_back(p->max_tree);
@@ -1391,6 +1450,10 @@ static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
   p->mode = o->evidence_mode;
   if (p->mode < 0 || p->mode > 2) throw TnError(TN_E_INVALID, "unknown evidence mode");
   p->max_batch = p->mode == TN_EVIDENCE_INDICATOR ? std::max(1, o->max_batch) : 1;
+  if (o->batch_layout < 0 || o->batch_layout > 2) throw TnError(TN_E_INVALID, "unknown batch layout");
+  p->inter = p->mode == TN_EVIDENCE_INDICATOR && p->max_batch > 1 &&
+             (o->batch_layout == 2 || (o->batch_layout == 0 && o->dtype == TN_F32));
+  if (p->inter) p->max_batch = (p->max_batch + kInterLanes - 1) / kInterLanes * kInterLanes;
   p->want_sum = (o->semiring_mask & TN_SUM_PRODUCT) != 0;
   p->want_max = (o->semiring_mask & TN_MAX_PLUS) != 0;
   p->want_grad = o->want_factor_grad != 0;
@@ -1596,7 +1659,9 @@ extern "C" tn_status tn_plan_info_get(const tn_plan_t *p, tn_plan_info *info) {
       for (const Op &op : *L) {
         info->n_dense += op.a.kind == 2 ? 1 : 0;
         info->n_wave += op.a.kind == 3 ? 1 : 0;
+        info->n_interleaved += op.a.kind == 4 ? 1 : 0;
       }
+    info->batch_stride = p->inter ? p->max_batch : 0;
     for (const auto &g : p->groups)
       for (const Op &op : g.ops) {
         info->n_dense += op.a.kind == 2 ? 1 : 0;
@@ -1687,6 +1752,8 @@ void run_sched(tn_plan_t *p, const std::vector<Op> &ops, const Schedule &sc) {
     } else if (L.gemm) {
       launch_group(L.semi, 3 + (L.semi == SEMI_SUM ? p->opts.dtype : 0), L.d_args, L.d_start, L.d_nblk,
                    (int)L.ops.size(), L.total, p->stream);
+    } else if (L.inter) {
+      launch_group(L.semi, 6, L.d_args, L.d_start, L.d_nblk, (int)L.ops.size(), L.total, p->stream);
     } else if (!L.split) {
       launch_group(L.semi, 0, L.d_args, L.d_start, L.d_nblk, (int)L.ops.size(), L.total, p->stream);
     } else {
@@ -1712,6 +1779,7 @@ static PrepareArgs prep_args(tn_plan_t *p, const std::vector<LeafDesc> &h, const
   a.reset_end = reset ? p->reset_end : 0;
   a.batch = p->max_batch;
   a.max_batch = p->max_batch;
+  a.interleaved = p->inter ? 1 : 0;
   return a;
 }
 
@@ -1775,7 +1843,7 @@ static void forward_sum(tn_plan_t *p, bool with_bwd, bool allow_fused = true) {
     if (fz) run_sched(p, p->ffwd, p->sched_ffwd);
     else run_sched(p, p->sum_tree.ops, p->sched_fwd);
     const TensorBuf &r = p->T[p->sum_tree.root];
-    launch_logz(p->arena + r.off, r.batched ? r.size : 0, p->ex, r.slot, r.batched, p->max_batch, p->d_out, p->stream);
+    launch_logz(p->arena + r.off, r.batched ? (p->inter ? 1 : r.size) : 0, p->ex, r.slot, r.batched, p->max_batch, p->d_out, p->stream);
     if (with_bwd) {
       if (fz) run_sched(p, p->fbwd, p->sched_fbwd);
       else run_sched(p, p->bwd, p->sched_bwd);
@@ -1856,7 +1924,7 @@ extern "C" tn_status tn_map(tn_plan_t *p, int32_t batch, const int32_t *evidence
       const TensorBuf &r = p->T[p->max_tree.root];
       std::vector<float> rv(nb);
       for (int b = 0; b < nb; ++b)
-        hip_check(hipMemcpyAsync(&rv[b], p->arena + r.off + (r.batched ? (int64_t)b * r.size : 0), 4,
+        hip_check(hipMemcpyAsync(&rv[b], p->arena + r.off + (r.batched ? (int64_t)b * (p->inter ? 1 : r.size) : 0), 4,
                                  hipMemcpyDeviceToHost, p->stream), "D2H");
       hip_check(hipStreamSynchronize(p->stream), "map");
       if (logp)
@@ -2172,12 +2240,13 @@ static tn_status profile_impl(tn_plan_t *p, int32_t task, int32_t batch, const i
         double fl = 0, by = 0;
         for (int i : L.ops) {
           const Op &op = ops[i];
-          fl += op.seg >= 0 ? op.flops : op.flops * op.nb;
-          by += op.seg >= 0 ? op.bytes : (op.bytes + (op.semi == SEMI_MAX ? 4.0 * p->T[op.Z].size : 0.0)) * op.nb;
+          fl += op.seg >= 0 ? op.flops : op.flops * op.inst;
+          by += op.seg >= 0 ? op.bytes : (op.bytes + (op.semi == SEMI_MAX ? 4.0 * p->T[op.Z].size : 0.0)) * op.inst;
         }
         int kind;
         if (L.seg) kind = 5 + L.seg_kind;  // 6 carrier forward, 7 carrier reverse, 8 composed maps, 9 adjoint sweeps
         else if (L.gemm) kind = L.semi == SEMI_MAX ? 11 : 10;
+        else if (L.inter) kind = L.semi == SEMI_MAX ? 13 : 12;
         else kind = (L.split ? 2 : 0) + (L.semi == SEMI_MAX ? 1 : 0);
         const Launch *lp = &L;
         const std::vector<Op> *opsp = &ops;
@@ -2194,7 +2263,7 @@ static tn_status profile_impl(tn_plan_t *p, int32_t task, int32_t batch, const i
       else add_ops(p->sum_tree.ops, p->sched_fwd);
       ls.push_back({5, 0, 0, [p] {
                       const TensorBuf &r = p->T[p->sum_tree.root];
-                      launch_logz(p->arena + r.off, r.batched ? r.size : 0, p->ex, r.slot, r.batched, p->max_batch,
+                      launch_logz(p->arena + r.off, r.batched ? (p->inter ? 1 : r.size) : 0, p->ex, r.slot, r.batched, p->max_batch,
                                   p->d_out, p->stream);
                     }});
       if (task == 1) {

@@ -102,7 +102,8 @@ struct ContractArgs {
   // row form (kind 1): one lane per row, all summed entries and columns in
   // registers; offsets of the summed entries in X, Y and of the columns in
   // Y, Z, in canonical order
-  int32_t kind = 0;  // 0 generic, 1 row form, 2 dense matrix-core form, 3 wave per output
+  int32_t kind = 0;  // 0 generic, 1 row form, 2 dense matrix-core form, 3 wave per output,
+                     // 4 interleaved instances (lane = instance)
   int32_t ns = 0, nc = 0;
   int32_t rl_shift = -1;  // log2(nRl) when nRl is a power of two
   int32_t sx[kRowMax], sy[kRowMax], cy[kRowMax], cz[kRowMax];
@@ -117,17 +118,28 @@ struct ContractArgs {
   int32_t y_n_fast = 0;     // Y's stride-1 label is a column label
   int32_t z_n_fast = 0;     // Z's stride-1 label is a column label
   int32_t prec = 0;         // matrix-core operands: 0 FP32, 1 BF16, 2 FP16 (FP32 accumulation)
+  // interleaved form (kind 4): element e of instance b of a batched tensor
+  // sits at e * es + b (es = instances held); a shared operand has es = 1
+  // and bs = 0.  Rows are split into batch labels and M labels as in the
+  // dense form (gb*, gm* tables; no Y: M = rows).
+  int32_t esX = 1, esY = 1, esZ = 1;
+  int32_t ksplit = 1;       // 4: the waves of a workgroup split the summed range of one tile
+  int32_t tile = 0;         // tile of a wave: 0 = 4 x 4, 1 = 8 x 8, 2 = 16 x 1 (rows x columns)
+  int32_t nslab = 1;        // groups of 64 instances
 };
 static constexpr int kGemmTile = 64;  // output tile edge of the dense form
+static constexpr int kInterTile = 4;  // output tile edge (rows x columns) of the interleaved form
+static constexpr int kInterLanes = 64;  // instances per wavefront of the interleaved form
 
 enum Semiring { SEMI_SUM = 0, SEMI_MAX = 1 };
 
 // a: host copy (grid shape); d_a: the same arguments in device memory
 void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, const ContractArgs *d_a, int nb,
                      void *stream);
-// blocks per instance of a one-lane-per-output launch
+// blocks per instance (interleaved form: per 64 instances) of a launch
 uint32_t map_blocks(const ContractArgs &a);
-// phase 0: map, 1: split partials, 2: split finish, 3 + p: dense form with operand precision p
+// phase 0: map, 1: split partials, 2: split finish, 3 + p: dense form with
+// operand precision p, 6: interleaved form
 void launch_group(int semi, int phase, const ContractArgs *ops, const uint32_t *start,
                   const uint32_t *nblk, int n, uint32_t total_blocks, void *stream);
 
@@ -228,6 +240,7 @@ struct PrepareArgs {
   int reset_begin = 0, reset_end = 0;  // slots zeroed each solve
   int batch = 1;
   int max_batch = 1;
+  int interleaved = 0;  // batched leaves: element i of instance b at i * max_batch + b
 };
 void launch_prepare(const PrepareArgs &a, void *stream);
 
@@ -240,7 +253,8 @@ struct MargDesc {
   int32_t card;
   int32_t out;    // column offset in the marginal row
   int32_t adj_batched, leaf_batched;
-  int64_t adj_bs, leaf_bs;
+  int64_t adj_bs, leaf_bs;  // instance strides
+  int64_t adj_es, leaf_es;  // element strides
 };
 void launch_marg(const float *arena, const MargDesc *d, int n, int batch, int row, double *out,
                  void *stream);
@@ -264,6 +278,7 @@ void launch_factor_grad(const float *arena, const GradDesc *d, int n, const int3
 struct BackStep {
   int64_t arg;       // int32 offset of the argmax array in the index arena
   int64_t bs;        // per-instance stride of the argmax array (0 = shared)
+  int64_t es;        // element stride of the argmax array
   int32_t in_begin, in_end;    // (var, stride) pairs
   int32_t out_begin, out_end;  // (var, card) pairs, last fastest
 };

@@ -34,6 +34,16 @@
 namespace tn {
 
 static constexpr int kBlock = 256;
+
+// Global-address-space views of device pointers: loads and stores through
+// them compile to global (not flat) memory instructions, which address with
+// a scalar base plus a 32-bit lane offset and wait only on the vector memory
+// counter.
+typedef __attribute__((address_space(1))) const int32_t gint;
+typedef __attribute__((address_space(1))) const uint32_t gu32;
+typedef __attribute__((address_space(1))) const float gcfloat;
+typedef __attribute__((address_space(1))) float gfloat;
+typedef __attribute__((address_space(1))) int32_t gint_w;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
@@ -89,7 +99,7 @@ __device__ __forceinline__ int max_exponent(uint32_t bits) {
 static constexpr int kMaxSub = kMaxSubSlots;
 
 __device__ __forceinline__ uint32_t read_max(const uint32_t *mx, int stride, int slot) {
-  const uint32_t v = mx[(threadIdx.x & 63) * stride + slot];
+  const uint32_t v = ((gu32 *)mx)[(threadIdx.x & 63) * stride + slot];
   return __float_as_uint(wave_max(__uint_as_float(v)));
 }
 
@@ -115,7 +125,7 @@ __device__ __forceinline__ void block_record_max(float v, uint32_t *slot) {
 
 __device__ __forceinline__ int32_t tab_off(const Tab2 &t, uint32_t i, uint32_t nlo) {
   uint32_t h = i / nlo;
-  return t.hi[h] + t.lo[i - h * nlo];
+  return ((gint *)t.hi)[h] + ((gint *)t.lo)[i - h * nlo];
 }
 
 // --------------------------------------------------------------------------
@@ -867,6 +877,244 @@ __global__ __launch_bounds__(kBlock) void k_gemm(const ContractArgs *__restrict_
   gemm_body<PREC>(*ap, blockIdx.y, blockIdx.x);
 }
 
+// --------------------------------------------------------------------------
+// interleaved-instance form (batched evidence).  Element e of instance b of
+// a batched tensor sits at e * es + b, so one wavefront computes the same
+// output elements for 64 consecutive instances (lane = instance): every
+// offset is uniform across the wave and lives in scalar registers, every
+// operand load and output store is one contiguous 256-byte row, and each lane
+// carries its own instance's scale.  A wave owns tiles of TM rows (M labels)
+// x TN columns within one batch-label assignment: per summed entry it loads
+// TM rows of X and TN rows of Y and does TM x TN multiply-adds (or max-plus
+// candidates).  Operand rows are read with buffer loads: the row's byte
+// offset is a scalar operand and the lane's offset a constant vector
+// register, so addressing costs no vector instructions.  The summed entries'
+// offsets are fetched 64 at a time, one per lane, and broadcast with
+// readlane; tile offsets likewise.  Edge tiles repeat their last row /
+// column (loads stay in bounds, the copies are never stored), so the inner
+// loop has no branches and several summed entries' loads are in flight at
+// once.  Tile variants (a.tile): 0 = 4 x 4, 1 = 8 x 8, 2 = 16 x 1.  With
+// ksplit = 4 (4 x 4 tiles) the four waves of a workgroup share one tile and
+// split the summed range in four consecutive parts, folded in wave order
+// through LDS (deterministic; for max-plus the earlier part wins ties, which
+// keeps the first maximiser).
+// --------------------------------------------------------------------------
+static constexpr int kIT = kInterTile;
+
+__device__ __forceinline__ int32_t bcast(int32_t v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
+// raw buffer over a tensor (no range limit: every offset is in bounds by
+// construction); word 3 as for all gfx9 parts
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void *base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)0xffffffff, 0x00020000);
+}
+
+// one FP32 word per lane at byte offset row + lane (the builtin returns the raw bits)
+__device__ __forceinline__ float ld_row(__amdgpu_buffer_rsrc_t r, int lane_off, int row_off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, lane_off, row_off, 0));
+}
+
+template <int TM, int TN>
+struct InterShared {
+  float v[kBlock / 64 - 1][TM * TN][64];
+  int32_t i[kBlock / 64 - 1][TM * TN][64];
+};
+
+template <int SEMI, bool HASY, int TM, int TN0, bool SPLIT>
+__device__ __forceinline__ void inter_tiles(const ContractArgs &a, const int slab, const uint32_t blk,
+                                            const uint32_t nblk) {
+  constexpr int TN = HASY ? TN0 : 1;  // without Y there are no column labels
+  constexpr int NW = kBlock / 64;
+  constexpr int UNROLL = TM * TN >= 64 ? 2 : 4;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int b = slab * kInterLanes + lane;
+  // uniform bases at this group's first instance; the lane offset is a constant
+  const __amdgpu_buffer_rsrc_t rX = raw_rsrc(a.X + (int64_t)slab * kInterLanes * a.bsX);
+  const __amdgpu_buffer_rsrc_t rY = raw_rsrc(HASY ? a.Y + (int64_t)slab * kInterLanes * a.bsY : a.X);
+  const int vx = lane * 4 * (int)a.bsX, vy = HASY ? lane * 4 * (int)a.bsY : 0;
+  const int esX = a.esX * 4, esY = HASY ? a.esY * 4 : 0;  // bytes per element
+  gfloat *__restrict__ Zp = (gfloat *)a.Z;
+  gint_w *__restrict__ Ip = (gint_w *)a.I;
+  const int64_t esZ = a.esZ;
+  float sx = 1.f, sy = 1.f;
+  int kx = 0, ky = 0;
+  if (SEMI == SEMI_SUM) {
+    kx = max_exponent(a.batX ? ((gu32 *)a.mx)[a.slotX + b] : read_max(a.mx, a.mx_stride, a.slotX));
+    sx = ldexpf(1.f, -kx);
+    if (HASY) {
+      ky = max_exponent(a.batY ? ((gu32 *)a.mx)[a.slotY + b] : read_max(a.mx, a.mx_stride, a.slotY));
+      sy = ldexpf(1.f, -ky);
+    }
+  }
+  const uint32_t nM = a.nM, nC = a.nC, nS = a.nS, nSl = a.nSl;
+  const uint32_t tm = (nM + TM - 1) / TM, tn = (nC + TN - 1) / TN;
+  const uint32_t ntiles = a.nB * tm * tn;
+  const bool split = SPLIT && a.ksplit > 1;
+  uint32_t sb = 0, se = nS;
+  if (split) {
+    const uint32_t per = (nS + NW - 1) / NW;
+    sb = min(nS, w * per);
+    se = min(nS, sb + per);
+  }
+  const uint32_t t0 = split ? blk : blk * NW + w, tstep = split ? nblk : nblk * NW;
+  float lmax = 0.f;
+  for (uint32_t t = t0; t < ntiles; t += tstep) {
+    const uint32_t bt = t / (tm * tn), rem = t - bt * tm * tn;
+    const uint32_t mt = rem / tn, nt = rem - mt * tn;
+    const uint32_t m0 = mt * TM, n0 = nt * TN;
+    const int mi = (int)min((uint32_t)TM, nM - m0), nj = (int)min((uint32_t)TN, nC - n0);
+    // tile offsets: lanes 0..TM-1 rows, 32..32+TN-1 columns, 63 the batch labels
+    int32_t v0 = 0, v1 = 0, v2 = 0;
+    if (lane < mi) {
+      v0 = tab_off(a.gmX, m0 + lane, a.nMl);
+      v1 = tab_off(a.gmZ, m0 + lane, a.nMl);
+    } else if (lane >= 32 && lane < 32 + nj) {
+      v0 = HASY ? tab_off(a.cY, n0 + lane - 32, a.nCl) : 0;
+      v1 = tab_off(a.cZ, n0 + lane - 32, a.nCl);
+    } else if (lane == 63) {
+      v0 = tab_off(a.gbX, bt, a.nBl);
+      v1 = HASY ? tab_off(a.gbY, bt, a.nBl) : 0;
+      v2 = tab_off(a.gbZ, bt, a.nBl);
+    }
+    const int32_t xb = bcast(v0, 63), yb = bcast(v1, 63), zb = bcast(v2, 63);
+    int32_t xm[TM], zm[TM], yn[TN], zn[TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int ii = i < mi ? i : mi - 1;
+      xm[i] = xb + bcast(v0, ii);
+      zm[i] = zb + bcast(v1, ii);
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int jj = j < nj ? j : nj - 1;
+      yn[j] = yb + bcast(v0, 32 + jj);
+      zn[j] = bcast(v1, 32 + jj);
+    }
+    float acc[TM][TN];
+    int32_t arg[SEMI == SEMI_MAX ? TM : 1][SEMI == SEMI_MAX ? TN : 1];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        acc[i][j] = SEMI == SEMI_SUM ? 0.f : -INFINITY;
+        if (SEMI == SEMI_MAX) arg[i][j] = 0;
+      }
+    auto step = [&](int32_t xs, int32_t ys, int32_t s) {
+      float xv[TM], yv[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) xv[i] = ld_row(rX, vx, (xm[i] + xs) * esX);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) yv[j] = HASY ? ld_row(rY, vy, (yn[j] + ys) * esY) : 0.f;
+      if (SEMI == SEMI_SUM) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i) xv[i] *= sx;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) yv[j] *= sy;
+      }
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          if (SEMI == SEMI_SUM) {
+            if (HASY) acc[i][j] = fmaf(xv[i], yv[j], acc[i][j]);
+            else acc[i][j] += xv[i];
+          } else {
+            const float v = HASY ? xv[i] + yv[j] : xv[i];
+            if (s == 0 || v > acc[i][j]) {
+              acc[i][j] = v;
+              arg[i][j] = s;
+            }
+          }
+        }
+    };
+    for (uint32_t s0 = sb; s0 < se; s0 += 64) {
+      int32_t ox = 0, oy = 0;
+      if (s0 + lane < se) {
+        ox = tab_off(a.sX, s0 + lane, nSl);
+        if (HASY) oy = tab_off(a.sY, s0 + lane, nSl);
+      }
+      const int cnt = (int)min(64u, se - s0);
+      int k = 0;
+      for (; k + UNROLL <= cnt; k += UNROLL) {
+#pragma unroll
+        for (int u = 0; u < UNROLL; ++u)
+          step(bcast(ox, k + u), HASY ? bcast(oy, k + u) : 0, (int32_t)(s0 + k + u));
+      }
+      for (; k < cnt; ++k) step(bcast(ox, k), HASY ? bcast(oy, k) : 0, (int32_t)(s0 + k));
+    }
+    if (SPLIT && split) {
+      __shared__ InterShared<TM, TN> red;
+      if (w > 0) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) {
+            red.v[w - 1][i * TN + j][lane] = acc[i][j];
+            if (SEMI == SEMI_MAX) red.i[w - 1][i * TN + j][lane] = arg[i][j];
+          }
+      }
+      __syncthreads();
+      if (w == 0) {
+        for (int q = 0; q < NW - 1; ++q)
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+              const float v = red.v[q][i * TN + j][lane];
+              if (SEMI == SEMI_SUM) {
+                acc[i][j] += v;
+              } else if (v > acc[i][j]) {
+                acc[i][j] = v;
+                arg[i][j] = red.i[q][i * TN + j][lane];
+              }
+            }
+      }
+      __syncthreads();
+      if (w > 0) continue;
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        if (i < mi && j < nj) {
+          const int64_t zo = (int64_t)(zm[i] + zn[j]) * esZ;
+          Zp[zo + b] = acc[i][j];
+          if (SEMI == SEMI_SUM) lmax = fmaxf(lmax, acc[i][j]);
+          else Ip[zo + b] = arg[i][j];
+        }
+  }
+  if (SEMI == SEMI_SUM) {
+    // this wave's maximum per instance, recorded in sub-slot 0 of the
+    // instance's slot (guarded: maxima only grow within a launch)
+    uint32_t *slot = a.mx + a.slotZ + b;
+    if (lmax > 0.f && __uint_as_float(*(volatile uint32_t *)slot) < lmax) atomicMax(slot, __float_as_uint(lmax));
+    if (blk == 0 && w == 0) {
+      int e = ((gint *)a.ex)[a.slotX + (a.batX ? b : 0)] + kx;
+      if (HASY) e += ((gint *)a.ex)[a.slotY + (a.batY ? b : 0)] + ky;
+      ((gint_w *)a.ex)[a.slotZ + b] = e;
+    }
+  }
+}
+
+template <int SEMI, bool HASY>
+__device__ __forceinline__ void inter_body(const ContractArgs &a, const int slab, const uint32_t blk,
+                                           const uint32_t nblk) {
+  if (SEMI == SEMI_SUM && a.tile == 1) inter_tiles<SEMI, HASY, 8, 8, false>(a, slab, blk, nblk);
+  else if (SEMI == SEMI_SUM && a.tile == 2) inter_tiles<SEMI, HASY, 16, 1, false>(a, slab, blk, nblk);
+  else inter_tiles<SEMI, HASY, kIT, kIT, true>(a, slab, blk, nblk);
+}
+
+// Workgroups of a launch go to the XCDs in turn (workgroup id modulo 8), so
+// the id is decoded group-of-instances fastest: with 8 (or a multiple of 8)
+// groups every workgroup of one group of 64 instances lands on the same XCD
+// and the tiles that share operand rows share that XCD's L2.
+template <int SEMI, bool HASY>
+__global__ __launch_bounds__(kBlock) void k_inter(const ContractArgs *__restrict__ ap) {
+  const ContractArgs &a = *ap;
+  const uint32_t ns = (uint32_t)a.nslab;
+  inter_body<SEMI, HASY>(a, (int)(blockIdx.x % ns), blockIdx.x / ns, gridDim.x / ns);
+}
+
 // Arguments live in device memory (a pointer is the only kernel argument):
 // large by-value argument blocks cost microseconds per launch.
 template <int SEMI, bool HASY>
@@ -885,14 +1133,21 @@ __global__ __launch_bounds__(kBlock) void k_split_finish(const ContractArgs *__r
 // Several independent contractions in one launch (one stage of the tree
 // schedule).  Block ranges: op i owns blocks [start[i], start[i+1]), split
 // as instance-major (b, blk) with nblk[i] blocks per instance.
+// The op of block x: the starts are ascending, so the ops starting at or
+// before x form a prefix; each lane tests one start (64 per round) and the
+// wave counts the prefix with a ballot (one load round instead of a chain of
+// dependent loads).
 __device__ __forceinline__ int find_op(const uint32_t *start, int n, uint32_t x) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (start[mid] <= x) lo = mid;
-    else hi = mid - 1;
+  const int lane = threadIdx.x & 63;
+  int idx = 0;
+  for (int base = 0; base < n; base += 64) {
+    const int j = base + lane;
+    const bool le = j < n && ((gu32 *)start)[j] <= x;
+    const int c = __popcll(__ballot(le));
+    idx = base + c - 1;
+    if (c < 64) break;
   }
-  return lo;
+  return idx;
 }
 
 template <int SEMI, int PHASE>
@@ -903,9 +1158,15 @@ __global__ __launch_bounds__(kBlock) void k_group(const ContractArgs *__restrict
   const ContractArgs &a = ops[i];
   const uint32_t local = blockIdx.x - start[i];
   const uint32_t per = nblk[i];
+  const bool hy = a.Y != nullptr;
+  if (PHASE == 6) {  // interleaved form: group of 64 instances fastest (see k_inter)
+    const uint32_t ns = (uint32_t)a.nslab;
+    if (hy) inter_body<SEMI, true>(a, (int)(local % ns), local / ns, per);
+    else inter_body<SEMI, false>(a, (int)(local % ns), local / ns, per);
+    return;
+  }
   const int b = (int)(local / per);
   const uint32_t blk = local - (uint32_t)b * per;
-  const bool hy = a.Y != nullptr;
   if (PHASE == 0) {
     if (hy) any_map_body<SEMI, true>(a, b, blk, per);
     else any_map_body<SEMI, false>(a, b, blk, per);
@@ -926,6 +1187,11 @@ void launch_group(int semi, int phase, const ContractArgs *ops, const uint32_t *
   if (n <= 0 || total_blocks == 0) return;
   hipStream_t s = (hipStream_t)stream;
   dim3 g(total_blocks);
+  if (phase == 6) {
+    if (semi == SEMI_SUM) k_group<SEMI_SUM, 6><<<g, kBlock, 0, s>>>(ops, start, nblk, n);
+    else k_group<SEMI_MAX, 6><<<g, kBlock, 0, s>>>(ops, start, nblk, n);
+    return;
+  }
   if (phase >= 3 && semi == SEMI_MAX) {  // dense max-plus form
     k_group<SEMI_MAX, 3><<<g, kBlock, 0, s>>>(ops, start, nblk, n);
     return;
@@ -948,6 +1214,13 @@ void launch_group(int semi, int phase, const ContractArgs *ops, const uint32_t *
 }
 
 uint32_t map_blocks(const ContractArgs &a) {
+  if (a.kind == 4) {  // one tile per wave (split: per workgroup), grid-stride beyond 256 workgroups
+    const uint32_t TM = a.tile == 1 ? 8 : (a.tile == 2 ? 16 : kIT), TN = a.tile == 1 ? 8 : (a.tile == 2 ? 1 : kIT);
+    const uint32_t tn = a.Y ? (a.nC + TN - 1) / TN : 1;
+    const uint32_t tiles = a.nB * ((a.nM + TM - 1) / TM) * tn;
+    const uint32_t blocks = a.ksplit > 1 ? tiles : (tiles + kBlock / 64 - 1) / (kBlock / 64);
+    return blocks > 256u ? 256u : blocks;
+  }
   if (a.kind == 2)  // one 64 x 64 tile per workgroup
     return a.nB * ((a.nM + kGT - 1) / kGT) * ((a.nC + kGT - 1) / kGT);
   const uint32_t n_out = a.kind == 1 ? a.nR : a.nR * a.nC;
@@ -963,6 +1236,17 @@ void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, co
                      void *stream) {
   hipStream_t s = (hipStream_t)stream;
   const uint32_t n_out = a.nR * a.nC;
+  if (a.kind == 4) {  // nb: groups of 64 instances
+    const dim3 g(map_blocks(a) * nb);
+    if (semi == SEMI_SUM) {
+      if (has_y) k_inter<SEMI_SUM, true><<<g, kBlock, 0, s>>>(d_a);
+      else k_inter<SEMI_SUM, false><<<g, kBlock, 0, s>>>(d_a);
+    } else {
+      if (has_y) k_inter<SEMI_MAX, true><<<g, kBlock, 0, s>>>(d_a);
+      else k_inter<SEMI_MAX, false><<<g, kBlock, 0, s>>>(d_a);
+    }
+    return;
+  }
   if (a.kind == 2) {
     const dim3 g(map_blocks(a), nb);
     if (semi == SEMI_MAX) k_gemm_max<<<g, kBlock, 0, s>>>(d_a);
@@ -1039,9 +1323,6 @@ struct SegShared {
   float m[kSegMaxLocal * (kSegMaxLocal + 1)];
   int32_t kx, kg;
 };
-typedef __attribute__((address_space(1))) const int32_t gint;
-typedef __attribute__((address_space(1))) const uint32_t gu32;
-typedef __attribute__((address_space(1))) const float gcfloat;
 
 __device__ __forceinline__ void seg_prologue(const SegArgs &a, uint32_t o0, bool want_g, SegShared &sh) {
   const int t = threadIdx.x;
@@ -1088,8 +1369,6 @@ __device__ __forceinline__ void seg_prologue(const SegArgs &a, uint32_t o0, bool
 // written by the thread.
 static constexpr int kSegIter = kSegMaxLocal * kSegOB / kSegThreads;
 
-// carriers are read and written through global-address-space pointers
-typedef __attribute__((address_space(1))) float gfloat;
 
 // (entry, outer assignment) of task t
 template <bool OUTER_FAST>
@@ -1512,7 +1791,9 @@ __global__ __launch_bounds__(kBlock) void k_prepare(PrepareArgs a) {
   const LeafDesc d = a.leaves[blockIdx.x];
   if (!d.batched && b > 0) return;
   const int row = d.batched ? b : 0;
-  float *dst = a.arena + d.dst + (d.batched ? (int64_t)b * d.size : 0);
+  // element stride: interleaved batched leaves hold element i of instance b at i * max_batch + b
+  const int64_t es = d.batched && a.interleaved ? a.max_batch : 1;
+  float *dst = a.arena + d.dst + (d.batched ? (a.interleaved ? (int64_t)b : (int64_t)b * d.size) : 0);
   const float one = d.maxdom ? 0.f : 1.f;
   const float zero = d.maxdom ? -INFINITY : 0.f;
   float lmax = 0.f;
@@ -1523,15 +1804,15 @@ __global__ __launch_bounds__(kBlock) void k_prepare(PrepareArgs a) {
     const float *src = a.arena + d.src + base;
     for (int i = threadIdx.x; i < d.size; i += kBlock) {
       const float v = src[a.gmap[d.gmap + i]];
-      dst[i] = v;
+      dst[i * es] = v;
       lmax = fmaxf(lmax, fabsf(v));
     }
   } else if (d.kind == 1) {
-    for (int i = threadIdx.x; i < d.size; i += kBlock) dst[i] = one;
+    for (int i = threadIdx.x; i < d.size; i += kBlock) dst[i * es] = one;
     lmax = 1.f;
   } else {
     const int e = a.evidence[(int64_t)row * a.n_vars + d.var];
-    for (int i = threadIdx.x; i < d.size; i += kBlock) dst[i] = (e < 0 || e == i) ? one : zero;
+    for (int i = threadIdx.x; i < d.size; i += kBlock) dst[i * es] = (e < 0 || e == i) ? one : zero;
     lmax = 1.f;
   }
   __shared__ float sm[kBlock / 64];
@@ -1583,9 +1864,10 @@ __global__ void k_marg(const float *arena, const MargDesc *d, int n, int batch, 
   const float *adj = arena + m.adj + (m.adj_batched ? (int64_t)b * m.adj_bs : 0);
   const float *lam = arena + m.leaf + (m.leaf_batched ? (int64_t)b * m.leaf_bs : 0);
   double tot = 0.0;
-  for (int x = 0; x < m.card; ++x) tot += (double)adj[x] * (double)lam[x];
+  for (int x = 0; x < m.card; ++x) tot += (double)adj[x * m.adj_es] * (double)lam[x * m.leaf_es];
   for (int x = 0; x < m.card; ++x)
-    out[(int64_t)b * row + m.out + x] = tot > 0.0 ? (double)adj[x] * (double)lam[x] / tot : 0.0;
+    out[(int64_t)b * row + m.out + x] =
+        tot > 0.0 ? (double)adj[x * m.adj_es] * (double)lam[x * m.leaf_es] / tot : 0.0;
 }
 
 void launch_marg(const float *arena, const MargDesc *d, int n, int batch, int row, double *out,
@@ -1641,7 +1923,7 @@ __device__ __forceinline__ void back_step(const int32_t *__restrict__ iarena, co
     off += (int64_t)xv * pairs[2 * i + 1];
   }
   if (!ok) return;  // an input left unassigned: leave this step's outputs unset
-  int32_t k = iarena[s.arg + (int64_t)b * s.bs + off];
+  int32_t k = iarena[s.arg + (int64_t)b * s.bs + off * s.es];
   for (int j = s.out_end - 1; j >= s.out_begin; --j) {
     const int c = pairs[2 * j + 1];
     x[pairs[2 * j]] = k % c;

@@ -14,8 +14,9 @@ namespace tn {
 
 // A tensor resident in the float arena.  Values are row-major over the
 // sorted labels (last label fastest); batched tensors hold one copy per
-// instance (instance outermost).  Sum-product tensors carry a scaling slot:
-// value = raw * 2^ex[slot (+ instance)].
+// instance, instance outermost (element e of instance b at b * size + e) or,
+// in interleaved plans, innermost (at e * max_batch + b).  Sum-product
+// tensors carry a scaling slot: value = raw * 2^ex[slot (+ instance)].
 struct TensorBuf {
   Labels lab;
   int64_t size = 1;      // elements per instance
@@ -35,7 +36,8 @@ struct Op {
   int semi = SEMI_SUM;
   int X = -1, Y = -1, Z = -1, I = -1;  // tensor ids; I = argmax IntBuf id
   bool split = false;
-  int nb = 1;
+  int nb = 1;                         // grid rows: instances (interleaved form: groups of 64)
+  int inst = 1;                       // instances computed
   ContractArgs a;                     // pointers filled after allocation
   // table offsets into the host table store (-1 = unused)
   int64_t t_rX[2], t_rY[2], t_rZ[2], t_cY[2], t_cZ[2], t_sX[2], t_sY[2];
@@ -48,7 +50,8 @@ struct Op {
   // written, for scheduling
   int seg = -1, seg_kind = 0;
   std::vector<int> ins, outs;
-  int forms = 0;                      // eligible kernel forms: 1 generic, 2 row, 4 dense, 8 wave
+  int forms = 0;                      // eligible kernel forms: 1 generic, 2 row, 4 dense, 8 wave,
+                                      // 16 interleaved
 };
 
 // Host description of a fused segment (tables as offsets into the plan's
@@ -78,6 +81,7 @@ struct Launch {
   int semi = SEMI_SUM;
   bool split = false;
   bool gemm = false;                  // dense-form contractions (matrix cores)
+  bool inter = false;                 // interleaved-form contractions
   bool seg = false;                   // fused-segment kernels (carrier kinds alone)
   int seg_kind = 0;
   std::vector<int> ops;               // indices into the op list
@@ -124,6 +128,7 @@ struct tn_plan_impl {
   std::vector<int> card;
   int mode = 0;
   int max_batch = 1;
+  bool inter = false;                  // batched tensors interleaved (instance fastest)
   bool want_sum = false, want_max = false, want_grad = false, is_mmap = false;
   std::vector<int> observed;           // mode SLICED
   std::vector<char> is_obs;

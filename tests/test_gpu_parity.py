@@ -117,6 +117,71 @@ def test_batched_indicators_small(T):
     assert np.allclose(lz3, lz[:3], rtol=0, atol=1e-9)
 
 
+def test_interleaved_layout_against_oracle(T):
+    """Interleaved instances (lane = instance): 70 evidence sets, so two
+    groups of 64 lanes with a ragged second group; sampled instances against
+    the oracle, every instance against the instance-major layout; batched MAP
+    bit for bit against the oracle's FP32 emulation and across layouts."""
+    bn = W.random_bn(120, 3)
+    B = 70
+    ev = W.bn_evidence_batch(bn, B, seed=7)
+    P = T.Plan(T.Network(bn), evidence_mode=T.EVIDENCE_INDICATOR, max_batch=B, semirings=T.SUM_PRODUCT,
+               batch_layout=T.LAYOUT_INTERLEAVED)
+    info = P.info()
+    assert info["batch_stride"] == 128 and info["n_interleaved"] > 0 and info["n_dense"] == 0
+    lz, m = P.marginals(ev, batch=B)
+    for b in (0, 1, 63, 64, B - 1):
+        want_lz, want_m, *_ = oracle.marginals(bn, ev[b], mode="indicator")
+        assert rel(lz[b], want_lz) <= 1e-5, b
+        got = P.split_marginals(m[b])
+        assert max(np.abs(x - y).max() for x, y in zip(got, want_m)) <= 1e-5, b
+    Q = T.Plan(T.Network(bn), evidence_mode=T.EVIDENCE_INDICATOR, max_batch=B, semirings=T.SUM_PRODUCT,
+               batch_layout=T.LAYOUT_INSTANCE_MAJOR)
+    lz2, m2 = Q.marginals(ev, batch=B)
+    assert np.abs(lz - lz2).max() <= 1e-5 * max(1.0, np.abs(lz2).max())
+    assert np.abs(m - m2).max() <= 1e-5
+    # fewer instances than max_batch
+    lz3 = P.log_z(ev[:5], batch=5)
+    assert np.allclose(lz3, lz[:5], rtol=0, atol=1e-9)
+    # batched MAP on the oracle's tree
+    lvs = {b: oracle.build_leaves(bn, ev[b], "indicator", domain="log") for b in (0, 64, B - 1)}
+    pairs = oracle.default_tree(lvs[0])
+    Pm = T.Plan(T.Network(bn), evidence_mode=T.EVIDENCE_INDICATOR, max_batch=B, semirings=T.MAX_PLUS,
+                batch_layout=T.LAYOUT_INTERLEAVED, tree=pairs)
+    Qm = T.Plan(T.Network(bn), evidence_mode=T.EVIDENCE_INDICATOR, max_batch=B, semirings=T.MAX_PLUS,
+                batch_layout=T.LAYOUT_INSTANCE_MAJOR, tree=pairs)
+    lp, x = Pm.map(ev, batch=B)
+    lq, xq = Qm.map(ev, batch=B)
+    assert np.array_equal(x, xq) and np.array_equal(lp.astype(np.float32), lq.astype(np.float32))
+    for b, lv in lvs.items():
+        v32, x32 = oracle.max_forward(lv, pairs, fp32=True)
+        assert np.array_equal(x[b], x32), b
+        assert np.float32(lp[b]) == np.float32(v32), b
+
+
+def test_bn500x512_full_size_sampled(T):
+    """The batched workload at full size (500 variables, 512 evidence sets,
+    one pass in the layout and launch configuration the benchmark times):
+    sampled instances against the oracle, invariants on all of them."""
+    c = W.config(3, 0)
+    bn, ev = c["net"], c["evidence"]
+    B = ev.shape[0]
+    P = T.Plan(T.Network(bn), evidence_mode=T.EVIDENCE_INDICATOR, max_batch=B, semirings=T.SUM_PRODUCT)
+    assert P.info()["n_interleaved"] > 0
+    lz, m = P.marginals(ev, batch=B)
+    assert np.all(np.isfinite(lz))
+    for b in (0, 255, B - 1):
+        want_lz, want_m, *_ = oracle.marginals(bn, ev[b], mode="indicator")
+        assert rel(lz[b], want_lz) <= 1e-5, b
+        got = P.split_marginals(m[b])
+        assert max(np.abs(x - y).max() for x, y in zip(got, want_m)) <= 1e-5, b
+    for b in range(B):  # every variable's marginal sums to one, observed ones are one-hot
+        got = P.split_marginals(m[b])
+        assert max(abs(g.sum() - 1.0) for g in got) <= 1e-5, b
+        for v in np.nonzero(ev[b] >= 0)[0]:
+            assert got[v][ev[b][v]] == 1.0, (b, v)
+
+
 @pytest.mark.parametrize("seed", [0, 4])
 def test_dense_form_against_oracle(T, seed):
     """Bayesian networks whose trees hold dense contractions (matrix-core
@@ -133,7 +198,8 @@ def test_dense_form_against_oracle(T, seed):
     c = W.config(3, seed=seed, small=True)
     bn, ev = c["net"], c["evidence"]
     B = ev.shape[0]
-    P = T.Plan(T.Network(bn), evidence_mode=T.EVIDENCE_INDICATOR, max_batch=B, semirings=T.SUM_PRODUCT)
+    P = T.Plan(T.Network(bn), evidence_mode=T.EVIDENCE_INDICATOR, max_batch=B, semirings=T.SUM_PRODUCT,
+               batch_layout=T.LAYOUT_INSTANCE_MAJOR)
     assert P.info()["n_dense"] > 0
     lz, m = P.marginals(ev, batch=B)
     for b in (0, B // 2, B - 1):
@@ -181,7 +247,7 @@ def test_autotuned_plans_against_oracle(T):
     bn, ev = c["net"], c["evidence"]
     B = ev.shape[0]
     P = T.Plan(T.Network(bn), evidence_mode=T.EVIDENCE_INDICATOR, max_batch=B, semirings=T.SUM_PRODUCT,
-               autotune=True)
+               autotune=True, batch_layout=T.LAYOUT_INSTANCE_MAJOR)
     lz, m = P.marginals(ev, batch=B)
     for b in (0, B - 1):
         want_lz, want_m, *_ = oracle.marginals(bn, ev[b], mode="indicator")
