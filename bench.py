@@ -155,6 +155,14 @@ def bench_bn500x512(args, T, W, np, sync):
     sec1, _ = timed(lambda: [one.marginals(ev[b:b + 1], batch=1) for b in range(n1)], 1, 1,
                     lambda: (one.sync(), sync()))
     lz1 = np.array([one.marginals(ev[b:b + 1], batch=1)[0][0] for b in range(4)])
+    # the batched form with BF16 operands on the matrix cores (instance-major
+    # layout, dense contractions on MFMA, FP32 accumulation and storage)
+    lp_plan = None
+    if args.dtype == "f32":
+        lp_plan = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, evidence_mode=T.EVIDENCE_INDICATOR, max_batch=B,
+                         use_graph=not args.no_graph, dtype=T.TN_BF16, batch_layout=T.LAYOUT_INSTANCE_MAJOR)
+        sec_lp, (lz_lp, m_lp) = timed(lambda: lp_plan.marginals(ev, batch=B), max(3, args.steps // 2), args.warmup,
+                                      lambda: (lp_plan.sync(), sync()))
     out = dict(value=round(B / sec, 1), unit="instance-solves/s", ms_per_step=round(sec * 1e3, 4),
                dtype=args.dtype,
                config=dict(workload="bn500 x 512 evidence sets, logZ+all-marginals, batched indicator pass",
@@ -166,21 +174,33 @@ def bench_bn500x512(args, T, W, np, sync):
                tflops=round(flops / sec / 1e12, 4), roofline=roof, kernels=kernels,
                per_instance_fp32=dict(value=round(n1 / sec1, 2), unit="instance-solves/s",
                                       max_log_z_diff_vs_batched=float(np.abs(lz1 - lz[:4]).max())))
+    if lp_plan is not None:
+        out["batched_bf16_mfma"] = dict(value=round(B / sec_lp, 1), unit="instance-solves/s",
+                                        ms_per_step=round(sec_lp * 1e3, 4), layout="instance_major",
+                                        dense_nodes=lp_plan.info()["n_dense"])
     if not args.no_cpu_baseline:
         import oracle
         n_o, t0 = 0, time.perf_counter()
-        errs = []
+        errs, errs_lp = [], []
         while n_o < 64 and time.perf_counter() - t0 < 20.0:
             lz_o, marg_o, *_ = oracle.marginals(net, ev[n_o], mode="indicator")
             got = plan.split_marginals(m[n_o])
             errs.append((abs(lz[n_o] - lz_o) / max(1.0, abs(lz_o)),
                          max(np.abs(a - b).max() for a, b in zip(got, marg_o))))
+            if lp_plan is not None:
+                got = lp_plan.split_marginals(m_lp[n_o])
+                errs_lp.append((abs(lz_lp[n_o] - lz_o) / max(1.0, abs(lz_o)),
+                                max(np.abs(a - b).max() for a, b in zip(got, marg_o))))
             n_o += 1
         d = time.perf_counter() - t0
         out["cpu_baseline"] = dict(value=n_o / d, unit="instance-solves/s", cores=1, kind="oracle",
                                    sample="first %d of the 512 evidence sets, single-threaded FP64, %.1f s" % (n_o, d))
         out["err_vs_oracle"] = dict(log_z_rel=float(max(e[0] for e in errs)),
                                     marginal_max_abs=float(max(e[1] for e in errs)), instances=n_o)
+        if errs_lp:
+            out["batched_bf16_mfma"]["err_vs_oracle"] = dict(
+                log_z_rel=float(max(e[0] for e in errs_lp)), marginal_max_abs=float(max(e[1] for e in errs_lp)),
+                instances=n_o)
     return out
 
 

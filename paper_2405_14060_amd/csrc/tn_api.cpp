@@ -1490,6 +1490,18 @@ static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
     p->planner_used = pc.planner;
   }
   auto lab = node_labels(p->leaf_lab, p->pairs, {}, p->n_vars);
+  if (p->inter) {
+    // interleaved rows are addressed with 32-bit byte offsets: every batched
+    // tensor (largest node or leaf, all instances) must stay below 2 GiB
+    double big = std::exp2(p->stats.sc);
+    for (const auto &l : p->leaf_lab) big = std::max(big, (double)numel(l, p->card));
+    if (big * p->max_batch * 4.0 >= 2147483648.0) {
+      if (o->batch_layout == 2)
+        throw TnError(TN_E_TOO_LARGE, "interleaved layout: a batched tensor would exceed 2 GiB");
+      p->inter = false;
+      p->max_batch = std::max(1, o->max_batch);
+    }
+  }
   if (o->max_log2_size > 0 && p->stats.sc > o->max_log2_size + 1e-9)
     throw TnError(TN_E_UNSUPPORTED, "slicing is available for MMAP plans; increase max_log2_size");
   // leaf tensors and descriptors

@@ -936,16 +936,23 @@ __device__ __forceinline__ void inter_tiles(const ContractArgs &a, const int sla
   gfloat *__restrict__ Zp = (gfloat *)a.Z;
   gint_w *__restrict__ Ip = (gint_w *)a.I;
   const int64_t esZ = a.esZ;
-  float sx = 1.f, sy = 1.f;
-  int kx = 0, ky = 0;
+  // operand maxima (one word per lane for batched operands) and, for the
+  // wave that writes the output exponent, the operands' exponents: issued
+  // here, first used after the first tile's offset loads are in flight
+  uint32_t mxX = 0, mxY = 0;
+  int exX = 0, exY = 0;
+  const bool ex_writer = SEMI == SEMI_SUM && blk == 0 && w == 0;
   if (SEMI == SEMI_SUM) {
-    kx = max_exponent(a.batX ? ((gu32 *)a.mx)[a.slotX + b] : read_max(a.mx, a.mx_stride, a.slotX));
-    sx = ldexpf(1.f, -kx);
-    if (HASY) {
-      ky = max_exponent(a.batY ? ((gu32 *)a.mx)[a.slotY + b] : read_max(a.mx, a.mx_stride, a.slotY));
-      sy = ldexpf(1.f, -ky);
+    mxX = a.batX ? ((gu32 *)a.mx)[a.slotX + b] : read_max(a.mx, a.mx_stride, a.slotX);
+    if (HASY) mxY = a.batY ? ((gu32 *)a.mx)[a.slotY + b] : read_max(a.mx, a.mx_stride, a.slotY);
+    if (ex_writer) {
+      exX = ((gint *)a.ex)[a.slotX + (a.batX ? b : 0)];
+      if (HASY) exY = ((gint *)a.ex)[a.slotY + (a.batY ? b : 0)];
     }
   }
+  float sx = 1.f, sy = 1.f;
+  int kx = 0, ky = 0;
+  bool scaled = false;
   const uint32_t nM = a.nM, nC = a.nC, nS = a.nS, nSl = a.nSl;
   const uint32_t tm = (nM + TM - 1) / TM, tn = (nC + TN - 1) / TN;
   const uint32_t ntiles = a.nB * tm * tn;
@@ -975,6 +982,15 @@ __device__ __forceinline__ void inter_tiles(const ContractArgs &a, const int sla
       v0 = tab_off(a.gbX, bt, a.nBl);
       v1 = HASY ? tab_off(a.gbY, bt, a.nBl) : 0;
       v2 = tab_off(a.gbZ, bt, a.nBl);
+    }
+    if (SEMI == SEMI_SUM && !scaled) {
+      kx = max_exponent(mxX);
+      sx = ldexpf(1.f, -kx);
+      if (HASY) {
+        ky = max_exponent(mxY);
+        sy = ldexpf(1.f, -ky);
+      }
+      scaled = true;
     }
     const int32_t xb = bcast(v0, 63), yb = bcast(v1, 63), zb = bcast(v2, 63);
     int32_t xm[TM], zm[TM], yn[TN], zn[TN];
@@ -1085,13 +1101,19 @@ __device__ __forceinline__ void inter_tiles(const ContractArgs &a, const int sla
   }
   if (SEMI == SEMI_SUM) {
     // this wave's maximum per instance, recorded in sub-slot 0 of the
-    // instance's slot (guarded: maxima only grow within a launch)
+    // instance's slot; with many waves per group of instances the atomic is
+    // skipped where the stored maximum is already larger (maxima only grow
+    // within a launch)
     uint32_t *slot = a.mx + a.slotZ + b;
-    if (lmax > 0.f && __uint_as_float(*(volatile uint32_t *)slot) < lmax) atomicMax(slot, __float_as_uint(lmax));
-    if (blk == 0 && w == 0) {
-      int e = ((gint *)a.ex)[a.slotX + (a.batX ? b : 0)] + kx;
-      if (HASY) e += ((gint *)a.ex)[a.slotY + (a.batY ? b : 0)] + ky;
-      ((gint_w *)a.ex)[a.slotZ + b] = e;
+    const bool guard = tstep > 16;
+    if (lmax > 0.f && (!guard || __uint_as_float(*(volatile uint32_t *)slot) < lmax))
+      atomicMax(slot, __float_as_uint(lmax));
+    if (ex_writer) {
+      if (!scaled) {
+        kx = max_exponent(mxX);
+        ky = HASY ? max_exponent(mxY) : 0;
+      }
+      ((gint_w *)a.ex)[a.slotZ + b] = exX + kx + (HASY ? exY + ky : 0);
     }
   }
 }
@@ -1790,10 +1812,41 @@ __global__ __launch_bounds__(kBlock) void k_prepare(PrepareArgs a) {
   }
   const LeafDesc d = a.leaves[blockIdx.x];
   if (!d.batched && b > 0) return;
+  if (d.batched && a.interleaved) {
+    // one thread per instance: element i of instance bi at i * max_batch + bi
+    const int bi = b * kBlock + threadIdx.x;
+    if (bi >= a.max_batch) return;
+    gfloat *dst = (gfloat *)(a.arena + d.dst) + bi;
+    const int64_t es = a.max_batch;
+    float m = 1.f;
+    if (d.kind == 0) {
+      int64_t base = 0;
+      for (int o = d.obs_begin; o < d.obs_end; ++o)
+        base += (int64_t)a.evidence[(int64_t)bi * a.n_vars + a.obs[2 * o]] * a.obs[2 * o + 1];
+      const float *src = a.arena + d.src + base;
+      m = 0.f;
+      for (int i = 0; i < d.size; ++i) {
+        const float v = src[a.gmap[d.gmap + i]];
+        dst[i * es] = v;
+        m = fmaxf(m, fabsf(v));
+      }
+    } else if (d.kind == 1) {
+      const float one = d.maxdom ? 0.f : 1.f;
+      for (int i = 0; i < d.size; ++i) dst[i * es] = one;
+    } else {
+      const float one = d.maxdom ? 0.f : 1.f, zero = d.maxdom ? -INFINITY : 0.f;
+      const int e = a.evidence[(int64_t)bi * a.n_vars + d.var];
+      for (int i = 0; i < d.size; ++i) dst[i * es] = (e < 0 || e == i) ? one : zero;
+    }
+    if (d.slot >= 0) {
+      a.mx[d.slot + bi] = __float_as_uint(m);
+      a.ex[d.slot + bi] = 0;
+    }
+    return;
+  }
   const int row = d.batched ? b : 0;
   // element stride: interleaved batched leaves hold element i of instance b at i * max_batch + b
-  const int64_t es = d.batched && a.interleaved ? a.max_batch : 1;
-  float *dst = a.arena + d.dst + (d.batched ? (a.interleaved ? (int64_t)b : (int64_t)b * d.size) : 0);
+  float *dst = a.arena + d.dst + (d.batched ? (int64_t)b * d.size : 0);
   const float one = d.maxdom ? 0.f : 1.f;
   const float zero = d.maxdom ? -INFINITY : 0.f;
   float lmax = 0.f;
@@ -1804,15 +1857,15 @@ __global__ __launch_bounds__(kBlock) void k_prepare(PrepareArgs a) {
     const float *src = a.arena + d.src + base;
     for (int i = threadIdx.x; i < d.size; i += kBlock) {
       const float v = src[a.gmap[d.gmap + i]];
-      dst[i * es] = v;
+      dst[i] = v;
       lmax = fmaxf(lmax, fabsf(v));
     }
   } else if (d.kind == 1) {
-    for (int i = threadIdx.x; i < d.size; i += kBlock) dst[i * es] = one;
+    for (int i = threadIdx.x; i < d.size; i += kBlock) dst[i] = one;
     lmax = 1.f;
   } else {
     const int e = a.evidence[(int64_t)row * a.n_vars + d.var];
-    for (int i = threadIdx.x; i < d.size; i += kBlock) dst[i * es] = (e < 0 || e == i) ? one : zero;
+    for (int i = threadIdx.x; i < d.size; i += kBlock) dst[i] = (e < 0 || e == i) ? one : zero;
     lmax = 1.f;
   }
   __shared__ float sm[kBlock / 64];
@@ -1829,8 +1882,9 @@ __global__ __launch_bounds__(kBlock) void k_prepare(PrepareArgs a) {
 
 void launch_prepare(const PrepareArgs &a, void *stream) {
   const int reset_blocks = (a.reset_end - a.reset_begin + kBlock - 1) / kBlock;
+  // interleaved batched leaves take one thread per instance
   dim3 g(a.n_leaves + (reset_blocks > 0 ? (reset_blocks > 1024 ? 1024 : reset_blocks) : 0),
-         a.batch);
+         a.interleaved ? (a.batch + kBlock - 1) / kBlock : a.batch);
   if (g.x == 0) return;
   k_prepare<<<g, kBlock, 0, (hipStream_t)stream>>>(a);
 }
