@@ -109,10 +109,10 @@ typedef struct {
                                 may then be called */
   int32_t no_fuse;           /* keep every tree node a separate contraction */
   int32_t autotune;          /* 1: at plan time, time every eligible kernel form
-                                (generic, row, wave, dense; interleaved with or
-                                without the workgroup split of the summed
-                                range) of each distinct contraction shape on
-                                the device and keep the fastest; 0: fixed rules */
+                                (generic, row, wave, dense) of each distinct
+                                contraction shape on the device and keep the
+                                fastest; 0: fixed rules.  The interleaved
+                                layout's tile variants always follow rules. */
   int32_t batch_layout;      /* batched evidence (mode INDICATOR, max_batch > 1):
                                 0 automatic (interleaved for dtype TN_F32),
                                 1 instance-major (each instance's tensor

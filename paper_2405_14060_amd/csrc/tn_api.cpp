@@ -294,6 +294,11 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
     a.tile = 0;
     if (a.ksplit == 1 && (op.forms & 64)) a.tile = 1;
     else if (a.ksplit == 1 && (op.forms & 128)) a.tile = 2;
+    // the variants are not offered to the autotuner: timed alone a variant
+    // does not predict its cost inside a grouped stage launch (measured on
+    // the 512-set network: per-shape choices by isolated timing were 5 %
+    // slower than these rules)
+    op.forms = 16;
     op.flops = 2.0 * (double)n_out * (double)a.nS;
     op.bytes = 4.0 * (double)(p->T[X].size + (Y >= 0 ? p->T[Y].size : 0) + p->T[Z].size);
     return op;

@@ -892,8 +892,8 @@ __global__ __launch_bounds__(kBlock) void k_gemm(const ContractArgs *__restrict_
 // offsets are fetched 64 at a time, one per lane, and broadcast with
 // readlane; tile offsets likewise.  Edge tiles repeat their last row /
 // column (loads stay in bounds, the copies are never stored), so the inner
-// loop has no branches and several summed entries' loads are in flight at
-// once.  Tile variants (a.tile): 0 = 4 x 4, 1 = 8 x 8, 2 = 16 x 1.  With
+// loop has no branches; it is software-pipelined (the rows of the next one
+// or two summed entries are loaded while the current ones are multiplied).  Tile variants (a.tile): 0 = 4 x 4, 1 = 8 x 8, 2 = 16 x 1.  With
 // ksplit = 4 (4 x 4 tiles) the four waves of a workgroup share one tile and
 // split the summed range in four consecutive parts, folded in wave order
 // through LDS (deterministic; for max-plus the earlier part wins ties, which
@@ -925,7 +925,6 @@ __device__ __forceinline__ void inter_tiles(const ContractArgs &a, const int sla
                                             const uint32_t nblk) {
   constexpr int TN = HASY ? TN0 : 1;  // without Y there are no column labels
   constexpr int NW = kBlock / 64;
-  constexpr int UNROLL = TM * TN >= 64 ? 2 : 4;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int b = slab * kInterLanes + lane;
   // uniform bases at this group's first instance; the lane offset is a constant
@@ -1050,13 +1049,59 @@ __device__ __forceinline__ void inter_tiles(const ContractArgs &a, const int sla
         if (HASY) oy = tab_off(a.sY, s0 + lane, nSl);
       }
       const int cnt = (int)min(64u, se - s0);
-      int k = 0;
-      for (; k + UNROLL <= cnt; k += UNROLL) {
+      // software pipeline over groups of G summed entries: the rows of the
+      // next group are in flight while the current group is multiplied
+      constexpr int G = TM * TN >= 64 ? 1 : 2;
+      float xa[G][TM], ya[G][TN], xb2[G][TM], yb2[G][TN];
+      auto load = [&](float (&xv)[G][TM], float (&yv)[G][TN], int k) {
 #pragma unroll
-        for (int u = 0; u < UNROLL; ++u)
-          step(bcast(ox, k + u), HASY ? bcast(oy, k + u) : 0, (int32_t)(s0 + k + u));
+        for (int g = 0; g < G; ++g) {
+          const int32_t xs = bcast(ox, k + g), ys = HASY ? bcast(oy, k + g) : 0;
+#pragma unroll
+          for (int i = 0; i < TM; ++i) xv[g][i] = ld_row(rX, vx, (xm[i] + xs) * esX);
+#pragma unroll
+          for (int j = 0; j < TN; ++j) yv[g][j] = HASY ? ld_row(rY, vy, (yn[j] + ys) * esY) : 0.f;
+        }
+      };
+      auto compute = [&](float (&xv)[G][TM], float (&yv)[G][TN], int32_t s) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          if (SEMI == SEMI_SUM) {
+#pragma unroll
+            for (int i = 0; i < TM; ++i) xv[g][i] *= sx;
+#pragma unroll
+            for (int j = 0; j < TN; ++j) yv[g][j] *= sy;
+          }
+#pragma unroll
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+              if (SEMI == SEMI_SUM) {
+                if (HASY) acc[i][j] = fmaf(xv[g][i], yv[g][j], acc[i][j]);
+                else acc[i][j] += xv[g][i];
+              } else {
+                const float v = HASY ? xv[g][i] + yv[g][j] : xv[g][i];
+                if (s + g == 0 || v > acc[i][j]) {
+                  acc[i][j] = v;
+                  arg[i][j] = s + g;
+                }
+              }
+            }
+        }
+      };
+      const int ng = cnt / G;
+      if (ng > 0) {
+        load(xa, ya, 0);
+        int q = 0;
+        for (; q + 2 <= ng; q += 2) {
+          load(xb2, yb2, (q + 1) * G);
+          compute(xa, ya, (int32_t)(s0 + q * G));
+          if (q + 2 < ng) load(xa, ya, (q + 2) * G);
+          compute(xb2, yb2, (int32_t)(s0 + (q + 1) * G));
+        }
+        if (q < ng) compute(xa, ya, (int32_t)(s0 + q * G));
       }
-      for (; k < cnt; ++k) step(bcast(ox, k), HASY ? bcast(oy, k) : 0, (int32_t)(s0 + k));
+      for (int k = ng * G; k < cnt; ++k) step(bcast(ox, k), HASY ? bcast(oy, k) : 0, (int32_t)(s0 + k));
     }
     if (SPLIT && split) {
       __shared__ InterShared<TM, TN> red;
