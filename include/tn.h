@@ -138,7 +138,8 @@ typedef struct {
   double bytes_fwd;              /* algorithmic bytes of one forward */
   int32_t n_sliced;              /* sliced labels */
   int32_t planner_used;          /* TN_PLANNER_* that won */
-  int64_t device_bytes;          /* device memory held by the plan */
+  int64_t device_bytes;          /* device memory held by the plan (host_only plans: the
+                                    float arena it would allocate) */
   int32_t n_launches_fwd;        /* kernel launches after stage grouping */
   int32_t n_launches_bwd;
   int32_t n_launches_max;
@@ -266,7 +267,9 @@ typedef struct {
   double flops, bytes, ms;
 } tn_op_profile;
 
-/* task: 0 log Z, 1 log Z + marginals, 2 MAP.  Runs the task reps times
+/* task: 0 log Z, 1 log Z + marginals, 2 MAP, 3 (MMAP plans) the sum phase of
+ * every group for its first slice (sliced variables at 0; evidence one row;
+ * batch ignored).  Runs the task reps times
  * without graph capture and fills out[0..min(cap, n)-1]; *n_ops = n. */
 tn_status tn_profile(tn_plan_t *plan, int32_t task, int32_t batch, const int32_t *evidence,
                      int32_t reps, tn_op_profile *out, int32_t cap, int32_t *n_ops);

@@ -1655,6 +1655,8 @@ extern "C" tn_status tn_plan_info_get(const tn_plan_t *p, tn_plan_info *info) {
     info->n_sliced = (int32_t)p->sliced.size();
     info->planner_used = p->planner_used;
     info->device_bytes = p->device_bytes;
+    if (p->opts.host_only)  // planned only: the float arena the plan would hold
+      for (const auto &t : p->T) info->device_bytes += 4 * t.size * (t.batched ? p->max_batch : 1);
     auto count = [](const Schedule &sc) {
       int n = 0;
       for (const Launch &L : sc.launches) n += L.split ? 2 : 1;
@@ -2238,11 +2240,27 @@ static tn_status profile_impl(tn_plan_t *p, int32_t task, int32_t batch, const i
                               tn_op_profile *out, int32_t cap, int32_t *n_ops, int32_t kind_only) {
   return guard([&] {
     if (!p || reps < 1) throw TnError(TN_E_INVALID, "bad argument");
-    if (p->is_mmap) throw TnError(TN_E_UNSUPPORTED, "profile of MMAP plans");
+    if (p->is_mmap != (task == 3)) throw TnError(TN_E_UNSUPPORTED, "task 3 is the profile of MMAP plans");
     if ((task <= 1 && !p->want_sum) || (task == 2 && !p->want_max)) throw TnError(TN_E_UNSUPPORTED, "task not in plan");
-    check_batch(p, batch);
-    if (p->mode == TN_EVIDENCE_SLICED && batch != 1) throw TnError(TN_E_INVALID, "profile one instance at a time");
-    upload_evidence(p, batch, evidence);
+    std::vector<int32_t> slice_row;
+    if (task == 3) {
+      // sum phase of every group for its first slice (sliced variables at 0)
+      slice_row.assign(p->n_vars, -1);
+      for (int v = 0; v < p->n_vars; ++v) {
+        const int e = evidence ? evidence[v] : -1;
+        if (e < -1 || e >= p->card[v] || (e >= 0) != (bool)p->is_obs[v])
+          throw TnError(TN_E_INVALID, "evidence must give exactly the plan's observed variables");
+        slice_row[v] = e;
+      }
+      for (int v : p->sliced) slice_row[v] = 0;
+      hip_check(hipMemcpyAsync(p->d_evidence, slice_row.data(), slice_row.size() * 4, hipMemcpyHostToDevice, p->stream),
+                "slice");
+      hip_check(hipStreamSynchronize(p->stream), "slice");
+    } else {
+      check_batch(p, batch);
+      if (p->mode == TN_EVIDENCE_SLICED && batch != 1) throw TnError(TN_E_INVALID, "profile one instance at a time");
+      upload_evidence(p, batch, evidence);
+    }
     // launch list: (kind, flops, bytes, launcher)
     struct L {
       int kind;
@@ -2289,6 +2307,16 @@ static tn_status profile_impl(tn_plan_t *p, int32_t task, int32_t batch, const i
         ls.push_back({5, 0, 0, [p] {
                         launch_marg(p->arena, p->d_marg_desc, (int)p->marg.size(), p->max_batch, p->marg_row,
                                     p->d_marg, p->stream);
+                      }});
+      }
+    } else if (task == 3) {
+      int32_t *acc_ex = p->iarena + p->iarena_ints;
+      for (size_t g = 0; g < p->groups.size(); ++g) {
+        ls.push_back({4, 0, 0, [p, g] { launch_prepare_set(p, p->group_leaves[g], p->d_group_leaves[g], true); }});
+        add_ops(p->groups[g].ops, p->sched_groups[g]);
+        ls.push_back({5, 0, 0, [p, g, acc_ex] {
+                        const TensorBuf &r = p->T[p->groups[g].root];
+                        launch_slice_acc(p->arena + r.off, p->mx, p->ex, r.slot, p->d_acc, acc_ex, r.size, 1, p->stream);
                       }});
       }
     } else {

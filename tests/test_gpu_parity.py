@@ -461,6 +461,40 @@ def test_mmap_sliced(T):
     if ogap > 1e-4:
         assert np.array_equal(x, ox) and np.array_equal(x0, ox)
     assert abs(val - ov) <= 1e-5 * max(1, abs(ov))
+    # one-slice profile of the sum phase (the benchmark's projection): its
+    # launches carry the per-slice work, and a solve afterwards is unchanged
+    prof = P.profile(3, reps=2)
+    kinds = [k for k, _, _, _ in prof]
+    assert kinds[0] == 4 and sum(fl for _, fl, _, _ in prof) > 0 and all(ms >= 0 for *_, ms in prof)
+    val2, x2 = P.mmap()
+    assert np.array_equal(x2, x) and val2 == val
+
+
+def test_regular3_220_mmap_full_size(T):
+    """The MMAP workload at full size (220 binary variables on a 3-regular
+    graph, 25 query variables, sum phase sliced to intermediates <= 2^28,
+    2048 slices), in the configuration the benchmark times.  The oracle cannot
+    contract it, so the answer is certified by properties that hold at any
+    size: the oracle's log p(Q = answer) (the network with the query observed
+    is small) equals the reported value, and no single flip of a query
+    variable scores higher (all 26 candidates scored by a GPU plan with the
+    query observed, whose first score is itself checked against the oracle)."""
+    c = W.config(4, 0)
+    net, q = c["net"], np.asarray(c["query"])
+    P = T.Plan(T.Network(net), query=q, max_log2_size=28, use_graph=False)
+    assert P.info()["n_sliced"] >= 8 and P.info()["sc"] <= 28
+    val, x = P.mmap()
+    ev = -np.ones(net.n_vars, np.int32)
+    ev[q] = x
+    lp = oracle.log_z(net, ev, mode="slice")
+    assert abs(val - lp) <= 1e-5 * max(1.0, abs(lp)), (val, lp)
+    rows = np.repeat(ev[None, :], len(q) + 1, axis=0)
+    for i, v in enumerate(q):
+        rows[i + 1, v] = 1 - rows[i + 1, v]
+    Q = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, evidence_mode=T.EVIDENCE_SLICED, observed=q)
+    lz = Q.log_z(rows, batch=len(rows))
+    assert abs(lz[0] - lp) <= 1e-5 * max(1.0, abs(lp))
+    assert np.all(lz[1:] <= lz[0] + 1e-4), (lz[1:] - lz[0]).max()
 
 
 def test_sampling_same_rng_as_oracle(T):
