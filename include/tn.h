@@ -89,7 +89,13 @@ typedef struct {
   int32_t restarts;          /* randomised restarts per strategy */
   uint64_t seed;             /* planner tie-break seed */
   double max_log2_size;      /* slicing cap on log2(elements) of any
-                                intermediate; 0 = no slicing */
+                                intermediate; 0 = no slicing.  MMAP plans
+                                slice each group's sum; sum-product plans
+                                (modes NONE / SLICED, no max-plus, no factor
+                                gradients) slice the tree and then support
+                                tn_logZ (Z summed over the slices) and
+                                tn_sample (each sample first draws its slice
+                                with probability Z_s / Z) */
   int32_t dtype;             /* tn_dtype of the matrix-core operands of the
                                 sum-product contractions (dense form and fused
                                 segments): TN_F32, or TN_BF16 / TN_F16 (operands
@@ -187,6 +193,10 @@ tn_status tn_plan_info_get(const tn_plan_t *plan, tn_plan_info *info);
  * returns the count in *n_pairs and the leaf count in *n_leaves. */
 tn_status tn_plan_tree(const tn_plan_t *plan, int32_t *pairs, int32_t cap, int32_t *n_pairs,
                        int32_t *n_leaves);
+
+/* Sliced variables of a plan (ascending; slices enumerate their values in
+ * row-major order, last fastest): writes up to cap ids, *n = count. */
+tn_status tn_plan_sliced(const tn_plan_t *plan, int32_t *vars, int32_t cap, int32_t *n);
 
 /*
  * Planning only (host, no device): contraction tree and complexity of the

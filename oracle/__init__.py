@@ -59,7 +59,7 @@ def lib():
         L.or_max_forward.argtypes = [ctypes.c_int, i32p, ctypes.c_int, i64p, i32p, f64p,
                                      ctypes.c_int, i32p, ctypes.c_int, f64p, i32p]
         L.or_sample.argtypes = [ctypes.c_int, i32p, ctypes.c_int, i64p, i32p, f64p,
-                                ctypes.c_int, i32p, ctypes.c_uint64, ctypes.c_int64, i32p]
+                                ctypes.c_int, i32p, ctypes.c_uint64, ctypes.c_int64, i64p, i32p]
         L.or_philox4x32_10.argtypes = [P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32)]
         _lib = L
     return _lib
@@ -334,15 +334,100 @@ def max_forward(leaves: Leaves, pairs, fp32: bool = False):
     return float(val[0]), asg
 
 
-def sample_tree(leaves: Leaves, pairs, n: int, seed: int) -> np.ndarray:
+def sample_tree(leaves: Leaves, pairs, n: int, seed: int, ids=None) -> np.ndarray:
+    """Top-down sampling (eq. sample, eq. condition-prob).  Sample j uses
+    ids[j] (default j) as its Philox counter; row j of the result."""
     L = lib()
     ptr, lab, vals = leaves.csr()
     pairs = np.ascontiguousarray(np.asarray(pairs, np.int32).reshape(-1, 2))
     card = np.ascontiguousarray(leaves.card)
     out = np.full((n, len(card)), -1, np.int32)
+    idp = None
+    if ids is not None:
+        ids = np.ascontiguousarray(np.asarray(ids, np.int64))
+        assert ids.size == n
+        idp = _p(ids, ctypes.c_int64)
     _check(L.or_sample(len(card), _p(card, ctypes.c_int), len(leaves), _p(ptr, ctypes.c_int64),
                        _p(lab, ctypes.c_int), _p(vals, ctypes.c_double), len(pairs),
-                       _p(pairs, ctypes.c_int), ctypes.c_uint64(seed), n, _p(out, ctypes.c_int)))
+                       _p(pairs, ctypes.c_int), ctypes.c_uint64(seed), n, idp, _p(out, ctypes.c_int)))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Slicing (fixed variables per slice) for log Z and sampling
+# ---------------------------------------------------------------------------
+
+SLICE_DRAW_NODE = 0xFFFFFFFF  # Philox node word of a sample's slice draw
+
+
+def fix_leaves(leaves: Leaves, assign: dict) -> Leaves:
+    """The same leaves with the variables in ``assign`` fixed at their values
+    (each table indexed there, the variables dropped from its labels); the
+    leaf count and order are kept, so a tree over the leaves still applies."""
+    labels, values = [], []
+    for lab, val in zip(leaves.labels, leaves.values):
+        t = np.asarray(val).reshape([int(leaves.card[v]) for v in lab]) if len(lab) else np.asarray(val).reshape(())
+        idx = tuple(int(assign[int(v)]) if int(v) in assign else slice(None) for v in lab)
+        t = t[idx] if len(lab) else t
+        labels.append(np.array([v for v in lab if int(v) not in assign], np.int32))
+        values.append(np.ascontiguousarray(t).ravel())
+    return Leaves(leaves.card, labels, values, leaves.kind, leaves.factor_of, leaves.var_of)
+
+
+def slice_assignments(sliced, card):
+    """Assignments of the sliced variables, row-major (last fastest)."""
+    sliced = [int(v) for v in sliced]
+    dims = [int(card[v]) for v in sliced]
+    for k in range(int(np.prod(dims)) if dims else 1):
+        a, r = {}, k
+        for v, d in zip(reversed(sliced), reversed(dims)):
+            a[v] = r % d
+            r //= d
+        yield a
+
+
+def slice_log_z(leaves: Leaves, pairs, sliced) -> np.ndarray:
+    """log Z_s of every slice (Z = sum over slices of Z_s)."""
+    out = []
+    for a in slice_assignments(sliced, leaves.card):
+        root, ex = sum_forward(fix_leaves(leaves, a), pairs)
+        out.append(math.log(root[0]) + ex * LN2 if root[0] > 0 else -math.inf)
+    return np.array(out)
+
+
+def uniform53(sample: int, node: int, slot: int, seed: int) -> float:
+    """Philox uniform in [0, 1): 53 bits of the first two output words."""
+    o = philox4x32_10([sample & 0xFFFFFFFF, sample >> 32, node, slot], [seed & 0xFFFFFFFF, seed >> 32])
+    return ((o[0] >> 5) * 67108864.0 + (o[1] >> 6)) / 9007199254740992.0
+
+
+def sample_sliced(leaves: Leaves, pairs, sliced, n: int, seed: int) -> np.ndarray:
+    """Sampling when the tree is contracted slice by slice: sample i draws its
+    slice s with probability Z_s / Z (inverse CDF over the slices in order,
+    uniform from counter (i, SLICE_DRAW_NODE, 0)), then the per-node rule
+    inside that slice with counter i.  Sliced variables take the slice's
+    values."""
+    lz = slice_log_z(leaves, pairs, sliced)
+    top = lz.max()
+    w = np.exp(lz - top)
+    tot = math.log(w.sum()) + top
+    cdf = np.cumsum(np.exp(lz - tot))
+    choice = np.empty(n, np.int64)
+    for i in range(n):
+        u = uniform53(i, SLICE_DRAW_NODE, 0, seed) * cdf[-1]
+        s = int(np.searchsorted(cdf, u, side="right"))
+        while s >= len(lz) or not lz[s] > -math.inf:
+            s = s - 1 if s > 0 else 0
+        choice[i] = s
+    out = np.full((n, len(leaves.card)), -1, np.int32)
+    for s, a in enumerate(slice_assignments(sliced, leaves.card)):
+        ids = np.nonzero(choice == s)[0]
+        if ids.size == 0:
+            continue
+        rows = sample_tree(fix_leaves(leaves, a), pairs, ids.size, seed, ids)
+        for v, x in a.items():
+            rows[:, v] = x
+        out[ids] = rows
     return out
 
 

@@ -648,7 +648,7 @@ static int reduce_sum(const Ten *A, const int *keep, int nkeep, Ten *out, const 
  */
 int or_sample(int n_vars, const int *card, int n_leaves, const int64_t *leaf_ptr,
               const int *leaf_lab, const double *leaf_vals, int n_pairs, const int *pairs,
-              uint64_t seed, int64_t n, int *samples) {
+              uint64_t seed, int64_t n, const int64_t *ids, int *samples) {
   Tree t;
   if (tree_build(&t, n_vars, n_leaves, leaf_ptr, leaf_lab, n_pairs, pairs, 0, NULL)) return -1;
   Ten *T = (Ten *)calloc(t.n_nodes, sizeof(Ten));
@@ -680,7 +680,10 @@ int or_sample(int n_vars, const int *card, int n_leaves, const int64_t *leaf_ptr
   for (int i = 0; i < t.n_nodes; ++i)
     if (T[i].size > wcap) wcap = T[i].size;
   double *w = (double *)malloc(sizeof(double) * wcap);
-  for (int64_t s = 0; s < n && !rc; ++s) {
+  for (int64_t j = 0; j < n && !rc; ++j) {
+    /* sample j draws with counter ids[j] (its index among all samples when
+       the caller samples a subset, e.g. one slice's samples) */
+    const int64_t s = ids ? ids[j] : j;
     for (int v = 0; v < n_vars; ++v) x[v] = -1;
     int r = root_id(&t);
     if (T[r].nl) {
@@ -724,7 +727,7 @@ int or_sample(int n_vars, const int *card, int n_leaves, const int64_t *leaf_ptr
         decode_index(q, np, P, x, card);
       }
     }
-    for (int v = 0; v < n_vars; ++v) samples[s * n_vars + v] = x[v];
+    for (int v = 0; v < n_vars; ++v) samples[j * n_vars + v] = x[v];
   }
   free(w);
   free(x);

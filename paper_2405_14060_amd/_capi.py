@@ -31,7 +31,7 @@ LAYOUT_AUTO, LAYOUT_INSTANCE_MAJOR, LAYOUT_INTERLEAVED = 0, 1, 2
 PLANNER_BEST, PLANNER_GREEDY, PLANNER_MINFILL, PLANNER_NATURAL, PLANNER_MINDEG = range(5)
 
 EXPORTS = ["tn_plan_opts_default", "tn_load_network", "tn_free_network", "tn_plan", "tn_free_plan",
-           "tn_plan_info_get", "tn_plan_tree", "tn_plan_tree_host", "tn_logZ", "tn_marginals",
+           "tn_plan_info_get", "tn_plan_tree", "tn_plan_sliced", "tn_plan_tree_host", "tn_logZ", "tn_marginals",
            "tn_map", "tn_mmap", "tn_sample", "tn_logZ_dev", "tn_sync", "tn_profile", "tn_profile_kind", "tn_last_error"]
 
 i32p = ctypes.POINTER(ctypes.c_int32)
@@ -107,6 +107,7 @@ def lib():
     L.tn_free_plan.restype = None
     L.tn_plan_info_get.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     L.tn_plan_tree.argtypes = [vp, i32p, ctypes.c_int32, i32p, i32p]
+    L.tn_plan_sliced.argtypes = [vp, i32p, ctypes.c_int32, i32p]
     L.tn_plan_tree_host.argtypes = [vp, ctypes.POINTER(PlanOpts), i32p, ctypes.c_int32, i32p, i32p,
                                     ctypes.POINTER(PlanInfo)]
     L.tn_logZ.argtypes = [vp, ctypes.c_int32, i32p, f64p]
@@ -120,7 +121,7 @@ def lib():
                              ctypes.POINTER(OpProfile), ctypes.c_int32, i32p]
     L.tn_profile_kind.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, i32p, ctypes.c_int32,
                                   ctypes.POINTER(OpProfile), i32p]
-    for name in ("tn_load_network", "tn_plan", "tn_plan_info_get", "tn_plan_tree", "tn_plan_tree_host",
+    for name in ("tn_load_network", "tn_plan", "tn_plan_info_get", "tn_plan_tree", "tn_plan_sliced", "tn_plan_tree_host",
                  "tn_logZ", "tn_marginals", "tn_map", "tn_mmap", "tn_sample", "tn_logZ_dev", "tn_sync",
                  "tn_profile", "tn_profile_kind"):
         getattr(L, name).restype = ctypes.c_int
@@ -316,6 +317,13 @@ class Plan:
         _check(lib().tn_profile_kind(self.h, task, kind, batch, _ptr(ev, ctypes.c_int32), reps,
                                      ctypes.byref(o), ctypes.byref(n)))
         return o.ms, o.flops, o.bytes, n.value
+
+    def sliced_vars(self):
+        """Sliced variables (ascending); slices run over their values, last fastest."""
+        buf = np.zeros(max(1, self.n_vars), np.int32)
+        n = ctypes.c_int32()
+        _check(lib().tn_plan_sliced(self.h, _ptr(buf, ctypes.c_int32), buf.size, ctypes.byref(n)))
+        return buf[:n.value].copy()
 
     def sync(self):
         _check(lib().tn_sync(self.h))

@@ -563,9 +563,15 @@ static void build_backtrack(tn_plan_t *p, TreeExec &t) {
   t.back = std::move(sorted);
 }
 
+// Top-down sampling steps (eq. sample, eq. condition-prob): at every node the
+// shared eliminated labels are drawn with weights Ar[z, k] * Br[z, k], where
+// Ar, Br are the children summed over their private eliminated labels
+// (reduction contractions run after the forward pass when sampling), then
+// each child's private labels are drawn from the child itself.
 static void build_sampling(tn_plan_t *p, const TreeExec &t) {
   p->samp.clear();
   p->samp_meta.clear();
+  p->samp_ops.clear();
   const int L = (int)t.leaf_tensor.size();
   auto quad = [&](int v, int c, int64_t sa, int64_t sb) {
     p->samp_meta.push_back(v);
@@ -577,8 +583,9 @@ static void build_sampling(tn_plan_t *p, const TreeExec &t) {
     SampleStep st{};
     st.A = t.leaf_tensor[0];
     st.B = -1;
+    st.Ar = st.A;
+    st.Br = -1;
     st.node = L;
-    st.aIn_b = st.aIn_e = st.bIn_b = st.bIn_e = st.k_b = st.k_e = st.pb_b = st.pb_e = 0;
     const Labels &la = p->T[t.leaf_tensor[0]].lab;
     st.pa_b = (int32_t)(p->samp_meta.size() / 4);
     for (int v : la) quad(v, p->card[v], stride_in(la, v, p->card), 0);
@@ -593,21 +600,37 @@ static void build_sampling(tn_plan_t *p, const TreeExec &t) {
     st.A = t.node_tensor[l];
     st.B = t.node_tensor[r];
     st.node = c;
+    const Labels K = minus(inter(La, Lb), Lc);
+    const Labels Pa = minus(minus(La, Lb), Lc), Pb = minus(minus(Lb, La), Lc);
+    // reduced children (only needed when shared labels are drawn)
+    auto reduced = [&](int child, const Labels &Lx, const Labels &P) -> int {
+      if (K.empty() || P.empty()) return child;
+      const int red = new_tensor(p, minus(Lx, P), false, true);
+      p->samp_ops.push_back(make_op(p, SEMI_SUM, child, -1, red, -1));
+      return red;
+    };
+    const int ar = reduced((int)st.A, La, Pa), br = reduced((int)st.B, Lb, Pb);
+    st.Ar = ar;
+    st.Br = br;
+    const Labels &LAr = p->T[ar].lab, &LBr = p->T[br].lab;
     auto beg = [&] { return (int32_t)(p->samp_meta.size() / 4); };
     st.aIn_b = beg();
-    for (int v : inter(La, Lc)) quad(v, p->card[v], stride_in(La, v, p->card), 0);
+    for (int v : inter(La, Lc)) quad(v, p->card[v], stride_in(La, v, p->card), stride_in(LAr, v, p->card));
     st.aIn_e = beg();
     st.bIn_b = beg();
-    for (int v : inter(Lb, Lc)) quad(v, p->card[v], 0, stride_in(Lb, v, p->card));
+    for (int v : inter(Lb, Lc)) quad(v, p->card[v], stride_in(Lb, v, p->card), stride_in(LBr, v, p->card));
     st.bIn_e = beg();
     st.k_b = beg();
-    for (int v : minus(inter(La, Lb), Lc)) quad(v, p->card[v], stride_in(La, v, p->card), stride_in(Lb, v, p->card));
+    for (int v : K) quad(v, p->card[v], stride_in(La, v, p->card), stride_in(Lb, v, p->card));
     st.k_e = beg();
+    st.kr_b = beg();
+    for (int v : K) quad(v, p->card[v], stride_in(LAr, v, p->card), stride_in(LBr, v, p->card));
+    st.kr_e = beg();
     st.pa_b = beg();
-    for (int v : minus(minus(La, Lb), Lc)) quad(v, p->card[v], stride_in(La, v, p->card), 0);
+    for (int v : Pa) quad(v, p->card[v], stride_in(La, v, p->card), 0);
     st.pa_e = beg();
     st.pb_b = beg();
-    for (int v : minus(minus(Lb, La), Lc)) quad(v, p->card[v], 0, stride_in(Lb, v, p->card));
+    for (int v : Pb) quad(v, p->card[v], 0, stride_in(Lb, v, p->card));
     st.pb_e = beg();
     p->samp.push_back(st);
   }
@@ -971,6 +994,7 @@ static void allocate(tn_plan_t *p, const tn_net *net) {
   for (auto &g : p->groups)
     for (auto &op : g.ops) fill_args(p, op);
   for (auto &op : p->qtree.ops) fill_args(p, op);
+  for (auto &op : p->samp_ops) fill_args(p, op);
   {
     std::vector<Op *> all;
     for (auto &op : p->sum_tree.ops) all.push_back(&op);
@@ -979,6 +1003,7 @@ static void allocate(tn_plan_t *p, const tn_net *net) {
     for (auto &g : p->groups)
       for (auto &op : g.ops) all.push_back(&op);
     for (auto &op : p->qtree.ops) all.push_back(&op);
+    for (auto &op : p->samp_ops) all.push_back(&op);
     std::vector<ContractArgs> host;
     for (Op *op : all) host.push_back(op->a);
     ContractArgs *d = dupload(p, host);
@@ -1001,10 +1026,12 @@ static void allocate(tn_plan_t *p, const tn_net *net) {
   p->sched_bwd = build_schedule(p, p->bwd, true);
   p->sched_max = build_schedule(p, p->max_tree.ops, false);
   p->sched_q = build_schedule(p, p->qtree.ops, false);
+  p->sched_samp = build_schedule(p, p->samp_ops, false);
   upload_schedule(p, p->sched_fwd, p->sum_tree.ops);
   upload_schedule(p, p->sched_bwd, p->bwd);
   upload_schedule(p, p->sched_max, p->max_tree.ops);
   upload_schedule(p, p->sched_q, p->qtree.ops);
+  upload_schedule(p, p->sched_samp, p->samp_ops);
   for (auto &g : p->groups) {
     p->sched_groups.push_back(build_schedule(p, g.ops, false));
     upload_schedule(p, p->sched_groups.back(), g.ops);
@@ -1082,6 +1109,8 @@ static void allocate(tn_plan_t *p, const tn_net *net) {
   for (auto &s : p->samp) {
     s.A = p->T[(int)s.A].off;
     if (s.B >= 0) s.B = p->T[(int)s.B].off;
+    s.Ar = p->T[(int)s.Ar].off;
+    if (s.Br >= 0) s.Br = p->T[(int)s.Br].off;
   }
   p->d_samp = dupload(p, p->samp);
   p->d_samp_meta = dupload(p, p->samp_meta);
@@ -1489,7 +1518,8 @@ static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
     p->stats = tree_stats(p->leaf_lab, p->pairs, {}, p->card);
     p->planner_used = -1;
   } else {
-    PlanChoice pc = plan_tree(p->leaf_lab, p->card, {}, o->planner, o->restarts, o->seed);
+    PlanChoice pc = plan_tree(p->leaf_lab, p->card, {}, o->planner, o->restarts, o->seed,
+                              p->mode == TN_EVIDENCE_INDICATOR ? 0.0 : o->max_log2_size);
     p->pairs = pc.pairs;
     p->stats = pc.stats;
     p->planner_used = pc.planner;
@@ -1507,10 +1537,26 @@ static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
       p->max_batch = std::max(1, o->max_batch);
     }
   }
-  if (o->max_log2_size > 0 && p->stats.sc > o->max_log2_size + 1e-9)
-    throw TnError(TN_E_UNSUPPORTED, "slicing is available for MMAP plans; increase max_log2_size");
-  // leaf tensors and descriptors
   std::vector<char> fixed = p->is_obs;
+  if (o->max_log2_size > 0 && p->stats.sc > o->max_log2_size + 1e-9) {
+    // sliced sum-product plan (log Z and sampling): the chosen variables are
+    // fixed per slice like evidence; the tree over the leaves stays, its
+    // labels lose the sliced variables
+    if (p->mode == TN_EVIDENCE_INDICATOR || p->want_max || p->want_grad)
+      throw TnError(TN_E_UNSUPPORTED, "slicing: sum-product plans without batched evidence or gradients");
+    p->sliced = choose_slices(p->leaf_lab, p->pairs, {}, p->card, o->max_log2_size);
+    for (int v : p->sliced) fixed[v] = 1;
+    for (auto &l : p->leaf_lab) l.erase(std::remove_if(l.begin(), l.end(), [&](int v) { return (bool)fixed[v]; }), l.end());
+    TreeStats st = tree_stats(p->leaf_lab, p->pairs, {}, p->card);
+    double n_slices = 1;
+    for (int v : p->sliced) n_slices *= p->card[v];
+    st.flops *= n_slices;
+    st.bytes *= n_slices;
+    st.tc = st.flops > 0 ? std::log2(st.flops / 2) : 0;
+    p->stats = st;
+    lab = node_labels(p->leaf_lab, p->pairs, {}, p->n_vars);
+  }
+  // leaf tensors and descriptors
   std::vector<int> leaf_sum(L, -1), leaf_max(L, -1);
   for (int i = 0; i < L; ++i) {
     const bool bat = p->leaf_kind[i] == 2;
@@ -1702,6 +1748,14 @@ extern "C" tn_status tn_plan_tree(const tn_plan_t *p, int32_t *pairs, int32_t ca
   });
 }
 
+extern "C" tn_status tn_plan_sliced(const tn_plan_t *p, int32_t *vars, int32_t cap, int32_t *n) {
+  return guard([&] {
+    if (!p) throw TnError(TN_E_INVALID, "NULL plan");
+    if (n) *n = (int32_t)p->sliced.size();
+    for (int i = 0; i < (int)p->sliced.size() && i < cap; ++i) vars[i] = p->sliced[i];
+  });
+}
+
 extern "C" tn_status tn_plan_tree_host(const tn_net *net, const tn_plan_opts *opts, int32_t *pairs,
                                        int32_t cap, int32_t *n_pairs, int32_t *n_leaves,
                                        tn_plan_info *stats) {
@@ -1721,7 +1775,8 @@ extern "C" tn_status tn_plan_tree_host(const tn_net *net, const tn_plan_opts *op
         p.is_obs[o.observed[i]] = 1;
       }
     build_leaves(&p, net);
-    PlanChoice pc = plan_tree(p.leaf_lab, p.card, {}, o.planner, o.restarts, o.seed);
+    PlanChoice pc = plan_tree(p.leaf_lab, p.card, {}, o.planner, o.restarts, o.seed,
+                              p.mode == TN_EVIDENCE_INDICATOR ? 0.0 : o.max_log2_size);
     if (n_pairs) *n_pairs = (int32_t)pc.pairs.size();
     if (n_leaves) *n_leaves = (int32_t)p.leaf_lab.size();
     for (int i = 0; i < (int)pc.pairs.size() && i < cap; ++i) {
@@ -1847,6 +1902,54 @@ static void upload_evidence(tn_plan_t *p, int batch, const int32_t *ev) {
   hip_check(hipStreamSynchronize(p->stream), "evidence upload");
 }
 
+// Sliced sum-product plans: the caller's evidence row with the sliced
+// variables at slice s (slices in row-major order over the sliced variables,
+// last fastest), uploaded as the plan's evidence.
+static int64_t n_slices_of(const tn_plan_t *p) {
+  int64_t n = 1;
+  for (int v : p->sliced) n *= p->card[v];
+  return n;
+}
+static std::vector<int32_t> slice_row(const tn_plan_t *p, const int32_t *ev, int64_t s) {
+  std::vector<int32_t> row(p->n_vars, -1);
+  for (int v = 0; v < p->n_vars; ++v) {
+    const int e = ev ? ev[v] : -1;
+    if (e < -1 || e >= p->card[v]) throw TnError(TN_E_INVALID, "evidence value out of range");
+    if (p->mode == TN_EVIDENCE_NONE && e >= 0) throw TnError(TN_E_INVALID, "plan has no evidence; pass -1");
+    if (p->mode == TN_EVIDENCE_SLICED && (e >= 0) != (bool)p->is_obs[v])
+      throw TnError(TN_E_INVALID, "evidence must give exactly the plan's observed variables");
+    row[v] = e;
+  }
+  for (int i = (int)p->sliced.size() - 1; i >= 0; --i) {
+    const int v = p->sliced[i];
+    row[v] = (int32_t)(s % p->card[v]);
+    s /= p->card[v];
+  }
+  return row;
+}
+static void forward_sum(tn_plan_t *p, bool with_bwd, bool allow_fused);
+// log Z_s of every slice (FP64 per slice)
+static std::vector<double> slice_log_z(tn_plan_t *p, const int32_t *ev, bool unfused) {
+  const int64_t ns = n_slices_of(p);
+  std::vector<double> lz(ns);
+  for (int64_t s = 0; s < ns; ++s) {
+    const std::vector<int32_t> row = slice_row(p, ev, s);
+    hip_check(hipMemcpyAsync(p->d_evidence, row.data(), row.size() * 4, hipMemcpyHostToDevice, p->stream), "slice");
+    forward_sum(p, false, !unfused);
+    hip_check(hipMemcpyAsync(&lz[s], p->d_out, sizeof(double), hipMemcpyDeviceToHost, p->stream), "D2H");
+    hip_check(hipStreamSynchronize(p->stream), "slice");
+  }
+  return lz;
+}
+static double log_sum_exp(const std::vector<double> &v) {
+  double m = -INFINITY;
+  for (double x : v) m = std::max(m, x);
+  if (!(m > -INFINITY)) return -INFINITY;
+  double t = 0;
+  for (double x : v) t += std::exp(x - m);
+  return m + std::log(t);
+}
+
 static void check_batch(tn_plan_t *p, int batch) {
   if (batch < 1) throw TnError(TN_E_INVALID, "batch must be >= 1");
   if (p->mode == TN_EVIDENCE_INDICATOR && batch > p->max_batch) throw TnError(TN_E_INVALID, "batch exceeds max_batch");
@@ -1886,12 +1989,17 @@ extern "C" tn_status tn_logZ(tn_plan_t *p, int32_t batch, const int32_t *evidenc
     if (!p || !logz) throw TnError(TN_E_INVALID, "NULL argument");
     if (!p->want_sum || p->is_mmap) throw TnError(TN_E_UNSUPPORTED, "plan has no sum-product pass");
     check_batch(p, batch);
-    per_instance(p, batch, evidence, [&](int b0, int nb, const int32_t *ev) {
-      upload_evidence(p, nb, ev);
-      forward_sum(p, false);
-      hip_check(hipMemcpyAsync(logz + b0, p->d_out, nb * sizeof(double), hipMemcpyDeviceToHost, p->stream), "D2H");
-      hip_check(hipStreamSynchronize(p->stream), "logZ");
-    });
+    if (!p->sliced.empty()) {  // Z = sum over the slices of Z_s
+      for (int b = 0; b < batch; ++b)
+        logz[b] = log_sum_exp(slice_log_z(p, evidence ? evidence + (int64_t)b * p->n_vars : nullptr, false));
+    } else {
+      per_instance(p, batch, evidence, [&](int b0, int nb, const int32_t *ev) {
+        upload_evidence(p, nb, ev);
+        forward_sum(p, false);
+        hip_check(hipMemcpyAsync(logz + b0, p->d_out, nb * sizeof(double), hipMemcpyDeviceToHost, p->stream), "D2H");
+        hip_check(hipStreamSynchronize(p->stream), "logZ");
+      });
+    }
     for (int b = 0; b < batch; ++b)
       if (!(logz[b] > -INFINITY)) throw TnError(TN_E_ZERO_EVIDENCE, "p(e) = 0 for instance " + std::to_string(b));
   });
@@ -1902,6 +2010,7 @@ extern "C" tn_status tn_marginals(tn_plan_t *p, int32_t batch, const int32_t *ev
   return guard([&] {
     if (!p || !marg) throw TnError(TN_E_INVALID, "NULL argument");
     if (!p->want_sum || p->is_mmap) throw TnError(TN_E_UNSUPPORTED, "plan has no sum-product pass");
+    if (!p->sliced.empty()) throw TnError(TN_E_UNSUPPORTED, "marginals of sliced plans");
     check_batch(p, batch);
     std::vector<double> lz(batch);
     per_instance(p, batch, evidence, [&](int b0, int nb, const int32_t *ev) {
@@ -1952,29 +2061,77 @@ extern "C" tn_status tn_map(tn_plan_t *p, int32_t batch, const int32_t *evidence
   });
 }
 
+// Sampling from a sliced plan (reading of the paper's sampling step under
+// slicing): sample i first draws its slice s with probability Z_s / Z by
+// inverse CDF over the slices in order (uniform: Philox counter (i, slice
+// draw word, slot 0)); then, slice by slice, the forward pass of that slice is
+// recomputed and its samples follow the per-node rule with their own indices
+// as counters.
+static void ensure_sample_buffer(tn_plan_t *p, int64_t n) {
+  if (n <= p->samp_cap) return;
+  if (p->d_samp_out) {
+    hip_check(hipFree(p->d_samp_out), "hipFree");
+    p->allocs.erase(std::find(p->allocs.begin(), p->allocs.end(), (void *)p->d_samp_out));
+  }
+  p->d_samp_out = dalloc<int32_t>(p, (size_t)n * p->n_vars);
+  p->samp_cap = n;
+}
+static void sample_sliced(tn_plan_t *p, const int32_t *evidence, int64_t n, uint64_t seed, int32_t *samples) {
+  const std::vector<double> lz = slice_log_z(p, evidence, true);
+  const double total = log_sum_exp(lz);
+  if (!(total > -INFINITY)) throw TnError(TN_E_ZERO_EVIDENCE, "p(e) = 0");
+  if (n == 0) return;
+  std::vector<double> cdf(lz.size());
+  double acc = 0;
+  for (size_t s = 0; s < lz.size(); ++s) cdf[s] = acc += std::exp(lz[s] - total);
+  std::vector<std::vector<int64_t>> ids(lz.size());
+  for (int64_t i = 0; i < n; ++i) {
+    const double u = sample_uniform(i, kSliceDrawNode, 0, seed) * acc;
+    size_t s = std::upper_bound(cdf.begin(), cdf.end(), u) - cdf.begin();
+    while (s >= lz.size() || !(lz[s] > -INFINITY)) s = s > 0 ? s - 1 : 0;  // rounding at the top end
+    ids[s].push_back(i);
+  }
+  ensure_sample_buffer(p, n);
+  int64_t *d_ids = dalloc<int64_t>(p, (size_t)n);
+  for (size_t s = 0; s < lz.size(); ++s) {
+    if (ids[s].empty()) continue;
+    const std::vector<int32_t> row = slice_row(p, evidence, (int64_t)s);
+    hip_check(hipMemcpyAsync(p->d_evidence, row.data(), row.size() * 4, hipMemcpyHostToDevice, p->stream), "slice");
+    hip_check(hipMemcpyAsync(d_ids, ids[s].data(), ids[s].size() * 8, hipMemcpyHostToDevice, p->stream), "ids");
+    forward_sum(p, false, false);
+    run_sched(p, p->samp_ops, p->sched_samp);
+    launch_sample(p->arena, p->d_samp, (int)p->samp.size(), p->d_samp_meta, p->n_vars, (int64_t)ids[s].size(), seed,
+                  p->d_evidence, d_ids, p->d_samp_out, p->stream);
+    hip_check(hipGetLastError(), "sample launch");
+    hip_check(hipStreamSynchronize(p->stream), "sample");
+  }
+  hip_check(hipFree(d_ids), "hipFree");
+  p->allocs.erase(std::find(p->allocs.begin(), p->allocs.end(), (void *)d_ids));
+  hip_check(hipMemcpyAsync(samples, p->d_samp_out, (size_t)n * p->n_vars * 4, hipMemcpyDeviceToHost, p->stream), "D2H");
+  hip_check(hipStreamSynchronize(p->stream), "sample");
+}
+
 extern "C" tn_status tn_sample(tn_plan_t *p, const int32_t *evidence, int64_t n, uint64_t seed, int32_t *samples) {
   return guard([&] {
     if (!p || (!samples && n > 0)) throw TnError(TN_E_INVALID, "NULL argument");
     if (n < 0) throw TnError(TN_E_INVALID, "negative sample count");
     if (!p->want_sum || p->is_mmap || p->mode == TN_EVIDENCE_INDICATOR)
       throw TnError(TN_E_UNSUPPORTED, "sampling needs a sum-product plan without batched evidence");
+    if (!p->sliced.empty()) {
+      sample_sliced(p, evidence, n, seed, samples);
+      return;
+    }
     upload_evidence(p, 1, evidence);
     forward_sum(p, false, false);
+    run_sched(p, p->samp_ops, p->sched_samp);
     std::vector<double> lz(1);
     hip_check(hipMemcpyAsync(lz.data(), p->d_out, sizeof(double), hipMemcpyDeviceToHost, p->stream), "D2H");
     hip_check(hipStreamSynchronize(p->stream), "sample forward");
     if (!(lz[0] > -INFINITY)) throw TnError(TN_E_ZERO_EVIDENCE, "p(e) = 0");
     if (n == 0) return;
-    if (n > p->samp_cap) {
-      if (p->d_samp_out) {
-        hip_check(hipFree(p->d_samp_out), "hipFree");
-        p->allocs.erase(std::find(p->allocs.begin(), p->allocs.end(), (void *)p->d_samp_out));
-      }
-      p->d_samp_out = dalloc<int32_t>(p, (size_t)n * p->n_vars);
-      p->samp_cap = n;
-    }
+    ensure_sample_buffer(p, n);
     launch_sample(p->arena, p->d_samp, (int)p->samp.size(), p->d_samp_meta, p->n_vars, n, seed, p->d_evidence,
-                  p->d_samp_out, p->stream);
+                  nullptr, p->d_samp_out, p->stream);
     hip_check(hipGetLastError(), "sample launch");
     hip_check(hipMemcpyAsync(samples, p->d_samp_out, (size_t)n * p->n_vars * 4, hipMemcpyDeviceToHost, p->stream), "D2H");
     hip_check(hipStreamSynchronize(p->stream), "sample");
@@ -1988,6 +2145,7 @@ extern "C" tn_status tn_logZ_dev(tn_plan_t *p, const int32_t *evidence, const fl
     if (!p->want_sum || p->is_mmap || p->mode == TN_EVIDENCE_INDICATOR)
       throw TnError(TN_E_UNSUPPORTED, "tn_logZ_dev needs a sum-product plan in mode NONE or SLICED");
     if (grad_dev && !p->want_grad) throw TnError(TN_E_UNSUPPORTED, "plan built without want_factor_grad");
+    if (!p->sliced.empty()) throw TnError(TN_E_UNSUPPORTED, "tn_logZ_dev on a sliced plan");
     const tn_net *net = p->net_src;
     upload_evidence(p, 1, evidence);
     // factor store (linear) lives at arena offset 0
@@ -2078,7 +2236,7 @@ static void build_mmap(tn_plan_t *p, const tn_net *net) {
     }
     std::sort(outq.begin(), outq.end());
     outq.erase(std::unique(outq.begin(), outq.end()), outq.end());
-    PlanChoice pc = plan_tree(labs, p->card, outq, o.planner, o.restarts, o.seed);
+    PlanChoice pc = plan_tree(labs, p->card, outq, o.planner, o.restarts, o.seed, o.max_log2_size);
     Labels sl;
     if (o.max_log2_size > 0 && pc.stats.sc > o.max_log2_size + 1e-9)
       sl = choose_slices(labs, pc.pairs, outq, p->card, o.max_log2_size);

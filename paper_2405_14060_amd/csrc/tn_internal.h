@@ -57,9 +57,13 @@ struct PlanChoice {
 };
 
 // Choose a contraction tree over the leaves; labels in `out` are never
-// eliminated.  `strategy` is a TN_PLANNER_* value.
+// eliminated.  `strategy` is a TN_PLANNER_* value.  Candidates are ranked by
+// (largest intermediate, work); with a slicing cap (cap > 0) a candidate that
+// exceeds it is ranked by its total work once sliced below the cap (the
+// work of one slice times the number of slices), so that a tree with larger
+// intermediates but much less sliced work wins.
 PlanChoice plan_tree(const std::vector<Labels> &leaves, const std::vector<int> &card,
-                     const Labels &out, int strategy, int restarts, uint64_t seed);
+                     const Labels &out, int strategy, int restarts, uint64_t seed, double cap = 0);
 
 // Pick labels to slice (fix per slice) so that every node output and every
 // node label union is at most 2^cap elements.
@@ -288,16 +292,26 @@ void launch_backtrack(const int32_t *iarena, const BackStep *steps, const int32_
 // Top-down sampling steps (see tn_sample).
 struct SampleStep {
   int64_t A, B;        // float offsets of the two children (B < 0: none)
+  int64_t Ar, Br;      // the children summed over their private eliminated
+                       // labels (the child itself when it has none): the
+                       // weights of the shared eliminated labels
   int32_t node;        // tree node id (Philox counter word 2)
-  int32_t aIn_b, aIn_e;    // (var, stride in A) for A's labels already drawn
-  int32_t bIn_b, bIn_e;    // (var, stride in B)
+  int32_t aIn_b, aIn_e;    // (var, card, stride in A, stride in Ar) for A's labels already drawn
+  int32_t bIn_b, bIn_e;    // (var, card, stride in B, stride in Br)
   int32_t k_b, k_e;        // (var, card, strideA, strideB): shared eliminated
+  int32_t kr_b, kr_e;      // (var, card, strideAr, strideBr): the same labels in Ar, Br
   int32_t pa_b, pa_e;      // (var, card, strideA, 0): A-private eliminated
   int32_t pb_b, pb_e;      // (var, card, 0, strideB): B-private eliminated
 };
+// n samples; sample j uses index ids[j] (ids == nullptr: j) as its Philox
+// counter and writes row ids[j] of out
 void launch_sample(const float *arena, const SampleStep *steps, int n_steps, const int32_t *meta,
-                   int n_vars, int64_t n, uint64_t seed, const int32_t *init, int32_t *out,
-                   void *stream);
+                   int n_vars, int64_t n, uint64_t seed, const int32_t *init, const int64_t *ids,
+                   int32_t *out, void *stream);
+// Philox4x32-10 uniform in [0, 1) with 53 bits, counter (sample, node, slot),
+// key seed: the draws of the sampler, on the host (slice choice)
+double sample_uniform(uint64_t sample, uint32_t node, uint32_t slot, uint64_t seed);
+static constexpr uint32_t kSliceDrawNode = 0xffffffffu;  // node word of a sample's slice draw
 
 void launch_tolog(const float *src, const int32_t *ex, int slot, int64_t n, float *dst,
                   void *stream);

@@ -639,22 +639,34 @@ static constexpr int kGK = 16;          // summed entries per chunk
 static constexpr int kGKP = kGT + 16;   // chunk row pitch: conflict-free MFMA operand reads
 static constexpr int kGCP = kGT + 1;    // epilogue tile pitch
 
+// Summed entries per chunk of the sum-product dense form, and the largest
+// summed set whose offsets are staged in LDS once per workgroup (larger sets
+// look their offsets up per element).
+static constexpr int kDK = 32;
+static constexpr int kDSOff = 2048;
+
 template <int PREC>
 __device__ __forceinline__ void gemm_body(const ContractArgs &a, const int b, const uint32_t blk) {
   __shared__ int32_t oMX[kGT], oMZ[kGT], oNY[kGT], oNZ[kGT];
-  __shared__ float As[kGK * kGKP], Bs[kGK * kGKP];
-  __shared__ float Cs[kGT * kGCP];
+  __shared__ int32_t sOX[kDSOff], sOY[kDSOff];
+  __shared__ float AB[2 * kDK * kGKP];
   __shared__ int ksh[2];
+  float *As = AB, *Bs = AB + kDK * kGKP;
+  float *Cs = AB;  // the epilogue tile reuses the operand chunks (64 x 65 <= 2 x 32 x 80 floats)
+  static_assert(kGT * kGCP <= 2 * kDK * kGKP, "epilogue tile fits the operand chunks");
   const int t = threadIdx.x, l = t & 63, w = t >> 6;
   const uint32_t tm = (a.nM + kGT - 1) / kGT, tn = (a.nC + kGT - 1) / kGT;
   const uint32_t bt = blk / (tm * tn), rem = blk - bt * tm * tn;
   const uint32_t mt = rem / tn, nt = rem - mt * tn;
   const uint32_t m0 = mt * kGT, n0 = nt * kGT;
   const int32_t xb = tab_off(a.gbX, bt, a.nBl), yb = tab_off(a.gbY, bt, a.nBl), zb = tab_off(a.gbZ, bt, a.nBl);
-  const float *__restrict__ X = a.X + (int64_t)b * a.bsX + xb;
-  const float *__restrict__ Y = a.Y + (int64_t)b * a.bsY + yb;
-  float *__restrict__ Z = a.Z + (int64_t)b * a.bsZ + zb;
-  // prologue: row / column offsets and the operands' exponents, one read each
+  gcfloat *__restrict__ X = (gcfloat *)(a.X + (int64_t)b * a.bsX + xb);
+  gcfloat *__restrict__ Y = (gcfloat *)(a.Y + (int64_t)b * a.bsY + yb);
+  gfloat *__restrict__ Z = (gfloat *)(a.Z + (int64_t)b * a.bsZ + zb);
+  const uint32_t nS = a.nS;
+  const bool staged = nS <= (uint32_t)kDSOff;
+  // prologue: row / column offsets, the operands' exponents and (small
+  // summed sets) every summed entry's offsets, one read each
   if (w == 0) {
     const uint32_t m = m0 + l;
     oMX[l] = m < a.nM ? tab_off(a.gmX, m, a.nMl) : -1;
@@ -668,40 +680,65 @@ __device__ __forceinline__ void gemm_body(const ContractArgs &a, const int b, co
     const int k = max_exponent(read_max(a.mx, a.mx_stride, slot));
     if (l == 0) ksh[w - 2] = k;
   }
+  if (staged)
+    for (uint32_t s = t; s < nS; s += kBlock) {
+      sOX[s] = tab_off(a.sX, s, a.nSl);
+      sOY[s] = tab_off(a.sY, s, a.nSl);
+    }
   __syncthreads();
   const int kx = ksh[0], ky = ksh[1];
   const float sx = ldexpf(1.f, -kx), sy = ldexpf(1.f, -ky);
+  // per thread: 8 entries of each operand per chunk; entry q of A is
+  // (row mA[q], summed kA[q]) and of B (summed kB[q], column nB[q]), with
+  // consecutive threads on the operand's stride-1 label
+  constexpr int NQ = kGT * kDK / kBlock;
+  int32_t oa[NQ], ob[NQ];
+  int kA[NQ], kB[NQ], dA[NQ], dB[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int e = t + q * kBlock;
+    int m, k;
+    if (a.x_s_fast) { k = e % kDK; m = e / kDK; } else { m = e % kGT; k = e / kGT; }
+    oa[q] = oMX[m];
+    kA[q] = k;
+    dA[q] = k * kGKP + m;
+    int n, k2;
+    if (a.y_n_fast) { n = e % kGT; k2 = e / kGT; } else { k2 = e % kDK; n = e / kDK; }
+    ob[q] = oNY[n];
+    kB[q] = k2;
+    dB[q] = k2 * kGKP + n;
+  }
+  // loads of one chunk: every address in bounds (rows past the tile and
+  // summed entries past nS read entry 0 of the operand), masked afterwards
+  auto load_chunk = [&](uint32_t s0, float (&va)[NQ], float (&vb)[NQ]) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const uint32_t s = s0 + kA[q], s2 = s0 + kB[q];
+      const uint32_t sc = s < nS ? s : 0u, sc2 = s2 < nS ? s2 : 0u;
+      const int32_t ox = staged ? sOX[sc] : tab_off(a.sX, sc, a.nSl);
+      const int32_t oy = staged ? sOY[sc2] : tab_off(a.sY, sc2, a.nSl);
+      const float x = X[(oa[q] >= 0 ? oa[q] : 0) + ox];
+      const float y = Y[(ob[q] >= 0 ? ob[q] : 0) + oy];
+      va[q] = (oa[q] >= 0 && s < nS) ? x * sx : 0.f;
+      vb[q] = (ob[q] >= 0 && s2 < nS) ? y * sy : 0.f;
+    }
+  };
   f32x4 acc[2][2] = {};
   const int wm = w & 1, wn = w >> 1;
-  for (uint32_t s0 = 0; s0 < a.nS; s0 += kGK) {
-    // gather the chunk: A^T as As[k][m], B as Bs[k][n]
-    float va[4], vb[4];
-    int da[4], db[4];
+  float va[NQ], vb[NQ], na[NQ], nb[NQ];
+  load_chunk(0, va, vb);
+  for (uint32_t s0 = 0; s0 < nS; s0 += kDK) {
+    const bool more = s0 + kDK < nS;
+    if (more) load_chunk(s0 + kDK, na, nb);  // next chunk in flight during this one's products
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = t + q * kBlock;
-      int m, k;
-      if (a.x_s_fast) { k = e % kGK; m = e / kGK; } else { m = e % kGT; k = e / kGT; }
-      const uint32_t s = s0 + k;
-      const int32_t om = oMX[m];
-      va[q] = (om >= 0 && s < a.nS) ? X[om + tab_off(a.sX, s, a.nSl)] : 0.f;
-      da[q] = k * kGKP + m;
-      int n, k2;
-      if (a.y_n_fast) { n = e % kGT; k2 = e / kGT; } else { k2 = e % kGK; n = e / kGK; }
-      const uint32_t s2 = s0 + k2;
-      const int32_t on = oNY[n];
-      vb[q] = (on >= 0 && s2 < a.nS) ? Y[on + tab_off(a.sY, s2, a.nSl)] : 0.f;
-      db[q] = k2 * kGKP + n;
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      As[da[q]] = va[q] * sx;
-      Bs[db[q]] = vb[q] * sy;
+    for (int q = 0; q < NQ; ++q) {
+      As[dA[q]] = va[q];
+      Bs[dB[q]] = vb[q];
     }
     __syncthreads();
     if (PREC == 0) {
 #pragma unroll
-      for (int kk = 0; kk < kGK; kk += 4) {
+      for (int kk = 0; kk < kDK; kk += 4) {
         const int r = (kk + (l >> 4)) * kGKP + (l & 15);
         const float a0 = As[r + 32 * wm], a1 = As[r + 32 * wm + 16];
         const float b0 = Bs[r + 32 * wn], b1 = Bs[r + 32 * wn + 16];
@@ -710,22 +747,32 @@ __device__ __forceinline__ void gemm_body(const ContractArgs &a, const int b, co
         acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
         acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
       }
-    } else {  // the whole chunk (16 summed entries) in one low-precision step
-      float a0[4], a1[4], b0[4], b1[4];
+    } else {  // 16 summed entries per low-precision step
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int r = (4 * (l >> 4) + j) * kGKP + (l & 15);
-        a0[j] = As[r + 32 * wm];
-        a1[j] = As[r + 32 * wm + 16];
-        b0[j] = Bs[r + 32 * wn];
-        b1[j] = Bs[r + 32 * wn + 16];
+      for (int kk = 0; kk < kDK; kk += 16) {
+        float a0[4], a1[4], b0[4], b1[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int r = (kk + 4 * (l >> 4) + j) * kGKP + (l & 15);
+          a0[j] = As[r + 32 * wm];
+          a1[j] = As[r + 32 * wm + 16];
+          b0[j] = Bs[r + 32 * wn];
+          b1[j] = Bs[r + 32 * wn + 16];
+        }
+        acc[0][0] = mfma16_lp<PREC>(a0, b0, acc[0][0]);
+        acc[0][1] = mfma16_lp<PREC>(a0, b1, acc[0][1]);
+        acc[1][0] = mfma16_lp<PREC>(a1, b0, acc[1][0]);
+        acc[1][1] = mfma16_lp<PREC>(a1, b1, acc[1][1]);
       }
-      acc[0][0] = mfma16_lp<PREC>(a0, b0, acc[0][0]);
-      acc[0][1] = mfma16_lp<PREC>(a0, b1, acc[0][1]);
-      acc[1][0] = mfma16_lp<PREC>(a1, b0, acc[1][0]);
-      acc[1][1] = mfma16_lp<PREC>(a1, b1, acc[1][1]);
     }
     __syncthreads();
+    if (more) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        va[q] = na[q];
+        vb[q] = nb[q];
+      }
+    }
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -2067,7 +2114,7 @@ void launch_backtrack(const int32_t *iarena, const BackStep *steps, const int32_
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
 // 32x32->64 multiplications with the Weyl-sequence key schedule.
-__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+__host__ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     if (r) {
@@ -2085,8 +2132,8 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
   }
 }
 
-__device__ __forceinline__ double uniform53(uint64_t sample, uint32_t node, uint32_t slot,
-                                            uint64_t seed) {
+__host__ __device__ __forceinline__ double uniform53(uint64_t sample, uint32_t node, uint32_t slot,
+                                                     uint64_t seed) {
   uint32_t c[4] = {(uint32_t)sample, (uint32_t)(sample >> 32), node, slot};
   philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
   return ((double)(c[0] >> 5) * 67108864.0 + (double)(c[1] >> 6)) * (1.0 / 9007199254740992.0);
@@ -2118,69 +2165,108 @@ __device__ __forceinline__ int64_t count_of(const int32_t *q, int qb, int qe) {
   return n;
 }
 
-__global__ void k_sample(const float *arena, const SampleStep *steps, int n_steps, const int32_t *q,
-                         int n_vars, int64_t n, uint64_t seed, const int32_t *init, int32_t *out) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  int32_t *x = out + s * n_vars;
-  for (int v = 0; v < n_vars; ++v) x[v] = init[v];
-  for (int t = 0; t < n_steps; ++t) {
-    const SampleStep st = steps[t];
-    const float *A = arena + st.A;
-    const float *B = st.B >= 0 ? arena + st.B : nullptr;
-    int64_t oa = 0, ob = 0;
-    bool ok = true;
-    for (int i = st.aIn_b; i < st.aIn_e; ++i) {
-      ok = ok && x[q[4 * i]] >= 0;
-      oa += (int64_t)x[q[4 * i]] * q[4 * i + 2];
-    }
-    for (int i = st.bIn_b; i < st.bIn_e; ++i) {
-      ok = ok && x[q[4 * i]] >= 0;
-      ob += (int64_t)x[q[4 * i]] * q[4 * i + 3];
-    }
-    if (!ok) continue;  // an input left unassigned: leave this step's outputs unset
-    // shared eliminated labels: w(k) = (sum_pa A) * (sum_pb B)
-    if (st.k_e > st.k_b) {
-      const int64_t nK = count_of(q, st.k_b, st.k_e);
-      const int64_t nPa = count_of(q, st.pa_b, st.pa_e), nPb = count_of(q, st.pb_b, st.pb_e);
-      auto weight = [&](int64_t k) {
-        int64_t ka, kb;
-        decode_offsets(k, q, st.k_b, st.k_e, ka, kb);
-        double wa = 0.0, wb = 0.0;
-        for (int64_t p = 0; p < nPa; ++p) {
-          int64_t pa, dummy;
-          decode_offsets(p, q, st.pa_b, st.pa_e, pa, dummy);
-          wa += (double)A[oa + ka + pa];
-        }
-        if (B) {
-          for (int64_t p = 0; p < nPb; ++p) {
-            int64_t dummy, pb;
-            decode_offsets(p, q, st.pb_b, st.pb_e, dummy, pb);
-            wb += (double)B[ob + kb + pb];
-          }
-        } else {
-          wb = 1.0;
-        }
-        return wa * wb;
-      };
-      double tot = 0.0;
-      for (int64_t k = 0; k < nK; ++k) tot += weight(k);
-      const double target = uniform53((uint64_t)s, (uint32_t)st.node, 0u, seed) * tot;
-      double cum = 0.0;
-      int64_t pick = -1, last = 0;
-      for (int64_t k = 0; k < nK; ++k) {
+double sample_uniform(uint64_t sample, uint32_t node, uint32_t slot, uint64_t seed) {
+  return uniform53(sample, node, slot, seed);
+}
+
+// One wavefront per sample.  A categorical draw over n entries in canonical
+// order: lane l sums the weights of its contiguous chunk, an exclusive scan
+// over the lanes gives each chunk's starting cumulative weight, and the lane
+// whose chunk holds the target scans it: the first entry with positive
+// weight whose cumulative weight exceeds u * total (the last positive entry
+// if rounding leaves the target at the end) - the sequential rule, with the
+// sum associated chunk-wise.
+template <class W>
+__device__ __forceinline__ int64_t wave_draw(int64_t n, double u, W weight) {
+  const int lane = threadIdx.x & 63;
+  const int64_t ch = (n + 63) / 64, b0 = min(n, lane * ch), b1 = min(n, b0 + ch);
+  double part = 0.0;
+  int64_t lastpos = -1;
+  for (int64_t k = b0; k < b1; ++k) {
+    const double w = weight(k);
+    part += w;
+    if (w > 0.0) lastpos = k;
+  }
+  double incl = part;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  const double total = __shfl(incl, 63, 64);
+  const double excl = incl - part;
+  const double target = u * total;
+  const bool mine = part > 0.0 && incl > target;
+  const uint64_t m = __ballot(mine);
+  int64_t pick = -1;
+  if (m) {
+    const int L = __ffsll((unsigned long long)m) - 1;
+    if (lane == L) {
+      double cum = excl;
+      for (int64_t k = b0; k < b1; ++k) {
         const double w = weight(k);
-        if (w > 0.0) last = k;
         cum += w;
         if (w > 0.0 && cum > target) {
           pick = k;
           break;
         }
       }
-      if (pick < 0) pick = last;
+      if (pick < 0) pick = lastpos;
+    }
+    pick = __shfl(pick, L, 64);
+  } else {
+    // rounding: the last entry with positive weight (0 if none)
+    int64_t lp = lastpos;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) lp = max(lp, (int64_t)__shfl_xor(lp, o, 64));
+    pick = lp < 0 ? 0 : lp;
+  }
+  return pick;
+}
+
+__global__ void k_sample(const float *arena, const SampleStep *steps, int n_steps, const int32_t *q,
+                         int n_vars, int64_t n, uint64_t seed, const int32_t *init, const int64_t *ids,
+                         int32_t *out) {
+  const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (j >= n) return;  // whole waves
+  const int64_t s = ids ? ids[j] : j;
+  int32_t *x = out + s * n_vars;
+  // every lane writes the whole row with the same values, so each lane only
+  // ever reads back its own writes
+  for (int v = 0; v < n_vars; ++v) x[v] = init[v];
+  for (int t = 0; t < n_steps; ++t) {
+    const SampleStep st = steps[t];
+    const float *A = arena + st.A;
+    const float *B = st.B >= 0 ? arena + st.B : nullptr;
+    const float *Ar = arena + st.Ar;
+    const float *Br = st.Br >= 0 ? arena + st.Br : nullptr;
+    // offsets of the labels already drawn, in each child and its reduction
+    int64_t oa = 0, ob = 0, oar = 0, obr = 0;
+    bool ok = true;
+    for (int i = st.aIn_b; i < st.aIn_e; ++i) {
+      const int32_t xv = x[q[4 * i]];
+      ok = ok && xv >= 0;
+      oa += (int64_t)xv * q[4 * i + 2];
+      oar += (int64_t)xv * q[4 * i + 3];
+    }
+    for (int i = st.bIn_b; i < st.bIn_e; ++i) {
+      const int32_t xv = x[q[4 * i]];
+      ok = ok && xv >= 0;
+      ob += (int64_t)xv * q[4 * i + 2];
+      obr += (int64_t)xv * q[4 * i + 3];
+    }
+    if (!ok) continue;  // an input left unassigned: leave this step's outputs unset (uniform)
+    // shared eliminated labels: w(k) = Ar[z, k] * Br[z, k]
+    if (st.k_e > st.k_b) {
+      const int64_t nK = count_of(q, st.k_b, st.k_e);
+      const int64_t pick = wave_draw(nK, uniform53((uint64_t)s, (uint32_t)st.node, 0u, seed), [&](int64_t k) {
+        int64_t ka, kb;
+        decode_offsets(k, q, st.kr_b, st.kr_e, ka, kb);
+        return (double)Ar[oar + ka] * (Br ? (double)Br[obr + kb] : 1.0);
+      });
       int64_t ka, kb;
       decode_offsets(pick, q, st.k_b, st.k_e, ka, kb);
-      decode_assign(pick, q, st.k_b, st.k_e, x);
+      decode_assign(pick, q, st.k_b, st.k_e, x);  // every lane writes the same values
       oa += ka;
       ob += kb;
     }
@@ -2191,39 +2277,23 @@ __global__ void k_sample(const float *arena, const SampleStep *steps, int n_step
       const float *T = side ? B : A;
       const int64_t base = side ? ob : oa;
       const int64_t nP = count_of(q, pb, pe);
-      double tot = 0.0;
-      for (int64_t p = 0; p < nP; ++p) {
+      const int64_t pick = wave_draw(nP, uniform53((uint64_t)s, (uint32_t)st.node, 1u + side, seed), [&](int64_t p) {
         int64_t da, db;
         decode_offsets(p, q, pb, pe, da, db);
-        tot += (double)T[base + (side ? db : da)];
-      }
-      const double target = uniform53((uint64_t)s, (uint32_t)st.node, 1u + side, seed) * tot;
-      double cum = 0.0;
-      int64_t pick = -1, last = 0;
-      for (int64_t p = 0; p < nP; ++p) {
-        int64_t da, db;
-        decode_offsets(p, q, pb, pe, da, db);
-        const double w = (double)T[base + (side ? db : da)];
-        if (w > 0.0) last = p;
-        cum += w;
-        if (w > 0.0 && cum > target) {
-          pick = p;
-          break;
-        }
-      }
-      if (pick < 0) pick = last;
+        return (double)T[base + (side ? db : da)];
+      });
       decode_assign(pick, q, pb, pe, x);
     }
   }
 }
 
 void launch_sample(const float *arena, const SampleStep *steps, int n_steps, const int32_t *meta,
-                   int n_vars, int64_t n, uint64_t seed, const int32_t *init, int32_t *out,
-                   void *stream) {
+                   int n_vars, int64_t n, uint64_t seed, const int32_t *init, const int64_t *ids,
+                   int32_t *out, void *stream) {
   if (n <= 0) return;
-  const int64_t blocks = (n + 63) / 64;
-  k_sample<<<(unsigned)blocks, 64, 0, (hipStream_t)stream>>>(arena, steps, n_steps, meta, n_vars, n,
-                                                            seed, init, out);
+  const int64_t blocks = (n + 3) / 4;  // four samples (waves) per workgroup
+  k_sample<<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>(arena, steps, n_steps, meta, n_vars, n,
+                                                             seed, init, ids, out);
 }
 
 // --------------------------------------------------------------------------

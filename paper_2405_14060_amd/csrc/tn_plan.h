@@ -129,6 +129,8 @@ struct tn_plan_impl {
   int mode = 0;
   int max_batch = 1;
   bool inter = false;                  // batched tensors interleaved (instance fastest)
+  std::vector<tn::Op> samp_ops;        // sampling: children summed over their private labels
+  tn::Schedule sched_samp;
   bool want_sum = false, want_max = false, want_grad = false, is_mmap = false;
   std::vector<int> observed;           // mode SLICED
   std::vector<char> is_obs;

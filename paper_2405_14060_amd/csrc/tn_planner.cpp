@@ -324,19 +324,42 @@ static std::vector<Pair> greedy_pairs(const std::vector<Labels> &leaves, const s
 }
 
 PlanChoice plan_tree(const std::vector<Labels> &leaves, const std::vector<int> &card,
-                     const Labels &out, int strategy, int restarts, uint64_t seed) {
+                     const Labels &out, int strategy, int restarts, uint64_t seed, double cap) {
   const int n_vars = (int)card.size();
   std::vector<char> isout(n_vars, 0);
   for (int v : out) isout[v] = 1;
   PlanChoice best;
+  std::pair<double, double> best_key;
   bool have = false;
   auto consider = [&](std::vector<Pair> pairs, int which) {
     TreeStats st = tree_stats(leaves, pairs, out, card);
-    auto key = [](const TreeStats &s) { return std::make_pair(std::round(2 * s.sc) / 2, s.tc); };
-    if (!have || key(st) < key(best.stats)) {
+    std::pair<double, double> key(std::round(2 * st.sc) / 2, st.tc);
+    if (cap > 0 && st.sc > cap + 1e-9) {
+      // total work once sliced below the cap
+      Labels sl;
+      try {
+        sl = choose_slices(leaves, pairs, out, card, cap);
+      } catch (const TnError &) {
+        return;  // cannot be sliced below the cap (output labels)
+      }
+      std::vector<char> fixed(n_vars, 0);
+      for (int v : sl) fixed[v] = 1;
+      std::vector<Labels> lv(leaves.size());
+      for (size_t i = 0; i < leaves.size(); ++i)
+        for (int v : leaves[i])
+          if (!fixed[v]) lv[i].push_back(v);
+      const TreeStats ss = tree_stats(lv, pairs, out, card);
+      double ns = 1;
+      for (int v : sl) ns *= card[v];
+      key = std::make_pair(std::round(2 * cap) / 2, ss.flops > 0 ? std::log2(ss.flops * ns / 2) : 0);
+    } else if (cap > 0) {
+      key.first = std::round(2 * cap) / 2;  // within the cap: ranked by work alone
+    }
+    if (!have || key < best_key) {
       best.pairs = std::move(pairs);
       best.stats = st;
       best.planner = which;
+      best_key = key;
       have = true;
     }
   };

@@ -509,6 +509,30 @@ def test_sampling_same_rng_as_oracle(T):
     assert agree >= 0.99, agree
 
 
+def test_sliced_log_z_and_sampling(T):
+    """A sum-product plan sliced below its largest intermediate: log Z is the
+    sum over the slices, and sampling first draws each sample's slice with
+    probability Z_s / Z; same Philox stream as the oracle's sliced sampler."""
+    net = W.grid_mrf(4, 5, 11)
+    lv = oracle.build_leaves(net)
+    pairs = oracle.default_tree(lv)
+    P0 = T.Plan(T.Network(net), tree=pairs, semirings=T.SUM_PRODUCT)
+    cap = P0.info()["sc"] - 2
+    P = T.Plan(T.Network(net), tree=pairs, semirings=T.SUM_PRODUCT, max_log2_size=cap)
+    sliced = P.sliced_vars()
+    assert len(sliced) >= 1 and P.info()["sc"] <= cap
+    lz = P.log_z()[0]
+    assert rel(lz, oracle.log_z(net)) <= 1e-5
+    assert rel(lz, P0.log_z()[0]) <= 1e-5
+    n = 4000
+    s = P.sample(n, seed=77)
+    so = oracle.sample_sliced(lv, pairs, sliced, n, seed=77)
+    agree = np.mean(np.all(s == so, axis=1))
+    assert agree >= 0.99, agree
+    with pytest.raises(T.TNError):
+        P.marginals()
+
+
 def test_sampling_marginals(T):
     bn = W.random_bn(40, seed=12)
     obs, ev = W.bn_evidence(bn, seed=13, frac=0.2)

@@ -334,6 +334,52 @@ def test_sampler_marginals_within_four_sigma():
         assert abs(emp - p) < 4.5 * sig + 1e-12, v
 
 
+def test_slices_sum_to_the_partition_function():
+    """Z = sum over the slices of Z_s (fixing variables splits the sum of
+    eq. contraction-definition into disjoint parts), against brute force."""
+    net = W.grid_mrf(3, 4, 5)
+    lv = oracle.build_leaves(net)
+    pairs = oracle.default_tree(lv)
+    for sliced in ([0], [1, 6], [2, 5, 11]):
+        lz = oracle.slice_log_z(lv, pairs, sliced)
+        assert len(lz) == 2 ** len(sliced)
+        tot = lz.max() + math.log(np.exp(lz - lz.max()).sum())
+        assert abs(tot - bf.log_z(net)) <= 1e-10 * max(1.0, abs(tot))
+        # each slice equals the brute-force sum with those variables observed
+        for a, lzs in zip(oracle.slice_assignments(sliced, net.card), lz):
+            ev = -np.ones(net.n_vars, np.int32)
+            for v, x in a.items():
+                ev[v] = x
+            assert abs(lzs - bf.log_z(net, ev)) <= 1e-10 * max(1.0, abs(lzs))
+
+
+def test_sampler_counters_follow_ids():
+    net = W.grid_mrf(3, 3, 2)
+    lv = oracle.build_leaves(net)
+    pairs = oracle.default_tree(lv)
+    full = oracle.sample_tree(lv, pairs, 50, seed=8)
+    assert np.array_equal(oracle.sample_tree(lv, pairs, 50, seed=8, ids=np.arange(50)), full)
+    ids = np.array([3, 17, 40])
+    assert np.array_equal(oracle.sample_tree(lv, pairs, 3, seed=8, ids=ids), full[ids])
+
+
+def test_sliced_sampler_marginals_within_four_sigma():
+    """Drawing the slice with probability Z_s / Z, then sampling inside it,
+    samples the joint distribution: marginals against brute force."""
+    net = W.grid_mrf(3, 4, 9)
+    lv = oracle.build_leaves(net)
+    pairs = oracle.default_tree(lv)
+    n = 20000
+    s = oracle.sample_sliced(lv, pairs, [1, 6], n, seed=31)
+    assert np.all(s >= 0)
+    exact = bf.marginals(net)
+    for v in range(net.n_vars):
+        p = exact[v][1]
+        emp = np.mean(s[:, v] == 1)
+        sig = math.sqrt(p * (1 - p) / n)
+        assert abs(emp - p) < 4.5 * sig + 1e-12, v
+
+
 def test_sampler_joint_chi_square():
     from scipy import stats
     net = W.random_small_mrf(5, 7, seed=400, cards=(2, 3))
