@@ -213,7 +213,7 @@ def bench_regular3_mmap(args, T, W, np, sync):
     c = W.config(4, 0)
     net, q = c["net"], c["query"]
     plan = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT | T.MAX_PLUS, query=q, max_log2_size=28,
-                  use_graph=False, autotune=args.autotune)
+                  use_graph=False, autotune=args.autotune, restarts=16)
     info = plan.info()
     n_slices = 2 ** info["n_sliced"]
     t0 = time.perf_counter()
@@ -240,6 +240,20 @@ def bench_regular3_mmap(args, T, W, np, sync):
                roofline=roof, kernels_one_slice=kernels,
                certificate=dict(oracle_log_p_of_answer=lp_oracle, abs_diff=abs(lp_oracle - val),
                                 oracle_s=round(t_oracle_cert, 1)))
+    # the same network without the query: log Z and 10k samples from a
+    # sum-product plan sliced to the same cap (each sample draws its slice
+    # with probability Z_s / Z, then the per-node rule inside it)
+    splan = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, max_log2_size=28, restarts=16)
+    sinfo = splan.info()
+    t0 = time.perf_counter()
+    lz = splan.log_z()[0]
+    t_lz = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    smp = splan.sample(10000, seed=1)
+    t_s = time.perf_counter() - t0
+    out["sampling"] = dict(n=10000, seconds=round(t_s, 2), samples_per_s=round(10000 / t_s, 1), log_z=lz,
+                           log_z_seconds=round(t_lz, 2), n_sliced=sinfo["n_sliced"],
+                           tree_tc_log2=round(sinfo["tc"], 3), complete=bool(np.all(smp >= 0)))
     if not args.no_cpu_baseline:
         qs = set(int(v) for v in q)
         summed = [v for v in range(net.n_vars) if v not in qs]

@@ -327,7 +327,10 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
     if (Y >= 0) {
       const Labels Bl = inter(R, LY), Ml = minus(R, LY);
       const int64_t nB = numel(Bl, card), nM = numel(Ml, card);
-      const bool s_ok = semi == SEMI_SUM ? (a.nS >= 8 || a.nS == 1) : a.nS >= 8;
+      // eligible for any summed set (sum-product) or >= 8 entries (max-plus);
+      // the rules below take it for >= 8 entries or none (sum-product), the
+      // autotuner may take it for 2..7 as well
+      const bool s_ok = semi == SEMI_SUM ? true : a.nS >= 8;
       if (nM >= 16 && a.nC >= 8 && s_ok &&
           nB * ((nM + kGemmTile - 1) / kGemmTile) * (((int64_t)a.nC + kGemmTile - 1) / kGemmTile) < (1LL << 31)) {
         op.forms |= 4;
@@ -375,7 +378,7 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
       }
     }
     // rules: dense, else wave for long sums, else row, else generic
-    if (op.forms & 4) a.kind = 2;
+    if ((op.forms & 4) && (a.nS >= 8 || a.nS == 1)) a.kind = 2;
     else if (a.nS >= 64) a.kind = 3;
     else if (op.forms & 2) a.kind = 1;
     else a.kind = 0;

@@ -60,8 +60,9 @@ struct PlanChoice {
 // eliminated.  `strategy` is a TN_PLANNER_* value.  Candidates are ranked by
 // (largest intermediate, work); with a slicing cap (cap > 0) a candidate that
 // exceeds it is ranked by its total work once sliced below the cap (the
-// work of one slice times the number of slices), so that a tree with larger
-// intermediates but much less sliced work wins.
+// work of one slice plus a launch cost per node, times the number of
+// slices), so that a tree with larger intermediates but much less sliced
+// work wins.
 PlanChoice plan_tree(const std::vector<Labels> &leaves, const std::vector<int> &card,
                      const Labels &out, int strategy, int restarts, uint64_t seed, double cap = 0);
 

@@ -134,10 +134,10 @@ __device__ __forceinline__ int32_t tab_off(const Tab2 &t, uint32_t i, uint32_t n
 template <int SEMI, bool HASY>
 __device__ __forceinline__ void map_body(const ContractArgs &a, const int b, const uint32_t blk,
                                          const uint32_t nblk) {
-  const float *__restrict__ X = a.X + (int64_t)b * a.bsX;
-  const float *__restrict__ Y = HASY ? a.Y + (int64_t)b * a.bsY : nullptr;
-  float *__restrict__ Z = a.Z + (int64_t)b * a.bsZ;
-  int32_t *__restrict__ I = SEMI == SEMI_MAX ? a.I + (int64_t)b * a.bsZ : nullptr;
+  gcfloat *__restrict__ X = (gcfloat *)(a.X + (int64_t)b * a.bsX);
+  gcfloat *__restrict__ Y = HASY ? (gcfloat *)(a.Y + (int64_t)b * a.bsY) : nullptr;
+  gfloat *__restrict__ Z = (gfloat *)(a.Z + (int64_t)b * a.bsZ);
+  gint_w *__restrict__ I = SEMI == SEMI_MAX ? (gint_w *)(a.I + (int64_t)b * a.bsZ) : nullptr;
   float sx = 1.f, sy = 1.f;
   int kx = 0, ky = 0;
   if (SEMI == SEMI_SUM) {
@@ -227,8 +227,8 @@ static constexpr int kSplitOuts = 16;
 
 template <int SEMI, bool HASY>
 __device__ __forceinline__ void split_body(const ContractArgs &a, const int b, const uint32_t chunk) {
-  const float *__restrict__ X = a.X + (int64_t)b * a.bsX;
-  const float *__restrict__ Y = HASY ? a.Y + (int64_t)b * a.bsY : nullptr;
+  gcfloat *__restrict__ X = (gcfloat *)(a.X + (int64_t)b * a.bsX);
+  gcfloat *__restrict__ Y = HASY ? (gcfloat *)(a.Y + (int64_t)b * a.bsY) : nullptr;
   float sx = 1.f, sy = 1.f;
   if (SEMI == SEMI_SUM) {
     sx = ldexpf(1.f, -max_exponent(read_max(a.mx, a.mx_stride, a.slotX + (a.batX ? b : 0))));
@@ -345,7 +345,7 @@ template <int SEMI, bool HASY>
 __device__ __forceinline__ void finish_body(const ContractArgs &a, const int b, const uint32_t o) {
   // one block per output element: lanes stride over the chunks, then a
   // fixed-shape tree reduction (deterministic)
-  float *__restrict__ Z = a.Z + (int64_t)b * a.bsZ;
+  gfloat *__restrict__ Z = (gfloat *)(a.Z + (int64_t)b * a.bsZ);
   const uint32_t n_out = a.nR * a.nC;
   uint32_t r, c;
   if (a.col_fastest) {
@@ -384,7 +384,7 @@ __device__ __forceinline__ void finish_body(const ContractArgs &a, const int b, 
       }
     }
   } else {
-    int32_t *__restrict__ I = a.I + (int64_t)b * a.bsZ;
+    gint_w *__restrict__ I = (gint_w *)(a.I + (int64_t)b * a.bsZ);
     float bv = -INFINITY;
     int32_t bj = -1;
     for (uint32_t ch = threadIdx.x; ch < a.n_chunks; ch += kBlock) {
@@ -432,10 +432,10 @@ __device__ __forceinline__ void rows_body(const ContractArgs &a, const int b, co
                                           const uint32_t nblk) {
   // every argument is copied to registers before the loop: the arguments
   // live in device memory and stores to Z would otherwise force reloads
-  const float *__restrict__ X = a.X + (int64_t)b * a.bsX;
-  const float *__restrict__ Y = HASY ? a.Y + (int64_t)b * a.bsY : nullptr;
-  float *__restrict__ Z = a.Z + (int64_t)b * a.bsZ;
-  int32_t *__restrict__ I = SEMI == SEMI_MAX ? a.I + (int64_t)b * a.bsZ : nullptr;
+  gcfloat *__restrict__ X = (gcfloat *)(a.X + (int64_t)b * a.bsX);
+  gcfloat *__restrict__ Y = HASY ? (gcfloat *)(a.Y + (int64_t)b * a.bsY) : nullptr;
+  gfloat *__restrict__ Z = (gfloat *)(a.Z + (int64_t)b * a.bsZ);
+  gint_w *__restrict__ I = SEMI == SEMI_MAX ? (gint_w *)(a.I + (int64_t)b * a.bsZ) : nullptr;
   const int32_t *__restrict__ rXh = a.rX.hi, *__restrict__ rXl = a.rX.lo;
   const int32_t *__restrict__ rZh = a.rZ.hi, *__restrict__ rZl = a.rZ.lo;
   const int32_t *__restrict__ rYh = a.rY.hi, *__restrict__ rYl = a.rY.lo;
@@ -461,48 +461,70 @@ __device__ __forceinline__ void rows_body(const ContractArgs &a, const int b, co
     }
   }
   float lmax = 0.f;
-  for (uint32_t r = blk * kBlock + threadIdx.x; r < nR; r += nblk * kBlock) {
-    uint32_t rh, rl;
-    if (rls >= 0) {
-      rh = r >> rls;
-      rl = r & (nRl - 1);
-    } else {
-      rh = r / nRl;
-      rl = r - rh * nRl;
-    }
-    const int32_t xo = rXh[rh] + rXl[rl];
-    const int32_t zo = rZh[rh] + rZl[rl];
-    const int32_t yo = HASY ? rYh[rh] + rYl[rl] : 0;
-    float xv[B];
+  // U rows per lane per pass (U = 4 for the small sum-product variant): all
+  // their offsets and operand loads are issued before the first product;
+  // rows past nR repeat row 0's addresses and are not stored
+  constexpr int U = (B <= 4 && SEMI == SEMI_SUM) ? 4 : 1;
+  const uint32_t stride = nblk * kBlock;
+  for (uint32_t r0 = blk * kBlock + threadIdx.x; r0 < nR; r0 += U * stride) {
+    int32_t xo[U], zo[U], yo[U];
+    bool live[U];
 #pragma unroll
-    for (int k = 0; k < B; ++k)
-      if (k < ns) xv[k] = SEMI == SEMI_SUM ? X[xo + sx[k]] * fx : X[xo + sx[k]];
-#pragma unroll
-    for (int c = 0; c < B; ++c) {
-      if (c >= nc) continue;
-      const int32_t yc = yo + cy[c];
-      if (SEMI == SEMI_SUM) {
-        float acc = 0.f;
-#pragma unroll
-        for (int k = 0; k < B; ++k)
-          if (k < ns) acc = HASY ? fmaf(xv[k], Y[yc + sy[k]] * fy, acc) : acc + xv[k];
-        Z[zo + cz[c]] = acc;
-        lmax = fmaxf(lmax, acc);
+    for (int u = 0; u < U; ++u) {
+      const uint32_t r = r0 + u * stride;
+      live[u] = r < nR;
+      const uint32_t rr = live[u] ? r : 0u;
+      uint32_t rh, rl;
+      if (rls >= 0) {
+        rh = rr >> rls;
+        rl = rr & (nRl - 1);
       } else {
-        float best = -INFINITY;
-        int32_t bi = 0;
+        rh = rr / nRl;
+        rl = rr - rh * nRl;
+      }
+      xo[u] = ((gint *)rXh)[rh] + ((gint *)rXl)[rl];
+      zo[u] = ((gint *)rZh)[rh] + ((gint *)rZl)[rl];
+      yo[u] = HASY ? ((gint *)rYh)[rh] + ((gint *)rYl)[rl] : 0;
+    }
+    float xv[U][B];
 #pragma unroll
-        for (int k = 0; k < B; ++k)
-          if (k < ns) {
-            float v = xv[k];
-            if (HASY) v = v + Y[yc + sy[k]];
-            if (k == 0 || v > best) {
-              best = v;
-              bi = k;
-            }
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int k = 0; k < B; ++k)
+        if (k < ns) xv[u][k] = SEMI == SEMI_SUM ? X[xo[u] + sx[k]] * fx : X[xo[u] + sx[k]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+      for (int c = 0; c < B; ++c) {
+        if (c >= nc) continue;
+        const int32_t yc = yo[u] + cy[c];
+        if (SEMI == SEMI_SUM) {
+          float acc = 0.f;
+#pragma unroll
+          for (int k = 0; k < B; ++k)
+            if (k < ns) acc = HASY ? fmaf(xv[u][k], Y[yc + sy[k]] * fy, acc) : acc + xv[u][k];
+          if (live[u]) {
+            Z[zo[u] + cz[c]] = acc;
+            lmax = fmaxf(lmax, acc);
           }
-        Z[zo + cz[c]] = best;
-        I[zo + cz[c]] = bi;
+        } else {
+          float best = -INFINITY;
+          int32_t bi = 0;
+#pragma unroll
+          for (int k = 0; k < B; ++k)
+            if (k < ns) {
+              float v = xv[u][k];
+              if (HASY) v = v + Y[yc + sy[k]];
+              if (k == 0 || v > best) {
+                best = v;
+                bi = k;
+              }
+            }
+          if (live[u]) {
+            Z[zo[u] + cz[c]] = best;
+            I[zo[u] + cz[c]] = bi;
+          }
+        }
       }
     }
   }
@@ -529,10 +551,10 @@ static constexpr int kWaveOuts = kBlock / 64;  // outputs per workgroup pass
 template <int SEMI, bool HASY>
 __device__ __forceinline__ void wave_body(const ContractArgs &a, const int b, const uint32_t blk,
                                           const uint32_t nblk) {
-  const float *__restrict__ X = a.X + (int64_t)b * a.bsX;
-  const float *__restrict__ Y = HASY ? a.Y + (int64_t)b * a.bsY : nullptr;
-  float *__restrict__ Z = a.Z + (int64_t)b * a.bsZ;
-  int32_t *__restrict__ I = SEMI == SEMI_MAX ? a.I + (int64_t)b * a.bsZ : nullptr;
+  gcfloat *__restrict__ X = (gcfloat *)(a.X + (int64_t)b * a.bsX);
+  gcfloat *__restrict__ Y = HASY ? (gcfloat *)(a.Y + (int64_t)b * a.bsY) : nullptr;
+  gfloat *__restrict__ Z = (gfloat *)(a.Z + (int64_t)b * a.bsZ);
+  gint_w *__restrict__ I = SEMI == SEMI_MAX ? (gint_w *)(a.I + (int64_t)b * a.bsZ) : nullptr;
   float sx = 1.f, sy = 1.f;
   int kx = 0, ky = 0;
   if (SEMI == SEMI_SUM) {
@@ -820,10 +842,10 @@ __device__ __forceinline__ void gemm_max_body(const ContractArgs &a, const int b
   const uint32_t mt = rem / tn, nt = rem - mt * tn;
   const uint32_t m0 = mt * kGT, n0 = nt * kGT;
   const int32_t xb = tab_off(a.gbX, bt, a.nBl), yb = tab_off(a.gbY, bt, a.nBl), zb = tab_off(a.gbZ, bt, a.nBl);
-  const float *__restrict__ X = a.X + (int64_t)b * a.bsX + xb;
-  const float *__restrict__ Y = a.Y + (int64_t)b * a.bsY + yb;
-  float *__restrict__ Z = a.Z + (int64_t)b * a.bsZ + zb;
-  int32_t *__restrict__ I = a.I + (int64_t)b * a.bsZ + zb;
+  gcfloat *__restrict__ X = (gcfloat *)(a.X + (int64_t)b * a.bsX + xb);
+  gcfloat *__restrict__ Y = (gcfloat *)(a.Y + (int64_t)b * a.bsY + yb);
+  gfloat *__restrict__ Z = (gfloat *)(a.Z + (int64_t)b * a.bsZ + zb);
+  gint_w *__restrict__ I = (gint_w *)(a.I + (int64_t)b * a.bsZ + zb);
   if (w == 0) {
     const uint32_t m = m0 + l;
     oMX[l] = m < a.nM ? tab_off(a.gmX, m, a.nMl) : -1;

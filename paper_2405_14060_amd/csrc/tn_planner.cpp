@@ -351,7 +351,10 @@ PlanChoice plan_tree(const std::vector<Labels> &leaves, const std::vector<int> &
       const TreeStats ss = tree_stats(lv, pairs, out, card);
       double ns = 1;
       for (int v : sl) ns *= card[v];
-      key = std::make_pair(std::round(2 * cap) / 2, ss.flops > 0 ? std::log2(ss.flops * ns / 2) : 0);
+      // every slice also pays its launches: about 5 us per node, counted as
+      // 5e7 multiply-adds (20 TFLOP/s), so that many tiny slices do not win
+      const double per_slice = 5e7 * (double)pairs.size();
+      key = std::make_pair(std::round(2 * cap) / 2, std::log2(ss.flops * ns / 2 + per_slice * ns));
     } else if (cap > 0) {
       key.first = std::round(2 * cap) / 2;  // within the cap: ranked by work alone
     }
