@@ -1523,8 +1523,9 @@ static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
   } else {
     PlanChoice pc = plan_tree(p->leaf_lab, p->card, {}, o->planner, o->restarts, o->seed,
                               p->mode == TN_EVIDENCE_INDICATOR ? 0.0 : o->max_log2_size);
-    p->pairs = pc.pairs;
-    p->stats = pc.stats;
+    // chains of nodes below the fused-segment size (2^12 outputs) in fewer levels
+    p->pairs = rebalance_small_chains(p->leaf_lab, pc.pairs, {}, p->card, 11.0);
+    p->stats = tree_stats(p->leaf_lab, p->pairs, {}, p->card);
     p->planner_used = pc.planner;
   }
   auto lab = node_labels(p->leaf_lab, p->pairs, {}, p->n_vars);

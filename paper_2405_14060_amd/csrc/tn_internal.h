@@ -66,6 +66,12 @@ struct PlanChoice {
 PlanChoice plan_tree(const std::vector<Labels> &leaves, const std::vector<int> &card,
                      const Labels &out, int strategy, int restarts, uint64_t seed, double cap = 0);
 
+// Rebalance chains of nodes with at most 2^max_log2 outputs into balanced
+// trees over the same inputs (fewer sequential levels), when the largest
+// intermediate does not grow and the work grows by at most 10 %.
+std::vector<Pair> rebalance_small_chains(const std::vector<Labels> &leaves, const std::vector<Pair> &pairs,
+                                         const Labels &out, const std::vector<int> &card, double max_log2);
+
 // Pick labels to slice (fix per slice) so that every node output and every
 // node label union is at most 2^cap elements.
 Labels choose_slices(const std::vector<Labels> &leaves, const std::vector<Pair> &pairs,

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <functional>
 #include <limits>
 #include <numeric>
 #include <queue>
@@ -391,6 +392,78 @@ PlanChoice plan_tree(const std::vector<Labels> &leaves, const std::vector<int> &
   }
   if (!have) throw TnError(TN_E_INVALID, "unknown planner");
   return best;
+}
+
+// Tree refinement for launch count: a chain of small nodes, each absorbing
+// one side input into the previous node's result, takes one launch per node
+// however little work it does.  The same inputs contracted as a balanced tree
+// (adjacent inputs first, order kept) give the same result in log2(length)
+// levels, and the levels' independent nodes share launches.  A chain is
+// rebalanced only if the tree's largest intermediate does not grow and its
+// work grows by at most 10 %.
+std::vector<Pair> rebalance_small_chains(const std::vector<Labels> &leaves, const std::vector<Pair> &pairs,
+                                         const Labels &out, const std::vector<int> &card, double max_log2) {
+  const int L = (int)leaves.size(), P = (int)pairs.size(), N = L + P;
+  if (P < 3) return pairs;
+  const auto lab = node_labels(leaves, pairs, out, (int)card.size());
+  std::vector<int> left(N, -1), right(N, -1), parent(N, -1), nleaf(N, 1);
+  for (int q = 0; q < P; ++q) {
+    const int c = L + q;
+    left[c] = pairs[q][0];
+    right[c] = pairs[q][1];
+    parent[left[c]] = parent[right[c]] = c;
+    nleaf[c] = nleaf[left[c]] + nleaf[right[c]];
+  }
+  auto small = [&](int c) { return c >= L && log2size(lab[c], card) <= max_log2 + 1e-9; };
+  // carrier child of a small internal node: its small internal child with
+  // more leaves (the other child is a side input)
+  auto carrier = [&](int c) {
+    const int a = left[c], b = right[c];
+    const bool sa = small(a), sb = small(b);
+    if (sa && sb) return nleaf[a] >= nleaf[b] ? a : b;
+    return sa ? a : (sb ? b : -1);
+  };
+  // new tree: item lists per rebuilt chain top, emitted recursively
+  std::vector<std::vector<int>> items_of(N);
+  std::vector<char> rebuilt(N, 0);
+  for (int c = L; c < N; ++c) {
+    if (!small(c)) continue;
+    const int pc = parent[c];
+    if (pc >= 0 && small(pc) && carrier(pc) == c) continue;  // not a chain top
+    std::vector<int> chain;  // top down
+    for (int x = c; x >= 0 && small(x); x = carrier(x)) chain.push_back(x);
+    if (chain.size() < 3) continue;
+    std::vector<int> items;
+    const int bottom = chain.back();
+    items.push_back(left[bottom]);
+    items.push_back(right[bottom]);
+    for (int i = (int)chain.size() - 2; i >= 0; --i) {
+      const int x = chain[i], cx = chain[i + 1];
+      items.push_back(left[x] == cx ? right[x] : left[x]);
+    }
+    items_of[c] = items;
+    rebuilt[c] = 1;
+  }
+  std::vector<Pair> np;
+  std::function<int(int)> emit;
+  std::function<int(const std::vector<int> &, int, int)> balanced = [&](const std::vector<int> &it, int lo, int hi) {
+    if (hi - lo == 1) return emit(it[lo]);
+    const int mid = (lo + hi + 1) / 2;
+    const int a = balanced(it, lo, mid), b = balanced(it, mid, hi);
+    np.push_back({a, b});
+    return L + (int)np.size() - 1;
+  };
+  emit = [&](int c) -> int {
+    if (c < L) return c;
+    if (rebuilt[c]) return balanced(items_of[c], 0, (int)items_of[c].size());
+    const int a = emit(left[c]), b = emit(right[c]);
+    np.push_back({a, b});
+    return L + (int)np.size() - 1;
+  };
+  emit(N - 1);
+  const TreeStats s0 = tree_stats(leaves, pairs, out, card), s1 = tree_stats(leaves, np, out, card);
+  if (s1.sc > s0.sc + 1e-9 || s1.flops > 1.1 * s0.flops) return pairs;
+  return np;
 }
 
 Labels choose_slices(const std::vector<Labels> &leaves, const std::vector<Pair> &pairs,
