@@ -156,6 +156,7 @@ typedef struct {
   int32_t n_interleaved;         /* contractions in the interleaved-instance form */
   int32_t batch_stride;          /* interleaved plans: instances held per element (max_batch
                                     rounded up to a multiple of 64); 0 otherwise */
+  int32_t n_dense_large;         /* of n_dense: contractions with 128 x 128 output tiles */
 } tn_plan_info;
 
 /* Fill *o with defaults: sum-product + max-plus, no evidence, best planner,

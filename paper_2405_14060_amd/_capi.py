@@ -65,7 +65,8 @@ class PlanInfo(ctypes.Structure):
                 ("n_launches_bwd", ctypes.c_int32), ("n_launches_max", ctypes.c_int32),
                 ("n_segments", ctypes.c_int32), ("n_fused_nodes", ctypes.c_int32),
                 ("n_dense", ctypes.c_int32), ("n_wave", ctypes.c_int32),
-                ("n_interleaved", ctypes.c_int32), ("batch_stride", ctypes.c_int32)]
+                ("n_interleaved", ctypes.c_int32), ("batch_stride", ctypes.c_int32),
+                ("n_dense_large", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

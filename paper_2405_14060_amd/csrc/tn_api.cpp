@@ -377,11 +377,18 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
         a.rl_shift = sh;
       }
     }
-    // rules: dense, else wave for long sums, else row, else generic
+    // large dense tiles (FP32 sum-product): 128 x 128 output tiles where
+    // rows and columns are wide and the summed set fills a chunk
+    if ((op.forms & 4) && semi == SEMI_SUM && p->opts.dtype == TN_F32 && a.nM >= 128 && a.nC >= 128 &&
+        a.nS >= 16)
+      op.forms |= 256;
+    // rules: dense (large tiles where eligible), else wave for long sums,
+    // else row, else generic
     if ((op.forms & 4) && (a.nS >= 8 || a.nS == 1)) a.kind = 2;
     else if (a.nS >= 64) a.kind = 3;
     else if (op.forms & 2) a.kind = 1;
     else a.kind = 0;
+    if (op.forms & 256) a.tile = 1;
   }
   op.flops = 2.0 * (double)n_out * (double)a.nS;
   op.bytes = 4.0 * (double)(p->T[X].size + (Y >= 0 ? p->T[Y].size : 0) + p->T[Z].size);
@@ -780,7 +787,15 @@ static Schedule build_schedule(tn_plan_t *p, const std::vector<Op> &ops, bool al
         for (int i = 0; i < n; ++i) {
           const Op &op = ops[i];
           const int c = op.split ? 1 : (op.a.kind == 2 ? 2 : (op.a.kind == 4 ? 3 : 0));
-          if (stage[i] == st && op.seg < 0 && op.semi == semi && c == cls) L.ops.push_back(i);
+          if (stage[i] == st && op.seg < 0 && op.semi == semi && c == cls) {
+            if (c == 2 && op.a.tile == 1) {  // large dense tiles: a launch of their own
+              Launch one = L;
+              one.ops.push_back(i);
+              sc.launches.push_back(std::move(one));
+            } else {
+              L.ops.push_back(i);
+            }
+          }
         }
         if (!L.ops.empty()) sc.launches.push_back(std::move(L));
       }
@@ -850,9 +865,9 @@ static void autotune_ops(tn_plan_t *p, const std::vector<Op *> &ops) {
   hipEvent_t e0, e1;
   hip_check(hipEventCreate(&e0), "event");
   hip_check(hipEventCreate(&e1), "event");
-  // (form bit, kind, workgroup split of the summed range, interleaved tile)
-  static const int kForm[8][4] = {{1, 0, 1, 0},  {2, 1, 1, 0},  {4, 2, 1, 0},  {8, 3, 1, 0},
-                                  {16, 4, 1, 0}, {32, 4, 4, 0}, {64, 4, 1, 1}, {128, 4, 1, 2}};
+  // (form bit, kind, workgroup split of the summed range, tile variant)
+  static const int kForm[9][4] = {{1, 0, 1, 0},  {2, 1, 1, 0},  {4, 2, 1, 0},    {8, 3, 1, 0},  {16, 4, 1, 0},
+                                  {32, 4, 4, 0}, {64, 4, 1, 1}, {128, 4, 1, 2}, {256, 2, 1, 1}};
   for (Op *op : ops) {
     if (op->split || op->seg >= 0) continue;
     std::vector<std::array<int, 3>> cands;
@@ -1727,6 +1742,7 @@ extern "C" tn_status tn_plan_info_get(const tn_plan_t *p, tn_plan_info *info) {
     for (const auto *L : {&p->sum_tree.ops, &p->bwd, &p->qtree.ops, &p->max_tree.ops})
       for (const Op &op : *L) {
         info->n_dense += op.a.kind == 2 ? 1 : 0;
+        info->n_dense_large += op.a.kind == 2 && op.a.tile == 1 ? 1 : 0;
         info->n_wave += op.a.kind == 3 ? 1 : 0;
         info->n_interleaved += op.a.kind == 4 ? 1 : 0;
       }
@@ -1734,6 +1750,7 @@ extern "C" tn_status tn_plan_info_get(const tn_plan_t *p, tn_plan_info *info) {
     for (const auto &g : p->groups)
       for (const Op &op : g.ops) {
         info->n_dense += op.a.kind == 2 ? 1 : 0;
+        info->n_dense_large += op.a.kind == 2 && op.a.tile == 1 ? 1 : 0;
         info->n_wave += op.a.kind == 3 ? 1 : 0;
       }
   });

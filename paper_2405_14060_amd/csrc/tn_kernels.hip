@@ -947,6 +947,166 @@ __global__ __launch_bounds__(kBlock) void k_gemm(const ContractArgs *__restrict_
 }
 
 // --------------------------------------------------------------------------
+// dense form with large tiles (FP32 sum-product, wide row and column sets):
+// a 128 x 128 tile of Z[M, N] = sum_S X[M, S] Y[S, N] per workgroup, each
+// wave a 64 x 64 quarter as 4 x 4 v_mfma_f32_16x16x4_f32 tiles.  A chunk of
+// 16 summed entries sits in LDS summed-fastest (rows of A and columns of B,
+// pitch 20 floats), so one 128-bit LDS read gives a lane its operand for four
+// MFMA steps: in step j the lanes of group g = l / 16 supply summed entry
+// 4 g + j of both operands, which covers the chunk once.  Two LDS buffers:
+// the next chunk's global loads are in flight during this chunk's products,
+// and one barrier per chunk separates the reuse of a buffer.  The tile leaves
+// through LDS in two halves of 64 rows with consecutive threads on Z's
+// stride-1 label.  Workgroup ids are remapped so that the workgroups one XCD
+// receives (every eighth id) take consecutive tiles, which share operand
+// rows and columns in that XCD's L2.
+// --------------------------------------------------------------------------
+static constexpr int kBT = 2 * kGemmTile;  // 128
+static constexpr int kBK = 16;             // summed entries per chunk
+static constexpr int kBKP = 20;            // LDS pitch of a row (column) of a chunk, floats
+static constexpr int kBCP = kBT + 1;       // epilogue pitch
+static constexpr int kBBuf = 2 * kBT * kBKP;  // floats of one buffer (A rows, then B columns)
+static constexpr int kBSOff = 1024;        // largest summed set whose offsets are staged in LDS
+
+template <bool XS, bool YN>
+__device__ __forceinline__ void gemm_big_body(const ContractArgs &a, const int b, const uint32_t blk,
+                                              const uint32_t nblk) {
+  __shared__ int32_t oMX[kBT], oMZ[kBT], oNY[kBT], oNZ[kBT];
+  __shared__ int32_t sOX[kBSOff], sOY[kBSOff];
+  __shared__ __align__(16) float AB[2 * kBBuf];
+  __shared__ int ksh[2];
+  static_assert(64 * kBCP <= 2 * kBBuf, "half of the epilogue tile fits the operand buffers");
+  const int t = threadIdx.x, l = t & 63, w = t >> 6;
+  const uint32_t tile = (nblk & 7u) == 0 ? (blk & 7u) * (nblk >> 3) + (blk >> 3) : blk;
+  const uint32_t tm = (a.nM + kBT - 1) / kBT, tn = (a.nC + kBT - 1) / kBT;
+  const uint32_t bt = tile / (tm * tn), rem = tile - bt * tm * tn;
+  const uint32_t mt = rem / tn, nt = rem - mt * tn;
+  const uint32_t m0 = mt * kBT, n0 = nt * kBT;
+  const int32_t xb = tab_off(a.gbX, bt, a.nBl), yb = tab_off(a.gbY, bt, a.nBl), zb = tab_off(a.gbZ, bt, a.nBl);
+  gcfloat *__restrict__ X = (gcfloat *)(a.X + (int64_t)b * a.bsX + xb);
+  gcfloat *__restrict__ Y = (gcfloat *)(a.Y + (int64_t)b * a.bsY + yb);
+  gfloat *__restrict__ Z = (gfloat *)(a.Z + (int64_t)b * a.bsZ + zb);
+  const uint32_t nS = a.nS;
+  const bool staged = nS <= (uint32_t)kBSOff;
+  // prologue: row offsets (waves 0, 1), column offsets and the operands'
+  // exponents (waves 2, 3), small summed sets' offsets (all)
+  if (t < kBT) {
+    const uint32_t m = m0 + t;
+    oMX[t] = m < a.nM ? tab_off(a.gmX, m, a.nMl) : -1;
+    oMZ[t] = m < a.nM ? tab_off(a.gmZ, m, a.nMl) : -1;
+  } else {
+    const uint32_t n = n0 + (t - kBT);
+    oNY[t - kBT] = n < a.nC ? tab_off(a.cY, n, a.nCl) : -1;
+    oNZ[t - kBT] = n < a.nC ? tab_off(a.cZ, n, a.nCl) : -1;
+    const int slot = w == 2 ? a.slotX + (a.batX ? b : 0) : a.slotY + (a.batY ? b : 0);
+    const int k = max_exponent(read_max(a.mx, a.mx_stride, slot));
+    if (l == 0) ksh[w - 2] = k;
+  }
+  if (staged)
+    for (uint32_t s = t; s < nS; s += kBlock) {
+      sOX[s] = tab_off(a.sX, s, a.nSl);
+      sOY[s] = tab_off(a.sY, s, a.nSl);
+    }
+  __syncthreads();
+  const int kx = ksh[0], ky = ksh[1];
+  const float sx = ldexpf(1.f, -kx), sy = ldexpf(1.f, -ky);
+  // 8 entries of each operand per thread and chunk, consecutive threads on
+  // the operand's stride-1 label: summed-fast A takes (row t / 16 + 16 q,
+  // summed t % 16), row-fast A (row t % 128, summed t / 128 + 2 q); B alike
+  constexpr int NQ = kBT * kBK / kBlock;
+  const int kA0 = XS ? (t & 15) : (t >> 7), kB0 = YN ? (t >> 7) : (t & 15);
+  const int32_t oa0 = XS ? 0 : oMX[t & 127], ob0 = YN ? oNY[t & 127] : 0;
+  auto rowA = [&](int q) { return XS ? (t >> 4) + 16 * q : (t & 127); };
+  auto sumA = [&](int q) { return XS ? kA0 : kA0 + 2 * q; };
+  auto colB = [&](int q) { return YN ? (t & 127) : (t >> 4) + 16 * q; };
+  auto sumB = [&](int q) { return YN ? kB0 + 2 * q : kB0; };
+  auto sx_off = [&](uint32_t s) { return staged ? sOX[s] : tab_off(a.sX, s, a.nSl); };
+  auto sy_off = [&](uint32_t s) { return staged ? sOY[s] : tab_off(a.sY, s, a.nSl); };
+  // every address in bounds (rows past the tile and summed entries past nS
+  // read entry 0 of the operand), masked afterwards
+  auto load_chunk = [&](uint32_t s0, float (&va)[NQ], float (&vb)[NQ]) {
+    const uint32_t sa = s0 + kA0, sb = s0 + kB0;
+    const int32_t oxc = XS ? sx_off(sa < nS ? sa : 0u) : 0, oyc = YN ? 0 : sy_off(sb < nS ? sb : 0u);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const uint32_t s = s0 + sumA(q), s2 = s0 + sumB(q);
+      const int32_t om = XS ? oMX[rowA(q)] : oa0, on = YN ? ob0 : oNY[colB(q)];
+      const int32_t ox = XS ? oxc : sx_off(s < nS ? s : 0u);
+      const int32_t oy = YN ? sy_off(s2 < nS ? s2 : 0u) : oyc;
+      const float x = X[(om >= 0 ? om : 0) + ox];
+      const float y = Y[(on >= 0 ? on : 0) + oy];
+      va[q] = (om >= 0 && s < nS) ? x * sx : 0.f;
+      vb[q] = (on >= 0 && s2 < nS) ? y * sy : 0.f;
+    }
+  };
+  f32x4 acc[4][4] = {};
+  const int wm = w & 1, wn = w >> 1, g = l >> 4, li = l & 15;
+  float va[NQ], vb[NQ];
+  load_chunk(0, va, vb);
+  uint32_t c = 0;
+  for (uint32_t s0 = 0; s0 < nS; s0 += kBK, ++c) {
+    float *As = AB + (c & 1u) * kBBuf, *Bs = As + kBT * kBKP;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      As[rowA(q) * kBKP + sumA(q)] = va[q];
+      Bs[colB(q) * kBKP + sumB(q)] = vb[q];
+    }
+    __syncthreads();
+    if (s0 + kBK < nS) load_chunk(s0 + kBK, va, vb);  // in flight during the products below
+    f32x4 av[4], bv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      av[i] = *(const f32x4 *)&As[(64 * wm + 16 * i + li) * kBKP + 4 * g];
+      bv[i] = *(const f32x4 *)&Bs[(64 * wn + 16 * i + li) * kBKP + 4 * g];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+          acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][j], bv[jj][j], acc[i][jj], 0, 0, 0);
+  }
+  // epilogue: two halves of 64 rows through LDS
+  float lmax = 0.f;
+  float *Cs = AB;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    __syncthreads();  // the operand buffers (or the previous half) are no longer read
+    if (wm == h) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            Cs[(16 * i + 4 * g + r) * kBCP + 64 * wn + 16 * jj + li] = acc[i][jj][r];
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int q = 0; q < 64 * kBT / kBlock; ++q) {
+      const int e = t + q * kBlock;
+      int m, n;
+      if (a.z_n_fast) { n = e % kBT; m = e / kBT; } else { m = e % 64; n = e / 64; }
+      const int32_t om = oMZ[64 * h + m], on = oNZ[n];
+      if (om >= 0 && on >= 0) {
+        const float v = Cs[m * kBCP + n];
+        Z[om + on] = v;
+        lmax = fmaxf(lmax, v);
+      }
+    }
+  }
+  block_record_max(lmax, a.mx + (blk % kMaxSub) * a.mx_stride + a.slotZ + (a.batZ ? b : 0));
+  if (blk == 0 && threadIdx.x == 0)
+    a.ex[a.slotZ + (a.batZ ? b : 0)] = a.ex[a.slotX + (a.batX ? b : 0)] + kx + a.ex[a.slotY + (a.batY ? b : 0)] + ky;
+}
+
+template <bool XS, bool YN>
+__global__ __launch_bounds__(kBlock) void k_gemm_big(const ContractArgs *__restrict__ ap) {
+  gemm_big_body<XS, YN>(*ap, blockIdx.y, blockIdx.x, gridDim.x);
+}
+
+// --------------------------------------------------------------------------
 // interleaved-instance form (batched evidence).  Element e of instance b of
 // a batched tensor sits at e * es + b, so one wavefront computes the same
 // output elements for 64 consecutive instances (lane = instance): every
@@ -1357,6 +1517,8 @@ uint32_t map_blocks(const ContractArgs &a) {
     const uint32_t blocks = a.ksplit > 1 ? tiles : (tiles + kBlock / 64 - 1) / (kBlock / 64);
     return blocks > 256u ? 256u : blocks;
   }
+  if (a.kind == 2 && a.tile == 1)  // one 128 x 128 tile per workgroup
+    return a.nB * ((a.nM + kBT - 1) / kBT) * ((a.nC + kBT - 1) / kBT);
   if (a.kind == 2)  // one 64 x 64 tile per workgroup
     return a.nB * ((a.nM + kGT - 1) / kGT) * ((a.nC + kGT - 1) / kGT);
   const uint32_t n_out = a.kind == 1 ? a.nR : a.nR * a.nC;
@@ -1381,6 +1543,14 @@ void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, co
       if (has_y) k_inter<SEMI_MAX, true><<<g, kBlock, 0, s>>>(d_a);
       else k_inter<SEMI_MAX, false><<<g, kBlock, 0, s>>>(d_a);
     }
+    return;
+  }
+  if (a.kind == 2 && a.tile == 1) {  // large tiles: FP32 sum-product only
+    const dim3 g(map_blocks(a), nb);
+    if (a.x_s_fast && a.y_n_fast) k_gemm_big<true, true><<<g, kBlock, 0, s>>>(d_a);
+    else if (a.x_s_fast) k_gemm_big<true, false><<<g, kBlock, 0, s>>>(d_a);
+    else if (a.y_n_fast) k_gemm_big<false, true><<<g, kBlock, 0, s>>>(d_a);
+    else k_gemm_big<false, false><<<g, kBlock, 0, s>>>(d_a);
     return;
   }
   if (a.kind == 2) {

@@ -51,7 +51,7 @@ struct Op {
   int seg = -1, seg_kind = 0;
   std::vector<int> ins, outs;
   int forms = 0;                      // eligible kernel forms: 1 generic, 2 row, 4 dense, 8 wave,
-                                      // 16 interleaved
+                                      // 16 interleaved, 256 dense with 128 x 128 tiles
 };
 
 // Host description of a fused segment (tables as offsets into the plan's

@@ -209,6 +209,45 @@ def test_dense_form_against_oracle(T, seed):
         assert max(np.abs(x - y).max() for x, y in zip(got, want_m)) <= 1e-5, b
 
 
+def gemm_net(n_s, order, seed):
+    """Three factors over batch (B), row (M), summed (S) and column (N)
+    variables, X(B, M, S), Y(B, S, N), Z(B, M, N): ternary M, N and S
+    variables give row / column / summed sets that are not multiples of the
+    dense tiles.  `order` permutes the variable ids (which labels are
+    stride-1 in each operand)."""
+    rng = np.random.default_rng(seed)
+    card = np.array([2] * 2 + [3] * 5 + [3] * n_s + [3] * 5, np.int32)
+    n = card.size
+    perm = np.arange(n) if order == "contiguous" else rng.permutation(n)
+    B, M, S, N = perm[:2], perm[2:7], perm[7:7 + n_s], perm[7 + n_s:]
+    card = card[np.argsort(perm)]
+    scopes = [np.sort(np.concatenate(g)).astype(np.int32) for g in ((B, M, S), (B, S, N), (B, M, N))]
+    vals = [rng.normal(0.0, 0.3, int(np.prod(card[sc]))) for sc in scopes]
+    return W.Network(card=card.astype(np.int32), scopes=scopes, values=vals, is_log=True)
+
+
+@pytest.mark.parametrize("order", ["contiguous", "shuffled"])
+def test_large_dense_tiles_against_oracle(T, order):
+    """Contractions in the dense form with 128 x 128 tiles (rows, columns
+    and summed sets of 243: ragged in every dimension) against the oracle:
+    log Z and all marginals (the reverse pass holds large-tile contractions
+    too); with 2187 summed entries (offsets looked up per element) log Z."""
+    net = gemm_net(5, order, 5)
+    P = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT)
+    assert P.info()["n_dense_large"] > 0
+    lz, m = P.marginals()
+    pairs, _ = P.tree()
+    lzo, marg, *_ = oracle.marginals(net, pairs=pairs.astype(np.int64))
+    assert rel(lz[0], lzo) <= 1e-5
+    got = P.split_marginals(m[0])
+    assert max(np.abs(a - b).max() for a, b in zip(got, marg)) <= 1e-5
+    net = gemm_net(7, order, 6)
+    P = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT)
+    assert P.info()["n_dense_large"] > 0
+    pairs, _ = P.tree()
+    assert rel(P.log_z()[0], oracle.log_z(net, pairs=pairs.astype(np.int64))) <= 1e-5
+
+
 @pytest.mark.parametrize("dtype,tol_lz,tol_m", [("bf16", 1e-3, 5e-3), ("f16", 1e-3, 5e-3)])
 def test_low_precision_matrix_cores(T, dtype, tol_lz, tol_m):
     """BF16 / FP16 operands on the matrix cores (FP32 accumulation, FP32
