@@ -953,9 +953,10 @@ __global__ __launch_bounds__(kBlock) void k_gemm(const ContractArgs *__restrict_
 // 16 summed entries sits in LDS summed-fastest (rows of A and columns of B,
 // pitch 20 floats), so one 128-bit LDS read gives a lane its operand for four
 // MFMA steps: in step j the lanes of group g = l / 16 supply summed entry
-// 4 g + j of both operands, which covers the chunk once.  Two LDS buffers:
-// the next chunk's global loads are in flight during this chunk's products,
-// and one barrier per chunk separates the reuse of a buffer.  The tile leaves
+// 4 g + j of both operands, which covers the chunk once.  Two LDS buffers
+// and two register sets: the global loads of the chunk after next are in
+// flight during this chunk's products, and one barrier per chunk separates
+// the reuse of an LDS buffer.  The tile leaves
 // through LDS in two halves of 64 rows with consecutive threads on Z's
 // stride-1 label.  Workgroup ids are remapped so that the workgroups one XCD
 // receives (every eighth id) take consecutive tiles, which share operand
@@ -1023,36 +1024,39 @@ __device__ __forceinline__ void gemm_big_body(const ContractArgs &a, const int b
   auto sx_off = [&](uint32_t s) { return staged ? sOX[s] : tab_off(a.sX, s, a.nSl); };
   auto sy_off = [&](uint32_t s) { return staged ? sOY[s] : tab_off(a.sY, s, a.nSl); };
   // every address in bounds (rows past the tile and summed entries past nS
-  // read entry 0 of the operand), masked afterwards
-  auto load_chunk = [&](uint32_t s0, float (&va)[NQ], float (&vb)[NQ]) {
+  // read entry 0 of the operand); the raw values stay untouched until they
+  // are stored to LDS, so that the loads of the next chunk stay in flight
+  // during this chunk's products, and the validity of each entry is a bit
+  auto load_chunk = [&](uint32_t s0, float (&ra)[NQ], float (&rb)[NQ], uint32_t &valid) {
     const uint32_t sa = s0 + kA0, sb = s0 + kB0;
     const int32_t oxc = XS ? sx_off(sa < nS ? sa : 0u) : 0, oyc = YN ? 0 : sy_off(sb < nS ? sb : 0u);
+    valid = 0;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const uint32_t s = s0 + sumA(q), s2 = s0 + sumB(q);
       const int32_t om = XS ? oMX[rowA(q)] : oa0, on = YN ? ob0 : oNY[colB(q)];
       const int32_t ox = XS ? oxc : sx_off(s < nS ? s : 0u);
       const int32_t oy = YN ? sy_off(s2 < nS ? s2 : 0u) : oyc;
-      const float x = X[(om >= 0 ? om : 0) + ox];
-      const float y = Y[(on >= 0 ? on : 0) + oy];
-      va[q] = (om >= 0 && s < nS) ? x * sx : 0.f;
-      vb[q] = (on >= 0 && s2 < nS) ? y * sy : 0.f;
+      ra[q] = X[max(om, 0) + ox];
+      rb[q] = Y[max(on, 0) + oy];
+      valid |= ((om >= 0 && s < nS) ? 1u : 0u) << q;
+      valid |= ((on >= 0 && s2 < nS) ? 1u : 0u) << (q + NQ);
     }
   };
   f32x4 acc[4][4] = {};
   const int wm = w & 1, wn = w >> 1, g = l >> 4, li = l & 15;
-  float va[NQ], vb[NQ];
-  load_chunk(0, va, vb);
-  uint32_t c = 0;
-  for (uint32_t s0 = 0; s0 < nS; s0 += kBK, ++c) {
+  // chunk c: its raw values (loaded two chunks ahead, register set c % 2)
+  // go to LDS buffer c % 2, then the loads of chunk c + 2 are issued, then
+  // the products of chunk c run
+  auto step = [&](uint32_t s0, uint32_t c, float (&ra)[NQ], float (&rb)[NQ], uint32_t &valid) {
     float *As = AB + (c & 1u) * kBBuf, *Bs = As + kBT * kBKP;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      As[rowA(q) * kBKP + sumA(q)] = va[q];
-      Bs[colB(q) * kBKP + sumB(q)] = vb[q];
+      As[rowA(q) * kBKP + sumA(q)] = (valid >> q & 1u) ? ra[q] * sx : 0.f;
+      Bs[colB(q) * kBKP + sumB(q)] = (valid >> (q + NQ) & 1u) ? rb[q] * sy : 0.f;
     }
     __syncthreads();
-    if (s0 + kBK < nS) load_chunk(s0 + kBK, va, vb);  // in flight during the products below
+    if (s0 + 2 * kBK < nS) load_chunk(s0 + 2 * kBK, ra, rb, valid);
     f32x4 av[4], bv[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -1066,6 +1070,14 @@ __device__ __forceinline__ void gemm_big_body(const ContractArgs &a, const int b
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj)
           acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][j], bv[jj][j], acc[i][jj], 0, 0, 0);
+  };
+  float ra0[NQ], rb0[NQ], ra1[NQ], rb1[NQ];
+  uint32_t valid0, valid1 = 0;
+  load_chunk(0, ra0, rb0, valid0);
+  if (kBK < nS) load_chunk(kBK, ra1, rb1, valid1);
+  for (uint32_t s0 = 0, c = 0; s0 < nS; s0 += 2 * kBK, c += 2) {
+    step(s0, c, ra0, rb0, valid0);
+    if (s0 + kBK < nS) step(s0 + kBK, c + 1, ra1, rb1, valid1);
   }
   // epilogue: two halves of 64 rows through LDS
   float lmax = 0.f;
@@ -1101,8 +1113,9 @@ __device__ __forceinline__ void gemm_big_body(const ContractArgs &a, const int b
     a.ex[a.slotZ + (a.batZ ? b : 0)] = a.ex[a.slotX + (a.batX ? b : 0)] + kx + a.ex[a.slotY + (a.batY ? b : 0)] + ky;
 }
 
+// three workgroups per CU (LDS holds three; registers capped to match)
 template <bool XS, bool YN>
-__global__ __launch_bounds__(kBlock) void k_gemm_big(const ContractArgs *__restrict__ ap) {
+__global__ __launch_bounds__(kBlock, 3) void k_gemm_big(const ContractArgs *__restrict__ ap) {
   gemm_big_body<XS, YN>(*ap, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
