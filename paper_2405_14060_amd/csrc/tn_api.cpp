@@ -378,9 +378,9 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
       }
     }
     // large dense tiles (FP32 sum-product): 128 x 128 output tiles where
-    // rows and columns are wide and the summed set fills a chunk
-    if ((op.forms & 4) && semi == SEMI_SUM && p->opts.dtype == TN_F32 && a.nM >= 128 && a.nC >= 128 &&
-        a.nS >= 16)
+    // rows and columns are wide; the rules take them where the summed set
+    // fills a chunk of 16, the autotuner may take them for shorter sums
+    if ((op.forms & 4) && semi == SEMI_SUM && p->opts.dtype == TN_F32 && a.nM >= 128 && a.nC >= 128)
       op.forms |= 256;
     // rules: dense (large tiles where eligible), else wave for long sums,
     // else row, else generic
@@ -388,7 +388,7 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
     else if (a.nS >= 64) a.kind = 3;
     else if (op.forms & 2) a.kind = 1;
     else a.kind = 0;
-    if (op.forms & 256) a.tile = 1;
+    if (a.kind == 2 && (op.forms & 256) && a.nS >= 16) a.tile = 1;
   }
   op.flops = 2.0 * (double)n_out * (double)a.nS;
   op.bytes = 4.0 * (double)(p->T[X].size + (Y >= 0 ? p->T[Y].size : 0) + p->T[Z].size);
