@@ -466,6 +466,19 @@ __device__ __forceinline__ void rows_body(const ContractArgs &a, const int b, co
   // rows past nR repeat row 0's addresses and are not stored
   constexpr int U = (B <= 4 && SEMI == SEMI_SUM) ? 4 : 1;
   const uint32_t stride = nblk * kBlock;
+  // With low tables of a power of two >= 64 entries the 64 rows of a wave
+  // (64-aligned, consecutive) share one high entry, and with a grid stride
+  // that is a multiple of the low table every row of a lane has the same low
+  // entry: the lane reads its low offsets once, and the high ones are one
+  // wave-uniform read per row group.
+  const bool fixed_lo = rls >= 6 && (stride & (nRl - 1)) == 0;
+  int32_t xl = 0, zl = 0, yl = 0;
+  if (fixed_lo) {
+    const uint32_t rl = (blk * kBlock + threadIdx.x) & (nRl - 1);
+    xl = ((gint *)rXl)[rl];
+    zl = ((gint *)rZl)[rl];
+    yl = HASY ? ((gint *)rYl)[rl] : 0;
+  }
   for (uint32_t r0 = blk * kBlock + threadIdx.x; r0 < nR; r0 += U * stride) {
     int32_t xo[U], zo[U], yo[U];
     bool live[U];
@@ -474,6 +487,13 @@ __device__ __forceinline__ void rows_body(const ContractArgs &a, const int b, co
       const uint32_t r = r0 + u * stride;
       live[u] = r < nR;
       const uint32_t rr = live[u] ? r : 0u;
+      if (fixed_lo) {  // nR is a multiple of nRl >= 64: live is wave-uniform, so is rh
+        const uint32_t rh = __builtin_amdgcn_readfirstlane(rr >> rls);
+        xo[u] = ((gint *)rXh)[rh] + xl;
+        zo[u] = ((gint *)rZh)[rh] + zl;
+        yo[u] = HASY ? ((gint *)rYh)[rh] + yl : 0;
+        continue;
+      }
       uint32_t rh, rl;
       if (rls >= 0) {
         rh = rr >> rls;
