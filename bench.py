@@ -65,13 +65,14 @@ def kernel_summary(prof):
     return agg
 
 
-def roofline(plan, task, workload, evidence=None, batch=1):
-    """Dominant kernel kind of one task by executed time; its launches timed
-    back to back between two HIP events on the plan's stream."""
+def roofline(plan, task, workload, evidence=None, batch=1, kernel=None):
+    """Dominant kernel kind of one task by executed time (or the named kind);
+    its launches timed back to back between two HIP events on the plan's
+    stream."""
     prof = plan.profile(task, reps=3, evidence=evidence, batch=batch)
     agg = kernel_summary(prof)
     flops_task = sum(fl for _, fl, _, _ in prof)
-    dom_name, _ = max(agg.items(), key=lambda kv: kv[1]["ms"])
+    dom_name = kernel or max(agg.items(), key=lambda kv: kv[1]["ms"])[0]
     kind_of = {v: k for k, v in KIND_NAMES.items()}
     avg_ms, fl_launch, by_launch, n_launch = plan.profile_kind(task, kind_of[dom_name], reps=5,
                                                                evidence=evidence, batch=batch)
@@ -223,6 +224,8 @@ def bench_regular3_mmap(args, T, W, np, sync):
     prof = plan.profile(3, reps=1)
     slice_s = sum(ms for _, _, _, ms in prof) / 1e3
     roof, kernels, slice_flops = roofline(plan, 3, "regular3_220")
+    # the matrix-core kernel of the slice against the FP32 matrix-core peak
+    roof_dense = roofline(plan, 3, "regular3_220", kernel="contract_mfma_sum")[0]
     # certificate at full size: log p(Q = x) by the oracle (the network with
     # the query variables observed is small) equals the reported value
     import oracle
@@ -237,7 +240,7 @@ def bench_regular3_mmap(args, T, W, np, sync):
                            tree_sc_log2=round(info["sc"], 3), tree_tc_log2=round(info["tc"], 3),
                            device_gb=round(info["device_bytes"] / 1e9, 2), graph=False, autotune=args.autotune),
                log_value=val, slice_ms=round(slice_s * 1e3, 3), tflops=round(slice_flops / slice_s / 1e12, 3),
-               roofline=roof, kernels_one_slice=kernels,
+               roofline=roof, roofline_dense=roof_dense, kernels_one_slice=kernels,
                certificate=dict(oracle_log_p_of_answer=lp_oracle, abs_diff=abs(lp_oracle - val),
                                 oracle_s=round(t_oracle_cert, 1)))
     # the same network without the query: log Z and 10k samples from a

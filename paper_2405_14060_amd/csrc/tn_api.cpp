@@ -380,7 +380,9 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
     // large dense tiles (FP32 sum-product): 128 x 128 output tiles where
     // rows and columns are wide; the rules take them where the summed set
     // fills a chunk of 16, the autotuner may take them for shorter sums
-    if ((op.forms & 4) && semi == SEMI_SUM && p->opts.dtype == TN_F32 && a.nM >= 128 && a.nC >= 128)
+    // (operands below 2^29 entries per instance: 32-bit byte offsets)
+    if ((op.forms & 4) && semi == SEMI_SUM && p->opts.dtype == TN_F32 && a.nM >= 128 && a.nC >= 128 &&
+        p->T[X].size < (int64_t(1) << 29) && p->T[Y].size < (int64_t(1) << 29))
       op.forms |= 256;
     // rules: dense (large tiles where eligible), else wave for long sums,
     // else row, else generic

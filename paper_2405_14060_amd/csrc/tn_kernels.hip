@@ -989,11 +989,20 @@ static constexpr int kBCP = kBT + 1;       // epilogue pitch
 static constexpr int kBBuf = 2 * kBT * kBKP;  // floats of one buffer (A rows, then B columns)
 static constexpr int kBSOff = 1024;        // largest summed set whose offsets are staged in LDS
 
-template <bool XS, bool YN>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void *base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)0xffffffff, 0x00020000);
+}
+
+// one FP32 word per lane at byte offset row + lane (the builtin returns the raw bits)
+__device__ __forceinline__ float ld_row(__amdgpu_buffer_rsrc_t r, int lane_off, int row_off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, lane_off, row_off, 0));
+}
+
+template <bool XS, bool YN, bool ST>
 __device__ __forceinline__ void gemm_big_body(const ContractArgs &a, const int b, const uint32_t blk,
                                               const uint32_t nblk) {
   __shared__ int32_t oMX[kBT], oMZ[kBT], oNY[kBT], oNZ[kBT];
-  __shared__ int32_t sOX[kBSOff], sOY[kBSOff];
+  __shared__ int32_t sOX[ST ? kBSOff : 1], sOY[ST ? kBSOff : 1];
   __shared__ __align__(16) float AB[2 * kBBuf];
   __shared__ int ksh[2];
   static_assert(64 * kBCP <= 2 * kBBuf, "half of the epilogue tile fits the operand buffers");
@@ -1004,13 +1013,14 @@ __device__ __forceinline__ void gemm_big_body(const ContractArgs &a, const int b
   const uint32_t mt = rem / tn, nt = rem - mt * tn;
   const uint32_t m0 = mt * kBT, n0 = nt * kBT;
   const int32_t xb = tab_off(a.gbX, bt, a.nBl), yb = tab_off(a.gbY, bt, a.nBl), zb = tab_off(a.gbZ, bt, a.nBl);
-  gcfloat *__restrict__ X = (gcfloat *)(a.X + (int64_t)b * a.bsX + xb);
-  gcfloat *__restrict__ Y = (gcfloat *)(a.Y + (int64_t)b * a.bsY + yb);
+  // operands through buffer resources (each operand below 2^30 entries:
+  // 32-bit byte offsets)
+  const __amdgpu_buffer_rsrc_t rX = raw_rsrc(a.X + (int64_t)b * a.bsX + xb);
+  const __amdgpu_buffer_rsrc_t rY = raw_rsrc(a.Y + (int64_t)b * a.bsY + yb);
   gfloat *__restrict__ Z = (gfloat *)(a.Z + (int64_t)b * a.bsZ + zb);
   const uint32_t nS = a.nS;
-  const bool staged = nS <= (uint32_t)kBSOff;
   // prologue: row offsets (waves 0, 1), column offsets and the operands'
-  // exponents (waves 2, 3), small summed sets' offsets (all)
+  // exponents (waves 2, 3), the summed entries' offsets (all)
   if (t < kBT) {
     const uint32_t m = m0 + t;
     oMX[t] = m < a.nM ? tab_off(a.gmX, m, a.nMl) : -1;
@@ -1023,60 +1033,83 @@ __device__ __forceinline__ void gemm_big_body(const ContractArgs &a, const int b
     const int k = max_exponent(read_max(a.mx, a.mx_stride, slot));
     if (l == 0) ksh[w - 2] = k;
   }
-  if (staged)
+  if (ST)
     for (uint32_t s = t; s < nS; s += kBlock) {
-      sOX[s] = tab_off(a.sX, s, a.nSl);
-      sOY[s] = tab_off(a.sY, s, a.nSl);
+      sOX[s] = tab_off(a.sX, s, a.nSl) * 4;
+      sOY[s] = tab_off(a.sY, s, a.nSl) * 4;
     }
   __syncthreads();
   const int kx = ksh[0], ky = ksh[1];
   const float sx = ldexpf(1.f, -kx), sy = ldexpf(1.f, -ky);
   // 8 entries of each operand per thread and chunk, consecutive threads on
   // the operand's stride-1 label: summed-fast A takes (row t / 16 + 16 q,
-  // summed t % 16), row-fast A (row t % 128, summed t / 128 + 2 q); B alike
+  // summed t % 16), row-fast A (row t % 128, summed t / 128 + 2 q); B alike.
+  // Row (column) byte offsets are fixed per thread; rows past the operand
+  // read its entry 0 and are masked at the LDS store.
   constexpr int NQ = kBT * kBK / kBlock;
   const int kA0 = XS ? (t & 15) : (t >> 7), kB0 = YN ? (t >> 7) : (t & 15);
-  const int32_t oa0 = XS ? 0 : oMX[t & 127], ob0 = YN ? oNY[t & 127] : 0;
   auto rowA = [&](int q) { return XS ? (t >> 4) + 16 * q : (t & 127); };
   auto sumA = [&](int q) { return XS ? kA0 : kA0 + 2 * q; };
   auto colB = [&](int q) { return YN ? (t & 127) : (t >> 4) + 16 * q; };
   auto sumB = [&](int q) { return YN ? kB0 + 2 * q : kB0; };
-  auto sx_off = [&](uint32_t s) { return staged ? sOX[s] : tab_off(a.sX, s, a.nSl); };
-  auto sy_off = [&](uint32_t s) { return staged ? sOY[s] : tab_off(a.sY, s, a.nSl); };
-  // every address in bounds (rows past the tile and summed entries past nS
-  // read entry 0 of the operand); the raw values stay untouched until they
-  // are stored to LDS, so that the loads of the next chunk stay in flight
-  // during this chunk's products, and the validity of each entry is a bit
-  auto load_chunk = [&](uint32_t s0, float (&ra)[NQ], float (&rb)[NQ], uint32_t &valid) {
+  int32_t oa[XS ? NQ : 1], ob[YN ? 1 : NQ];
+  uint32_t live = 0;  // bit q: A entry q's row exists; bit NQ + q: B entry q's column
+#pragma unroll
+  for (int q = 0; q < (XS ? NQ : 1); ++q) {
+    const int32_t o = oMX[rowA(q)];
+    oa[q] = o >= 0 ? o * 4 : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < (YN ? 1 : NQ); ++q) {
+    const int32_t o = oNY[colB(q)];
+    ob[q] = o >= 0 ? o * 4 : 0;
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    live |= (oMX[rowA(q)] >= 0 ? 1u : 0u) << q;
+    live |= (oNY[colB(q)] >= 0 ? 1u : 0u) << (q + NQ);
+  }
+  auto sx_off = [&](uint32_t s) { return ST ? sOX[s] : tab_off(a.sX, s, a.nSl) * 4; };
+  auto sy_off = [&](uint32_t s) { return ST ? sOY[s] : tab_off(a.sY, s, a.nSl) * 4; };
+  // raw values stay untouched until their LDS store, so that the loads of
+  // later chunks stay in flight during this chunk's products; summed
+  // entries past nS read entry 0 and are masked at the store
+  auto load_chunk = [&](uint32_t s0, float (&ra)[NQ], float (&rb)[NQ]) {
     const uint32_t sa = s0 + kA0, sb = s0 + kB0;
     const int32_t oxc = XS ? sx_off(sa < nS ? sa : 0u) : 0, oyc = YN ? 0 : sy_off(sb < nS ? sb : 0u);
-    valid = 0;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const uint32_t s = s0 + sumA(q), s2 = s0 + sumB(q);
-      const int32_t om = XS ? oMX[rowA(q)] : oa0, on = YN ? ob0 : oNY[colB(q)];
-      const int32_t ox = XS ? oxc : sx_off(s < nS ? s : 0u);
-      const int32_t oy = YN ? sy_off(s2 < nS ? s2 : 0u) : oyc;
-      ra[q] = X[max(om, 0) + ox];
-      rb[q] = Y[max(on, 0) + oy];
-      valid |= ((om >= 0 && s < nS) ? 1u : 0u) << q;
-      valid |= ((on >= 0 && s2 < nS) ? 1u : 0u) << (q + NQ);
+      const int32_t ox = XS ? oa[q] + oxc : oa[0] + sx_off(s < nS ? s : 0u);
+      const int32_t oy = YN ? ob[0] + sy_off(s2 < nS ? s2 : 0u) : ob[q] + oyc;
+      ra[q] = ld_row(rX, ox, 0);
+      rb[q] = ld_row(rY, oy, 0);
     }
   };
   f32x4 acc[4][4] = {};
   const int wm = w & 1, wn = w >> 1, g = l >> 4, li = l & 15;
+  const bool full_rows = live == (1u << (2 * NQ)) - 1u;
   // chunk c: its raw values (loaded two chunks ahead, register set c % 2)
   // go to LDS buffer c % 2, then the loads of chunk c + 2 are issued, then
   // the products of chunk c run
-  auto step = [&](uint32_t s0, uint32_t c, float (&ra)[NQ], float (&rb)[NQ], uint32_t &valid) {
+  auto step = [&](uint32_t s0, uint32_t c, float (&ra)[NQ], float (&rb)[NQ]) {
     float *As = AB + (c & 1u) * kBBuf, *Bs = As + kBT * kBKP;
+    if (full_rows && s0 + kBK <= nS) {
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      As[rowA(q) * kBKP + sumA(q)] = (valid >> q & 1u) ? ra[q] * sx : 0.f;
-      Bs[colB(q) * kBKP + sumB(q)] = (valid >> (q + NQ) & 1u) ? rb[q] * sy : 0.f;
+      for (int q = 0; q < NQ; ++q) {
+        As[rowA(q) * kBKP + sumA(q)] = ra[q] * sx;
+        Bs[colB(q) * kBKP + sumB(q)] = rb[q] * sy;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const bool va = (live >> q & 1u) && s0 + sumA(q) < nS, vb = (live >> (q + NQ) & 1u) && s0 + sumB(q) < nS;
+        As[rowA(q) * kBKP + sumA(q)] = va ? ra[q] * sx : 0.f;
+        Bs[colB(q) * kBKP + sumB(q)] = vb ? rb[q] * sy : 0.f;
+      }
     }
     __syncthreads();
-    if (s0 + 2 * kBK < nS) load_chunk(s0 + 2 * kBK, ra, rb, valid);
+    if (s0 + 2 * kBK < nS) load_chunk(s0 + 2 * kBK, ra, rb);
     f32x4 av[4], bv[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -1092,12 +1125,11 @@ __device__ __forceinline__ void gemm_big_body(const ContractArgs &a, const int b
           acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][j], bv[jj][j], acc[i][jj], 0, 0, 0);
   };
   float ra0[NQ], rb0[NQ], ra1[NQ], rb1[NQ];
-  uint32_t valid0, valid1 = 0;
-  load_chunk(0, ra0, rb0, valid0);
-  if (kBK < nS) load_chunk(kBK, ra1, rb1, valid1);
+  load_chunk(0, ra0, rb0);
+  if (kBK < nS) load_chunk(kBK, ra1, rb1);
   for (uint32_t s0 = 0, c = 0; s0 < nS; s0 += 2 * kBK, c += 2) {
-    step(s0, c, ra0, rb0, valid0);
-    if (s0 + kBK < nS) step(s0 + kBK, c + 1, ra1, rb1, valid1);
+    step(s0, c, ra0, rb0);
+    if (s0 + kBK < nS) step(s0 + kBK, c + 1, ra1, rb1);
   }
   // epilogue: two halves of 64 rows through LDS
   float lmax = 0.f;
@@ -1134,9 +1166,9 @@ __device__ __forceinline__ void gemm_big_body(const ContractArgs &a, const int b
 }
 
 // three workgroups per CU (LDS holds three; registers capped to match)
-template <bool XS, bool YN>
+template <bool XS, bool YN, bool ST>
 __global__ __launch_bounds__(kBlock, 3) void k_gemm_big(const ContractArgs *__restrict__ ap) {
-  gemm_big_body<XS, YN>(*ap, blockIdx.y, blockIdx.x, gridDim.x);
+  gemm_big_body<XS, YN, ST>(*ap, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
 // --------------------------------------------------------------------------
@@ -1167,14 +1199,6 @@ __device__ __forceinline__ int32_t bcast(int32_t v, int lane) { return __builtin
 
 // raw buffer over a tensor (no range limit: every offset is in bounds by
 // construction); word 3 as for all gfx9 parts
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void *base) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)0xffffffff, 0x00020000);
-}
-
-// one FP32 word per lane at byte offset row + lane (the builtin returns the raw bits)
-__device__ __forceinline__ float ld_row(__amdgpu_buffer_rsrc_t r, int lane_off, int row_off) {
-  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, lane_off, row_off, 0));
-}
 
 template <int TM, int TN>
 struct InterShared {
@@ -1580,10 +1604,20 @@ void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, co
   }
   if (a.kind == 2 && a.tile == 1) {  // large tiles: FP32 sum-product only
     const dim3 g(map_blocks(a), nb);
-    if (a.x_s_fast && a.y_n_fast) k_gemm_big<true, true><<<g, kBlock, 0, s>>>(d_a);
-    else if (a.x_s_fast) k_gemm_big<true, false><<<g, kBlock, 0, s>>>(d_a);
-    else if (a.y_n_fast) k_gemm_big<false, true><<<g, kBlock, 0, s>>>(d_a);
-    else k_gemm_big<false, false><<<g, kBlock, 0, s>>>(d_a);
+    const bool st = a.nS <= (uint32_t)kBSOff;  // summed offsets staged in LDS
+    if (a.x_s_fast && a.y_n_fast) {
+      if (st) k_gemm_big<true, true, true><<<g, kBlock, 0, s>>>(d_a);
+      else k_gemm_big<true, true, false><<<g, kBlock, 0, s>>>(d_a);
+    } else if (a.x_s_fast) {
+      if (st) k_gemm_big<true, false, true><<<g, kBlock, 0, s>>>(d_a);
+      else k_gemm_big<true, false, false><<<g, kBlock, 0, s>>>(d_a);
+    } else if (a.y_n_fast) {
+      if (st) k_gemm_big<false, true, true><<<g, kBlock, 0, s>>>(d_a);
+      else k_gemm_big<false, true, false><<<g, kBlock, 0, s>>>(d_a);
+    } else {
+      if (st) k_gemm_big<false, false, true><<<g, kBlock, 0, s>>>(d_a);
+      else k_gemm_big<false, false, false><<<g, kBlock, 0, s>>>(d_a);
+    }
     return;
   }
   if (a.kind == 2) {
