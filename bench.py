@@ -217,15 +217,23 @@ def bench_regular3_mmap(args, T, W, np, sync):
                   use_graph=False, autotune=args.autotune, restarts=16)
     info = plan.info()
     n_slices = 2 ** info["n_sliced"]
-    t0 = time.perf_counter()
-    val, x = plan.mmap()
-    sync()
-    sec = time.perf_counter() - t0
+    if not args.slice_only:
+        t0 = time.perf_counter()
+        val, x = plan.mmap()
+        sync()
+        sec = time.perf_counter() - t0
     prof = plan.profile(3, reps=1)
     slice_s = sum(ms for _, _, _, ms in prof) / 1e3
     roof, kernels, slice_flops = roofline(plan, 3, "regular3_220")
     # the matrix-core kernel of the slice against the FP32 matrix-core peak
     roof_dense = roofline(plan, 3, "regular3_220", kernel="contract_mfma_sum")[0]
+    if args.slice_only:  # profiling aid: one slice, time of the query projected from it
+        return dict(value=1.0 / (slice_s * n_slices), unit="MMAP solves/s (projected from one slice)",
+                    ms_per_step=round(slice_s * n_slices * 1e3, 1), dtype="f32",
+                    config=dict(workload="regular3 220 vars, MMAP with 25 query vars, intermediates <= 2^28 "
+                                "(sliced), one slice", seed=0, n_slices=n_slices, autotune=args.autotune),
+                    slice_ms=round(slice_s * 1e3, 3), roofline=roof, roofline_dense=roof_dense,
+                    kernels_one_slice=kernels)
     # certificate at full size: log p(Q = x) by the oracle (the network with
     # the query variables observed is small) equals the reported value
     import oracle
@@ -328,6 +336,8 @@ def main():
                          "contraction shape at plan time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--slice-only", action="store_true",
+                    help="regular3_mmap: plan and profile one slice only (for profilers)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
