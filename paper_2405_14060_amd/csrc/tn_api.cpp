@@ -791,7 +791,9 @@ static Schedule build_schedule(tn_plan_t *p, const std::vector<Op> &ops, bool al
           const int c = op.split ? 1 : (op.a.kind == 2 ? 2 : (op.a.kind == 4 ? 3 : 0));
           if (stage[i] == st && op.seg < 0 && op.semi == semi && c == cls) {
             if (c == 2 && op.a.tile == 1) {  // large dense tiles: a launch of their own
-              Launch one = L;
+              Launch one;
+              one.semi = semi;
+              one.gemm = true;
               one.ops.push_back(i);
               sc.launches.push_back(std::move(one));
             } else {

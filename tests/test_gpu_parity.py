@@ -226,6 +226,42 @@ def gemm_net(n_s, order, seed):
     return W.Network(card=card.astype(np.int32), scopes=scopes, values=vals, is_log=True)
 
 
+def two_gemm_nets(seed):
+    """Two disconnected three-factor networks of the same shape, one with
+    243-wide row, column and summed sets (128 x 128 dense tiles), one with
+    27-wide sets (64 x 64 dense tiles): their contractions fall in the same
+    stages, so a stage holds dense contractions of both tile sizes."""
+    rng = np.random.default_rng(seed)
+    scopes, vals, card = [], [], []
+    for width in (5, 3):
+        base = len(card)
+        cd = [2] * 2 + [3] * width + [3] * width + [3] * width
+        ids = base + np.arange(len(cd))
+        B, M, S, N = ids[:2], ids[2:2 + width], ids[2 + width:2 + 2 * width], ids[2 + 2 * width:]
+        card += cd
+        for g in ((B, M, S), (B, S, N), (B, M, N)):
+            sc = np.sort(np.concatenate(g)).astype(np.int32)
+            scopes.append(sc)
+            vals.append(rng.normal(0.0, 0.3, int(np.prod(np.asarray(card)[sc]))))
+    return W.Network(card=np.asarray(card, np.int32), scopes=scopes, values=vals, is_log=True)
+
+
+def test_mixed_dense_tile_stages_against_oracle(T):
+    """Stages holding dense contractions with both tile sizes (each large-tile
+    contraction launches alone, the others grouped): log Z and all marginals
+    against the oracle."""
+    net = two_gemm_nets(7)
+    P = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT)
+    info = P.info()
+    assert info["n_dense_large"] > 0 and info["n_dense"] > info["n_dense_large"]
+    lz, m = P.marginals()
+    pairs, _ = P.tree()
+    lzo, marg, *_ = oracle.marginals(net, pairs=pairs.astype(np.int64))
+    assert rel(lz[0], lzo) <= 1e-5
+    got = P.split_marginals(m[0])
+    assert max(np.abs(a - b).max() for a, b in zip(got, marg)) <= 1e-5
+
+
 @pytest.mark.parametrize("order", ["contiguous", "shuffled"])
 def test_large_dense_tiles_against_oracle(T, order):
     """Contractions in the dense form with 128 x 128 tiles (rows, columns
