@@ -338,6 +338,31 @@ def test_autotuned_plans_against_oracle(T):
     assert np.float32(lp[0]) == np.float32(v32)
 
 
+def test_autotuned_dense_and_mmap_against_oracle(T):
+    """The autotuner choosing among the dense tile sizes and the other forms
+    (stages may then mix large-tile and grouped contractions): marginals of
+    the two-width three-factor networks, and a sliced MMAP plan."""
+    net = two_gemm_nets(8)
+    P = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, autotune=True)
+    lz, m = P.marginals()
+    pairs, _ = P.tree()
+    lzo, marg, *_ = oracle.marginals(net, pairs=pairs.astype(np.int64))
+    assert rel(lz[0], lzo) <= 1e-5
+    got = P.split_marginals(m[0])
+    assert max(np.abs(a - b).max() for a, b in zip(got, marg)) <= 1e-5
+    net = W.random_regular3(40, seed=1, n_query=4)
+    q = net.meta["query"]
+    ov, ox, ogap = oracle.mmap(net, q)
+    P0 = T.Plan(T.Network(net), query=q)
+    cap = max(float(len(q)), P0.info()["sc"] - 2)
+    P = T.Plan(T.Network(net), query=q, max_log2_size=cap, autotune=True)
+    assert P.info()["n_sliced"] > 0
+    val, x = P.mmap()
+    assert abs(val - ov) <= 1e-5 * max(1, abs(ov))
+    if ogap > 1e-4:
+        assert np.array_equal(x, ox)
+
+
 def test_grid20x20_full_size_against_oracle(T):
     ref = json.load(open(os.path.join(GOLDEN, "oracle_grid20x20_seed0.json")))
     net = W.grid_mrf(20, 20, 0)
