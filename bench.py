@@ -46,6 +46,8 @@ KIND_NAMES = {0: "contract_map_sum", 1: "contract_map_max", 2: "contract_split_s
 MEASURED_TRAFFIC = {
     ("seg_carrier_bwd", "grid20x20"): {"src": "8cadff1e7370275b", "bytes": 13260152},
     ("contract_interleaved_sum", "bn500x512"): {"src": "8cadff1e7370275b", "bytes": 69857854},
+    ("contract_map_sum", "regular3_220"): {"src": "8cadff1e7370275b", "bytes": 419927695},
+    ("contract_mfma_sum", "regular3_220"): {"src": "8cadff1e7370275b", "bytes": 1145658192},
 }
 
 
