@@ -344,8 +344,8 @@ def main():
                     help="also run a plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU; runs on more than one GPU are not part of this build "
-              "(the path shards by evidence instance or slice, see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only; a run on several GPUs would shard the work by evidence "
+              "instance or by slice, and is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
