@@ -1584,6 +1584,12 @@ uint32_t map_blocks(const ContractArgs &a) {
     return blocks > 4096u ? 4096u : blocks;
   }
   uint32_t blocks = (n_out + kBlock - 1) / kBlock;
+  // Grid-stride launches of about 8 workgroups per CU, except over many
+  // outputs (>= 2^22), where one pass per lane (four rows per lane in the
+  // row form) leaves the overlap of memory latency to the hardware's wave
+  // dispatch: measured on 2^24..2^27-row contractions, a long grid-stride
+  // loop per wave ran at 1.3-1.6 TB/s, one pass per lane 1.7-2.2 TB/s.
+  if (n_out >= (1u << 22)) return a.kind == 1 ? (blocks + 3) / 4 : blocks;
   return blocks > 2048u ? 2048u : blocks;
 }
 
