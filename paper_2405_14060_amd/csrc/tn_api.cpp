@@ -238,7 +238,7 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
   if (semi == SEMI_MAX && !minus(C, LY).empty()) throw TnError(TN_E_INVALID, "internal: broadcast in max-plus node");
   const size_t rs = lo_split(R, card), cs = lo_split(C, card), ss = lo_split(S, card);
   for (auto *t : {op.t_rX, op.t_rY, op.t_rZ, op.t_cY, op.t_cZ, op.t_sX, op.t_sY, op.t_gbX, op.t_gbY, op.t_gbZ,
-                  op.t_gmX, op.t_gmZ})
+                  op.t_gmX, op.t_gmZ, op.t_oX, op.t_oY})
     t[0] = t[1] = -1;
   add_tabs(p, R, rs, LX, op.t_rX);
   add_tabs(p, R, rs, LZ, op.t_rZ);
@@ -324,6 +324,16 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
   // vector ALUs
   if (!op.split) {
     op.forms = 1 | 8;
+    // generic form in output order: for large outputs whose writes the
+    // (rows, columns) enumeration would scatter (labels of X and of Y
+    // interleaved in Z's layout); the autotuner may take it
+    if (n_out >= (1u << 16)) {
+      op.forms |= 512;
+      const size_t os = lo_split(LZ, card);
+      add_tabs(p, LZ, os, LX, op.t_oX);
+      if (Y >= 0) add_tabs(p, LZ, os, LY, op.t_oY);
+      a.nOl = (uint32_t)numel(Labels(LZ.begin() + os, LZ.end()), card);
+    }
     if (Y >= 0) {
       const Labels Bl = inter(R, LY), Ml = minus(R, LY);
       const int64_t nB = numel(Bl, card), nM = numel(Ml, card);
@@ -390,6 +400,15 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
     else if (a.nS >= 64) a.kind = 3;
     else if (op.forms & 2) a.kind = 1;
     else a.kind = 0;
+    // the generic form writes runs of Z as long as the trailing labels of Z
+    // of the class it enumerates fastest; below 16 entries it takes the
+    // output order
+    if (a.kind == 0 && (op.forms & 512)) {
+      const Labels &fast = a.col_fastest ? C : R;
+      int64_t run = 1;
+      for (auto it = LZ.rbegin(); it != LZ.rend() && has(fast, *it); ++it) run *= card[*it];
+      if (run < 16) a.tile = 1;
+    }
     if (a.kind == 2 && (op.forms & 256) && a.nS >= 16) a.tile = 1;
   }
   op.flops = 2.0 * (double)n_out * (double)a.nS;
@@ -691,6 +710,8 @@ static void fill_args(tn_plan_t *p, Op &op) {
   a.gbZ = tab(op.t_gbZ);
   a.gmX = tab(op.t_gmX);
   a.gmZ = tab(op.t_gmZ);
+  a.oX = tab(op.t_oX);
+  a.oY = tab(op.t_oY);
   const TensorBuf &X = p->T[op.X], &Z = p->T[op.Z];
   // instance stride bs and element stride es of an operand
   auto strides = [&](const TensorBuf &t, int64_t &bs, int32_t &es) {
@@ -870,8 +891,8 @@ static void autotune_ops(tn_plan_t *p, const std::vector<Op *> &ops) {
   hip_check(hipEventCreate(&e0), "event");
   hip_check(hipEventCreate(&e1), "event");
   // (form bit, kind, workgroup split of the summed range, tile variant)
-  static const int kForm[9][4] = {{1, 0, 1, 0},  {2, 1, 1, 0},  {4, 2, 1, 0},    {8, 3, 1, 0},  {16, 4, 1, 0},
-                                  {32, 4, 4, 0}, {64, 4, 1, 1}, {128, 4, 1, 2}, {256, 2, 1, 1}};
+  static const int kForm[10][4] = {{1, 0, 1, 0},  {2, 1, 1, 0},  {4, 2, 1, 0},    {8, 3, 1, 0},   {16, 4, 1, 0},
+                                   {32, 4, 4, 0}, {64, 4, 1, 1}, {128, 4, 1, 2}, {256, 2, 1, 1}, {512, 0, 1, 1}};
   for (Op *op : ops) {
     if (op->split || op->seg >= 0) continue;
     std::vector<std::array<int, 3>> cands;

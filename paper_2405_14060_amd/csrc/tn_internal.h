@@ -137,6 +137,11 @@ struct ContractArgs {
   int32_t ksplit = 1;       // 4: the waves of a workgroup split the summed range of one tile
   int32_t tile = 0;         // tile of a wave: 0 = 4 x 4, 1 = 8 x 8, 2 = 16 x 1 (rows x columns)
   int32_t nslab = 1;        // groups of 64 instances
+  // generic form in output order (kind 0, tile 1): outputs enumerated in
+  // Z's memory order (lane o writes Z[o]); offsets of X and Y for every
+  // output through tables over Z's labels (stride 0 for labels they lack)
+  Tab2 oX, oY;
+  uint32_t nOl = 1;         // entries of the low tables
 };
 static constexpr int kGemmTile = 64;  // output tile edge of the dense form
 static constexpr int kInterTile = 4;  // output tile edge (rows x columns) of the interleaved form

@@ -153,24 +153,38 @@ __device__ __forceinline__ void map_body(const ContractArgs &a, const int b, con
   const uint32_t nSh = a.nS / nSl;
   const bool colf = a.col_fastest != 0;
   const Tab2 rX = a.rX, rY = a.rY, rZ = a.rZ, cY = a.cY, cZ = a.cZ, sXt = a.sX, sYt = a.sY;
+  // output order (tile 1): output o is Z[o]; X and Y offsets from tables
+  // over Z's labels
+  const bool oord = a.tile == 1;
+  const Tab2 oX = a.oX, oY = a.oY;
+  const uint32_t nOl = a.nOl;
+  const int osh = (nOl & (nOl - 1)) == 0 ? __builtin_ctz(nOl) : -1;
   float lmax = 0.f;
   for (uint32_t o = blk * kBlock + threadIdx.x; o < n_out; o += nblk * kBlock) {
-    uint32_t r, c;
-    if (colf) {
-      r = o / nC;
-      c = o - r * nC;
+    int32_t xo, zo, yo;
+    if (oord) {
+      const uint32_t oh = osh >= 0 ? o >> osh : o / nOl, ol = o - oh * nOl;
+      xo = oX.hi[oh] + oX.lo[ol];
+      yo = HASY ? oY.hi[oh] + oY.lo[ol] : 0;
+      zo = (int32_t)o;
     } else {
-      c = o / nR;
-      r = o - c * nR;
-    }
-    const uint32_t rh = r / nRl, rl = r - rh * nRl;
-    const int32_t xo = rX.hi[rh] + rX.lo[rl];
-    int32_t zo = rZ.hi[rh] + rZ.lo[rl];
-    int32_t yo = HASY ? rY.hi[rh] + rY.lo[rl] : 0;
-    if (nC > 1) {
-      const uint32_t ch = c / nCl, cl = c - ch * nCl;
-      zo += cZ.hi[ch] + cZ.lo[cl];
-      if (HASY) yo += cY.hi[ch] + cY.lo[cl];
+      uint32_t r, c;
+      if (colf) {
+        r = o / nC;
+        c = o - r * nC;
+      } else {
+        c = o / nR;
+        r = o - c * nR;
+      }
+      const uint32_t rh = r / nRl, rl = r - rh * nRl;
+      xo = rX.hi[rh] + rX.lo[rl];
+      zo = rZ.hi[rh] + rZ.lo[rl];
+      yo = HASY ? rY.hi[rh] + rY.lo[rl] : 0;
+      if (nC > 1) {
+        const uint32_t ch = c / nCl, cl = c - ch * nCl;
+        zo += cZ.hi[ch] + cZ.lo[cl];
+        if (HASY) yo += cY.hi[ch] + cY.lo[cl];
+      }
     }
     if (SEMI == SEMI_SUM) {
       float acc = 0.f;

@@ -42,6 +42,7 @@ struct Op {
   // table offsets into the host table store (-1 = unused)
   int64_t t_rX[2], t_rY[2], t_rZ[2], t_cY[2], t_cZ[2], t_sX[2], t_sY[2];
   int64_t t_gbX[2], t_gbY[2], t_gbZ[2], t_gmX[2], t_gmZ[2];  // dense form
+  int64_t t_oX[2], t_oY[2];           // generic form in output order
   double flops = 0, bytes = 0;        // algorithmic, per instance
   int64_t part_off = -1;              // partial-sum region of a split contraction
   ContractArgs *d_a = nullptr;        // device copy of `a`
@@ -51,7 +52,8 @@ struct Op {
   int seg = -1, seg_kind = 0;
   std::vector<int> ins, outs;
   int forms = 0;                      // eligible kernel forms: 1 generic, 2 row, 4 dense, 8 wave,
-                                      // 16 interleaved, 256 dense with 128 x 128 tiles
+                                      // 16 interleaved, 256 dense with 128 x 128 tiles, 512 generic
+                                      // in output order
 };
 
 // Host description of a fused segment (tables as offsets into the plan's

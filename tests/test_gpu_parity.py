@@ -570,6 +570,25 @@ def test_mmap_sliced(T):
     assert np.array_equal(x2, x) and val2 == val
 
 
+def test_mmap_generic_output_order(T):
+    """A 100-variable regular graph (10 query variables) whose sum phase
+    holds generic contractions over >= 2^17 outputs with labels of both
+    operands interleaved in the output (enumerated in the output's memory
+    order): MMAP unsliced and sliced against the oracle."""
+    net = W.random_regular3(100, seed=0, n_query=10)
+    q = net.meta["query"]
+    ov, ox, ogap = oracle.mmap(net, q)
+    P0 = T.Plan(T.Network(net), query=q)
+    val0, x0 = P0.mmap()
+    assert abs(val0 - ov) <= 1e-5 * max(1, abs(ov))
+    P = T.Plan(T.Network(net), query=q, max_log2_size=P0.info()["sc"] - 2)
+    assert P.info()["n_sliced"] > 0
+    val, x = P.mmap()
+    assert abs(val - ov) <= 1e-5 * max(1, abs(ov))
+    if ogap > 1e-4:
+        assert np.array_equal(x, ox) and np.array_equal(x0, ox)
+
+
 def test_regular3_220_mmap_full_size(T):
     """The MMAP workload at full size (220 binary variables on a 3-regular
     graph, 25 query variables, sum phase sliced to intermediates <= 2^28,
