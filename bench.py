@@ -44,10 +44,10 @@ KIND_NAMES = {0: "contract_map_sum", 1: "contract_map_max", 2: "contract_split_s
 # the kernel source they were taken from (sha256 prefix of tn_kernels.hip):
 # {(kernel, workload): {"src": sha, "bytes": B}}
 MEASURED_TRAFFIC = {
-    ("seg_carrier_bwd", "grid20x20"): {"src": "2af4bc1eb8f1a07b", "bytes": 13260159},
-    ("contract_interleaved_sum", "bn500x512"): {"src": "2af4bc1eb8f1a07b", "bytes": 69851416},
-    ("contract_map_sum", "regular3_220"): {"src": "2af4bc1eb8f1a07b", "bytes": 416771015},
-    ("contract_mfma_sum", "regular3_220"): {"src": "2af4bc1eb8f1a07b", "bytes": 1144788273},
+    ("seg_carrier_bwd", "grid20x20"): {"src": "8404cfeadbe4827d", "bytes": 13264092},
+    ("contract_interleaved_sum", "bn500x512"): {"src": "8404cfeadbe4827d", "bytes": 69861026},
+    ("contract_map_sum", "regular3_220"): {"src": "8404cfeadbe4827d", "bytes": 416936097},
+    ("contract_mfma_sum", "regular3_220"): {"src": "8404cfeadbe4827d", "bytes": 1139594223},
 }
 
 
