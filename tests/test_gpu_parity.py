@@ -166,7 +166,8 @@ def test_bn500x512_full_size_sampled(T):
     c = W.config(3, 0)
     bn, ev = c["net"], c["evidence"]
     B = ev.shape[0]
-    P = T.Plan(T.Network(bn), evidence_mode=T.EVIDENCE_INDICATOR, max_batch=B, semirings=T.SUM_PRODUCT)
+    P = T.Plan(T.Network(bn), evidence_mode=T.EVIDENCE_INDICATOR, max_batch=B, semirings=T.SUM_PRODUCT,
+               autotune=True)
     assert P.info()["n_interleaved"] > 0
     lz, m = P.marginals(ev, batch=B)
     assert np.all(np.isfinite(lz))
@@ -366,7 +367,7 @@ def test_autotuned_dense_and_mmap_against_oracle(T):
 def test_grid20x20_full_size_against_oracle(T):
     ref = json.load(open(os.path.join(GOLDEN, "oracle_grid20x20_seed0.json")))
     net = W.grid_mrf(20, 20, 0)
-    P = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT)
+    P = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, autotune=True)  # as the benchmark plans it
     info = P.info()
     assert info["sc"] <= 22
     lz, m = P.marginals()
@@ -589,10 +590,12 @@ def test_mmap_generic_output_order(T):
         assert np.array_equal(x, ox) and np.array_equal(x0, ox)
 
 
-def test_regular3_220_mmap_full_size(T):
+@pytest.mark.parametrize("autotune", [True, False])
+def test_regular3_220_mmap_full_size(T, autotune):
     """The MMAP workload at full size (220 binary variables on a 3-regular
     graph, 25 query variables, sum phase sliced to intermediates <= 2^28,
-    2048 slices), in the configuration the benchmark times.  The oracle cannot
+    2048 slices), planned as the benchmark plans it (autotuned forms, 16
+    planner restarts) and with the rules' forms.  The oracle cannot
     contract it, so the answer is certified by properties that hold at any
     size: the oracle's log p(Q = answer) (the network with the query observed
     is small) equals the reported value, and no single flip of a query
@@ -600,7 +603,7 @@ def test_regular3_220_mmap_full_size(T):
     query observed, whose first score is itself checked against the oracle)."""
     c = W.config(4, 0)
     net, q = c["net"], np.asarray(c["query"])
-    P = T.Plan(T.Network(net), query=q, max_log2_size=28, use_graph=False)
+    P = T.Plan(T.Network(net), query=q, max_log2_size=28, use_graph=False, autotune=autotune, restarts=16)
     assert P.info()["n_sliced"] >= 8 and P.info()["sc"] <= 28
     val, x = P.mmap()
     ev = -np.ones(net.n_vars, np.int32)
