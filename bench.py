@@ -48,6 +48,7 @@ MEASURED_TRAFFIC = {
     ("contract_interleaved_sum", "bn500x512"): {"src": "8404cfeadbe4827d", "bytes": 69861026},
     ("contract_map_sum", "regular3_220"): {"src": "8404cfeadbe4827d", "bytes": 416936097},
     ("contract_mfma_sum", "regular3_220"): {"src": "8404cfeadbe4827d", "bytes": 1139594223},
+    ("contract_map_max", "grid20_map"): {"src": "8404cfeadbe4827d", "bytes": 11998717},
 }
 
 
