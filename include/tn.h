@@ -94,8 +94,10 @@ typedef struct {
                                 (modes NONE / SLICED, no max-plus, no factor
                                 gradients) slice the tree and then support
                                 tn_logZ (Z summed over the slices) and
-                                tn_sample (each sample first draws its slice
-                                with probability Z_s / Z) */
+                                tn_sample (each sample ends in slice s with
+                                probability Z_s / Z: one pass over the slices
+                                in order, sample i taking slice s with
+                                probability Z_s / (Z_0 + ... + Z_s)) */
   int32_t dtype;             /* tn_dtype of the matrix-core operands of the
                                 sum-product contractions (dense form and fused
                                 segments): TN_F32, or TN_BF16 / TN_F16 (operands

@@ -402,23 +402,23 @@ def uniform53(sample: int, node: int, slot: int, seed: int) -> float:
 
 
 def sample_sliced(leaves: Leaves, pairs, sliced, n: int, seed: int) -> np.ndarray:
-    """Sampling when the tree is contracted slice by slice: sample i draws its
-    slice s with probability Z_s / Z (inverse CDF over the slices in order,
-    uniform from counter (i, SLICE_DRAW_NODE, 0)), then the per-node rule
-    inside that slice with counter i.  Sliced variables take the slice's
-    values."""
+    """Sampling when the tree is contracted slice by slice, in one pass over
+    the slices in order: sample i takes slice s with probability
+    Z_s / (Z_0 + ... + Z_s) (uniform from counter (i, SLICE_DRAW_NODE, s)),
+    and the last slice it takes is its slice -- with probability Z_s / Z, a
+    weighted reservoir of one.  Inside its slice it follows the per-node rule
+    with counter i.  Sliced variables take the slice's values."""
     lz = slice_log_z(leaves, pairs, sliced)
-    top = lz.max()
-    w = np.exp(lz - top)
-    tot = math.log(w.sum()) + top
-    cdf = np.cumsum(np.exp(lz - tot))
-    choice = np.empty(n, np.int64)
-    for i in range(n):
-        u = uniform53(i, SLICE_DRAW_NODE, 0, seed) * cdf[-1]
-        s = int(np.searchsorted(cdf, u, side="right"))
-        while s >= len(lz) or not lz[s] > -math.inf:
-            s = s - 1 if s > 0 else 0
-        choice[i] = s
+    choice = np.full(n, -1, np.int64)
+    prefix = -math.inf
+    for s in range(len(lz)):
+        if not lz[s] > -math.inf:
+            continue
+        prefix = float(np.logaddexp(prefix, lz[s]))
+        q = math.exp(lz[s] - prefix)
+        for i in range(n):
+            if uniform53(i, SLICE_DRAW_NODE, s, seed) < q:
+                choice[i] = s
     out = np.full((n, len(leaves.card)), -1, np.int32)
     for s, a in enumerate(slice_assignments(sliced, leaves.card)):
         ids = np.nonzero(choice == s)[0]

@@ -2107,12 +2107,6 @@ extern "C" tn_status tn_map(tn_plan_t *p, int32_t batch, const int32_t *evidence
   });
 }
 
-// Sampling from a sliced plan (reading of the paper's sampling step under
-// slicing): sample i first draws its slice s with probability Z_s / Z by
-// inverse CDF over the slices in order (uniform: Philox counter (i, slice
-// draw word, slot 0)); then, slice by slice, the forward pass of that slice is
-// recomputed and its samples follow the per-node rule with their own indices
-// as counters.
 static void ensure_sample_buffer(tn_plan_t *p, int64_t n) {
   if (n <= p->samp_cap) return;
   if (p->d_samp_out) {
@@ -2122,37 +2116,51 @@ static void ensure_sample_buffer(tn_plan_t *p, int64_t n) {
   p->d_samp_out = dalloc<int32_t>(p, (size_t)n * p->n_vars);
   p->samp_cap = n;
 }
+// Sampling a sliced plan (reading of the paper's sampling step under
+// slicing), in one pass over the slices in order: sample i
+// takes slice s with probability Z_s / (Z_0 + ... + Z_s) (uniform from
+// counter (i, kSliceDrawNode, s)); the last slice it takes is its slice,
+// with probability Z_s / Z (a weighted reservoir of one).  A sample is drawn
+// inside every slice it takes, right after that slice's forward pass; its
+// row ends as the draw of its last slice (the per-node counters follow the
+// sample id, so that draw equals drawing the slice first).
 static void sample_sliced(tn_plan_t *p, const int32_t *evidence, int64_t n, uint64_t seed, int32_t *samples) {
-  const std::vector<double> lz = slice_log_z(p, evidence, true);
-  const double total = log_sum_exp(lz);
-  if (!(total > -INFINITY)) throw TnError(TN_E_ZERO_EVIDENCE, "p(e) = 0");
-  if (n == 0) return;
-  std::vector<double> cdf(lz.size());
-  double acc = 0;
-  for (size_t s = 0; s < lz.size(); ++s) cdf[s] = acc += std::exp(lz[s] - total);
-  std::vector<std::vector<int64_t>> ids(lz.size());
-  for (int64_t i = 0; i < n; ++i) {
-    const double u = sample_uniform(i, kSliceDrawNode, 0, seed) * acc;
-    size_t s = std::upper_bound(cdf.begin(), cdf.end(), u) - cdf.begin();
-    while (s >= lz.size() || !(lz[s] > -INFINITY)) s = s > 0 ? s - 1 : 0;  // rounding at the top end
-    ids[s].push_back(i);
+  if (n == 0) {
+    if (!(log_sum_exp(slice_log_z(p, evidence, false)) > -INFINITY))
+      throw TnError(TN_E_ZERO_EVIDENCE, "p(e) = 0");
+    return;
   }
   ensure_sample_buffer(p, n);
   int64_t *d_ids = dalloc<int64_t>(p, (size_t)n);
-  for (size_t s = 0; s < lz.size(); ++s) {
-    if (ids[s].empty()) continue;
-    const std::vector<int32_t> row = slice_row(p, evidence, (int64_t)s);
+  const int64_t ns = n_slices_of(p);
+  double prefix = -INFINITY;
+  std::vector<int64_t> ids;
+  ids.reserve((size_t)n);
+  for (int64_t s = 0; s < ns; ++s) {
+    const std::vector<int32_t> row = slice_row(p, evidence, s);
     hip_check(hipMemcpyAsync(p->d_evidence, row.data(), row.size() * 4, hipMemcpyHostToDevice, p->stream), "slice");
-    hip_check(hipMemcpyAsync(d_ids, ids[s].data(), ids[s].size() * 8, hipMemcpyHostToDevice, p->stream), "ids");
     forward_sum(p, false, false);
+    double lz = -INFINITY;
+    hip_check(hipMemcpyAsync(&lz, p->d_out, sizeof(double), hipMemcpyDeviceToHost, p->stream), "D2H");
+    hip_check(hipStreamSynchronize(p->stream), "slice");
+    if (!(lz > -INFINITY)) continue;
+    const double m = std::max(prefix, lz);
+    prefix = m + std::log(std::exp(prefix - m) + std::exp(lz - m));
+    const double q = std::exp(lz - prefix);
+    ids.clear();
+    for (int64_t i = 0; i < n; ++i)
+      if (sample_uniform((uint64_t)i, kSliceDrawNode, (uint32_t)s, seed) < q) ids.push_back(i);
+    if (ids.empty()) continue;
+    hip_check(hipMemcpyAsync(d_ids, ids.data(), ids.size() * 8, hipMemcpyHostToDevice, p->stream), "ids");
     run_sched(p, p->samp_ops, p->sched_samp);
-    launch_sample(p->arena, p->d_samp, (int)p->samp.size(), p->d_samp_meta, p->n_vars, (int64_t)ids[s].size(), seed,
+    launch_sample(p->arena, p->d_samp, (int)p->samp.size(), p->d_samp_meta, p->n_vars, (int64_t)ids.size(), seed,
                   p->d_evidence, d_ids, p->d_samp_out, p->stream);
     hip_check(hipGetLastError(), "sample launch");
     hip_check(hipStreamSynchronize(p->stream), "sample");
   }
   hip_check(hipFree(d_ids), "hipFree");
   p->allocs.erase(std::find(p->allocs.begin(), p->allocs.end(), (void *)d_ids));
+  if (!(prefix > -INFINITY)) throw TnError(TN_E_ZERO_EVIDENCE, "p(e) = 0");
   hip_check(hipMemcpyAsync(samples, p->d_samp_out, (size_t)n * p->n_vars * 4, hipMemcpyDeviceToHost, p->stream), "D2H");
   hip_check(hipStreamSynchronize(p->stream), "sample");
 }

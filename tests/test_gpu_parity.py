@@ -633,8 +633,9 @@ def test_sampling_same_rng_as_oracle(T):
 
 def test_sliced_log_z_and_sampling(T):
     """A sum-product plan sliced below its largest intermediate: log Z is the
-    sum over the slices, and sampling first draws each sample's slice with
-    probability Z_s / Z; same Philox stream as the oracle's sliced sampler."""
+    sum over the slices, and sampling leaves each sample in slice s with
+    probability Z_s / Z (one pass, weighted reservoir); same Philox stream as
+    the oracle's sliced sampler."""
     net = W.grid_mrf(4, 5, 11)
     lv = oracle.build_leaves(net)
     pairs = oracle.default_tree(lv)

@@ -364,8 +364,9 @@ def test_sampler_counters_follow_ids():
 
 
 def test_sliced_sampler_marginals_within_four_sigma():
-    """Drawing the slice with probability Z_s / Z, then sampling inside it,
-    samples the joint distribution: marginals against brute force."""
+    """Each sample ending in slice s with probability Z_s / Z (one pass
+    over the slices, weighted reservoir), then sampled inside it, samples the
+    joint distribution: marginals against brute force."""
     net = W.grid_mrf(3, 4, 9)
     lv = oracle.build_leaves(net)
     pairs = oracle.default_tree(lv)
