@@ -257,7 +257,7 @@ def bench_regular3_mmap(args, T, W, np, sync):
     # the same network without the query: log Z and 10k samples from a
     # sum-product plan sliced to the same cap (each sample draws its slice
     # with probability Z_s / Z, then the per-node rule inside it)
-    splan = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, max_log2_size=28, restarts=16)
+    splan = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, max_log2_size=28, restarts=16, autotune=args.autotune)
     sinfo = splan.info()
     t0 = time.perf_counter()
     lz = splan.log_z()[0]
