@@ -401,14 +401,11 @@ def uniform53(sample: int, node: int, slot: int, seed: int) -> float:
     return ((o[0] >> 5) * 67108864.0 + (o[1] >> 6)) / 9007199254740992.0
 
 
-def sample_sliced(leaves: Leaves, pairs, sliced, n: int, seed: int) -> np.ndarray:
-    """Sampling when the tree is contracted slice by slice, in one pass over
-    the slices in order: sample i takes slice s with probability
-    Z_s / (Z_0 + ... + Z_s) (uniform from counter (i, SLICE_DRAW_NODE, s)),
-    and the last slice it takes is its slice -- with probability Z_s / Z, a
-    weighted reservoir of one.  Inside its slice it follows the per-node rule
-    with counter i.  Sliced variables take the slice's values."""
-    lz = slice_log_z(leaves, pairs, sliced)
+def reservoir_slices(lz, n: int, seed: int) -> np.ndarray:
+    """The slice of each of n samples from the slices' log weights lz, in one
+    pass over the slices in order: sample i takes slice s when the uniform
+    from counter (i, SLICE_DRAW_NODE, s) is below Z_s / (Z_0 + ... + Z_s);
+    the last slice taken is kept (-1 if every weight is zero)."""
     choice = np.full(n, -1, np.int64)
     prefix = -math.inf
     for s in range(len(lz)):
@@ -419,6 +416,18 @@ def sample_sliced(leaves: Leaves, pairs, sliced, n: int, seed: int) -> np.ndarra
         for i in range(n):
             if uniform53(i, SLICE_DRAW_NODE, s, seed) < q:
                 choice[i] = s
+    return choice
+
+
+def sample_sliced(leaves: Leaves, pairs, sliced, n: int, seed: int) -> np.ndarray:
+    """Sampling when the tree is contracted slice by slice, in one pass over
+    the slices in order: sample i takes slice s with probability
+    Z_s / (Z_0 + ... + Z_s) (uniform from counter (i, SLICE_DRAW_NODE, s)),
+    and the last slice it takes is its slice -- with probability Z_s / Z, a
+    weighted reservoir of one.  Inside its slice it follows the per-node rule
+    with counter i.  Sliced variables take the slice's values."""
+    lz = slice_log_z(leaves, pairs, sliced)
+    choice = reservoir_slices(lz, n, seed)
     out = np.full((n, len(leaves.card)), -1, np.int32)
     for s, a in enumerate(slice_assignments(sliced, leaves.card)):
         ids = np.nonzero(choice == s)[0]

@@ -363,6 +363,21 @@ def test_sampler_counters_follow_ids():
     assert np.array_equal(oracle.sample_tree(lv, pairs, 3, seed=8, ids=ids), full[ids])
 
 
+def test_reservoir_slice_frequencies():
+    """One pass over the slices keeping slice s with probability
+    Z_s / (Z_0 + ... + Z_s) leaves a sample in slice s with probability
+    Z_s / Z (weights spanning orders of magnitude, a zero-weight slice)."""
+    lz = np.array([math.log(3.0), -math.inf, math.log(0.5), math.log(10.0), math.log(1e-3), 0.0])
+    n = 40000
+    c = oracle.reservoir_slices(lz, n, seed=5)
+    assert np.all(c >= 0) and not np.any(c == 1)
+    p = np.exp(lz - np.logaddexp.reduce(lz[np.isfinite(lz)]))
+    for s in range(len(lz)):
+        emp = np.mean(c == s)
+        sig = math.sqrt(p[s] * (1 - p[s]) / n)
+        assert abs(emp - p[s]) <= 4.5 * sig + 1e-12, s
+
+
 def test_sliced_sampler_marginals_within_four_sigma():
     """Each sample ending in slice s with probability Z_s / Z (one pass
     over the slices, weighted reservoir), then sampled inside it, samples the
