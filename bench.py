@@ -44,11 +44,11 @@ KIND_NAMES = {0: "contract_map_sum", 1: "contract_map_max", 2: "contract_split_s
 # the kernel source they were taken from (sha256 prefix of tn_kernels.hip):
 # {(kernel, workload): {"src": sha, "bytes": B}}
 MEASURED_TRAFFIC = {
-    ("seg_carrier_bwd", "grid20x20"): {"src": "8404cfeadbe4827d", "bytes": 13264092},
-    ("contract_interleaved_sum", "bn500x512"): {"src": "8404cfeadbe4827d", "bytes": 69861026},
-    ("contract_map_sum", "regular3_220"): {"src": "8404cfeadbe4827d", "bytes": 416936097},
-    ("contract_mfma_sum", "regular3_220"): {"src": "8404cfeadbe4827d", "bytes": 1139594223},
-    ("contract_map_max", "grid20_map"): {"src": "8404cfeadbe4827d", "bytes": 11998717},
+    ("seg_carrier_bwd", "grid20x20"): {"src": "96807fd6122a01cf", "bytes": 13263135},
+    ("contract_interleaved_sum", "bn500x512"): {"src": "96807fd6122a01cf", "bytes": 69867628},
+    ("contract_map_sum", "regular3_220"): {"src": "96807fd6122a01cf", "bytes": 417957446},
+    ("contract_mfma_sum", "regular3_220"): {"src": "96807fd6122a01cf", "bytes": 1144862874},
+    ("contract_map_max", "grid20_map"): {"src": "96807fd6122a01cf", "bytes": 12002718},
 }
 
 

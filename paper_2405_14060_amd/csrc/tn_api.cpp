@@ -1861,8 +1861,8 @@ void run_sched(tn_plan_t *p, const std::vector<Op> &ops, const Schedule &sc) {
     if (L.seg) {
       const Op &op = ops[L.ops[0]];
       switch (L.seg_kind) {
-        case 1: launch_seg_fwd(p->seg_fwd_h[op.seg], p->d_seg_fwd + op.seg, p->stream); break;
-        case 2: launch_seg_bwd(p->seg_bwd_h[op.seg], p->d_seg_bwd + op.seg, p->stream); break;
+        case 1: launch_seg_fwd(p->seg_fwd_h[op.seg], p->stream); break;
+        case 2: launch_seg_bwd(p->seg_bwd_h[op.seg], p->stream); break;
         case 3: launch_seg_mat(p->d_seg_fwd, L.d_ids, (int)L.ops.size(), L.lds, p->stream); break;
         default: launch_seg_fin(p->d_seg_bwd, L.d_ids, (int)L.ops.size(), L.lds, p->stream); break;
       }

@@ -222,8 +222,9 @@ struct SegArgs {
   int32_t mat_lds = 0, fin_lds = 0;  // floats of LDS of the sweep kernels
   int32_t prec = 0;              // matrix-core operands: 0 FP32, 1 BF16, 2 FP16 (FP32 accumulation)
 };
-void launch_seg_fwd(const SegArgs &a, const SegArgs *d_a, void *stream);
-void launch_seg_bwd(const SegArgs &a, const SegArgs *d_a, void *stream);
+// carrier kernels: the arguments are passed by value
+void launch_seg_fwd(const SegArgs &a, void *stream);
+void launch_seg_bwd(const SegArgs &a, void *stream);
 // one workgroup per listed segment; lds_floats = the largest mat_lds / fin_lds of them
 void launch_seg_mat(const SegArgs *d_base, const int32_t *d_ids, int n, int lds_floats, void *stream);
 void launch_seg_fin(const SegArgs *d_base, const int32_t *d_ids, int n, int lds_floats, void *stream);

@@ -1715,6 +1715,7 @@ struct SegShared {
   int32_t offX[kSegOB], offZ[kSegOB], locX[kSegMaxLocal], locZ[kSegMaxLocal];
   float m[kSegMaxLocal * (kSegMaxLocal + 1)];
   int32_t kx, kg;
+  int32_t exX, exG, exM;  // workgroup 0: the operands' exponents (for the output's exponent)
 };
 
 __device__ __forceinline__ void seg_prologue(const SegArgs &a, uint32_t o0, bool want_g, SegShared &sh) {
@@ -1750,6 +1751,10 @@ __device__ __forceinline__ void seg_prologue(const SegArgs &a, uint32_t o0, bool
     const uint32_t v = ((gu32 *)a.mx)[l * a.mx_stride + slot];
     const int k = max_exponent(__float_as_uint(wave_max(__uint_as_float(v))));
     if (l == 0) (wv == 5 ? sh.kx : sh.kg) = k;
+  } else if (wv == 7 && blockIdx.x == 0 && l == 0) {  // read here, not after the stores
+    sh.exX = a.ex[a.slotX];
+    sh.exM = a.ex[a.slotM];
+    if (want_g) sh.exG = a.ex[a.slotG];
   }
 }
 
@@ -1862,10 +1867,12 @@ __device__ __forceinline__ void seg_put(const f32x4 &d, int n, float *tile) {
 }
 
 // Forward: C_L[:, o] = M C_0[:, o] for the workgroup's kSegOB outer
-// assignments (one 32-wide column block per wave).
+// assignments (one 32-wide column block per wave).  The arguments are passed
+// by value: the kernel's first reads then come from the argument block
+// itself, one dependent round trip fewer than through a pointer to them
+// (measured on the 20 x 20 grid: 7.4 -> 6.6 us forward, 9.6 -> 9.1 us reverse).
 template <int PREC>
-__global__ __launch_bounds__(kSegThreads) void k_seg_fwd(const SegArgs *__restrict__ ap) {
-  const SegArgs &a = *ap;
+__global__ __launch_bounds__(kSegThreads) void k_seg_fwd(const SegArgs a) {
   __shared__ float tile[kSegMaxLocal * kSegRow];
   __shared__ SegShared sh;
   const uint32_t o0 = blockIdx.x * kSegOB;
@@ -1881,15 +1888,14 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_fwd(const SegArgs *__restri
   __syncthreads();
   const float lmax = seg_store(a.arena + a.Z, sh.offZ, sh.locZ, n_out, a.out_outer_fast, tile);
   block_record_max<kSegThreads, false>(lmax, a.mx + (blockIdx.x % kMaxSub) * a.mx_stride + a.slotZ);
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.ex[a.slotZ] = a.ex[a.slotX] + kx + a.ex[a.slotM];
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.ex[a.slotZ] = sh.exX + kx + sh.exM;
 }
 
 // Reverse: Cbar_0[:, o] = M^T Gbar[:, o], and the workgroup's partial of
 // S = sum_o Gbar[:, o] C_0[:, o]^T: wave w computes the 16 x 16 quadrant
 // w % 4 of S over the outer quarter w / 4; quarters are added in order.
 template <int PREC>
-__global__ __launch_bounds__(kSegThreads) void k_seg_bwd(const SegArgs *__restrict__ ap) {
-  const SegArgs &a = *ap;
+__global__ __launch_bounds__(kSegThreads) void k_seg_bwd(const SegArgs a) {
   __shared__ float tg[kSegMaxLocal * kSegRow];  // output adjoint; later the waves' S partials
   __shared__ float tx[kSegMaxLocal * kSegRow];  // input carrier; later its adjoint
   __shared__ SegShared sh;
@@ -1950,8 +1956,8 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_bwd(const SegArgs *__restri
   }
   block_record_max<kSegThreads, false>(lmax, a.mx + (blockIdx.x % kMaxSub) * a.mx_stride + a.slotZ);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    a.ex[a.slotZ] = a.ex[a.slotG] + kg + a.ex[a.slotM];
-    if (want_s) a.ex[a.slotSp] = (a.ex[a.slotG] + kg) + (a.ex[a.slotX] + kx);
+    a.ex[a.slotZ] = sh.exG + kg + sh.exM;
+    if (want_s) a.ex[a.slotSp] = (sh.exG + kg) + (sh.exX + kx);
   }
 }
 
@@ -2147,17 +2153,17 @@ __global__ __launch_bounds__(kSweepThreads) void k_seg_sred(const SegArgs *__res
   }
 }
 
-void launch_seg_fwd(const SegArgs &a, const SegArgs *d_a, void *stream) {
+void launch_seg_fwd(const SegArgs &a, void *stream) {
   hipStream_t s = (hipStream_t)stream;
-  if (a.prec == 1) k_seg_fwd<1><<<seg_blocks(a), kSegThreads, 0, s>>>(d_a);
-  else if (a.prec == 2) k_seg_fwd<2><<<seg_blocks(a), kSegThreads, 0, s>>>(d_a);
-  else k_seg_fwd<0><<<seg_blocks(a), kSegThreads, 0, s>>>(d_a);
+  if (a.prec == 1) k_seg_fwd<1><<<seg_blocks(a), kSegThreads, 0, s>>>(a);
+  else if (a.prec == 2) k_seg_fwd<2><<<seg_blocks(a), kSegThreads, 0, s>>>(a);
+  else k_seg_fwd<0><<<seg_blocks(a), kSegThreads, 0, s>>>(a);
 }
-void launch_seg_bwd(const SegArgs &a, const SegArgs *d_a, void *stream) {
+void launch_seg_bwd(const SegArgs &a, void *stream) {
   hipStream_t s = (hipStream_t)stream;
-  if (a.prec == 1) k_seg_bwd<1><<<seg_blocks(a), kSegThreads, 0, s>>>(d_a);
-  else if (a.prec == 2) k_seg_bwd<2><<<seg_blocks(a), kSegThreads, 0, s>>>(d_a);
-  else k_seg_bwd<0><<<seg_blocks(a), kSegThreads, 0, s>>>(d_a);
+  if (a.prec == 1) k_seg_bwd<1><<<seg_blocks(a), kSegThreads, 0, s>>>(a);
+  else if (a.prec == 2) k_seg_bwd<2><<<seg_blocks(a), kSegThreads, 0, s>>>(a);
+  else k_seg_bwd<0><<<seg_blocks(a), kSegThreads, 0, s>>>(a);
 }
 void launch_seg_mat(const SegArgs *d_base, const int32_t *d_ids, int n, int lds_floats, void *stream) {
   k_seg_mat<<<n, kSweepThreads, (size_t)lds_floats * sizeof(float), (hipStream_t)stream>>>(d_base, d_ids);
