@@ -44,11 +44,11 @@ KIND_NAMES = {0: "contract_map_sum", 1: "contract_map_max", 2: "contract_split_s
 # the kernel source they were taken from (sha256 prefix of tn_kernels.hip):
 # {(kernel, workload): {"src": sha, "bytes": B}}
 MEASURED_TRAFFIC = {
-    ("seg_carrier_bwd", "grid20x20"): {"src": "96807fd6122a01cf", "bytes": 13263135},
-    ("contract_interleaved_sum", "bn500x512"): {"src": "96807fd6122a01cf", "bytes": 69867628},
-    ("contract_map_sum", "regular3_220"): {"src": "96807fd6122a01cf", "bytes": 417957446},
-    ("contract_mfma_sum", "regular3_220"): {"src": "96807fd6122a01cf", "bytes": 1144862874},
-    ("contract_map_max", "grid20_map"): {"src": "96807fd6122a01cf", "bytes": 12002718},
+    ("seg_carrier_bwd", "grid20x20"): {"src": "53095fad60b1ce50", "bytes": 13251866},
+    ("contract_interleaved_sum", "bn500x512"): {"src": "53095fad60b1ce50", "bytes": 69857041},
+    ("contract_map_sum", "regular3_220"): {"src": "53095fad60b1ce50", "bytes": 417180225},
+    ("contract_mfma_sum", "regular3_220"): {"src": "53095fad60b1ce50", "bytes": 1144958922},
+    ("contract_map_max", "grid20_map"): {"src": "53095fad60b1ce50", "bytes": 12005372},
 }
 
 

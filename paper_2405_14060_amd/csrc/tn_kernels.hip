@@ -1985,14 +1985,57 @@ __device__ int seg_normalize(float *v, int n, float *red) {
   return k;
 }
 
-// The sweep kernels stage the segment's index lists and small operands in
-// LDS first (one round of global reads), so that every step below reads
-// LDS only.
-__device__ __forceinline__ void seg_stage_lists(const SegArgs &a, int32_t *li, float *yv) {
-  for (int t = threadIdx.x; t < a.list_len; t += kSweepThreads) li[t] = a.lists[t];
-  for (int k = 0; k < a.n_steps; ++k) {
-    const SegStep &st = a.steps[k];
-    for (int t = threadIdx.x; t < st.ny; t += kSweepThreads) yv[k * 64 + t] = a.arena[st.y + t];
+// The sweep kernels stage the segment's step descriptors, the exponents of
+// its small operands, its index lists and the small operands in LDS first,
+// so that every step below reads LDS only.  Each thread issues a batch of
+// loads before it stores any of them: a load followed at once by its LDS
+// store costs one memory round trip per loop pass.
+struct SegStepsLds {
+  SegStep st[kSegMaxSteps];
+  int32_t ey[kSegMaxSteps];  // exponent of each step's small operand
+};
+static constexpr int kStageBatch = 8;
+static_assert(kSegMaxSteps * 64 == 4 * kSweepThreads, "four (step, entry) pairs per thread");
+
+// descriptors and exponents (one thread per step), then the lists; the
+// caller synchronises before seg_stage_operands
+__device__ __forceinline__ void seg_stage_lists(const SegArgs &a, SegStepsLds &ss, int32_t *li) {
+  if ((int)threadIdx.x < a.n_steps) {  // word by word (a struct copy goes through private memory)
+    const int32_t *src = (const int32_t *)(a.steps + threadIdx.x);
+    int32_t *dst = (int32_t *)&ss.st[threadIdx.x];
+    int32_t w[sizeof(SegStep) / 4];
+#pragma unroll
+    for (int j = 0; j < (int)(sizeof(SegStep) / 4); ++j) w[j] = src[j];
+    ss.ey[threadIdx.x] = a.ex[a.steps[threadIdx.x].yslot];
+#pragma unroll
+    for (int j = 0; j < (int)(sizeof(SegStep) / 4); ++j) dst[j] = w[j];
+  }
+  for (int t0 = 0; t0 < a.list_len; t0 += kStageBatch * kSweepThreads) {
+    int32_t v[kStageBatch];
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u) {
+      const int t = t0 + u * kSweepThreads + (int)threadIdx.x;
+      v[u] = t < a.list_len ? a.lists[t] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kStageBatch; ++u) {
+      const int t = t0 + u * kSweepThreads + (int)threadIdx.x;
+      if (t < a.list_len) li[t] = v[u];
+    }
+  }
+}
+// small operands, 64 entries per step (needs the staged descriptors)
+__device__ __forceinline__ void seg_stage_operands(const SegArgs &a, const SegStepsLds &ss, float *yv) {
+  float v[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int p = (int)threadIdx.x + u * kSweepThreads, k = p >> 6, i = p & 63;
+    v[u] = (k < a.n_steps && i < ss.st[k].ny) ? a.arena[ss.st[k].y + i] : 0.f;
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int p = (int)threadIdx.x + u * kSweepThreads, k = p >> 6, i = p & 63;
+    if (k < a.n_steps && i < ss.st[k].ny) yv[k * 64 + i] = v[u];
   }
 }
 
@@ -2030,18 +2073,22 @@ __global__ __launch_bounds__(kSweepThreads) void k_seg_mat(const SegArgs *__rest
   const SegArgs &a = base[ids[blockIdx.x]];
   extern __shared__ float lds[];
   __shared__ float red[4];
+  __shared__ __align__(16) unsigned char ss_mem[sizeof(SegStepsLds)];  // SegStep has initialisers
+  SegStepsLds &ss = *reinterpret_cast<SegStepsLds *>(ss_mem);
   const int nc = a.n_in0;
   float *A = lds, *B = lds + 1024, *yv = lds + 2048;
   int32_t *li = (int32_t *)(yv + 64 * a.n_steps);
-  seg_stage_lists(a, li, yv);
+  seg_stage_lists(a, ss, li);
   for (int t = threadIdx.x; t < nc * nc; t += kSweepThreads) A[t] = (t / nc == t % nc) ? 1.f : 0.f;
+  __syncthreads();
+  seg_stage_operands(a, ss, yv);
   __syncthreads();
   int e = 0;
   for (int k = 0; k < a.n_steps; ++k) {
-    const SegStep &st = a.steps[k];
+    const SegStep &st = ss.st[k];
     seg_step_fwd(st, li, yv + 64 * k, A, B, nc);
     __syncthreads();
-    e += a.ex[st.yslot] + seg_normalize(B, st.n_out * nc, red);
+    e += ss.ey[k] + seg_normalize(B, st.n_out * nc, red);
     float *tmp = A;
     A = B;
     B = tmp;
@@ -2054,43 +2101,61 @@ __global__ __launch_bounds__(kSweepThreads) void k_seg_mat(const SegArgs *__rest
 // (P_0 = I) and G_k = (steps k..L-1)^T S (G_L = S), the adjoint of step k's
 // map is W_k = G_{k+1} P_k^T (eq. einback summed over the outer labels), and
 // the small operand's adjoint entry s sums W_k over the triples of s.
-// LDS: three 32 x 32 work areas, P_0 .. P_{L-1}, the small operands, the lists.
+// LDS: three 32 x 32 work areas, the lists, the small operands, P_0 .. P_{L-1}.
 __global__ __launch_bounds__(kSweepThreads) void k_seg_fin(const SegArgs *__restrict__ base,
                                                            const int32_t *__restrict__ ids) {
   const SegArgs &a = base[ids[blockIdx.x]];
   extern __shared__ float lds[];
   __shared__ float red[4];
   __shared__ int eP[kSegMaxSteps], poff[kSegMaxSteps + 1];
+  __shared__ __align__(16) unsigned char ss_mem[sizeof(SegStepsLds)];  // SegStep has initialisers
+  SegStepsLds &ss = *reinterpret_cast<SegStepsLds *>(ss_mem);
+  __shared__ int eS;
   const int nc = a.n_in0, L = a.n_steps, nS = a.n_outL * nc;
-  float *G0 = lds, *G1 = lds + 1024, *W = lds + 2048, *P = lds + 3072;
+  float *G0 = lds, *G1 = lds + 1024, *W = lds + 2048;
+  int32_t *li = (int32_t *)(lds + 3072);
+  float *yv = (float *)(li + a.list_len), *P = yv + 64 * L;
+  seg_stage_lists(a, ss, li);
+  // S (summed by k_seg_sred into the first partial) and its exponent
+  {
+    float v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = (int)threadIdx.x + u * kSweepThreads;
+      v[u] = t < nS ? a.arena[a.Sp + t] : 0.f;
+    }
+    if (threadIdx.x == 0) eS = a.ex[a.slotSp];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = (int)threadIdx.x + u * kSweepThreads;
+      if (t < nS) G0[t] = v[u];
+    }
+  }
+  static_assert(kSegMaxLocal * kSegMaxLocal == 4 * kSweepThreads, "four entries of S per thread");
+  for (int t = threadIdx.x; t < nc * nc; t += kSweepThreads) P[t] = (t / nc == t % nc) ? 1.f : 0.f;
+  __syncthreads();
   if (threadIdx.x == 0) {
     int off = 0;
     for (int k = 0; k < L; ++k) {
       poff[k] = off;
-      off += a.steps[k].n_in * nc;
+      off += ss.st[k].n_in * nc;
     }
     poff[L] = off;
     eP[0] = 0;
   }
-  __syncthreads();
-  float *yv = P + poff[L];
-  int32_t *li = (int32_t *)(yv + 64 * L);
-  seg_stage_lists(a, li, yv);
-  // S (summed by k_seg_sred into the first partial)
-  for (int t = threadIdx.x; t < nS; t += kSweepThreads) G0[t] = a.arena[a.Sp + t];
-  for (int t = threadIdx.x; t < nc * nc; t += kSweepThreads) P[t] = (t / nc == t % nc) ? 1.f : 0.f;
+  seg_stage_operands(a, ss, yv);
   __syncthreads();
   for (int k = 0; k + 1 < L; ++k) {
-    const SegStep &st = a.steps[k];
+    const SegStep &st = ss.st[k];
     float *nxt = P + poff[k + 1];
     seg_step_fwd(st, li, yv + 64 * k, P + poff[k], nxt, nc);
     __syncthreads();
     const int sh = seg_normalize(nxt, st.n_out * nc, red);
-    if (threadIdx.x == 0) eP[k + 1] = eP[k] + a.ex[st.yslot] + sh;
+    if (threadIdx.x == 0) eP[k + 1] = eP[k] + ss.ey[k] + sh;
   }
-  int eG = a.ex[a.slotSp] + seg_normalize(G0, nS, red);
+  int eG = eS + seg_normalize(G0, nS, red);
   for (int k = L - 1; k >= 0; --k) {
-    const SegStep &st = a.steps[k];
+    const SegStep &st = ss.st[k];
     if (st.ybar >= 0) {
       const float *Pk = P + poff[k];
       for (int t = threadIdx.x; t < st.n_out * st.n_in; t += kSweepThreads) {
@@ -2117,7 +2182,7 @@ __global__ __launch_bounds__(kSweepThreads) void k_seg_fin(const SegArgs *__rest
     if (k > 0) {
       seg_step_bwd(st, li, yv + 64 * k, G0, G1, nc);
       __syncthreads();
-      eG += a.ex[st.yslot] + seg_normalize(G1, st.n_in * nc, red);
+      eG += ss.ey[k] + seg_normalize(G1, st.n_in * nc, red);
       float *tmp = G0;
       G0 = G1;
       G1 = tmp;
