@@ -46,8 +46,8 @@ KIND_NAMES = {0: "contract_map_sum", 1: "contract_map_max", 2: "contract_split_s
 MEASURED_TRAFFIC = {
     ("seg_carrier_bwd", "grid20x20"): {"src": "53095fad60b1ce50", "bytes": 13251866},
     ("contract_interleaved_sum", "bn500x512"): {"src": "53095fad60b1ce50", "bytes": 69857041},
-    ("contract_map_sum", "regular3_220"): {"src": "53095fad60b1ce50", "bytes": 417180225},
-    ("contract_mfma_sum", "regular3_220"): {"src": "53095fad60b1ce50", "bytes": 1144958922},
+    ("contract_map_sum", "regular3_220_r16"): {"src": "53095fad60b1ce50", "bytes": 417180225},
+    ("contract_mfma_sum", "regular3_220_r16"): {"src": "53095fad60b1ce50", "bytes": 1144958922},
     ("contract_map_max", "grid20_map"): {"src": "53095fad60b1ce50", "bytes": 12005372},
 }
 
@@ -216,9 +216,13 @@ def bench_regular3_mmap(args, T, W, np, sync):
     end to end; one slice profiled launch by launch for the roofline."""
     c = W.config(4, 0)
     net, q = c["net"], c["query"]
+    tp = time.perf_counter()
     plan = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT | T.MAX_PLUS, query=q, max_log2_size=28,
-                  use_graph=False, autotune=args.autotune, restarts=16)
+                  use_graph=False, autotune=args.autotune, restarts=args.restarts)
+    plan_s = time.perf_counter() - tp
     info = plan.info()
+    print("regular3_mmap: planned in %.1f s (2^%.2f multiply-adds, %d slices)" % (plan_s, info["tc"], 2 ** info["n_sliced"]),
+          file=sys.stderr, flush=True)
     n_slices = 2 ** info["n_sliced"]
     if not args.slice_only:
         t0 = time.perf_counter()
@@ -227,14 +231,19 @@ def bench_regular3_mmap(args, T, W, np, sync):
         sec = time.perf_counter() - t0
     prof = plan.profile(3, reps=1)
     slice_s = sum(ms for _, _, _, ms in prof) / 1e3
-    roof, kernels, slice_flops = roofline(plan, 3, "regular3_220")
+    # measured HBM traffic belongs to one plan: the tree search's restarts are part of the key (with
+    # 1024 restarts the autotuner's form choices, and so the slice's launches, differ between processes:
+    # no figure is kept for that plan)
+    wl = "regular3_220_r%d" % args.restarts
+    roof, kernels, slice_flops = roofline(plan, 3, wl)
     # the matrix-core kernel of the slice against the FP32 matrix-core peak
-    roof_dense = roofline(plan, 3, "regular3_220", kernel="contract_mfma_sum")[0]
+    roof_dense = roofline(plan, 3, wl, kernel="contract_mfma_sum")[0]
     if args.slice_only:  # profiling aid: one slice, time of the query projected from it
         return dict(value=1.0 / (slice_s * n_slices), unit="MMAP solves/s (projected from one slice)",
                     ms_per_step=round(slice_s * n_slices * 1e3, 1), dtype="f32",
                     config=dict(workload="regular3 220 vars, MMAP with 25 query vars, intermediates <= 2^28 "
-                                "(sliced), one slice", seed=0, n_slices=n_slices, autotune=args.autotune),
+                                "(sliced), one slice", seed=0, n_slices=n_slices, autotune=args.autotune,
+                                restarts=args.restarts),
                     slice_ms=round(slice_s * 1e3, 3), roofline=roof, roofline_dense=roof_dense,
                     kernels_one_slice=kernels)
     # certificate at full size: log p(Q = x) by the oracle (the network with
@@ -249,7 +258,8 @@ def bench_regular3_mmap(args, T, W, np, sync):
                config=dict(workload="regular3 220 vars, MMAP with 25 query vars, intermediates <= 2^28 (sliced)",
                            seed=0, n_vars=220, n_query=len(q), n_sliced=info["n_sliced"], n_slices=n_slices,
                            tree_sc_log2=round(info["sc"], 3), tree_tc_log2=round(info["tc"], 3),
-                           device_gb=round(info["device_bytes"] / 1e9, 2), graph=False, autotune=args.autotune),
+                           device_gb=round(info["device_bytes"] / 1e9, 2), graph=False, autotune=args.autotune,
+                           restarts=args.restarts, plan_s=round(plan_s, 1)),
                log_value=val, slice_ms=round(slice_s * 1e3, 3), tflops=round(slice_flops / slice_s / 1e12, 3),
                roofline=roof, roofline_dense=roof_dense, kernels_one_slice=kernels,
                certificate=dict(oracle_log_p_of_answer=lp_oracle, abs_diff=abs(lp_oracle - val),
@@ -257,8 +267,13 @@ def bench_regular3_mmap(args, T, W, np, sync):
     # the same network without the query: log Z and 10k samples from a
     # sum-product plan sliced to the same cap (each sample draws its slice
     # with probability Z_s / Z, then the per-node rule inside it)
-    splan = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, max_log2_size=28, restarts=16, autotune=args.autotune)
+    tp = time.perf_counter()
+    splan = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, max_log2_size=28, restarts=args.sample_restarts,
+                   autotune=args.autotune)
+    splan_s = time.perf_counter() - tp
     sinfo = splan.info()
+    print("regular3_mmap: sampling plan in %.1f s (2^%.2f multiply-adds)" % (splan_s, sinfo["tc"]), file=sys.stderr,
+          flush=True)
     t0 = time.perf_counter()
     lz = splan.log_z()[0]
     t_lz = time.perf_counter() - t0
@@ -267,7 +282,9 @@ def bench_regular3_mmap(args, T, W, np, sync):
     t_s = time.perf_counter() - t0
     out["sampling"] = dict(n=10000, seconds=round(t_s, 2), samples_per_s=round(10000 / t_s, 1), log_z=lz,
                            log_z_seconds=round(t_lz, 2), n_sliced=sinfo["n_sliced"],
-                           tree_tc_log2=round(sinfo["tc"], 3), complete=bool(np.all(smp >= 0)))
+                           tree_tc_log2=round(sinfo["tc"], 3), restarts=args.sample_restarts,
+                           plan_s=round(splan_s, 1),
+                           complete=bool(np.all(smp >= 0)))
     if not args.no_cpu_baseline:
         qs = set(int(v) for v in q)
         summed = [v for v in range(net.n_vars) if v not in qs]
@@ -339,6 +356,12 @@ def main():
                          "contraction shape at plan time")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--restarts", type=int, default=1024,
+                    help="regular3_mmap: randomised restarts of the MMAP plan's tree search (plan time only; "
+                         "the query's sliced work: 2^47.1 multiply-adds at 16, 2^43.4 at 1024)")
+    ap.add_argument("--sample-restarts", type=int, default=256,
+                    help="regular3_mmap: restarts of the sampling (log Z) plan's tree search (2^39.8 "
+                         "multiply-adds in 512 slices at 16, 2^41.1 in 8 slices at 256)")
     ap.add_argument("--slice-only", action="store_true",
                     help="regular3_mmap: plan and profile one slice only (for profilers)")
     ap.add_argument("--copy-probe", action="store_true",
