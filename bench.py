@@ -44,11 +44,9 @@ KIND_NAMES = {0: "contract_map_sum", 1: "contract_map_max", 2: "contract_split_s
 # the kernel source they were taken from (sha256 prefix of tn_kernels.hip):
 # {(kernel, workload): {"src": sha, "bytes": B}}
 MEASURED_TRAFFIC = {
-    ("seg_carrier_bwd", "grid20x20"): {"src": "53095fad60b1ce50", "bytes": 13251866},
-    ("contract_interleaved_sum", "bn500x512"): {"src": "53095fad60b1ce50", "bytes": 69857041},
-    ("contract_map_sum", "regular3_220_r16"): {"src": "53095fad60b1ce50", "bytes": 417180225},
-    ("contract_mfma_sum", "regular3_220_r16"): {"src": "53095fad60b1ce50", "bytes": 1144958922},
-    ("contract_map_max", "grid20_map"): {"src": "53095fad60b1ce50", "bytes": 12005372},
+    ("seg_carrier_bwd", "grid20x20"): {"src": "dfffab7897d1877a", "bytes": 13261141},
+    ("contract_interleaved_sum", "bn500x512"): {"src": "dfffab7897d1877a", "bytes": 69851738},
+    ("contract_map_max", "grid20_map"): {"src": "dfffab7897d1877a", "bytes": 12012694},
 }
 
 

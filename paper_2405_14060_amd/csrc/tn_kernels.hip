@@ -1687,6 +1687,7 @@ void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, co
 
 static constexpr int kSegThreads = 1024;          // 16 waves: enough in flight per CU to cover latency
 static constexpr int kSweepThreads = 256;         // sweep kernels (one workgroup per segment)
+static constexpr int kFinThreads = 1024;          // the adjoint sweep: its per-step loops span up to 32 x 32 entries
 static constexpr int kSegOB = kSegOuterBlock;     // outer assignments per workgroup (32 per wave)
 static constexpr int kSegRow = kSegOB + 1;        // padded LDS tile row: conflict-free in both directions
 
@@ -1962,24 +1963,30 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_bwd(const SegArgs a) {
 }
 
 // --- sweeps over the steps (one workgroup per segment) ---------------------
+// (red: NT / 64 floats)
+template <int NT = kSweepThreads>
 __device__ __forceinline__ float seg_block_max(float v, float *red) {
   v = wave_max(v);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  return fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  float m = red[0];
+#pragma unroll
+  for (int w = 1; w < NT / 64; ++w) m = fmaxf(m, red[w]);
+  return m;
 }
 
 // Scale v[0, n) so that its maximum lies in [0.5, 1); returns the exponent
 // taken out (values are non-negative).
+template <int NT = kSweepThreads>
 __device__ int seg_normalize(float *v, int n, float *red) {
   float m = 0.f;
-  for (int t = threadIdx.x; t < n; t += kSweepThreads) m = fmaxf(m, v[t]);
-  m = seg_block_max(m, red);
+  for (int t = threadIdx.x; t < n; t += NT) m = fmaxf(m, v[t]);
+  m = seg_block_max<NT>(m, red);
   const int k = max_exponent(__float_as_uint(m));
   if (k != 0) {
     const float sc = ldexpf(1.f, -k);
-    for (int t = threadIdx.x; t < n; t += kSweepThreads) v[t] *= sc;
+    for (int t = threadIdx.x; t < n; t += NT) v[t] *= sc;
   }
   __syncthreads();
   return k;
@@ -1995,10 +2002,12 @@ struct SegStepsLds {
   int32_t ey[kSegMaxSteps];  // exponent of each step's small operand
 };
 static constexpr int kStageBatch = 8;
-static_assert(kSegMaxSteps * 64 == 4 * kSweepThreads, "four (step, entry) pairs per thread");
+static_assert(kSegMaxSteps * 64 % kSweepThreads == 0 && kSegMaxSteps * 64 % kFinThreads == 0,
+              "whole (step, entry) pairs per thread");
 
 // descriptors and exponents (one thread per step), then the lists; the
 // caller synchronises before seg_stage_operands
+template <int NT = kSweepThreads>
 __device__ __forceinline__ void seg_stage_lists(const SegArgs &a, SegStepsLds &ss, int32_t *li) {
   if ((int)threadIdx.x < a.n_steps) {  // word by word (a struct copy goes through private memory)
     const int32_t *src = (const int32_t *)(a.steps + threadIdx.x);
@@ -2010,41 +2019,44 @@ __device__ __forceinline__ void seg_stage_lists(const SegArgs &a, SegStepsLds &s
 #pragma unroll
     for (int j = 0; j < (int)(sizeof(SegStep) / 4); ++j) dst[j] = w[j];
   }
-  for (int t0 = 0; t0 < a.list_len; t0 += kStageBatch * kSweepThreads) {
+  for (int t0 = 0; t0 < a.list_len; t0 += kStageBatch * NT) {
     int32_t v[kStageBatch];
 #pragma unroll
     for (int u = 0; u < kStageBatch; ++u) {
-      const int t = t0 + u * kSweepThreads + (int)threadIdx.x;
+      const int t = t0 + u * NT + (int)threadIdx.x;
       v[u] = t < a.list_len ? a.lists[t] : 0;
     }
 #pragma unroll
     for (int u = 0; u < kStageBatch; ++u) {
-      const int t = t0 + u * kSweepThreads + (int)threadIdx.x;
+      const int t = t0 + u * NT + (int)threadIdx.x;
       if (t < a.list_len) li[t] = v[u];
     }
   }
 }
 // small operands, 64 entries per step (needs the staged descriptors)
+template <int NT = kSweepThreads>
 __device__ __forceinline__ void seg_stage_operands(const SegArgs &a, const SegStepsLds &ss, float *yv) {
-  float v[4];
+  constexpr int kPer = kSegMaxSteps * 64 / NT;
+  float v[kPer];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int p = (int)threadIdx.x + u * kSweepThreads, k = p >> 6, i = p & 63;
+  for (int u = 0; u < kPer; ++u) {
+    const int p = (int)threadIdx.x + u * NT, k = p >> 6, i = p & 63;
     v[u] = (k < a.n_steps && i < ss.st[k].ny) ? a.arena[ss.st[k].y + i] : 0.f;
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int p = (int)threadIdx.x + u * kSweepThreads, k = p >> 6, i = p & 63;
+  for (int u = 0; u < kPer; ++u) {
+    const int p = (int)threadIdx.x + u * NT, k = p >> 6, i = p & 63;
     if (k < a.n_steps && i < ss.st[k].ny) yv[k * 64 + i] = v[u];
   }
 }
 
 // out = (step's map) in, column by column: out[j][c] = sum over the triples
 // of output entry j of in[i][c] * y[s]; rows of nc columns.
+template <int NT = kSweepThreads>
 __device__ void seg_step_fwd(const SegStep &st, const int32_t *li, const float *y, const float *in, float *out,
                              int nc) {
   const int32_t *ptr = li + st.fo_ptr, *xi = li + st.fo_in, *xs = li + st.fo_s;
-  for (int t = threadIdx.x; t < st.n_out * nc; t += kSweepThreads) {
+  for (int t = threadIdx.x; t < st.n_out * nc; t += NT) {
     const int j = t / nc, c = t - j * nc;
     float acc = 0.f;
     for (int e = ptr[j]; e < ptr[j + 1]; ++e) acc = fmaf(in[xi[e] * nc + c], y[xs[e]], acc);
@@ -2054,10 +2066,11 @@ __device__ void seg_step_fwd(const SegStep &st, const int32_t *li, const float *
 
 // out = (step's map)^T in: out[i][c] = sum over the triples of input entry i
 // of in[j][c] * y[s].
+template <int NT = kSweepThreads>
 __device__ void seg_step_bwd(const SegStep &st, const int32_t *li, const float *y, const float *in, float *out,
                              int nc) {
   const int32_t *ptr = li + st.bi_ptr, *xo = li + st.bi_out, *xs = li + st.bi_s;
-  for (int t = threadIdx.x; t < st.n_in * nc; t += kSweepThreads) {
+  for (int t = threadIdx.x; t < st.n_in * nc; t += NT) {
     const int i = t / nc, c = t - i * nc;
     float acc = 0.f;
     for (int e = ptr[i]; e < ptr[i + 1]; ++e) acc = fmaf(in[xo[e] * nc + c], y[xs[e]], acc);
@@ -2102,11 +2115,11 @@ __global__ __launch_bounds__(kSweepThreads) void k_seg_mat(const SegArgs *__rest
 // map is W_k = G_{k+1} P_k^T (eq. einback summed over the outer labels), and
 // the small operand's adjoint entry s sums W_k over the triples of s.
 // LDS: three 32 x 32 work areas, the lists, the small operands, P_0 .. P_{L-1}.
-__global__ __launch_bounds__(kSweepThreads) void k_seg_fin(const SegArgs *__restrict__ base,
+__global__ __launch_bounds__(kFinThreads) void k_seg_fin(const SegArgs *__restrict__ base,
                                                            const int32_t *__restrict__ ids) {
   const SegArgs &a = base[ids[blockIdx.x]];
   extern __shared__ float lds[];
-  __shared__ float red[4];
+  __shared__ float red[kFinThreads / 64];
   __shared__ int eP[kSegMaxSteps], poff[kSegMaxSteps + 1];
   __shared__ __align__(16) unsigned char ss_mem[sizeof(SegStepsLds)];  // SegStep has initialisers
   SegStepsLds &ss = *reinterpret_cast<SegStepsLds *>(ss_mem);
@@ -2115,24 +2128,16 @@ __global__ __launch_bounds__(kSweepThreads) void k_seg_fin(const SegArgs *__rest
   float *G0 = lds, *G1 = lds + 1024, *W = lds + 2048;
   int32_t *li = (int32_t *)(lds + 3072);
   float *yv = (float *)(li + a.list_len), *P = yv + 64 * L;
-  seg_stage_lists(a, ss, li);
+  seg_stage_lists<kFinThreads>(a, ss, li);
   // S (summed by k_seg_sred into the first partial) and its exponent
   {
-    float v[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int t = (int)threadIdx.x + u * kSweepThreads;
-      v[u] = t < nS ? a.arena[a.Sp + t] : 0.f;
-    }
+    static_assert(kSegMaxLocal * kSegMaxLocal == kFinThreads, "one entry of S per thread");
+    const int t = (int)threadIdx.x;
+    const float v = t < nS ? a.arena[a.Sp + t] : 0.f;
     if (threadIdx.x == 0) eS = a.ex[a.slotSp];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int t = (int)threadIdx.x + u * kSweepThreads;
-      if (t < nS) G0[t] = v[u];
-    }
+    if (t < nS) G0[t] = v;
   }
-  static_assert(kSegMaxLocal * kSegMaxLocal == 4 * kSweepThreads, "four entries of S per thread");
-  for (int t = threadIdx.x; t < nc * nc; t += kSweepThreads) P[t] = (t / nc == t % nc) ? 1.f : 0.f;
+  for (int t = threadIdx.x; t < nc * nc; t += kFinThreads) P[t] = (t / nc == t % nc) ? 1.f : 0.f;
   __syncthreads();
   if (threadIdx.x == 0) {
     int off = 0;
@@ -2143,22 +2148,22 @@ __global__ __launch_bounds__(kSweepThreads) void k_seg_fin(const SegArgs *__rest
     poff[L] = off;
     eP[0] = 0;
   }
-  seg_stage_operands(a, ss, yv);
+  seg_stage_operands<kFinThreads>(a, ss, yv);
   __syncthreads();
   for (int k = 0; k + 1 < L; ++k) {
     const SegStep &st = ss.st[k];
     float *nxt = P + poff[k + 1];
-    seg_step_fwd(st, li, yv + 64 * k, P + poff[k], nxt, nc);
+    seg_step_fwd<kFinThreads>(st, li, yv + 64 * k, P + poff[k], nxt, nc);
     __syncthreads();
-    const int sh = seg_normalize(nxt, st.n_out * nc, red);
+    const int sh = seg_normalize<kFinThreads>(nxt, st.n_out * nc, red);
     if (threadIdx.x == 0) eP[k + 1] = eP[k] + ss.ey[k] + sh;
   }
-  int eG = eS + seg_normalize(G0, nS, red);
+  int eG = eS + seg_normalize<kFinThreads>(G0, nS, red);
   for (int k = L - 1; k >= 0; --k) {
     const SegStep &st = ss.st[k];
     if (st.ybar >= 0) {
       const float *Pk = P + poff[k];
-      for (int t = threadIdx.x; t < st.n_out * st.n_in; t += kSweepThreads) {
+      for (int t = threadIdx.x; t < st.n_out * st.n_in; t += kFinThreads) {
         const int j = t / st.n_in, i = t - j * st.n_in;
         float acc = 0.f;
         for (int c = 0; c < nc; ++c) acc = fmaf(G0[j * nc + c], Pk[i * nc + c], acc);
@@ -2167,22 +2172,22 @@ __global__ __launch_bounds__(kSweepThreads) void k_seg_fin(const SegArgs *__rest
       __syncthreads();
       const int32_t *ptr = li + st.bs_ptr, *xi = li + st.bs_in, *xo = li + st.bs_out;
       float m = 0.f;
-      for (int sidx = threadIdx.x; sidx < st.ny; sidx += kSweepThreads) {
+      for (int sidx = threadIdx.x; sidx < st.ny; sidx += kFinThreads) {
         float acc = 0.f;
         for (int e = ptr[sidx]; e < ptr[sidx + 1]; ++e) acc += W[xo[e] * st.n_in + xi[e]];
         a.arena[st.ybar + sidx] = acc;
         m = fmaxf(m, acc);
       }
-      m = seg_block_max(m, red);
+      m = seg_block_max<kFinThreads>(m, red);
       if (threadIdx.x == 0) {
         a.mx[st.ybar_slot] = __float_as_uint(m);
         a.ex[st.ybar_slot] = eG + eP[k];
       }
     }
     if (k > 0) {
-      seg_step_bwd(st, li, yv + 64 * k, G0, G1, nc);
+      seg_step_bwd<kFinThreads>(st, li, yv + 64 * k, G0, G1, nc);
       __syncthreads();
-      eG += ss.ey[k] + seg_normalize(G1, st.n_in * nc, red);
+      eG += ss.ey[k] + seg_normalize<kFinThreads>(G1, st.n_in * nc, red);
       float *tmp = G0;
       G0 = G1;
       G1 = tmp;
@@ -2235,7 +2240,7 @@ void launch_seg_mat(const SegArgs *d_base, const int32_t *d_ids, int n, int lds_
 }
 void launch_seg_fin(const SegArgs *d_base, const int32_t *d_ids, int n, int lds_floats, void *stream) {
   k_seg_sred<<<n * kSredChunks, kSweepThreads, 0, (hipStream_t)stream>>>(d_base, d_ids);
-  k_seg_fin<<<n, kSweepThreads, (size_t)lds_floats * sizeof(float), (hipStream_t)stream>>>(d_base, d_ids);
+  k_seg_fin<<<n, kFinThreads, (size_t)lds_floats * sizeof(float), (hipStream_t)stream>>>(d_base, d_ids);
 }
 
 // --------------------------------------------------------------------------
