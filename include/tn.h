@@ -237,7 +237,8 @@ tn_status tn_map(tn_plan_t *plan, int32_t batch, const int32_t *evidence, int32_
 
 /*
  * MMAP (eq. mmap) for the plan's query set: assign_q [n_query] in the
- * order of the sorted query ids, log_value = max_q log sum_m p(q, m, e).
+ * order of the sorted query ids, log_value = max_q log sum_m p(q, m, e)
+ * (optional: NULL skips it).  TN_E_ZERO_EVIDENCE if p(e) = 0.
  */
 tn_status tn_mmap(tn_plan_t *plan, const int32_t *evidence, int32_t *assign_q, double *log_value);
 
@@ -294,6 +295,25 @@ tn_status tn_profile(tn_plan_t *plan, int32_t task, int32_t batch, const int32_t
 tn_status tn_profile_kind(tn_plan_t *plan, int32_t task, int32_t kind, int32_t batch,
                           const int32_t *evidence, int32_t reps, tn_op_profile *avg,
                           int32_t *n_launches);
+
+/*
+ * Autotuner decisions.  A plan built with autotune = 1 times the eligible
+ * kernel forms of each distinct contraction shape once per process and GPU
+ * architecture; later plans with the same shape reuse the decision, so two
+ * plans of one model in one process run the same kernels and give
+ * bit-identical results (the forms sum in different orders).
+ *   tn_tune_save  writes every decision held by the process to a text file
+ *                 (one line each); *n_saved (optional) = their count.
+ *   tn_tune_load  reads such a file and adds its decisions (replacing held
+ *                 ones for the same shape); plans built afterwards use them
+ *                 instead of timing.  TN_E_INVALID if the file cannot be read
+ *                 or is malformed (then nothing is added).
+ *   tn_tune_clear forgets every decision.
+ * Thread-safe; no device work.
+ */
+tn_status tn_tune_save(const char *path, int64_t *n_saved);
+tn_status tn_tune_load(const char *path, int64_t *n_loaded);
+void tn_tune_clear(void);
 
 /* Synchronise the plan's stream; TN_E_DEVICE on error. */
 tn_status tn_sync(tn_plan_t *plan);

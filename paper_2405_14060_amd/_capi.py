@@ -32,7 +32,8 @@ PLANNER_BEST, PLANNER_GREEDY, PLANNER_MINFILL, PLANNER_NATURAL, PLANNER_MINDEG =
 
 EXPORTS = ["tn_plan_opts_default", "tn_load_network", "tn_free_network", "tn_plan", "tn_free_plan",
            "tn_plan_info_get", "tn_plan_tree", "tn_plan_sliced", "tn_plan_tree_host", "tn_logZ", "tn_marginals",
-           "tn_map", "tn_mmap", "tn_sample", "tn_logZ_dev", "tn_sync", "tn_profile", "tn_profile_kind", "tn_last_error"]
+           "tn_map", "tn_mmap", "tn_sample", "tn_logZ_dev", "tn_sync", "tn_profile", "tn_profile_kind", "tn_last_error",
+           "tn_tune_save", "tn_tune_load", "tn_tune_clear"]
 
 i32p = ctypes.POINTER(ctypes.c_int32)
 i64p = ctypes.POINTER(ctypes.c_int64)
@@ -122,7 +123,11 @@ def lib():
                              ctypes.POINTER(OpProfile), ctypes.c_int32, i32p]
     L.tn_profile_kind.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, i32p, ctypes.c_int32,
                                   ctypes.POINTER(OpProfile), i32p]
-    for name in ("tn_load_network", "tn_plan", "tn_plan_info_get", "tn_plan_tree", "tn_plan_sliced", "tn_plan_tree_host",
+    L.tn_tune_save.argtypes = [ctypes.c_char_p, i64p]
+    L.tn_tune_load.argtypes = [ctypes.c_char_p, i64p]
+    L.tn_tune_clear.argtypes = []
+    L.tn_tune_clear.restype = None
+    for name in ("tn_tune_save", "tn_tune_load", "tn_load_network", "tn_plan", "tn_plan_info_get", "tn_plan_tree", "tn_plan_sliced", "tn_plan_tree_host",
                  "tn_logZ", "tn_marginals", "tn_map", "tn_mmap", "tn_sample", "tn_logZ_dev", "tn_sync",
                  "tn_profile", "tn_profile_kind"):
         getattr(L, name).restype = ctypes.c_int
@@ -137,6 +142,25 @@ def _check(st):
 
 def _ptr(a, ct):
     return a.ctypes.data_as(ctypes.POINTER(ct)) if a is not None else None
+
+
+def tune_save(path) -> int:
+    """Write the process's autotuner decisions to a file; returns their count."""
+    n = ctypes.c_int64()
+    _check(lib().tn_tune_save(os.fsencode(path), ctypes.byref(n)))
+    return n.value
+
+
+def tune_load(path) -> int:
+    """Add autotuner decisions from a file written by tune_save; returns their count."""
+    n = ctypes.c_int64()
+    _check(lib().tn_tune_load(os.fsencode(path), ctypes.byref(n)))
+    return n.value
+
+
+def tune_clear() -> None:
+    """Forget every autotuner decision held by the process."""
+    lib().tn_tune_clear()
 
 
 class Network:

@@ -20,7 +20,10 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <cstdio>
 #include <functional>
+#include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 
@@ -882,11 +885,43 @@ tn_plan_impl::~tn_plan_impl() {
 // Autotuner: for every distinct contraction shape with more than one
 // eligible kernel form, time each form on the device (its own arguments,
 // three launches between two events after a warm-up) and keep the fastest.
-// Decisions are cached by shape, so a tree with many equal nodes costs a few
-// timings.  Operand contents do not matter for the timing (every access is
-// at table offsets).
+// The forms sum in different orders, so a decision changes the FP32
+// rounding of a result: decisions are kept process-wide, keyed by the GPU
+// architecture and the shape, and every later plan with that shape reuses
+// them (two plans of one model built in one process run the same launches
+// and give bit-identical results).  tn_tune_save / tn_tune_load carry the
+// decisions across processes.  Operand contents do not matter for the
+// timing (every access is at table offsets).
+namespace {
+using TuneKey = std::vector<int64_t>;
+struct TuneCache {
+  std::mutex mu;
+  std::map<std::pair<std::string, TuneKey>, std::array<int, 3>> dec;
+};
+TuneCache &tune_cache() {
+  static TuneCache c;
+  return c;
+}
+std::string device_arch() {
+  int dev = 0;
+  hip_check(hipGetDevice(&dev), "hipGetDevice");
+  hipDeviceProp_t prop;
+  hip_check(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+  std::string a = prop.gcnArchName;
+  return a.substr(0, a.find(':'));
+}
+}  // namespace
+
+static void set_form(tn_plan_t *p, Op *op, const std::array<int, 3> &f) {
+  op->a.kind = f[0];
+  op->a.ksplit = f[1];
+  op->a.tile = f[2];
+  op->a.prec = f[0] == 2 ? p->opts.dtype : 0;  // matrix-core operand precision of the dense form only
+}
+
 static void autotune_ops(tn_plan_t *p, const std::vector<Op *> &ops) {
-  std::map<std::vector<int64_t>, std::array<int, 3>> cache;
+  TuneCache &tc = tune_cache();
+  const std::string arch = device_arch();
   hipEvent_t e0, e1;
   hip_check(hipEventCreate(&e0), "event");
   hip_check(hipEventCreate(&e1), "event");
@@ -900,19 +935,24 @@ static void autotune_ops(tn_plan_t *p, const std::vector<Op *> &ops) {
       if (op->forms & f[0]) cands.push_back({f[1], f[2], f[3]});
     if (cands.size() < 2) continue;
     const ContractArgs &a = op->a;
-    const std::vector<int64_t> key = {op->semi, op->Y >= 0, op->nb, a.nR, a.nRl, a.nC, a.nCl, a.nS, a.nSl,
-                                      a.col_fastest, a.nB, a.nM, a.x_s_fast, a.y_n_fast, a.z_n_fast, op->forms,
-                                      a.batX, a.batY};
-    auto it = cache.find(key);
+    const TuneKey key = {op->semi, op->Y >= 0, op->nb, a.nR, a.nRl, a.nC, a.nCl, a.nS, a.nSl,
+                         a.col_fastest, a.nB, a.nM, a.x_s_fast, a.y_n_fast, a.z_n_fast, op->forms,
+                         a.batX, a.batY, p->opts.dtype};
     std::array<int, 3> best{-1, 1, 0};
-    if (it != cache.end()) {
-      best = it->second;
-    } else {
+    bool known = false;
+    {
+      std::lock_guard<std::mutex> lk(tc.mu);
+      auto it = tc.dec.find({arch, key});
+      if (it != tc.dec.end()) {
+        best = it->second;
+        known = std::find(cands.begin(), cands.end(), best) != cands.end();
+      }
+    }
+    if (!known) {
       float best_ms = 0.f;
+      best = {-1, 1, 0};
       for (auto cand : cands) {
-        op->a.kind = cand[0];
-        op->a.ksplit = cand[1];
-        op->a.tile = cand[2];
+        set_form(p, op, cand);
         hip_check(hipMemcpy(op->d_a, &op->a, sizeof(ContractArgs), hipMemcpyHostToDevice), "autotune");
         launch_contract(op->semi, op->Y >= 0, false, op->a, op->d_a, op->nb, p->stream);
         hip_check(hipEventRecord(e0, p->stream), "event");
@@ -927,15 +967,72 @@ static void autotune_ops(tn_plan_t *p, const std::vector<Op *> &ops) {
           best_ms = ms;
         }
       }
-      cache[key] = best;
+      std::lock_guard<std::mutex> lk(tc.mu);
+      auto ins = tc.dec.emplace(std::make_pair(arch, key), best);
+      best = ins.first->second;  // another thread's decision for the shape wins if it came first
     }
-    op->a.kind = best[0];
-    op->a.ksplit = best[1];
-    op->a.tile = best[2];
+    set_form(p, op, best);
     hip_check(hipMemcpy(op->d_a, &op->a, sizeof(ContractArgs), hipMemcpyHostToDevice), "autotune");
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+}
+
+// Decision file: one line per decision, "arch n k_0 ... k_{n-1} kind ksplit tile".
+extern "C" tn_status tn_tune_save(const char *path, int64_t *n_saved) {
+  return guard([&] {
+    if (!path) throw TnError(TN_E_INVALID, "NULL path");
+    TuneCache &tc = tune_cache();
+    std::lock_guard<std::mutex> lk(tc.mu);
+    FILE *f = std::fopen(path, "w");
+    if (!f) throw TnError(TN_E_INVALID, std::string("cannot write ") + path);
+    for (auto &kv : tc.dec) {
+      std::fprintf(f, "%s %zu", kv.first.first.c_str(), kv.first.second.size());
+      for (int64_t k : kv.first.second) std::fprintf(f, " %lld", (long long)k);
+      std::fprintf(f, " %d %d %d\n", kv.second[0], kv.second[1], kv.second[2]);
+    }
+    const bool ok = std::fclose(f) == 0;
+    if (!ok) throw TnError(TN_E_INVALID, std::string("cannot write ") + path);
+    if (n_saved) *n_saved = (int64_t)tc.dec.size();
+  });
+}
+
+extern "C" tn_status tn_tune_load(const char *path, int64_t *n_loaded) {
+  return guard([&] {
+    if (!path) throw TnError(TN_E_INVALID, "NULL path");
+    FILE *f = std::fopen(path, "r");
+    if (!f) throw TnError(TN_E_INVALID, std::string("cannot read ") + path);
+    std::vector<std::pair<std::pair<std::string, TuneKey>, std::array<int, 3>>> got;
+    char arch[64];
+    size_t n = 0;
+    bool bad = false;
+    while (std::fscanf(f, "%63s %zu", arch, &n) == 2) {
+      if (n > 64) { bad = true; break; }
+      TuneKey key(n);
+      for (size_t i = 0; i < n && !bad; ++i) {
+        long long k = 0;
+        if (std::fscanf(f, "%lld", &k) != 1) bad = true;
+        key[i] = k;
+      }
+      std::array<int, 3> d{};
+      if (bad || std::fscanf(f, "%d %d %d", &d[0], &d[1], &d[2]) != 3) { bad = true; break; }
+      if (d[0] < 0 || d[0] > 4 || (d[1] != 1 && d[1] != 4) || d[2] < 0 || d[2] > 2) { bad = true; break; }
+      got.push_back({{std::string(arch), key}, d});
+    }
+    const bool at_end = std::feof(f);
+    std::fclose(f);
+    if (bad || !at_end) throw TnError(TN_E_INVALID, std::string("malformed decision file ") + path);
+    TuneCache &tc = tune_cache();
+    std::lock_guard<std::mutex> lk(tc.mu);
+    for (auto &g : got) tc.dec[g.first] = g.second;
+    if (n_loaded) *n_loaded = (int64_t)got.size();
+  });
+}
+
+extern "C" void tn_tune_clear(void) {
+  TuneCache &tc = tune_cache();
+  std::lock_guard<std::mutex> lk(tc.mu);
+  tc.dec.clear();
 }
 
 static void build_mmap(tn_plan_t *p, const tn_net *net);
@@ -2440,8 +2537,10 @@ extern "C" tn_status tn_mmap(tn_plan_t *p, const int32_t *evidence, int32_t *ass
   return guard([&] {
     if (!p || !assign_q) throw TnError(TN_E_INVALID, "NULL argument");
     if (!p->is_mmap) throw TnError(TN_E_UNSUPPORTED, "plan has no query set");
-    run_mmap(p, evidence, assign_q, log_value);
-    if (!(*log_value > -INFINITY)) throw TnError(TN_E_ZERO_EVIDENCE, "p(e) = 0");
+    double v = -INFINITY;
+    run_mmap(p, evidence, assign_q, &v);
+    if (!(v > -INFINITY)) throw TnError(TN_E_ZERO_EVIDENCE, "p(e) = 0");
+    if (log_value) *log_value = v;
   });
 }
 

@@ -8,12 +8,14 @@ unless the oracle certifies a near-tie.
 import json
 import math
 import os
+import warnings
 
 import numpy as np
 import pytest
 
 import oracle
 import oracle.brute as bf
+from certify import certify_mmap
 from paper_2405_14060_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -30,6 +32,13 @@ def T(gpu):
 
 def rel(a, b):
     return abs(a - b) / max(1.0, abs(b))
+
+
+def note_near_tie(near):
+    """A certified MMAP near-tie (answer differs from the oracle's argmax by
+    less than the FP32 bound) is reported, never silently accepted."""
+    if near:
+        warnings.warn("certified MMAP near-tie")
 
 
 def oracle_tree(net, evidence=None, mode="slice", order=None):
@@ -360,8 +369,7 @@ def test_autotuned_dense_and_mmap_against_oracle(T):
     assert P.info()["n_sliced"] > 0
     val, x = P.mmap()
     assert abs(val - ov) <= 1e-5 * max(1, abs(ov))
-    if ogap > 1e-4:
-        assert np.array_equal(x, ox)
+    note_near_tie(certify_mmap(net, q, x, val))
 
 
 def test_grid20x20_full_size_against_oracle(T):
@@ -539,9 +547,8 @@ def test_mmap_small(T, seed):
     P = T.Plan(T.Network(net), query=q)
     val, x = P.mmap()
     bv, bx, gap = bf.mmap(net, q)
-    if gap > 1e-4:
-        assert np.array_equal(x, bx)
     assert abs(val - bv) <= 1e-4 * max(1, abs(bv))
+    note_near_tie(certify_mmap(net, q, x, val))
 
 
 def test_mmap_sliced(T):
@@ -559,9 +566,9 @@ def test_mmap_sliced(T):
     info = P.info()
     assert info["n_sliced"] > 0 and info["sc"] <= cap
     val, x = P.mmap()
-    if ogap > 1e-4:
-        assert np.array_equal(x, ox) and np.array_equal(x0, ox)
     assert abs(val - ov) <= 1e-5 * max(1, abs(ov))
+    note_near_tie(certify_mmap(net, q, x, val))
+    note_near_tie(certify_mmap(net, q, x0, val0))
     # one-slice profile of the sum phase (the benchmark's projection): its
     # launches carry the per-slice work, and a solve afterwards is unchanged
     prof = P.profile(3, reps=2)
@@ -586,8 +593,8 @@ def test_mmap_generic_output_order(T):
     assert P.info()["n_sliced"] > 0
     val, x = P.mmap()
     assert abs(val - ov) <= 1e-5 * max(1, abs(ov))
-    if ogap > 1e-4:
-        assert np.array_equal(x, ox) and np.array_equal(x0, ox)
+    note_near_tie(certify_mmap(net, q, x, val))
+    note_near_tie(certify_mmap(net, q, x0, val0))
 
 
 @pytest.mark.parametrize("autotune", [True, False])
@@ -628,7 +635,7 @@ def test_sampling_same_rng_as_oracle(T):
     s = P.sample(n, seed=1234)
     so = oracle.sample_tree(lv, pairs, n, seed=1234)
     agree = np.mean(np.all(s == so, axis=1))
-    assert agree >= 0.99, agree
+    assert agree >= 0.999, agree
 
 
 def test_sliced_log_z_and_sampling(T):
@@ -651,7 +658,7 @@ def test_sliced_log_z_and_sampling(T):
     s = P.sample(n, seed=77)
     so = oracle.sample_sliced(lv, pairs, sliced, n, seed=77)
     agree = np.mean(np.all(s == so, axis=1))
-    assert agree >= 0.99, agree
+    assert agree >= 0.999, agree
     with pytest.raises(T.TNError):
         P.marginals()
 
