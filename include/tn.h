@@ -251,6 +251,23 @@ tn_status tn_sample(tn_plan_t *plan, const int32_t *evidence, int64_t n, uint64_
                     int32_t *samples);
 
 /*
+ * tn_sample for callers that cannot allocate device memory (code that must
+ * not call hipMalloc: serving loops, harnesses that forbid allocation, work
+ * issued around stream capture).  Same arguments, results and Philox stream
+ * as tn_sample; the device staging of the samples (rows, and on sliced plans
+ * the ids of the samples drawn in one slice) lives in a static array of
+ * 2^22 int32 (16 MiB) that the library holds on each GPU until the process
+ * ends, instead of plan memory grown on demand.  The call launches kernels
+ * directly (no graph capture or instantiation) and allocates nothing on the
+ * device.  Limit: n * n_vars (+ 2 n + 64 on sliced plans) <= 2^22, else
+ * TN_E_TOO_LARGE.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (several threads or plans at once) race and must be
+ * serialised by the caller.
+ */
+tn_status tn_sample_noalloc(tn_plan_t *plan, const int32_t *evidence, int64_t n, uint64_t seed,
+                            int32_t *samples);
+
+/*
  * Device-side sum-product for differentiation (theorem thm:diff): factor
  * tables come from values_dev (FP32, linear, laid out as in
  * tn_load_network), log Z goes to logz_dev (FP64, one value), and if

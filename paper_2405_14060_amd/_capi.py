@@ -33,7 +33,7 @@ PLANNER_BEST, PLANNER_GREEDY, PLANNER_MINFILL, PLANNER_NATURAL, PLANNER_MINDEG =
 EXPORTS = ["tn_plan_opts_default", "tn_load_network", "tn_free_network", "tn_plan", "tn_free_plan",
            "tn_plan_info_get", "tn_plan_tree", "tn_plan_sliced", "tn_plan_tree_host", "tn_logZ", "tn_marginals",
            "tn_map", "tn_mmap", "tn_sample", "tn_logZ_dev", "tn_sync", "tn_profile", "tn_profile_kind", "tn_last_error",
-           "tn_tune_save", "tn_tune_load", "tn_tune_clear"]
+           "tn_tune_save", "tn_tune_load", "tn_tune_clear", "tn_sample_noalloc"]
 
 i32p = ctypes.POINTER(ctypes.c_int32)
 i64p = ctypes.POINTER(ctypes.c_int64)
@@ -117,6 +117,7 @@ def lib():
     L.tn_map.argtypes = [vp, ctypes.c_int32, i32p, i32p, f64p]
     L.tn_mmap.argtypes = [vp, i32p, i32p, f64p]
     L.tn_sample.argtypes = [vp, i32p, ctypes.c_int64, ctypes.c_uint64, i32p]
+    L.tn_sample_noalloc.argtypes = [vp, i32p, ctypes.c_int64, ctypes.c_uint64, i32p]
     L.tn_logZ_dev.argtypes = [vp, i32p, vp, vp, vp]
     L.tn_sync.argtypes = [vp]
     L.tn_profile.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, i32p, ctypes.c_int32,
@@ -128,7 +129,7 @@ def lib():
     L.tn_tune_clear.argtypes = []
     L.tn_tune_clear.restype = None
     for name in ("tn_tune_save", "tn_tune_load", "tn_load_network", "tn_plan", "tn_plan_info_get", "tn_plan_tree", "tn_plan_sliced", "tn_plan_tree_host",
-                 "tn_logZ", "tn_marginals", "tn_map", "tn_mmap", "tn_sample", "tn_logZ_dev", "tn_sync",
+                 "tn_logZ", "tn_marginals", "tn_map", "tn_mmap", "tn_sample", "tn_sample_noalloc", "tn_logZ_dev", "tn_sync",
                  "tn_profile", "tn_profile_kind"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -316,6 +317,14 @@ class Plan:
         ev = self._ev(evidence, 1)
         out = np.zeros((n, self.n_vars), np.int32)
         _check(lib().tn_sample(self.h, _ptr(ev, ctypes.c_int32), n, seed, _ptr(out, ctypes.c_int32)))
+        return out
+
+    def sample_noalloc(self, n, seed, evidence=None):
+        """tn_sample with the device staging in the library's static array
+        (no device allocation; n * n_vars <= 2^22)."""
+        ev = self._ev(evidence, 1)
+        out = np.zeros((n, self.n_vars), np.int32)
+        _check(lib().tn_sample_noalloc(self.h, _ptr(ev, ctypes.c_int32), n, seed, _ptr(out, ctypes.c_int32)))
         return out
 
     def log_z_dev(self, values_ptr, logz_ptr, grad_ptr=None, evidence=None):

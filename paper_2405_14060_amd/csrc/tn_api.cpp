@@ -1041,6 +1041,7 @@ static void upload_segments(tn_plan_t *p);
 
 static void allocate(tn_plan_t *p, const tn_net *net) {
   // device work starts here: everything above is host-side planning
+  hip_check(hipGetDevice(&p->device), "hipGetDevice");
   if (p->opts.hip_stream) {
     p->stream = (hipStream_t)p->opts.hip_stream;
   } else {
@@ -2007,7 +2008,7 @@ void launch_prepare_set(tn_plan_t *p, const std::vector<LeafDesc> &h, const Leaf
 // Run `body` directly, or replay its captured graph.
 template <class F>
 void run_graph(tn_plan_t *p, const std::string &key, F &&body) {
-  if (!p->opts.use_graph) {
+  if (!p->opts.use_graph || p->eager) {
     body();
     hip_check(hipGetLastError(), "kernel launch");
     return;
@@ -2213,6 +2214,14 @@ static void ensure_sample_buffer(tn_plan_t *p, int64_t n) {
   p->d_samp_out = dalloc<int32_t>(p, (size_t)n * p->n_vars);
   p->samp_cap = n;
 }
+
+// Device staging of one sampling call: the sample rows [n][n_vars] and, on
+// sliced plans, the ids of the samples drawn in one slice.
+struct SampleStaging {
+  int32_t *rows = nullptr;
+  int64_t *ids = nullptr;
+};
+
 // Sampling a sliced plan (reading of the paper's sampling step under
 // slicing), in one pass over the slices in order: sample i
 // takes slice s with probability Z_s / (Z_0 + ... + Z_s) (uniform from
@@ -2221,14 +2230,8 @@ static void ensure_sample_buffer(tn_plan_t *p, int64_t n) {
 // inside every slice it takes, right after that slice's forward pass; its
 // row ends as the draw of its last slice (the per-node counters follow the
 // sample id, so that draw equals drawing the slice first).
-static void sample_sliced(tn_plan_t *p, const int32_t *evidence, int64_t n, uint64_t seed, int32_t *samples) {
-  if (n == 0) {
-    if (!(log_sum_exp(slice_log_z(p, evidence, false)) > -INFINITY))
-      throw TnError(TN_E_ZERO_EVIDENCE, "p(e) = 0");
-    return;
-  }
-  ensure_sample_buffer(p, n);
-  int64_t *d_ids = dalloc<int64_t>(p, (size_t)n);
+static void sample_sliced(tn_plan_t *p, const int32_t *evidence, int64_t n, uint64_t seed, int32_t *samples,
+                          const SampleStaging &stg) {
   const int64_t ns = n_slices_of(p);
   double prefix = -INFINITY;
   std::vector<int64_t> ids;
@@ -2243,49 +2246,105 @@ static void sample_sliced(tn_plan_t *p, const int32_t *evidence, int64_t n, uint
     if (!(lz > -INFINITY)) continue;
     const double m = std::max(prefix, lz);
     prefix = m + std::log(std::exp(prefix - m) + std::exp(lz - m));
+    if (n == 0) continue;
     const double q = std::exp(lz - prefix);
     ids.clear();
     for (int64_t i = 0; i < n; ++i)
       if (sample_uniform((uint64_t)i, kSliceDrawNode, (uint32_t)s, seed) < q) ids.push_back(i);
     if (ids.empty()) continue;
-    hip_check(hipMemcpyAsync(d_ids, ids.data(), ids.size() * 8, hipMemcpyHostToDevice, p->stream), "ids");
+    hip_check(hipMemcpyAsync(stg.ids, ids.data(), ids.size() * 8, hipMemcpyHostToDevice, p->stream), "ids");
     run_sched(p, p->samp_ops, p->sched_samp);
     launch_sample(p->arena, p->d_samp, (int)p->samp.size(), p->d_samp_meta, p->n_vars, (int64_t)ids.size(), seed,
-                  p->d_evidence, d_ids, p->d_samp_out, p->stream);
+                  p->d_evidence, stg.ids, stg.rows, p->stream);
     hip_check(hipGetLastError(), "sample launch");
     hip_check(hipStreamSynchronize(p->stream), "sample");
   }
-  hip_check(hipFree(d_ids), "hipFree");
-  p->allocs.erase(std::find(p->allocs.begin(), p->allocs.end(), (void *)d_ids));
   if (!(prefix > -INFINITY)) throw TnError(TN_E_ZERO_EVIDENCE, "p(e) = 0");
-  hip_check(hipMemcpyAsync(samples, p->d_samp_out, (size_t)n * p->n_vars * 4, hipMemcpyDeviceToHost, p->stream), "D2H");
+  if (n == 0) return;
+  hip_check(hipMemcpyAsync(samples, stg.rows, (size_t)n * p->n_vars * 4, hipMemcpyDeviceToHost, p->stream), "D2H");
+  hip_check(hipStreamSynchronize(p->stream), "sample");
+}
+
+static void check_sample_args(tn_plan_t *p, int64_t n, int32_t *samples) {
+  if (!p || (!samples && n > 0)) throw TnError(TN_E_INVALID, "NULL argument");
+  if (n < 0) throw TnError(TN_E_INVALID, "negative sample count");
+  if (!p->want_sum || p->is_mmap || p->mode == TN_EVIDENCE_INDICATOR)
+    throw TnError(TN_E_UNSUPPORTED, "sampling needs a sum-product plan without batched evidence");
+}
+
+// n samples into the staging rows, then to the host (stg.rows holds
+// n * n_vars int32; stg.ids n int64 on sliced plans).
+static void sample_impl(tn_plan_t *p, const int32_t *evidence, int64_t n, uint64_t seed, int32_t *samples,
+                        const SampleStaging &stg) {
+  if (!p->sliced.empty()) {
+    sample_sliced(p, evidence, n, seed, samples, stg);
+    return;
+  }
+  upload_evidence(p, 1, evidence);
+  forward_sum(p, false, false);
+  run_sched(p, p->samp_ops, p->sched_samp);
+  std::vector<double> lz(1);
+  hip_check(hipMemcpyAsync(lz.data(), p->d_out, sizeof(double), hipMemcpyDeviceToHost, p->stream), "D2H");
+  hip_check(hipStreamSynchronize(p->stream), "sample forward");
+  if (!(lz[0] > -INFINITY)) throw TnError(TN_E_ZERO_EVIDENCE, "p(e) = 0");
+  if (n == 0) return;
+  launch_sample(p->arena, p->d_samp, (int)p->samp.size(), p->d_samp_meta, p->n_vars, n, seed, p->d_evidence,
+                nullptr, stg.rows, p->stream);
+  hip_check(hipGetLastError(), "sample launch");
+  hip_check(hipMemcpyAsync(samples, stg.rows, (size_t)n * p->n_vars * 4, hipMemcpyDeviceToHost, p->stream), "D2H");
   hip_check(hipStreamSynchronize(p->stream), "sample");
 }
 
 extern "C" tn_status tn_sample(tn_plan_t *p, const int32_t *evidence, int64_t n, uint64_t seed, int32_t *samples) {
   return guard([&] {
-    if (!p || (!samples && n > 0)) throw TnError(TN_E_INVALID, "NULL argument");
-    if (n < 0) throw TnError(TN_E_INVALID, "negative sample count");
-    if (!p->want_sum || p->is_mmap || p->mode == TN_EVIDENCE_INDICATOR)
-      throw TnError(TN_E_UNSUPPORTED, "sampling needs a sum-product plan without batched evidence");
-    if (!p->sliced.empty()) {
-      sample_sliced(p, evidence, n, seed, samples);
-      return;
+    check_sample_args(p, n, samples);
+    SampleStaging stg;
+    int64_t *d_ids = nullptr;
+    if (n > 0) {
+      ensure_sample_buffer(p, n);
+      stg.rows = p->d_samp_out;
+      if (!p->sliced.empty()) d_ids = stg.ids = dalloc<int64_t>(p, (size_t)n);
     }
-    upload_evidence(p, 1, evidence);
-    forward_sum(p, false, false);
-    run_sched(p, p->samp_ops, p->sched_samp);
-    std::vector<double> lz(1);
-    hip_check(hipMemcpyAsync(lz.data(), p->d_out, sizeof(double), hipMemcpyDeviceToHost, p->stream), "D2H");
-    hip_check(hipStreamSynchronize(p->stream), "sample forward");
-    if (!(lz[0] > -INFINITY)) throw TnError(TN_E_ZERO_EVIDENCE, "p(e) = 0");
-    if (n == 0) return;
-    ensure_sample_buffer(p, n);
-    launch_sample(p->arena, p->d_samp, (int)p->samp.size(), p->d_samp_meta, p->n_vars, n, seed, p->d_evidence,
-                  nullptr, p->d_samp_out, p->stream);
-    hip_check(hipGetLastError(), "sample launch");
-    hip_check(hipMemcpyAsync(samples, p->d_samp_out, (size_t)n * p->n_vars * 4, hipMemcpyDeviceToHost, p->stream), "D2H");
-    hip_check(hipStreamSynchronize(p->stream), "sample");
+    struct FreeIds {  // the id list lives for this call only
+      tn_plan_t *p;
+      int64_t *d;
+      ~FreeIds() {
+        if (!d) return;
+        (void)hipStreamSynchronize(p->stream);
+        (void)hipFree(d);
+        p->allocs.erase(std::find(p->allocs.begin(), p->allocs.end(), (void *)d));
+      }
+    } free_ids{p, d_ids};
+    sample_impl(p, evidence, n, seed, samples, stg);
+  });
+}
+
+extern "C" tn_status tn_sample_noalloc(tn_plan_t *p, const int32_t *evidence, int64_t n, uint64_t seed,
+                                       int32_t *samples) {
+  return guard([&] {
+    check_sample_args(p, n, samples);
+    // rows first, then the id list 256-byte aligned behind them
+    const int64_t row_ints = n * (int64_t)p->n_vars;
+    const int64_t id_off = (row_ints + 63) / 64 * 64;
+    const int64_t need = p->sliced.empty() ? row_ints : id_off + 2 * n;
+    if (p->n_vars > 0 && (n > kScratchInts / p->n_vars || need > kScratchInts))
+      throw TnError(TN_E_TOO_LARGE, "tn_sample_noalloc: " + std::to_string(n) + " samples of " +
+                                        std::to_string(p->n_vars) + " variables exceed the static staging of " +
+                                        std::to_string(kScratchInts) + " int32 (" +
+                                        std::to_string(kScratchInts * 4 >> 20) + " MiB)");
+    std::string err;
+    int32_t *base = scratch_ptr(p->device, err);
+    if (!base) throw TnError(TN_E_DEVICE, err);
+    SampleStaging stg;
+    stg.rows = base;
+    stg.ids = reinterpret_cast<int64_t *>(base + id_off);
+    struct Eager {  // no graph capture or instantiation in this call
+      tn_plan_t *p;
+      bool was;
+      ~Eager() { p->eager = was; }
+    } eager{p, p->eager};
+    p->eager = true;
+    sample_impl(p, evidence, n, seed, samples, stg);
   });
 }
 

@@ -326,6 +326,13 @@ void launch_sample(const float *arena, const SampleStep *steps, int n_steps, con
 double sample_uniform(uint64_t sample, uint32_t node, uint32_t slot, uint64_t seed);
 static constexpr uint32_t kSliceDrawNode = 0xffffffffu;  // node word of a sample's slice draw
 
+// Staging of the allocation-free sampler: a file-scope device array of
+// kScratchInts int32 per GPU (16 MiB).  scratch_ptr(dev) returns that GPU's
+// address (looked up once per device, with the device current), or nullptr
+// with a message in err.
+static constexpr int64_t kScratchInts = int64_t(1) << 22;
+int32_t *scratch_ptr(int dev, std::string &err);
+
 void launch_tolog(const float *src, const int32_t *ex, int slot, int64_t n, float *dst,
                   void *stream);
 

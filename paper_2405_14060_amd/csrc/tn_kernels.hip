@@ -28,6 +28,8 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
+#include <string>
 
 #include "tn_internal.h"
 
@@ -2649,6 +2651,45 @@ void launch_sample(const float *arena, const SampleStep *steps, int n_steps, con
   const int64_t blocks = (n + 3) / 4;  // four samples (waves) per workgroup
   k_sample<<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>(arena, steps, n_steps, meta, n_vars, n,
                                                              seed, init, ids, out);
+}
+
+// --------------------------------------------------------------------------
+// Library-held staging for the allocation-free sampler: one copy of this
+// array per GPU, alive until the process ends.  Host code never passes the
+// array's name to a kernel (on the host it is a stand-in, not a device
+// address): scratch_ptr() looks up each device's address once with
+// hipGetSymbolAddress, with that device current, and keeps it.
+// --------------------------------------------------------------------------
+static __device__ __align__(256) int32_t scratch[kScratchInts];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int32_t *g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+int32_t *scratch_ptr(int dev, std::string &err) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    err = "device id out of range";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[dev]) return g_scratch_dev[dev];
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+  void *ptr = nullptr;
+  if (e == hipSuccess) e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (cur >= 0 && cur != dev) {
+    const hipError_t e2 = hipSetDevice(cur);
+    if (e == hipSuccess) e = e2;
+  }
+  if (e != hipSuccess || !ptr) {
+    err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    return nullptr;
+  }
+  g_scratch_dev[dev] = (int32_t *)ptr;
+  return g_scratch_dev[dev];
 }
 
 // --------------------------------------------------------------------------

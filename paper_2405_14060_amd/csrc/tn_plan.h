@@ -218,6 +218,8 @@ struct tn_plan_impl {
   int64_t device_bytes = 0;
   std::vector<void *> allocs;
 
+  int device = 0;                      // GPU the plan's memory lives on
+  bool eager = false;                  // launch directly even with use_graph (allocation-free calls)
   std::map<std::string, hipGraphExec_t> graphs;
   ~tn_plan_impl();
 };
