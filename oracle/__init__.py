@@ -534,3 +534,84 @@ def mmap(net, query, evidence=None, pairs=None):
     gap = float(srt[-1] - srt[-2]) if flat.size > 1 else math.inf
     idx = np.unravel_index(k, [int(net.card[v]) for v in q]) if len(q) else ()
     return float(flat[k]), np.asarray(idx, np.int32), gap
+
+
+# ---------------------------------------------------------------------------
+# Joint and factor marginals (MAR section: unity tensors over several
+# variables; theorem thm:diff for the factors' own adjoints)
+# ---------------------------------------------------------------------------
+
+def add_joint_unity(leaves: Leaves, sets, evidence=None, mode: str = "slice") -> Leaves:
+    """The leaves plus one unity tensor (all ones) per variable set, over the
+    set's sorted variables (in slice mode its observed variables left out:
+    they are not labels of the sliced network).  Appended after the other
+    leaves, in the order of ``sets``; kind 'joint'."""
+    n = len(leaves.card)
+    ev = np.full(n, -1, np.int32) if evidence is None else np.asarray(evidence, np.int32)
+    labels, values, kind = list(leaves.labels), list(leaves.values), list(leaves.kind)
+    fo, vo = list(leaves.factor_of), list(leaves.var_of)
+    for s in sets:
+        lab = np.array(sorted(int(v) for v in s if not (mode == "slice" and ev[int(v)] >= 0)), np.int32)
+        labels.append(lab)
+        values.append(np.ones(int(np.prod(leaves.card[lab])) if lab.size else 1))
+        kind.append("joint")
+        fo.append(-1)
+        vo.append(-1)
+    return Leaves(leaves.card, labels, values, kind, fo, vo)
+
+
+def joint_marginals(net, sets, evidence=None, mode="slice", pairs=None):
+    """p(x_S | e) for every variable set S (sorted ascending; row-major,
+    last variable fastest) from the adjoint of a unity tensor over S: with
+    the unity tensor in the network Z is unchanged, and its adjoint is the
+    contraction of everything else with S left open, i.e. p(x_S, e) up to
+    the common factor.  Observed variables of S (slice mode) are one-hot.
+    Returns (log Z, list of arrays shaped by the sorted set's cards)."""
+    lv = add_joint_unity(build_leaves(net, evidence, mode), sets, evidence, mode)
+    pairs = default_tree(lv) if pairs is None else pairs
+    root, ex, adj, aexp = sum_forward(lv, pairs, want_adj=True)
+    ev = np.full(net.n_vars, -1) if evidence is None else np.asarray(evidence)
+    base = len(lv) - len(sets)
+    out = []
+    for k, s in enumerate(sets):
+        srt = sorted(int(v) for v in s)
+        free = [v for v in srt if not (mode == "slice" and ev[v] >= 0)]
+        w = adj[base + k] * lv.values[base + k]
+        w = w / w.sum()
+        full = np.zeros([int(net.card[v]) for v in srt])
+        idx = tuple(int(ev[v]) if (mode == "slice" and ev[v] >= 0) else slice(None) for v in srt)
+        full[idx] = w.reshape([int(net.card[v]) for v in free]) if free else w[0]
+        out.append(full)
+    lz = math.log(root[0]) + ex * LN2 if root[0] > 0 else -math.inf
+    return lz, out
+
+
+def factor_marginals(net, evidence=None, mode="slice", pairs=None):
+    """p(x_f | e) over every factor's scope (theorem thm:diff: the factor's
+    adjoint is dZ/dT_f, so T_f * Tbar_f / Z sums to one over the scope).
+    Each result is flattened in the factor's scope order as loaded (last
+    variable fastest), with zeros where an observed variable (slice mode)
+    takes another value.  Returns (log Z, list of flat arrays)."""
+    lv = build_leaves(net, evidence, mode)
+    pairs = default_tree(lv) if pairs is None else pairs
+    root, ex, adj, aexp = sum_forward(lv, pairs, want_adj=True)
+    ev = np.full(net.n_vars, -1) if evidence is None else np.asarray(evidence)
+    out = [None] * net.n_factors
+    for i, k in enumerate(lv.kind):
+        if k != "factor":
+            continue
+        f = lv.factor_of[i]
+        s = [int(v) for v in net.scopes[f]]
+        free_sorted = [int(v) for v in lv.labels[i]]
+        w = adj[i] * lv.values[i]
+        w = w / w.sum()
+        # sorted free labels -> scope order, observed axes one-hot
+        t = w.reshape([int(net.card[v]) for v in free_sorted]) if free_sorted else w.reshape(())
+        perm = [free_sorted.index(v) for v in s if v in free_sorted]
+        t = np.transpose(t, perm) if free_sorted else t
+        full = np.zeros([int(net.card[v]) for v in s])
+        idx = tuple(int(ev[v]) if (mode == "slice" and ev[v] >= 0) else slice(None) for v in s)
+        full[idx] = t
+        out[f] = full.ravel()
+    lz = math.log(root[0]) + ex * LN2 if root[0] > 0 else -math.inf
+    return lz, out

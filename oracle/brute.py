@@ -102,3 +102,20 @@ def mmap(net, query, evidence=None):
     ev = np.full(net.n_vars, -1) if evidence is None else np.asarray(evidence)
     idx = np.unravel_index(k, qt.shape)
     return float(flat[k]), np.asarray(idx, np.int32), gap
+
+
+def joint_marginal(net, variables, evidence=None):
+    """p(x_S | e) over the sorted set S by summing the joint table over every
+    other variable; observed variables of S are one-hot."""
+    s = sorted(int(v) for v in variables)
+    t = joint_log_table(net, evidence)
+    m = np.max(t)
+    p = np.exp(t - m)
+    p /= p.sum()
+    axes = tuple(a for a in range(net.n_vars) if a not in s)
+    q = p.sum(axis=axes) if axes else p
+    ev = np.full(net.n_vars, -1) if evidence is None else np.asarray(evidence)
+    full = np.zeros([int(net.card[v]) for v in s])
+    idx = tuple(slice(int(ev[v]), int(ev[v]) + 1) if ev[v] >= 0 else slice(None) for v in s)
+    full[idx] = q
+    return full
