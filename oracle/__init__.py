@@ -39,7 +39,7 @@ _lib = None
 def build(force: bool = True) -> str:
     """Compile the C part with gcc (plain -O2, no fast-math, no FP contraction)."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
                                "-shared", "-o", _SO, _SRC, "-lm"])
     return _SO
 
@@ -61,8 +61,23 @@ def lib():
         L.or_sample.argtypes = [ctypes.c_int, i32p, ctypes.c_int, i64p, i32p, f64p,
                                 ctypes.c_int, i32p, ctypes.c_uint64, ctypes.c_int64, i64p, i32p]
         L.or_philox4x32_10.argtypes = [P(ctypes.c_uint32), P(ctypes.c_uint32), P(ctypes.c_uint32)]
+        L.or_set_threads.argtypes = [ctypes.c_int]
+        L.or_set_threads.restype = None
+        L.or_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's parallel loops (each output element of a
+    contraction is one sum in a fixed order, so every thread count gives the
+    same bits); returns the count now in use."""
+    lib().or_set_threads(int(n))
+    return int(lib().or_threads())
+
+
+def threads() -> int:
+    return int(lib().or_threads())
 
 
 def _p(a, ct):

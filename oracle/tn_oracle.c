@@ -49,6 +49,9 @@
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 static char g_err[512];
 const char *or_last_error(void) { return g_err; }
@@ -271,41 +274,113 @@ static int root_id(const Tree *t) { return t->n_nodes - 1; }
 /* Sum-product                                                               */
 /* ------------------------------------------------------------------------ */
 
-/* C[x_c] += A[x_a] * B[x_b] over all assignments of the union of the labels
+/* out[x_o] = sum over the assignments of the labels of P and Q not in out
+ * (row-major, last fastest) of P[x_p] * Q[x_q]; out's labels are a subset
+ * of P's and Q's.  Each output element is one independent sum taken in that
+ * order, so the elements may be computed in parallel (OpenMP) with the same
+ * result as one sequential pass over the whole label union. */
+static int sum_into(const Ten *P, const Ten *Q, Ten *out, const int *card) {
+  int U[128], E[128];
+  if (P->nl + Q->nl > 128) return fail("label union too large");
+  const int nu = label_union(P, Q, U);
+  int ne = 0;
+  for (int j = 0; j < nu; ++j)
+    if (!has_label(out, U[j])) E[ne++] = U[j];
+  if (ne > 64 || out->nl > 64) return fail("too many labels in one contraction");
+  int64_t sPo[64], sQo[64], sPe[64], sQe[64];
+  int co[64], ce[64];
+  for (int j = 0; j < out->nl; ++j) {
+    co[j] = card[out->lab[j]];
+    sPo[j] = stride_of(P, out->lab[j], card);
+    sQo[j] = stride_of(Q, out->lab[j], card);
+  }
+  int64_t n_e = 1;
+  for (int j = 0; j < ne; ++j) {
+    ce[j] = card[E[j]];
+    sPe[j] = stride_of(P, E[j], card);
+    sQe[j] = stride_of(Q, E[j], card);
+    n_e *= ce[j];
+  }
+  const int64_t n_o = out->size;
+#pragma omp parallel
+  {
+    /* a contiguous range of output elements per thread: decode its first
+     * element, then step through the rest in row-major order */
+    int nt = 1, it = 0;
+#ifdef _OPENMP
+    nt = omp_get_num_threads();
+    it = omp_get_thread_num();
+#endif
+    const int64_t lo = n_o * it / nt, hi = n_o * (it + 1) / nt;
+    int dout[64], d[64];
+    int64_t k = lo, p0 = 0, q0 = 0;
+    for (int j = out->nl - 1; j >= 0; --j) {
+      dout[j] = (int)(k % co[j]);
+      k /= co[j];
+      p0 += dout[j] * sPo[j];
+      q0 += dout[j] * sQo[j];
+    }
+    for (int64_t oc = lo; oc < hi; ++oc) {
+      for (int j = 0; j < ne; ++j) d[j] = 0;
+      int64_t p = p0, q = q0;
+      double acc = 0.0;
+      for (int64_t e = 0; e < n_e; ++e) {
+        acc += P->v[p] * Q->v[q];
+        for (int j = ne - 1; j >= 0; --j) { /* next assignment of E */
+          if (++d[j] < ce[j]) { p += sPe[j]; q += sQe[j]; break; }
+          d[j] = 0;
+          p -= sPe[j] * (ce[j] - 1);
+          q -= sQe[j] * (ce[j] - 1);
+        }
+      }
+      out->v[oc] = acc;
+      for (int j = out->nl - 1; j >= 0; --j) { /* next output element */
+        if (++dout[j] < co[j]) { p0 += sPo[j]; q0 += sQo[j]; break; }
+        dout[j] = 0;
+        p0 -= sPo[j] * (co[j] - 1);
+        q0 -= sQo[j] * (co[j] - 1);
+      }
+    }
+  }
+  return 0;
+}
+
+/* C[x_c] = sum over the labels of A and B not in C of A[x_a] * B[x_b]
  * (B may be NULL for a single operand). */
 static int contract_sum(const Ten *A, const Ten *B, Ten *C, const int *card) {
-  static const Ten one = {0, NULL, 1, NULL, 0};
-  const Ten *b = B ? B : &one;
-  int U[128];
-  if (A->nl + b->nl > 128) return fail("label union too large");
-  int nu = label_union(A, b, U);
-  Odo o;
-  if (odo_init(&o, nu, U, card, A, b, C)) return -1;
-  do {
-    double bv = B ? B->v[o.off[1]] : 1.0;
-    C->v[o.off[2]] += A->v[o.off[0]] * bv;
-  } while (odo_next(&o));
+  static double one_v = 1.0;
+  static const Ten one = {0, NULL, 1, &one_v, 0};
+  if (sum_into(A, B ? B : &one, C, card)) return -1;
   C->ex = A->ex + (B ? B->ex : 0);
   rescale(C);
   return 0;
 }
 
-/* Reverse rule (eq. einback): Abar += Cbar * B, Bbar += Cbar * A. */
+/* Reverse rule (eq. einback): Abar = con(Cbar, B -> labels of A),
+ * Bbar = con(Cbar, A -> labels of B). */
 static int adjoint_sum(const Ten *A, const Ten *B, const Ten *Cbar, Ten *Abar, Ten *Bbar,
                        const int *card) {
-  int U[128];
-  if (A->nl + B->nl > 128) return fail("label union too large");
-  int nu = label_union(A, B, U);
-  Odo o;
-  if (odo_init(&o, nu, U, card, A, B, Cbar)) return -1;
-  do {
-    double cb = Cbar->v[o.off[2]];
-    if (Abar) Abar->v[o.off[0]] += cb * B->v[o.off[1]];
-    if (Bbar) Bbar->v[o.off[1]] += cb * A->v[o.off[0]];
-  } while (odo_next(&o));
+  if (Abar && sum_into(Cbar, B, Abar, card)) return -1;
+  if (Bbar && sum_into(Cbar, A, Bbar, card)) return -1;
   if (Abar) { Abar->ex = Cbar->ex + B->ex; rescale(Abar); }
   if (Bbar) { Bbar->ex = Cbar->ex + A->ex; rescale(Bbar); }
   return 0;
+}
+
+/* Threads of the parallel loops (OpenMP); n <= 0 leaves the default. */
+void or_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+int or_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }
 
 /*
