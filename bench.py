@@ -18,6 +18,11 @@ Other workloads (--workload), each printed as the same kind of JSON line:
               oracle's FP32 emulation
   grid20_map  MAP on the 20x20 grid (max-plus at the size of the sum-product
               workload)
+  regular3_mmap  MMAP on the 220-variable 3-regular graph (25 query variables,
+              sliced to intermediates <= 2^28) and 10k samples
+  tropical_gemm  MAP on a three-factor network whose time is one dense
+              max-plus product (4 x 729^3 candidates, argmax kept), against
+              the vector-ALU bound
 
 Prints one JSON line.
 """
@@ -128,9 +133,10 @@ def bench_grid20(args, T, W, np, sync):
         t0 = time.perf_counter()
         lz_o, marg_o, *_ = oracle.marginals(net, pairs=pairs)
         d = time.perf_counter() - t0
-        out["cpu_baseline"] = dict(value=1.0 / d, unit="solves/s", cores=1, kind="oracle",
+        out["cpu_baseline"] = dict(value=1.0 / d, unit="solves/s", cores=oracle.threads(), kind="oracle",
                                    sample="one full solve (log Z + all 400 marginals) of the same 20x20 grid, "
-                                          "single-threaded FP64 loop nests, %.1f s" % d)
+                                          "FP64 loop nests, output elements of each contraction split over "
+                                          "%d threads (OpenMP), %.1f s" % (oracle.threads(), d))
         got = plan.split_marginals(m[0])
         out["err_vs_oracle"] = dict(log_z_rel=abs(float(lz[0]) - lz_o) / abs(lz_o),
                                     marginal_max_abs=float(max(np.abs(a - b).max() for a, b in zip(got, marg_o))))
@@ -196,8 +202,9 @@ def bench_bn500x512(args, T, W, np, sync):
                                 max(np.abs(a - b).max() for a, b in zip(got, marg_o))))
             n_o += 1
         d = time.perf_counter() - t0
-        out["cpu_baseline"] = dict(value=n_o / d, unit="instance-solves/s", cores=1, kind="oracle",
-                                   sample="first %d of the 512 evidence sets, single-threaded FP64, %.1f s" % (n_o, d))
+        out["cpu_baseline"] = dict(value=n_o / d, unit="instance-solves/s", cores=oracle.threads(), kind="oracle",
+                                   sample="first %d of the 512 evidence sets, FP64 loop nests over %d threads "
+                                          "(OpenMP), %.1f s" % (n_o, oracle.threads(), d))
         out["err_vs_oracle"] = dict(log_z_rel=float(max(e[0] for e in errs)),
                                     marginal_max_abs=float(max(e[1] for e in errs)), instances=n_o)
         if errs_lp:
@@ -298,12 +305,58 @@ def bench_regular3_mmap(args, T, W, np, sync):
         oracle.sum_forward(lv, pairs, out=np.sort(q))
         d = time.perf_counter() - t0
         mac_rate = 2.0 ** st["tc"] / d
-        out["cpu_baseline"] = dict(value=mac_rate / 2.0 ** info["tc"], unit="MMAP solves/s (projected)", cores=1,
+        out["cpu_baseline"] = dict(value=mac_rate / 2.0 ** info["tc"], unit="MMAP solves/s (projected)",
+                                   cores=oracle.threads(),
                                    kind="oracle",
                                    sample="oracle sum phase of one sub-slice (%d summed variables fixed, its own "
-                                          "tree, 2^%.2f multiply-adds, %.1f s, single-threaded FP64); projected to "
+                                          "tree, 2^%.2f multiply-adds, %.1f s, FP64 over all host threads); projected to "
                                           "the plan's 2^%.2f multiply-adds at the same rate" % (k, st["tc"], d,
                                                                                                info["tc"]))
+    return out
+
+
+# dense max-plus on the vector ALUs: one candidate is one FP32 add and one
+# max (2 tropical ops, as a sum-product candidate is a multiply and an add);
+# each is one non-packed VALU instruction per lane, and the chip issues
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T such lane-operations per
+# second.  Keeping the argmax costs a compare and a second select per
+# candidate on top of that (the fraction is against the value-only bound).
+TROPICAL_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def bench_tropical_gemm(args, T, W, np, sync):
+    """MAP on a three-factor network whose max-plus tree starts with one
+    large dense tropical product Z[b, m, n] = max_s X[b, m, s] + Y[b, s, n]
+    (4 x 729 x 729 x 729 candidates), with its argmax; then the small
+    remainder of the tree and the argmax readout."""
+    net = W.three_factor_net(2, 6, 6, 6, 3, seed=0)
+    plan = T.Plan(T.Network(net), semirings=T.MAX_PLUS, use_graph=not args.no_graph)
+    info = plan.info()
+    sec, (lp, x) = timed(lambda: plan.map(), args.steps, args.warmup, lambda: (plan.sync(), sync()))
+    prof = plan.profile(2, reps=3)
+    kind_of = {v: k for k, v in KIND_NAMES.items()}
+    avg_ms, fl_launch, by_launch, n_launch = plan.profile_kind(2, kind_of["contract_tropical_dense"], reps=5)
+    tops = fl_launch / (avg_ms * 1e-3) / 1e12
+    roof = dict(bound="alu", achieved=round(tops, 3), peak=round(TROPICAL_PEAK_TOPS, 2), unit="T tropical-op/s",
+                frac=round(tops / TROPICAL_PEAK_TOPS, 4), traffic=None, kernel="contract_tropical_dense",
+                launches_per_solve=n_launch, avg_launch_us=round(avg_ms * 1e3, 3), bytes_per_launch=round(by_launch),
+                flops_per_launch=round(fl_launch), candidates_per_s=round(fl_launch / 2 / (avg_ms * 1e-3), 1))
+    kernels = {k: dict(n=v["n"], ms=round(v["ms"], 4)) for k, v in kernel_summary(prof).items()}
+    out = dict(value=round(1.0 / sec, 3), unit="MAP solves/s", ms_per_step=round(sec * 1e3, 4), dtype="f32",
+               config=dict(workload="three-factor network, 4 x 729 x 729 x 729 dense max-plus product + readout",
+                           seed=0, n_vars=int(net.n_vars), tree_sc_log2=round(info["sc"], 3),
+                           tree_tc_log2=round(info["tc"], 3), graph=not args.no_graph),
+               log_p=float(lp[0]), roofline=roof, kernels=kernels)
+    if not args.no_cpu_baseline:
+        import oracle
+        pairs, _ = plan.tree()
+        t0 = time.perf_counter()
+        val, asg = oracle.map_assignment(net, None, pairs=pairs.astype(np.int64), fp32=True)
+        d = time.perf_counter() - t0
+        out["cpu_baseline"] = dict(value=1.0 / d, unit="MAP solves/s", cores=1, kind="oracle",
+                                   sample="one MAP solve on the plan's tree, FP32-emulating loops, %.1f s" % d)
+        out["bit_exact_vs_oracle_fp32"] = bool(np.array_equal(np.asarray(asg), x[0]) and
+                                               np.float32(val) == np.float32(lp[0]))
     return out
 
 
@@ -344,7 +397,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="grid20", choices=["grid20", "bn500x512", "bn300_map", "grid20_map",
-                                                               "regular3_mmap"])
+                                                               "regular3_mmap", "tropical_gemm"])
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "f16"],
                     help="matrix-core operand precision of the sum-product workloads")
     ap.add_argument("--batch-layout", default="auto", choices=["auto", "instance_major", "interleaved"],
@@ -384,6 +437,8 @@ def main():
         res = bench_bn500x512(args, T, W, np, sync)
     elif args.workload == "regular3_mmap":
         res = bench_regular3_mmap(args, T, W, np, sync)
+    elif args.workload == "tropical_gemm":
+        res = bench_tropical_gemm(args, T, W, np, sync)
     else:
         res = bench_map(args, T, W, np, sync, args.workload)
     out = dict(metric=METRIC, value=res.pop("value"), unit=res.pop("unit"), n_gpus=1, steps=args.steps,

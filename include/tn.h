@@ -130,6 +130,13 @@ typedef struct {
                                 multiple of 64: one wavefront computes one
                                 output element for 64 instances, FP32 on the
                                 vector ALUs) */
+  const int64_t *joint_ptr;  /* joint marginals (tn_joint_marginals): n_joint + 1
+                                offsets into joint_vars, set k = joint_vars
+                                [joint_ptr[k], joint_ptr[k + 1]); NULL = none */
+  const int32_t *joint_vars; /* variables of the sets (distinct within a set) */
+  int32_t n_joint;           /* number of sets; each adds a unity tensor over
+                                its variables to the network (leaf ids after
+                                the unity vectors, in set order) */
 } tn_plan_opts;
 
 /* Summary of a plan (tn_plan_info). */
@@ -159,6 +166,10 @@ typedef struct {
   int32_t batch_stride;          /* interleaved plans: instances held per element (max_batch
                                     rounded up to a multiple of 64); 0 otherwise */
   int32_t n_dense_large;         /* of n_dense: contractions with 128 x 128 output tiles */
+  int32_t two_front;             /* 1: the tree is the two-front variant of the planner's
+                                    elimination order (two intermediates grown from both ends
+                                    of the order, contracted side by side until they meet) */
+  int32_t n_levels;              /* levels of the main tree (longest leaf-to-root path) */
 } tn_plan_info;
 
 /* Fill *o with defaults: sum-product + max-plus, no evidence, best planner,
@@ -178,12 +189,48 @@ tn_status tn_load_network(int32_t n_vars, const int32_t *card, int32_t n_factors
 void tn_free_network(tn_net *net);
 
 /*
+ * A model file in the UAI inference-competition format (the format of the
+ * problem sets of the paper's benchmarks): preamble MARKOV or BAYES, the
+ * number of variables, their domain sizes, the number of functions, each
+ * function's scope (size, then variable ids), then each function's table
+ * (entry count, then the entries row-major over the scope, last variable
+ * fastest; linear values).  White space of any kind separates tokens.  A
+ * BAYES file's conditional probability tables load as factors unchanged.
+ * Errors: TN_E_INVALID (unreadable file, malformed content; the message
+ * names the file and the token), TN_E_NOMEM.
+ */
+tn_status tn_load_uai(const char *path, tn_net **out);
+
+/*
+ * A UAI evidence file: "n v_1 x_1 ... v_n x_n" (one evidence set) or a set
+ * count m followed by m such sets.  Writes up to cap_rows rows of n_vars
+ * int32 (-1 = unobserved) into evidence and the number of sets in the file
+ * to *n_rows (call with cap_rows = 0 to size the buffer).  card (n_vars
+ * entries) checks the values.  Errors: TN_E_INVALID.
+ */
+tn_status tn_read_uai_evidence(const char *path, int32_t n_vars, const int32_t *card, int32_t *evidence,
+                               int32_t cap_rows, int32_t *n_rows);
+
+/* A UAI query file "n q_1 ... q_n" (e.g. the MMAP max variables): writes up
+ * to cap ids to vars and n to *n.  Errors: TN_E_INVALID. */
+tn_status tn_read_uai_query(const char *path, int32_t n_vars, int32_t *vars, int32_t cap, int32_t *n);
+
+/* Read back a loaded network: sizes (any pointer may be NULL), then the
+ * arrays in the layout of tn_load_network (caller-allocated; NULL skips). */
+tn_status tn_network_sizes(const tn_net *net, int32_t *n_vars, int32_t *n_factors, int64_t *n_scope,
+                           int64_t *n_values);
+tn_status tn_network_get(const tn_net *net, int32_t *card, int64_t *scope_ptr, int32_t *scope_vars,
+                         double *values, int32_t *values_are_log);
+
+/*
  * Build a plan: leaves, contraction tree, per-node kernel descriptors,
  * device buffers.  Leaf ids (for tree_pairs): factors 0..n_factors-1 in
  * load order, then one unity vector per variable in increasing id order --
  * all variables for modes NONE and INDICATOR, only unobserved ones for mode
- * SLICED.  (paper: MAR algorithm step 1 adds one unity tensor per query
- * variable; with batched evidence it doubles as the evidence indicator.)
+ * SLICED -- then one unity tensor per joint set (joint_*), in set order
+ * (none for a set whose variables are all observed in mode SLICED).
+ * (paper: MAR algorithm step 1 adds one unity tensor per query variable;
+ * with batched evidence it doubles as the evidence indicator.)
  * With a query set, the plan holds the two MMAP phases instead.
  * Errors: TN_E_INVALID (bad options or tree), TN_E_TOO_LARGE, TN_E_NOMEM,
  * TN_E_DEVICE.
@@ -226,6 +273,29 @@ tn_status tn_logZ(tn_plan_t *plan, int32_t batch, const int32_t *evidence, doubl
  */
 tn_status tn_marginals(tn_plan_t *plan, int32_t batch, const int32_t *evidence, double *logz,
                        double *marg);
+
+/*
+ * Joint marginals p(x_S | e) of the plan's variable sets (tn_plan_opts
+ * joint_*): the adjoint of a unity tensor over each set, normalised (the MAR
+ * algorithm's unity tensors over several variables; theorem thm:diff).
+ * joint: [batch][sum_k prod_{v in S_k} card[v]] FP64; set k's table is
+ * row-major over its variables sorted ascending (last fastest), zero where an
+ * observed variable takes another value.  logz optional.  Modes as for
+ * tn_marginals.  TN_E_UNSUPPORTED if the plan has no sets.
+ */
+tn_status tn_joint_marginals(tn_plan_t *plan, int32_t batch, const int32_t *evidence, double *logz,
+                             double *joint);
+
+/*
+ * Factor marginals p(x_f | e) = T_f(x_f) Tbar_f(x_f) / Z for every factor
+ * (theorem thm:diff: Tbar_f = dZ / dT_f, and the products sum to Z over the
+ * factor's scope).  fmarg: [batch][n_values] FP64, laid out as the values of
+ * tn_load_network (scope order as loaded, last fastest), zero where an
+ * observed variable takes another value.  logz optional.  Needs a plan built
+ * with want_factor_grad; modes as for tn_marginals.
+ */
+tn_status tn_factor_marginals(tn_plan_t *plan, int32_t batch, const int32_t *evidence, double *logz,
+                              double *fmarg);
 
 /*
  * MPE (eq. log-map): assign [batch][n_vars] (evidence copied in), logp

@@ -33,7 +33,9 @@ PLANNER_BEST, PLANNER_GREEDY, PLANNER_MINFILL, PLANNER_NATURAL, PLANNER_MINDEG =
 EXPORTS = ["tn_plan_opts_default", "tn_load_network", "tn_free_network", "tn_plan", "tn_free_plan",
            "tn_plan_info_get", "tn_plan_tree", "tn_plan_sliced", "tn_plan_tree_host", "tn_logZ", "tn_marginals",
            "tn_map", "tn_mmap", "tn_sample", "tn_logZ_dev", "tn_sync", "tn_profile", "tn_profile_kind", "tn_last_error",
-           "tn_tune_save", "tn_tune_load", "tn_tune_clear", "tn_sample_noalloc"]
+           "tn_tune_save", "tn_tune_load", "tn_tune_clear", "tn_sample_noalloc", "tn_joint_marginals",
+           "tn_factor_marginals", "tn_load_uai", "tn_read_uai_evidence", "tn_read_uai_query", "tn_network_sizes",
+           "tn_network_get"]
 
 i32p = ctypes.POINTER(ctypes.c_int32)
 i64p = ctypes.POINTER(ctypes.c_int64)
@@ -52,7 +54,8 @@ class PlanOpts(ctypes.Structure):
                 ("tree_pairs", i32p), ("n_tree_pairs", ctypes.c_int32),
                 ("want_factor_grad", ctypes.c_int32), ("host_only", ctypes.c_int32),
                 ("no_fuse", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("batch_layout", ctypes.c_int32)]
+                ("batch_layout", ctypes.c_int32), ("joint_ptr", i64p), ("joint_vars", i32p),
+                ("n_joint", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -67,7 +70,8 @@ class PlanInfo(ctypes.Structure):
                 ("n_segments", ctypes.c_int32), ("n_fused_nodes", ctypes.c_int32),
                 ("n_dense", ctypes.c_int32), ("n_wave", ctypes.c_int32),
                 ("n_interleaved", ctypes.c_int32), ("batch_stride", ctypes.c_int32),
-                ("n_dense_large", ctypes.c_int32)]
+                ("n_dense_large", ctypes.c_int32), ("two_front", ctypes.c_int32),
+                ("n_levels", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -115,6 +119,8 @@ def lib():
     L.tn_logZ.argtypes = [vp, ctypes.c_int32, i32p, f64p]
     L.tn_marginals.argtypes = [vp, ctypes.c_int32, i32p, f64p, f64p]
     L.tn_map.argtypes = [vp, ctypes.c_int32, i32p, i32p, f64p]
+    L.tn_joint_marginals.argtypes = [vp, ctypes.c_int32, i32p, f64p, f64p]
+    L.tn_factor_marginals.argtypes = [vp, ctypes.c_int32, i32p, f64p, f64p]
     L.tn_mmap.argtypes = [vp, i32p, i32p, f64p]
     L.tn_sample.argtypes = [vp, i32p, ctypes.c_int64, ctypes.c_uint64, i32p]
     L.tn_sample_noalloc.argtypes = [vp, i32p, ctypes.c_int64, ctypes.c_uint64, i32p]
@@ -124,12 +130,19 @@ def lib():
                              ctypes.POINTER(OpProfile), ctypes.c_int32, i32p]
     L.tn_profile_kind.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, i32p, ctypes.c_int32,
                                   ctypes.POINTER(OpProfile), i32p]
+    L.tn_load_uai.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
+    L.tn_read_uai_evidence.argtypes = [ctypes.c_char_p, ctypes.c_int32, i32p, i32p, ctypes.c_int32, i32p]
+    L.tn_read_uai_query.argtypes = [ctypes.c_char_p, ctypes.c_int32, i32p, ctypes.c_int32, i32p]
+    L.tn_network_sizes.argtypes = [vp, i32p, i32p, i64p, i64p]
+    L.tn_network_get.argtypes = [vp, i32p, i64p, i32p, f64p, i32p]
     L.tn_tune_save.argtypes = [ctypes.c_char_p, i64p]
     L.tn_tune_load.argtypes = [ctypes.c_char_p, i64p]
     L.tn_tune_clear.argtypes = []
     L.tn_tune_clear.restype = None
-    for name in ("tn_tune_save", "tn_tune_load", "tn_load_network", "tn_plan", "tn_plan_info_get", "tn_plan_tree", "tn_plan_sliced", "tn_plan_tree_host",
-                 "tn_logZ", "tn_marginals", "tn_map", "tn_mmap", "tn_sample", "tn_sample_noalloc", "tn_logZ_dev", "tn_sync",
+    for name in ("tn_load_uai", "tn_read_uai_evidence", "tn_read_uai_query", "tn_network_sizes", "tn_network_get",
+                 "tn_tune_save", "tn_tune_load", "tn_load_network", "tn_plan", "tn_plan_info_get", "tn_plan_tree", "tn_plan_sliced", "tn_plan_tree_host",
+                 "tn_logZ", "tn_marginals", "tn_joint_marginals", "tn_factor_marginals", "tn_map", "tn_mmap",
+                 "tn_sample", "tn_sample_noalloc", "tn_logZ_dev", "tn_sync",
                  "tn_profile", "tn_profile_kind"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -167,6 +180,56 @@ def tune_clear() -> None:
 class Network:
     """A model loaded into libtn (copy of the factor tables)."""
 
+    @classmethod
+    def from_uai(cls, path):
+        """Load a UAI-format model file (MARKOV or BAYES) through tn_load_uai."""
+        h = ctypes.c_void_p()
+        _check(lib().tn_load_uai(os.fsencode(path), ctypes.byref(h)))
+        self = cls.__new__(cls)
+        self.h = h
+        self._read_back()
+        return self
+
+    def _read_back(self):
+        """Fill src, card and sizes from the library's copy of the model."""
+        from . import workloads as W
+        nv, nf, ns, nvals = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().tn_network_sizes(self.h, ctypes.byref(nv), ctypes.byref(nf), ctypes.byref(ns), ctypes.byref(nvals)))
+        card = np.zeros(max(1, nv.value), np.int32)
+        sp = np.zeros(nf.value + 1, np.int64)
+        sv = np.zeros(max(1, ns.value), np.int32)
+        vals = np.zeros(max(1, nvals.value))
+        is_log = ctypes.c_int32()
+        _check(lib().tn_network_get(self.h, _ptr(card, ctypes.c_int32), _ptr(sp, ctypes.c_int64),
+                                    _ptr(sv, ctypes.c_int32), _ptr(vals, ctypes.c_double), ctypes.byref(is_log)))
+        card = card[:nv.value]
+        scopes = [sv[sp[f]:sp[f + 1]].copy() for f in range(nf.value)]
+        vp = np.concatenate([[0], np.cumsum([int(np.prod(card[s])) if len(s) else 1 for s in scopes])]).astype(np.int64)
+        values = [vals[vp[f]:vp[f + 1]].copy() for f in range(nf.value)]
+        self.src = W.Network(card.copy(), scopes, values, bool(is_log.value))
+        self.card = np.ascontiguousarray(card, np.int32)
+        self.n_vars = int(nv.value)
+        self.n_values = int(nvals.value)
+        self.value_offsets = vp
+
+    def read_uai_evidence(self, path):
+        """Evidence sets of a UAI evidence file: int32 [sets, n_vars], -1 = free."""
+        n = ctypes.c_int32()
+        _check(lib().tn_read_uai_evidence(os.fsencode(path), self.n_vars, _ptr(self.card, ctypes.c_int32), None, 0,
+                                          ctypes.byref(n)))
+        ev = np.full((max(1, n.value), max(1, self.n_vars)), -1, np.int32)
+        _check(lib().tn_read_uai_evidence(os.fsencode(path), self.n_vars, _ptr(self.card, ctypes.c_int32),
+                                          _ptr(ev, ctypes.c_int32), n.value, ctypes.byref(n)))
+        return ev[:n.value, :self.n_vars]
+
+    def read_uai_query(self, path):
+        """Variables of a UAI query file (in file order)."""
+        buf = np.zeros(max(1, self.n_vars), np.int32)
+        n = ctypes.c_int32()
+        _check(lib().tn_read_uai_query(os.fsencode(path), self.n_vars, _ptr(buf, ctypes.c_int32), buf.size,
+                                       ctypes.byref(n)))
+        return buf[:n.value].copy()
+
     def __init__(self, net):
         self.src = net
         sp, sv, vp, vals = net.flat()
@@ -190,7 +253,8 @@ class Network:
 def make_opts(semirings=SUM_PRODUCT | MAX_PLUS, evidence_mode=EVIDENCE_NONE, observed=None,
               query=None, planner=PLANNER_BEST, restarts=4, seed=0, max_log2_size=0.0,
               dtype=TN_F32, max_batch=1, use_graph=True, stream=None, tree=None,
-              want_factor_grad=False, host_only=False, fuse=True, autotune=False, batch_layout=0):
+              want_factor_grad=False, host_only=False, fuse=True, autotune=False, batch_layout=0,
+              joint_sets=None):
     o = PlanOpts()
     lib().tn_plan_opts_default(ctypes.byref(o))
     keep = []
@@ -224,6 +288,15 @@ def make_opts(semirings=SUM_PRODUCT | MAX_PLUS, evidence_mode=EVIDENCE_NONE, obs
     o.no_fuse = 0 if fuse else 1
     o.autotune = 1 if autotune else 0
     o.batch_layout = batch_layout
+    if joint_sets:
+        ptr = np.zeros(len(joint_sets) + 1, np.int64)
+        for k, st in enumerate(joint_sets):
+            ptr[k + 1] = ptr[k] + len(st)
+        jv = np.ascontiguousarray(np.concatenate([np.asarray(st, np.int32) for st in joint_sets]), np.int32)
+        keep += [ptr, jv]
+        o.joint_ptr = _ptr(ptr, ctypes.c_int64)
+        o.joint_vars = _ptr(jv, ctypes.c_int32)
+        o.n_joint = len(joint_sets)
     return o, keep
 
 
@@ -296,6 +369,40 @@ class Plan:
 
     def split_marginals(self, row):
         return [row[self.marg_cols[v]:self.marg_cols[v + 1]] for v in range(self.n_vars)]
+
+    def joint_marginals(self, evidence=None, batch=1):
+        """Returns (log Z [batch], per instance a list of tables, one per joint
+        set, shaped by the cards of the set's variables sorted ascending)."""
+        sets = [sorted(int(v) for v in st) for st in self.kw.get("joint_sets") or []]
+        sizes = [int(np.prod([int(self.card[v]) for v in st])) for st in sets]
+        ev = self._ev(evidence, batch)
+        lz = np.zeros(batch)
+        out = np.zeros((batch, max(1, sum(sizes))))
+        _check(lib().tn_joint_marginals(self.h, batch, _ptr(ev, ctypes.c_int32), _ptr(lz, ctypes.c_double),
+                                        _ptr(out, ctypes.c_double)))
+        res = []
+        for b in range(batch):
+            tabs, o = [], 0
+            for st, n in zip(sets, sizes):
+                tabs.append(out[b, o:o + n].reshape([int(self.card[v]) for v in st]))
+                o += n
+            res.append(tabs)
+        return lz, res
+
+    def factor_marginals(self, evidence=None, batch=1):
+        """Returns (log Z [batch], [batch, n_values] factor marginals laid out
+        as the network's values)."""
+        ev = self._ev(evidence, batch)
+        lz = np.zeros(batch)
+        out = np.zeros((batch, max(1, self.network.n_values)))
+        _check(lib().tn_factor_marginals(self.h, batch, _ptr(ev, ctypes.c_int32), _ptr(lz, ctypes.c_double),
+                                         _ptr(out, ctypes.c_double)))
+        return lz, out[:, :self.network.n_values]
+
+    def split_factors(self, row):
+        """A factor-marginal row split per factor (flat, scope order as loaded)."""
+        vp = self.network.value_offsets
+        return [row[vp[f]:vp[f + 1]] for f in range(len(vp) - 1)]
 
     def map(self, evidence=None, batch=1):
         ev = self._ev(evidence, batch)

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "libtn.so")
-SOURCES = ["tn_api.cpp", "tn_planner.cpp", "tn_kernels.hip"]
+SOURCES = ["tn_api.cpp", "tn_planner.cpp", "tn_uai.cpp", "tn_kernels.hip"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-result", "-I", os.path.join(HERE, "..", "include")]

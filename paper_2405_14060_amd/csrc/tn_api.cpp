@@ -34,6 +34,7 @@ using namespace tn;
 static thread_local std::string g_err;
 
 extern "C" const char *tn_last_error(void) { return g_err.c_str(); }
+void tn::set_last_error(const std::string &m) { g_err = m; }
 
 template <class F>
 static tn_status guard(F &&f) {
@@ -443,6 +444,17 @@ static void build_leaves(tn_plan_t *p, const tn_net *net) {
     p->leaf_var.push_back(v);
     p->leaf_factor.push_back(-1);
   }
+  // one unity tensor (all ones) per joint set, over its unobserved variables
+  for (const auto &set : p->joint_sets) {
+    Labels lab;
+    for (int v : set)
+      if (!(p->mode == TN_EVIDENCE_SLICED && p->is_obs[v])) lab.push_back(v);
+    if (lab.empty()) continue;
+    p->leaf_lab.push_back(lab);
+    p->leaf_kind.push_back(3);
+    p->leaf_var.push_back(-1);
+    p->leaf_factor.push_back(-1);
+  }
 }
 
 // gather map of factor f restricted to its unobserved variables (sorted),
@@ -795,14 +807,19 @@ static Schedule build_schedule(tn_plan_t *p, const std::vector<Op> &ops, bool al
         if (stage[i] == st && ops[i].seg >= 0 && ops[i].seg_kind == kind) L.ops.push_back(i);
       if (!L.ops.empty()) sc.launches.push_back(std::move(L));
     }
-    for (int i = 0; i < n; ++i)
-      if (stage[i] == st && ops[i].seg >= 0 && ops[i].seg_kind <= 2) {
+    for (int kind = 1; kind <= 2; ++kind) {  // carrier transforms: two independent segments per launch
+      std::vector<int> ids;
+      for (int i = 0; i < n; ++i)
+        if (stage[i] == st && ops[i].seg >= 0 && ops[i].seg_kind == kind) ids.push_back(i);
+      for (size_t j = 0; j < ids.size(); j += 2) {
         Launch L;
         L.seg = true;
-        L.seg_kind = ops[i].seg_kind;
-        L.ops.push_back(i);
+        L.seg_kind = kind;
+        L.ops.push_back(ids[j]);
+        if (j + 1 < ids.size()) L.ops.push_back(ids[j + 1]);
         sc.launches.push_back(std::move(L));
       }
+    }
     for (int semi = 0; semi < 2; ++semi)
       for (int cls = 0; cls < 4; ++cls) {  // one-lane-per-output forms, split reductions, dense, interleaved
         Launch L;
@@ -1229,8 +1246,30 @@ static void allocate(tn_plan_t *p, const tn_net *net) {
     const TensorBuf &A = p->T[(int)g.adj];
     g.slot = A.slot;
     g.adj = A.off;
+    const TensorBuf &Lf = p->T[(int)g.leaf];
+    g.leaf = Lf.off;
+    g.leaf_batched = Lf.batched;
+    g.leaf_bs = p->inter ? 1 : Lf.size;
+    g.leaf_es = Lf.batched && p->inter ? p->max_batch : 1;
+    g.adj_batched = A.batched;
+    g.adj_bs = p->inter ? 1 : A.size;
+    g.adj_es = A.batched && p->inter ? p->max_batch : 1;
   }
   p->d_grad_desc = dupload(p, p->grads);
+  if (!p->grads.empty()) p->d_fmarg = dalloc<double>(p, (size_t)p->max_batch * std::max<int64_t>(1, net->n_values));
+  for (auto &j : p->joint) {
+    if (j.adj < 0) continue;
+    const TensorBuf &A = p->T[(int)j.adj];
+    j.adj = A.off;
+    j.adj_batched = A.batched;
+    j.adj_bs = p->inter ? 1 : A.size;
+    j.adj_es = A.batched && p->inter ? p->max_batch : 1;
+  }
+  if (!p->joint.empty()) {
+    p->d_joint_desc = dupload(p, p->joint);
+    p->d_joint_tab = dupload(p, p->joint_tab);
+    p->d_joint = dalloc<double>(p, (size_t)p->max_batch * std::max(1, p->joint_row));
+  }
   auto fix_back = [&](TreeExec &t) {
     for (auto &s : t.back) {
       const IntBuf &b = p->IB[(int)s.arg];
@@ -1335,8 +1374,19 @@ static bool describe_segment(tn_plan_t *p, const std::vector<Op> &ops, const std
     }
     return off;
   };
-  sp.in_outer_fast = (!V[0].empty() && !O.empty() && V[0].back() == O.back()) ? 1 : 0;
-  sp.out_outer_fast = (!V[L].empty() && !O.empty() && V[L].back() == O.back()) ? 1 : 0;
+  // carrier labels faster than its fastest outer label (all local): the
+  // tile moves take them fastest, then the outer assignment; a count that is
+  // not a power of two takes every local entry fastest
+  auto lo_shift = [&](const Labels &Vc) {
+    int64_t n = 1;
+    for (int v : Vc)
+      if (v > O.back()) n *= card[v];
+    int sh = 0;
+    while ((int64_t(1) << sh) < n) ++sh;
+    return (int64_t(1) << sh) == n && sh <= 5 ? sh : 5;
+  };
+  sp.in_lo_shift = lo_shift(V[0]);
+  sp.out_lo_shift = lo_shift(V[L]);
   sp.inX = local_tab(Loc[0], V[0]);
   sp.outZ = local_tab(Loc[L], V[L]);
   sp.n_in0 = (int32_t)numel(Loc[0], card);
@@ -1581,8 +1631,8 @@ static void upload_segments(tn_plan_t *p) {
       a.outZ = p->d_tabs + sp.outZ;
       a.n_in0 = sp.n_in0;
       a.n_outL = sp.n_outL;
-      a.in_outer_fast = sp.in_outer_fast;
-      a.out_outer_fast = sp.out_outer_fast;
+      a.in_lo_shift = sp.in_lo_shift;
+      a.out_lo_shift = sp.out_lo_shift;
       a.lists = p->d_tabs + sp.list_off;
       a.n_steps = (int32_t)sp.steps.size();
       a.list_len = sp.list_len;
@@ -1624,9 +1674,10 @@ static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
   p->card = net->card;
   p->mode = o->evidence_mode;
   if (p->mode < 0 || p->mode > 2) throw TnError(TN_E_INVALID, "unknown evidence mode");
-  p->max_batch = p->mode == TN_EVIDENCE_INDICATOR ? std::max(1, o->max_batch) : 1;
+  p->max_batch = p->mode == TN_EVIDENCE_NONE ? 1 : std::max(1, o->max_batch);
+  p->batched_ev = p->mode == TN_EVIDENCE_INDICATOR || (p->mode == TN_EVIDENCE_SLICED && p->max_batch > 1);
   if (o->batch_layout < 0 || o->batch_layout > 2) throw TnError(TN_E_INVALID, "unknown batch layout");
-  p->inter = p->mode == TN_EVIDENCE_INDICATOR && p->max_batch > 1 &&
+  p->inter = p->batched_ev && p->max_batch > 1 &&
              (o->batch_layout == 2 || (o->batch_layout == 0 && o->dtype == TN_F32));
   if (p->inter) p->max_batch = (p->max_batch + kInterLanes - 1) / kInterLanes * kInterLanes;
   p->want_sum = (o->semiring_mask & TN_SUM_PRODUCT) != 0;
@@ -1643,9 +1694,30 @@ static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
       p->observed.push_back(v);
     }
   }
+  if (o->n_joint > 0) {
+    if (!o->joint_ptr || !o->joint_vars) throw TnError(TN_E_INVALID, "joint sets: NULL arrays");
+    if (o->query && o->n_query > 0) throw TnError(TN_E_UNSUPPORTED, "joint marginals in an MMAP plan");
+    for (int k = 0; k < o->n_joint; ++k) {
+      const int64_t b = o->joint_ptr[k], e = o->joint_ptr[k + 1];
+      if (b < 0 || e <= b) throw TnError(TN_E_INVALID, "joint set " + std::to_string(k) + " is empty or malformed");
+      std::vector<int> set;
+      double log2n = 0;
+      for (int64_t i = b; i < e; ++i) {
+        const int v = o->joint_vars[i];
+        if (v < 0 || v >= p->n_vars) throw TnError(TN_E_INVALID, "joint set variable out of range");
+        set.push_back(v);
+        log2n += std::log2((double)p->card[v]);
+      }
+      std::sort(set.begin(), set.end());
+      if (std::adjacent_find(set.begin(), set.end()) != set.end())
+        throw TnError(TN_E_INVALID, "joint set lists a variable twice");
+      if (log2n > 24) throw TnError(TN_E_TOO_LARGE, "joint set table above 2^24 entries");
+      p->joint_sets.push_back(std::move(set));
+    }
+  }
   if (o->query && o->n_query > 0) {
     p->is_mmap = true;
-    if (p->mode == TN_EVIDENCE_INDICATOR) throw TnError(TN_E_UNSUPPORTED, "MMAP with batched evidence");
+    if (p->batched_ev) throw TnError(TN_E_UNSUPPORTED, "MMAP with batched evidence");
     build_mmap(p, net);
     if (!o->host_only) allocate(p, net);
     return;
@@ -1660,11 +1732,12 @@ static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
     p->planner_used = -1;
   } else {
     PlanChoice pc = plan_tree(p->leaf_lab, p->card, {}, o->planner, o->restarts, o->seed,
-                              p->mode == TN_EVIDENCE_INDICATOR ? 0.0 : o->max_log2_size);
+                              p->batched_ev ? 0.0 : o->max_log2_size);
     // chains of nodes below the fused-segment size (2^12 outputs) in fewer levels
     p->pairs = rebalance_small_chains(p->leaf_lab, pc.pairs, {}, p->card, 11.0);
     p->stats = tree_stats(p->leaf_lab, p->pairs, {}, p->card);
     p->planner_used = pc.planner;
+    p->two_front = pc.two_front;
   }
   auto lab = node_labels(p->leaf_lab, p->pairs, {}, p->n_vars);
   if (p->inter) {
@@ -1684,7 +1757,7 @@ static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
     // sliced sum-product plan (log Z and sampling): the chosen variables are
     // fixed per slice like evidence; the tree over the leaves stays, its
     // labels lose the sliced variables
-    if (p->mode == TN_EVIDENCE_INDICATOR || p->want_max || p->want_grad)
+    if (p->batched_ev || p->want_max || p->want_grad)
       throw TnError(TN_E_UNSUPPORTED, "slicing: sum-product plans without batched evidence or gradients");
     p->sliced = choose_slices(p->leaf_lab, p->pairs, {}, p->card, o->max_log2_size);
     for (int v : p->sliced) fixed[v] = 1;
@@ -1701,17 +1774,20 @@ static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
   // leaf tensors and descriptors
   std::vector<int> leaf_sum(L, -1), leaf_max(L, -1);
   for (int i = 0; i < L; ++i) {
-    const bool bat = p->leaf_kind[i] == 2;
     LeafDesc d{};
-    d.kind = p->leaf_kind[i];
+    d.kind = p->leaf_kind[i] == 3 ? 1 : p->leaf_kind[i];  // joint-set unity tensors: constant ones
     d.var = p->leaf_var[i];
-    d.batched = bat;
     d.size = (int32_t)numel(p->leaf_lab[i], p->card);
     if (d.kind == 0) {
       const int f = p->leaf_factor[i];
       factor_gather(p, net, f, fixed, d.gmap, d.obs_begin, d.obs_end);
       d.src = net->val_off[f];
     }
+    // batched: indicator vectors, and under batched sliced evidence every
+    // factor sliced at an observed variable (one slice per instance)
+    const bool bat = p->leaf_kind[i] == 2 ||
+                     (p->mode == TN_EVIDENCE_SLICED && p->batched_ev && d.kind == 0 && d.obs_end > d.obs_begin);
+    d.batched = bat;
     if (p->want_sum) {
       leaf_sum[i] = new_tensor(p, p->leaf_lab[i], bat, true);
       LeafDesc s = d;
@@ -1742,7 +1818,7 @@ static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
       need[L + q] = need[p->pairs[q][0]] || need[p->pairs[q][1]];
     p->adj_tensor.assign(L + p->pairs.size(), -1);
     const int rootn = L + (int)p->pairs.size() - 1;
-    p->seed_tensor = new_tensor(p, p->T[t.root].lab, p->mode == TN_EVIDENCE_INDICATOR, true);
+    p->seed_tensor = new_tensor(p, p->T[t.root].lab, p->batched_ev, true);
     if (t.root != t.node_tensor[rootn]) {
       // root reduction: its adjoint is a broadcast of the seed
       int a = new_tensor(p, p->T[t.node_tensor[rootn]].lab, p->T[p->seed_tensor].batched, true);
@@ -1774,7 +1850,9 @@ static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
     }
     p->marg_row = col;
     for (int i = 0; i < L; ++i) {
-      if (p->leaf_kind[i] != 0) {
+      if (p->leaf_kind[i] == 3) {
+        continue;  // joint sets: below
+      } else if (p->leaf_kind[i] != 0) {
         MargDesc m{};
         m.adj = p->adj_tensor[i];
         m.leaf = leaf_sum[i];
@@ -1791,11 +1869,43 @@ static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
         g.gmap = ld.gmap;
         g.obs_begin = ld.obs_begin;
         g.obs_end = ld.obs_end;
+        g.leaf = leaf_sum[i];
+        int64_t full = 1;
+        for (int v : net->scope[f]) full *= p->card[v];
+        g.full = (int32_t)full;
         p->grads.push_back(g);
       }
     }
-    if (p->mode != TN_EVIDENCE_INDICATOR) build_sampling(p, t);
-    if (!p->opts.no_fuse && p->mode != TN_EVIDENCE_INDICATOR) build_fusion(p, need, L);
+    // joint sets: the unity tensor of each (leaves after the unity vectors,
+    // in set order) and the layout of its table
+    {
+      int li = 0;
+      while (li < L && p->leaf_kind[li] != 3) ++li;
+      int col = 0;
+      for (const auto &set : p->joint_sets) {
+        JointDesc j;
+        j.out = col;
+        j.v_begin = (int32_t)(p->joint_tab.size() / 3);
+        Labels lab;
+        for (int v : set)
+          if (!(p->mode == TN_EVIDENCE_SLICED && p->is_obs[v])) lab.push_back(v);
+        int64_t n_full = 1;
+        for (int v : set) {
+          n_full *= p->card[v];
+          p->joint_tab.push_back(v);
+          p->joint_tab.push_back(p->card[v]);
+          p->joint_tab.push_back(has(lab, v) ? (int32_t)stride_in(lab, v, p->card) : -1);
+        }
+        j.v_end = (int32_t)(p->joint_tab.size() / 3);
+        j.n_full = (int32_t)n_full;
+        if (!lab.empty()) j.adj = p->adj_tensor[li++];  // tensor id until allocation
+        p->joint.push_back(j);
+        col += (int)n_full;
+      }
+      p->joint_row = col;
+    }
+    if (!p->batched_ev) build_sampling(p, t);
+    if (!p->opts.no_fuse && !p->batched_ev) build_fusion(p, need, L);
   }
   if (p->want_max) {
     TreeExec &t = p->max_tree;
@@ -1842,6 +1952,8 @@ extern "C" tn_status tn_plan_info_get(const tn_plan_t *p, tn_plan_info *info) {
     info->bytes_fwd = p->stats.bytes;
     info->n_sliced = (int32_t)p->sliced.size();
     info->planner_used = p->planner_used;
+    info->two_front = p->two_front ? 1 : 0;
+    if (!p->pairs.empty()) stage_time(p->leaf_lab, p->pairs, {}, p->card, &info->n_levels);
     info->device_bytes = p->device_bytes;
     if (p->opts.host_only)  // planned only: the float arena the plan would hold
       for (const auto &t : p->T) info->device_bytes += 4 * t.size * (t.batched ? p->max_batch : 1);
@@ -1853,9 +1965,11 @@ extern "C" tn_status tn_plan_info_get(const tn_plan_t *p, tn_plan_info *info) {
     info->n_launches_fwd = count(p->sched_fwd);
     info->n_launches_bwd = count(p->sched_bwd);
     info->n_launches_max = count(p->sched_max);
-    if (p->opts.host_only) {  // schedules are built at allocation: count ops
-      info->n_launches_fwd = (int32_t)(p->fused ? p->ffwd.size() : p->sum_tree.ops.size());
-      info->n_launches_bwd = (int32_t)(p->fused ? p->fbwd.size() : p->bwd.size());
+    if (p->opts.host_only) {  // schedules are built at allocation: build them here (host only)
+      tn_plan_t *q = const_cast<tn_plan_t *>(p);
+      info->n_launches_fwd = count(p->fused ? build_schedule(q, p->ffwd, false) : build_schedule(q, p->sum_tree.ops, false));
+      info->n_launches_bwd = count(p->fused ? build_schedule(q, p->fbwd, true) : build_schedule(q, p->bwd, true));
+      info->n_launches_max = count(build_schedule(q, p->max_tree.ops, false));
     } else if (p->fused) {
       info->n_launches_fwd = count(p->sched_ffwd);
       info->n_launches_bwd = count(p->sched_fbwd);
@@ -1919,8 +2033,9 @@ extern "C" tn_status tn_plan_tree_host(const tn_net *net, const tn_plan_opts *op
         p.is_obs[o.observed[i]] = 1;
       }
     build_leaves(&p, net);
+    const bool batched = p.mode == TN_EVIDENCE_INDICATOR || (p.mode == TN_EVIDENCE_SLICED && o.max_batch > 1);
     PlanChoice pc = plan_tree(p.leaf_lab, p.card, {}, o.planner, o.restarts, o.seed,
-                              p.mode == TN_EVIDENCE_INDICATOR ? 0.0 : o.max_log2_size);
+                              batched ? 0.0 : o.max_log2_size);
     if (n_pairs) *n_pairs = (int32_t)pc.pairs.size();
     if (n_leaves) *n_leaves = (int32_t)p.leaf_lab.size();
     for (int i = 0; i < (int)pc.pairs.size() && i < cap; ++i) {
@@ -1937,6 +2052,8 @@ extern "C" tn_status tn_plan_tree_host(const tn_net *net, const tn_plan_opts *op
       stats->flops_fwd = pc.stats.flops;
       stats->bytes_fwd = pc.stats.bytes;
       stats->planner_used = pc.planner;
+      stats->two_front = pc.two_front ? 1 : 0;
+      if (!pc.pairs.empty()) stage_time(p.leaf_lab, pc.pairs, {}, p.card, &stats->n_levels);
       if (o.max_log2_size > 0) {
         Labels sl = choose_slices(p.leaf_lab, pc.pairs, {}, p.card, o.max_log2_size);
         stats->n_sliced = (int32_t)sl.size();
@@ -1958,9 +2075,16 @@ void run_sched(tn_plan_t *p, const std::vector<Op> &ops, const Schedule &sc) {
   for (const Launch &L : sc.launches) {
     if (L.seg) {
       const Op &op = ops[L.ops[0]];
+      const int seg2 = L.ops.size() > 1 ? ops[L.ops[1]].seg : -1;
       switch (L.seg_kind) {
-        case 1: launch_seg_fwd(p->seg_fwd_h[op.seg], p->stream); break;
-        case 2: launch_seg_bwd(p->seg_bwd_h[op.seg], p->stream); break;
+        case 1:
+          if (seg2 >= 0) launch_seg_fwd2(p->seg_fwd_h[op.seg], p->seg_fwd_h[seg2], p->stream);
+          else launch_seg_fwd(p->seg_fwd_h[op.seg], p->stream);
+          break;
+        case 2:
+          if (seg2 >= 0) launch_seg_bwd2(p->seg_bwd_h[op.seg], p->seg_bwd_h[seg2], p->stream);
+          else launch_seg_bwd(p->seg_bwd_h[op.seg], p->stream);
+          break;
         case 3: launch_seg_mat(p->d_seg_fwd, L.d_ids, (int)L.ops.size(), L.lds, p->stream); break;
         default: launch_seg_fin(p->d_seg_bwd, L.d_ids, (int)L.ops.size(), L.lds, p->stream); break;
       }
@@ -2042,6 +2166,11 @@ static void upload_evidence(tn_plan_t *p, int batch, const int32_t *ev) {
         throw TnError(TN_E_INVALID, "evidence must give exactly the plan's observed variables");
       h[(size_t)b * p->n_vars + v] = e;
     }
+  // sliced leaves gather at the observed values of every row, so rows past
+  // the batch repeat the first one
+  if (p->mode == TN_EVIDENCE_SLICED)
+    for (int b = std::max(1, batch); b < p->max_batch; ++b)
+      std::copy(h.begin(), h.begin() + p->n_vars, h.begin() + (size_t)b * p->n_vars);
   hip_check(hipMemcpyAsync(p->d_evidence, h.data(), h.size() * 4, hipMemcpyHostToDevice, p->stream), "evidence upload");
   hip_check(hipStreamSynchronize(p->stream), "evidence upload");
 }
@@ -2096,7 +2225,7 @@ static double log_sum_exp(const std::vector<double> &v) {
 
 static void check_batch(tn_plan_t *p, int batch) {
   if (batch < 1) throw TnError(TN_E_INVALID, "batch must be >= 1");
-  if (p->mode == TN_EVIDENCE_INDICATOR && batch > p->max_batch) throw TnError(TN_E_INVALID, "batch exceeds max_batch");
+  if (p->batched_ev && batch > p->max_batch) throw TnError(TN_E_INVALID, "batch exceeds max_batch");
   if (p->mode == TN_EVIDENCE_NONE && batch != 1) throw TnError(TN_E_INVALID, "mode NONE takes batch 1");
 }
 
@@ -2114,14 +2243,17 @@ static void forward_sum(tn_plan_t *p, bool with_bwd, bool allow_fused = true) {
       if (fz) run_sched(p, p->fbwd, p->sched_fbwd);
       else run_sched(p, p->bwd, p->sched_bwd);
       launch_marg(p->arena, p->d_marg_desc, (int)p->marg.size(), p->max_batch, p->marg_row, p->d_marg, p->stream);
+      launch_joint(p->arena, p->d_joint_desc, (int)p->joint.size(), p->d_joint_tab, p->d_evidence, p->n_vars,
+                   p->max_batch, p->joint_row, p->d_joint, p->stream);
     }
   });
 }
 
 template <class F>
 static void per_instance(tn_plan_t *p, int batch, const int32_t *ev, F &&f) {
-  // modes NONE / INDICATOR: one pass over the batch; SLICED: one pass each
-  if (p->mode == TN_EVIDENCE_SLICED) {
+  // one pass over the batch, except SLICED plans built for one instance:
+  // one pass each
+  if (!p->batched_ev && p->mode == TN_EVIDENCE_SLICED) {
     for (int b = 0; b < batch; ++b) f(b, 1, ev ? ev + (int64_t)b * p->n_vars : nullptr);
   } else {
     f(0, batch, ev);
@@ -2165,10 +2297,62 @@ extern "C" tn_status tn_marginals(tn_plan_t *p, int32_t batch, const int32_t *ev
                                hipMemcpyDeviceToHost, p->stream), "D2H");
       hip_check(hipStreamSynchronize(p->stream), "marginals");
       if (p->mode == TN_EVIDENCE_SLICED)
-        for (int v : p->observed) {
-          double *row = marg + (int64_t)b0 * p->marg_row + p->marg_col[v];
-          for (int x = 0; x < p->card[v]; ++x) row[x] = x == ev[v] ? 1.0 : 0.0;
-        }
+        for (int b = 0; b < nb; ++b)
+          for (int v : p->observed) {
+            double *row = marg + (int64_t)(b0 + b) * p->marg_row + p->marg_col[v];
+            const int e = ev[(int64_t)b * p->n_vars + v];
+            for (int x = 0; x < p->card[v]; ++x) row[x] = x == e ? 1.0 : 0.0;
+          }
+    });
+    if (logz) std::copy(lz.begin(), lz.end(), logz);
+    for (int b = 0; b < batch; ++b)
+      if (!(lz[b] > -INFINITY)) throw TnError(TN_E_ZERO_EVIDENCE, "p(e) = 0 for instance " + std::to_string(b));
+  });
+}
+
+extern "C" tn_status tn_joint_marginals(tn_plan_t *p, int32_t batch, const int32_t *evidence, double *logz,
+                                        double *joint) {
+  return guard([&] {
+    if (!p || !joint) throw TnError(TN_E_INVALID, "NULL argument");
+    if (!p->want_sum || p->is_mmap) throw TnError(TN_E_UNSUPPORTED, "plan has no sum-product pass");
+    if (p->joint.empty()) throw TnError(TN_E_UNSUPPORTED, "plan has no joint sets");
+    if (!p->sliced.empty()) throw TnError(TN_E_UNSUPPORTED, "joint marginals of sliced plans");
+    check_batch(p, batch);
+    std::vector<double> lz(batch);
+    per_instance(p, batch, evidence, [&](int b0, int nb, const int32_t *ev) {
+      upload_evidence(p, nb, ev);
+      forward_sum(p, true);
+      hip_check(hipMemcpyAsync(lz.data() + b0, p->d_out, nb * sizeof(double), hipMemcpyDeviceToHost, p->stream), "D2H");
+      hip_check(hipMemcpyAsync(joint + (int64_t)b0 * p->joint_row, p->d_joint,
+                               (size_t)nb * p->joint_row * sizeof(double), hipMemcpyDeviceToHost, p->stream), "D2H");
+      hip_check(hipStreamSynchronize(p->stream), "joint marginals");
+    });
+    if (logz) std::copy(lz.begin(), lz.end(), logz);
+    for (int b = 0; b < batch; ++b)
+      if (!(lz[b] > -INFINITY)) throw TnError(TN_E_ZERO_EVIDENCE, "p(e) = 0 for instance " + std::to_string(b));
+  });
+}
+
+extern "C" tn_status tn_factor_marginals(tn_plan_t *p, int32_t batch, const int32_t *evidence, double *logz,
+                                         double *fmarg) {
+  return guard([&] {
+    if (!p || !fmarg) throw TnError(TN_E_INVALID, "NULL argument");
+    if (!p->want_sum || p->is_mmap) throw TnError(TN_E_UNSUPPORTED, "plan has no sum-product pass");
+    if (!p->want_grad) throw TnError(TN_E_UNSUPPORTED, "plan built without want_factor_grad");
+    if (!p->sliced.empty()) throw TnError(TN_E_UNSUPPORTED, "factor marginals of sliced plans");
+    check_batch(p, batch);
+    const int64_t nv = p->net_src->n_values;
+    std::vector<double> lz(batch);
+    per_instance(p, batch, evidence, [&](int b0, int nb, const int32_t *ev) {
+      upload_evidence(p, nb, ev);
+      forward_sum(p, true);
+      launch_factor_marg(p->arena, p->d_grad_desc, (int)p->grads.size(), p->d_gmap, p->d_obs, p->d_evidence,
+                         p->n_vars, nb, nv, p->d_fmarg, p->stream);
+      hip_check(hipGetLastError(), "factor marginal launch");
+      hip_check(hipMemcpyAsync(lz.data() + b0, p->d_out, nb * sizeof(double), hipMemcpyDeviceToHost, p->stream), "D2H");
+      hip_check(hipMemcpyAsync(fmarg + b0 * nv, p->d_fmarg, (size_t)nb * nv * sizeof(double), hipMemcpyDeviceToHost,
+                               p->stream), "D2H");
+      hip_check(hipStreamSynchronize(p->stream), "factor marginals");
     });
     if (logz) std::copy(lz.begin(), lz.end(), logz);
     for (int b = 0; b < batch; ++b)
@@ -2268,7 +2452,7 @@ static void sample_sliced(tn_plan_t *p, const int32_t *evidence, int64_t n, uint
 static void check_sample_args(tn_plan_t *p, int64_t n, int32_t *samples) {
   if (!p || (!samples && n > 0)) throw TnError(TN_E_INVALID, "NULL argument");
   if (n < 0) throw TnError(TN_E_INVALID, "negative sample count");
-  if (!p->want_sum || p->is_mmap || p->mode == TN_EVIDENCE_INDICATOR)
+  if (!p->want_sum || p->is_mmap || p->batched_ev)
     throw TnError(TN_E_UNSUPPORTED, "sampling needs a sum-product plan without batched evidence");
 }
 
@@ -2352,8 +2536,8 @@ extern "C" tn_status tn_logZ_dev(tn_plan_t *p, const int32_t *evidence, const fl
                                  float *grad_dev) {
   return guard([&] {
     if (!p || !values_dev || !logz_dev) throw TnError(TN_E_INVALID, "NULL argument");
-    if (!p->want_sum || p->is_mmap || p->mode == TN_EVIDENCE_INDICATOR)
-      throw TnError(TN_E_UNSUPPORTED, "tn_logZ_dev needs a sum-product plan in mode NONE or SLICED");
+    if (!p->want_sum || p->is_mmap || p->batched_ev)
+      throw TnError(TN_E_UNSUPPORTED, "tn_logZ_dev needs a sum-product plan in mode NONE or SLICED (one instance)");
     if (grad_dev && !p->want_grad) throw TnError(TN_E_UNSUPPORTED, "plan built without want_factor_grad");
     if (!p->sliced.empty()) throw TnError(TN_E_UNSUPPORTED, "tn_logZ_dev on a sliced plan");
     const tn_net *net = p->net_src;
@@ -2628,7 +2812,8 @@ static tn_status profile_impl(tn_plan_t *p, int32_t task, int32_t batch, const i
       hip_check(hipStreamSynchronize(p->stream), "slice");
     } else {
       check_batch(p, batch);
-      if (p->mode == TN_EVIDENCE_SLICED && batch != 1) throw TnError(TN_E_INVALID, "profile one instance at a time");
+      if (p->mode == TN_EVIDENCE_SLICED && !p->batched_ev && batch != 1)
+        throw TnError(TN_E_INVALID, "profile one instance at a time");
       upload_evidence(p, batch, evidence);
     }
     // launch list: (kind, flops, bytes, launcher)

@@ -27,6 +27,9 @@ struct tn_net {
 
 namespace tn {
 
+// The thread-local message returned by tn_last_error().
+void set_last_error(const std::string &m);
+
 using Labels = std::vector<int>;  // variable ids, sorted ascending
 using Pair = std::array<int, 2>;
 
@@ -54,11 +57,22 @@ struct PlanChoice {
   std::vector<Pair> pairs;
   TreeStats stats;
   int planner = 0;
+  bool two_front = false;  // the two-front variant of the planner's order won
 };
 
+// Time model of a tree under the stage schedule (contractions grouped by
+// level, a level costs its slowest node): sum over levels of
+// max(launch cost + multiply-adds / rate).  n_levels (optional) = levels.
+static constexpr double kStageLaunchSeconds = 4e-6;
+static constexpr double kStageMacRate = 2e13;
+double stage_time(const std::vector<Labels> &leaves, const std::vector<Pair> &pairs, const Labels &out,
+                  const std::vector<int> &card, int *n_levels);
+
 // Choose a contraction tree over the leaves; labels in `out` are never
-// eliminated.  `strategy` is a TN_PLANNER_* value.  Candidates are ranked by
-// (largest intermediate, work); with a slicing cap (cap > 0) a candidate that
+// eliminated.  `strategy` is a TN_PLANNER_* value.  Without a slicing cap,
+// candidates (every order and its two-front variant) are ranked by (largest
+// intermediate to half a power of two, stage_time); with a cap (cap > 0)
+// by (largest intermediate, work), and a candidate that
 // exceeds it is ranked by its total work once sliced below the cap (the
 // work of one slice plus a launch cost per node, times the number of
 // slices), so that a tree with larger intermediates but much less sliced
@@ -217,14 +231,22 @@ struct SegArgs {
   int32_t n_steps = 0;
   const int32_t *lists = nullptr;  // the steps' CSR lists (offsets in SegStep are relative)
   int32_t list_len = 0;            // int32 entries of the lists
-  int32_t in_outer_fast = 0;     // the input carrier's stride-1 label is an outer label
-  int32_t out_outer_fast = 0;    // same for the output carrier
+  int32_t in_lo_shift = 5;       // log2 of the input carrier's local entries below its fastest
+                                 // outer label (tile load order: those, then outer, then the rest)
+  int32_t out_lo_shift = 5;      // same for the output carrier
   int32_t mat_lds = 0, fin_lds = 0;  // floats of LDS of the sweep kernels
   int32_t prec = 0;              // matrix-core operands: 0 FP32, 1 BF16, 2 FP16 (FP32 accumulation)
 };
 // carrier kernels: the arguments are passed by value
 void launch_seg_fwd(const SegArgs &a, void *stream);
 void launch_seg_bwd(const SegArgs &a, void *stream);
+// two independent segments (same precision) in one launch
+struct SegPair {
+  SegArgs a[2];
+  uint32_t split = 0;  // workgroups of the first segment
+};
+void launch_seg_fwd2(const SegArgs &a, const SegArgs &b, void *stream);
+void launch_seg_bwd2(const SegArgs &a, const SegArgs &b, void *stream);
 // one workgroup per listed segment; lds_floats = the largest mat_lds / fin_lds of them
 void launch_seg_mat(const SegArgs *d_base, const int32_t *d_ids, int n, int lds_floats, void *stream);
 void launch_seg_fin(const SegArgs *d_base, const int32_t *d_ids, int n, int lds_floats, void *stream);
@@ -283,11 +305,36 @@ struct GradDesc {
   int64_t dst;       // offset of the factor in the gradient array
   int32_t gmap;      // gather map of the leaf (leaf element -> table entry)
   int32_t obs_begin, obs_end;
+  int64_t leaf;      // float offset of the factor leaf (sliced table)
+  int32_t full;      // entries of the factor's whole table
+  int32_t adj_batched;
+  int64_t adj_bs, adj_es;  // instance and element strides of the adjoint
+  int32_t leaf_batched;    // the leaf holds one slice per instance (batched sliced evidence)
+  int64_t leaf_bs, leaf_es;
 };
 void launch_factor_grad(const float *arena, const GradDesc *d, int n, const int32_t *gmap,
                         const int32_t *obs, const int32_t *evidence, const int32_t *ex,
                         const float *root, int root_slot, int64_t n_values, float *grad,
                         void *stream);
+
+// Factor marginals T_f Tbar_f / sum over the leaf, scattered into the
+// factor's whole table (zeros elsewhere): out[b * row + dst + entry], FP64.
+void launch_factor_marg(const float *arena, const GradDesc *d, int n, const int32_t *gmap, const int32_t *obs,
+                        const int32_t *evidence, int n_vars, int batch, int64_t row, double *out, void *stream);
+
+// Joint marginal of a variable set from its unity tensor's adjoint.  The
+// set's variables (sorted) are (var, card, stride of the variable in the
+// unity tensor, -1 if observed and sliced out) triples at tab[3 * v_begin ..].
+struct JointDesc {
+  int64_t adj = -1;          // float offset of the unity tensor's adjoint (-1: every variable sliced out)
+  int64_t adj_bs = 0, adj_es = 1;
+  int32_t adj_batched = 0;
+  int32_t out = 0;           // column of the set's table in the joint row
+  int32_t n_full = 1;        // entries of the table over the whole set
+  int32_t v_begin = 0, v_end = 0;
+};
+void launch_joint(const float *arena, const JointDesc *d, int n, const int32_t *tab, const int32_t *evidence,
+                  int n_vars, int batch, int row, double *out, void *stream);
 
 // Argmax readout: steps run level by level (the steps of a level in
 // parallel); each reads x at its input labels, fetches an argmax index and

@@ -133,6 +133,8 @@ __device__ __forceinline__ int32_t tab_off(const Tab2 &t, uint32_t i, uint32_t n
 // --------------------------------------------------------------------------
 // generic contraction, one lane per output element
 // --------------------------------------------------------------------------
+static constexpr int kMapU = 4;  // outputs per lane and pass of the generic form
+
 template <int SEMI, bool HASY>
 __device__ __forceinline__ void map_body(const ContractArgs &a, const int b, const uint32_t blk,
                                          const uint32_t nblk) {
@@ -161,9 +163,11 @@ __device__ __forceinline__ void map_body(const ContractArgs &a, const int b, con
   const Tab2 oX = a.oX, oY = a.oY;
   const uint32_t nOl = a.nOl;
   const int osh = (nOl & (nOl - 1)) == 0 ? __builtin_ctz(nOl) : -1;
-  float lmax = 0.f;
-  for (uint32_t o = blk * kBlock + threadIdx.x; o < n_out; o += nblk * kBlock) {
-    int32_t xo, zo, yo;
+  // kMapU outputs per lane and pass, kMapU grid strides apart (each of them
+  // coalesced across the wave), their operand loads issued together so that
+  // several are in flight per lane; lanes past the end clamp to the last
+  // output (loads stay in range) and store nothing
+  auto offsets = [&](uint32_t o, int32_t &xo, int32_t &yo, int32_t &zo) {
     if (oord) {
       const uint32_t oh = osh >= 0 ? o >> osh : o / nOl, ol = o - oh * nOl;
       xo = oX.hi[oh] + oX.lo[ol];
@@ -188,39 +192,82 @@ __device__ __forceinline__ void map_body(const ContractArgs &a, const int b, con
         if (HASY) yo += cY.hi[ch] + cY.lo[cl];
       }
     }
+  };
+  float lmax = 0.f;
+  const uint32_t step = nblk * kBlock;
+  for (uint32_t o0 = blk * kBlock + threadIdx.x; o0 < n_out; o0 += kMapU * step) {
+    int32_t xo[kMapU], yo[kMapU], zo[kMapU];
+    bool live[kMapU];
+#pragma unroll
+    for (int u = 0; u < kMapU; ++u) {
+      const uint32_t o = o0 + u * step;
+      live[u] = o < n_out;
+      offsets(live[u] ? o : n_out - 1, xo[u], yo[u], zo[u]);
+    }
     if (SEMI == SEMI_SUM) {
-      float acc = 0.f;
+      float acc[kMapU];
+#pragma unroll
+      for (int u = 0; u < kMapU; ++u) acc[u] = 0.f;
       for (uint32_t sh = 0; sh < nSh; ++sh) {
-        const int32_t xs = xo + sXt.hi[sh];
-        const int32_t ys = HASY ? yo + sYt.hi[sh] : 0;
+        const int32_t xs = sXt.hi[sh];
+        const int32_t ys = HASY ? sYt.hi[sh] : 0;
         for (uint32_t sl = 0; sl < nSl; ++sl) {
-          const float xv = X[xs + sXt.lo[sl]] * sx;
-          if (HASY)
-            acc = fmaf(xv, Y[ys + sYt.lo[sl]] * sy, acc);
-          else
-            acc += xv;
-        }
-      }
-      Z[zo] = acc;
-      lmax = fmaxf(lmax, acc);
-    } else {
-      float best = -INFINITY;
-      int32_t bi = 0;
-      uint32_t s = 0;
-      for (uint32_t sh = 0; sh < nSh; ++sh) {
-        const int32_t xs = xo + sXt.hi[sh];
-        const int32_t ys = HASY ? yo + sYt.hi[sh] : 0;
-        for (uint32_t sl = 0; sl < nSl; ++sl, ++s) {
-          float v = X[xs + sXt.lo[sl]];
-          if (HASY) v = v + Y[ys + sYt.lo[sl]];
-          if (s == 0 || v > best) {
-            best = v;
-            bi = (int32_t)s;
+          const int32_t xl = xs + sXt.lo[sl], yl = HASY ? ys + sYt.lo[sl] : 0;
+          float xv[kMapU], yv[kMapU];
+#pragma unroll
+          for (int u = 0; u < kMapU; ++u) {
+            xv[u] = X[xo[u] + xl];
+            if (HASY) yv[u] = Y[yo[u] + yl];
+          }
+#pragma unroll
+          for (int u = 0; u < kMapU; ++u) {
+            if (HASY)
+              acc[u] = fmaf(xv[u] * sx, yv[u] * sy, acc[u]);
+            else
+              acc[u] += xv[u] * sx;
           }
         }
       }
-      Z[zo] = best;
-      I[zo] = bi;
+#pragma unroll
+      for (int u = 0; u < kMapU; ++u)
+        if (live[u]) {
+          Z[zo[u]] = acc[u];
+          lmax = fmaxf(lmax, acc[u]);
+        }
+    } else {
+      float best[kMapU];
+      int32_t bi[kMapU];
+#pragma unroll
+      for (int u = 0; u < kMapU; ++u) {
+        best[u] = -INFINITY;
+        bi[u] = 0;
+      }
+      uint32_t s = 0;
+      for (uint32_t sh = 0; sh < nSh; ++sh) {
+        const int32_t xs = sXt.hi[sh];
+        const int32_t ys = HASY ? sYt.hi[sh] : 0;
+        for (uint32_t sl = 0; sl < nSl; ++sl, ++s) {
+          const int32_t xl = xs + sXt.lo[sl], yl = HASY ? ys + sYt.lo[sl] : 0;
+          float v[kMapU];
+#pragma unroll
+          for (int u = 0; u < kMapU; ++u) {
+            v[u] = X[xo[u] + xl];
+            if (HASY) v[u] = v[u] + Y[yo[u] + yl];
+          }
+#pragma unroll
+          for (int u = 0; u < kMapU; ++u)
+            if (s == 0 || v[u] > best[u]) {
+              best[u] = v[u];
+              bi[u] = (int32_t)s;
+            }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kMapU; ++u)
+        if (live[u]) {
+          Z[zo[u]] = best[u];
+          I[zo[u]] = bi[u];
+        }
     }
   }
   if (SEMI == SEMI_SUM) {
@@ -1602,10 +1649,11 @@ uint32_t map_blocks(const ContractArgs &a) {
   uint32_t blocks = (n_out + kBlock - 1) / kBlock;
   // Grid-stride launches of about 8 workgroups per CU, except over many
   // outputs (>= 2^22), where one pass per lane (four rows per lane in the
-  // row form) leaves the overlap of memory latency to the hardware's wave
-  // dispatch: measured on 2^24..2^27-row contractions, a long grid-stride
-  // loop per wave ran at 1.3-1.6 TB/s, one pass per lane 1.7-2.2 TB/s.
-  if (n_out >= (1u << 22)) return a.kind == 1 ? (blocks + 3) / 4 : blocks;
+  // row form, four outputs per lane in the generic form) leaves the overlap
+  // of memory latency to the hardware's wave dispatch: measured on
+  // 2^24..2^27-row contractions, a long grid-stride loop per wave ran at
+  // 1.3-1.6 TB/s, one pass per lane 1.7-2.2 TB/s.
+  if (n_out >= (1u << 22)) return (blocks + 3) / 4;  // the row form's rows, the generic form's kMapU outputs
   return blocks > 2048u ? 2048u : blocks;
 }
 
@@ -1721,16 +1769,21 @@ struct SegShared {
   int32_t exX, exG, exM;  // workgroup 0: the operands' exponents (for the output's exponent)
 };
 
-__device__ __forceinline__ void seg_prologue(const SegArgs &a, uint32_t o0, bool want_g, SegShared &sh) {
+// M into LDS (zero-padded to 32 x 32), one entry per thread
+__device__ __forceinline__ void seg_stage_m(const SegArgs &a, SegShared &sh) {
   const int t = threadIdx.x;
-  const int wv = __builtin_amdgcn_readfirstlane(t) >> 6;  // wave index, uniform
+  const int r = t >> 5, c = t & 31;
+  const float x = ((gcfloat *)(a.arena + a.M))[min(r, a.n_outL - 1) * a.n_in0 + min(c, a.n_in0 - 1)];
+  sh.m[r * (kSegMaxLocal + 1) + c] = (r < a.n_outL && c < a.n_in0) ? x : 0.f;
+}
+static_assert(kSegThreads == kSegMaxLocal * kSegMaxLocal, "one M entry per thread");
+
+// The rest of the prologue, by eight waves (wave index wv in 0..7 within
+// them): outer offsets, local offsets, operand maxima, exponents.
+__device__ __forceinline__ void seg_roles(const SegArgs &a, uint32_t blk, bool want_g, SegShared &sh, int wv) {
+  const uint32_t o0 = blk * kSegOB;
+  const int t = threadIdx.x;
   const int l = t & 63;
-  // M, one entry per thread
-  {
-    const int r = t >> 5, c = t & 31;
-    const float x = ((gcfloat *)(a.arena + a.M))[min(r, a.n_outL - 1) * a.n_in0 + min(c, a.n_in0 - 1)];
-    sh.m[r * (kSegMaxLocal + 1) + c] = (r < a.n_outL && c < a.n_in0) ? x : 0.f;
-  }
   if (wv < 4) {  // outer offsets: waves 0-1 the input carrier, 2-3 the output carrier
     const bool in = wv < 2;
     const int tt = t & (kSegOB - 1);
@@ -1754,11 +1807,17 @@ __device__ __forceinline__ void seg_prologue(const SegArgs &a, uint32_t o0, bool
     const uint32_t v = ((gu32 *)a.mx)[l * a.mx_stride + slot];
     const int k = max_exponent(__float_as_uint(wave_max(__uint_as_float(v))));
     if (l == 0) (wv == 5 ? sh.kx : sh.kg) = k;
-  } else if (wv == 7 && blockIdx.x == 0 && l == 0) {  // read here, not after the stores
+  } else if (wv == 7 && blk == 0 && l == 0) {  // read here, not after the stores
     sh.exX = a.ex[a.slotX];
     sh.exM = a.ex[a.slotM];
     if (want_g) sh.exG = a.ex[a.slotG];
   }
+}
+
+__device__ __forceinline__ void seg_prologue(const SegArgs &a, uint32_t blk, bool want_g, SegShared &sh) {
+  seg_stage_m(a, sh);
+  const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x) >> 6;  // wave index, uniform
+  if (wv < 8) seg_roles(a, blk, want_g, sh, wv);
 }
 
 // Move a tile (kSegMaxLocal entries x kSegOB outer assignments) between a
@@ -1771,39 +1830,53 @@ __device__ __forceinline__ void seg_prologue(const SegArgs &a, uint32_t o0, bool
 static constexpr int kSegIter = kSegMaxLocal * kSegOB / kSegThreads;
 
 
-// (entry, outer assignment) of task t
-template <bool OUTER_FAST>
-__device__ __forceinline__ int2 seg_task(int t) {
-  if (OUTER_FAST) return make_int2(t / kSegOB, t % kSegOB);
-  return make_int2(t % kSegMaxLocal, t / kSegMaxLocal);
+// (entry, outer assignment) of task t.  The carrier's labels below its
+// fastest outer label (2^ls local entries, the fastest ones of the local
+// index) vary fastest, then the outer assignment, then the other local
+// entries: consecutive threads then take consecutive addresses of the
+// carrier (runs of 2^ls x kSegOB floats when the block's outer labels are
+// the carrier's next-fastest ones).
+__device__ __forceinline__ int2 seg_task(int t, int ls) {
+  const int l = t & ((1 << ls) - 1);
+  const int o = (t >> ls) & (kSegOB - 1);
+  const int h = t >> (ls + 7);
+  return make_int2((h << ls) | l, o);
 }
+static_assert(kSegOB == 128, "seg_task decodes 7 bits of outer assignment");
 
-template <bool OUTER_FAST>
-__device__ __forceinline__ void seg_load_t(const float *src, const int32_t *off, const int32_t *loc, int n,
-                                           float *tile, float scale) {
+// global -> registers (entries past n and outer assignments past nO read 0)
+__device__ __forceinline__ void seg_fetch(const float *src, const int32_t *off, const int32_t *loc, int n, int ls,
+                                          float (&v)[kSegIter]) {
   const gfloat *g = (const gfloat *)src;
-  float v[kSegIter];
 #pragma unroll
   for (int k = 0; k < kSegIter; ++k) {
-    const int2 jo = seg_task<OUTER_FAST>(threadIdx.x + k * kSegThreads);
+    const int2 jo = seg_task(threadIdx.x + k * kSegThreads, ls);
     const int32_t oo = off[jo.y];
     v[k] = (jo.x < n && oo >= 0) ? g[(uint32_t)(oo + loc[jo.x])] : 0.f;
   }
+}
+// registers -> LDS tile, scaled
+__device__ __forceinline__ void seg_stash(const float (&v)[kSegIter], int ls, float *tile, float scale) {
 #pragma unroll
   for (int k = 0; k < kSegIter; ++k) {
-    const int2 jo = seg_task<OUTER_FAST>(threadIdx.x + k * kSegThreads);
+    const int2 jo = seg_task(threadIdx.x + k * kSegThreads, ls);
     tile[jo.x * kSegRow + jo.y] = v[k] * scale;
   }
 }
+__device__ __forceinline__ void seg_load(const float *src, const int32_t *off, const int32_t *loc, int n, int ls,
+                                         float *tile, float scale) {
+  float v[kSegIter];
+  seg_fetch(src, off, loc, n, ls, v);
+  seg_stash(v, ls, tile, scale);
+}
 
-template <bool OUTER_FAST>
-__device__ __forceinline__ float seg_store_t(float *dst, const int32_t *off, const int32_t *loc, int n,
-                                             const float *tile) {
+__device__ __forceinline__ float seg_store(float *dst, const int32_t *off, const int32_t *loc, int n, int ls,
+                                           const float *tile) {
   gfloat *g = (gfloat *)dst;
   float lmax = 0.f;
 #pragma unroll
   for (int k = 0; k < kSegIter; ++k) {
-    const int2 jo = seg_task<OUTER_FAST>(threadIdx.x + k * kSegThreads);
+    const int2 jo = seg_task(threadIdx.x + k * kSegThreads, ls);
     const int32_t oo = off[jo.y];
     if (jo.x < n && oo >= 0) {
       const float x = tile[jo.x * kSegRow + jo.y];
@@ -1812,16 +1885,6 @@ __device__ __forceinline__ float seg_store_t(float *dst, const int32_t *off, con
     }
   }
   return lmax;
-}
-
-__device__ __forceinline__ void seg_load(const float *src, const int32_t *off, const int32_t *loc, int n,
-                                         bool outer_fast, float *tile, float scale) {
-  if (outer_fast) seg_load_t<true>(src, off, loc, n, tile, scale);
-  else seg_load_t<false>(src, off, loc, n, tile, scale);
-}
-__device__ __forceinline__ float seg_store(float *dst, const int32_t *off, const int32_t *loc, int n, bool outer_fast,
-                                           const float *tile) {
-  return outer_fast ? seg_store_t<true>(dst, off, loc, n, tile) : seg_store_t<false>(dst, off, loc, n, tile);
 }
 
 // Matrix-core tiles: v_mfma_f32_16x16x4_f32, D (16 x 16) += A (16 x 4) B (4 x 16)
@@ -1875,42 +1938,56 @@ __device__ __forceinline__ void seg_put(const f32x4 &d, int n, float *tile) {
 // itself, one dependent round trip fewer than through a pointer to them
 // (measured on the 20 x 20 grid: 7.4 -> 6.6 us forward, 9.6 -> 9.1 us reverse).
 template <int PREC>
-__global__ __launch_bounds__(kSegThreads) void k_seg_fwd(const SegArgs a) {
+__device__ __forceinline__ void seg_fwd_body(const SegArgs &a, const uint32_t blk) {
   __shared__ float tile[kSegMaxLocal * kSegRow];
   __shared__ SegShared sh;
-  const uint32_t o0 = blockIdx.x * kSegOB;
   const int n_in = a.n_in0, n_out = a.n_outL;
-  seg_prologue(a, o0, false, sh);
+  seg_prologue(a, blk, false, sh);
   __syncthreads();
   const int kx = sh.kx;
-  seg_load(a.arena + a.X, sh.offX, sh.locX, n_in, a.in_outer_fast, tile, ldexpf(1.f, -kx));
+  seg_load(a.arena + a.X, sh.offX, sh.locX, n_in, a.in_lo_shift, tile, ldexpf(1.f, -kx));
   __syncthreads();
   const f32x4 d = seg_mfma<PREC, false>(sh, tile);
   __syncthreads();
   seg_put(d, n_out, tile);
   __syncthreads();
-  const float lmax = seg_store(a.arena + a.Z, sh.offZ, sh.locZ, n_out, a.out_outer_fast, tile);
-  block_record_max<kSegThreads, false>(lmax, a.mx + (blockIdx.x % kMaxSub) * a.mx_stride + a.slotZ);
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.ex[a.slotZ] = sh.exX + kx + sh.exM;
+  const float lmax = seg_store(a.arena + a.Z, sh.offZ, sh.locZ, n_out, a.out_lo_shift, tile);
+  block_record_max<kSegThreads, false>(lmax, a.mx + (blk % kMaxSub) * a.mx_stride + a.slotZ);
+  if (blk == 0 && threadIdx.x == 0) a.ex[a.slotZ] = sh.exX + kx + sh.exM;
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kSegThreads) void k_seg_fwd(const SegArgs a) {
+  seg_fwd_body<PREC>(a, blockIdx.x);
+}
+
+// Two independent segments of one stage in one launch: workgroups
+// [0, split) run the first, the rest the second.  (Measured on the 20 x 20
+// grid: one workgroup per tile of each segment; a workgroup taking the same
+// tile of both segments, with both tiles' loads in flight together, ran
+// slower, 11.2 vs 10.4 us forward and 15.4 vs 14.2 us reverse per pair.)
+template <int PREC>
+__global__ __launch_bounds__(kSegThreads) void k_seg_fwd2(const SegPair g) {
+  const uint32_t second = blockIdx.x >= g.split ? 1u : 0u;
+  seg_fwd_body<PREC>(g.a[second], blockIdx.x - second * g.split);
 }
 
 // Reverse: Cbar_0[:, o] = M^T Gbar[:, o], and the workgroup's partial of
 // S = sum_o Gbar[:, o] C_0[:, o]^T: wave w computes the 16 x 16 quadrant
 // w % 4 of S over the outer quarter w / 4; quarters are added in order.
+// After the loads: the tiles into LDS, Cbar_0 tile = M^T Gbar tile, the S
+// partial, the stores, the maximum.  vg: Gbar tile, vx: C_0 tile (when the
+// segment needs S).
 template <int PREC>
-__global__ __launch_bounds__(kSegThreads) void k_seg_bwd(const SegArgs a) {
-  __shared__ float tg[kSegMaxLocal * kSegRow];  // output adjoint; later the waves' S partials
-  __shared__ float tx[kSegMaxLocal * kSegRow];  // input carrier; later its adjoint
-  __shared__ SegShared sh;
+__device__ __forceinline__ void seg_bwd_finish(const SegArgs &a, const uint32_t blk, const SegShared &sh,
+                                               const float (&vg)[kSegIter], const float (&vx)[kSegIter],
+                                               float *tg, float *tx) {
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint32_t o0 = blockIdx.x * kSegOB;
   const int n_in = a.n_in0, n_out = a.n_outL;
   const bool want_s = a.n_part > 0;
-  seg_prologue(a, o0, true, sh);
-  __syncthreads();
   const int kx = sh.kx, kg = sh.kg;
-  seg_load(a.arena + a.G, sh.offZ, sh.locZ, n_out, a.out_outer_fast, tg, ldexpf(1.f, -kg));
-  if (want_s) seg_load(a.arena + a.X, sh.offX, sh.locX, n_in, a.in_outer_fast, tx, ldexpf(1.f, -kx));
+  seg_stash(vg, a.out_lo_shift, tg, ldexpf(1.f, -kg));
+  if (want_s) seg_stash(vx, a.in_lo_shift, tx, ldexpf(1.f, -kx));
   __syncthreads();
   const f32x4 xb = seg_mfma<PREC, true>(sh, tg);  // A = M^T
   f32x4 s = {};
@@ -1944,10 +2021,10 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_bwd(const SegArgs a) {
     for (int r = 0; r < 4; ++r) tg[(w - 4) * 256 + r * 64 + l] = s[r];
   }
   __syncthreads();
-  const float lmax = seg_store(a.arena + a.Z, sh.offX, sh.locX, n_in, a.in_outer_fast, tx);
+  const float lmax = seg_store(a.arena + a.Z, sh.offX, sh.locX, n_in, a.in_lo_shift, tx);
   if (want_s && w < 4) {
     const int nS = n_out * n_in;
-    float *part = a.arena + a.Sp + (size_t)blockIdx.x * nS;
+    float *part = a.arena + a.Sp + (size_t)blk * nS;
     const int qr = w & 1, qc = w >> 1;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -1957,11 +2034,36 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_bwd(const SegArgs a) {
       if (j < n_out && i < n_in) part[j * n_in + i] = v;
     }
   }
-  block_record_max<kSegThreads, false>(lmax, a.mx + (blockIdx.x % kMaxSub) * a.mx_stride + a.slotZ);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  block_record_max<kSegThreads, false>(lmax, a.mx + (blk % kMaxSub) * a.mx_stride + a.slotZ);
+  if (blk == 0 && threadIdx.x == 0) {
     a.ex[a.slotZ] = sh.exG + kg + sh.exM;
     if (want_s) a.ex[a.slotSp] = (sh.exG + kg) + (sh.exX + kx);
   }
+}
+
+template <int PREC>
+__device__ __forceinline__ void seg_bwd_body(const SegArgs &a, const uint32_t blk) {
+  __shared__ float tg[kSegMaxLocal * kSegRow];  // output adjoint; later the waves' S partials
+  __shared__ float tx[kSegMaxLocal * kSegRow];  // input carrier; later its adjoint
+  __shared__ SegShared sh;
+  seg_prologue(a, blk, true, sh);
+  __syncthreads();
+  float vg[kSegIter], vx[kSegIter];
+  seg_fetch(a.arena + a.G, sh.offZ, sh.locZ, a.n_outL, a.out_lo_shift, vg);
+  if (a.n_part > 0) seg_fetch(a.arena + a.X, sh.offX, sh.locX, a.n_in0, a.in_lo_shift, vx);
+  seg_bwd_finish<PREC>(a, blk, sh, vg, vx, tg, tx);
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kSegThreads) void k_seg_bwd(const SegArgs a) {
+  seg_bwd_body<PREC>(a, blockIdx.x);
+}
+
+// Two independent segments' reverse steps in one launch, as k_seg_fwd2.
+template <int PREC>
+__global__ __launch_bounds__(kSegThreads) void k_seg_bwd2(const SegPair g) {
+  const uint32_t second = blockIdx.x >= g.split ? 1u : 0u;
+  seg_bwd_body<PREC>(g.a[second], blockIdx.x - second * g.split);
 }
 
 // --- sweeps over the steps (one workgroup per segment) ---------------------
@@ -2237,6 +2339,28 @@ void launch_seg_bwd(const SegArgs &a, void *stream) {
   else if (a.prec == 2) k_seg_bwd<2><<<seg_blocks(a), kSegThreads, 0, s>>>(a);
   else k_seg_bwd<0><<<seg_blocks(a), kSegThreads, 0, s>>>(a);
 }
+void launch_seg_fwd2(const SegArgs &a, const SegArgs &b, void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  SegPair g;
+  g.a[0] = a;
+  g.a[1] = b;
+  g.split = seg_blocks(a);
+  const unsigned nb = g.split + seg_blocks(b);
+  if (a.prec == 1) k_seg_fwd2<1><<<nb, kSegThreads, 0, s>>>(g);
+  else if (a.prec == 2) k_seg_fwd2<2><<<nb, kSegThreads, 0, s>>>(g);
+  else k_seg_fwd2<0><<<nb, kSegThreads, 0, s>>>(g);
+}
+void launch_seg_bwd2(const SegArgs &a, const SegArgs &b, void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  SegPair g;
+  g.a[0] = a;
+  g.a[1] = b;
+  g.split = seg_blocks(a);
+  const unsigned nb = g.split + seg_blocks(b);
+  if (a.prec == 1) k_seg_bwd2<1><<<nb, kSegThreads, 0, s>>>(g);
+  else if (a.prec == 2) k_seg_bwd2<2><<<nb, kSegThreads, 0, s>>>(g);
+  else k_seg_bwd2<0><<<nb, kSegThreads, 0, s>>>(g);
+}
 void launch_seg_mat(const SegArgs *d_base, const int32_t *d_ids, int n, int lds_floats, void *stream) {
   k_seg_mat<<<n, kSweepThreads, (size_t)lds_floats * sizeof(float), (hipStream_t)stream>>>(d_base, d_ids);
 }
@@ -2406,6 +2530,102 @@ void launch_factor_grad(const float *arena, const GradDesc *d, int n, const int3
   if (n <= 0) return;
   k_factor_grad<<<n, 256, 0, (hipStream_t)stream>>>(arena, d, n, gmap, obs, evidence, ex, root,
                                                     root_slot, grad);
+}
+
+// --------------------------------------------------------------------------
+// factor marginals and joint marginals (one workgroup per table and instance)
+// --------------------------------------------------------------------------
+static constexpr int kMargThreads = 256;
+
+__device__ __forceinline__ double block_sum_f64(double v, double *red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+#pragma unroll
+  for (int h = kMargThreads / 2; h > 0; h >>= 1) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kMargThreads) void k_factor_marg(const float *arena, const GradDesc *d, int n,
+                                                              const int32_t *gmap, const int32_t *obs,
+                                                              const int32_t *evidence, int n_vars,
+                                                              int64_t row, double *out) {
+  __shared__ double red[kMargThreads];
+  const int f = blockIdx.x, b = blockIdx.y;
+  if (f >= n) return;
+  const GradDesc g = d[f];
+  const float *adj = arena + g.adj + (g.adj_batched ? (int64_t)b * g.adj_bs : 0);
+  const float *leaf = arena + g.leaf + (g.leaf_batched ? (int64_t)b * g.leaf_bs : 0);
+  const int64_t les = g.leaf_batched ? g.leaf_es : 1;
+  double part = 0.0;
+  for (int i = threadIdx.x; i < g.size; i += kMargThreads)
+    part += (double)leaf[i * les] * (double)adj[(int64_t)i * g.adj_es];
+  const double tot = block_sum_f64(part, red);
+  double *o = out + (int64_t)b * row + g.dst;
+  for (int j = threadIdx.x; j < g.full; j += kMargThreads) o[j] = 0.0;
+  __syncthreads();  // the zeros before the consistent entries (same workgroup)
+  int64_t base = 0;
+  for (int k = g.obs_begin; k < g.obs_end; ++k) base += (int64_t)evidence[(int64_t)b * n_vars + obs[2 * k]] * obs[2 * k + 1];
+  const double inv = tot > 0.0 ? 1.0 / tot : 0.0;
+  for (int i = threadIdx.x; i < g.size; i += kMargThreads)
+    o[base + gmap[g.gmap + i]] = (double)leaf[i * les] * (double)adj[(int64_t)i * g.adj_es] * inv;
+}
+
+void launch_factor_marg(const float *arena, const GradDesc *d, int n, const int32_t *gmap, const int32_t *obs,
+                        const int32_t *evidence, int n_vars, int batch, int64_t row, double *out, void *stream) {
+  if (n <= 0 || batch <= 0) return;
+  k_factor_marg<<<dim3(n, batch), kMargThreads, 0, (hipStream_t)stream>>>(arena, d, n, gmap, obs, evidence, n_vars,
+                                                                          row, out);
+}
+
+__global__ __launch_bounds__(kMargThreads) void k_joint(const float *arena, const JointDesc *d, int n,
+                                                        const int32_t *tab, const int32_t *evidence, int n_vars,
+                                                        int row, double *out) {
+  __shared__ double red[kMargThreads];
+  const int k = blockIdx.x, b = blockIdx.y;
+  if (k >= n) return;
+  const JointDesc j = d[k];
+  const float *adj = j.adj >= 0 ? arena + j.adj + (j.adj_batched ? (int64_t)b * j.adj_bs : 0) : nullptr;
+  const int32_t *ev = evidence + (int64_t)b * n_vars;
+  // entry e of the whole table -> the unity tensor's entry (-1: an observed
+  // variable takes another value)
+  auto free_index = [&](int32_t e) -> int64_t {
+    int64_t fi = 0;
+    for (int t = j.v_end - 1; t >= j.v_begin; --t) {
+      const int32_t var = tab[3 * t], card = tab[3 * t + 1], st = tab[3 * t + 2];
+      const int32_t x = e % card;
+      e /= card;
+      if (st < 0) {
+        if (x != ev[var]) return -1;
+      } else {
+        fi += (int64_t)x * st;
+      }
+    }
+    return fi;
+  };
+  double part = 0.0;
+  for (int32_t e = threadIdx.x; e < j.n_full; e += kMargThreads) {
+    const int64_t fi = free_index(e);
+    if (fi >= 0) part += adj ? (double)adj[fi * j.adj_es] : 1.0;
+  }
+  const double tot = block_sum_f64(part, red);
+  const double inv = tot > 0.0 ? 1.0 / tot : 0.0;
+  double *o = out + (int64_t)b * row + j.out;
+  for (int32_t e = threadIdx.x; e < j.n_full; e += kMargThreads) {
+    const int64_t fi = free_index(e);
+    o[e] = fi >= 0 ? (adj ? (double)adj[fi * j.adj_es] : 1.0) * inv : 0.0;
+  }
+}
+
+void launch_joint(const float *arena, const JointDesc *d, int n, const int32_t *tab, const int32_t *evidence,
+                  int n_vars, int batch, int row, double *out, void *stream) {
+  if (n <= 0 || batch <= 0) return;
+  k_joint<<<dim3(n, batch), kMargThreads, 0, (hipStream_t)stream>>>(arena, d, n, tab, evidence, n_vars, row, out);
 }
 
 // --------------------------------------------------------------------------

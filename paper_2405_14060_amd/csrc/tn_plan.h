@@ -65,7 +65,7 @@ struct SegPlan {
   uint32_t nO = 1, nOl = 1;
   int32_t n_in0 = 0, n_outL = 0;
   int64_t list_off = 0;               // the steps' CSR lists in the table store
-  int32_t in_outer_fast = 0, out_outer_fast = 0;
+  int32_t in_lo_shift = 5, out_lo_shift = 5;
   std::vector<SegStep> steps;
   int mt = -1;                        // tensor holding the composed map M
   int spt = -1;                       // reverse: tensor holding the partials of S (-1 = none)
@@ -130,6 +130,7 @@ struct tn_plan_impl {
   std::vector<int> card;
   int mode = 0;
   int max_batch = 1;
+  bool batched_ev = false;             // instances run as one batch (INDICATOR, or SLICED with max_batch > 1)
   bool inter = false;                  // batched tensors interleaved (instance fastest)
   std::vector<tn::Op> samp_ops;        // sampling: children summed over their private labels
   tn::Schedule sched_samp;
@@ -144,6 +145,7 @@ struct tn_plan_impl {
   std::vector<tn::Pair> pairs;
   tn::TreeStats stats;
   int planner_used = 0;
+  bool two_front = false;
   std::vector<int> sliced;
 
   // tensors
@@ -176,6 +178,11 @@ struct tn_plan_impl {
   std::vector<int32_t> samp_meta;
   std::vector<int> marg_col;           // column offset of each variable
   int marg_row = 0;
+  // joint marginals: variable sets (sorted), their unity tensors' tables
+  std::vector<std::vector<int>> joint_sets;
+  std::vector<tn::JointDesc> joint;
+  std::vector<int32_t> joint_tab;      // (var, card, stride in the unity tensor or -1) per set variable
+  int joint_row = 0;
 
   // MMAP
   std::vector<tn::TreeExec> groups;    // sum phase, one tree per group
@@ -200,6 +207,10 @@ struct tn_plan_impl {
   int32_t *d_assign = nullptr;         // [max_batch][n_vars]
   double *d_out = nullptr;             // logz [max_batch]
   double *d_marg = nullptr;            // [max_batch][marg_row]
+  double *d_joint = nullptr;           // [max_batch][joint_row]
+  tn::JointDesc *d_joint_desc = nullptr;
+  int32_t *d_joint_tab = nullptr;
+  double *d_fmarg = nullptr;           // [max_batch][n_values] (plans with factor adjoints)
   tn::LeafDesc *d_leaves_sum = nullptr, *d_leaves_max = nullptr, *d_qleaves = nullptr;
   std::vector<tn::LeafDesc *> d_group_leaves;
   tn::MargDesc *d_marg_desc = nullptr;

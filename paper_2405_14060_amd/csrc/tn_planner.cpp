@@ -324,6 +324,42 @@ static std::vector<Pair> greedy_pairs(const std::vector<Labels> &leaves, const s
   return F.pairs;
 }
 
+// Two-front variant of an elimination order: the first half in order and the
+// second half from its end, interleaved (v_0, v_{n-1}, v_1, v_{n-2}, ...).
+// Bucket elimination then grows two intermediates from the two ends of the
+// order, independent until they meet, so their contractions pair up in
+// stages (half the sequential levels of a sweep).
+static std::vector<int> two_front(const std::vector<int> &order) {
+  const size_t n = order.size(), h = (n + 1) / 2;
+  std::vector<int> r;
+  r.reserve(n);
+  for (size_t i = 0; i < h; ++i) {
+    r.push_back(order[i]);
+    if (n - 1 - i >= h) r.push_back(order[n - 1 - i]);
+  }
+  return r;
+}
+
+double stage_time(const std::vector<Labels> &leaves, const std::vector<Pair> &pairs, const Labels &out,
+                  const std::vector<int> &card, int *n_levels) {
+  const int L = (int)leaves.size(), P = (int)pairs.size();
+  const auto lab = node_labels(leaves, pairs, out, (int)card.size());
+  std::vector<int> level(L + P, 0);
+  std::vector<double> worst;  // per level: the slowest node
+  for (int q = 0; q < P; ++q) {
+    const int c = L + q, a = pairs[q][0], b = pairs[q][1];
+    level[c] = 1 + std::max(level[a], level[b]);
+    const double mac = std::exp2(log2size(merge_sorted(lab[a], lab[b]), card));
+    const double t = kStageLaunchSeconds + mac / kStageMacRate;
+    if ((int)worst.size() < level[c]) worst.resize(level[c], 0.0);
+    worst[level[c] - 1] = std::max(worst[level[c] - 1], t);
+  }
+  if (n_levels) *n_levels = (int)worst.size();
+  double t = 0;
+  for (double w : worst) t += w;
+  return t;
+}
+
 PlanChoice plan_tree(const std::vector<Labels> &leaves, const std::vector<int> &card,
                      const Labels &out, int strategy, int restarts, uint64_t seed, double cap) {
   const int n_vars = (int)card.size();
@@ -332,10 +368,14 @@ PlanChoice plan_tree(const std::vector<Labels> &leaves, const std::vector<int> &
   PlanChoice best;
   std::pair<double, double> best_key;
   bool have = false;
-  auto consider = [&](std::vector<Pair> pairs, int which) {
+  auto consider = [&](std::vector<Pair> pairs, int which, bool twofront = false) {
     TreeStats st = tree_stats(leaves, pairs, out, card);
     std::pair<double, double> key(std::round(2 * st.sc) / 2, st.tc);
-    if (cap > 0 && st.sc > cap + 1e-9) {
+    if (cap <= 0) {
+      // unsliced: among trees of one space-complexity class, the estimated
+      // time of the stage schedule (every stage costs its slowest node)
+      key.second = stage_time(leaves, pairs, out, card, nullptr);
+    } else if (st.sc > cap + 1e-9) {
       // total work once sliced below the cap
       Labels sl;
       try {
@@ -356,16 +396,24 @@ PlanChoice plan_tree(const std::vector<Labels> &leaves, const std::vector<int> &
       // 5e7 multiply-adds (20 TFLOP/s), so that many tiny slices do not win
       const double per_slice = 5e7 * (double)pairs.size();
       key = std::make_pair(std::round(2 * cap) / 2, std::log2(ss.flops * ns / 2 + per_slice * ns));
-    } else if (cap > 0) {
+    } else {
       key.first = std::round(2 * cap) / 2;  // within the cap: ranked by work alone
     }
     if (!have || key < best_key) {
       best.pairs = std::move(pairs);
       best.stats = st;
       best.planner = which;
+      best.two_front = twofront;
       best_key = key;
       have = true;
     }
+  };
+  // unsliced plans also try the two-front variant of each order (ties of its
+  // bucket merges are not randomised, so the restarts' random streams stay
+  // those of the base orders)
+  auto consider_order = [&](const std::vector<int> &order, std::mt19937_64 *R, int which) {
+    consider(bucket_tree(leaves, card, out, order, R), which);
+    if (cap <= 0) consider(bucket_tree(leaves, card, out, two_front(order), nullptr), which, true);
   };
   if (leaves.size() == 1) {
     consider({}, strategy);
@@ -376,17 +424,15 @@ PlanChoice plan_tree(const std::vector<Labels> &leaves, const std::vector<int> &
     std::vector<int> order;
     for (int v = 0; v < n_vars; ++v)
       if (!isout[v]) order.push_back(v);
-    consider(bucket_tree(leaves, card, out, order, nullptr), TN_PLANNER_NATURAL);
+    consider_order(order, nullptr, TN_PLANNER_NATURAL);
   }
   for (int r = 0; r < restarts; ++r) {
     std::mt19937_64 rng(seed * 1000003ull + (uint64_t)r);
     std::mt19937_64 *R = r ? &rng : nullptr;
     if (strategy == TN_PLANNER_BEST || strategy == TN_PLANNER_MINFILL)
-      consider(bucket_tree(leaves, card, out, greedy_order(leaves, n_vars, out, 1, R), R),
-               TN_PLANNER_MINFILL);
+      consider_order(greedy_order(leaves, n_vars, out, 1, R), R, TN_PLANNER_MINFILL);
     if (strategy == TN_PLANNER_BEST || strategy == TN_PLANNER_MINDEG)
-      consider(bucket_tree(leaves, card, out, greedy_order(leaves, n_vars, out, 0, R), R),
-               TN_PLANNER_MINDEG);
+      consider_order(greedy_order(leaves, n_vars, out, 0, R), R, TN_PLANNER_MINDEG);
     if (strategy == TN_PLANNER_BEST || strategy == TN_PLANNER_GREEDY)
       consider(greedy_pairs(leaves, card, out, R), TN_PLANNER_GREEDY);
   }

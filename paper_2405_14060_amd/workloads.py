@@ -221,6 +221,37 @@ def bn_evidence_batch(bn: Network, batch: int, seed: int,
     return out
 
 
+def three_factor_net(n_b: int, n_m: int, n_s: int, n_n: int, card: int, seed: int,
+                     sd: float = 1.0) -> Network:
+    """Three factors X(B, M, S), Y(B, S, N), Z(B, M, N) over binary batch
+    variables B and `card`-valued row (M), summed (S) and column (N)
+    variables, i.i.d. N(0, sd) log-potentials: a network whose first
+    contraction is one large dense product (batched matrix product, or its
+    max-plus counterpart for MAP).  Variable ids: B, then M, S, N."""
+    rng = np.random.default_rng(seed)
+    c = np.array([2] * n_b + [card] * (n_m + n_s + n_n), np.int32)
+    ids = np.arange(c.size)
+    B, M = ids[:n_b], ids[n_b:n_b + n_m]
+    S, N = ids[n_b + n_m:n_b + n_m + n_s], ids[n_b + n_m + n_s:]
+    scopes = [np.concatenate(g).astype(np.int32) for g in ((B, M, S), (B, S, N), (B, M, N))]
+    values = [rng.normal(0.0, sd, int(np.prod(c[sc]))) for sc in scopes]
+    return Network(c, scopes, values, True, dict(kind="three_factor", seed=seed))
+
+
+def bn_evidence_shared(bn: Network, batch: int, seed: int, frac: float = 0.1):
+    """Batch of evidence sets sharing one observed set: round(frac*n)
+    variables drawn uniformly once, values from a fresh ancestral draw per
+    set.  Returns (observed ids sorted int32, int32 [batch, n_vars], -1 = free)."""
+    rng = np.random.default_rng(seed)
+    n = bn.n_vars
+    obs = np.sort(rng.choice(n, size=int(round(frac * n)), replace=False)).astype(np.int32)
+    out = np.full((batch, n), -1, np.int32)
+    for b in range(batch):
+        x = ancestral_sample(bn, rng)
+        out[b, obs] = x[obs]
+    return obs, out
+
+
 def random_small_mrf(n: int, n_factors: int, seed: int, max_arity: int = 3,
                      cards=(2, 3)) -> Network:
     """Small random factor graph with mixed domain sizes, for exhaustive checks.

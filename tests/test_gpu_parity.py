@@ -392,7 +392,7 @@ def test_fused_segments_against_oracle(T, rows, cols, card):
     """Grids whose planned trees hold fused chain segments (composed maps on
     the matrix cores), including odd local sizes (card 3: 27 entries)."""
     net = W.grid_mrf(rows, cols, 1, card=card)
-    P = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT)
+    P = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, planner=T.PLANNER_NATURAL)
     info = P.info()
     assert info["n_segments"] > 0
     lz, m = P.marginals()
