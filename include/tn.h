@@ -402,6 +402,22 @@ tn_status tn_tune_save(const char *path, int64_t *n_saved);
 tn_status tn_tune_load(const char *path, int64_t *n_loaded);
 void tn_tune_clear(void);
 
+/* Contractions of one task, for inspection: per contraction its kernel form
+ * (0 generic one lane per output, 1 row, 2 dense on the matrix cores or, for
+ * max-plus, the vector ALUs, 3 wave per output, 4 interleaved instances, 5
+ * fused-segment kernel), semiring (0 sum-product, 1 max-plus), the label
+ * classes' sizes (rows = output labels held by X, columns = output labels X
+ * lacks, summed = labels of X or Y not in the output) and the operands'
+ * elements per instance.  task: 0 forward sum-product (fused list when the
+ * plan fuses), 1 reverse pass, 2 max-plus, 3 MMAP plans: the sum phase of
+ * every group.  Writes up to cap entries; *n = count. */
+typedef struct {
+  int32_t form, semiring, variant;   /* variant: tile / order variant of the form */
+  int64_t rows, cols, summed;
+  int64_t x_size, y_size, z_size;
+} tn_op_info;
+tn_status tn_plan_ops(const tn_plan_t *plan, int32_t task, tn_op_info *out, int32_t cap, int32_t *n);
+
 /* Synchronise the plan's stream; TN_E_DEVICE on error. */
 tn_status tn_sync(tn_plan_t *plan);
 

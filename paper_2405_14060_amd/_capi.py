@@ -35,7 +35,7 @@ EXPORTS = ["tn_plan_opts_default", "tn_load_network", "tn_free_network", "tn_pla
            "tn_map", "tn_mmap", "tn_sample", "tn_logZ_dev", "tn_sync", "tn_profile", "tn_profile_kind", "tn_last_error",
            "tn_tune_save", "tn_tune_load", "tn_tune_clear", "tn_sample_noalloc", "tn_joint_marginals",
            "tn_factor_marginals", "tn_load_uai", "tn_read_uai_evidence", "tn_read_uai_query", "tn_network_sizes",
-           "tn_network_get"]
+           "tn_network_get", "tn_plan_ops"]
 
 i32p = ctypes.POINTER(ctypes.c_int32)
 i64p = ctypes.POINTER(ctypes.c_int64)
@@ -80,6 +80,12 @@ class PlanInfo(ctypes.Structure):
 class OpProfile(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("flops", ctypes.c_double), ("bytes", ctypes.c_double),
                 ("ms", ctypes.c_double)]
+
+
+class OpInfo(ctypes.Structure):
+    _fields_ = [("form", ctypes.c_int32), ("semiring", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("rows", ctypes.c_int64), ("cols", ctypes.c_int64), ("summed", ctypes.c_int64),
+                ("x_size", ctypes.c_int64), ("y_size", ctypes.c_int64), ("z_size", ctypes.c_int64)]
 
 
 class TNError(RuntimeError):
@@ -135,11 +141,12 @@ def lib():
     L.tn_read_uai_query.argtypes = [ctypes.c_char_p, ctypes.c_int32, i32p, ctypes.c_int32, i32p]
     L.tn_network_sizes.argtypes = [vp, i32p, i32p, i64p, i64p]
     L.tn_network_get.argtypes = [vp, i32p, i64p, i32p, f64p, i32p]
+    L.tn_plan_ops.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(OpInfo), ctypes.c_int32, i32p]
     L.tn_tune_save.argtypes = [ctypes.c_char_p, i64p]
     L.tn_tune_load.argtypes = [ctypes.c_char_p, i64p]
     L.tn_tune_clear.argtypes = []
     L.tn_tune_clear.restype = None
-    for name in ("tn_load_uai", "tn_read_uai_evidence", "tn_read_uai_query", "tn_network_sizes", "tn_network_get",
+    for name in ("tn_plan_ops", "tn_load_uai", "tn_read_uai_evidence", "tn_read_uai_query", "tn_network_sizes", "tn_network_get",
                  "tn_tune_save", "tn_tune_load", "tn_load_network", "tn_plan", "tn_plan_info_get", "tn_plan_tree", "tn_plan_sliced", "tn_plan_tree_host",
                  "tn_logZ", "tn_marginals", "tn_joint_marginals", "tn_factor_marginals", "tn_map", "tn_mmap",
                  "tn_sample", "tn_sample_noalloc", "tn_logZ_dev", "tn_sync",
@@ -458,6 +465,16 @@ class Plan:
         _check(lib().tn_profile_kind(self.h, task, kind, batch, _ptr(ev, ctypes.c_int32), reps,
                                      ctypes.byref(o), ctypes.byref(n)))
         return o.ms, o.flops, o.bytes, n.value
+
+    def ops(self, task):
+        """Contractions of a task (0 forward, 1 reverse, 2 max-plus, 3 MMAP
+        sum phase) as dicts of form, semiring, variant, label-class sizes and
+        operand sizes."""
+        n = ctypes.c_int32()
+        _check(lib().tn_plan_ops(self.h, task, None, 0, ctypes.byref(n)))
+        buf = (OpInfo * max(1, n.value))()
+        _check(lib().tn_plan_ops(self.h, task, buf, n.value, ctypes.byref(n)))
+        return [{k: getattr(buf[i], k) for k, _ in OpInfo._fields_} for i in range(n.value)]
 
     def sliced_vars(self):
         """Sliced variables (ascending); slices run over their values, last fastest."""

@@ -1132,12 +1132,28 @@ static void allocate(tn_plan_t *p, const tn_net *net) {
     d.dst = p->T[tensor].off;
     if (d.kind == 0) d.src += maxdom ? fs_log : fs_lin;
   };
+  // the largest leaves of a set (up to kPrepBig, above 2^14 entries, not
+  // interleaved) are prepared by several workgroups, one per 2^14 entries
+  auto split_large = [&](std::vector<LeafDesc> &set) {
+    std::vector<size_t> idx;
+    for (size_t i = 0; i < set.size(); ++i) {
+      set[i].nsub = 1;
+      if (set[i].size > (1 << 14) && !(set[i].batched && p->inter)) idx.push_back(i);
+    }
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return set[x].size > set[y].size; });
+    for (size_t k = 0; k < idx.size() && k < (size_t)kPrepBig; ++k)
+      set[idx[k]].nsub = std::min<int32_t>(kMaxSubSlots, (set[idx[k]].size + (1 << 14) - 1) >> 14);
+  };
   // leaf descriptors carry the tensor id in dst until here
   for (auto &d : p->leaves_sum) fix_leaf(d, (int)d.dst, false);
   for (auto &d : p->leaves_max) fix_leaf(d, (int)d.dst, true);
   for (auto &gl : p->group_leaves)
     for (auto &d : gl) fix_leaf(d, (int)d.dst, false);
   for (auto &d : p->qleaves) fix_leaf(d, (int)d.dst, true);
+  split_large(p->leaves_sum);
+  split_large(p->leaves_max);
+  for (auto &gl : p->group_leaves) split_large(gl);
+  split_large(p->qleaves);
   p->d_tabs = dupload(p, p->tabs);
   p->d_gmap = dupload(p, p->gmap);
   p->d_obs = dupload(p, p->obs);
@@ -2006,6 +2022,37 @@ extern "C" tn_status tn_plan_tree(const tn_plan_t *p, int32_t *pairs, int32_t ca
   });
 }
 
+extern "C" tn_status tn_plan_ops(const tn_plan_t *p, int32_t task, tn_op_info *out, int32_t cap, int32_t *n) {
+  return guard([&] {
+    if (!p || !n) throw TnError(TN_E_INVALID, "NULL argument");
+    std::vector<const Op *> ops;
+    auto add = [&](const std::vector<Op> &v) {
+      for (const Op &op : v) ops.push_back(&op);
+    };
+    if (task == 0) add(p->fused ? p->ffwd : p->sum_tree.ops);
+    else if (task == 1) add(p->fused ? p->fbwd : p->bwd);
+    else if (task == 2) add(p->max_tree.ops);
+    else if (task == 3)
+      for (const auto &g : p->groups) add(g.ops);
+    else throw TnError(TN_E_INVALID, "unknown task");
+    *n = (int32_t)ops.size();
+    for (size_t i = 0; i < ops.size() && (int32_t)i < cap; ++i) {
+      const Op &op = *ops[i];
+      tn_op_info o{};
+      o.form = op.seg >= 0 ? 5 : op.a.kind;
+      o.semiring = op.semi;
+      o.variant = op.seg >= 0 ? op.seg_kind : op.a.tile;
+      o.rows = op.a.nR;
+      o.cols = op.a.nC;
+      o.summed = op.a.nS;
+      o.x_size = op.X >= 0 ? p->T[op.X].size : 0;
+      o.y_size = op.Y >= 0 ? p->T[op.Y].size : 0;
+      o.z_size = op.Z >= 0 ? p->T[op.Z].size : 0;
+      out[i] = o;
+    }
+  });
+}
+
 extern "C" tn_status tn_plan_sliced(const tn_plan_t *p, int32_t *vars, int32_t cap, int32_t *n) {
   return guard([&] {
     if (!p) throw TnError(TN_E_INVALID, "NULL plan");
@@ -2122,6 +2169,12 @@ static PrepareArgs prep_args(tn_plan_t *p, const std::vector<LeafDesc> &h, const
   a.batch = p->max_batch;
   a.max_batch = p->max_batch;
   a.interleaved = p->inter ? 1 : 0;
+  for (size_t i = 0; i < h.size() && a.n_big < kPrepBig; ++i)
+    if (h[i].nsub > 1) {
+      a.big_leaf[a.n_big] = (int32_t)i;
+      a.big_blk0[a.n_big + 1] = a.big_blk0[a.n_big] + h[i].nsub;
+      ++a.n_big;
+    }
   return a;
 }
 

@@ -263,7 +263,11 @@ struct LeafDesc {
   int32_t obs_begin, obs_end;  // (var, stride) pairs in the observation list
   int32_t slot;      // mx slot (ex slot is the same index)
   int32_t maxdom;    // 1: log domain (zero = -inf, one = 0)
+  int32_t nsub;      // workgroups preparing the leaf (> 1: a large leaf, each
+                     // workgroup's maximum in its own sub-slot)
 };
+
+static constexpr int kPrepBig = 16;  // leaves per launch prepared by several workgroups
 
 struct PrepareArgs {
   float *arena = nullptr;
@@ -280,6 +284,11 @@ struct PrepareArgs {
   int batch = 1;
   int max_batch = 1;
   int interleaved = 0;  // batched leaves: element i of instance b at i * max_batch + b
+  // large leaves (nsub > 1): their indices and first workgroup (after the
+  // n_leaves one-per-leaf workgroups, which skip them)
+  int n_big = 0;
+  int32_t big_leaf[kPrepBig] = {};
+  int32_t big_blk0[kPrepBig + 1] = {};
 };
 void launch_prepare(const PrepareArgs &a, void *stream);
 

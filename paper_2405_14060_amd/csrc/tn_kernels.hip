@@ -912,14 +912,22 @@ __device__ __forceinline__ void gemm_body(const ContractArgs &a, const int b, co
 // (entries past nS read as -inf, so they never win); every thread keeps a
 // 4 x 4 block of (value, index) pairs in registers and scans the chunk in
 // canonical order with a strict comparison, so the first maximiser is kept
-// (every candidate one FP32 addition).
+// (every candidate one FP32 addition).  The next chunk's loads are in flight
+// (registers) during this chunk's candidates, and the summed entries'
+// offsets of small summed sets are staged in LDS once.
 // --------------------------------------------------------------------------
+static constexpr int kMSOff = 1024;  // largest summed set whose offsets are staged in LDS
+
 __device__ __forceinline__ void gemm_max_body(const ContractArgs &a, const int b, const uint32_t blk) {
   __shared__ int32_t oMX[kGT], oMZ[kGT], oNY[kGT], oNZ[kGT];
   __shared__ float As[kGK * kGKP], Bs[kGK * kGKP];
-  __shared__ float Cs[kGT * kGCP];
   __shared__ int32_t Ci[kGT * kGCP];
-  const int t = threadIdx.x, l = t & 63, w = t >> 6;
+  __shared__ float U[kGT * kGCP];  // the staged summed offsets during the scan, the value tile after it
+  static_assert(2 * kMSOff <= kGT * kGCP, "staged offsets fit the epilogue tile");
+  int32_t *sOX = reinterpret_cast<int32_t *>(U), *sOY = sOX + kMSOff;
+  float *Cs = U;
+  const int t = threadIdx.x;
+  const int l = t & 63, w = t >> 6;
   const uint32_t tm = (a.nM + kGT - 1) / kGT, tn = (a.nC + kGT - 1) / kGT;
   const uint32_t bt = blk / (tm * tn), rem = blk - bt * tm * tn;
   const uint32_t mt = rem / tn, nt = rem - mt * tn;
@@ -929,6 +937,8 @@ __device__ __forceinline__ void gemm_max_body(const ContractArgs &a, const int b
   gcfloat *__restrict__ Y = (gcfloat *)(a.Y + (int64_t)b * a.bsY + yb);
   gfloat *__restrict__ Z = (gfloat *)(a.Z + (int64_t)b * a.bsZ + zb);
   gint_w *__restrict__ I = (gint_w *)(a.I + (int64_t)b * a.bsZ + zb);
+  const uint32_t nS = a.nS;
+  const bool staged = nS <= (uint32_t)kMSOff;
   if (w == 0) {
     const uint32_t m = m0 + l;
     oMX[l] = m < a.nM ? tab_off(a.gmX, m, a.nMl) : -1;
@@ -938,7 +948,46 @@ __device__ __forceinline__ void gemm_max_body(const ContractArgs &a, const int b
     oNY[l] = n < a.nC ? (a.nC > 1 ? tab_off(a.cY, n, a.nCl) : 0) : -1;
     oNZ[l] = n < a.nC ? (a.nC > 1 ? tab_off(a.cZ, n, a.nCl) : 0) : -1;
   }
+  if (staged)
+    for (uint32_t s = t; s < nS; s += kBlock) {
+      sOX[s] = tab_off(a.sX, s, a.nSl);
+      sOY[s] = tab_off(a.sY, s, a.nSl);
+    }
   __syncthreads();
+  // per thread: 4 entries of each operand per chunk, consecutive threads on
+  // the operand's stride-1 label
+  constexpr int NQ = kGT * kGK / kBlock;
+  int32_t oa[NQ], ob[NQ];
+  int kA[NQ], kB[NQ], dA[NQ], dB[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int e = t + q * kBlock;
+    int m, k;
+    if (a.x_s_fast) { k = e % kGK; m = e / kGK; } else { m = e % kGT; k = e / kGT; }
+    oa[q] = oMX[m];
+    kA[q] = k;
+    dA[q] = k * kGKP + m;
+    int n, k2;
+    if (a.y_n_fast) { n = e % kGT; k2 = e / kGT; } else { k2 = e % kGK; n = e / kGK; }
+    ob[q] = oNY[n];
+    kB[q] = k2;
+    dB[q] = k2 * kGKP + n;
+  }
+  // every address in bounds (rows past the tile and summed entries past nS
+  // read entry 0), masked to -inf afterwards
+  auto load_chunk = [&](uint32_t s0, float (&va)[NQ], float (&vb)[NQ]) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const uint32_t s = s0 + kA[q], s2 = s0 + kB[q];
+      const uint32_t sc = s < nS ? s : 0u, sc2 = s2 < nS ? s2 : 0u;
+      const int32_t ox = staged ? sOX[sc] : tab_off(a.sX, sc, a.nSl);
+      const int32_t oy = staged ? sOY[sc2] : tab_off(a.sY, sc2, a.nSl);
+      const float x = X[(oa[q] >= 0 ? oa[q] : 0) + ox];
+      const float y = Y[(ob[q] >= 0 ? ob[q] : 0) + oy];
+      va[q] = (oa[q] >= 0 && s < nS) ? x : -INFINITY;
+      vb[q] = (ob[q] >= 0 && s2 < nS) ? y : -INFINITY;
+    }
+  };
   // thread (ty, tx) owns rows ty + 16 i and columns tx + 16 j, i, j < 4
   const int ty = t >> 4, tx = t & 15;
   float best[4][4];
@@ -950,32 +999,18 @@ __device__ __forceinline__ void gemm_max_body(const ContractArgs &a, const int b
       best[i][j] = -INFINITY;
       arg[i][j] = 0;
     }
-  for (uint32_t s0 = 0; s0 < a.nS; s0 += kGK) {
-    float va[4], vb[4];
-    int da[4], db[4];
+  float va[NQ], vb[NQ], na[NQ], nb[NQ];
+  if (nS > 0) load_chunk(0, va, vb);
+  for (uint32_t s0 = 0; s0 < nS; s0 += kGK) {
+    const bool more = s0 + kGK < nS;
+    if (more) load_chunk(s0 + kGK, na, nb);  // next chunk in flight during this one's candidates
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int e = t + q * kBlock;
-      int m, k;
-      if (a.x_s_fast) { k = e % kGK; m = e / kGK; } else { m = e % kGT; k = e / kGT; }
-      const uint32_t sa = s0 + k;
-      const int32_t om = oMX[m];
-      va[q] = (om >= 0 && sa < a.nS) ? X[om + tab_off(a.sX, sa, a.nSl)] : -INFINITY;
-      da[q] = k * kGKP + m;
-      int n, k2;
-      if (a.y_n_fast) { n = e % kGT; k2 = e / kGT; } else { k2 = e % kGK; n = e / kGK; }
-      const uint32_t sb = s0 + k2;
-      const int32_t on = oNY[n];
-      vb[q] = (on >= 0 && sb < a.nS) ? Y[on + tab_off(a.sY, sb, a.nSl)] : -INFINITY;
-      db[q] = k2 * kGKP + n;
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      As[da[q]] = va[q];
-      Bs[db[q]] = vb[q];
+    for (int q = 0; q < NQ; ++q) {
+      As[dA[q]] = va[q];
+      Bs[dB[q]] = vb[q];
     }
     __syncthreads();
-    const int kn = (int)min((uint32_t)kGK, a.nS - s0);
+    const int kn = (int)min((uint32_t)kGK, nS - s0);
     for (int k = 0; k < kn; ++k) {
       float av[4], bv[4];
 #pragma unroll
@@ -996,7 +1031,15 @@ __device__ __forceinline__ void gemm_max_body(const ContractArgs &a, const int b
         }
     }
     __syncthreads();
+    if (more) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        va[q] = na[q];
+        vb[q] = nb[q];
+      }
+    }
   }
+  // the value tile reuses the staged offsets (the last chunk's loads are done)
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -2375,15 +2418,25 @@ void launch_seg_fin(const SegArgs *d_base, const int32_t *d_ids, int n, int lds_
 // --------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_prepare(PrepareArgs a) {
   const int b = blockIdx.y;
-  if ((int)blockIdx.x >= a.n_leaves) {
+  const int n_lb = a.n_leaves + a.big_blk0[a.n_big];  // workgroups of leaves
+  if ((int)blockIdx.x >= n_lb) {
     if (b != 0) return;
     const int n = a.reset_end - a.reset_begin;
-    for (int i = (blockIdx.x - a.n_leaves) * kBlock + threadIdx.x; i < n * kMaxSub;
-         i += (gridDim.x - a.n_leaves) * kBlock)
+    for (int i = (blockIdx.x - n_lb) * kBlock + threadIdx.x; i < n * kMaxSub; i += (gridDim.x - n_lb) * kBlock)
       a.mx[(i / n) * a.mx_stride + a.reset_begin + i % n] = 0u;
     return;
   }
-  const LeafDesc d = a.leaves[blockIdx.x];
+  int li = blockIdx.x, sub = 0;
+  if (li >= a.n_leaves) {  // a workgroup of a large leaf
+    const int x = li - a.n_leaves;
+    int j = 0;
+    while (j + 1 < a.n_big && a.big_blk0[j + 1] <= x) ++j;
+    li = a.big_leaf[j];
+    sub = x - a.big_blk0[j];
+  }
+  const LeafDesc d = a.leaves[li];
+  if (blockIdx.x < (unsigned)a.n_leaves && d.nsub > 1) return;  // prepared by its own workgroups
+  const int nsub = d.nsub > 1 ? d.nsub : 1;
   if (!d.batched && b > 0) return;
   if (d.batched && a.interleaved) {
     // one thread per instance: element i of instance bi at i * max_batch + bi
@@ -2423,22 +2476,23 @@ __global__ __launch_bounds__(kBlock) void k_prepare(PrepareArgs a) {
   const float one = d.maxdom ? 0.f : 1.f;
   const float zero = d.maxdom ? -INFINITY : 0.f;
   float lmax = 0.f;
+  const int i0 = sub * kBlock + threadIdx.x, istep = nsub * kBlock;
   if (d.kind == 0) {
     int64_t base = 0;
     for (int o = d.obs_begin; o < d.obs_end; ++o)
       base += (int64_t)a.evidence[(int64_t)row * a.n_vars + a.obs[2 * o]] * a.obs[2 * o + 1];
     const float *src = a.arena + d.src + base;
-    for (int i = threadIdx.x; i < d.size; i += kBlock) {
+    for (int i = i0; i < d.size; i += istep) {
       const float v = src[a.gmap[d.gmap + i]];
       dst[i] = v;
       lmax = fmaxf(lmax, fabsf(v));
     }
   } else if (d.kind == 1) {
-    for (int i = threadIdx.x; i < d.size; i += kBlock) dst[i] = one;
+    for (int i = i0; i < d.size; i += istep) dst[i] = one;
     lmax = 1.f;
   } else {
     const int e = a.evidence[(int64_t)row * a.n_vars + d.var];
-    for (int i = threadIdx.x; i < d.size; i += kBlock) dst[i] = (e < 0 || e == i) ? one : zero;
+    for (int i = i0; i < d.size; i += istep) dst[i] = (e < 0 || e == i) ? one : zero;
     lmax = 1.f;
   }
   __shared__ float sm[kBlock / 64];
@@ -2448,15 +2502,17 @@ __global__ __launch_bounds__(kBlock) void k_prepare(PrepareArgs a) {
   if (threadIdx.x == 0 && d.slot >= 0) {
     float m = sm[0];
     for (int w = 1; w < kBlock / 64; ++w) m = fmaxf(m, sm[w]);
-    a.mx[d.slot + (d.batched ? b : 0)] = __float_as_uint(m);
-    a.ex[d.slot + (d.batched ? b : 0)] = 0;
+    // workgroup sub of a large leaf: sub-slot sub (the same sub-slots on
+    // every call, the others stay zero)
+    a.mx[sub * a.mx_stride + d.slot + (d.batched ? b : 0)] = __float_as_uint(m);
+    if (sub == 0) a.ex[d.slot + (d.batched ? b : 0)] = 0;
   }
 }
 
 void launch_prepare(const PrepareArgs &a, void *stream) {
   const int reset_blocks = (a.reset_end - a.reset_begin + kBlock - 1) / kBlock;
   // interleaved batched leaves take one thread per instance
-  dim3 g(a.n_leaves + (reset_blocks > 0 ? (reset_blocks > 1024 ? 1024 : reset_blocks) : 0),
+  dim3 g(a.n_leaves + a.big_blk0[a.n_big] + (reset_blocks > 0 ? (reset_blocks > 1024 ? 1024 : reset_blocks) : 0),
          a.interleaved ? (a.batch + kBlock - 1) / kBlock : a.batch);
   if (g.x == 0) return;
   k_prepare<<<g, kBlock, 0, (hipStream_t)stream>>>(a);
