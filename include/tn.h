@@ -115,7 +115,12 @@ typedef struct {
   int32_t host_only;         /* build host structures only (no device memory);
                                 only tn_plan_info_get / tn_plan_tree / tn_free_plan
                                 may then be called */
-  int32_t no_fuse;           /* keep every tree node a separate contraction */
+  int32_t no_fuse;           /* 0: fuse chains of small-operand contractions into
+                                segments and run two consecutive segments of a
+                                chain as one carrier pass where the tiles fit
+                                (the intermediate carrier is never stored);
+                                1: keep every tree node a separate contraction;
+                                2: segments, one carrier pass each */
   int32_t autotune;          /* 1: at plan time, time every eligible kernel form
                                 (generic, row, wave, dense) of each distinct
                                 contraction shape on the device and keep the
@@ -405,7 +410,9 @@ void tn_tune_clear(void);
 /* Contractions of one task, for inspection: per contraction its kernel form
  * (0 generic one lane per output, 1 row, 2 dense on the matrix cores or, for
  * max-plus, the vector ALUs, 3 wave per output, 4 interleaved instances, 5
- * fused-segment kernel), semiring (0 sum-product, 1 max-plus), the label
+ * fused-segment kernel with variant 1 carrier pass, 2 its reverse, 3
+ * composed maps, 4 adjoint sweeps, 5 carrier pass of two consecutive
+ * segments, 6 its reverse), semiring (0 sum-product, 1 max-plus), the label
  * classes' sizes (rows = output labels held by X, columns = output labels X
  * lacks, summed = labels of X or Y not in the output) and the operands'
  * elements per instance.  task: 0 forward sum-product (fused list when the

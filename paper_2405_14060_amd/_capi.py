@@ -261,7 +261,7 @@ def make_opts(semirings=SUM_PRODUCT | MAX_PLUS, evidence_mode=EVIDENCE_NONE, obs
               query=None, planner=PLANNER_BEST, restarts=4, seed=0, max_log2_size=0.0,
               dtype=TN_F32, max_batch=1, use_graph=True, stream=None, tree=None,
               want_factor_grad=False, host_only=False, fuse=True, autotune=False, batch_layout=0,
-              joint_sets=None):
+              joint_sets=None, pair_segments=True):
     o = PlanOpts()
     lib().tn_plan_opts_default(ctypes.byref(o))
     keep = []
@@ -292,7 +292,7 @@ def make_opts(semirings=SUM_PRODUCT | MAX_PLUS, evidence_mode=EVIDENCE_NONE, obs
         o.n_tree_pairs = int(t.shape[0])
     o.want_factor_grad = 1 if want_factor_grad else 0
     o.host_only = 1 if host_only else 0
-    o.no_fuse = 0 if fuse else 1
+    o.no_fuse = (0 if pair_segments else 2) if fuse else 1
     o.autotune = 1 if autotune else 0
     o.batch_layout = batch_layout
     if joint_sets:

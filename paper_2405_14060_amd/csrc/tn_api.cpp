@@ -807,7 +807,7 @@ static Schedule build_schedule(tn_plan_t *p, const std::vector<Op> &ops, bool al
         if (stage[i] == st && ops[i].seg >= 0 && ops[i].seg_kind == kind) L.ops.push_back(i);
       if (!L.ops.empty()) sc.launches.push_back(std::move(L));
     }
-    for (int kind = 1; kind <= 2; ++kind) {  // carrier transforms: two independent segments per launch
+    for (int kind : {1, 2, 5, 6}) {  // carrier passes: two independent ones of a kind per launch
       std::vector<int> ids;
       for (int i = 0; i < n; ++i)
         if (stage[i] == st && ops[i].seg >= 0 && ops[i].seg_kind == kind) ids.push_back(i);
@@ -851,7 +851,7 @@ static Schedule build_schedule(tn_plan_t *p, const std::vector<Op> &ops, bool al
 
 static void upload_schedule(tn_plan_t *p, Schedule &sc, const std::vector<Op> &ops) {
   for (Launch &L : sc.launches) {
-    if (L.seg && L.seg_kind >= 3) {
+    if (L.seg && (L.seg_kind == 3 || L.seg_kind == 4)) {
       std::vector<int32_t> ids;
       L.lds = 0;
       for (int i : L.ops) {
@@ -1366,6 +1366,9 @@ static bool describe_segment(tn_plan_t *p, const std::vector<Op> &ops, const std
   if (fin_lds > 15 * 1024) return false;
   if (!commit) return true;
   sp.ops = chain;
+  sp.loc_in = Loc[0];
+  sp.loc_out = Loc[L];
+  sp.outer = O;
   sp.c0 = ops[chain[0]].X;
   sp.cL = ops[chain[L - 1]].Z;
   sp.nO = (uint32_t)nO;
@@ -1466,6 +1469,128 @@ static bool describe_segment(tn_plan_t *p, const std::vector<Op> &ops, const std
   return true;
 }
 
+// Labels faster in a carrier (labels TL) than all of the tile's column
+// labels `cols`: log2 of their assignments, when a power of two up to 2^5,
+// else 5 (every local entry fastest).
+static int32_t tile_lo_shift(const Labels &loc, const Labels &cols, const std::vector<int> &card) {
+  const int fc = cols.empty() ? -1 : cols.back();
+  int64_t n = 1;
+  for (int v : loc)
+    if (v > fc) n *= card[v];
+  int sh = 0;
+  while ((int64_t(1) << sh) < n) ++sh;
+  return (int64_t(1) << sh) == n && sh <= 5 ? sh : 5;
+}
+
+// Segments s1 and s2 (s2's input carrier is s1's output) as one carrier
+// pass: the labels of the pass (DSegArgs), the workgroup shape and the
+// tables.  False when a tile would not fit: at most 32 assignments of Q and
+// of R (at least four outer assignments per workgroup).
+static bool describe_pair(tn_plan_t *p, int s1, int s2, DSegPlan &dp, bool commit) {
+  const SegPlan &a = p->segs[s1], &b = p->segs[s2];
+  const auto &card = p->card;
+  const Labels &V0 = p->T[a.c0].lab, &V2 = p->T[b.cL].lab;
+  const Labels &A = a.loc_in, &B = a.loc_out, &C = b.loc_in, &D = b.loc_out;
+  const Labels P = inter(C, B), Q = inter(C, a.outer), R = minus(B, C), O = minus(a.outer, Q);
+  if (unite(P, Q) != C || !minus(O, V2).empty()) return false;
+  const int64_t nQ = numel(Q, card), nR = numel(R, card), nO = numel(O, card);
+  if (nQ > kSegMaxLocal || nR > kSegMaxLocal || O.empty()) return false;
+  int nob = kSegOuterBlock;
+  while ((int64_t)nob * std::max(nQ, nR) > kSegOuterBlock) nob >>= 1;
+  if (nob < 4 || nO >= (int64_t(1) << 31)) return false;
+  if (!commit) return true;
+  dp.s1 = s1;
+  dp.s2 = s2;
+  dp.nO = (uint32_t)nO;
+  const size_t os = lo_split(O, card);
+  dp.nOl = (uint32_t)numel(Labels(O.begin() + os, O.end()), card);
+  add_tabs(p, O, os, V0, dp.oX);
+  add_tabs(p, O, os, V2, dp.oZ);
+  dp.nob = nob;
+  dp.nQ = (int32_t)nQ;
+  dp.nR = (int32_t)nR;
+  // column order: the tile's fastest column label decides which part of a
+  // column runs fastest
+  const Labels colX = unite(Q, O), colZ = unite(R, O);
+  dp.q_fast = !Q.empty() && Q.back() == colX.back();
+  dp.r_fast = !R.empty() && R.back() == colZ.back();
+  dp.in_lo_shift = tile_lo_shift(A, colX, card);
+  dp.out_lo_shift = tile_lo_shift(D, colZ, card);
+  dp.n_part = (int32_t)((nO + nob - 1) / nob);
+  std::vector<int32_t> t(kDSegTab * kSegMaxLocal, 0);
+  std::vector<int> val(p->n_vars, 0);
+  // offsets of the assignments of Lc (row-major) in a carrier with labels TL
+  auto offsets = [&](const Labels &Lc, const Labels &TL, int row) {
+    const int64_t n = numel(Lc, card);
+    std::vector<int> d(Lc.size(), 0);
+    for (int64_t i = 0; i < n; ++i) {
+      int64_t o = 0;
+      for (size_t k = 0; k < Lc.size(); ++k) o += (int64_t)d[k] * stride_in(TL, Lc[k], card);
+      t[row * kSegMaxLocal + i] = (int32_t)o;
+      for (int k = (int)Lc.size() - 1; k >= 0; --k) {
+        if (++d[k] < card[Lc[k]]) break;
+        d[k] = 0;
+      }
+    }
+  };
+  offsets(A, V0, 0);
+  offsets(D, V2, 1);
+  offsets(Q, V0, 2);
+  offsets(R, V2, 3);
+  offsets(R, B, 6);  // per r: its part of the index in B
+  {  // per c in C: the P part of its index in B and its index in Q
+    const int64_t n = numel(C, card);
+    std::vector<int> d(C.size(), 0);
+    for (int64_t i = 0; i < n; ++i) {
+      for (size_t k = 0; k < C.size(); ++k) val[C[k]] = d[k];
+      int64_t pb = 0, qi = 0;
+      for (int v : P) pb += (int64_t)val[v] * stride_in(B, v, card);
+      for (int v : Q) qi += (int64_t)val[v] * stride_in(Q, v, card);
+      t[4 * kSegMaxLocal + i] = (int32_t)pb;
+      t[5 * kSegMaxLocal + i] = (int32_t)qi;
+      for (int k = (int)C.size() - 1; k >= 0; --k) {
+        if (++d[k] < card[C[k]]) break;
+        d[k] = 0;
+      }
+    }
+  }
+  dp.tab = (int64_t)p->tabs.size();
+  p->tabs.insert(p->tabs.end(), t.begin(), t.end());
+  dp.bytes_fwd = 4.0 * (double)(p->T[a.c0].size + p->T[b.cL].size);
+  dp.bytes_bwd = 4.0 * (double)(2 * p->T[a.c0].size + p->T[b.cL].size);
+  dp.flops = a.flops + b.flops;
+  return true;
+}
+
+// Pairs of consecutive segments along each chain, from its start.
+static void plan_pairs(tn_plan_t *p) {
+  std::map<int, int> by_input;  // input carrier -> segment
+  for (size_t si = 0; si < p->segs.size(); ++si) by_input[p->segs[si].c0] = (int)si;
+  std::vector<char> has_prev(p->segs.size(), 0);
+  for (size_t si = 0; si < p->segs.size(); ++si) {
+    auto it = by_input.find(p->segs[si].cL);
+    if (it != by_input.end()) has_prev[it->second] = 1;
+  }
+  for (size_t s0 = 0; s0 < p->segs.size(); ++s0) {
+    if (has_prev[s0]) continue;
+    int cur = (int)s0;
+    while (cur >= 0) {
+      auto it = by_input.find(p->segs[cur].cL);
+      const int nxt = it == by_input.end() ? -1 : it->second;
+      DSegPlan dp;
+      if (nxt >= 0 && describe_pair(p, cur, nxt, dp, false)) {
+        describe_pair(p, cur, nxt, dp, true);
+        p->segs[cur].pair = p->segs[nxt].pair = (int)p->dsegs.size();
+        p->dsegs.push_back(dp);
+        auto it2 = by_input.find(p->segs[nxt].cL);
+        cur = it2 == by_input.end() ? -1 : it2->second;
+      } else {
+        cur = nxt;
+      }
+    }
+  }
+}
+
 static void build_fusion(tn_plan_t *p, std::vector<char> &need, int L_leaves) {
   const std::vector<Op> &ops = p->sum_tree.ops;
   const int n = (int)ops.size();
@@ -1516,6 +1641,7 @@ static void build_fusion(tn_plan_t *p, std::vector<char> &need, int L_leaves) {
   }
   if (p->segs.empty()) return;
   p->fused = true;
+  if (p->opts.no_fuse == 0) plan_pairs(p);
   // forward list: at the position of a segment's last node, the composed
   // map (it reads the small operands only, so the schedule hoists it) and
   // the carrier transform
@@ -1530,6 +1656,7 @@ static void build_fusion(tn_plan_t *p, std::vector<char> &need, int L_leaves) {
     }
     SegPlan &sp = p->segs[seg_of[i]];
     if (i != sp.ops.back()) continue;
+    const int pr = sp.pair;
     Op m;
     m.seg = seg_of[i];
     m.seg_kind = 3;
@@ -1538,14 +1665,27 @@ static void build_fusion(tn_plan_t *p, std::vector<char> &need, int L_leaves) {
     for (int j : sp.ops) m.flops += 2.0 * p->T[ops[j].Y].size * sp.n_in0;
     m.bytes = 4.0 * sp.n_outL * sp.n_in0;
     p->ffwd.push_back(m);
+    if (pr >= 0 && p->dsegs[pr].s1 == seg_of[i]) continue;  // its carrier pass is the pair's
     Op op;
-    op.seg = seg_of[i];
-    op.seg_kind = 1;
-    op.X = sp.c0;
-    op.Z = sp.cL;
-    op.ins.push_back(sp.mt);
-    op.flops = sp.flops;
-    op.bytes = sp.bytes_fwd;
+    if (pr >= 0) {  // both segments of the pair: C_0 -> C_2
+      const DSegPlan &dp = p->dsegs[pr];
+      op.seg = pr;
+      op.seg_kind = 5;
+      op.X = p->segs[dp.s1].c0;
+      op.Z = sp.cL;
+      op.ins.push_back(p->segs[dp.s1].mt);
+      op.ins.push_back(sp.mt);
+      op.flops = dp.flops;
+      op.bytes = dp.bytes_fwd;
+    } else {
+      op.seg = seg_of[i];
+      op.seg_kind = 1;
+      op.X = sp.c0;
+      op.Z = sp.cL;
+      op.ins.push_back(sp.mt);
+      op.flops = sp.flops;
+      op.bytes = sp.bytes_fwd;
+    }
     p->ffwd.push_back(op);
   }
   // reverse list: the two adjoint contractions of every fused node are
@@ -1568,11 +1708,11 @@ static void build_fusion(tn_plan_t *p, std::vector<char> &need, int L_leaves) {
       if (p->adj_tensor[xnode] >= 0) adj_to_seg[p->adj_tensor[xnode]] = (int)si;
     }
     if (any) {
-      sp.n_part = (int32_t)((sp.nO + kSegOuterBlock - 1) / kSegOuterBlock);
+      sp.n_part = sp.pair >= 0 ? p->dsegs[sp.pair].n_part : (int32_t)((sp.nO + kSegOuterBlock - 1) / kSegOuterBlock);
       sp.spt = new_raw_tensor(p, (int64_t)sp.n_part * sp.n_outL * sp.n_in0, true);
     }
   }
-  std::vector<char> emitted(p->segs.size(), 0);
+  std::vector<char> emitted(p->segs.size(), 0), pair_emitted(p->dsegs.size(), 0);
   for (const Op &op : p->bwd) {
     auto it = adj_to_seg.find(op.Z);
     if (it == adj_to_seg.end()) {
@@ -1583,17 +1723,36 @@ static void build_fusion(tn_plan_t *p, std::vector<char> &need, int L_leaves) {
     if (emitted[si]) continue;
     emitted[si] = 1;
     SegPlan &sp = p->segs[si];
-    Op b;
-    b.seg = si;
-    b.seg_kind = 2;
-    b.X = sp.g;
-    b.Z = sp.c0bar;
-    b.ins.push_back(sp.c0);
-    b.ins.push_back(sp.mt);
-    if (sp.spt >= 0) b.outs.push_back(sp.spt);
-    b.flops = 2 * sp.flops;
-    b.bytes = sp.bytes_bwd;
-    p->fbwd.push_back(b);
+    if (sp.pair < 0) {
+      Op b;
+      b.seg = si;
+      b.seg_kind = 2;
+      b.X = sp.g;
+      b.Z = sp.c0bar;
+      b.ins.push_back(sp.c0);
+      b.ins.push_back(sp.mt);
+      if (sp.spt >= 0) b.outs.push_back(sp.spt);
+      b.flops = 2 * sp.flops;
+      b.bytes = sp.bytes_bwd;
+      p->fbwd.push_back(b);
+    } else if (!pair_emitted[sp.pair]) {  // the pair's reverse pass: adjoint of C_2 -> adjoint of C_0
+      pair_emitted[sp.pair] = 1;
+      const DSegPlan &dp = p->dsegs[sp.pair];
+      const SegPlan &s1 = p->segs[dp.s1], &s2 = p->segs[dp.s2];
+      Op b;
+      b.seg = sp.pair;
+      b.seg_kind = 6;
+      b.X = s2.g;
+      b.Z = s1.c0bar;
+      b.ins.push_back(s1.c0);
+      b.ins.push_back(s1.mt);
+      b.ins.push_back(s2.mt);
+      if (s1.spt >= 0) b.outs.push_back(s1.spt);
+      if (s2.spt >= 0) b.outs.push_back(s2.spt);
+      b.flops = 2 * dp.flops;
+      b.bytes = dp.bytes_bwd;
+      p->fbwd.push_back(b);
+    }
     if (sp.spt < 0) continue;
     Op f;
     f.seg = si;
@@ -1609,6 +1768,18 @@ static void build_fusion(tn_plan_t *p, std::vector<char> &need, int L_leaves) {
     f.bytes = 4.0 * (double)sp.n_part * sp.n_outL * sp.n_in0;
     f.flops = 2.0 * (double)sp.n_part * sp.n_outL * sp.n_in0;
     p->fbwd.push_back(f);
+  }
+  // a pair never writes its intermediate carrier C_1 nor its adjoint: no
+  // other contraction may read them
+  for (const DSegPlan &dp : p->dsegs) {
+    const int c1 = p->segs[dp.s1].cL, c1bar = p->segs[dp.s1].g;
+    for (const auto *L : {&p->ffwd, &p->fbwd})
+      for (const Op &op : *L) {
+        if (op.seg >= 0 && op.seg_kind != 1 && op.seg_kind != 2) continue;  // small operands / pairs
+        bool reads = op.X == c1 || op.Y == c1 || op.X == c1bar || op.Y == c1bar;
+        for (int t : op.ins) reads = reads || t == c1 || t == c1bar;
+        if (reads) throw TnError(TN_E_INVALID, "internal: a paired segments' carrier has another reader");
+      }
   }
   (void)L_leaves;
 }
@@ -1682,6 +1853,65 @@ static void upload_segments(tn_plan_t *p) {
     if (kind) p->d_seg_bwd = d;
     else p->d_seg_fwd = d;
   }
+  for (int kind = 0; kind < 2; ++kind) {
+    std::vector<DSegArgs> &H = kind ? p->dseg_bwd_h : p->dseg_fwd_h;
+    for (const DSegPlan &dp : p->dsegs) {
+      const SegPlan &s1 = p->segs[dp.s1], &s2 = p->segs[dp.s2];
+      DSegArgs a;
+      a.arena = p->arena;
+      a.mx = p->mx;
+      a.ex = p->ex;
+      a.mx_stride = std::max(1, p->n_slots);
+      a.X = p->T[s1.c0].off;
+      a.slotX = p->T[s1.c0].slot;
+      a.M1 = p->T[s1.mt].off;
+      a.slotM1 = p->T[s1.mt].slot;
+      a.M2 = p->T[s2.mt].off;
+      a.slotM2 = p->T[s2.mt].slot;
+      a.nO = dp.nO;
+      a.nOl = dp.nOl;
+      if ((dp.nOl & (dp.nOl - 1)) == 0) {
+        int sh = 0;
+        while ((1u << sh) < dp.nOl) ++sh;
+        a.ol_shift = sh;
+      }
+      a.oX = Tab2{p->d_tabs + dp.oX[0], p->d_tabs + dp.oX[1]};
+      a.oZ = Tab2{p->d_tabs + dp.oZ[0], p->d_tabs + dp.oZ[1]};
+      a.nob = dp.nob;
+      a.nA = s1.n_in0;
+      a.nB = s1.n_outL;
+      a.nC = s2.n_in0;
+      a.nD = s2.n_outL;
+      a.nQ = dp.nQ;
+      a.nR = dp.nR;
+      a.q_fast = dp.q_fast;
+      a.r_fast = dp.r_fast;
+      a.in_lo_shift = dp.in_lo_shift;
+      a.out_lo_shift = dp.out_lo_shift;
+      a.tab = p->d_tabs + dp.tab;
+      a.prec = p->opts.dtype;
+      if (!kind) {
+        a.Z = p->T[s2.cL].off;
+        a.slotZ = p->T[s2.cL].slot;
+      } else {
+        a.G = p->T[s2.g].off;
+        a.slotG = p->T[s2.g].slot;
+        a.Z = p->T[s1.c0bar].off;
+        a.slotZ = p->T[s1.c0bar].slot;
+        if (s1.spt >= 0) {
+          if (s1.n_part != dp.n_part) throw TnError(TN_E_INVALID, "internal: pair partial count");
+          a.Sp1 = p->T[s1.spt].off;
+          a.slotSp1 = p->T[s1.spt].slot;
+        }
+        if (s2.spt >= 0) {
+          if (s2.n_part != dp.n_part) throw TnError(TN_E_INVALID, "internal: pair partial count");
+          a.Sp2 = p->T[s2.spt].off;
+          a.slotSp2 = p->T[s2.spt].slot;
+        }
+      }
+      H.push_back(a);
+    }
+  }
 }
 
 static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
@@ -1699,6 +1929,7 @@ static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
   p->want_sum = (o->semiring_mask & TN_SUM_PRODUCT) != 0;
   p->want_max = (o->semiring_mask & TN_MAX_PLUS) != 0;
   p->want_grad = o->want_factor_grad != 0;
+  if (o->no_fuse < 0 || o->no_fuse > 2) throw TnError(TN_E_INVALID, "no_fuse: 0, 1 or 2");
   if (o->dtype < TN_F32 || o->dtype > TN_F16) throw TnError(TN_E_INVALID, "unknown dtype");
   p->is_obs.assign(p->n_vars, 0);
   if (p->mode == TN_EVIDENCE_SLICED) {
@@ -1921,7 +2152,7 @@ static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
       p->joint_row = col;
     }
     if (!p->batched_ev) build_sampling(p, t);
-    if (!p->opts.no_fuse && !p->batched_ev) build_fusion(p, need, L);
+    if (p->opts.no_fuse != 1 && !p->batched_ev) build_fusion(p, need, L);
   }
   if (p->want_max) {
     TreeExec &t = p->max_tree;
@@ -2132,6 +2363,8 @@ void run_sched(tn_plan_t *p, const std::vector<Op> &ops, const Schedule &sc) {
           if (seg2 >= 0) launch_seg_bwd2(p->seg_bwd_h[op.seg], p->seg_bwd_h[seg2], p->stream);
           else launch_seg_bwd(p->seg_bwd_h[op.seg], p->stream);
           break;
+        case 5: launch_dseg_fwd(p->dseg_fwd_h[op.seg], seg2 >= 0 ? &p->dseg_fwd_h[seg2] : nullptr, p->stream); break;
+        case 6: launch_dseg_bwd(p->dseg_bwd_h[op.seg], seg2 >= 0 ? &p->dseg_bwd_h[seg2] : nullptr, p->stream); break;
         case 3: launch_seg_mat(p->d_seg_fwd, L.d_ids, (int)L.ops.size(), L.lds, p->stream); break;
         default: launch_seg_fin(p->d_seg_bwd, L.d_ids, (int)L.ops.size(), L.lds, p->stream); break;
       }
@@ -2887,7 +3120,9 @@ static tn_status profile_impl(tn_plan_t *p, int32_t task, int32_t batch, const i
           by += op.seg >= 0 ? op.bytes : (op.bytes + (op.semi == SEMI_MAX ? 4.0 * p->T[op.Z].size : 0.0)) * op.inst;
         }
         int kind;
-        if (L.seg) kind = 5 + L.seg_kind;  // 6 carrier forward, 7 carrier reverse, 8 composed maps, 9 adjoint sweeps
+        if (L.seg) kind = L.seg_kind >= 5 ? L.seg_kind + 1 : 5 + L.seg_kind;  // 6 carrier forward (one segment
+                                                                               // or a pair), 7 carrier reverse,
+                                                                               // 8 composed maps, 9 adjoint sweeps
         else if (L.gemm) kind = L.semi == SEMI_MAX ? 11 : 10;
         else if (L.inter) kind = L.semi == SEMI_MAX ? 13 : 12;
         else kind = (L.split ? 2 : 0) + (L.semi == SEMI_MAX ? 1 : 0);

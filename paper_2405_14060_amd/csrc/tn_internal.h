@@ -252,6 +252,47 @@ void launch_seg_mat(const SegArgs *d_base, const int32_t *d_ids, int n, int lds_
 void launch_seg_fin(const SegArgs *d_base, const int32_t *d_ids, int n, int lds_floats, void *stream);
 unsigned seg_blocks(const SegArgs &a);  // workgroups of a carrier launch
 
+// Two consecutive segments of a chain in one carrier pass.  Segment 1 maps
+// C_0 to C_1 on local labels A -> B (map M1), segment 2 maps C_1 to C_2 on
+// C -> D (map M2).  C splits into P (labels of B) and Q (outer labels of
+// segment 1), R = B \ C passes through segment 2 and O, the other outer
+// labels, is common to C_0, C_1 and C_2.  The forward pass forms C_2 from
+// C_0 without writing C_1; the reverse pass recomputes C_1 and its adjoint
+// in LDS.
+struct DSegArgs {
+  float *arena = nullptr;
+  uint32_t *mx = nullptr;
+  int32_t *ex = nullptr;
+  int32_t mx_stride = 0;
+  int64_t X = 0, Z = 0, G = 0;     // forward: X = C_0, Z = C_2; reverse: G = adjoint of C_2,
+                                   // X = C_0, Z = adjoint of C_0
+  int32_t slotX = -1, slotZ = -1, slotG = -1;
+  int64_t M1 = 0, M2 = 0;          // composed maps (B x A and D x C, row-major)
+  int32_t slotM1 = -1, slotM2 = -1;
+  int64_t Sp1 = 0, Sp2 = 0;        // reverse: per-workgroup partials of each segment's S
+  int32_t slotSp1 = -1, slotSp2 = -1;  // (-1: that segment needs none)
+  uint32_t nO = 1, nOl = 1;        // assignments of O; split of its tables
+  int32_t ol_shift = -1;           // log2(nOl) when nOl is a power of two
+  Tab2 oX, oZ;                     // offsets of O's assignments in C_0 / C_2
+  int32_t nob = 1;                 // assignments of O per workgroup (power of two)
+  int32_t nA = 0, nB = 0, nC = 0, nD = 0, nQ = 1, nR = 1;
+  int32_t q_fast = 0, r_fast = 0;  // tile column order: 1 = the Q (R) assignment fastest
+  int32_t in_lo_shift = 5, out_lo_shift = 5;  // as in SegArgs, for C_0 and C_2
+  const int32_t *tab = nullptr;    // kDSegTab x 32 int32: offsets of A in C_0, of D in C_2,
+                                   // of Q in C_0, of R in C_2; per c in C its P part of the
+                                   // index in B and its Q index; per r its part of the index in B
+  int32_t prec = 0;
+};
+static constexpr int kDSegTab = 7;
+struct DSegPair {
+  DSegArgs a[2];
+  uint32_t split = 0;  // workgroups of the first
+};
+unsigned dseg_blocks(const DSegArgs &a);
+// one or two (b != nullptr) independent pairs of segments per launch
+void launch_dseg_fwd(const DSegArgs &a, const DSegArgs *b, void *stream);
+void launch_dseg_bwd(const DSegArgs &a, const DSegArgs *b, void *stream);
+
 struct LeafDesc {
   int32_t kind;      // 0 factor gather, 1 constant one-vector, 2 indicator
   int32_t var;       // indicator variable

@@ -2413,6 +2413,282 @@ void launch_seg_fin(const SegArgs *d_base, const int32_t *d_ids, int n, int lds_
 }
 
 // --------------------------------------------------------------------------
+// two consecutive segments in one carrier pass
+// --------------------------------------------------------------------------
+// A workgroup takes nob assignments of the common outer labels O.  Its X
+// tile is C_0 over A (rows) x (Q, o) (columns), its Z tile C_2 over D x
+// (R, o); the column order follows the carriers' memory order (q_fast,
+// r_fast).  Y = M1 X is C_1 over B x (Q, o).  Column (r, o) of the second
+// map's operand, row c = (p, q), is Y[P part of c + R part of r][column of
+// (q, o)]: per c the tables give the P part (pb) and the Q column part (qc),
+// per Z column the R part (yr, -1: no such column) and the o part (yc).
+
+unsigned dseg_blocks(const DSegArgs &a) { return (a.nO + (uint32_t)a.nob - 1) / (uint32_t)a.nob; }
+
+struct DSegShared {
+  int32_t colX[kSegOB], colZ[kSegOB];  // column offsets in C_0 / C_2 (-1: none)
+  int32_t yr[kSegOB], yc[kSegOB];      // per Z column: row and column parts in Y
+  int32_t locA[kSegMaxLocal], locD[kSegMaxLocal], pb[kSegMaxLocal], qc[kSegMaxLocal];
+  float m1[kSegMaxLocal * (kSegMaxLocal + 1)], m2[kSegMaxLocal * (kSegMaxLocal + 1)];
+  int32_t kx, kg;
+  int32_t exX, exG, exM1, exM2;
+};
+
+// D (16 x 16) += sum over k < 32 of A(i, k) B(k, j) for the lane's row i
+// and column j (both l % 16, bound by the caller): fa(k), fb(k) give the
+// lane's operands; register r of the result is row 4 (l / 16) + r.
+template <int PREC, class FA, class FB>
+__device__ __forceinline__ f32x4 mfma_k32(FA fa, FB fb) {
+  const int l = threadIdx.x & 63;
+  f32x4 acc = {};
+  if (PREC == 0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int k = 4 * q + (l >> 4);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(fa(k), fb(k), acc, 0, 0, 0);
+    }
+  } else {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      float av[4], bv[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = 16 * h + 4 * (l >> 4) + j;
+        av[j] = fa(k);
+        bv[j] = fb(k);
+      }
+      acc = mfma16_lp<PREC>(av, bv, acc);
+    }
+  }
+  return acc;
+}
+
+// Prologue: both maps (one entry of each per thread), then by waves 0-10:
+// column offsets of both tiles, local offsets, the gather tables, operand
+// maxima and (workgroup 0) exponents.  Every global read is independent.
+__device__ __forceinline__ void dseg_prologue(const DSegArgs &a, uint32_t blk, bool want_g, DSegShared &sh) {
+  const int t = threadIdx.x, l = t & 63;
+  {
+    const int r = t >> 5, c = t & 31;
+    const float x1 = ((gcfloat *)(a.arena + a.M1))[min(r, a.nB - 1) * a.nA + min(c, a.nA - 1)];
+    const float x2 = ((gcfloat *)(a.arena + a.M2))[min(r, a.nD - 1) * a.nC + min(c, a.nC - 1)];
+    sh.m1[r * (kSegMaxLocal + 1) + c] = (r < a.nB && c < a.nA) ? x1 : 0.f;
+    sh.m2[r * (kSegMaxLocal + 1) + c] = (r < a.nD && c < a.nC) ? x2 : 0.f;
+  }
+  const int wv = __builtin_amdgcn_readfirstlane(t) >> 6;
+  gint *tab = (gint *)a.tab;
+  if (wv < 4) {  // column offsets: waves 0-1 the X tile (A x (Q, o)), 2-3 the Z tile (D x (R, o))
+    const bool in = wv < 2;
+    const int c = t & (kSegOB - 1);
+    const int nq = in ? a.nQ : a.nR, fast = in ? a.q_fast : a.r_fast;
+    const int q = fast ? c % nq : c / a.nob, ol = fast ? c / nq : (c & (a.nob - 1));
+    const uint32_t o = blk * (uint32_t)a.nob + (uint32_t)ol, oc = min(o, a.nO - 1);
+    gint *hi = (gint *)(in ? a.oX.hi : a.oZ.hi), *lo = (gint *)(in ? a.oX.lo : a.oZ.lo);
+    int32_t oo;
+    if (a.ol_shift >= 0) oo = hi[oc >> a.ol_shift] + lo[oc & (a.nOl - 1)];
+    else oo = hi[oc / a.nOl] + lo[oc % a.nOl];
+    const int32_t qo = tab[(in ? 2 : 3) * kSegMaxLocal + min(q, nq - 1)];
+    (in ? sh.colX : sh.colZ)[c] = (q < nq && ol < a.nob && o < a.nO) ? oo + qo : -1;
+  } else if (wv == 4) {  // local offsets: lanes 0-31 A in C_0, 32-63 D in C_2
+    const int j = l & 31;
+    const int32_t v = tab[(l < 32 ? 0 : 1) * kSegMaxLocal + j];
+    (l < 32 ? sh.locA : sh.locD)[j] = v;
+  } else if (wv == 5) {  // per c: P part of the row in Y (lanes 0-31), Q column part (32-63)
+    const int j = l & 31;
+    const int32_t v = tab[(l < 32 ? 4 : 5) * kSegMaxLocal + j];
+    if (l < 32) sh.pb[j] = v;
+    else sh.qc[j] = a.q_fast ? v : v * a.nob;
+  } else if (wv == 6 || wv == 7) {  // per Z column: R part of the row in Y, o part of its column
+    const int c = t & (kSegOB - 1);
+    const int r = a.r_fast ? c % a.nR : c / a.nob, ol = a.r_fast ? c / a.nR : (c & (a.nob - 1));
+    const int32_t v = tab[6 * kSegMaxLocal + min(r, a.nR - 1)];
+    const bool ok = r < a.nR && ol < a.nob;
+    sh.yr[c] = ok ? v : -1;
+    sh.yc[c] = a.q_fast ? ol * a.nQ : ol;
+  } else if (wv == 8 || (wv == 9 && want_g)) {  // maxima of the operands (64 sub-slots)
+    const int slot = wv == 8 ? a.slotX : a.slotG;
+    const uint32_t v = ((gu32 *)a.mx)[l * a.mx_stride + slot];
+    const int k = max_exponent(__float_as_uint(wave_max(__uint_as_float(v))));
+    if (l == 0) (wv == 8 ? sh.kx : sh.kg) = k;
+  } else if (wv == 10 && blk == 0 && l == 0) {
+    sh.exX = a.ex[a.slotX];
+    sh.exM1 = a.ex[a.slotM1];
+    sh.exM2 = a.ex[a.slotM2];
+    if (want_g) sh.exG = a.ex[a.slotG];
+  }
+}
+
+// Operand of the second map: row k (an assignment c of C), column n (an
+// assignment (r, o) of the Z tile), read from the Y tile.
+__device__ __forceinline__ float dseg_b2(const DSegShared &sh, const float *ty, int nC, int k, int n) {
+  const int yr = sh.yr[n];
+  return (k < nC && yr >= 0) ? ty[(sh.pb[k] + yr) * kSegRow + sh.qc[k] + sh.yc[n]] : 0.f;
+}
+
+template <int PREC>
+__device__ __forceinline__ void dseg_fwd_body(const DSegArgs &a, const uint32_t blk) {
+  __shared__ float tx[kSegMaxLocal * kSegRow];  // C_0 tile, later the C_2 tile
+  __shared__ float ty[kSegMaxLocal * kSegRow];  // C_1 tile
+  __shared__ DSegShared sh;
+  dseg_prologue(a, blk, false, sh);
+  __syncthreads();
+  const int kx = sh.kx;
+  seg_load(a.arena + a.X, sh.colX, sh.locA, a.nA, a.in_lo_shift, tx, ldexpf(1.f, -kx));
+  __syncthreads();
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = 16 * (w & 1) + (l & 15), n = 16 * (w >> 1) + (l & 15);
+  const f32x4 y = mfma_k32<PREC>([&](int k) { return sh.m1[i * (kSegMaxLocal + 1) + k]; },
+                                 [&](int k) { return tx[k * kSegRow + n]; });
+  seg_put(y, kSegMaxLocal, ty);
+  __syncthreads();
+  const int nC = a.nC;
+  const f32x4 z = mfma_k32<PREC>([&](int k) { return sh.m2[i * (kSegMaxLocal + 1) + k]; },
+                                 [&](int k) { return dseg_b2(sh, ty, nC, k, n); });
+  seg_put(z, a.nD, tx);
+  __syncthreads();
+  const float lmax = seg_store(a.arena + a.Z, sh.colZ, sh.locD, a.nD, a.out_lo_shift, tx);
+  block_record_max<kSegThreads, false>(lmax, a.mx + (blk % kMaxSub) * a.mx_stride + a.slotZ);
+  if (blk == 0 && threadIdx.x == 0) a.ex[a.slotZ] = sh.exX + kx + sh.exM1 + sh.exM2;
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kSegThreads) void k_dseg_fwd(const DSegPair g) {
+  const uint32_t second = blockIdx.x >= g.split ? 1u : 0u;
+  dseg_fwd_body<PREC>(g.a[second], blockIdx.x - second * g.split);
+}
+
+// Wave w's 16 x 16 quadrant (w % 4) of sum over the column quarter w / 4
+// of F(row, col) G(row', col): rows of F are the result's rows.
+template <int PREC, class F, class G>
+__device__ __forceinline__ f32x4 dseg_s_quadrant(F f, G gf) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int qr = w & 1, qc = (w >> 1) & 1, n0 = 32 * (w >> 2);
+  const int i = 16 * qr + (l & 15), j = 16 * qc + (l & 15);
+  return mfma_k32<PREC>([&](int k) { return f(i, n0 + k); }, [&](int k) { return gf(j, n0 + k); });
+}
+// The four quarters of a quadrant added in order (waves 4-15 park theirs in
+// park[]; waves 0-3 add them after a barrier), then the partial is written.
+__device__ __forceinline__ void dseg_s_park(const f32x4 &s, float *park) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (w >= 4) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) park[(w - 4) * 256 + r * 64 + l] = s[r];
+  }
+}
+__device__ __forceinline__ void dseg_s_write(const f32x4 &s, const float *park, float *part, int n_rows, int n_cols) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (w >= 4) return;
+  const int qr = w & 1, qc = w >> 1;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const float v = ((s[r] + park[w * 256 + r * 64 + l]) + park[(w + 4) * 256 + r * 64 + l]) +
+                    park[(w + 8) * 256 + r * 64 + l];
+    const int row = 16 * qr + 4 * (l >> 4) + r, col = 16 * qc + (l & 15);
+    if (row < n_rows && col < n_cols) part[row * n_cols + col] = v;
+  }
+}
+
+// Reverse: with G2 = the C_2 tile's adjoint and Y = M1 X recomputed,
+//   S2 = sum over columns of G2 B2^T (B2 = the second map's operand),
+//   G1 = M2^T G2 placed back into Y's layout (the adjoint of C_1),
+//   S1 = sum over columns of G1 X^T, and the adjoint of C_0 = M1^T G1.
+template <int PREC>
+__device__ __forceinline__ void dseg_bwd_body(const DSegArgs &a, const uint32_t blk) {
+  __shared__ float tg[kSegMaxLocal * kSegRow];  // G2 tile; later S2's parked quarters, then S1's
+  __shared__ float tx[kSegMaxLocal * kSegRow];  // C_0 tile; later its adjoint
+  __shared__ float ty[kSegMaxLocal * kSegRow];  // C_1 tile; later its adjoint
+  __shared__ DSegShared sh;
+  dseg_prologue(a, blk, true, sh);
+  __syncthreads();
+  const int kx = sh.kx, kg = sh.kg;
+  {
+    float vg[kSegIter], vx[kSegIter];
+    seg_fetch(a.arena + a.G, sh.colZ, sh.locD, a.nD, a.out_lo_shift, vg);
+    seg_fetch(a.arena + a.X, sh.colX, sh.locA, a.nA, a.in_lo_shift, vx);
+    seg_stash(vg, a.out_lo_shift, tg, ldexpf(1.f, -kg));
+    seg_stash(vx, a.in_lo_shift, tx, ldexpf(1.f, -kx));
+  }
+  __syncthreads();
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = 16 * (w & 1) + (l & 15), n = 16 * (w >> 1) + (l & 15);
+  const int nC = a.nC;
+  const f32x4 y = mfma_k32<PREC>([&](int k) { return sh.m1[i * (kSegMaxLocal + 1) + k]; },
+                                 [&](int k) { return tx[k * kSegRow + n]; });
+  const f32x4 wt = mfma_k32<PREC>([&](int k) { return sh.m2[k * (kSegMaxLocal + 1) + i]; },
+                                  [&](int k) { return tg[k * kSegRow + n]; });
+  seg_put(y, kSegMaxLocal, ty);  // rows past nB are zero (zero rows of M1)
+  __syncthreads();
+  const bool want2 = a.slotSp2 >= 0, want1 = a.slotSp1 >= 0;
+  f32x4 s2 = {};
+  if (want2)
+    s2 = dseg_s_quadrant<PREC>([&](int r, int c) { return tg[r * kSegRow + c]; },
+                               [&](int r, int c) { return dseg_b2(sh, ty, nC, r, c); });
+  __syncthreads();
+  // G1 over Y: every entry of a valid (row, column) of Y is written once; the
+  // rest of Y is zero
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int c = 16 * (w & 1) + 4 * (l >> 4) + r;
+    const int yr = sh.yr[n];
+    if (c < nC && yr >= 0) ty[(sh.pb[c] + yr) * kSegRow + sh.qc[c] + sh.yc[n]] = wt[r];
+  }
+  if (want2) dseg_s_park(s2, tg);
+  __syncthreads();
+  f32x4 s1 = {};
+  if (want1)
+    s1 = dseg_s_quadrant<PREC>([&](int r, int c) { return ty[r * kSegRow + c]; },
+                               [&](int r, int c) { return tx[r * kSegRow + c]; });
+  const f32x4 xb = mfma_k32<PREC>([&](int k) { return sh.m1[k * (kSegMaxLocal + 1) + i]; },
+                                  [&](int k) { return ty[k * kSegRow + n]; });
+  const int nP2 = a.nD * a.nC, nP1 = a.nB * a.nA;
+  if (want2) dseg_s_write(s2, tg, a.arena + a.Sp2 + (size_t)blk * nP2, a.nD, a.nC);
+  __syncthreads();
+  seg_put(xb, a.nA, tx);
+  if (want1) dseg_s_park(s1, tg);
+  __syncthreads();
+  const float lmax = seg_store(a.arena + a.Z, sh.colX, sh.locA, a.nA, a.in_lo_shift, tx);
+  if (want1) dseg_s_write(s1, tg, a.arena + a.Sp1 + (size_t)blk * nP1, a.nB, a.nA);
+  block_record_max<kSegThreads, false>(lmax, a.mx + (blk % kMaxSub) * a.mx_stride + a.slotZ);
+  if (blk == 0 && threadIdx.x == 0) {
+    const int eg = sh.exG + kg, exx = sh.exX + kx;
+    a.ex[a.slotZ] = eg + sh.exM2 + sh.exM1;
+    if (want2) a.ex[a.slotSp2] = eg + (exx + sh.exM1);
+    if (want1) a.ex[a.slotSp1] = (eg + sh.exM2) + exx;
+  }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kSegThreads) void k_dseg_bwd(const DSegPair g) {
+  const uint32_t second = blockIdx.x >= g.split ? 1u : 0u;
+  dseg_bwd_body<PREC>(g.a[second], blockIdx.x - second * g.split);
+}
+
+static DSegPair dseg_pair(const DSegArgs &a, const DSegArgs *b, unsigned &nb) {
+  DSegPair g;
+  g.a[0] = a;
+  g.a[1] = b ? *b : a;
+  g.split = dseg_blocks(a);
+  nb = g.split + (b ? dseg_blocks(*b) : 0u);
+  return g;
+}
+void launch_dseg_fwd(const DSegArgs &a, const DSegArgs *b, void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  unsigned nb = 0;
+  const DSegPair g = dseg_pair(a, b, nb);
+  if (a.prec == 1) k_dseg_fwd<1><<<nb, kSegThreads, 0, s>>>(g);
+  else if (a.prec == 2) k_dseg_fwd<2><<<nb, kSegThreads, 0, s>>>(g);
+  else k_dseg_fwd<0><<<nb, kSegThreads, 0, s>>>(g);
+}
+void launch_dseg_bwd(const DSegArgs &a, const DSegArgs *b, void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  unsigned nb = 0;
+  const DSegPair g = dseg_pair(a, b, nb);
+  if (a.prec == 1) k_dseg_bwd<1><<<nb, kSegThreads, 0, s>>>(g);
+  else if (a.prec == 2) k_dseg_bwd<2><<<nb, kSegThreads, 0, s>>>(g);
+  else k_dseg_bwd<0><<<nb, kSegThreads, 0, s>>>(g);
+}
+
+// --------------------------------------------------------------------------
 // leaf preparation: evidence slicing (gather), indicator vectors, maxima;
 // extra blocks clear the maxima of the tensors produced in this solve
 // --------------------------------------------------------------------------

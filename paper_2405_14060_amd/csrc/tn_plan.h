@@ -75,6 +75,20 @@ struct SegPlan {
   std::vector<int> ybar_tensor;       // reverse: adjoint tensor of each small operand (-1)
   int g = -1, c0bar = -1;             // reverse: adjoint tensors of C_L and C_0
   double bytes_fwd = 0, bytes_bwd = 0, flops = 0;
+  Labels loc_in, loc_out, outer;      // local labels of C_0 and C_L; outer labels
+  int pair = -1;                      // index of the two-segment pass holding it (-1: none)
+};
+
+// Two consecutive segments run as one carrier pass (DSegArgs).
+struct DSegPlan {
+  int s1 = -1, s2 = -1;               // segments: s1's output carrier is s2's input
+  uint32_t nO = 1, nOl = 1;           // common outer labels O
+  int64_t oX[2], oZ[2];               // their offset tables in C_0 and C_2
+  int32_t nob = 1, nQ = 1, nR = 1, q_fast = 0, r_fast = 0;
+  int32_t in_lo_shift = 5, out_lo_shift = 5;
+  int64_t tab = 0;                    // kDSegTab x 32 tables in the table store
+  int32_t n_part = 0;                 // workgroups
+  double bytes_fwd = 0, bytes_bwd = 0, flops = 0;
 };
 
 // One launch of a schedule: a single contraction, or several independent
@@ -169,6 +183,8 @@ struct tn_plan_impl {
   tn::Schedule sched_ffwd, sched_fbwd;
   tn::SegArgs *d_seg_fwd = nullptr, *d_seg_bwd = nullptr;
   std::vector<tn::SegArgs> seg_fwd_h, seg_bwd_h;
+  std::vector<tn::DSegPlan> dsegs;    // two-segment carrier passes
+  std::vector<tn::DSegArgs> dseg_fwd_h, dseg_bwd_h;
   std::vector<tn::Schedule> sched_groups;
   int seed_tensor = -1;                // adjoint of the root (ones)
   std::vector<int> adj_tensor;         // per node of sum_tree, -1 = none

@@ -77,3 +77,18 @@ def test_plan_tree_rejects_bad_tree_on_host(T):
     with pytest.raises(T.TNError) as ei:
         T.Plan(N, tree=np.array([[0, 1]], np.int32))
     assert ei.value.status == TN_E_INVALID
+
+
+def test_segment_pairs_on_host(T):
+    """Consecutive fused segments of a grid's chains run as pairs (one
+    carrier pass each) unless asked otherwise: fewer launches, same tree."""
+    net = W.grid_mrf(12, 12, 0)
+    P = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, host_only=True)
+    U = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, host_only=True, pair_segments=False)
+    assert np.array_equal(P.tree()[0], U.tree()[0])
+    vp = [o["variant"] for o in P.ops(0) + P.ops(1) if o["form"] == 5]
+    vu = [o["variant"] for o in U.ops(0) + U.ops(1) if o["form"] == 5]
+    assert 5 in vp and 6 in vp and 5 not in vu and 6 not in vu
+    # every pair replaces two single-segment passes in each direction
+    assert vp.count(5) == vp.count(6) and vu.count(1) == vp.count(1) + 2 * vp.count(5)
+    assert P.info()["n_launches_fwd"] < U.info()["n_launches_fwd"]
