@@ -1484,8 +1484,9 @@ static int32_t tile_lo_shift(const Labels &loc, const Labels &cols, const std::v
 
 // Segments s1 and s2 (s2's input carrier is s1's output) as one carrier
 // pass: the labels of the pass (DSegArgs), the workgroup shape and the
-// tables.  False when a tile would not fit: at most 32 assignments of Q and
-// of R (at least four outer assignments per workgroup).
+// tables.  False when a tile would not fit (at most 32 assignments of Q and
+// of R, at least four outer assignments per workgroup) or would leave a
+// large carrier's tile mostly empty.
 static bool describe_pair(tn_plan_t *p, int s1, int s2, DSegPlan &dp, bool commit) {
   const SegPlan &a = p->segs[s1], &b = p->segs[s2];
   const auto &card = p->card;
@@ -1498,6 +1499,11 @@ static bool describe_pair(tn_plan_t *p, int s1, int s2, DSegPlan &dp, bool commi
   int nob = kSegOuterBlock;
   while ((int64_t)nob * std::max(nQ, nR) > kSegOuterBlock) nob >>= 1;
   if (nob < 4 || nO >= (int64_t(1) << 31)) return false;
+  // a large carrier in a tile it fills less than three quarters of runs
+  // faster in a pass of its own
+  const double use_x = (double)a.n_in0 * nQ * nob / (kSegMaxLocal * kSegOuterBlock);
+  const double use_z = (double)b.n_outL * nR * nob / (kSegMaxLocal * kSegOuterBlock);
+  if ((use_x < 0.75 && p->T[a.c0].size >= (1 << 16)) || (use_z < 0.75 && p->T[b.cL].size >= (1 << 16))) return false;
   if (!commit) return true;
   dp.s1 = s1;
   dp.s2 = s2;
