@@ -1187,7 +1187,9 @@ static void allocate(tn_plan_t *p, const tn_net *net) {
       // the fused lists hold copies of the unfused contractions: same choice
       std::map<int, std::array<int, 3>> kind_of;  // output tensor -> form
       for (Op *op : all) kind_of[op->Z] = {op->a.kind, op->a.ksplit, op->a.tile};
-      for (auto *L : {&p->ffwd, &p->fbwd})
+      std::vector<std::vector<Op> *> lists{&p->ffwd, &p->fbwd};
+      for (auto &g : p->groups) lists.push_back(&g.fops);
+      for (auto *L : lists)
         for (Op &op : *L)
           if (op.seg < 0 && kind_of.count(op.Z)) {
             op.a.kind = kind_of[op.Z][0];
@@ -1207,9 +1209,23 @@ static void allocate(tn_plan_t *p, const tn_net *net) {
   upload_schedule(p, p->sched_q, p->qtree.ops);
   upload_schedule(p, p->sched_samp, p->samp_ops);
   for (auto &g : p->groups) {
-    p->sched_groups.push_back(build_schedule(p, g.ops, false));
-    upload_schedule(p, p->sched_groups.back(), g.ops);
+    if (g.fused) {  // contraction arguments of the fused list's unfused ops
+      std::vector<ContractArgs> host;
+      for (auto &op : g.fops)
+        if (op.seg < 0) {
+          fill_args(p, op);
+          host.push_back(op.a);
+        }
+      ContractArgs *d = dupload(p, host);
+      size_t k = 0;
+      for (auto &op : g.fops)
+        if (op.seg < 0) op.d_a = d + k++;
+    }
+    const std::vector<Op> &gl = g.fused ? g.fops : g.ops;
+    p->sched_groups.push_back(build_schedule(p, gl, false));
+    upload_schedule(p, p->sched_groups.back(), gl);
   }
+  if (!p->fused && !p->segs.empty()) upload_segments(p);
   if (p->fused) {
     for (auto &op : p->ffwd)
       if (op.seg < 0) fill_args(p, op);
@@ -1568,16 +1584,17 @@ static bool describe_pair(tn_plan_t *p, int s1, int s2, DSegPlan &dp, bool commi
   return true;
 }
 
-// Pairs of consecutive segments along each chain, from its start.
-static void plan_pairs(tn_plan_t *p) {
+// Pairs of consecutive segments along each chain, from its start (segments
+// s_begin.. of the plan).
+static void plan_pairs(tn_plan_t *p, size_t s_begin) {
   std::map<int, int> by_input;  // input carrier -> segment
-  for (size_t si = 0; si < p->segs.size(); ++si) by_input[p->segs[si].c0] = (int)si;
+  for (size_t si = s_begin; si < p->segs.size(); ++si) by_input[p->segs[si].c0] = (int)si;
   std::vector<char> has_prev(p->segs.size(), 0);
-  for (size_t si = 0; si < p->segs.size(); ++si) {
+  for (size_t si = s_begin; si < p->segs.size(); ++si) {
     auto it = by_input.find(p->segs[si].cL);
     if (it != by_input.end()) has_prev[it->second] = 1;
   }
-  for (size_t s0 = 0; s0 < p->segs.size(); ++s0) {
+  for (size_t s0 = s_begin; s0 < p->segs.size(); ++s0) {
     if (has_prev[s0]) continue;
     int cur = (int)s0;
     while (cur >= 0) {
@@ -1597,21 +1614,23 @@ static void plan_pairs(tn_plan_t *p) {
   }
 }
 
-static void build_fusion(tn_plan_t *p, std::vector<char> &need, int L_leaves) {
-  const std::vector<Op> &ops = p->sum_tree.ops;
+// Fused segments over a forward op list: chains of sum-product contractions
+// that absorb small operands (<= 64 entries) into a large carrier (>= 4096),
+// among the ops that `allowed` admits.  Appends the segments (and pairs of
+// consecutive ones) to the plan, writes the fused forward list to `fwd` and
+// returns every op's segment (-1: none); fwd stays empty without segments.
+static std::vector<int> fuse_forward(tn_plan_t *p, const std::vector<Op> &ops, const std::vector<char> &allowed,
+                                     std::vector<Op> &fwd) {
   const int n = (int)ops.size();
+  const size_t s_begin = p->segs.size();
   std::map<int, int> prod;
   for (int i = 0; i < n; ++i) prod[ops[i].Z] = i;
   std::vector<char> chainable(n, 0);
   for (int i = 0; i < n; ++i) {
     const Op &op = ops[i];
-    chainable[i] = op.semi == SEMI_SUM && op.Y >= 0 && !op.split && p->T[op.Y].size <= 64 &&
+    chainable[i] = allowed[i] && op.semi == SEMI_SUM && op.Y >= 0 && !op.split && p->T[op.Y].size <= 64 &&
                    p->T[op.X].size >= 4096 && !p->T[op.X].batched && !p->T[op.Y].batched;
   }
-  std::map<int, int> node_of;  // node of the sum tree that holds each tensor
-  for (size_t c = 0; c < p->sum_tree.node_tensor.size(); ++c) node_of[p->sum_tree.node_tensor[c]] = (int)c;
-  for (int i = 0; i < n; ++i)  // the reverse segment needs the carriers' adjoints
-    if (chainable[i] && !need[node_of.at(ops[i].X)]) chainable[i] = 0;
   std::vector<int> next(n, -1), has_prev(n, 0);
   for (int i = 0; i < n; ++i) {
     if (!chainable[i]) continue;
@@ -1645,19 +1664,18 @@ static void build_fusion(tn_plan_t *p, std::vector<char> &need, int L_leaves) {
       cur = after;
     }
   }
-  if (p->segs.empty()) return;
-  p->fused = true;
-  if (p->opts.no_fuse == 0) plan_pairs(p);
+  if (p->segs.size() == s_begin) return seg_of;
+  if (p->opts.no_fuse == 0) plan_pairs(p, s_begin);
   // forward list: at the position of a segment's last node, the composed
   // map (it reads the small operands only, so the schedule hoists it) and
   // the carrier transform
-  for (size_t si = 0; si < p->segs.size(); ++si) {
+  for (size_t si = s_begin; si < p->segs.size(); ++si) {
     SegPlan &sp = p->segs[si];
     sp.mt = new_raw_tensor(p, (int64_t)sp.n_outL * sp.n_in0, true);
   }
   for (int i = 0; i < n; ++i) {
     if (seg_of[i] < 0) {
-      p->ffwd.push_back(ops[i]);
+      fwd.push_back(ops[i]);
       continue;
     }
     SegPlan &sp = p->segs[seg_of[i]];
@@ -1670,7 +1688,7 @@ static void build_fusion(tn_plan_t *p, std::vector<char> &need, int L_leaves) {
     for (int j : sp.ops) m.ins.push_back(ops[j].Y);
     for (int j : sp.ops) m.flops += 2.0 * p->T[ops[j].Y].size * sp.n_in0;
     m.bytes = 4.0 * sp.n_outL * sp.n_in0;
-    p->ffwd.push_back(m);
+    fwd.push_back(m);
     if (pr >= 0 && p->dsegs[pr].s1 == seg_of[i]) continue;  // its carrier pass is the pair's
     Op op;
     if (pr >= 0) {  // both segments of the pair: C_0 -> C_2
@@ -1692,8 +1710,22 @@ static void build_fusion(tn_plan_t *p, std::vector<char> &need, int L_leaves) {
       op.flops = sp.flops;
       op.bytes = sp.bytes_fwd;
     }
-    p->ffwd.push_back(op);
+    fwd.push_back(op);
   }
+  return seg_of;
+}
+
+static void build_fusion(tn_plan_t *p, std::vector<char> &need, int L_leaves) {
+  const std::vector<Op> &ops = p->sum_tree.ops;
+  const int n = (int)ops.size();
+  std::map<int, int> node_of;  // node of the sum tree that holds each tensor
+  for (size_t c = 0; c < p->sum_tree.node_tensor.size(); ++c) node_of[p->sum_tree.node_tensor[c]] = (int)c;
+  std::vector<char> allowed(n, 0);
+  for (int i = 0; i < n; ++i)  // the reverse segment needs the carriers' adjoints
+    allowed[i] = ops[i].X >= 0 && node_of.count(ops[i].X) && need[node_of.at(ops[i].X)];
+  fuse_forward(p, ops, allowed, p->ffwd);
+  if (p->segs.empty()) return;
+  p->fused = true;
   // reverse list: the two adjoint contractions of every fused node are
   // replaced by one reverse segment at the position of the first of them
   std::map<int, int> adj_to_seg;  // adjoint tensor produced by a replaced op -> segment
@@ -1797,7 +1829,7 @@ static void upload_segments(tn_plan_t *p) {
       const int yt = (int)st.y;
       st.y = p->T[yt].off;
       st.yslot = p->T[yt].slot;
-      if (sp.ybar_tensor[j] >= 0) {
+      if (j < sp.ybar_tensor.size() && sp.ybar_tensor[j] >= 0) {
         st.ybar = p->T[sp.ybar_tensor[j]].off;
         st.ybar_slot = p->T[sp.ybar_tensor[j]].slot;
       }
@@ -1841,7 +1873,7 @@ static void upload_segments(tn_plan_t *p) {
         for (auto &x : st) x.ybar = -1;
         a.Z = p->T[sp.cL].off;
         a.slotZ = p->T[sp.cL].slot;
-      } else {
+      } else if (sp.g >= 0) {  // segments of a forward-only list have no reverse step
         a.G = p->T[sp.g].off;
         a.slotG = p->T[sp.g].slot;
         a.Z = p->T[sp.c0bar].off;
@@ -1899,7 +1931,7 @@ static void upload_segments(tn_plan_t *p) {
       if (!kind) {
         a.Z = p->T[s2.cL].off;
         a.slotZ = p->T[s2.cL].slot;
-      } else {
+      } else if (s2.g >= 0) {
         a.G = p->T[s2.g].off;
         a.slotG = p->T[s2.g].slot;
         a.Z = p->T[s1.c0bar].off;
@@ -2270,7 +2302,7 @@ extern "C" tn_status tn_plan_ops(const tn_plan_t *p, int32_t task, tn_op_info *o
     else if (task == 1) add(p->fused ? p->fbwd : p->bwd);
     else if (task == 2) add(p->max_tree.ops);
     else if (task == 3)
-      for (const auto &g : p->groups) add(g.ops);
+      for (const auto &g : p->groups) add(g.fused ? g.fops : g.ops);
     else throw TnError(TN_E_INVALID, "unknown task");
     *n = (int32_t)ops.size();
     for (size_t i = 0; i < ops.size() && (int32_t)i < cap; ++i) {
@@ -2961,6 +2993,10 @@ static void build_mmap(tn_plan_t *p, const tn_net *net) {
     p->stats.flops += st.flops * nsl;
     p->stats.bytes += st.bytes * nsl;
     build_forward(p, t, SEMI_SUM);
+    if (o.no_fuse != 1) {  // the sum phase runs forward only: every chain may fuse
+      fuse_forward(p, t.ops, std::vector<char>(t.ops.size(), 1), t.fops);
+      t.fused = !t.fops.empty();
+    }
     // log-domain copy of the group result: a leaf of the max phase
     int lg = new_tensor(p, outq, false, false);
     p->group_log.push_back(lg);
@@ -3044,7 +3080,7 @@ static void run_mmap(tn_plan_t *p, const int32_t *evidence, int32_t *assign_q, d
       }
       hip_check(hipMemcpyAsync(p->d_evidence, row.data(), row.size() * 4, hipMemcpyHostToDevice, p->stream), "slice");
       launch_prepare_set(p, p->group_leaves[g], p->d_group_leaves[g], true);
-      run_sched(p, t.ops, p->sched_groups[g]);
+      run_sched(p, t.fused ? t.fops : t.ops, p->sched_groups[g]);
       launch_slice_acc(p->arena + r.off, p->mx, p->ex, r.slot, p->d_acc, acc_ex, r.size, s == 0 ? 1 : 0, p->stream);
       hip_check(hipStreamSynchronize(p->stream), "slice");
     }
@@ -3162,7 +3198,7 @@ static tn_status profile_impl(tn_plan_t *p, int32_t task, int32_t batch, const i
       int32_t *acc_ex = p->iarena + p->iarena_ints;
       for (size_t g = 0; g < p->groups.size(); ++g) {
         ls.push_back({4, 0, 0, [p, g] { launch_prepare_set(p, p->group_leaves[g], p->d_group_leaves[g], true); }});
-        add_ops(p->groups[g].ops, p->sched_groups[g]);
+        add_ops(p->groups[g].fused ? p->groups[g].fops : p->groups[g].ops, p->sched_groups[g]);
         ls.push_back({5, 0, 0, [p, g, acc_ex] {
                         const TensorBuf &r = p->T[p->groups[g].root];
                         launch_slice_acc(p->arena + r.off, p->mx, p->ex, r.slot, p->d_acc, acc_ex, r.size, 1, p->stream);

@@ -65,6 +65,15 @@ struct PlanChoice {
 // max(launch cost + multiply-adds / rate).  n_levels (optional) = levels.
 static constexpr double kStageLaunchSeconds = 4e-6;
 static constexpr double kStageMacRate = 2e13;
+// Roofline estimate of one pass over a tree (seconds): per node a launch
+// plus the slower of its flops at its kernel form's rate and its operand and
+// output bytes at that form's HBM rate (rates measured on this GPU: the
+// matrix-core form on scattered tiles, and the one-lane-per-output forms).
+static constexpr double kNodeLaunchSeconds = 5e-6;
+static constexpr double kDenseFlopRate = 2.5e13, kDenseByteRate = 3e12;
+static constexpr double kVectorFlopRate = 8e12, kVectorByteRate = 1.8e12;
+double roofline_time(const std::vector<Labels> &leaves, const std::vector<Pair> &pairs, const Labels &out,
+                     const std::vector<int> &card);
 double stage_time(const std::vector<Labels> &leaves, const std::vector<Pair> &pairs, const Labels &out,
                   const std::vector<int> &card, int *n_levels);
 

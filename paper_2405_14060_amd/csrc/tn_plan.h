@@ -127,6 +127,8 @@ struct TreeExec {
   std::vector<int> node_tensor;       // tensor id of every node
   int root = -1;                      // tensor holding the result over `out`
   std::vector<Op> ops;
+  std::vector<Op> fops;               // forward list with fused segments (when fused)
+  bool fused = false;
   std::vector<std::vector<int>> node_ops;  // op indices per pair (reductions, then main)
   int root_op = -1;                   // op reducing the root to `out`, if any
   // max-plus only: readout steps

@@ -340,6 +340,35 @@ static std::vector<int> two_front(const std::vector<int> &order) {
   return r;
 }
 
+double roofline_time(const std::vector<Labels> &leaves, const std::vector<Pair> &pairs, const Labels &out,
+                     const std::vector<int> &card) {
+  const int L = (int)leaves.size();
+  const auto lab = node_labels(leaves, pairs, out, (int)card.size());
+  auto has = [](const Labels &l, int v) { return std::binary_search(l.begin(), l.end(), v); };
+  double t = 0;
+  for (size_t q = 0; q < pairs.size(); ++q) {
+    const Labels &A = lab[pairs[q][0]], &B = lab[pairs[q][1]], &C = lab[L + q];
+    const Labels U = merge_sorted(A, B);
+    double m = 0, n = 0, s = 0;  // log2 entries of rows, columns and summed labels
+    for (int v : U) {
+      const bool a = has(A, v), b = has(B, v), c = has(C, v);
+      const double lc = std::log2((double)card[v]);
+      if (a && !b && c) m += lc;
+      else if (b && !a && c) n += lc;
+      else if (a && b && !c) s += lc;
+    }
+    // the dense form's eligibility: >= 16 rows, >= 8 columns, >= 8 summed
+    // entries or none
+    const bool dense = m >= 4 - 1e-9 && n >= 3 - 1e-9 && (s >= 3 - 1e-9 || s < 1e-9);
+    const double flops = 2.0 * std::exp2(log2size(U, card));
+    const double bytes = 4.0 * (std::exp2(log2size(A, card)) + std::exp2(log2size(B, card)) +
+                                std::exp2(log2size(C, card)));
+    t += kNodeLaunchSeconds + std::max(flops / (dense ? kDenseFlopRate : kVectorFlopRate),
+                                       bytes / (dense ? kDenseByteRate : kVectorByteRate));
+  }
+  return t;
+}
+
 double stage_time(const std::vector<Labels> &leaves, const std::vector<Pair> &pairs, const Labels &out,
                   const std::vector<int> &card, int *n_levels) {
   const int L = (int)leaves.size(), P = (int)pairs.size();
@@ -389,15 +418,12 @@ PlanChoice plan_tree(const std::vector<Labels> &leaves, const std::vector<int> &
       for (size_t i = 0; i < leaves.size(); ++i)
         for (int v : leaves[i])
           if (!fixed[v]) lv[i].push_back(v);
-      const TreeStats ss = tree_stats(lv, pairs, out, card);
       double ns = 1;
       for (int v : sl) ns *= card[v];
-      // every slice also pays its launches: about 5 us per node, counted as
-      // 5e7 multiply-adds (20 TFLOP/s), so that many tiny slices do not win
-      const double per_slice = 5e7 * (double)pairs.size();
-      key = std::make_pair(std::round(2 * cap) / 2, std::log2(ss.flops * ns / 2 + per_slice * ns));
+      // every slice runs the sliced tree: its roofline time, launches included
+      key = std::make_pair(std::round(2 * cap) / 2, std::log2(ns * roofline_time(lv, pairs, out, card)));
     } else {
-      key.first = std::round(2 * cap) / 2;  // within the cap: ranked by work alone
+      key = std::make_pair(std::round(2 * cap) / 2, std::log2(roofline_time(leaves, pairs, out, card)));
     }
     if (!have || key < best_key) {
       best.pairs = std::move(pairs);
