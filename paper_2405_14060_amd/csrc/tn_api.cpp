@@ -864,29 +864,28 @@ static void upload_schedule(tn_plan_t *p, Schedule &sc, const std::vector<Op> &o
     }
     if (L.seg || L.ops.size() < 2) continue;
     std::vector<ContractArgs> args;
-    std::vector<uint32_t> st, nb, st2, nb2;
-    uint32_t tot = 0, tot2 = 0;
+    std::vector<uint32_t> nb, nb2;
+    std::vector<GroupBlock> bl, bl2;
     for (int i : L.ops) {
       const Op &op = ops[i];
+      const uint32_t k = (uint32_t)args.size();
       args.push_back(op.a);
       const uint32_t per = L.split ? op.a.n_chunks : map_blocks(op.a);
-      st.push_back(tot);
       nb.push_back(per);
-      tot += per * (uint32_t)op.nb;
+      for (uint32_t b = 0; b < per * (uint32_t)op.nb; ++b) bl.push_back(GroupBlock{k, b});
       if (L.split) {
         const uint32_t per2 = op.a.nR * op.a.nC;
-        st2.push_back(tot2);
         nb2.push_back(per2);
-        tot2 += per2 * (uint32_t)op.nb;
+        for (uint32_t b = 0; b < per2 * (uint32_t)op.nb; ++b) bl2.push_back(GroupBlock{k, b});
       }
     }
-    L.total = tot;
-    L.total2 = tot2;
+    L.total = (uint32_t)bl.size();
+    L.total2 = (uint32_t)bl2.size();
     L.d_args = dalloc_vec(p, args);
-    L.d_start = dalloc_vec(p, st);
+    L.d_blk = dalloc_vec(p, bl);
     L.d_nblk = dalloc_vec(p, nb);
     if (L.split) {
-      L.d_start2 = dalloc_vec(p, st2);
+      L.d_blk2 = dalloc_vec(p, bl2);
       L.d_nblk2 = dalloc_vec(p, nb2);
     }
   }
@@ -2410,15 +2409,15 @@ void run_sched(tn_plan_t *p, const std::vector<Op> &ops, const Schedule &sc) {
       const Op &op = ops[L.ops[0]];
       launch_contract(op.semi, op.Y >= 0, op.split, op.a, op.d_a, op.nb, p->stream);
     } else if (L.gemm) {
-      launch_group(L.semi, 3 + (L.semi == SEMI_SUM ? p->opts.dtype : 0), L.d_args, L.d_start, L.d_nblk,
+      launch_group(L.semi, 3 + (L.semi == SEMI_SUM ? p->opts.dtype : 0), L.d_args, L.d_blk, L.d_nblk,
                    (int)L.ops.size(), L.total, p->stream);
     } else if (L.inter) {
-      launch_group(L.semi, 6, L.d_args, L.d_start, L.d_nblk, (int)L.ops.size(), L.total, p->stream);
+      launch_group(L.semi, 6, L.d_args, L.d_blk, L.d_nblk, (int)L.ops.size(), L.total, p->stream);
     } else if (!L.split) {
-      launch_group(L.semi, 0, L.d_args, L.d_start, L.d_nblk, (int)L.ops.size(), L.total, p->stream);
+      launch_group(L.semi, 0, L.d_args, L.d_blk, L.d_nblk, (int)L.ops.size(), L.total, p->stream);
     } else {
-      launch_group(L.semi, 1, L.d_args, L.d_start, L.d_nblk, (int)L.ops.size(), L.total, p->stream);
-      launch_group(L.semi, 2, L.d_args, L.d_start2, L.d_nblk2, (int)L.ops.size(), L.total2, p->stream);
+      launch_group(L.semi, 1, L.d_args, L.d_blk, L.d_nblk, (int)L.ops.size(), L.total, p->stream);
+      launch_group(L.semi, 2, L.d_args, L.d_blk2, L.d_nblk2, (int)L.ops.size(), L.total2, p->stream);
     }
   }
 }

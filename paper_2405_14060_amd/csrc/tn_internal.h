@@ -179,7 +179,12 @@ void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, co
 uint32_t map_blocks(const ContractArgs &a);
 // phase 0: map, 1: split partials, 2: split finish, 3 + p: dense form with
 // operand precision p, 6: interleaved form
-void launch_group(int semi, int phase, const ContractArgs *ops, const uint32_t *start,
+// blk: per workgroup of the launch, its contraction and its workgroup index
+// within that contraction (one read instead of a search over the ops)
+struct GroupBlock {
+  uint32_t op, local;
+};
+void launch_group(int semi, int phase, const ContractArgs *ops, const GroupBlock *blk,
                   const uint32_t *nblk, int n, uint32_t total_blocks, void *stream);
 
 // Fused chain segment: consecutive tree nodes that each contract the

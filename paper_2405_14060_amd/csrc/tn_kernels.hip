@@ -1590,32 +1590,20 @@ __global__ __launch_bounds__(kBlock) void k_split_finish(const ContractArgs *__r
 }
 
 // Several independent contractions in one launch (one stage of the tree
-// schedule).  Block ranges: op i owns blocks [start[i], start[i+1]), split
-// as instance-major (b, blk) with nblk[i] blocks per instance.
-// The op of block x: the starts are ascending, so the ops starting at or
-// before x form a prefix; each lane tests one start (64 per round) and the
-// wave counts the prefix with a ballot (one load round instead of a chain of
-// dependent loads).
-__device__ __forceinline__ int find_op(const uint32_t *start, int n, uint32_t x) {
-  const int lane = threadIdx.x & 63;
-  int idx = 0;
-  for (int base = 0; base < n; base += 64) {
-    const int j = base + lane;
-    const bool le = j < n && ((gu32 *)start)[j] <= x;
-    const int c = __popcll(__ballot(le));
-    idx = base + c - 1;
-    if (c < 64) break;
-  }
-  return idx;
-}
+// schedule).  Workgroup x runs contraction tab[x].op, its workgroup
+// tab[x].local, split as instance-major (b, blk) with nblk[op] workgroups per
+// instance: one read of a table built at plan time (a search over the ops'
+// block ranges cost a chain of dependent loads, up to 12 on a launch of
+// 760 leaf products).
 
 template <int SEMI, int PHASE>
 __global__ __launch_bounds__(kBlock) void k_group(const ContractArgs *__restrict__ ops,
-                                                  const uint32_t *__restrict__ start,
+                                                  const GroupBlock *__restrict__ tab,
                                                   const uint32_t *__restrict__ nblk, int n) {
-  const int i = find_op(start, n, blockIdx.x);
+  const GroupBlock e = tab[blockIdx.x];
+  const int i = (int)e.op;
   const ContractArgs &a = ops[i];
-  const uint32_t local = blockIdx.x - start[i];
+  const uint32_t local = e.local;
   const uint32_t per = nblk[i];
   const bool hy = a.Y != nullptr;
   if (PHASE == 6) {  // interleaved form: group of 64 instances fastest (see k_inter)
@@ -1641,7 +1629,7 @@ __global__ __launch_bounds__(kBlock) void k_group(const ContractArgs *__restrict
   }
 }
 
-void launch_group(int semi, int phase, const ContractArgs *ops, const uint32_t *start, const uint32_t *nblk,
+void launch_group(int semi, int phase, const ContractArgs *ops, const GroupBlock *start, const uint32_t *nblk,
                   int n, uint32_t total_blocks, void *stream) {
   if (n <= 0 || total_blocks == 0) return;
   hipStream_t s = (hipStream_t)stream;

@@ -105,8 +105,10 @@ struct Launch {
   int lds = 0;                        // segment kinds 3 / 4: LDS floats
   // grouped launches: device copies of the ops' arguments and block ranges
   ContractArgs *d_args = nullptr;
-  uint32_t *d_start = nullptr, *d_nblk = nullptr;    // map, or split partials
-  uint32_t *d_start2 = nullptr, *d_nblk2 = nullptr;  // split finish
+  tn::GroupBlock *d_blk = nullptr;    // map, or split partials
+  uint32_t *d_nblk = nullptr;
+  tn::GroupBlock *d_blk2 = nullptr;   // split finish
+  uint32_t *d_nblk2 = nullptr;
   uint32_t total = 0, total2 = 0;
 };
 
