@@ -599,14 +599,45 @@ static void build_backtrack(tn_plan_t *p, TreeExec &t) {
     lev[i] = l;
     n_lev = std::max(n_lev, l + 1);
   }
+  // steps in level order, each step's pairs laid out in that order too
   std::vector<BackStep> sorted;
+  std::vector<int32_t> meta;
   t.back_lev.assign(1, 0);
   for (int l = 0; l < n_lev; ++l) {
     for (size_t i = 0; i < t.back.size(); ++i)
-      if (lev[i] == l) sorted.push_back(t.back[i]);
+      if (lev[i] == l) {
+        BackStep s = t.back[i];
+        const int32_t b = (int32_t)(meta.size() / 2);
+        meta.insert(meta.end(), t.back_meta.begin() + 2 * s.in_begin, t.back_meta.begin() + 2 * s.out_end);
+        s.in_end = b + (s.in_end - s.in_begin);
+        s.out_begin = b + (s.out_begin - s.in_begin);
+        s.out_end = b + (s.out_end - s.in_begin);
+        s.in_begin = b;
+        sorted.push_back(s);
+      }
     t.back_lev.push_back((int32_t)sorted.size());
   }
   t.back = std::move(sorted);
+  t.back_meta = std::move(meta);
+  // chunks of whole levels for the readout kernel's LDS staging
+  t.n_back_lev = n_lev;
+  std::vector<int32_t> chunks;
+  auto pairs_of = [&](int l0, int l1) {
+    const int s0 = t.back_lev[l0], s1 = t.back_lev[l1];
+    return s1 > s0 ? t.back[s1 - 1].out_end - t.back[s0].in_begin : 0;
+  };
+  for (int l0 = 0; l0 < n_lev;) {
+    int l1 = l0 + 1;
+    while (l1 < n_lev && t.back_lev[l1 + 1] - t.back_lev[l0] <= kBackChunkSteps &&
+           pairs_of(l0, l1 + 1) <= kBackChunkPairs)
+      ++l1;
+    const int s0 = t.back_lev[l0], s1 = t.back_lev[l1];
+    chunks.insert(chunks.end(), {l0, l1, s0, s1, s1 > s0 ? t.back[s0].in_begin : 0,
+                                 s1 > s0 ? t.back[s1 - 1].out_end : 0});
+    l0 = l1;
+  }
+  t.n_back_chunks = (int32_t)(chunks.size() / kBackChunkInts);
+  t.back_lev.insert(t.back_lev.end(), chunks.begin(), chunks.end());
 }
 
 // Top-down sampling steps (eq. sample, eq. condition-prob): at every node the
@@ -2695,7 +2726,7 @@ extern "C" tn_status tn_map(tn_plan_t *p, int32_t batch, const int32_t *evidence
       run_graph(p, "max", [&] {
         launch_prepare_set(p, p->leaves_max, p->d_leaves_max, false);
         run_sched(p, p->max_tree.ops, p->sched_max);
-        launch_backtrack(p->iarena, p->d_back, p->d_back_lev, (int)p->max_tree.back_lev.size() - 1, p->d_back_meta,
+        launch_backtrack(p->iarena, p->d_back, p->d_back_lev, p->max_tree.n_back_lev, p->max_tree.n_back_chunks, p->d_back_meta,
                          p->n_vars, p->max_batch, p->d_assign, p->stream);
       });
       hip_check(hipMemcpyAsync(assign + (int64_t)b0 * p->n_vars, p->d_assign, (size_t)nb * p->n_vars * 4,
@@ -3090,7 +3121,7 @@ static void run_mmap(tn_plan_t *p, const int32_t *evidence, int32_t *assign_q, d
   hip_check(hipMemcpyAsync(p->d_assign, row.data(), row.size() * 4, hipMemcpyHostToDevice, p->stream), "init");
   launch_prepare_set(p, p->qleaves, p->d_qleaves, false);
   run_sched(p, p->qtree.ops, p->sched_q);
-  launch_backtrack(p->iarena, p->d_qback, p->d_qback_lev, (int)p->qtree.back_lev.size() - 1, p->d_qback_meta,
+  launch_backtrack(p->iarena, p->d_qback, p->d_qback_lev, p->qtree.n_back_lev, p->qtree.n_back_chunks, p->d_qback_meta,
                    p->n_vars, 1, p->d_assign,
                    p->stream);
   hip_check(hipGetLastError(), "mmap launch");
@@ -3207,8 +3238,8 @@ static tn_status profile_impl(tn_plan_t *p, int32_t task, int32_t batch, const i
       ls.push_back({4, 0, 0, [p] { launch_prepare_set(p, p->leaves_max, p->d_leaves_max, false); }});
       add_ops(p->max_tree.ops, p->sched_max);
       ls.push_back({5, 0, 0, [p] {
-                      launch_backtrack(p->iarena, p->d_back, p->d_back_lev, (int)p->max_tree.back_lev.size() - 1,
-                                       p->d_back_meta, p->n_vars, p->max_batch, p->d_assign, p->stream);
+                      launch_backtrack(p->iarena, p->d_back, p->d_back_lev, p->max_tree.n_back_lev,
+                                       p->max_tree.n_back_chunks, p->d_back_meta, p->n_vars, p->max_batch, p->d_assign, p->stream);
                     }});
     }
     if (kind_only >= 0) {

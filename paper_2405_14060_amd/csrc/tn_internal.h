@@ -410,7 +410,14 @@ struct BackStep {
   int32_t in_begin, in_end;    // (var, stride) pairs
   int32_t out_begin, out_end;  // (var, card) pairs, last fastest
 };
-void launch_backtrack(const int32_t *iarena, const BackStep *steps, const int32_t *lev, int n_lev,
+// Readout chunks: runs of whole levels whose steps (<= kBackChunkSteps) and
+// (var, stride / card) pairs (<= kBackChunkPairs, contiguous: the pairs are
+// laid out in step order) a workgroup stages in LDS with one round of loads;
+// per chunk: first and end level, first and end step, first and end pair.
+// A level larger than a chunk is a chunk of its own, read from global memory.
+static constexpr int kBackChunkSteps = 128, kBackChunkPairs = 2048, kBackChunkInts = 6;
+// lev: n_lev + 1 level boundaries, then n_chunks chunks
+void launch_backtrack(const int32_t *iarena, const BackStep *steps, const int32_t *lev, int n_lev, int n_chunks,
                       const int32_t *pairs, int n_vars, int batch, int32_t *assign, void *stream);
 
 // Top-down sampling steps (see tn_sample).

@@ -2953,31 +2953,39 @@ void launch_joint(const float *arena, const JointDesc *d, int n, const int32_t *
 // --------------------------------------------------------------------------
 // One workgroup per instance; the levels run in order, the steps of a level
 // spread over the threads.  The assignment lives in LDS when it fits (else in
-// global memory, fenced between levels).
-static constexpr int kBackLdsVars = 12288;
+// global memory, fenced between levels).  Levels are taken in chunks: a
+// chunk's steps, pairs and level boundaries are staged in LDS with one round
+// of loads, so that a level costs one dependent global read (the argmax
+// entry) instead of three (step, pairs, entry).
+static constexpr int kBackLdsVars = 8192;
 
+// pairs: the chunk's (var, stride / card) pairs, pair i at pairs[2 (i - p0)]
 __device__ __forceinline__ void back_step(const int32_t *__restrict__ iarena, const BackStep &s,
-                                          const int32_t *__restrict__ pairs, int b, int32_t *x) {
+                                          const int32_t *__restrict__ pairs, int p0, int b, int32_t *x) {
   int64_t off = 0;
   bool ok = true;
   for (int i = s.in_begin; i < s.in_end; ++i) {
-    const int32_t xv = x[pairs[2 * i]];
+    const int32_t xv = x[pairs[2 * (i - p0)]];
     ok = ok && xv >= 0;
-    off += (int64_t)xv * pairs[2 * i + 1];
+    off += (int64_t)xv * pairs[2 * (i - p0) + 1];
   }
   if (!ok) return;  // an input left unassigned: leave this step's outputs unset
   int32_t k = iarena[s.arg + (int64_t)b * s.bs + off * s.es];
   for (int j = s.out_end - 1; j >= s.out_begin; --j) {
-    const int c = pairs[2 * j + 1];
-    x[pairs[2 * j]] = k % c;
+    const int c = pairs[2 * (j - p0) + 1];
+    x[pairs[2 * (j - p0)]] = k % c;
     k /= c;
   }
 }
 
 template <bool LDS_X>
 __global__ __launch_bounds__(kBlock) void k_backtrack(const int32_t *iarena, const BackStep *steps, const int32_t *lev,
-                                                      int n_lev, const int32_t *pairs, int n_vars, int32_t *assign) {
+                                                      int n_lev, int n_chunks, const int32_t *pairs, int n_vars,
+                                                      int32_t *assign) {
   extern __shared__ int32_t xs[];
+  __shared__ BackStep cs[kBackChunkSteps];
+  __shared__ int32_t cp[2 * kBackChunkPairs];
+  __shared__ int32_t cl[kBackChunkSteps + 1];
   const int b = blockIdx.x;
   int32_t *xg = assign + (int64_t)b * n_vars;
   int32_t *x = LDS_X ? xs : xg;
@@ -2985,24 +2993,43 @@ __global__ __launch_bounds__(kBlock) void k_backtrack(const int32_t *iarena, con
     for (int i = threadIdx.x; i < n_vars; i += kBlock) xs[i] = xg[i];
     __syncthreads();
   }
-  for (int l = 0; l < n_lev; ++l) {
-    for (int st = lev[l] + threadIdx.x; st < lev[l + 1]; st += kBlock) back_step(iarena, steps[st], pairs, b, x);
-    if (!LDS_X) __threadfence();
-    __syncthreads();
+  const int32_t *chunk = lev + n_lev + 1;
+  for (int c = 0; c < n_chunks; ++c) {
+    const int l0 = chunk[kBackChunkInts * c], l1 = chunk[kBackChunkInts * c + 1];
+    const int s0 = chunk[kBackChunkInts * c + 2], s1 = chunk[kBackChunkInts * c + 3];
+    const int p0 = chunk[kBackChunkInts * c + 4], p1 = chunk[kBackChunkInts * c + 5];
+    const bool staged = s1 - s0 <= kBackChunkSteps && p1 - p0 <= kBackChunkPairs && l1 - l0 <= kBackChunkSteps;
+    if (staged) {  // the previous chunk's last level ended with a barrier
+      for (int i = threadIdx.x; i < s1 - s0; i += kBlock) cs[i] = steps[s0 + i];
+      for (int i = threadIdx.x; i < 2 * (p1 - p0); i += kBlock) cp[i] = pairs[2 * p0 + i];
+      for (int i = threadIdx.x; i <= l1 - l0; i += kBlock) cl[i] = lev[l0 + i];
+      __syncthreads();
+      for (int l = 0; l < l1 - l0; ++l) {
+        for (int st = cl[l] + threadIdx.x; st < cl[l + 1]; st += kBlock) back_step(iarena, cs[st - s0], cp, p0, b, x);
+        if (!LDS_X) __threadfence();
+        __syncthreads();
+      }
+    } else {
+      for (int l = l0; l < l1; ++l) {
+        for (int st = lev[l] + threadIdx.x; st < lev[l + 1]; st += kBlock) back_step(iarena, steps[st], pairs, 0, b, x);
+        if (!LDS_X) __threadfence();
+        __syncthreads();
+      }
+    }
   }
   if (LDS_X)
     for (int i = threadIdx.x; i < n_vars; i += kBlock) xg[i] = xs[i];
 }
 
-void launch_backtrack(const int32_t *iarena, const BackStep *steps, const int32_t *lev, int n_lev,
+void launch_backtrack(const int32_t *iarena, const BackStep *steps, const int32_t *lev, int n_lev, int n_chunks,
                       const int32_t *pairs, int n_vars, int batch, int32_t *assign, void *stream) {
   if (n_lev <= 0) return;
   hipStream_t s = (hipStream_t)stream;
   if (n_vars <= kBackLdsVars)
-    k_backtrack<true><<<batch, kBlock, (size_t)n_vars * sizeof(int32_t), s>>>(iarena, steps, lev, n_lev, pairs,
-                                                                                n_vars, assign);
+    k_backtrack<true><<<batch, kBlock, (size_t)n_vars * sizeof(int32_t), s>>>(iarena, steps, lev, n_lev, n_chunks,
+                                                                                pairs, n_vars, assign);
   else
-    k_backtrack<false><<<batch, kBlock, 0, s>>>(iarena, steps, lev, n_lev, pairs, n_vars, assign);
+    k_backtrack<false><<<batch, kBlock, 0, s>>>(iarena, steps, lev, n_lev, n_chunks, pairs, n_vars, assign);
 }
 
 // --------------------------------------------------------------------------

@@ -136,7 +136,9 @@ struct TreeExec {
   // max-plus only: readout steps
   std::vector<BackStep> back;
   std::vector<int32_t> back_meta;
-  std::vector<int32_t> back_lev;      // readout levels: steps [back_lev[l], back_lev[l + 1])
+  std::vector<int32_t> back_lev;      // readout levels: steps [back_lev[l], back_lev[l + 1]),
+                                      // then the chunks (kBackChunkInts each)
+  int32_t n_back_lev = 0, n_back_chunks = 0;
 };
 
 }  // namespace tn
