@@ -1774,6 +1774,16 @@ static constexpr int kSegRow = kSegOB + 1;        // padded LDS tile row: confli
 
 unsigned seg_blocks(const SegArgs &a) { return (a.nO + kSegOB - 1) / kSegOB; }
 
+// Workgroup x of n (ids counted from the first of a segment) -> its tile.
+// Workgroups go to the XCDs in turn (id modulo 8); the tiles are dealt so
+// that each XCD takes a run of consecutive tiles, whose carrier pieces share
+// cache lines when a tile's runs are shorter than a line (the other pieces
+// of the line are then read from that XCD's L2 instead of again from HBM).
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t x, uint32_t n) {
+  const uint32_t k = x & 7u;
+  return k * (n >> 3) + min(k, n & 7u) + (x >> 3);
+}
+
 __device__ __forceinline__ int32_t outer_off(const Tab2 &t, uint32_t o, uint32_t nlo) {
   const uint32_t h = o / nlo;
   return t.hi[h] + t.lo[o - h * nlo];
@@ -1989,7 +1999,7 @@ __device__ __forceinline__ void seg_fwd_body(const SegArgs &a, const uint32_t bl
 
 template <int PREC>
 __global__ __launch_bounds__(kSegThreads) void k_seg_fwd(const SegArgs a) {
-  seg_fwd_body<PREC>(a, blockIdx.x);
+  seg_fwd_body<PREC>(a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Two independent segments of one stage in one launch: workgroups
@@ -2000,7 +2010,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_fwd(const SegArgs a) {
 template <int PREC>
 __global__ __launch_bounds__(kSegThreads) void k_seg_fwd2(const SegPair g) {
   const uint32_t second = blockIdx.x >= g.split ? 1u : 0u;
-  seg_fwd_body<PREC>(g.a[second], blockIdx.x - second * g.split);
+  seg_fwd_body<PREC>(g.a[second], xcd_tile(blockIdx.x - second * g.split, second ? gridDim.x - g.split : g.split));
 }
 
 // Reverse: Cbar_0[:, o] = M^T Gbar[:, o], and the workgroup's partial of
@@ -2087,14 +2097,14 @@ __device__ __forceinline__ void seg_bwd_body(const SegArgs &a, const uint32_t bl
 
 template <int PREC>
 __global__ __launch_bounds__(kSegThreads) void k_seg_bwd(const SegArgs a) {
-  seg_bwd_body<PREC>(a, blockIdx.x);
+  seg_bwd_body<PREC>(a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // Two independent segments' reverse steps in one launch, as k_seg_fwd2.
 template <int PREC>
 __global__ __launch_bounds__(kSegThreads) void k_seg_bwd2(const SegPair g) {
   const uint32_t second = blockIdx.x >= g.split ? 1u : 0u;
-  seg_bwd_body<PREC>(g.a[second], blockIdx.x - second * g.split);
+  seg_bwd_body<PREC>(g.a[second], xcd_tile(blockIdx.x - second * g.split, second ? gridDim.x - g.split : g.split));
 }
 
 // --- sweeps over the steps (one workgroup per segment) ---------------------
@@ -2542,7 +2552,7 @@ __device__ __forceinline__ void dseg_fwd_body(const DSegArgs &a, const uint32_t 
 template <int PREC>
 __global__ __launch_bounds__(kSegThreads) void k_dseg_fwd(const DSegPair g) {
   const uint32_t second = blockIdx.x >= g.split ? 1u : 0u;
-  dseg_fwd_body<PREC>(g.a[second], blockIdx.x - second * g.split);
+  dseg_fwd_body<PREC>(g.a[second], xcd_tile(blockIdx.x - second * g.split, second ? gridDim.x - g.split : g.split));
 }
 
 // Wave w's 16 x 16 quadrant (w % 4) of sum over the column quarter w / 4
@@ -2648,7 +2658,7 @@ __device__ __forceinline__ void dseg_bwd_body(const DSegArgs &a, const uint32_t 
 template <int PREC>
 __global__ __launch_bounds__(kSegThreads) void k_dseg_bwd(const DSegPair g) {
   const uint32_t second = blockIdx.x >= g.split ? 1u : 0u;
-  dseg_bwd_body<PREC>(g.a[second], blockIdx.x - second * g.split);
+  dseg_bwd_body<PREC>(g.a[second], xcd_tile(blockIdx.x - second * g.split, second ? gridDim.x - g.split : g.split));
 }
 
 static DSegPair dseg_pair(const DSegArgs &a, const DSegArgs *b, unsigned &nb) {
