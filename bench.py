@@ -49,11 +49,11 @@ KIND_NAMES = {0: "contract_map_sum", 1: "contract_map_max", 2: "contract_split_s
 # the kernel source they were taken from (sha256 prefix of tn_kernels.hip):
 # {(kernel, workload): {"src": sha, "bytes": B}}
 MEASURED_TRAFFIC = {
-    ("seg_carrier_bwd", "grid20x20"): {"src": "dfffab7897d1877a", "bytes": 13261141},
-    ("contract_interleaved_sum", "bn500x512"): {"src": "dfffab7897d1877a", "bytes": 69851738},
-    ("contract_map_max", "grid20_map"): {"src": "dfffab7897d1877a", "bytes": 12012694},
+    ("seg_carrier_bwd", "grid20x20"): {"src": "1c294f238fa68d94", "bytes": 26390948},
+    ("contract_interleaved_sum", "bn500x512"): {"src": "1c294f238fa68d94", "bytes": 69951096},
+    ("contract_map_max", "grid20_map"): {"src": "1c294f238fa68d94", "bytes": 22759587},
+    ("contract_tropical_dense", "tropical_gemm"): {"src": "1c294f238fa68d94", "bytes": 115419110},
 }
-
 
 def kernel_src_sha():
     with open(os.path.join(ROOT, "paper_2405_14060_amd", "csrc", "tn_kernels.hip"), "rb") as f:
@@ -337,8 +337,10 @@ def bench_tropical_gemm(args, T, W, np, sync):
     kind_of = {v: k for k, v in KIND_NAMES.items()}
     avg_ms, fl_launch, by_launch, n_launch = plan.profile_kind(2, kind_of["contract_tropical_dense"], reps=5)
     tops = fl_launch / (avg_ms * 1e-3) / 1e12
+    meas = MEASURED_TRAFFIC.get(("contract_tropical_dense", "tropical_gemm"))
+    traffic = meas["bytes"] if meas and meas["src"] == kernel_src_sha() else None
     roof = dict(bound="alu", achieved=round(tops, 3), peak=round(TROPICAL_PEAK_TOPS, 2), unit="T tropical-op/s",
-                frac=round(tops / TROPICAL_PEAK_TOPS, 4), traffic=None, kernel="contract_tropical_dense",
+                frac=round(tops / TROPICAL_PEAK_TOPS, 4), traffic=traffic, kernel="contract_tropical_dense",
                 launches_per_solve=n_launch, avg_launch_us=round(avg_ms * 1e3, 3), bytes_per_launch=round(by_launch),
                 flops_per_launch=round(fl_launch), candidates_per_s=round(fl_launch / 2 / (avg_ms * 1e-3), 1))
     kernels = {k: dict(n=v["n"], ms=round(v["ms"], 4)) for k, v in kernel_summary(prof).items()}
