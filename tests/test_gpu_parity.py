@@ -774,3 +774,33 @@ def test_graph_replay_matches_eager(T):
         lp_e, x_e = Pe.map(ev, batch=8)
         assert np.array_equal(x_g, x_e)
         Pe.log_z(ev, batch=8)
+
+
+@pytest.mark.parametrize("n_vars", [600, 9000])
+def test_map_readout_wide_levels_and_many_variables(T, n_vars):
+    """The argmax readout stages runs of levels in LDS; a level with more
+    steps than a staged run (here hundreds of independent pairs, so the
+    first level holds hundreds of steps) is read from global memory, and
+    above 8192 variables the assignment itself lives in global memory.
+    Bit-exact against the oracle's FP32 emulation on the same tree, and the
+    assignment equals the per-pair brute-force maximiser."""
+    rng = np.random.default_rng(n_vars)
+    n_pairs = n_vars // 2
+    scopes = [np.array([2 * i, 2 * i + 1], np.int32) for i in range(n_pairs)]
+    vals = [rng.normal(0, 1, 4) for _ in range(n_pairs)]
+    net = W.Network(np.full(n_vars, 2, np.int32), scopes, vals, True)
+    if n_vars <= 4096:  # within the oracle's max-plus reference
+        lv = oracle.build_leaves(net, domain="log")
+        pairs = oracle.default_tree(lv)
+        P = T.Plan(T.Network(net), semirings=T.MAX_PLUS, tree=pairs)
+        lp, x = P.map()
+        v32, x32 = oracle.max_forward(lv, pairs, fp32=True)
+        assert np.array_equal(x[0], x32)
+        assert np.float32(lp[0]) == np.float32(v32)
+    else:
+        P = T.Plan(T.Network(net), semirings=T.MAX_PLUS)
+        lp, x = P.map()
+    # per pair, the maximiser of its FP32 log table (first index on ties)
+    best = np.array([int(np.argmax(np.asarray(v, np.float32))) for v in vals])
+    assert np.array_equal(x[0][0::2], best // 2) and np.array_equal(x[0][1::2], best % 2)
+    assert abs(lp[0] - sum(float(np.max(v)) for v in vals)) <= 1e-4 * n_pairs
