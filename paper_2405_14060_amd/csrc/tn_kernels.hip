@@ -2308,10 +2308,18 @@ __global__ __launch_bounds__(kFinThreads) void k_seg_fin(const SegArgs *__restri
     const SegStep &st = ss.st[k];
     if (st.ybar >= 0) {
       const float *Pk = P + poff[k];
+      // lanes of one wave take consecutive i: rows of Pk nc floats apart, so
+      // each lane starts its sum at column i (mod nc) — otherwise the 32
+      // lanes of a row of W read one LDS bank in every step (nc = 32)
       for (int t = threadIdx.x; t < st.n_out * st.n_in; t += kFinThreads) {
         const int j = t / st.n_in, i = t - j * st.n_in;
+        const float *gj = G0 + j * nc, *pi = Pk + i * nc;
+        int c = i % nc;
         float acc = 0.f;
-        for (int c = 0; c < nc; ++c) acc = fmaf(G0[j * nc + c], Pk[i * nc + c], acc);
+        for (int u = 0; u < nc; ++u) {
+          acc = fmaf(gj[c], pi[c], acc);
+          c = c + 1 == nc ? 0 : c + 1;
+        }
         W[t] = acc;
       }
       __syncthreads();
