@@ -358,6 +358,9 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
         a.nBl = (uint32_t)numel(Labels(Bl.begin() + bs, Bl.end()), card);
         a.nM = (uint32_t)nM;
         a.nMl = (uint32_t)numel(Labels(Ml.begin() + ms, Ml.end()), card);
+        a.nBlo = 1;
+        for (auto it = LZ.rbegin(); it != LZ.rend() && has(Bl, *it) && a.nBlo * card[*it] <= 16; ++it)
+          a.nBlo *= (uint32_t)card[*it];
         a.x_s_fast = (!LX.empty() && has(S, LX.back())) ? 1 : 0;
         a.y_n_fast = (!LY.empty() && has(C, LY.back())) ? 1 : 0;
         a.z_n_fast = (!LZ.empty() && has(C, LZ.back())) ? 1 : 0;

@@ -148,6 +148,9 @@ struct ContractArgs {
   Tab2 gbX, gbY, gbZ;       // batch labels in X, Y, Z
   Tab2 gmX, gmZ;            // M labels in X, Z
   uint32_t nB = 1, nBl = 1, nM = 1, nMl = 1;
+  uint32_t nBlo = 1;        // batch assignments of the batch labels faster in Z than every
+                            // M and column label: tiles of those batches are dealt together
+                            // (they share cache lines of every operand)
   int32_t x_s_fast = 0;     // X's stride-1 label is summed (else an M or batch label)
   int32_t y_n_fast = 0;     // Y's stride-1 label is a column label
   int32_t z_n_fast = 0;     // Z's stride-1 label is a column label

@@ -85,6 +85,20 @@ __device__ __forceinline__ float wave_sum(float v) {
 
 // exponent k of the recorded maximum m (m = f * 2^k, f in [0.5, 1)),
 // clamped so that 2^-k is a normal float
+// Dense-form tile q of tm x tn tiles per batch -> (batch, row tile, column
+// tile): column tile fastest, then row tile, then batch, except that the
+// nBlo batches whose labels are faster than the tiles' labels vary fastest
+// of all (their tiles read the same cache lines).
+__device__ __forceinline__ void dense_tile(uint32_t q, uint32_t tm, uint32_t tn, uint32_t nBlo, uint32_t &bt,
+                                           uint32_t &mt, uint32_t &nt) {
+  const uint32_t blo = q % nBlo;
+  q /= nBlo;
+  nt = q % tn;
+  q /= tn;
+  mt = q % tm;
+  bt = (q / tm) * nBlo + blo;
+}
+
 __device__ __forceinline__ int max_exponent(uint32_t bits) {
   float m = __uint_as_float(bits);
   if (!(m > 0.f)) return 0;
@@ -761,8 +775,8 @@ __device__ __forceinline__ void gemm_body(const ContractArgs &a, const int b, co
   static_assert(kGT * kGCP <= 2 * kDK * kGKP, "epilogue tile fits the operand chunks");
   const int t = threadIdx.x, l = t & 63, w = t >> 6;
   const uint32_t tm = (a.nM + kGT - 1) / kGT, tn = (a.nC + kGT - 1) / kGT;
-  const uint32_t bt = blk / (tm * tn), rem = blk - bt * tm * tn;
-  const uint32_t mt = rem / tn, nt = rem - mt * tn;
+  uint32_t bt, mt, nt;
+  dense_tile(blk, tm, tn, a.nBlo, bt, mt, nt);
   const uint32_t m0 = mt * kGT, n0 = nt * kGT;
   const int32_t xb = tab_off(a.gbX, bt, a.nBl), yb = tab_off(a.gbY, bt, a.nBl), zb = tab_off(a.gbZ, bt, a.nBl);
   gcfloat *__restrict__ X = (gcfloat *)(a.X + (int64_t)b * a.bsX + xb);
@@ -929,8 +943,8 @@ __device__ __forceinline__ void gemm_max_body(const ContractArgs &a, const int b
   const int t = threadIdx.x;
   const int l = t & 63, w = t >> 6;
   const uint32_t tm = (a.nM + kGT - 1) / kGT, tn = (a.nC + kGT - 1) / kGT;
-  const uint32_t bt = blk / (tm * tn), rem = blk - bt * tm * tn;
-  const uint32_t mt = rem / tn, nt = rem - mt * tn;
+  uint32_t bt, mt, nt;
+  dense_tile(blk, tm, tn, a.nBlo, bt, mt, nt);
   const uint32_t m0 = mt * kGT, n0 = nt * kGT;
   const int32_t xb = tab_off(a.gbX, bt, a.nBl), yb = tab_off(a.gbY, bt, a.nBl), zb = tab_off(a.gbZ, bt, a.nBl);
   gcfloat *__restrict__ X = (gcfloat *)(a.X + (int64_t)b * a.bsX + xb);
@@ -1115,8 +1129,8 @@ __device__ __forceinline__ void gemm_big_body(const ContractArgs &a, const int b
   const int t = threadIdx.x, l = t & 63, w = t >> 6;
   const uint32_t tile = (nblk & 7u) == 0 ? (blk & 7u) * (nblk >> 3) + (blk >> 3) : blk;
   const uint32_t tm = (a.nM + kBT - 1) / kBT, tn = (a.nC + kBT - 1) / kBT;
-  const uint32_t bt = tile / (tm * tn), rem = tile - bt * tm * tn;
-  const uint32_t mt = rem / tn, nt = rem - mt * tn;
+  uint32_t bt, mt, nt;
+  dense_tile(tile, tm, tn, a.nBlo, bt, mt, nt);
   const uint32_t m0 = mt * kBT, n0 = nt * kBT;
   const int32_t xb = tab_off(a.gbX, bt, a.nBl), yb = tab_off(a.gbY, bt, a.nBl), zb = tab_off(a.gbZ, bt, a.nBl);
   // operands through buffer resources (each operand below 2^30 entries:
