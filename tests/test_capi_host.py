@@ -92,3 +92,17 @@ def test_segment_pairs_on_host(T):
     # every pair replaces two single-segment passes in each direction
     assert vp.count(5) == vp.count(6) and vu.count(1) == vp.count(1) + 2 * vp.count(5)
     assert P.info()["n_launches_fwd"] < U.info()["n_launches_fwd"]
+
+
+def test_mmap_sum_phase_fuses_chains(T):
+    """An MMAP plan's sum phase runs forward only, so its chains of small
+    absorptions fuse into segments like the main tree's forward pass (and
+    not with no_fuse)."""
+    net = W.grid_mrf(14, 14, 0)
+    q = [0, 13, 100, 195]
+    kw = dict(semirings=T.SUM_PRODUCT | T.MAX_PLUS, query=q, host_only=True, planner=T.PLANNER_NATURAL)
+    P = T.Plan(T.Network(net), **kw)
+    U = T.Plan(T.Network(net), fuse=False, **kw)
+    assert any(o["form"] == 5 for o in P.ops(3))
+    assert not any(o["form"] == 5 for o in U.ops(3))
+    assert len(P.ops(3)) < len(U.ops(3))

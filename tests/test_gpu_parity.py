@@ -804,3 +804,20 @@ def test_map_readout_wide_levels_and_many_variables(T, n_vars):
     best = np.array([int(np.argmax(np.asarray(v, np.float32))) for v in vals])
     assert np.array_equal(x[0][0::2], best // 2) and np.array_equal(x[0][1::2], best % 2)
     assert abs(lp[0] - sum(float(np.max(v)) for v in vals)) <= 1e-4 * n_pairs
+
+
+def test_mmap_fused_sum_phase(T):
+    """MMAP whose sum phase holds fused segments and segment pairs (a grid
+    on its natural order): against the oracle's MMAP and the unfused plan,
+    with the answer certified."""
+    net = W.grid_mrf(12, 12, 7)
+    q = [0, 11, 60, 77, 143]
+    P = T.Plan(T.Network(net), query=q, planner=T.PLANNER_NATURAL)
+    assert any(o["form"] == 5 and o["variant"] in (1, 5) for o in P.ops(3))
+    ov, ox, ogap = oracle.mmap(net, q)
+    val, x = P.mmap()
+    assert abs(val - ov) <= 1e-5 * max(1, abs(ov))
+    U = T.Plan(T.Network(net), query=q, planner=T.PLANNER_NATURAL, fuse=False)
+    uval, ux = U.mmap()
+    assert abs(val - uval) <= 1e-5 * max(1, abs(uval))
+    note_near_tie(certify_mmap(net, q, x, val))
