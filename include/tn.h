@@ -175,6 +175,10 @@ typedef struct {
                                     elimination order (two intermediates grown from both ends
                                     of the order, contracted side by side until they meet) */
   int32_t n_levels;              /* levels of the main tree (longest leaf-to-root path) */
+  int32_t n_pairs;               /* pairs of consecutive segments run in one carrier pass */
+  int32_t n_pairs_moved;         /* of n_pairs: pairs whose tiles take a common outer label
+                                    into one map's rows and columns (that map applied as
+                                    M (x) I over it) */
 } tn_plan_info;
 
 /* Fill *o with defaults: sum-product + max-plus, no evidence, best planner,

@@ -71,7 +71,8 @@ class PlanInfo(ctypes.Structure):
                 ("n_dense", ctypes.c_int32), ("n_wave", ctypes.c_int32),
                 ("n_interleaved", ctypes.c_int32), ("batch_stride", ctypes.c_int32),
                 ("n_dense_large", ctypes.c_int32), ("two_front", ctypes.c_int32),
-                ("n_levels", ctypes.c_int32)]
+                ("n_levels", ctypes.c_int32), ("n_pairs", ctypes.c_int32),
+                ("n_pairs_moved", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -1191,6 +1191,10 @@ static void allocate(tn_plan_t *p, const tn_net *net) {
   p->d_gmap = dupload(p, p->gmap);
   p->d_obs = dupload(p, p->obs);
   p->d_evidence = dalloc<int32_t>(p, (size_t)p->max_batch * std::max(1, p->n_vars));
+  if (!p->sliced.empty() || !p->groups.empty()) {
+    p->d_slice_rows = dalloc<int32_t>(p, (size_t)kSliceChunk * std::max(1, p->n_vars));
+    p->d_slice_lz = dalloc<double>(p, (size_t)kSliceChunk);
+  }
   p->d_assign = dalloc<int32_t>(p, (size_t)p->max_batch * std::max(1, p->n_vars));
   p->d_out = dalloc<double>(p, (size_t)p->max_batch);
   p->d_part = dalloc<float>(p, (size_t)std::max<int64_t>(1, p->part_floats));
@@ -1534,41 +1538,79 @@ static int32_t tile_lo_shift(const Labels &loc, const Labels &cols, const std::v
 // Segments s1 and s2 (s2's input carrier is s1's output) as one carrier
 // pass: the labels of the pass (DSegArgs), the workgroup shape and the
 // tables.  False when a tile would not fit (at most 32 assignments of Q and
-// of R, at least four outer assignments per workgroup) or would leave a
-// large carrier's tile mostly empty.
+// of R, at least four outer assignments per workgroup) or would leave the
+// large carriers' tiles mostly empty.  Where one map's local sets are small
+// enough, the slowest common outer label o* joins its rows and columns (the
+// map becomes M (x) I; in the first map o* also joins R, in the second Q):
+// the tiles then hold more local entries and fewer outer assignments,
+// which fills them where the local sets alone would fill half.
 static bool describe_pair(tn_plan_t *p, int s1, int s2, DSegPlan &dp, bool commit) {
   const SegPlan &a = p->segs[s1], &b = p->segs[s2];
   const auto &card = p->card;
   const Labels &V0 = p->T[a.c0].lab, &V2 = p->T[b.cL].lab;
   const Labels &A = a.loc_in, &B = a.loc_out, &C = b.loc_in, &D = b.loc_out;
-  const Labels P = inter(C, B), Q = inter(C, a.outer), R = minus(B, C), O = minus(a.outer, Q);
+  const Labels P = inter(C, B), Q = inter(C, a.outer), R = minus(B, C);
+  Labels O = minus(a.outer, Q);
   if (unite(P, Q) != C || !minus(O, V2).empty()) return false;
-  const int64_t nQ = numel(Q, card), nR = numel(R, card), nO = numel(O, card);
+  const int64_t nQ = numel(Q, card), nR = numel(R, card);
   if (nQ > kSegMaxLocal || nR > kSegMaxLocal || O.empty()) return false;
-  int nob = kSegOuterBlock;
-  while ((int64_t)nob * std::max(nQ, nR) > kSegOuterBlock) nob >>= 1;
-  if (nob < 4 || nO >= (int64_t(1) << 31)) return false;
   // a large carrier in a tile it fills less than three quarters of runs
   // faster in a pass of its own
-  const double use_x = (double)a.n_in0 * nQ * nob / (kSegMaxLocal * kSegOuterBlock);
-  const double use_z = (double)b.n_outL * nR * nob / (kSegMaxLocal * kSegOuterBlock);
-  if ((use_x < 0.75 && p->T[a.c0].size >= (1 << 16)) || (use_z < 0.75 && p->T[b.cL].size >= (1 << 16))) return false;
+  const bool lx = p->T[a.c0].size >= (1 << 16), lz = p->T[b.cL].size >= (1 << 16);
+  // workgroup shape with o* (k1 or k2 assignments) in the first or second
+  // map; false when it does not fit or does not fill the tiles
+  auto shape = [&](int64_t k1, int64_t k2, int &nob) {
+    const int64_t q = nQ * k2, r = nR * k1;
+    if (a.n_in0 * k1 > kSegMaxLocal || a.n_outL * k1 > kSegMaxLocal || r > kSegMaxLocal ||
+        b.n_in0 * k2 > kSegMaxLocal || b.n_outL * k2 > kSegMaxLocal || q > kSegMaxLocal)
+      return false;
+    nob = kSegOuterBlock;
+    while ((int64_t)nob * std::max(q, r) > kSegOuterBlock) nob >>= 1;
+    const double use_x = (double)a.n_in0 * k1 * q * nob / (kSegMaxLocal * kSegOuterBlock);
+    const double use_z = (double)b.n_outL * k2 * r * nob / (kSegMaxLocal * kSegOuterBlock);
+    return nob >= 4 && !((use_x < 0.75 && lx) || (use_z < 0.75 && lz));
+  };
+  int nob = 0;
+  int64_t aug1 = 1, aug2 = 1;
+  if (!shape(1, 1, nob)) {
+    if (O.size() < 2) return false;
+    const int64_t k = card[O.front()];
+    if (shape(k, 1, nob)) aug1 = k;
+    else if (shape(1, k, nob)) aug2 = k;
+    else return false;
+  }
+  const int ostar = O.front();
+  if (aug1 > 1 || aug2 > 1) O.erase(O.begin());
+  const int64_t nO = numel(O, card);
+  if (nO >= (int64_t(1) << 31)) return false;
   if (!commit) return true;
+  // the tiles' row orders, with o* (when moved) slowest
+  auto with = [&](bool moved, const Labels &L) {
+    Labels o;
+    if (moved) o.push_back(ostar);
+    o.insert(o.end(), L.begin(), L.end());
+    return o;
+  };
+  const Labels Ao = with(aug1 > 1, A), Bo = with(aug1 > 1, B), Ro = with(aug1 > 1, R);
+  const Labels Co = with(aug2 > 1, C), Do = with(aug2 > 1, D), Qo = with(aug2 > 1, Q);
+  const Labels Rs = aug1 > 1 ? unite(R, Labels{ostar}) : R, Qs = aug2 > 1 ? unite(Q, Labels{ostar}) : Q;
   dp.s1 = s1;
   dp.s2 = s2;
+  dp.aug1 = (int32_t)aug1;
+  dp.aug2 = (int32_t)aug2;
   dp.nO = (uint32_t)nO;
   const size_t os = lo_split(O, card);
   dp.nOl = (uint32_t)numel(Labels(O.begin() + os, O.end()), card);
   add_tabs(p, O, os, V0, dp.oX);
   add_tabs(p, O, os, V2, dp.oZ);
   dp.nob = nob;
-  dp.nQ = (int32_t)nQ;
-  dp.nR = (int32_t)nR;
+  dp.nQ = (int32_t)(nQ * aug2);
+  dp.nR = (int32_t)(nR * aug1);
   // column order: the tile's fastest column label decides which part of a
   // column runs fastest
-  const Labels colX = unite(Q, O), colZ = unite(R, O);
-  dp.q_fast = !Q.empty() && Q.back() == colX.back();
-  dp.r_fast = !R.empty() && R.back() == colZ.back();
+  const Labels colX = unite(Qs, O), colZ = unite(Rs, O);
+  dp.q_fast = !Qs.empty() && Qs.back() == colX.back();
+  dp.r_fast = !Rs.empty() && Rs.back() == colZ.back();
   dp.in_lo_shift = tile_lo_shift(A, colX, card);
   dp.out_lo_shift = tile_lo_shift(D, colZ, card);
   dp.n_part = (int32_t)((nO + nob - 1) / nob);
@@ -1588,23 +1630,23 @@ static bool describe_pair(tn_plan_t *p, int s1, int s2, DSegPlan &dp, bool commi
       }
     }
   };
-  offsets(A, V0, 0);
-  offsets(D, V2, 1);
-  offsets(Q, V0, 2);
-  offsets(R, V2, 3);
-  offsets(R, B, 6);  // per r: its part of the index in B
-  {  // per c in C: the P part of its index in B and its index in Q
-    const int64_t n = numel(C, card);
-    std::vector<int> d(C.size(), 0);
+  offsets(Ao, V0, 0);
+  offsets(Do, V2, 1);
+  offsets(Qo, V0, 2);
+  offsets(Ro, V2, 3);
+  offsets(Ro, Bo, 6);  // per r: its part of the row in the first map's output tile
+  {  // per c in C: the P part of its row in the first map's output tile and its index in Q
+    const int64_t n = numel(Co, card);
+    std::vector<int> d(Co.size(), 0);
     for (int64_t i = 0; i < n; ++i) {
-      for (size_t k = 0; k < C.size(); ++k) val[C[k]] = d[k];
+      for (size_t k = 0; k < Co.size(); ++k) val[Co[k]] = d[k];
       int64_t pb = 0, qi = 0;
-      for (int v : P) pb += (int64_t)val[v] * stride_in(B, v, card);
-      for (int v : Q) qi += (int64_t)val[v] * stride_in(Q, v, card);
+      for (int v : P) pb += (int64_t)val[v] * stride_in(Bo, v, card);
+      for (int v : Qo) qi += (int64_t)val[v] * stride_in(Qo, v, card);
       t[4 * kSegMaxLocal + i] = (int32_t)pb;
       t[5 * kSegMaxLocal + i] = (int32_t)qi;
-      for (int k = (int)C.size() - 1; k >= 0; --k) {
-        if (++d[k] < card[C[k]]) break;
+      for (int k = (int)Co.size() - 1; k >= 0; --k) {
+        if (++d[k] < card[Co[k]]) break;
         d[k] = 0;
       }
     }
@@ -1949,10 +1991,12 @@ static void upload_segments(tn_plan_t *p) {
       a.oX = Tab2{p->d_tabs + dp.oX[0], p->d_tabs + dp.oX[1]};
       a.oZ = Tab2{p->d_tabs + dp.oZ[0], p->d_tabs + dp.oZ[1]};
       a.nob = dp.nob;
-      a.nA = s1.n_in0;
-      a.nB = s1.n_outL;
-      a.nC = s2.n_in0;
-      a.nD = s2.n_outL;
+      a.aug1 = dp.aug1;
+      a.aug2 = dp.aug2;
+      a.nA = s1.n_in0 * dp.aug1;
+      a.nB = s1.n_outL * dp.aug1;
+      a.nC = s2.n_in0 * dp.aug2;
+      a.nD = s2.n_outL * dp.aug2;
       a.nQ = dp.nQ;
       a.nR = dp.nR;
       a.q_fast = dp.q_fast;
@@ -2293,6 +2337,8 @@ extern "C" tn_status tn_plan_info_get(const tn_plan_t *p, tn_plan_info *info) {
       info->n_launches_bwd = count(p->sched_fbwd);
     }
     info->n_segments = (int32_t)p->segs.size();
+    info->n_pairs = (int32_t)p->dsegs.size();
+    for (const auto &dp : p->dsegs) info->n_pairs_moved += dp.aug1 > 1 || dp.aug2 > 1 ? 1 : 0;
     for (const auto &sp : p->segs) info->n_fused_nodes += (int32_t)sp.ops.size();
     for (const auto *L : {&p->sum_tree.ops, &p->bwd, &p->qtree.ops, &p->max_tree.ops})
       for (const Op &op : *L) {
@@ -2558,17 +2604,49 @@ static std::vector<int32_t> slice_row(const tn_plan_t *p, const int32_t *ev, int
   return row;
 }
 static void forward_sum(tn_plan_t *p, bool with_bwd, bool allow_fused);
+// Slices [s0, s0 + n) of a run (n <= kSliceChunk): their evidence rows
+// (row(s) fills one) go to the device in one copy; per slice, body(j) runs
+// after a stream-ordered copy of row j into the plan's evidence row.  The
+// host waits once per chunk (before `rows` is rebuilt), not once per slice.
+template <class Row, class Body>
+static void slice_chunk(tn_plan_t *p, std::vector<int32_t> &rows, int64_t s0, int64_t n, Row row, Body body) {
+  const size_t nv = (size_t)p->n_vars;
+  hip_check(hipStreamSynchronize(p->stream), "slice chunk");
+  rows.resize((size_t)n * nv);
+  for (int64_t j = 0; j < n; ++j) row(s0 + j, rows.data() + j * nv);
+  hip_check(hipMemcpyAsync(p->d_slice_rows, rows.data(), rows.size() * 4, hipMemcpyHostToDevice, p->stream), "slice");
+  for (int64_t j = 0; j < n; ++j) {
+    hip_check(hipMemcpyAsync(p->d_evidence, p->d_slice_rows + j * nv, nv * 4, hipMemcpyDeviceToDevice, p->stream),
+              "slice row");
+    body(j);
+  }
+}
 // log Z_s of every slice (FP64 per slice)
 static std::vector<double> slice_log_z(tn_plan_t *p, const int32_t *ev, bool unfused) {
   const int64_t ns = n_slices_of(p);
   std::vector<double> lz(ns);
-  for (int64_t s = 0; s < ns; ++s) {
-    const std::vector<int32_t> row = slice_row(p, ev, s);
-    hip_check(hipMemcpyAsync(p->d_evidence, row.data(), row.size() * 4, hipMemcpyHostToDevice, p->stream), "slice");
-    forward_sum(p, false, !unfused);
-    hip_check(hipMemcpyAsync(&lz[s], p->d_out, sizeof(double), hipMemcpyDeviceToHost, p->stream), "D2H");
-    hip_check(hipStreamSynchronize(p->stream), "slice");
+  const std::vector<int32_t> base = slice_row(p, ev, 0);
+  std::vector<int32_t> rows;
+  for (int64_t s0 = 0; s0 < ns; s0 += kSliceChunk) {
+    const int64_t n = std::min(kSliceChunk, ns - s0);
+    slice_chunk(
+        p, rows, s0, n,
+        [&](int64_t s, int32_t *r) {
+          std::copy(base.begin(), base.end(), r);
+          for (int i = (int)p->sliced.size() - 1; i >= 0; --i) {
+            const int v = p->sliced[i];
+            r[v] = (int32_t)(s % p->card[v]);
+            s /= p->card[v];
+          }
+        },
+        [&](int64_t j) {
+          forward_sum(p, false, !unfused);
+          hip_check(hipMemcpyAsync(p->d_slice_lz + j, p->d_out, sizeof(double), hipMemcpyDeviceToDevice, p->stream),
+                    "D2D");
+        });
+    hip_check(hipMemcpyAsync(&lz[s0], p->d_slice_lz, n * sizeof(double), hipMemcpyDeviceToHost, p->stream), "D2H");
   }
+  hip_check(hipStreamSynchronize(p->stream), "slices");
   return lz;
 }
 static double log_sum_exp(const std::vector<double> &v) {
@@ -3098,26 +3176,31 @@ static void run_mmap(tn_plan_t *p, const int32_t *evidence, int32_t *assign_q, d
     row[v] = e;
   }
   int32_t *acc_ex = p->iarena + p->iarena_ints;  // one int past the index arena
+  std::vector<int32_t> rows;
   for (size_t g = 0; g < p->groups.size(); ++g) {
     const TreeExec &t = p->groups[g];
     const int sb = p->group_sliced_ptr[g], se = p->group_sliced_ptr[g + 1];
     int64_t n_slices = 1;
     for (int i = sb; i < se; ++i) n_slices *= p->card[p->group_sliced_vars[i]];
     const TensorBuf &r = p->T[t.root];
-    for (int64_t s = 0; s < n_slices; ++s) {
-      int64_t k = s;
-      for (int i = se - 1; i >= sb; --i) {
-        const int v = p->group_sliced_vars[i];
-        row[v] = (int32_t)(k % p->card[v]);
-        k /= p->card[v];
-      }
-      hip_check(hipMemcpyAsync(p->d_evidence, row.data(), row.size() * 4, hipMemcpyHostToDevice, p->stream), "slice");
-      launch_prepare_set(p, p->group_leaves[g], p->d_group_leaves[g], true);
-      run_sched(p, t.fused ? t.fops : t.ops, p->sched_groups[g]);
-      launch_slice_acc(p->arena + r.off, p->mx, p->ex, r.slot, p->d_acc, acc_ex, r.size, s == 0 ? 1 : 0, p->stream);
-      hip_check(hipStreamSynchronize(p->stream), "slice");
+    for (int64_t s0 = 0; s0 < n_slices; s0 += kSliceChunk) {
+      slice_chunk(
+          p, rows, s0, std::min(kSliceChunk, n_slices - s0),
+          [&](int64_t s, int32_t *rw) {
+            std::copy(row.begin(), row.end(), rw);
+            for (int i = se - 1; i >= sb; --i) {
+              const int v = p->group_sliced_vars[i];
+              rw[v] = (int32_t)(s % p->card[v]);
+              s /= p->card[v];
+            }
+          },
+          [&](int64_t j) {
+            launch_prepare_set(p, p->group_leaves[g], p->d_group_leaves[g], true);
+            run_sched(p, t.fused ? t.fops : t.ops, p->sched_groups[g]);
+            launch_slice_acc(p->arena + r.off, p->mx, p->ex, r.slot, p->d_acc, acc_ex, r.size, s0 + j == 0 ? 1 : 0,
+                             p->stream);
+          });
     }
-    for (int i = sb; i < se; ++i) row[p->group_sliced_vars[i]] = -1;
     launch_acc_tolog(p->d_acc, acc_ex, r.size, p->arena + p->T[p->group_log[g]].off, p->stream);
   }
   hip_check(hipMemcpyAsync(p->d_evidence, row.data(), row.size() * 4, hipMemcpyHostToDevice, p->stream), "evidence");

@@ -220,6 +220,7 @@ struct SegStep {
   int32_t ybar_slot = -1;
 };
 
+static constexpr int64_t kSliceChunk = 256;  // slices whose evidence rows are uploaded at once
 static constexpr int kSegMaxLocal = 32;   // local entries of a carrier in a segment
 static constexpr int kSegOuterBlock = 128; // outer assignments per workgroup (4 waves x 32)
 static constexpr int kSegMaxSteps = 16;    // steps of a segment
@@ -292,7 +293,11 @@ struct DSegArgs {
   int32_t ol_shift = -1;           // log2(nOl) when nOl is a power of two
   Tab2 oX, oZ;                     // offsets of O's assignments in C_0 / C_2
   int32_t nob = 1;                 // assignments of O per workgroup (power of two)
-  int32_t nA = 0, nB = 0, nC = 0, nD = 0, nQ = 1, nR = 1;
+  int32_t nA = 0, nB = 0, nC = 0, nD = 0, nQ = 1, nR = 1;  // local entries of the tiles
+  int32_t aug1 = 1, aug2 = 1;      // the first map is M1 (x) I_aug1 over (o*, A) -> (o*, B),
+                                   // the second M2 (x) I_aug2 over (o*, C) -> (o*, D), for a
+                                   // common outer label o* of aug assignments placed slowest
+                                   // in the rows (nA, nB and nR, or nC, nD and nQ count it)
   int32_t q_fast = 0, r_fast = 0;  // tile column order: 1 = the Q (R) assignment fastest
   int32_t in_lo_shift = 5, out_lo_shift = 5;  // as in SegArgs, for C_0 and C_2
   const int32_t *tab = nullptr;    // kDSegTab x 32 int32: offsets of A in C_0, of D in C_2,

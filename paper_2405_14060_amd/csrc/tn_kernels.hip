@@ -2483,6 +2483,23 @@ __device__ __forceinline__ f32x4 mfma_k32(FA fa, FB fb) {
   return acc;
 }
 
+// Entry (r, c) of a map M (x) I_aug over rows (o, i) and columns (o', j),
+// M row-major (nr / aug) x (nc / aug): M[i][j] when o == o', else zero; zero
+// past nr rows or nc columns.
+__device__ __forceinline__ float dseg_map_entry(const gcfloat *m, int nr, int nc, int aug, int r, int c) {
+  int nr0 = nr, nc0 = nc, r0 = r, c0 = c;
+  bool diag = true;
+  if (aug > 1) {
+    nr0 = nr / aug;
+    nc0 = nc / aug;
+    r0 = r % nr0;
+    c0 = c % nc0;
+    diag = r / nr0 == c / nc0;
+  }
+  const float x = m[min(r0, nr0 - 1) * nc0 + min(c0, nc0 - 1)];
+  return (r < nr && c < nc && diag) ? x : 0.f;
+}
+
 // Prologue: both maps (one entry of each per thread), then by waves 0-10:
 // column offsets of both tiles, local offsets, the gather tables, operand
 // maxima and (workgroup 0) exponents.  Every global read is independent.
@@ -2490,10 +2507,8 @@ __device__ __forceinline__ void dseg_prologue(const DSegArgs &a, uint32_t blk, b
   const int t = threadIdx.x, l = t & 63;
   {
     const int r = t >> 5, c = t & 31;
-    const float x1 = ((gcfloat *)(a.arena + a.M1))[min(r, a.nB - 1) * a.nA + min(c, a.nA - 1)];
-    const float x2 = ((gcfloat *)(a.arena + a.M2))[min(r, a.nD - 1) * a.nC + min(c, a.nC - 1)];
-    sh.m1[r * (kSegMaxLocal + 1) + c] = (r < a.nB && c < a.nA) ? x1 : 0.f;
-    sh.m2[r * (kSegMaxLocal + 1) + c] = (r < a.nD && c < a.nC) ? x2 : 0.f;
+    sh.m1[r * (kSegMaxLocal + 1) + c] = dseg_map_entry((gcfloat *)(a.arena + a.M1), a.nB, a.nA, a.aug1, r, c);
+    sh.m2[r * (kSegMaxLocal + 1) + c] = dseg_map_entry((gcfloat *)(a.arena + a.M2), a.nD, a.nC, a.aug2, r, c);
   }
   const int wv = __builtin_amdgcn_readfirstlane(t) >> 6;
   gint *tab = (gint *)a.tab;
@@ -2608,6 +2623,33 @@ __device__ __forceinline__ void dseg_s_write(const f32x4 &s, const float *park, 
   }
 }
 
+// As dseg_s_write for a map M (x) I_aug: the S of the whole tile (rows
+// (o, b), columns (o', a)) goes to LDS after park's twelve quarters, and M's
+// partial is the sum of its aug diagonal blocks.  Every thread of the
+// workgroup calls it.
+__device__ __forceinline__ void dseg_s_fold(const f32x4 &s, float *park, float *part, int nB, int nA, int aug) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  float *full = park + 12 * 256;  // 32 x (kSegMaxLocal + 1)
+  if (w < 4) {
+    const int qr = w & 1, qc = w >> 1;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float v = ((s[r] + park[w * 256 + r * 64 + l]) + park[(w + 4) * 256 + r * 64 + l]) +
+                      park[(w + 8) * 256 + r * 64 + l];
+      full[(16 * qr + 4 * (l >> 4) + r) * (kSegMaxLocal + 1) + 16 * qc + (l & 15)] = v;
+    }
+  }
+  __syncthreads();
+  const int nB0 = nB / aug, nA0 = nA / aug, t = threadIdx.x;
+  if (t < nB0 * nA0) {
+    const int b = t / nA0, c = t - b * nA0;
+    float v = 0.f;
+    for (int o = 0; o < aug; ++o) v += full[(o * nB0 + b) * (kSegMaxLocal + 1) + o * nA0 + c];
+    part[t] = v;
+  }
+}
+static_assert(12 * 256 + kSegMaxLocal * (kSegMaxLocal + 1) <= kSegMaxLocal * kSegRow, "fold area fits the tile");
+
 // Reverse: with G2 = the C_2 tile's adjoint and Y = M1 X recomputed,
 //   S2 = sum over columns of G2 B2^T (B2 = the second map's operand),
 //   G1 = M2^T G2 placed back into Y's layout (the adjoint of C_1),
@@ -2660,14 +2702,20 @@ __device__ __forceinline__ void dseg_bwd_body(const DSegArgs &a, const uint32_t 
                                [&](int r, int c) { return tx[r * kSegRow + c]; });
   const f32x4 xb = mfma_k32<PREC>([&](int k) { return sh.m1[k * (kSegMaxLocal + 1) + i]; },
                                   [&](int k) { return ty[k * kSegRow + n]; });
-  const int nP2 = a.nD * a.nC, nP1 = a.nB * a.nA;
-  if (want2) dseg_s_write(s2, tg, a.arena + a.Sp2 + (size_t)blk * nP2, a.nD, a.nC);
+  const int nP2 = (a.nD / a.aug2) * (a.nC / a.aug2), nP1 = (a.nB / a.aug1) * (a.nA / a.aug1);
+  if (want2) {
+    if (a.aug2 > 1) dseg_s_fold(s2, tg, a.arena + a.Sp2 + (size_t)blk * nP2, a.nD, a.nC, a.aug2);
+    else dseg_s_write(s2, tg, a.arena + a.Sp2 + (size_t)blk * nP2, a.nD, a.nC);
+  }
   __syncthreads();
   seg_put(xb, a.nA, tx);
   if (want1) dseg_s_park(s1, tg);
   __syncthreads();
   const float lmax = seg_store(a.arena + a.Z, sh.colX, sh.locA, a.nA, a.in_lo_shift, tx);
-  if (want1) dseg_s_write(s1, tg, a.arena + a.Sp1 + (size_t)blk * nP1, a.nB, a.nA);
+  if (want1) {
+    if (a.aug1 > 1) dseg_s_fold(s1, tg, a.arena + a.Sp1 + (size_t)blk * nP1, a.nB, a.nA, a.aug1);
+    else dseg_s_write(s1, tg, a.arena + a.Sp1 + (size_t)blk * nP1, a.nB, a.nA);
+  }
   block_record_max<kSegThreads, false>(lmax, a.mx + (blk % kMaxSub) * a.mx_stride + a.slotZ);
   if (blk == 0 && threadIdx.x == 0) {
     const int eg = sh.exG + kg, exx = sh.exX + kx;

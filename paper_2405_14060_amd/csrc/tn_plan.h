@@ -85,6 +85,8 @@ struct DSegPlan {
   uint32_t nO = 1, nOl = 1;           // common outer labels O
   int64_t oX[2], oZ[2];               // their offset tables in C_0 and C_2
   int32_t nob = 1, nQ = 1, nR = 1, q_fast = 0, r_fast = 0;
+  int32_t aug1 = 1, aug2 = 1;         // assignments of the common outer label moved into
+                                      // the first (second) map's rows and columns (1: none)
   int32_t in_lo_shift = 5, out_lo_shift = 5;
   int64_t tab = 0;                    // kDSegTab x 32 tables in the table store
   int32_t n_part = 0;                 // workgroups
@@ -226,6 +228,8 @@ struct tn_plan_impl {
   int32_t *ex = nullptr;
   int32_t *d_tabs = nullptr, *d_gmap = nullptr, *d_obs = nullptr;
   int32_t *d_evidence = nullptr;       // [max_batch][n_vars]
+  int32_t *d_slice_rows = nullptr;     // sliced plans: evidence rows of a chunk of slices
+  double *d_slice_lz = nullptr;        // and their log Z_s
   int32_t *d_assign = nullptr;         // [max_batch][n_vars]
   double *d_out = nullptr;             // logz [max_batch]
   double *d_marg = nullptr;            // [max_batch][marg_row]

@@ -80,3 +80,34 @@ def test_segment_pairs_graph_replays(T):
         lzg, mg = G.marginals()
         assert lzg[0] == lze[0]
         assert np.array_equal(mg[0], me[0])
+
+
+@pytest.mark.parametrize("size,seed", [(16, 5), (20, 0)])
+def test_segment_pairs_moving_an_outer_label(T, size, seed):
+    """Pairs whose tiles would be half empty take the slowest common outer
+    label into one map's rows and columns (the map applied as M (x) I over
+    it; its S partial the sum of the diagonal blocks): on the 16x16 grid in
+    the first map, on the 20x20 grid in the first and in the second.  log Z,
+    marginals and factor marginals (theorem thm:diff, through both maps'
+    partials) against the oracle on the plan's own tree, and against the
+    plan of the same tree that runs every segment in a pass of its own."""
+    net = W.grid_mrf(size, size, seed)
+    P = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, want_factor_grad=True)
+    info = P.info()
+    assert info["n_pairs_moved"] > 0 and info["n_pairs"] > info["n_pairs_moved"]
+    lz, m = P.marginals()
+    lzf, fm = P.factor_marginals()
+    pairs, _ = P.tree()
+    lzo, marg, *_ = oracle.marginals(net, pairs=pairs.astype(np.int64))
+    assert rel(lz[0], lzo) <= 1e-5 and rel(lzf[0], lzo) <= 1e-5
+    err = max(np.abs(a - b).max() for a, b in zip(P.split_marginals(m[0]), marg))
+    assert err <= 1e-5, err
+    _, want = oracle.factor_marginals(net, None, pairs=pairs.astype(np.int64))
+    got = P.split_factors(fm[0])
+    worst = max(float(np.abs(got[f] - want[f]).max()) for f in range(net.n_factors))
+    assert worst <= 1e-5, worst
+    U = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, tree=pairs, pair_segments=False)
+    assert U.info()["n_pairs"] == 0
+    lzu, mu = U.marginals()
+    assert rel(lz[0], lzu[0]) <= 2e-6
+    assert np.abs(m[0] - mu[0]).max() <= 2e-6
