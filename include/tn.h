@@ -122,7 +122,7 @@ typedef struct {
                                 1: keep every tree node a separate contraction;
                                 2: segments, one carrier pass each */
   int32_t autotune;          /* 1: at plan time, time every eligible kernel form
-                                (generic, row, wave, dense) of each distinct
+                                (generic, row, batch-uniform row, wave, dense) of each distinct
                                 contraction shape on the device and keep the
                                 fastest; 0: fixed rules.  The interleaved
                                 layout's tile variants always follow rules. */
@@ -412,7 +412,8 @@ tn_status tn_tune_load(const char *path, int64_t *n_loaded);
 void tn_tune_clear(void);
 
 /* Contractions of one task, for inspection: per contraction its kernel form
- * (0 generic one lane per output, 1 row, 2 dense on the matrix cores or, for
+ * (0 generic one lane per output, 1 row (variant 1: one batch assignment per
+ * wavefront, Y's block of it read once per wavefront), 2 dense on the matrix cores or, for
  * max-plus, the vector ALUs, 3 wave per output, 4 interleaved instances, 5
  * fused-segment kernel with variant 1 carrier pass, 2 its reverse, 3
  * composed maps, 4 adjoint sweeps, 5 carrier pass of two consecutive
@@ -426,6 +427,10 @@ typedef struct {
   int32_t form, semiring, variant;   /* variant: tile / order variant of the form */
   int64_t rows, cols, summed;
   int64_t x_size, y_size, z_size;
+  int32_t eligible;                  /* forms the autotuner may choose among (bits: 1 generic,
+                                        2 row, 4 dense, 8 wave, 16/32/64/128 interleaved tiles,
+                                        256 dense 128 x 128 tiles, 512 generic in output order,
+                                        1024 batch-uniform row); 0 for fused-segment kernels */
 } tn_op_info;
 tn_status tn_plan_ops(const tn_plan_t *plan, int32_t task, tn_op_info *out, int32_t cap, int32_t *n);
 

@@ -86,7 +86,8 @@ class OpProfile(ctypes.Structure):
 class OpInfo(ctypes.Structure):
     _fields_ = [("form", ctypes.c_int32), ("semiring", ctypes.c_int32), ("variant", ctypes.c_int32),
                 ("rows", ctypes.c_int64), ("cols", ctypes.c_int64), ("summed", ctypes.c_int64),
-                ("x_size", ctypes.c_int64), ("y_size", ctypes.c_int64), ("z_size", ctypes.c_int64)]
+                ("x_size", ctypes.c_int64), ("y_size", ctypes.c_int64), ("z_size", ctypes.c_int64),
+                ("eligible", ctypes.c_int32)]
 
 
 class TNError(RuntimeError):

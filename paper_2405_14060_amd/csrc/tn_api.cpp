@@ -345,9 +345,18 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
       // the rules below take it for >= 8 entries or none (sum-product), the
       // autotuner may take it for 2..7 as well
       const bool s_ok = semi == SEMI_SUM ? true : a.nS >= 8;
-      if (nM >= 16 && a.nC >= 8 && s_ok &&
-          nB * ((nM + kGemmTile - 1) / kGemmTile) * (((int64_t)a.nC + kGemmTile - 1) / kGemmTile) < (1LL << 31)) {
-        op.forms |= 4;
+      const bool dense_ok =
+          nM >= 16 && a.nC >= 8 && s_ok &&
+          nB * ((nM + kGemmTile - 1) / kGemmTile) * (((int64_t)a.nC + kGemmTile - 1) / kGemmTile) < (1LL << 31);
+      // batch-uniform row form (sum-product, offered to the autotuner): Y's
+      // summed x columns block of a batch assignment fits two entries per
+      // lane, and every batch assignment fills wavefronts of M assignments
+      const bool rowsb_ok = semi == SEMI_SUM && a.nS <= (uint32_t)kRowMax && a.nC <= (uint32_t)kRowMax &&
+                            a.nS * a.nC <= (uint32_t)kRowBlock && nM >= 64 && n_out >= (1u << 16) &&
+                            nB * ((nM + 63) / 64) < (1LL << 31);
+      if (dense_ok) op.forms |= 4;
+      if (rowsb_ok) op.forms |= 1024;
+      if (dense_ok || rowsb_ok) {
         const size_t bs = lo_split(Bl, card), ms = lo_split(Ml, card);
         add_tabs(p, Bl, bs, LX, op.t_gbX);
         add_tabs(p, Bl, bs, LY, op.t_gbY);
@@ -367,8 +376,9 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
       }
     }
     // row form for skinny contractions: few summed entries and columns
-    if (a.nS <= (uint32_t)kRowMax && a.nC <= (uint32_t)kRowMax && a.nS * a.nC <= 64) {
-      op.forms |= 2;
+    const bool row_ok = a.nS <= (uint32_t)kRowFormMax && a.nC <= (uint32_t)kRowFormMax && a.nS * a.nC <= 64;
+    if (row_ok) op.forms |= 2;
+    if (row_ok || (op.forms & 1024)) {
       a.ns = (int32_t)a.nS;
       a.nc = (int32_t)a.nC;
       auto offsets = [&](const Labels &L, const Labels &TL, int32_t *dst) {
@@ -388,6 +398,19 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
       offsets(S, LY, a.sy);
       offsets(C, LY, a.cy);
       offsets(C, LZ, a.cz);
+      // runs of four adjacent, 16-byte aligned entries (every other offset
+      // of the operand a multiple of 4): vector loads of X's row and stores
+      // of Z's row in the batch-uniform row form
+      auto runs4 = [&](const int32_t *o, int64_t n, const Labels &L, const Labels &TL) {
+        if (n % 4 != 0 || n > kRowMax) return false;
+        for (int64_t i = 0; i < n; ++i)
+          if (o[i] != o[i - i % 4] + i % 4 || o[i - i % 4] % 4 != 0) return false;
+        for (int v : minus(TL, L))
+          if (stride_in(TL, v, card) % 4 != 0) return false;
+        return true;
+      };
+      a.row_vx = (op.forms & 1024) && runs4(a.sx, a.nS, S, LX) ? 1 : 0;
+      a.row_vz = (op.forms & 1024) && runs4(a.cz, a.nC, C, LZ) ? 1 : 0;
       if ((a.nRl & (a.nRl - 1)) == 0) {
         int sh = 0;
         while ((1u << sh) < a.nRl) ++sh;
@@ -865,10 +888,11 @@ static Schedule build_schedule(tn_plan_t *p, const std::vector<Op> &ops, bool al
           const Op &op = ops[i];
           const int c = op.split ? 1 : (op.a.kind == 2 ? 2 : (op.a.kind == 4 ? 3 : 0));
           if (stage[i] == st && op.seg < 0 && op.semi == semi && c == cls) {
-            if (c == 2 && op.a.tile == 1) {  // large dense tiles: a launch of their own
+            // large dense tiles and the batch-uniform row form: a launch of their own
+            if ((c == 2 || (op.a.kind == 1 && c == 0)) && op.a.tile == 1) {
               Launch one;
               one.semi = semi;
-              one.gemm = true;
+              one.gemm = c == 2;
               one.ops.push_back(i);
               sc.launches.push_back(std::move(one));
             } else {
@@ -976,8 +1000,9 @@ static void autotune_ops(tn_plan_t *p, const std::vector<Op *> &ops) {
   hip_check(hipEventCreate(&e0), "event");
   hip_check(hipEventCreate(&e1), "event");
   // (form bit, kind, workgroup split of the summed range, tile variant)
-  static const int kForm[10][4] = {{1, 0, 1, 0},  {2, 1, 1, 0},  {4, 2, 1, 0},    {8, 3, 1, 0},   {16, 4, 1, 0},
-                                   {32, 4, 4, 0}, {64, 4, 1, 1}, {128, 4, 1, 2}, {256, 2, 1, 1}, {512, 0, 1, 1}};
+  static const int kForm[11][4] = {{1, 0, 1, 0},    {2, 1, 1, 0},   {4, 2, 1, 0},    {8, 3, 1, 0},
+                                   {16, 4, 1, 0},   {32, 4, 4, 0},  {64, 4, 1, 1},   {128, 4, 1, 2},
+                                   {256, 2, 1, 1},  {512, 0, 1, 1}, {1024, 1, 1, 1}};
   for (Op *op : ops) {
     if (op->split || op->seg >= 0) continue;
     std::vector<std::array<int, 3>> cands;
@@ -2396,6 +2421,7 @@ extern "C" tn_status tn_plan_ops(const tn_plan_t *p, int32_t task, tn_op_info *o
       o.x_size = op.X >= 0 ? p->T[op.X].size : 0;
       o.y_size = op.Y >= 0 ? p->T[op.Y].size : 0;
       o.z_size = op.Z >= 0 ? p->T[op.Z].size : 0;
+      o.eligible = op.seg >= 0 ? 0 : op.forms;
       out[i] = o;
     }
   });

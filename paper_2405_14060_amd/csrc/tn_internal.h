@@ -110,7 +110,9 @@ struct Tab2 {
   const int32_t *hi = nullptr, *lo = nullptr;
 };
 
-static constexpr int kRowMax = 16;
+static constexpr int kRowMax = 32;      // summed entries and columns held by a row-form lane
+static constexpr int kRowFormMax = 16;  // of which the row form with per-lane operand reads takes 16
+static constexpr int kRowBlock = 128;   // batch-uniform row form: Y entries per batch (summed x columns)
 static constexpr int kMaxSubSlots = 64;  // sub-slots per recorded maximum
 
 struct ContractArgs {
@@ -135,11 +137,16 @@ struct ContractArgs {
   uint32_t n_chunks = 1;
   // row form (kind 1): one lane per row, all summed entries and columns in
   // registers; offsets of the summed entries in X, Y and of the columns in
-  // Y, Z, in canonical order
+  // Y, Z, in canonical order.  tile 1 (sum-product): the rows split into
+  // batch and M labels as in the dense form (gb*, gm* tables); a wavefront
+  // takes 64 M assignments of one batch assignment and reads that batch's
+  // summed x columns block of Y once
   int32_t kind = 0;  // 0 generic, 1 row form, 2 dense matrix-core form, 3 wave per output,
                      // 4 interleaved instances (lane = instance)
   int32_t ns = 0, nc = 0;
   int32_t rl_shift = -1;  // log2(nRl) when nRl is a power of two
+  int32_t row_vx = 0;     // tile 1: summed entries 4k..4k+3 adjacent in X, 16-byte aligned
+  int32_t row_vz = 0;     // tile 1: columns 4k..4k+3 adjacent in Z, 16-byte aligned
   int32_t sx[kRowMax], sy[kRowMax], cy[kRowMax], cz[kRowMax];
   // dense form (kind 2, sum-product): the rows split into batch labels
   // (held by Y too) and M labels (not held by Y); for every batch

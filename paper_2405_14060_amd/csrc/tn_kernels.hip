@@ -47,6 +47,8 @@ typedef __attribute__((address_space(1))) const float gcfloat;
 typedef __attribute__((address_space(1))) float gfloat;
 typedef __attribute__((address_space(1))) int32_t gint_w;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const f32x4 gcf32x4;
+typedef __attribute__((address_space(1))) f32x4 gf32x4;
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 
@@ -730,12 +732,127 @@ __device__ __forceinline__ void wave_body(const ContractArgs &a, const int b, co
   }
 }
 
+// --------------------------------------------------------------------------
+// batch-uniform row form (kind 1, tile 1; sum-product with Y): the rows are
+// (batch assignment g of the labels Y holds too, M assignment m of the
+// others).  A wavefront takes 64 consecutive m of one g, so the block
+// Y[g][s][c] (ns x nc <= BS x BC <= 128 entries) is the same for all its
+// lanes: it is read once per wavefront, two entries per lane, into LDS,
+// and every product reads its entry there (one address for all lanes).  A
+// lane keeps its row of X (ns entries) and its row of Z (nc entries) in
+// registers: X and Z are read and written once, Y once per wavefront.
+// Each output sums its products in canonical summed order, as the row form.
+// --------------------------------------------------------------------------
+template <int BS, int BC>
+__device__ __forceinline__ void rowsb_body(const ContractArgs &a, const int b, const uint32_t blk,
+                                           const uint32_t nblk) {
+  static_assert(BS * BC <= kRowBlock && BC % 4 == 0, "at most two block entries per lane, columns in fours");
+  constexpr int kWaves = kBlock / 64;
+  __shared__ float4 yblk[kWaves][kRowBlock / 4];  // each wavefront's block of Y, rows of BC entries
+  gcfloat *__restrict__ X = (gcfloat *)(a.X + (int64_t)b * a.bsX);
+  gcfloat *__restrict__ Y = (gcfloat *)(a.Y + (int64_t)b * a.bsY);
+  gfloat *__restrict__ Z = (gfloat *)(a.Z + (int64_t)b * a.bsZ);
+  const int ns = a.ns, nc = a.nc;
+  int32_t sx[BS], cz[BC];
+#pragma unroll
+  for (int k = 0; k < BS; ++k) sx[k] = k < ns ? a.sx[k] : 0;
+#pragma unroll
+  for (int k = 0; k < BC; ++k) cz[k] = k < nc ? a.cz[k] : 0;
+  const int kx = max_exponent(read_max(a.mx, a.mx_stride, a.slotX + (a.batX ? b : 0)));
+  const int ky = max_exponent(read_max(a.mx, a.mx_stride, a.slotY + (a.batY ? b : 0)));
+  const float fx = ldexpf(1.f, -kx), fy = ldexpf(1.f, -ky);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  float *const yw = (float *)yblk[wv];
+  // the lane's two entries of the block: index s * BC + c
+  int32_t yoff[2];
+  bool yok[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int idx = lane + 64 * h, s = idx / BC, c = idx % BC;
+    yok[h] = s < ns && c < nc;
+    yoff[h] = yok[h] ? a.sy[s] + a.cy[c] : 0;
+  }
+  // wavefront w takes batch assignment w % nB and M assignments 64 (w / nB)
+  // on: consecutive wavefronts run the batch assignments of one run of M
+  // assignments, which share the cache lines of X and Z where batch labels
+  // are faster than M labels
+  const uint32_t nM = a.nM, nB = a.nB, wpg = (nM + 63) / 64;  // wavefronts per batch assignment
+  const uint32_t n_waves = nB * wpg;
+  float lmax = 0.f;
+  // every wavefront of the workgroup runs every pass (the barriers), a pass
+  // past the last wavefront computes nothing it stores
+  for (uint32_t w0 = blk * kWaves; w0 < n_waves; w0 += nblk * kWaves) {
+    const uint32_t w = w0 + wv < n_waves ? w0 + wv : n_waves - 1;
+    const uint32_t mb = w / nB, g = w - mb * nB, m = mb * 64 + lane;
+    const bool live = w0 + wv < n_waves && m < nM;
+    const uint32_t mc = m < nM ? m : 0u;
+    const int32_t yg = tab_off(a.gbY, g, a.nBl);
+    const int32_t xo = tab_off(a.gbX, g, a.nBl) + tab_off(a.gmX, mc, a.nMl);
+    const int32_t zo = tab_off(a.gbZ, g, a.nBl) + tab_off(a.gmZ, mc, a.nMl);
+    float xv[BS];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) yw[lane + 64 * h] = yok[h] ? Y[yg + yoff[h]] * fy : 0.f;
+    if (BS >= 4 && a.row_vx) {  // summed entries in aligned runs of four
+#pragma unroll
+      for (int k = 0; k < BS; k += 4)
+        if (k < ns) {
+          const f32x4 v = *(gcf32x4 *)(X + xo + sx[k]);
+          xv[k] = v[0] * fx;
+          xv[k + 1] = v[1] * fx;
+          xv[k + 2] = v[2] * fx;
+          xv[k + 3] = v[3] * fx;
+        } else {
+          xv[k] = xv[k + 1] = xv[k + 2] = xv[k + 3] = 0.f;
+        }
+    } else {
+#pragma unroll
+      for (int k = 0; k < BS; ++k) xv[k] = k < ns ? X[xo + sx[k]] * fx : 0.f;
+    }
+    __syncthreads();
+    float acc[BC];
+#pragma unroll
+    for (int c = 0; c < BC; ++c) acc[c] = 0.f;
+#pragma unroll
+    for (int k = 0; k < BS; ++k) {
+      if (k >= ns) break;
+#pragma unroll
+      for (int c4 = 0; c4 < BC / 4; ++c4) {
+        const float4 y = yblk[wv][k * (BC / 4) + c4];  // the same address on every lane
+        acc[4 * c4] = fmaf(xv[k], y.x, acc[4 * c4]);
+        acc[4 * c4 + 1] = fmaf(xv[k], y.y, acc[4 * c4 + 1]);
+        acc[4 * c4 + 2] = fmaf(xv[k], y.z, acc[4 * c4 + 2]);
+        acc[4 * c4 + 3] = fmaf(xv[k], y.w, acc[4 * c4 + 3]);
+      }
+    }
+    if (live && a.row_vz) {  // columns in aligned runs of four
+#pragma unroll
+      for (int c = 0; c < BC; c += 4)
+        if (c < nc) {
+          const f32x4 v = {acc[c], acc[c + 1], acc[c + 2], acc[c + 3]};
+          *(gf32x4 *)(Z + zo + cz[c]) = v;
+          lmax = fmaxf(lmax, fmaxf(fmaxf(acc[c], acc[c + 1]), fmaxf(acc[c + 2], acc[c + 3])));
+        }
+    } else if (live) {
+#pragma unroll
+      for (int c = 0; c < BC; ++c)
+        if (c < nc) {
+          Z[zo + cz[c]] = acc[c];
+          lmax = fmaxf(lmax, acc[c]);
+        }
+    }
+    __syncthreads();  // the next pass rewrites the blocks
+  }
+  block_record_max(lmax, a.mx + (blk % kMaxSub) * a.mx_stride + a.slotZ + (a.batZ ? b : 0));
+  if (blk == 0 && threadIdx.x == 0)
+    a.ex[a.slotZ + (a.batZ ? b : 0)] = a.ex[a.slotX + (a.batX ? b : 0)] + kx + a.ex[a.slotY + (a.batY ? b : 0)] + ky;
+}
+
 template <int SEMI, bool HASY>
 __device__ __forceinline__ void any_map_body(const ContractArgs &a, const int b, const uint32_t blk,
                                              const uint32_t nblk) {
   if (a.kind == 1) {
     if (a.ns <= 4 && a.nc <= 4) rows_body<SEMI, HASY, 4>(a, b, blk, nblk);
-    else rows_body<SEMI, HASY, kRowMax>(a, b, blk, nblk);
+    else rows_body<SEMI, HASY, kRowFormMax>(a, b, blk, nblk);
   } else if (a.kind == 3) {
     wave_body<SEMI, HASY>(a, b, blk, nblk);
   } else {
@@ -1594,6 +1711,12 @@ template <int SEMI, bool HASY>
 __global__ __launch_bounds__(kBlock) void k_map(const ContractArgs *__restrict__ ap) {
   any_map_body<SEMI, HASY>(*ap, blockIdx.y, blockIdx.x, gridDim.x);
 }
+// the batch-uniform row form runs in launches of its own (its registers
+// would lower the occupancy of the other map forms)
+template <int BS, int BC>
+__global__ __launch_bounds__(kBlock) void k_rowsb(const ContractArgs *__restrict__ ap) {
+  rowsb_body<BS, BC>(*ap, blockIdx.y, blockIdx.x, gridDim.x);
+}
 template <int SEMI, bool HASY>
 __global__ __launch_bounds__(kBlock) void k_split(const ContractArgs *__restrict__ ap) {
   split_body<SEMI, HASY>(*ap, blockIdx.y, blockIdx.x);
@@ -1686,6 +1809,11 @@ uint32_t map_blocks(const ContractArgs &a) {
     return a.nB * ((a.nM + kBT - 1) / kBT) * ((a.nC + kBT - 1) / kBT);
   if (a.kind == 2)  // one 64 x 64 tile per workgroup
     return a.nB * ((a.nM + kGT - 1) / kGT) * ((a.nC + kGT - 1) / kGT);
+  if (a.kind == 1 && a.tile == 1) {  // one pass per wavefront of 64 M assignments of one batch assignment
+    const uint64_t waves = (uint64_t)a.nB * ((a.nM + 63) / 64);
+    const uint64_t blocks = (waves + kBlock / 64 - 1) / (kBlock / 64);
+    return blocks > (1u << 20) ? (1u << 20) : (uint32_t)blocks;
+  }
   const uint32_t n_out = a.kind == 1 ? a.nR : a.nR * a.nC;
   if (a.kind == 3) {  // kWaveOuts outputs per workgroup pass
     const uint32_t blocks = (n_out + kWaveOuts - 1) / kWaveOuts;
@@ -1741,6 +1869,17 @@ void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, co
     else if (a.prec == 1) k_gemm<1><<<g, kBlock, 0, s>>>(d_a);
     else if (a.prec == 2) k_gemm<2><<<g, kBlock, 0, s>>>(d_a);
     else k_gemm<0><<<g, kBlock, 0, s>>>(d_a);
+    return;
+  }
+  if (a.kind == 1 && a.tile == 1) {  // batch-uniform row form: sum-product with Y
+    const dim3 g(map_blocks(a), nb);
+    if (a.ns <= 4 && a.nc <= 8) k_rowsb<4, 8><<<g, kBlock, 0, s>>>(d_a);
+    else if (a.ns <= 4 && a.nc <= 16) k_rowsb<4, 16><<<g, kBlock, 0, s>>>(d_a);
+    else if (a.ns <= 4) k_rowsb<4, 32><<<g, kBlock, 0, s>>>(d_a);
+    else if (a.ns <= 8 && a.nc <= 8) k_rowsb<8, 8><<<g, kBlock, 0, s>>>(d_a);
+    else if (a.ns <= 8) k_rowsb<8, 16><<<g, kBlock, 0, s>>>(d_a);
+    else if (a.ns <= 16) k_rowsb<16, 8><<<g, kBlock, 0, s>>>(d_a);
+    else k_rowsb<32, 4><<<g, kBlock, 0, s>>>(d_a);
     return;
   }
   if (!split) {

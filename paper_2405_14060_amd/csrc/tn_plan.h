@@ -53,7 +53,7 @@ struct Op {
   std::vector<int> ins, outs;
   int forms = 0;                      // eligible kernel forms: 1 generic, 2 row, 4 dense, 8 wave,
                                       // 16 interleaved, 256 dense with 128 x 128 tiles, 512 generic
-                                      // in output order
+                                      // in output order, 1024 batch-uniform row form
 };
 
 // Host description of a fused segment (tables as offsets into the plan's
