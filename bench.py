@@ -49,10 +49,10 @@ KIND_NAMES = {0: "contract_map_sum", 1: "contract_map_max", 2: "contract_split_s
 # the kernel source they were taken from (sha256 prefix of tn_kernels.hip):
 # {(kernel, workload): {"src": sha, "bytes": B}}
 MEASURED_TRAFFIC = {
-    ("seg_carrier_bwd", "grid20x20"): {"src": "1c294f238fa68d94", "bytes": 26390948},
-    ("contract_interleaved_sum", "bn500x512"): {"src": "1c294f238fa68d94", "bytes": 69951096},
-    ("contract_map_max", "grid20_map"): {"src": "1c294f238fa68d94", "bytes": 22759587},
-    ("contract_tropical_dense", "tropical_gemm"): {"src": "1c294f238fa68d94", "bytes": 115419110},
+    ("seg_carrier_bwd", "grid20x20"): {"src": "04850ea7f4399c30", "bytes": 26371578},
+    ("contract_interleaved_sum", "bn500x512"): {"src": "04850ea7f4399c30", "bytes": 69933510},
+    ("contract_map_max", "grid20_map"): {"src": "04850ea7f4399c30", "bytes": 22761094},
+    ("contract_tropical_dense", "tropical_gemm"): {"src": "04850ea7f4399c30", "bytes": 115405029},
 }
 
 def kernel_src_sha():
