@@ -146,6 +146,17 @@ __device__ __forceinline__ int32_t tab_off(const Tab2 &t, uint32_t i, uint32_t n
   return ((gint *)t.hi)[h] + ((gint *)t.lo)[i - h * nlo];
 }
 
+// Workgroup x of n (ids counted from the first of a segment or launch) -> its
+// tile.  Workgroups go to the XCDs in turn (id modulo 8); the tiles are dealt
+// so that each XCD takes a run of consecutive tiles, whose pieces of an
+// operand share cache lines when a tile's runs are shorter than a line (the
+// other pieces of the line are then read from that XCD's L2 instead of again
+// from HBM).
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t x, uint32_t n) {
+  const uint32_t k = x & 7u;
+  return k * (n >> 3) + min(k, n & 7u) + (x >> 3);
+}
+
 // --------------------------------------------------------------------------
 // generic contraction, one lane per output element
 // --------------------------------------------------------------------------
@@ -775,7 +786,7 @@ __device__ __forceinline__ void rowsb_body(const ContractArgs &a, const int b, c
   // wavefront w takes batch assignment w % nB and M assignments 64 (w / nB)
   // on: consecutive wavefronts run the batch assignments of one run of M
   // assignments, which share the cache lines of X and Z where batch labels
-  // are faster than M labels
+  // are faster than M labels (consecutive workgroups run on one XCD)
   const uint32_t nM = a.nM, nB = a.nB, wpg = (nM + 63) / 64;  // wavefronts per batch assignment
   const uint32_t n_waves = nB * wpg;
   float lmax = 0.f;
@@ -1715,7 +1726,7 @@ __global__ __launch_bounds__(kBlock) void k_map(const ContractArgs *__restrict__
 // would lower the occupancy of the other map forms)
 template <int BS, int BC>
 __global__ __launch_bounds__(kBlock) void k_rowsb(const ContractArgs *__restrict__ ap) {
-  rowsb_body<BS, BC>(*ap, blockIdx.y, blockIdx.x, gridDim.x);
+  rowsb_body<BS, BC>(*ap, blockIdx.y, xcd_tile(blockIdx.x, gridDim.x), gridDim.x);
 }
 template <int SEMI, bool HASY>
 __global__ __launch_bounds__(kBlock) void k_split(const ContractArgs *__restrict__ ap) {
@@ -1926,16 +1937,6 @@ static constexpr int kSegOB = kSegOuterBlock;     // outer assignments per workg
 static constexpr int kSegRow = kSegOB + 1;        // padded LDS tile row: conflict-free in both directions
 
 unsigned seg_blocks(const SegArgs &a) { return (a.nO + kSegOB - 1) / kSegOB; }
-
-// Workgroup x of n (ids counted from the first of a segment) -> its tile.
-// Workgroups go to the XCDs in turn (id modulo 8); the tiles are dealt so
-// that each XCD takes a run of consecutive tiles, whose carrier pieces share
-// cache lines when a tile's runs are shorter than a line (the other pieces
-// of the line are then read from that XCD's L2 instead of again from HBM).
-__device__ __forceinline__ uint32_t xcd_tile(uint32_t x, uint32_t n) {
-  const uint32_t k = x & 7u;
-  return k * (n >> 3) + min(k, n & 7u) + (x >> 3);
-}
 
 __device__ __forceinline__ int32_t outer_off(const Tab2 &t, uint32_t o, uint32_t nlo) {
   const uint32_t h = o / nlo;
