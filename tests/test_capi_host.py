@@ -94,6 +94,41 @@ def test_segment_pairs_on_host(T):
     assert P.info()["n_launches_fwd"] < U.info()["n_launches_fwd"]
 
 
+def test_pairs_moving_an_outer_label_on_host(T):
+    """On the 20x20 grid every segment of both fronts is paired: the pairs
+    whose tiles would be half empty take a common outer label into one map's
+    rows (plan info counts them), which leaves fewer carrier passes than the
+    pairs without them would (each such pass then runs two segments)."""
+    net = W.grid_mrf(20, 20, 0)
+    P = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, host_only=True)
+    info = P.info()
+    assert info["n_pairs"] > info["n_pairs_moved"] > 0
+    # every segment in a pair but one per front (chains of odd length): the
+    # forward list holds at most two single-segment passes over a large carrier
+    def singles(plan):
+        return [o for o in plan.ops(0) if o["form"] == 5 and o["variant"] == 1 and o["x_size"] >= 1 << 16]
+    assert len(singles(P)) <= 2
+    U = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, host_only=True, pair_segments=False)
+    assert U.info()["n_pairs"] == 0 and U.info()["n_pairs_moved"] == 0
+    # unpaired, each pair's two segments run alone (the first pair starts on a
+    # carrier below 2^16 entries)
+    assert len(singles(U)) == len(singles(P)) + 2 * (info["n_pairs"] - 1)
+
+
+def test_row_batch_form_is_offered(T):
+    """The batch-uniform row form is eligible (never the rules' choice) for
+    the MMAP slice's batched products with small summed x column blocks."""
+    c = W.config(4, 0)
+    P = T.Plan(T.Network(c["net"]), semirings=T.SUM_PRODUCT | T.MAX_PLUS, query=c["query"], max_log2_size=28,
+               host_only=True, restarts=16)
+    ops = P.ops(3)
+    elig = [o for o in ops if o["eligible"] & 1024]
+    assert elig
+    for o in elig:
+        assert o["semiring"] == 0 and o["summed"] * o["cols"] <= 128 and o["z_size"] >= 1 << 16
+    assert not any(o["form"] == 1 and o["variant"] == 1 for o in ops)  # rules: not chosen
+
+
 def test_mmap_sum_phase_fuses_chains(T):
     """An MMAP plan's sum phase runs forward only, so its chains of small
     absorptions fuse into segments like the main tree's forward pass (and
