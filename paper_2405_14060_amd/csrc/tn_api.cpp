@@ -582,6 +582,126 @@ static void build_forward(tn_plan_t *p, TreeExec &t, int semi) {
 
 // Readout steps for a max-plus tree: top-down, each node's main argmax
 // first, then the argmax of its children's private reductions.
+// Pairs of consecutive max-plus contractions along the tree's chains (the
+// second's X is the first's output, which nothing else reads) run as one
+// pass (kKindMaxPair) where each step sums over at most four assignments,
+// the second adds at most four columns and its summed labels all come from
+// the first's output: the first's values stay in registers, both argmax
+// arrays are written as the unpaired contractions write them (same values,
+// same first-maximiser indices, so the readout is unchanged).  Contractions
+// of >= 2^16 outputs of one instance only.  Fills t.fops (a pair sits at
+// its second contraction's place, after every producer of its operands);
+// t.fused when a pair formed.
+static void build_max_pairs(tn_plan_t *p, TreeExec &t) {
+  const auto &card = p->card;
+  const int n = (int)t.ops.size();
+  std::map<int, int> uses, reader;  // tensor -> ops reading it; op reading it as X
+  for (int i = 0; i < n; ++i) {
+    uses[t.ops[i].X]++;
+    if (t.ops[i].Y >= 0) uses[t.ops[i].Y]++;
+    reader[t.ops[i].X] = i;
+  }
+  auto ok = [&](const Op &op) {
+    return op.semi == SEMI_MAX && op.Y >= 0 && !op.split && op.nb == 1 && op.inst == 1 && op.seg < 0 && op.I >= 0;
+  };
+  // offsets of the assignments of L (row-major, last fastest) in a tensor
+  // with labels TL (0 for labels it lacks)
+  auto offs = [&](const Labels &L, const Labels &TL) {
+    std::vector<int32_t> o;
+    std::vector<int> d(L.size(), 0);
+    for (int64_t i = 0, m = numel(L, card); i < m; ++i) {
+      int64_t v = 0;
+      for (size_t k = 0; k < L.size(); ++k) v += (int64_t)d[k] * stride_in(TL, L[k], card);
+      o.push_back((int32_t)v);
+      for (int k = (int)L.size() - 1; k >= 0; --k) {
+        if (++d[k] < card[L[k]]) break;
+        d[k] = 0;
+      }
+    }
+    return o;
+  };
+  std::vector<int> first_of(n, -1);  // second contraction of a pair -> its first
+  std::vector<char> in_pair(n, 0);
+  for (int i = 0; i < n; ++i) {
+    const Op &a = t.ops[i];
+    if (in_pair[i] || !ok(a) || a.Z == t.root || uses[a.Z] != 1 || !reader.count(a.Z)) continue;
+    const int j = reader[a.Z];
+    const Op &b = t.ops[j];
+    if (j <= i || in_pair[j] || !ok(b)) continue;
+    const Labels &LX = p->T[a.X].lab, &LY1 = p->T[a.Y].lab, &LZ1 = p->T[a.Z].lab;
+    const Labels &LY2 = p->T[b.Y].lab, &LZ2 = p->T[b.Z].lab;
+    const Labels S1 = minus(unite(LX, LY1), LZ1), S2 = minus(unite(LZ1, LY2), LZ2);
+    const Labels R2 = inter(LZ2, LZ1), C2 = minus(LZ2, LZ1);
+    if (!minus(S2, LZ1).empty() || numel(S1, card) > kPairMax || numel(S2, card) > kPairMax ||
+        numel(C2, card) > kPairMax || numel(LZ2, card) < (1 << 16) || numel(R2, card) >= (int64_t(1) << 31))
+      continue;
+    in_pair[i] = in_pair[j] = 1;
+    first_of[j] = i;
+  }
+  t.fops.clear();
+  t.fused = false;
+  for (int j = 0; j < n; ++j) {
+    if (in_pair[j] && first_of[j] < 0) continue;  // a pair's first: emitted with its second
+    if (first_of[j] < 0) {
+      t.fops.push_back(t.ops[j]);
+      continue;
+    }
+    const Op &a = t.ops[first_of[j]], &b = t.ops[j];
+    const Labels &LX = p->T[a.X].lab, &LY1 = p->T[a.Y].lab, &LZ1 = p->T[a.Z].lab;
+    const Labels &LY2 = p->T[b.Y].lab, &LZ2 = p->T[b.Z].lab;
+    const Labels S1 = minus(unite(LX, LY1), LZ1), S2 = minus(unite(LZ1, LY2), LZ2);
+    const Labels R2 = inter(LZ2, LZ1), C2 = minus(LZ2, LZ1);
+    Op f;
+    f.semi = SEMI_MAX;
+    f.X = a.X;
+    f.Y = a.Y;
+    f.Z = b.Z;
+    f.I = b.I;
+    f.Y2 = b.Y;
+    f.I1 = a.I;
+    f.ins.push_back(b.Y);
+    for (auto *tb : {f.t_rX, f.t_rY, f.t_rZ, f.t_cY, f.t_cZ, f.t_sX, f.t_sY, f.t_gbX, f.t_gbY, f.t_gbZ, f.t_gmX,
+                     f.t_gmZ, f.t_oX, f.t_oY})
+      tb[0] = tb[1] = -1;
+    const size_t rs = lo_split(R2, card);
+    add_tabs(p, R2, rs, LX, f.t_rX);
+    add_tabs(p, R2, rs, LY1, f.t_rY);
+    add_tabs(p, R2, rs, LZ2, f.t_rZ);
+    add_tabs(p, R2, rs, LZ1, f.t_gbZ);
+    add_tabs(p, R2, rs, LY2, f.t_gbY);
+    ContractArgs &c = f.a;
+    c.kind = kKindMaxPair;
+    c.nR = (uint32_t)numel(R2, card);
+    c.nRl = (uint32_t)numel(Labels(R2.begin() + rs, R2.end()), card);
+    if ((c.nRl & (c.nRl - 1)) == 0) {
+      int sh = 0;
+      while ((1u << sh) < c.nRl) ++sh;
+      c.rl_shift = sh;
+    }
+    c.ns = (int32_t)numel(S1, card);
+    c.ns2 = (int32_t)numel(S2, card);
+    c.nc = (int32_t)numel(C2, card);
+    c.nS = (uint32_t)c.ns;
+    c.nC = (uint32_t)c.nc;
+    const std::vector<int32_t> xs1 = offs(S1, LX), ys1 = offs(S1, LY1), xs2 = offs(S2, LX), ys2 = offs(S2, LY1);
+    const std::vector<int32_t> zs2 = offs(S2, LZ1), y2s2 = offs(S2, LY2), y2c = offs(C2, LY2), zc = offs(C2, LZ2);
+    for (int u = 0; u < c.ns2; ++u) {
+      for (int v = 0; v < c.ns; ++v) {
+        c.sx[kPairMax * u + v] = xs2[u] + xs1[v];
+        c.sy[kPairMax * u + v] = ys2[u] + ys1[v];
+      }
+      c.cz[u] = zs2[u];
+      for (int w = 0; w < c.nc; ++w) c.cy[kPairMax * w + u] = y2s2[u] + y2c[w];
+    }
+    for (int w = 0; w < c.nc; ++w) c.cz[kPairZ + w] = zc[w];
+    f.flops = a.flops + b.flops;
+    f.bytes = 4.0 * (double)(p->T[a.X].size + p->T[a.Y].size + p->T[b.Y].size + p->T[b.Z].size + p->T[a.Z].size);
+    t.fops.push_back(f);
+    t.fused = true;
+  }
+  if (!t.fused) t.fops.clear();
+}
+
 static void build_backtrack(tn_plan_t *p, TreeExec &t) {
   t.back.clear();
   t.back_meta.clear();
@@ -802,6 +922,8 @@ static void fill_args(tn_plan_t *p, Op &op) {
   a.Z = p->arena + Z.off;
   strides(Z, a.bsZ, a.esZ);
   a.I = op.I >= 0 ? p->iarena + p->IB[op.I].off : nullptr;
+  if (op.Y2 >= 0) a.Y2 = p->arena + p->T[op.Y2].off;
+  if (op.I1 >= 0) a.I1 = p->iarena + p->IB[op.I1].off;
   a.mx = p->mx;
   a.ex = p->ex;
   a.mx_stride = std::max(1, p->n_slots);
@@ -878,15 +1000,18 @@ static Schedule build_schedule(tn_plan_t *p, const std::vector<Op> &ops, bool al
       }
     }
     for (int semi = 0; semi < 2; ++semi)
-      for (int cls = 0; cls < 4; ++cls) {  // one-lane-per-output forms, split reductions, dense, interleaved
+      for (int cls = 0; cls < 5; ++cls) {  // one-lane-per-output forms, split reductions, dense, interleaved,
+                                           // max-plus pairs
         Launch L;
         L.semi = semi;
         L.split = cls == 1;
         L.gemm = cls == 2;
         L.inter = cls == 3;
+        L.mpair = cls == 4;
         for (int i = 0; i < n; ++i) {
           const Op &op = ops[i];
-          const int c = op.split ? 1 : (op.a.kind == 2 ? 2 : (op.a.kind == 4 ? 3 : 0));
+          const int c = op.split ? 1
+                                 : (op.a.kind == 2 ? 2 : (op.a.kind == 4 ? 3 : (op.a.kind == kKindMaxPair ? 4 : 0)));
           if (stage[i] == st && op.seg < 0 && op.semi == semi && c == cls) {
             // large dense tiles and the batch-uniform row form: a launch of their own
             if ((c == 2 || (op.a.kind == 1 && c == 0)) && op.a.tile == 1) {
@@ -1249,11 +1374,11 @@ static void allocate(tn_plan_t *p, const tn_net *net) {
       // the fused lists hold copies of the unfused contractions: same choice
       std::map<int, std::array<int, 3>> kind_of;  // output tensor -> form
       for (Op *op : all) kind_of[op->Z] = {op->a.kind, op->a.ksplit, op->a.tile};
-      std::vector<std::vector<Op> *> lists{&p->ffwd, &p->fbwd};
+      std::vector<std::vector<Op> *> lists{&p->ffwd, &p->fbwd, &p->max_tree.fops};
       for (auto &g : p->groups) lists.push_back(&g.fops);
       for (auto *L : lists)
         for (Op &op : *L)
-          if (op.seg < 0 && kind_of.count(op.Z)) {
+          if (op.seg < 0 && op.a.kind != kKindMaxPair && kind_of.count(op.Z)) {
             op.a.kind = kind_of[op.Z][0];
             op.a.ksplit = kind_of[op.Z][1];
             op.a.tile = kind_of[op.Z][2];
@@ -1262,12 +1387,22 @@ static void allocate(tn_plan_t *p, const tn_net *net) {
   }
   p->sched_fwd = build_schedule(p, p->sum_tree.ops, false);
   p->sched_bwd = build_schedule(p, p->bwd, true);
-  p->sched_max = build_schedule(p, p->max_tree.ops, false);
+  if (p->max_tree.fused) {  // arguments of the list with max-plus pairs
+    std::vector<ContractArgs> host;
+    for (auto &op : p->max_tree.fops) {
+      fill_args(p, op);
+      host.push_back(op.a);
+    }
+    ContractArgs *d = dupload(p, host);
+    for (size_t k = 0; k < p->max_tree.fops.size(); ++k) p->max_tree.fops[k].d_a = d + k;
+  }
+  const std::vector<Op> &max_list = p->max_tree.fused ? p->max_tree.fops : p->max_tree.ops;
+  p->sched_max = build_schedule(p, max_list, false);
   p->sched_q = build_schedule(p, p->qtree.ops, false);
   p->sched_samp = build_schedule(p, p->samp_ops, false);
   upload_schedule(p, p->sched_fwd, p->sum_tree.ops);
   upload_schedule(p, p->sched_bwd, p->bwd);
-  upload_schedule(p, p->sched_max, p->max_tree.ops);
+  upload_schedule(p, p->sched_max, max_list);
   upload_schedule(p, p->sched_q, p->qtree.ops);
   upload_schedule(p, p->sched_samp, p->samp_ops);
   for (auto &g : p->groups) {
@@ -2300,6 +2435,7 @@ static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
     t.pairs = p->pairs;
     t.lab = lab;
     build_forward(p, t, SEMI_MAX);
+    if (p->opts.no_fuse != 1 && !p->batched_ev && p->max_batch == 1) build_max_pairs(p, t);
     build_backtrack(p, t);
   }
   if (o->host_only) return;
@@ -2356,7 +2492,8 @@ extern "C" tn_status tn_plan_info_get(const tn_plan_t *p, tn_plan_info *info) {
       tn_plan_t *q = const_cast<tn_plan_t *>(p);
       info->n_launches_fwd = count(p->fused ? build_schedule(q, p->ffwd, false) : build_schedule(q, p->sum_tree.ops, false));
       info->n_launches_bwd = count(p->fused ? build_schedule(q, p->fbwd, true) : build_schedule(q, p->bwd, true));
-      info->n_launches_max = count(build_schedule(q, p->max_tree.ops, false));
+      info->n_launches_max =
+          count(build_schedule(q, p->max_tree.fused ? p->max_tree.fops : p->max_tree.ops, false));
     } else if (p->fused) {
       info->n_launches_fwd = count(p->sched_ffwd);
       info->n_launches_bwd = count(p->sched_fbwd);
@@ -2519,6 +2656,8 @@ void run_sched(tn_plan_t *p, const std::vector<Op> &ops, const Schedule &sc) {
                    (int)L.ops.size(), L.total, p->stream);
     } else if (L.inter) {
       launch_group(L.semi, 6, L.d_args, L.d_blk, L.d_nblk, (int)L.ops.size(), L.total, p->stream);
+    } else if (L.mpair) {
+      launch_group(L.semi, 7, L.d_args, L.d_blk, L.d_nblk, (int)L.ops.size(), L.total, p->stream);
     } else if (!L.split) {
       launch_group(L.semi, 0, L.d_args, L.d_blk, L.d_nblk, (int)L.ops.size(), L.total, p->stream);
     } else {
@@ -2832,7 +2971,7 @@ extern "C" tn_status tn_map(tn_plan_t *p, int32_t batch, const int32_t *evidence
                                hipMemcpyDeviceToDevice, p->stream), "init");
       run_graph(p, "max", [&] {
         launch_prepare_set(p, p->leaves_max, p->d_leaves_max, false);
-        run_sched(p, p->max_tree.ops, p->sched_max);
+        run_sched(p, p->max_tree.fused ? p->max_tree.fops : p->max_tree.ops, p->sched_max);
         launch_backtrack(p->iarena, p->d_back, p->d_back_lev, p->max_tree.n_back_lev, p->max_tree.n_back_chunks, p->d_back_meta,
                          p->n_vars, p->max_batch, p->d_assign, p->stream);
       });
@@ -3348,7 +3487,7 @@ static tn_status profile_impl(tn_plan_t *p, int32_t task, int32_t batch, const i
       }
     } else {
       ls.push_back({4, 0, 0, [p] { launch_prepare_set(p, p->leaves_max, p->d_leaves_max, false); }});
-      add_ops(p->max_tree.ops, p->sched_max);
+      add_ops(p->max_tree.fused ? p->max_tree.fops : p->max_tree.ops, p->sched_max);
       ls.push_back({5, 0, 0, [p] {
                       launch_backtrack(p->iarena, p->d_back, p->d_back_lev, p->max_tree.n_back_lev,
                                        p->max_tree.n_back_chunks, p->d_back_meta, p->n_vars, p->max_batch, p->d_assign, p->stream);

@@ -175,7 +175,21 @@ struct ContractArgs {
   // output through tables over Z's labels (stride 0 for labels they lack)
   Tab2 oX, oY;
   uint32_t nOl = 1;         // entries of the low tables
+  // two consecutive max-plus contractions in one pass (kind kKindMaxPair):
+  // Z1 = X (x) Y, then Z = Z1 (x) Y2, Z1's values kept in registers, both
+  // argmax arrays written (I1 over Z1's layout, I over Z's).  A lane takes
+  // one assignment r of R2 = Z's labels held by Z1; rX, rY, rZ: its offsets
+  // in X, Y, Z; gbZ, gbY: in Z1 and Y2.  Per summed assignment s2 of the
+  // second step (ns2 <= 4) and s1 of the first (ns <= 4), k = 4 s2 + s1:
+  // sx[k], sy[k] offsets in X and Y; cz[s2] in Z1; per column c (nc <= 4)
+  // cy[4 c + s2] in Y2 and cz[kPairZ + c] in Z.
+  const float *Y2 = nullptr;
+  int32_t *I1 = nullptr;
+  int32_t ns2 = 0;
 };
+static constexpr int kKindMaxPair = 7;
+static constexpr int kPairMax = 4;    // summed assignments of either step, columns of the second
+static constexpr int kPairZ = 16;     // cz[kPairZ + c]: Z offsets of the second step's columns
 static constexpr int kGemmTile = 64;  // output tile edge of the dense form
 static constexpr int kInterTile = 4;  // output tile edge (rows x columns) of the interleaved form
 static constexpr int kInterLanes = 64;  // instances per wavefront of the interleaved form

@@ -858,6 +858,91 @@ __device__ __forceinline__ void rowsb_body(const ContractArgs &a, const int b, c
     a.ex[a.slotZ + (a.batZ ? b : 0)] = a.ex[a.slotX + (a.batX ? b : 0)] + kx + a.ex[a.slotY + (a.batY ? b : 0)] + ky;
 }
 
+// --------------------------------------------------------------------------
+// two consecutive max-plus contractions in one pass (kind kKindMaxPair; the
+// arguments' layout is described with ContractArgs): a lane takes one
+// assignment r of R2, forms the first step's outputs (r, s2) for every s2
+// in registers (writing their argmax to I1, as the first contraction alone
+// would), then the second step's outputs (r, c) and their argmax.  Values
+// are one FP32 add per candidate and the first maximiser in canonical order
+// wins, exactly as in the other max-plus forms.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void mpair_body(const ContractArgs &a, const uint32_t blk, const uint32_t nblk) {
+  gcfloat *__restrict__ X = (gcfloat *)a.X;
+  gcfloat *__restrict__ Y1 = (gcfloat *)a.Y;
+  gcfloat *__restrict__ Y2 = (gcfloat *)a.Y2;
+  gfloat *__restrict__ Z = (gfloat *)a.Z;
+  gint_w *__restrict__ I1 = (gint_w *)a.I1;
+  gint_w *__restrict__ I2 = (gint_w *)a.I;
+  const int n1 = a.ns, n2 = a.ns2, nc = a.nc;
+  constexpr int K = kPairMax;
+  int32_t sx[K * K], sy[K * K], y2[K * K], z1[K], z2[K];
+#pragma unroll
+  for (int k = 0; k < K * K; ++k) {
+    const bool in1 = (k / K) < n2 && (k % K) < n1, in2 = (k / K) < nc && (k % K) < n2;
+    sx[k] = in1 ? a.sx[k] : 0;
+    sy[k] = in1 ? a.sy[k] : 0;
+    y2[k] = in2 ? a.cy[k] : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    z1[k] = k < n2 ? a.cz[k] : 0;
+    z2[k] = k < nc ? a.cz[kPairZ + k] : 0;
+  }
+  const uint32_t nR = a.nR, nRl = a.nRl;
+  const int rls = a.rl_shift;
+  for (uint32_t r = blk * kBlock + threadIdx.x; r < nR; r += nblk * kBlock) {
+    uint32_t rh, rl;
+    if (rls >= 0) {
+      rh = r >> rls;
+      rl = r & (nRl - 1);
+    } else {
+      rh = r / nRl;
+      rl = r - rh * nRl;
+    }
+    const int32_t xo = ((gint *)a.rX.hi)[rh] + ((gint *)a.rX.lo)[rl];
+    const int32_t y1o = ((gint *)a.rY.hi)[rh] + ((gint *)a.rY.lo)[rl];
+    const int32_t zo = ((gint *)a.rZ.hi)[rh] + ((gint *)a.rZ.lo)[rl];
+    const int32_t z1o = ((gint *)a.gbZ.hi)[rh] + ((gint *)a.gbZ.lo)[rl];
+    const int32_t y2o = ((gint *)a.gbY.hi)[rh] + ((gint *)a.gbY.lo)[rl];
+    float xv[K * K], v1[K];
+#pragma unroll
+    for (int k = 0; k < K * K; ++k)
+      if ((k / K) < n2 && (k % K) < n1) xv[k] = X[xo + sx[k]] + Y1[y1o + sy[k]];
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+      if (u >= n2) break;
+      float best = -INFINITY;
+      int32_t bi = 0;
+#pragma unroll
+      for (int w = 0; w < K; ++w)
+        if (w < n1 && (w == 0 || xv[K * u + w] > best)) {
+          best = xv[K * u + w];
+          bi = w;
+        }
+      v1[u] = best;
+      I1[z1o + z1[u]] = bi;
+    }
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+      if (c >= nc) break;
+      float best = -INFINITY;
+      int32_t bi = 0;
+#pragma unroll
+      for (int u = 0; u < K; ++u)
+        if (u < n2) {
+          const float v = v1[u] + Y2[y2o + y2[K * c + u]];
+          if (u == 0 || v > best) {
+            best = v;
+            bi = u;
+          }
+        }
+      Z[zo + z2[c]] = best;
+      I2[zo + z2[c]] = bi;
+    }
+  }
+}
+
 template <int SEMI, bool HASY>
 __device__ __forceinline__ void any_map_body(const ContractArgs &a, const int b, const uint32_t blk,
                                              const uint32_t nblk) {
@@ -1728,6 +1813,9 @@ template <int BS, int BC>
 __global__ __launch_bounds__(kBlock) void k_rowsb(const ContractArgs *__restrict__ ap) {
   rowsb_body<BS, BC>(*ap, blockIdx.y, xcd_tile(blockIdx.x, gridDim.x), gridDim.x);
 }
+__global__ __launch_bounds__(kBlock) void k_mpair(const ContractArgs *__restrict__ ap) {
+  mpair_body(*ap, blockIdx.x, gridDim.x);
+}
 template <int SEMI, bool HASY>
 __global__ __launch_bounds__(kBlock) void k_split(const ContractArgs *__restrict__ ap) {
   split_body<SEMI, HASY>(*ap, blockIdx.y, blockIdx.x);
@@ -1762,13 +1850,17 @@ __global__ __launch_bounds__(kBlock) void k_group(const ContractArgs *__restrict
   }
   const int b = (int)(local / per);
   const uint32_t blk = local - (uint32_t)b * per;
+  if (PHASE == 7) {  // pairs of max-plus contractions (one instance)
+    mpair_body(a, blk, per);
+    return;
+  }
   if (PHASE == 0) {
     if (hy) any_map_body<SEMI, true>(a, b, blk, per);
     else any_map_body<SEMI, false>(a, b, blk, per);
   } else if (PHASE == 1) {
     if (hy) split_body<SEMI, true>(a, b, blk);
     else split_body<SEMI, false>(a, b, blk);
-  } else if (PHASE >= 3) {  // dense form (sum-product: operand precision PHASE - 3)
+  } else if (PHASE >= 3 && PHASE <= 5) {  // dense form (sum-product: operand precision PHASE - 3)
     if (SEMI == SEMI_MAX) gemm_max_body(a, b, blk);
     else gemm_body<PHASE - 3>(a, b, blk);
   } else {
@@ -1785,6 +1877,10 @@ void launch_group(int semi, int phase, const ContractArgs *ops, const GroupBlock
   if (phase == 6) {
     if (semi == SEMI_SUM) k_group<SEMI_SUM, 6><<<g, kBlock, 0, s>>>(ops, start, nblk, n);
     else k_group<SEMI_MAX, 6><<<g, kBlock, 0, s>>>(ops, start, nblk, n);
+    return;
+  }
+  if (phase == 7) {  // pairs of max-plus contractions
+    k_group<SEMI_MAX, 7><<<g, kBlock, 0, s>>>(ops, start, nblk, n);
     return;
   }
   if (phase >= 3 && semi == SEMI_MAX) {  // dense max-plus form
@@ -1820,6 +1916,10 @@ uint32_t map_blocks(const ContractArgs &a) {
     return a.nB * ((a.nM + kBT - 1) / kBT) * ((a.nC + kBT - 1) / kBT);
   if (a.kind == 2)  // one 64 x 64 tile per workgroup
     return a.nB * ((a.nM + kGT - 1) / kGT) * ((a.nC + kGT - 1) / kGT);
+  if (a.kind == kKindMaxPair) {  // one lane per row
+    const uint32_t blocks = (a.nR + kBlock - 1) / kBlock;
+    return blocks > 65536u ? 65536u : blocks;
+  }
   if (a.kind == 1 && a.tile == 1) {  // one pass per wavefront of 64 M assignments of one batch assignment
     const uint64_t waves = (uint64_t)a.nB * ((a.nM + 63) / 64);
     const uint64_t blocks = (waves + kBlock / 64 - 1) / (kBlock / 64);
@@ -1880,6 +1980,10 @@ void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, co
     else if (a.prec == 1) k_gemm<1><<<g, kBlock, 0, s>>>(d_a);
     else if (a.prec == 2) k_gemm<2><<<g, kBlock, 0, s>>>(d_a);
     else k_gemm<0><<<g, kBlock, 0, s>>>(d_a);
+    return;
+  }
+  if (a.kind == kKindMaxPair) {
+    k_mpair<<<map_blocks(a), kBlock, 0, s>>>(d_a);
     return;
   }
   if (a.kind == 1 && a.tile == 1) {  // batch-uniform row form: sum-product with Y

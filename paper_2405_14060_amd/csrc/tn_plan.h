@@ -51,6 +51,8 @@ struct Op {
   // written, for scheduling
   int seg = -1, seg_kind = 0;
   std::vector<int> ins, outs;
+  int Y2 = -1, I1 = -1;               // two max-plus contractions in one pass: the second's Y,
+                                      // the first's argmax buffer
   int forms = 0;                      // eligible kernel forms: 1 generic, 2 row, 4 dense, 8 wave,
                                       // 16 interleaved, 256 dense with 128 x 128 tiles, 512 generic
                                       // in output order, 1024 batch-uniform row form
@@ -100,6 +102,7 @@ struct Launch {
   bool split = false;
   bool gemm = false;                  // dense-form contractions (matrix cores)
   bool inter = false;                 // interleaved-form contractions
+  bool mpair = false;                 // pairs of max-plus contractions (kKindMaxPair)
   bool seg = false;                   // fused-segment kernels (carrier kinds alone)
   int seg_kind = 0;
   std::vector<int> ops;               // indices into the op list
@@ -131,7 +134,7 @@ struct TreeExec {
   std::vector<int> node_tensor;       // tensor id of every node
   int root = -1;                      // tensor holding the result over `out`
   std::vector<Op> ops;
-  std::vector<Op> fops;               // forward list with fused segments (when fused)
+  std::vector<Op> fops;               // forward list with fused segments or max-plus pairs (when fused)
   bool fused = false;
   std::vector<std::vector<int>> node_ops;  // op indices per pair (reductions, then main)
   int root_op = -1;                   // op reducing the root to `out`, if any

@@ -525,6 +525,26 @@ def test_map_batched_indicators(T):
         assert np.float32(lp[b]) == np.float32(v32)
 
 
+@pytest.mark.parametrize("size", [16, 20])
+def test_map_paired_steps_bit_exact(T, size):
+    """Grids whose chains of max-plus contractions over >= 2^16 outputs run
+    two consecutive contractions per pass (the first's values in registers,
+    both argmax arrays written): assignment and value bit-identical to the
+    oracle's FP32 emulation on the plan's tree and to the plan that runs
+    every contraction alone (eq. log-map, tropical contraction)."""
+    net = W.grid_mrf(size, size, 0)
+    P = T.Plan(T.Network(net), semirings=T.MAX_PLUS)
+    pairs, _ = P.tree()
+    U = T.Plan(T.Network(net), semirings=T.MAX_PLUS, fuse=False, tree=pairs)
+    assert P.info()["n_launches_max"] < U.info()["n_launches_max"]
+    lp, x = P.map()
+    lpu, xu = U.map()
+    assert np.array_equal(x[0], xu[0]) and np.float32(lp[0]) == np.float32(lpu[0])
+    val, asg = oracle.map_assignment(net, None, pairs=pairs.astype(np.int64), fp32=True)
+    assert np.array_equal(x[0], np.asarray(asg))
+    assert np.float32(lp[0]) == np.float32(val)
+
+
 def test_map_ferromagnetic_tie(T):
     net = W.chain_mrf(np.full(40, 0.7))
     lv = oracle.build_leaves(net, domain="log")
