@@ -586,12 +586,14 @@ static void build_forward(tn_plan_t *p, TreeExec &t, int semi) {
 // second's X is the first's output, which nothing else reads) run as one
 // pass (kKindMaxPair) where each step sums over at most four assignments,
 // the second adds at most four columns and its summed labels all come from
-// the first's output: the first's values stay in registers, both argmax
-// arrays are written as the unpaired contractions write them (same values,
-// same first-maximiser indices, so the readout is unchanged).  Contractions
-// of >= 2^16 outputs of one instance only.  Fills t.fops (a pair sits at
-// its second contraction's place, after every producer of its operands);
-// t.fused when a pair formed.
+// the first's output: the first's values stay in registers (the same FP32
+// values and first maximisers as the unpaired contractions), and the
+// second's index array holds, per output, both steps' choices as one index
+// over (S1, S2), S2 fastest — the readout takes both steps with one read
+// and the first's index array is not written.  Contractions of >= 2^16
+// outputs of one instance only.  Fills t.fops (a pair sits at its second
+// contraction's place, after every producer of its operands) and
+// t.pair_first; t.fused when a pair formed.
 static void build_max_pairs(tn_plan_t *p, TreeExec &t) {
   const auto &card = p->card;
   const int n = (int)t.ops.size();
@@ -640,6 +642,12 @@ static void build_max_pairs(tn_plan_t *p, TreeExec &t) {
   }
   t.fops.clear();
   t.fused = false;
+  t.pair_first.assign(n, -1);
+  for (int j = 0; j < n; ++j)
+    if (first_of[j] >= 0) {
+      t.pair_first[j] = first_of[j];
+      t.pair_first[first_of[j]] = -2;
+    }
   for (int j = 0; j < n; ++j) {
     if (in_pair[j] && first_of[j] < 0) continue;  // a pair's first: emitted with its second
     if (first_of[j] < 0) {
@@ -658,7 +666,6 @@ static void build_max_pairs(tn_plan_t *p, TreeExec &t) {
     f.Z = b.Z;
     f.I = b.I;
     f.Y2 = b.Y;
-    f.I1 = a.I;
     f.ins.push_back(b.Y);
     for (auto *tb : {f.t_rX, f.t_rY, f.t_rZ, f.t_cY, f.t_cZ, f.t_sX, f.t_sY, f.t_gbX, f.t_gbY, f.t_gbZ, f.t_gmX,
                      f.t_gmZ, f.t_oX, f.t_oY})
@@ -667,7 +674,6 @@ static void build_max_pairs(tn_plan_t *p, TreeExec &t) {
     add_tabs(p, R2, rs, LX, f.t_rX);
     add_tabs(p, R2, rs, LY1, f.t_rY);
     add_tabs(p, R2, rs, LZ2, f.t_rZ);
-    add_tabs(p, R2, rs, LZ1, f.t_gbZ);
     add_tabs(p, R2, rs, LY2, f.t_gbY);
     ContractArgs &c = f.a;
     c.kind = kKindMaxPair;
@@ -684,28 +690,42 @@ static void build_max_pairs(tn_plan_t *p, TreeExec &t) {
     c.nS = (uint32_t)c.ns;
     c.nC = (uint32_t)c.nc;
     const std::vector<int32_t> xs1 = offs(S1, LX), ys1 = offs(S1, LY1), xs2 = offs(S2, LX), ys2 = offs(S2, LY1);
-    const std::vector<int32_t> zs2 = offs(S2, LZ1), y2s2 = offs(S2, LY2), y2c = offs(C2, LY2), zc = offs(C2, LZ2);
+    const std::vector<int32_t> y2s2 = offs(S2, LY2), y2c = offs(C2, LY2), zc = offs(C2, LZ2);
     for (int u = 0; u < c.ns2; ++u) {
       for (int v = 0; v < c.ns; ++v) {
         c.sx[kPairMax * u + v] = xs2[u] + xs1[v];
         c.sy[kPairMax * u + v] = ys2[u] + ys1[v];
       }
-      c.cz[u] = zs2[u];
       for (int w = 0; w < c.nc; ++w) c.cy[kPairMax * w + u] = y2s2[u] + y2c[w];
     }
     for (int w = 0; w < c.nc; ++w) c.cz[kPairZ + w] = zc[w];
     f.flops = a.flops + b.flops;
-    f.bytes = 4.0 * (double)(p->T[a.X].size + p->T[a.Y].size + p->T[b.Y].size + p->T[b.Z].size + p->T[a.Z].size);
+    f.bytes = 4.0 * (double)(p->T[a.X].size + p->T[a.Y].size + p->T[b.Y].size + p->T[b.Z].size);
     t.fops.push_back(f);
     t.fused = true;
   }
-  if (!t.fused) t.fops.clear();
+  if (!t.fused) {
+    t.fops.clear();
+    t.pair_first.clear();
+  }
 }
 
 static void build_backtrack(tn_plan_t *p, TreeExec &t) {
   t.back.clear();
   t.back_meta.clear();
-  auto add_step = [&](const Op &op) {
+  // a step reads the op's argmax at its output's assignment and assigns its
+  // eliminated variables; the second contraction of a max-plus pair assigns
+  // the first's too (its index runs over both, the second's fastest), and
+  // the first has no step of its own
+  auto eliminated = [&](const Op &op) {
+    Labels U = p->T[op.X].lab;
+    if (op.Y >= 0) U = unite(U, p->T[op.Y].lab);
+    return minus(U, p->T[op.Z].lab);
+  };
+  auto add_step = [&](int id) {
+    const int first = t.pair_first.empty() ? -1 : t.pair_first[id];
+    if (first == -2) return;
+    const Op &op = t.ops[id];
     BackStep s{};
     s.arg = op.I;  // IntBuf id; converted to an offset at allocation
     const Labels &LZ = p->T[op.Z].lab;
@@ -715,21 +735,23 @@ static void build_backtrack(tn_plan_t *p, TreeExec &t) {
       t.back_meta.push_back((int32_t)stride_in(LZ, v, p->card));
     }
     s.in_end = (int32_t)(t.back_meta.size() / 2);
-    Labels U = p->T[op.X].lab;
-    if (op.Y >= 0) U = unite(U, p->T[op.Y].lab);
     s.out_begin = s.in_end;
-    for (int v : minus(U, LZ)) {
+    Labels out;
+    if (first >= 0) out = eliminated(t.ops[first]);
+    const Labels own = eliminated(op);
+    out.insert(out.end(), own.begin(), own.end());
+    for (int v : out) {
       t.back_meta.push_back(v);
       t.back_meta.push_back(p->card[v]);
     }
     s.out_end = (int32_t)(t.back_meta.size() / 2);
     t.back.push_back(s);
   };
-  if (t.root_op >= 0) add_step(t.ops[t.root_op]);
+  if (t.root_op >= 0) add_step(t.root_op);
   for (int q = (int)t.pairs.size() - 1; q >= 0; --q) {
     const auto &ids = t.node_ops[q];
-    add_step(t.ops[ids.back()]);
-    for (size_t k = 0; k + 1 < ids.size(); ++k) add_step(t.ops[ids[k]]);
+    add_step(ids.back());
+    for (size_t k = 0; k + 1 < ids.size(); ++k) add_step(ids[k]);
   }
   // Readout levels: a step needs the variables of its node's output, which
   // earlier steps assign; level = 1 + the largest level among the steps that
@@ -923,7 +945,6 @@ static void fill_args(tn_plan_t *p, Op &op) {
   strides(Z, a.bsZ, a.esZ);
   a.I = op.I >= 0 ? p->iarena + p->IB[op.I].off : nullptr;
   if (op.Y2 >= 0) a.Y2 = p->arena + p->T[op.Y2].off;
-  if (op.I1 >= 0) a.I1 = p->iarena + p->IB[op.I1].off;
   a.mx = p->mx;
   a.ex = p->ex;
   a.mx_stride = std::max(1, p->n_slots);

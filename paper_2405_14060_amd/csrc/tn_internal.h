@@ -176,15 +176,14 @@ struct ContractArgs {
   Tab2 oX, oY;
   uint32_t nOl = 1;         // entries of the low tables
   // two consecutive max-plus contractions in one pass (kind kKindMaxPair):
-  // Z1 = X (x) Y, then Z = Z1 (x) Y2, Z1's values kept in registers, both
-  // argmax arrays written (I1 over Z1's layout, I over Z's).  A lane takes
-  // one assignment r of R2 = Z's labels held by Z1; rX, rY, rZ: its offsets
-  // in X, Y, Z; gbZ, gbY: in Z1 and Y2.  Per summed assignment s2 of the
+  // Z1 = X (x) Y, then Z = Z1 (x) Y2, Z1 kept in registers; I gets, per
+  // output of Z, the index s1 * ns2 + s2 of both steps' first maximisers.  A
+  // lane takes one assignment r of R2 = Z's labels held by Z1; rX, rY, rZ:
+  // its offsets in X, Y, Z; gbY: in Y2.  Per summed assignment s2 of the
   // second step (ns2 <= 4) and s1 of the first (ns <= 4), k = 4 s2 + s1:
-  // sx[k], sy[k] offsets in X and Y; cz[s2] in Z1; per column c (nc <= 4)
-  // cy[4 c + s2] in Y2 and cz[kPairZ + c] in Z.
+  // sx[k], sy[k] offsets in X and Y; per column c (nc <= 4) cy[4 c + s2]
+  // in Y2 and cz[kPairZ + c] in Z.
   const float *Y2 = nullptr;
-  int32_t *I1 = nullptr;
   int32_t ns2 = 0;
 };
 static constexpr int kKindMaxPair = 7;

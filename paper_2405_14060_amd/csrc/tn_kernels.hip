@@ -862,21 +862,21 @@ __device__ __forceinline__ void rowsb_body(const ContractArgs &a, const int b, c
 // two consecutive max-plus contractions in one pass (kind kKindMaxPair; the
 // arguments' layout is described with ContractArgs): a lane takes one
 // assignment r of R2, forms the first step's outputs (r, s2) for every s2
-// in registers (writing their argmax to I1, as the first contraction alone
-// would), then the second step's outputs (r, c) and their argmax.  Values
-// are one FP32 add per candidate and the first maximiser in canonical order
-// wins, exactly as in the other max-plus forms.
+// in registers with their argmax s1, then the second step's outputs (r, c);
+// its index array gets both choices as one index, s1 * ns2 + s2 (the
+// readout assigns both steps' variables from it).  Values are one FP32 add
+// per candidate and the first maximiser in canonical order wins, exactly as
+// in the other max-plus forms.
 // --------------------------------------------------------------------------
 __device__ __forceinline__ void mpair_body(const ContractArgs &a, const uint32_t blk, const uint32_t nblk) {
   gcfloat *__restrict__ X = (gcfloat *)a.X;
   gcfloat *__restrict__ Y1 = (gcfloat *)a.Y;
   gcfloat *__restrict__ Y2 = (gcfloat *)a.Y2;
   gfloat *__restrict__ Z = (gfloat *)a.Z;
-  gint_w *__restrict__ I1 = (gint_w *)a.I1;
   gint_w *__restrict__ I2 = (gint_w *)a.I;
   const int n1 = a.ns, n2 = a.ns2, nc = a.nc;
   constexpr int K = kPairMax;
-  int32_t sx[K * K], sy[K * K], y2[K * K], z1[K], z2[K];
+  int32_t sx[K * K], sy[K * K], y2[K * K], z2[K];
 #pragma unroll
   for (int k = 0; k < K * K; ++k) {
     const bool in1 = (k / K) < n2 && (k % K) < n1, in2 = (k / K) < nc && (k % K) < n2;
@@ -885,10 +885,7 @@ __device__ __forceinline__ void mpair_body(const ContractArgs &a, const uint32_t
     y2[k] = in2 ? a.cy[k] : 0;
   }
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    z1[k] = k < n2 ? a.cz[k] : 0;
-    z2[k] = k < nc ? a.cz[kPairZ + k] : 0;
-  }
+  for (int k = 0; k < K; ++k) z2[k] = k < nc ? a.cz[kPairZ + k] : 0;
   const uint32_t nR = a.nR, nRl = a.nRl;
   const int rls = a.rl_shift;
   for (uint32_t r = blk * kBlock + threadIdx.x; r < nR; r += nblk * kBlock) {
@@ -903,9 +900,9 @@ __device__ __forceinline__ void mpair_body(const ContractArgs &a, const uint32_t
     const int32_t xo = ((gint *)a.rX.hi)[rh] + ((gint *)a.rX.lo)[rl];
     const int32_t y1o = ((gint *)a.rY.hi)[rh] + ((gint *)a.rY.lo)[rl];
     const int32_t zo = ((gint *)a.rZ.hi)[rh] + ((gint *)a.rZ.lo)[rl];
-    const int32_t z1o = ((gint *)a.gbZ.hi)[rh] + ((gint *)a.gbZ.lo)[rl];
     const int32_t y2o = ((gint *)a.gbY.hi)[rh] + ((gint *)a.gbY.lo)[rl];
     float xv[K * K], v1[K];
+    int32_t i1[K];
 #pragma unroll
     for (int k = 0; k < K * K; ++k)
       if ((k / K) < n2 && (k % K) < n1) xv[k] = X[xo + sx[k]] + Y1[y1o + sy[k]];
@@ -921,13 +918,13 @@ __device__ __forceinline__ void mpair_body(const ContractArgs &a, const uint32_t
           bi = w;
         }
       v1[u] = best;
-      I1[z1o + z1[u]] = bi;
+      i1[u] = bi;
     }
 #pragma unroll
     for (int c = 0; c < K; ++c) {
       if (c >= nc) break;
       float best = -INFINITY;
-      int32_t bi = 0;
+      int32_t bi = 0, b1 = i1[0];
 #pragma unroll
       for (int u = 0; u < K; ++u)
         if (u < n2) {
@@ -935,10 +932,11 @@ __device__ __forceinline__ void mpair_body(const ContractArgs &a, const uint32_t
           if (u == 0 || v > best) {
             best = v;
             bi = u;
+            b1 = i1[u];
           }
         }
       Z[zo + z2[c]] = best;
-      I2[zo + z2[c]] = bi;
+      I2[zo + z2[c]] = b1 * n2 + bi;
     }
   }
 }

@@ -51,8 +51,7 @@ struct Op {
   // written, for scheduling
   int seg = -1, seg_kind = 0;
   std::vector<int> ins, outs;
-  int Y2 = -1, I1 = -1;               // two max-plus contractions in one pass: the second's Y,
-                                      // the first's argmax buffer
+  int Y2 = -1;                        // two max-plus contractions in one pass: the second's Y
   int forms = 0;                      // eligible kernel forms: 1 generic, 2 row, 4 dense, 8 wave,
                                       // 16 interleaved, 256 dense with 128 x 128 tiles, 512 generic
                                       // in output order, 1024 batch-uniform row form
@@ -135,6 +134,8 @@ struct TreeExec {
   int root = -1;                      // tensor holding the result over `out`
   std::vector<Op> ops;
   std::vector<Op> fops;               // forward list with fused segments or max-plus pairs (when fused)
+  std::vector<int> pair_first;        // max-plus pairs: per op, the first contraction of the pair
+                                      // it ends (-1: none); the first's own entry is -2
   bool fused = false;
   std::vector<std::vector<int>> node_ops;  // op indices per pair (reductions, then main)
   int root_op = -1;                   // op reducing the root to `out`, if any
