@@ -582,18 +582,20 @@ static void build_forward(tn_plan_t *p, TreeExec &t, int semi) {
 
 // Readout steps for a max-plus tree: top-down, each node's main argmax
 // first, then the argmax of its children's private reductions.
-// Pairs of consecutive max-plus contractions along the tree's chains (the
-// second's X is the first's output, which nothing else reads) run as one
-// pass (kKindMaxPair) where each step sums over at most four assignments,
-// the second adds at most four columns and its summed labels all come from
-// the first's output: the first's values stay in registers (the same FP32
-// values and first maximisers as the unpaired contractions), and the
-// second's index array holds, per output, both steps' choices as one index
-// over (S1, S2), S2 fastest — the readout takes both steps with one read
-// and the first's index array is not written.  Contractions of >= 2^16
-// outputs of one instance only.  Fills t.fops (a pair sits at its second
-// contraction's place, after every producer of its operands) and
-// t.pair_first; t.fused when a pair formed.
+// Chains of two or three consecutive max-plus contractions (each one's X is
+// the previous one's output, which nothing else reads) run as one pass
+// (kKindMaxPair): pairs where each step sums over at most four assignments
+// and the second adds at most four columns, triples where every step sums
+// over at most two and the third adds at most two; every later step's
+// summed labels come from the previous output.  The intermediate values
+// stay in registers (the same FP32 values and first maximisers as the
+// contractions alone), and the last step's index array holds, per output,
+// every step's choice as one index over (S1, S2[, S3]), the last fastest —
+// the readout takes the whole chain with one read, and the other index
+// arrays are not written.  Contractions of >= 2^16 outputs of one instance
+// only.  Fills t.fops (a chain sits at its last contraction's place, after
+// every producer of its operands), t.chain_prev and t.chain_inner; t.fused
+// when a chain formed.
 static void build_max_pairs(tn_plan_t *p, TreeExec &t) {
   const auto &card = p->card;
   const int n = (int)t.ops.size();
@@ -622,63 +624,96 @@ static void build_max_pairs(tn_plan_t *p, TreeExec &t) {
     }
     return o;
   };
-  std::vector<int> first_of(n, -1);  // second contraction of a pair -> its first
-  std::vector<char> in_pair(n, 0);
-  for (int i = 0; i < n; ++i) {
+  auto elim = [&](const Op &op) { return minus(unite(p->T[op.X].lab, p->T[op.Y].lab), p->T[op.Z].lab); };
+  // the contraction reading op i's output as its X, if op i may start or
+  // continue a chain
+  auto next = [&](int i) {
     const Op &a = t.ops[i];
-    if (in_pair[i] || !ok(a) || a.Z == t.root || uses[a.Z] != 1 || !reader.count(a.Z)) continue;
+    if (!ok(a) || a.Z == t.root || uses[a.Z] != 1 || !reader.count(a.Z)) return -1;
     const int j = reader[a.Z];
-    const Op &b = t.ops[j];
-    if (j <= i || in_pair[j] || !ok(b)) continue;
-    const Labels &LX = p->T[a.X].lab, &LY1 = p->T[a.Y].lab, &LZ1 = p->T[a.Z].lab;
-    const Labels &LY2 = p->T[b.Y].lab, &LZ2 = p->T[b.Z].lab;
-    const Labels S1 = minus(unite(LX, LY1), LZ1), S2 = minus(unite(LZ1, LY2), LZ2);
+    return j > i && ok(t.ops[j]) ? j : -1;
+  };
+  std::vector<std::vector<int>> chain_at(n);  // last contraction -> the chain
+  std::vector<char> used(n, 0);
+  for (int i = 0; i < n; ++i) {
+    if (used[i]) continue;
+    const int j = next(i);
+    if (j < 0 || used[j]) continue;
+    const Op &a = t.ops[i], &b = t.ops[j];
+    const Labels &LZ1 = p->T[a.Z].lab, &LZ2 = p->T[b.Z].lab;
+    const Labels S1 = elim(a), S2 = elim(b);
+    const int k = next(j);
+    if (k >= 0 && !used[k]) {  // three steps, each of at most two summed assignments
+      const Op &c = t.ops[k];
+      const Labels &LZ3 = p->T[c.Z].lab;
+      const Labels S3 = elim(c), C3 = minus(LZ3, LZ2), R3 = inter(LZ3, LZ2);
+      if (minus(S2, LZ1).empty() && minus(S3, LZ2).empty() && numel(S1, card) <= kTripleMax &&
+          numel(S2, card) <= kTripleMax && numel(S3, card) <= kTripleMax && numel(C3, card) <= kTripleMax &&
+          numel(LZ3, card) >= (1 << 16) && numel(R3, card) < (int64_t(1) << 31)) {
+        used[i] = used[j] = used[k] = 1;
+        chain_at[k] = {i, j, k};
+        continue;
+      }
+    }
     const Labels R2 = inter(LZ2, LZ1), C2 = minus(LZ2, LZ1);
     if (!minus(S2, LZ1).empty() || numel(S1, card) > kPairMax || numel(S2, card) > kPairMax ||
         numel(C2, card) > kPairMax || numel(LZ2, card) < (1 << 16) || numel(R2, card) >= (int64_t(1) << 31))
       continue;
-    in_pair[i] = in_pair[j] = 1;
-    first_of[j] = i;
+    used[i] = used[j] = 1;
+    chain_at[j] = {i, j};
   }
   t.fops.clear();
   t.fused = false;
-  t.pair_first.assign(n, -1);
-  for (int j = 0; j < n; ++j)
-    if (first_of[j] >= 0) {
-      t.pair_first[j] = first_of[j];
-      t.pair_first[first_of[j]] = -2;
-    }
+  t.chain_prev.assign(n, -1);
+  t.chain_inner.assign(n, 0);
   for (int j = 0; j < n; ++j) {
-    if (in_pair[j] && first_of[j] < 0) continue;  // a pair's first: emitted with its second
-    if (first_of[j] < 0) {
+    const std::vector<int> &ch = chain_at[j];
+    for (size_t q = 0; q < ch.size(); ++q) {
+      if (q > 0) t.chain_prev[ch[q]] = ch[q - 1];
+      if (q + 1 < ch.size()) t.chain_inner[ch[q]] = 1;
+    }
+  }
+  for (int j = 0; j < n; ++j) {
+    if (used[j] && chain_at[j].empty()) continue;  // emitted with its chain's last contraction
+    if (chain_at[j].empty()) {
       t.fops.push_back(t.ops[j]);
       continue;
     }
-    const Op &a = t.ops[first_of[j]], &b = t.ops[j];
-    const Labels &LX = p->T[a.X].lab, &LY1 = p->T[a.Y].lab, &LZ1 = p->T[a.Z].lab;
-    const Labels &LY2 = p->T[b.Y].lab, &LZ2 = p->T[b.Z].lab;
-    const Labels S1 = minus(unite(LX, LY1), LZ1), S2 = minus(unite(LZ1, LY2), LZ2);
-    const Labels R2 = inter(LZ2, LZ1), C2 = minus(LZ2, LZ1);
+    const std::vector<int> &ch = chain_at[j];
+    const bool three = ch.size() == 3;
+    const Op &a = t.ops[ch[0]], &b = t.ops[ch[1]], &last = t.ops[j];
+    const Labels &LX = p->T[a.X].lab, &LY1 = p->T[a.Y].lab, &LZ1 = p->T[a.Z].lab, &LY2 = p->T[b.Y].lab;
+    const Labels &LZ2 = p->T[b.Z].lab, &LZ = p->T[last.Z].lab;
+    const Labels &LY3 = p->T[last.Y].lab;
+    const Labels &Lprev = three ? LZ2 : LZ1;  // the last step's X
+    const Labels R = inter(LZ, Lprev), C = minus(LZ, Lprev);
+    const Labels S1 = elim(a), S2 = elim(b), S3 = three ? elim(last) : Labels{};
     Op f;
     f.semi = SEMI_MAX;
     f.X = a.X;
     f.Y = a.Y;
-    f.Z = b.Z;
-    f.I = b.I;
+    f.Z = last.Z;
+    f.I = last.I;
     f.Y2 = b.Y;
     f.ins.push_back(b.Y);
+    if (three) {
+      f.Y3 = last.Y;
+      f.ins.push_back(last.Y);
+    }
     for (auto *tb : {f.t_rX, f.t_rY, f.t_rZ, f.t_cY, f.t_cZ, f.t_sX, f.t_sY, f.t_gbX, f.t_gbY, f.t_gbZ, f.t_gmX,
                      f.t_gmZ, f.t_oX, f.t_oY})
       tb[0] = tb[1] = -1;
-    const size_t rs = lo_split(R2, card);
-    add_tabs(p, R2, rs, LX, f.t_rX);
-    add_tabs(p, R2, rs, LY1, f.t_rY);
-    add_tabs(p, R2, rs, LZ2, f.t_rZ);
-    add_tabs(p, R2, rs, LY2, f.t_gbY);
+    const size_t rs = lo_split(R, card);
+    add_tabs(p, R, rs, LX, f.t_rX);
+    add_tabs(p, R, rs, LY1, f.t_rY);
+    add_tabs(p, R, rs, LZ, f.t_rZ);
+    add_tabs(p, R, rs, LY2, f.t_gbY);
+    if (three) add_tabs(p, R, rs, LY3, f.t_gmX);
     ContractArgs &c = f.a;
     c.kind = kKindMaxPair;
-    c.nR = (uint32_t)numel(R2, card);
-    c.nRl = (uint32_t)numel(Labels(R2.begin() + rs, R2.end()), card);
+    c.steps = three ? 3 : 2;
+    c.nR = (uint32_t)numel(R, card);
+    c.nRl = (uint32_t)numel(Labels(R.begin() + rs, R.end()), card);
     if ((c.nRl & (c.nRl - 1)) == 0) {
       int sh = 0;
       while ((1u << sh) < c.nRl) ++sh;
@@ -686,27 +721,63 @@ static void build_max_pairs(tn_plan_t *p, TreeExec &t) {
     }
     c.ns = (int32_t)numel(S1, card);
     c.ns2 = (int32_t)numel(S2, card);
-    c.nc = (int32_t)numel(C2, card);
+    c.ns3 = three ? (int32_t)numel(S3, card) : 1;
+    c.nc = (int32_t)numel(C, card);
     c.nS = (uint32_t)c.ns;
     c.nC = (uint32_t)c.nc;
     const std::vector<int32_t> xs1 = offs(S1, LX), ys1 = offs(S1, LY1), xs2 = offs(S2, LX), ys2 = offs(S2, LY1);
-    const std::vector<int32_t> y2s2 = offs(S2, LY2), y2c = offs(C2, LY2), zc = offs(C2, LZ2);
-    for (int u = 0; u < c.ns2; ++u) {
-      for (int v = 0; v < c.ns; ++v) {
-        c.sx[kPairMax * u + v] = xs2[u] + xs1[v];
-        c.sy[kPairMax * u + v] = ys2[u] + ys1[v];
+    const std::vector<int32_t> zc = offs(C, LZ);
+    if (!three) {
+      const std::vector<int32_t> y2s2 = offs(S2, LY2), y2c = offs(C, LY2);
+      for (int u = 0; u < c.ns2; ++u) {
+        for (int v = 0; v < c.ns; ++v) {
+          c.sx[kPairMax * u + v] = xs2[u] + xs1[v];
+          c.sy[kPairMax * u + v] = ys2[u] + ys1[v];
+        }
+        for (int w = 0; w < c.nc; ++w) c.cy[kPairMax * w + u] = y2s2[u] + y2c[w];
       }
-      for (int w = 0; w < c.nc; ++w) c.cy[kPairMax * w + u] = y2s2[u] + y2c[w];
+    } else {
+      const std::vector<int32_t> xs3 = offs(S3, LX), ys3 = offs(S3, LY1), y2s2 = offs(S2, LY2), y2s3 = offs(S3, LY2);
+      const std::vector<int32_t> y3s3 = offs(S3, LY3), y3c = offs(C, LY3);
+      constexpr int K = kTripleMax;
+      for (int u3 = 0; u3 < c.ns3; ++u3) {
+        for (int u2 = 0; u2 < c.ns2; ++u2) {
+          for (int u1 = 0; u1 < c.ns; ++u1) {
+            c.sx[(K * u3 + u2) * K + u1] = xs3[u3] + xs2[u2] + xs1[u1];
+            c.sy[(K * u3 + u2) * K + u1] = ys3[u3] + ys2[u2] + ys1[u1];
+          }
+          c.cy[K * u3 + u2] = y2s3[u3] + y2s2[u2];
+        }
+        for (int w = 0; w < c.nc; ++w) c.cz[K * w + u3] = y3c[w] + y3s3[u3];
+      }
     }
     for (int w = 0; w < c.nc; ++w) c.cz[kPairZ + w] = zc[w];
-    f.flops = a.flops + b.flops;
-    f.bytes = 4.0 * (double)(p->T[a.X].size + p->T[a.Y].size + p->T[b.Y].size + p->T[b.Z].size);
+    // X's entries of a lane adjacent and 16-byte aligned (every step sums two
+    // assignments, the summed labels X's fastest ones in step order):
+    // vector loads
+    {
+      const int box = three ? c.ns * c.ns2 * c.ns3 : c.ns * c.ns2;
+      bool adj = c.ns == 2 && c.ns2 == 2 && (!three || c.ns3 == 2);
+      for (int u = 0; adj && u < box; ++u) {
+        const int k = three ? u : kPairMax * (u / 2) + u % 2;
+        adj = c.sx[k] == c.sx[0] + u;
+      }
+      if (adj && c.sx[0] % 4 == 0)
+        for (int v : R)
+          if (stride_in(LX, v, card) % 4 != 0) adj = false;
+      c.row_vx = adj ? 1 : 0;
+    }
+    f.flops = 0;
+    f.bytes = 4.0 * (double)(p->T[a.X].size + p->T[a.Y].size + p->T[b.Y].size + p->T[last.Z].size);
+    for (int q : ch) f.flops += t.ops[q].flops;
+    if (three) f.bytes += 4.0 * (double)p->T[last.Y].size;
     t.fops.push_back(f);
     t.fused = true;
   }
   if (!t.fused) {
     t.fops.clear();
-    t.pair_first.clear();
+    t.chain_prev.clear();
+    t.chain_inner.clear();
   }
 }
 
@@ -714,17 +785,16 @@ static void build_backtrack(tn_plan_t *p, TreeExec &t) {
   t.back.clear();
   t.back_meta.clear();
   // a step reads the op's argmax at its output's assignment and assigns its
-  // eliminated variables; the second contraction of a max-plus pair assigns
-  // the first's too (its index runs over both, the second's fastest), and
-  // the first has no step of its own
+  // eliminated variables; the last contraction of a max-plus chain run in
+  // one pass assigns every step's (its index runs over all of them, the
+  // last step's fastest), and the earlier ones have no step of their own
   auto eliminated = [&](const Op &op) {
     Labels U = p->T[op.X].lab;
     if (op.Y >= 0) U = unite(U, p->T[op.Y].lab);
     return minus(U, p->T[op.Z].lab);
   };
   auto add_step = [&](int id) {
-    const int first = t.pair_first.empty() ? -1 : t.pair_first[id];
-    if (first == -2) return;
+    if (!t.chain_inner.empty() && t.chain_inner[id]) return;
     const Op &op = t.ops[id];
     BackStep s{};
     s.arg = op.I;  // IntBuf id; converted to an offset at allocation
@@ -736,10 +806,13 @@ static void build_backtrack(tn_plan_t *p, TreeExec &t) {
     }
     s.in_end = (int32_t)(t.back_meta.size() / 2);
     s.out_begin = s.in_end;
+    std::vector<int> chain{id};  // the chain ending at this op, first contraction first
+    while (!t.chain_prev.empty() && t.chain_prev[chain.front()] >= 0) chain.insert(chain.begin(), t.chain_prev[chain.front()]);
     Labels out;
-    if (first >= 0) out = eliminated(t.ops[first]);
-    const Labels own = eliminated(op);
-    out.insert(out.end(), own.begin(), own.end());
+    for (int q : chain) {
+      const Labels e = eliminated(t.ops[q]);
+      out.insert(out.end(), e.begin(), e.end());
+    }
     for (int v : out) {
       t.back_meta.push_back(v);
       t.back_meta.push_back(p->card[v]);
@@ -945,6 +1018,7 @@ static void fill_args(tn_plan_t *p, Op &op) {
   strides(Z, a.bsZ, a.esZ);
   a.I = op.I >= 0 ? p->iarena + p->IB[op.I].off : nullptr;
   if (op.Y2 >= 0) a.Y2 = p->arena + p->T[op.Y2].off;
+  if (op.Y3 >= 0) a.Y3 = p->arena + p->T[op.Y3].off;
   a.mx = p->mx;
   a.ex = p->ex;
   a.mx_stride = std::max(1, p->n_slots);

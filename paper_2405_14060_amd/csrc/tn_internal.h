@@ -183,11 +183,17 @@ struct ContractArgs {
   // second step (ns2 <= 4) and s1 of the first (ns <= 4), k = 4 s2 + s1:
   // sx[k], sy[k] offsets in X and Y; per column c (nc <= 4) cy[4 c + s2]
   // in Y2 and cz[kPairZ + c] in Z.
-  const float *Y2 = nullptr;
-  int32_t ns2 = 0;
+  // steps = 3 (three contractions, each summing <= 2 assignments, <= 2
+  // columns): Z1 = X (x) Y, Z2 = Z1 (x) Y2, Z = Z2 (x) Y3; a lane takes r of
+  // R3 = Z's labels held by Z2; rX, rY, gbY, gmX, rZ: its offsets in X, Y,
+  // Y2, Y3, Z; k = 4 s3 + 2 s2 + s1: sx[k], sy[k]; cy[2 s3 + s2] in Y2;
+  // cz[2 c + s3] in Y3, cz[kPairZ + c] in Z; I gets (s1 ns2 + s2) ns3 + s3.
+  const float *Y2 = nullptr, *Y3 = nullptr;
+  int32_t ns2 = 0, ns3 = 0, steps = 2;
 };
 static constexpr int kKindMaxPair = 7;
 static constexpr int kPairMax = 4;    // summed assignments of either step, columns of the second
+static constexpr int kTripleMax = 2;  // the same for each step of a three-step chain
 static constexpr int kPairZ = 16;     // cz[kPairZ + c]: Z offsets of the second step's columns
 static constexpr int kGemmTile = 64;  // output tile edge of the dense form
 static constexpr int kInterTile = 4;  // output tile edge (rows x columns) of the interleaved form

@@ -868,7 +868,120 @@ __device__ __forceinline__ void rowsb_body(const ContractArgs &a, const int b, c
 // per candidate and the first maximiser in canonical order wins, exactly as
 // in the other max-plus forms.
 // --------------------------------------------------------------------------
+// three steps, each summing at most two assignments (steps = 3)
+__device__ __forceinline__ void mtriple_body(const ContractArgs &a, const uint32_t blk, const uint32_t nblk) {
+  gcfloat *__restrict__ X = (gcfloat *)a.X;
+  gcfloat *__restrict__ Y1 = (gcfloat *)a.Y;
+  gcfloat *__restrict__ Y2 = (gcfloat *)a.Y2;
+  gcfloat *__restrict__ Y3 = (gcfloat *)a.Y3;
+  gfloat *__restrict__ Z = (gfloat *)a.Z;
+  gint_w *__restrict__ I = (gint_w *)a.I;
+  const int n1 = a.ns, n2 = a.ns2, n3 = a.ns3, nc = a.nc;
+  constexpr int K = kTripleMax;
+  int32_t sx[K * K * K], sy[K * K * K], y2[K * K], y3[K * K], zc[K];
+#pragma unroll
+  for (int k = 0; k < K * K * K; ++k) {
+    const bool in = k / (K * K) < n3 && (k / K) % K < n2 && k % K < n1;
+    sx[k] = in ? a.sx[k] : 0;
+    sy[k] = in ? a.sy[k] : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < K * K; ++k) {
+    y2[k] = (k / K < n3 && k % K < n2) ? a.cy[k] : 0;
+    y3[k] = (k / K < nc && k % K < n3) ? a.cz[k] : 0;
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) zc[k] = k < nc ? a.cz[kPairZ + k] : 0;
+  const uint32_t nR = a.nR, nRl = a.nRl;
+  const int rls = a.rl_shift;
+  for (uint32_t r = blk * kBlock + threadIdx.x; r < nR; r += nblk * kBlock) {
+    uint32_t rh, rl;
+    if (rls >= 0) {
+      rh = r >> rls;
+      rl = r & (nRl - 1);
+    } else {
+      rh = r / nRl;
+      rl = r - rh * nRl;
+    }
+    const int32_t xo = ((gint *)a.rX.hi)[rh] + ((gint *)a.rX.lo)[rl];
+    const int32_t y1o = ((gint *)a.rY.hi)[rh] + ((gint *)a.rY.lo)[rl];
+    const int32_t y2o = ((gint *)a.gbY.hi)[rh] + ((gint *)a.gbY.lo)[rl];
+    const int32_t y3o = ((gint *)a.gmX.hi)[rh] + ((gint *)a.gmX.lo)[rl];
+    const int32_t zo = ((gint *)a.rZ.hi)[rh] + ((gint *)a.rZ.lo)[rl];
+    float xv[K * K * K];
+    if (a.row_vx) {  // the eight entries adjacent: two 16-byte loads
+      const f32x4 lo = *(gcf32x4 *)(X + xo + sx[0]), hi = *(gcf32x4 *)(X + xo + sx[0] + 4);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        xv[k] = lo[k] + Y1[y1o + sy[k]];
+        xv[k + 4] = hi[k] + Y1[y1o + sy[k + 4]];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < K * K * K; ++k)
+        if (k / (K * K) < n3 && (k / K) % K < n2 && k % K < n1) xv[k] = X[xo + sx[k]] + Y1[y1o + sy[k]];
+    }
+    // first step: outputs (r, s3, s2) and their first maximiser s1
+    float v1[K * K];
+    int32_t i1[K * K];
+#pragma unroll
+    for (int q = 0; q < K * K; ++q) {
+      v1[q] = -INFINITY;
+      i1[q] = 0;
+      if (q / K < n3 && q % K < n2) {
+#pragma unroll
+        for (int w = 0; w < K; ++w)
+          if (w < n1 && (w == 0 || xv[K * q + w] > v1[q])) {
+            v1[q] = xv[K * q + w];
+            i1[q] = w;
+          }
+      }
+    }
+    // second step: outputs (r, s3); the index over (s1, s2) of its choice
+    float v2[K];
+    int32_t i2[K];
+#pragma unroll
+    for (int u3 = 0; u3 < K; ++u3) {
+      v2[u3] = -INFINITY;
+      i2[u3] = 0;
+      if (u3 < n3) {
+#pragma unroll
+        for (int u2 = 0; u2 < K; ++u2)
+          if (u2 < n2) {
+            const float v = v1[K * u3 + u2] + Y2[y2o + y2[K * u3 + u2]];
+            if (u2 == 0 || v > v2[u3]) {
+              v2[u3] = v;
+              i2[u3] = i1[K * u3 + u2] * n2 + u2;
+            }
+          }
+      }
+    }
+    // third step: the outputs (r, c) and the index over (s1, s2, s3)
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+      if (c >= nc) break;
+      float best = -INFINITY;
+      int32_t bi = 0;
+#pragma unroll
+      for (int u3 = 0; u3 < K; ++u3)
+        if (u3 < n3) {
+          const float v = v2[u3] + Y3[y3o + y3[K * c + u3]];
+          if (u3 == 0 || v > best) {
+            best = v;
+            bi = i2[u3] * n3 + u3;
+          }
+        }
+      Z[zo + zc[c]] = best;
+      I[zo + zc[c]] = bi;
+    }
+  }
+}
+
 __device__ __forceinline__ void mpair_body(const ContractArgs &a, const uint32_t blk, const uint32_t nblk) {
+  if (a.steps == 3) {
+    mtriple_body(a, blk, nblk);
+    return;
+  }
   gcfloat *__restrict__ X = (gcfloat *)a.X;
   gcfloat *__restrict__ Y1 = (gcfloat *)a.Y;
   gcfloat *__restrict__ Y2 = (gcfloat *)a.Y2;
@@ -903,9 +1016,17 @@ __device__ __forceinline__ void mpair_body(const ContractArgs &a, const uint32_t
     const int32_t y2o = ((gint *)a.gbY.hi)[rh] + ((gint *)a.gbY.lo)[rl];
     float xv[K * K], v1[K];
     int32_t i1[K];
+    if (a.row_vx) {  // two steps of two summed assignments, the four entries adjacent: one 16-byte load
+      const f32x4 x4 = *(gcf32x4 *)(X + xo + sx[0]);
 #pragma unroll
-    for (int k = 0; k < K * K; ++k)
-      if ((k / K) < n2 && (k % K) < n1) xv[k] = X[xo + sx[k]] + Y1[y1o + sy[k]];
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int w = 0; w < 2; ++w) xv[K * u + w] = x4[2 * u + w] + Y1[y1o + sy[K * u + w]];
+    } else {
+#pragma unroll
+      for (int k = 0; k < K * K; ++k)
+        if ((k / K) < n2 && (k % K) < n1) xv[k] = X[xo + sx[k]] + Y1[y1o + sy[k]];
+    }
 #pragma unroll
     for (int u = 0; u < K; ++u) {
       if (u >= n2) break;

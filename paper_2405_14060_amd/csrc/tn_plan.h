@@ -51,7 +51,7 @@ struct Op {
   // written, for scheduling
   int seg = -1, seg_kind = 0;
   std::vector<int> ins, outs;
-  int Y2 = -1;                        // two max-plus contractions in one pass: the second's Y
+  int Y2 = -1, Y3 = -1;               // max-plus chain in one pass: the second's and third's Y
   int forms = 0;                      // eligible kernel forms: 1 generic, 2 row, 4 dense, 8 wave,
                                       // 16 interleaved, 256 dense with 128 x 128 tiles, 512 generic
                                       // in output order, 1024 batch-uniform row form
@@ -134,8 +134,10 @@ struct TreeExec {
   int root = -1;                      // tensor holding the result over `out`
   std::vector<Op> ops;
   std::vector<Op> fops;               // forward list with fused segments or max-plus pairs (when fused)
-  std::vector<int> pair_first;        // max-plus pairs: per op, the first contraction of the pair
-                                      // it ends (-1: none); the first's own entry is -2
+  std::vector<int> chain_prev;        // max-plus chains run in one pass: per op, the chain's
+                                      // previous contraction (-1: none)
+  std::vector<char> chain_inner;      // 1: a later contraction of its chain follows (the chain's
+                                      // last one holds the index of every step)
   bool fused = false;
   std::vector<std::vector<int>> node_ops;  // op indices per pair (reductions, then main)
   int root_op = -1;                   // op reducing the root to `out`, if any

@@ -525,14 +525,17 @@ def test_map_batched_indicators(T):
         assert np.float32(lp[b]) == np.float32(v32)
 
 
-@pytest.mark.parametrize("size", [16, 20])
-def test_map_paired_steps_bit_exact(T, size):
+@pytest.mark.parametrize("size,card", [(16, 2), (20, 2), (11, 3)])
+def test_map_paired_steps_bit_exact(T, size, card):
     """Grids whose chains of max-plus contractions over >= 2^16 outputs run
-    two consecutive contractions per pass (the first's values in registers,
-    both argmax arrays written): assignment and value bit-identical to the
-    oracle's FP32 emulation on the plan's tree and to the plan that runs
-    every contraction alone (eq. log-map, tropical contraction)."""
-    net = W.grid_mrf(size, size, 0)
+    two or three consecutive contractions per pass (binary grids: three, the
+    eight entries of X a lane reads adjacent; three states per variable:
+    two, each summing three assignments), the intermediate values in
+    registers and one index per output over every step's choice: assignment
+    and value bit-identical to the oracle's FP32 emulation on the plan's
+    tree and to the plan that runs every contraction alone (eq. log-map,
+    tropical contraction)."""
+    net = W.grid_mrf(size, size, 0, card=card)
     P = T.Plan(T.Network(net), semirings=T.MAX_PLUS)
     pairs, _ = P.tree()
     U = T.Plan(T.Network(net), semirings=T.MAX_PLUS, fuse=False, tree=pairs)
