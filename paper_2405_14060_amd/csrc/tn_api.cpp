@@ -592,8 +592,8 @@ static void build_forward(tn_plan_t *p, TreeExec &t, int semi) {
 // contractions alone), and the last step's index array holds, per output,
 // every step's choice as one index over (S1, S2[, S3]), the last fastest —
 // the readout takes the whole chain with one read, and the other index
-// arrays are not written.  Contractions of >= 2^16 outputs of one instance
-// only.  Fills t.fops (a chain sits at its last contraction's place, after
+// arrays are not written.  Contractions of >= 2^12 outputs of one instance
+// only (below, a separate launch class costs more than the pass saves).  Fills t.fops (a chain sits at its last contraction's place, after
 // every producer of its operands), t.chain_prev and t.chain_inner; t.fused
 // when a chain formed.
 static void build_max_pairs(tn_plan_t *p, TreeExec &t) {
@@ -649,7 +649,7 @@ static void build_max_pairs(tn_plan_t *p, TreeExec &t) {
       const Labels S3 = elim(c), C3 = minus(LZ3, LZ2), R3 = inter(LZ3, LZ2);
       if (minus(S2, LZ1).empty() && minus(S3, LZ2).empty() && numel(S1, card) <= kTripleMax &&
           numel(S2, card) <= kTripleMax && numel(S3, card) <= kTripleMax && numel(C3, card) <= kTripleMax &&
-          numel(LZ3, card) >= (1 << 16) && numel(R3, card) < (int64_t(1) << 31)) {
+          numel(LZ3, card) >= kChainMinOut && numel(R3, card) < (int64_t(1) << 31)) {
         used[i] = used[j] = used[k] = 1;
         chain_at[k] = {i, j, k};
         continue;
@@ -657,7 +657,7 @@ static void build_max_pairs(tn_plan_t *p, TreeExec &t) {
     }
     const Labels R2 = inter(LZ2, LZ1), C2 = minus(LZ2, LZ1);
     if (!minus(S2, LZ1).empty() || numel(S1, card) > kPairMax || numel(S2, card) > kPairMax ||
-        numel(C2, card) > kPairMax || numel(LZ2, card) < (1 << 16) || numel(R2, card) >= (int64_t(1) << 31))
+        numel(C2, card) > kPairMax || numel(LZ2, card) < kChainMinOut || numel(R2, card) >= (int64_t(1) << 31))
       continue;
     used[i] = used[j] = 1;
     chain_at[j] = {i, j};

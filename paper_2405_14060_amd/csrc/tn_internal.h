@@ -194,6 +194,7 @@ struct ContractArgs {
 static constexpr int kKindMaxPair = 7;
 static constexpr int kPairMax = 4;    // summed assignments of either step, columns of the second
 static constexpr int kTripleMax = 2;  // the same for each step of a three-step chain
+static constexpr int64_t kChainMinOut = 1 << 12;  // outputs of a chain's last step
 static constexpr int kPairZ = 16;     // cz[kPairZ + c]: Z offsets of the second step's columns
 static constexpr int kGemmTile = 64;  // output tile edge of the dense form
 static constexpr int kInterTile = 4;  // output tile edge (rows x columns) of the interleaved form

@@ -130,16 +130,16 @@ def test_row_batch_form_is_offered(T):
 
 
 def test_max_plus_pairs_on_host(T):
-    """The 20x20 grid's max-plus chain steps over >= 2^16 outputs run two
-    per pass: fewer launches than with every contraction alone; the plan's
-    contraction list (and so its tree) is unchanged."""
+    """The 20x20 grid's max-plus chain steps over >= 2^12 outputs run two or
+    three per pass: fewer launches than with every contraction alone; the
+    plan's contraction list (and so its tree) is unchanged."""
     net = W.grid_mrf(20, 20, 0)
     P = T.Plan(T.Network(net), semirings=T.MAX_PLUS, host_only=True)
     U = T.Plan(T.Network(net), semirings=T.MAX_PLUS, host_only=True, fuse=False)
     assert np.array_equal(P.tree()[0], U.tree()[0])
     assert len(P.ops(2)) == len(U.ops(2))
     assert P.info()["n_launches_max"] < 0.6 * U.info()["n_launches_max"]
-    small = W.grid_mrf(10, 10, 0)  # below 2^16 outputs: nothing paired
+    small = W.grid_mrf(10, 10, 0)  # below 2^12 outputs: nothing paired
     assert (T.Plan(T.Network(small), semirings=T.MAX_PLUS, host_only=True).info()["n_launches_max"] ==
             T.Plan(T.Network(small), semirings=T.MAX_PLUS, host_only=True, fuse=False).info()["n_launches_max"])
 

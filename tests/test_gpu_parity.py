@@ -527,7 +527,7 @@ def test_map_batched_indicators(T):
 
 @pytest.mark.parametrize("size,card", [(16, 2), (20, 2), (11, 3)])
 def test_map_paired_steps_bit_exact(T, size, card):
-    """Grids whose chains of max-plus contractions over >= 2^16 outputs run
+    """Grids whose chains of max-plus contractions over >= 2^12 outputs run
     two or three consecutive contractions per pass (binary grids: three, the
     eight entries of X a lane reads adjacent; three states per variable:
     two, each summing three assignments), the intermediate values in
