@@ -49,10 +49,10 @@ KIND_NAMES = {0: "contract_map_sum", 1: "contract_map_max", 2: "contract_split_s
 # the kernel source they were taken from (sha256 prefix of tn_kernels.hip):
 # {(kernel, workload): {"src": sha, "bytes": B}}
 MEASURED_TRAFFIC = {
-    ("seg_carrier_bwd", "grid20x20"): {"src": "835e4210f161c422", "bytes": 26371488},
-    ("contract_interleaved_sum", "bn500x512"): {"src": "835e4210f161c422", "bytes": 69932107},
-    ("contract_map_max", "grid20_map"): {"src": "835e4210f161c422", "bytes": 22761086},
-    ("contract_tropical_dense", "tropical_gemm"): {"src": "835e4210f161c422", "bytes": 115413983},
+    ("seg_carrier_bwd", "grid20x20"): {"src": "150ec6392dd99f0e", "bytes": 26376581},
+    ("contract_interleaved_sum", "bn500x512"): {"src": "150ec6392dd99f0e", "bytes": 69954919},
+    ("contract_map_max", "grid20_map"): {"src": "150ec6392dd99f0e", "bytes": 20525199},
+    ("contract_tropical_dense", "tropical_gemm"): {"src": "150ec6392dd99f0e", "bytes": 115414630},
 }
 
 def kernel_src_sha():
