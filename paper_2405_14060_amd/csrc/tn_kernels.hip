@@ -3507,23 +3507,32 @@ __host__ __device__ __forceinline__ double uniform53(uint64_t sample, uint32_t n
 }
 
 // meta quadruples (var, card, strideA, strideB)
-__device__ __forceinline__ void decode_offsets(int64_t k, const int32_t *q, int qb, int qe,
+// k < the labels' assignment count, below 2^31 (a tensor's entries): 32-bit
+// division
+__device__ __forceinline__ void decode_offsets(int64_t k64, const int32_t *q, int qb, int qe,
                                                int64_t &oa, int64_t &ob) {
+  uint32_t k = (uint32_t)k64;
   oa = 0;
   ob = 0;
   for (int j = qe - 1; j >= qb; --j) {
-    const int c = q[4 * j + 1];
-    const int64_t d = k % c;
-    k /= c;
-    oa += d * q[4 * j + 2];
-    ob += d * q[4 * j + 3];
+    const uint32_t c = (uint32_t)q[4 * j + 1];
+    const uint32_t h = k / c, d = k - h * c;
+    k = h;
+    oa += (int64_t)d * q[4 * j + 2];
+    ob += (int64_t)d * q[4 * j + 3];
   }
 }
-__device__ __forceinline__ void decode_assign(int64_t k, const int32_t *q, int qb, int qe, int32_t *x) {
+// assigns the labels' values of index k into the row x; `write`: whether
+// this lane writes (one lane for a row in LDS, every lane for a row in
+// global memory, whose lanes read back only their own writes)
+__device__ __forceinline__ void decode_assign(int64_t k64, const int32_t *q, int qb, int qe, int32_t *x,
+                                              bool write = true) {
+  uint32_t k = (uint32_t)k64;
   for (int j = qe - 1; j >= qb; --j) {
-    const int c = q[4 * j + 1];
-    x[q[4 * j]] = (int32_t)(k % c);
-    k /= c;
+    const uint32_t c = (uint32_t)q[4 * j + 1];
+    const uint32_t h = k / c;
+    if (write) x[q[4 * j]] = (int32_t)(k - h * c);
+    k = h;
   }
 }
 __device__ __forceinline__ int64_t count_of(const int32_t *q, int qb, int qe) {
@@ -3591,16 +3600,30 @@ __device__ __forceinline__ int64_t wave_draw(int64_t n, double u, W weight) {
   return pick;
 }
 
+// Rows of up to kSampleLdsVars variables are built in LDS (one row per
+// wavefront, written by lane 0: LDS instructions of a wavefront complete in
+// order, so every lane's later read sees them) and copied out at the end;
+// longer rows are built in place in global memory, every lane writing every
+// value (each lane then reads back only its own writes).
+static constexpr int kSampleLdsVars = 2048;
+
+template <bool LDS>
 __global__ void k_sample(const float *arena, const SampleStep *steps, int n_steps, const int32_t *q,
                          int n_vars, int64_t n, uint64_t seed, const int32_t *init, const int64_t *ids,
                          int32_t *out) {
+  __shared__ int32_t rows[LDS ? 4 * kSampleLdsVars : 1];
   const int64_t j = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  if (j >= n) return;  // whole waves
+  if (j >= n) return;  // whole waves (no workgroup barrier below)
+  const int lane = threadIdx.x & 63;
   const int64_t s = ids ? ids[j] : j;
-  int32_t *x = out + s * n_vars;
-  // every lane writes the whole row with the same values, so each lane only
-  // ever reads back its own writes
-  for (int v = 0; v < n_vars; ++v) x[v] = init[v];
+  int32_t *x = LDS ? rows + (threadIdx.x >> 6) * kSampleLdsVars : out + s * n_vars;
+  const bool w = !LDS || lane == 0;  // lanes that write the row
+  if (LDS) {
+    for (int v = lane; v < n_vars; v += 64) x[v] = init[v];
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    for (int v = 0; v < n_vars; ++v) x[v] = init[v];
+  }
   for (int t = 0; t < n_steps; ++t) {
     const SampleStep st = steps[t];
     const float *A = arena + st.A;
@@ -3633,7 +3656,8 @@ __global__ void k_sample(const float *arena, const SampleStep *steps, int n_step
       });
       int64_t ka, kb;
       decode_offsets(pick, q, st.k_b, st.k_e, ka, kb);
-      decode_assign(pick, q, st.k_b, st.k_e, x);  // every lane writes the same values
+      decode_assign(pick, q, st.k_b, st.k_e, x, w);
+      if (LDS) __builtin_amdgcn_wave_barrier();
       oa += ka;
       ob += kb;
     }
@@ -3649,8 +3673,13 @@ __global__ void k_sample(const float *arena, const SampleStep *steps, int n_step
         decode_offsets(p, q, pb, pe, da, db);
         return (double)T[base + (side ? db : da)];
       });
-      decode_assign(pick, q, pb, pe, x);
+      decode_assign(pick, q, pb, pe, x, w);
+      if (LDS) __builtin_amdgcn_wave_barrier();
     }
+  }
+  if (LDS) {
+    int32_t *o = out + s * n_vars;
+    for (int v = lane; v < n_vars; v += 64) o[v] = x[v];
   }
 }
 
@@ -3659,8 +3688,12 @@ void launch_sample(const float *arena, const SampleStep *steps, int n_steps, con
                    int32_t *out, void *stream) {
   if (n <= 0) return;
   const int64_t blocks = (n + 3) / 4;  // four samples (waves) per workgroup
-  k_sample<<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>(arena, steps, n_steps, meta, n_vars, n,
-                                                             seed, init, ids, out);
+  if (n_vars <= kSampleLdsVars)
+    k_sample<true><<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>(arena, steps, n_steps, meta, n_vars, n,
+                                                                     seed, init, ids, out);
+  else
+    k_sample<false><<<(unsigned)blocks, 256, 0, (hipStream_t)stream>>>(arena, steps, n_steps, meta, n_vars, n,
+                                                                      seed, init, ids, out);
 }
 
 // --------------------------------------------------------------------------
