@@ -372,6 +372,7 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
           a.nBlo *= (uint32_t)card[*it];
         a.x_s_fast = (!LX.empty() && has(S, LX.back())) ? 1 : 0;
         a.y_n_fast = (!LY.empty() && has(C, LY.back())) ? 1 : 0;
+        a.s_pair = a.x_s_fast && has(S, LY.back()) && card[LX.back()] == 2 && a.nS % 2 == 0 ? 1 : 0;
         a.z_n_fast = (!LZ.empty() && has(C, LZ.back())) ? 1 : 0;
       }
     }

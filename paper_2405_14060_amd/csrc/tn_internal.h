@@ -161,6 +161,8 @@ struct ContractArgs {
   int32_t x_s_fast = 0;     // X's stride-1 label is summed (else an M or batch label)
   int32_t y_n_fast = 0;     // Y's stride-1 label is a column label
   int32_t z_n_fast = 0;     // Z's stride-1 label is a column label
+  int32_t s_pair = 0;       // X's and Y's stride-1 label is a summed label of two values (and
+                            // the summed set even): the summed entries come in adjacent pairs
   int32_t prec = 0;         // matrix-core operands: 0 FP32, 1 BF16, 2 FP16 (FP32 accumulation)
   // interleaved form (kind 4): element e of instance b of a batched tensor
   // sits at e * es + b (es = instances held); a shared operand has es = 1

@@ -1450,9 +1450,13 @@ __device__ __forceinline__ float ld_row(__amdgpu_buffer_rsrc_t r, int lane_off, 
   return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, lane_off, row_off, 0));
 }
 
-template <bool XS, bool YN, bool ST>
+// P2 (X and Y summed-fast, their stride-1 summed label of two values):
+// each thread reads an adjacent pair of summed entries with one 8-byte load
+// (row or column (t >> 3) + 32 q, summed entries 2 (t % 8) and the next)
+template <bool XS, bool YN, bool ST, bool P2 = false>
 __device__ __forceinline__ void gemm_big_body(const ContractArgs &a, const int b, const uint32_t blk,
                                               const uint32_t nblk) {
+  static_assert(!P2 || (XS && !YN && ST), "pair loads: both operands summed-fast, offsets staged");
   __shared__ int32_t oMX[kBT], oMZ[kBT], oNY[kBT], oNZ[kBT];
   __shared__ int32_t sOX[ST ? kBSOff : 1], sOY[ST ? kBSOff : 1];
   __shared__ __align__(16) float AB[2 * kBBuf];
@@ -1499,25 +1503,27 @@ __device__ __forceinline__ void gemm_big_body(const ContractArgs &a, const int b
   // Row (column) byte offsets are fixed per thread; rows past the operand
   // read its entry 0 and are masked at the LDS store.
   constexpr int NQ = kBT * kBK / kBlock;
-  const int kA0 = XS ? (t & 15) : (t >> 7), kB0 = YN ? (t >> 7) : (t & 15);
-  auto rowA = [&](int q) { return XS ? (t >> 4) + 16 * q : (t & 127); };
+  constexpr int NL = P2 ? NQ / 2 : NQ;  // loads per operand and chunk
+  const int kA0 = XS ? (P2 ? 2 * (t & 7) : (t & 15)) : (t >> 7);
+  const int kB0 = YN ? (t >> 7) : (P2 ? 2 * (t & 7) : (t & 15));
+  auto rowA = [&](int q) { return XS ? (P2 ? (t >> 3) + 32 * q : (t >> 4) + 16 * q) : (t & 127); };
   auto sumA = [&](int q) { return XS ? kA0 : kA0 + 2 * q; };
-  auto colB = [&](int q) { return YN ? (t & 127) : (t >> 4) + 16 * q; };
+  auto colB = [&](int q) { return YN ? (t & 127) : (P2 ? (t >> 3) + 32 * q : (t >> 4) + 16 * q); };
   auto sumB = [&](int q) { return YN ? kB0 + 2 * q : kB0; };
-  int32_t oa[XS ? NQ : 1], ob[YN ? 1 : NQ];
+  int32_t oa[XS ? NL : 1], ob[YN ? 1 : NL];
   uint32_t live = 0;  // bit q: A entry q's row exists; bit NQ + q: B entry q's column
 #pragma unroll
-  for (int q = 0; q < (XS ? NQ : 1); ++q) {
+  for (int q = 0; q < (XS ? NL : 1); ++q) {
     const int32_t o = oMX[rowA(q)];
     oa[q] = o >= 0 ? o * 4 : 0;
   }
 #pragma unroll
-  for (int q = 0; q < (YN ? 1 : NQ); ++q) {
+  for (int q = 0; q < (YN ? 1 : NL); ++q) {
     const int32_t o = oNY[colB(q)];
     ob[q] = o >= 0 ? o * 4 : 0;
   }
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) {
+  for (int q = 0; q < NL; ++q) {
     live |= (oMX[rowA(q)] >= 0 ? 1u : 0u) << q;
     live |= (oNY[colB(q)] >= 0 ? 1u : 0u) << (q + NQ);
   }
@@ -1529,6 +1535,18 @@ __device__ __forceinline__ void gemm_big_body(const ContractArgs &a, const int b
   auto load_chunk = [&](uint32_t s0, float (&ra)[NQ], float (&rb)[NQ]) {
     const uint32_t sa = s0 + kA0, sb = s0 + kB0;
     const int32_t oxc = XS ? sx_off(sa < nS ? sa : 0u) : 0, oyc = YN ? 0 : sy_off(sb < nS ? sb : 0u);
+    if (P2) {  // entries 2q, 2q + 1: an adjacent pair
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        const auto va = __builtin_amdgcn_raw_buffer_load_b64(rX, oa[q] + oxc, 0, 0);
+        const auto vb = __builtin_amdgcn_raw_buffer_load_b64(rY, ob[q] + oyc, 0, 0);
+        ra[2 * q] = __uint_as_float(va[0]);
+        ra[2 * q + 1] = __uint_as_float(va[1]);
+        rb[2 * q] = __uint_as_float(vb[0]);
+        rb[2 * q + 1] = __uint_as_float(vb[1]);
+      }
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const uint32_t s = s0 + sumA(q), s2 = s0 + sumB(q);
@@ -1540,13 +1558,23 @@ __device__ __forceinline__ void gemm_big_body(const ContractArgs &a, const int b
   };
   f32x4 acc[4][4] = {};
   const int wm = w & 1, wn = w >> 1, g = l >> 4, li = l & 15;
-  const bool full_rows = live == (1u << (2 * NQ)) - 1u;
+  const bool full_rows = P2 || live == (1u << (2 * NQ)) - 1u;
   // chunk c: its raw values (loaded two chunks ahead, register set c % 2)
   // go to LDS buffer c % 2, then the loads of chunk c + 2 are issued, then
   // the products of chunk c run
   auto step = [&](uint32_t s0, uint32_t c, float (&ra)[NQ], float (&rb)[NQ]) {
     float *As = AB + (c & 1u) * kBBuf, *Bs = As + kBT * kBKP;
-    if (full_rows && s0 + kBK <= nS) {
+    if (P2) {
+      const bool in = s0 + kA0 < nS;  // the pair (nS even)
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        const bool va = (live >> q & 1u) && in, vb = (live >> (q + NQ) & 1u) && in;
+        As[rowA(q) * kBKP + kA0] = va ? ra[2 * q] * sx : 0.f;
+        As[rowA(q) * kBKP + kA0 + 1] = va ? ra[2 * q + 1] * sx : 0.f;
+        Bs[colB(q) * kBKP + kB0] = vb ? rb[2 * q] * sy : 0.f;
+        Bs[colB(q) * kBKP + kB0 + 1] = vb ? rb[2 * q + 1] * sy : 0.f;
+      }
+    } else if (full_rows && s0 + kBK <= nS) {
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         As[rowA(q) * kBKP + sumA(q)] = ra[q] * sx;
@@ -1618,9 +1646,9 @@ __device__ __forceinline__ void gemm_big_body(const ContractArgs &a, const int b
 }
 
 // three workgroups per CU (LDS holds three; registers capped to match)
-template <bool XS, bool YN, bool ST>
+template <bool XS, bool YN, bool ST, bool P2 = false>
 __global__ __launch_bounds__(kBlock, 3) void k_gemm_big(const ContractArgs *__restrict__ ap) {
-  gemm_big_body<XS, YN, ST>(*ap, blockIdx.y, blockIdx.x, gridDim.x);
+  gemm_big_body<XS, YN, ST, P2>(*ap, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
 // --------------------------------------------------------------------------
@@ -2082,7 +2110,8 @@ void launch_contract(int semi, bool has_y, bool split, const ContractArgs &a, co
       if (st) k_gemm_big<true, true, true><<<g, kBlock, 0, s>>>(d_a);
       else k_gemm_big<true, true, false><<<g, kBlock, 0, s>>>(d_a);
     } else if (a.x_s_fast) {
-      if (st) k_gemm_big<true, false, true><<<g, kBlock, 0, s>>>(d_a);
+      if (st && a.s_pair) k_gemm_big<true, false, true, true><<<g, kBlock, 0, s>>>(d_a);
+      else if (st) k_gemm_big<true, false, true><<<g, kBlock, 0, s>>>(d_a);
       else k_gemm_big<true, false, false><<<g, kBlock, 0, s>>>(d_a);
     } else if (a.y_n_fast) {
       if (st) k_gemm_big<false, true, true><<<g, kBlock, 0, s>>>(d_a);

@@ -236,6 +236,40 @@ def gemm_net(n_s, order, seed):
     return W.Network(card=card.astype(np.int32), scopes=scopes, values=vals, is_log=True)
 
 
+def pair_gemm_net(seed):
+    """Three binary-variable factors X(B, M, S), Y(B, S, N), Z(B, M, N) with
+    256-wide row, column and summed sets, whose largest variable id is a
+    summed one and whose next is a batch one: in X and Y the summed entries
+    come in adjacent pairs separated by the batch label (the layout of the
+    220-variable MMAP slice's large product)."""
+    rng = np.random.default_rng(seed)
+    n = 2 + 8 + 8 + 8
+    rest = rng.permutation(n - 2)  # ids 0 .. n - 3 for the other variables
+    B = np.array([n - 2, rest[0]])
+    M, S, N = rest[1:9], np.concatenate([[n - 1], rest[9:16]]), rest[16:24]
+    card = np.full(n, 2, np.int32)
+    scopes = [np.sort(np.concatenate(g)).astype(np.int32) for g in ((B, M, S), (B, S, N), (B, M, N))]
+    vals = [rng.normal(0.0, 0.3, 1 << len(sc)) for sc in scopes]
+    return W.Network(card=card, scopes=scopes, values=vals, is_log=True)
+
+
+def test_large_dense_tiles_summed_pairs_against_oracle(T):
+    """Large-tile dense contractions whose operands hold their summed
+    entries in adjacent pairs (read two at a time): log Z and all marginals
+    against the oracle, rules' and autotuned plans."""
+    net = pair_gemm_net(3)
+    for autotune in (False, True):
+        P = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, autotune=autotune)
+        if not autotune:
+            assert P.info()["n_dense_large"] > 0
+        lz, m = P.marginals()
+        pairs, _ = P.tree()
+        lzo, marg, *_ = oracle.marginals(net, pairs=pairs.astype(np.int64))
+        assert rel(lz[0], lzo) <= 1e-5
+        got = P.split_marginals(m[0])
+        assert max(np.abs(a - b).max() for a, b in zip(got, marg)) <= 1e-5
+
+
 def two_gemm_nets(seed):
     """Two disconnected three-factor networks of the same shape, one with
     243-wide row, column and summed sets (128 x 128 dense tiles), one with
