@@ -49,10 +49,10 @@ KIND_NAMES = {0: "contract_map_sum", 1: "contract_map_max", 2: "contract_split_s
 # the kernel source they were taken from (sha256 prefix of tn_kernels.hip):
 # {(kernel, workload): {"src": sha, "bytes": B}}
 MEASURED_TRAFFIC = {
-    ("seg_carrier_bwd", "grid20x20"): {"src": "150ec6392dd99f0e", "bytes": 26376581},
-    ("contract_interleaved_sum", "bn500x512"): {"src": "150ec6392dd99f0e", "bytes": 69954919},
-    ("contract_map_max", "grid20_map"): {"src": "150ec6392dd99f0e", "bytes": 20525199},
-    ("contract_tropical_dense", "tropical_gemm"): {"src": "150ec6392dd99f0e", "bytes": 115414630},
+    ("seg_carrier_bwd", "grid20x20"): {"src": "cbf1a4029bd0751e", "bytes": 26372266},
+    ("contract_interleaved_sum", "bn500x512"): {"src": "cbf1a4029bd0751e", "bytes": 69942002},
+    ("contract_map_max", "grid20_map"): {"src": "cbf1a4029bd0751e", "bytes": 20525245},
+    ("contract_tropical_dense", "tropical_gemm"): {"src": "cbf1a4029bd0751e", "bytes": 115401811},
 }
 
 def kernel_src_sha():
