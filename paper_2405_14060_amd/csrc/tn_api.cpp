@@ -402,16 +402,16 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
       // runs of four adjacent, 16-byte aligned entries (every other offset
       // of the operand a multiple of 4): vector loads of X's row and stores
       // of Z's row in the batch-uniform row form
-      auto runs4 = [&](const int32_t *o, int64_t n, const Labels &L, const Labels &TL) {
-        if (n % 4 != 0 || n > kRowMax) return false;
+      auto runs = [&](const int32_t *o, int64_t n, const Labels &L, const Labels &TL, int r) {
+        if (n % r != 0 || n > kRowMax) return false;
         for (int64_t i = 0; i < n; ++i)
-          if (o[i] != o[i - i % 4] + i % 4 || o[i - i % 4] % 4 != 0) return false;
+          if (o[i] != o[i - i % r] + i % r || o[i - i % r] % r != 0) return false;
         for (int v : minus(TL, L))
-          if (stride_in(TL, v, card) % 4 != 0) return false;
+          if (stride_in(TL, v, card) % r != 0) return false;
         return true;
       };
-      a.row_vx = (op.forms & 1024) && runs4(a.sx, a.nS, S, LX) ? 1 : 0;
-      a.row_vz = (op.forms & 1024) && runs4(a.cz, a.nC, C, LZ) ? 1 : 0;
+      a.row_vx = !(op.forms & 1024) ? 0 : runs(a.sx, a.nS, S, LX, 4) ? 1 : runs(a.sx, a.nS, S, LX, 2) ? 2 : 0;
+      a.row_vz = (op.forms & 1024) && runs(a.cz, a.nC, C, LZ, 4) ? 1 : 0;
       if ((a.nRl & (a.nRl - 1)) == 0) {
         int sh = 0;
         while ((1u << sh) < a.nRl) ++sh;

@@ -146,6 +146,7 @@ struct ContractArgs {
   int32_t ns = 0, nc = 0;
   int32_t rl_shift = -1;  // log2(nRl) when nRl is a power of two
   int32_t row_vx = 0;     // tile 1: summed entries 4k..4k+3 adjacent in X, 16-byte aligned
+                          // (2: entries 2k, 2k+1 adjacent, 8-byte aligned)
   int32_t row_vz = 0;     // tile 1: columns 4k..4k+3 adjacent in Z, 16-byte aligned
   int32_t sx[kRowMax], sy[kRowMax], cy[kRowMax], cz[kRowMax];
   // dense form (kind 2, sum-product): the rows split into batch labels

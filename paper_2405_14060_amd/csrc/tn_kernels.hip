@@ -48,6 +48,8 @@ typedef __attribute__((address_space(1))) float gfloat;
 typedef __attribute__((address_space(1))) int32_t gint_w;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const f32x4 gcf32x4;
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const f32x2 gcf32x2;
 typedef __attribute__((address_space(1))) f32x4 gf32x4;
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
@@ -803,7 +805,7 @@ __device__ __forceinline__ void rowsb_body(const ContractArgs &a, const int b, c
     float xv[BS];
 #pragma unroll
     for (int h = 0; h < 2; ++h) yw[lane + 64 * h] = yok[h] ? Y[yg + yoff[h]] * fy : 0.f;
-    if (BS >= 4 && a.row_vx) {  // summed entries in aligned runs of four
+    if (BS >= 4 && a.row_vx == 1) {  // summed entries in aligned runs of four
 #pragma unroll
       for (int k = 0; k < BS; k += 4)
         if (k < ns) {
@@ -814,6 +816,16 @@ __device__ __forceinline__ void rowsb_body(const ContractArgs &a, const int b, c
           xv[k + 3] = v[3] * fx;
         } else {
           xv[k] = xv[k + 1] = xv[k + 2] = xv[k + 3] = 0.f;
+        }
+    } else if (BS >= 2 && a.row_vx == 2) {  // in aligned pairs
+#pragma unroll
+      for (int k = 0; k < BS; k += 2)
+        if (k < ns) {
+          const f32x2 v = *(gcf32x2 *)(X + xo + sx[k]);
+          xv[k] = v[0] * fx;
+          xv[k + 1] = v[1] * fx;
+        } else {
+          xv[k] = xv[k + 1] = 0.f;
         }
     } else {
 #pragma unroll
