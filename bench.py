@@ -49,10 +49,10 @@ KIND_NAMES = {0: "contract_map_sum", 1: "contract_map_max", 2: "contract_split_s
 # the kernel source they were taken from (sha256 prefix of tn_kernels.hip):
 # {(kernel, workload): {"src": sha, "bytes": B}}
 MEASURED_TRAFFIC = {
-    ("seg_carrier_bwd", "grid20x20"): {"src": "cbf1a4029bd0751e", "bytes": 26372266},
-    ("contract_interleaved_sum", "bn500x512"): {"src": "cbf1a4029bd0751e", "bytes": 69942002},
-    ("contract_map_max", "grid20_map"): {"src": "cbf1a4029bd0751e", "bytes": 20525245},
-    ("contract_tropical_dense", "tropical_gemm"): {"src": "cbf1a4029bd0751e", "bytes": 115401811},
+    ("seg_carrier_bwd", "grid20x20"): {"src": "d21f25f9c24835be", "bytes": 26372963},
+    ("contract_interleaved_sum", "bn500x512"): {"src": "d21f25f9c24835be", "bytes": 69943273},
+    ("contract_map_max", "grid20_map"): {"src": "d21f25f9c24835be", "bytes": 20524760},
+    ("contract_tropical_dense", "tropical_gemm"): {"src": "d21f25f9c24835be", "bytes": 115420200},
 }
 
 def kernel_src_sha():
