@@ -111,6 +111,19 @@ def timed(fn, steps, warmup, sync):
     return (time.perf_counter() - t0) / steps, out
 
 
+def step_stats(fn, np, reps=50):
+    """Wall times of `reps` further calls, each timed alone: the calls return
+    their results in host memory, so one call is one whole solve end to end
+    (launch, kernels, copies back).  Median and 10th / 90th percentiles in ms."""
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    p10, med, p90 = np.percentile(np.array(ts) * 1e3, [10, 50, 90])
+    return dict(reps=reps, p10=round(float(p10), 4), median=round(float(med), 4), p90=round(float(p90), 4))
+
+
 def bench_grid20(args, T, W, np, sync):
     net = W.grid_mrf(20, 20, 0)
     dt = dict(f32=T.TN_F32, bf16=T.TN_BF16, f16=T.TN_F16)[args.dtype]
@@ -125,7 +138,8 @@ def bench_grid20(args, T, W, np, sync):
                            tree_sc_log2=info["sc"], tree_tc_log2=round(info["tc"], 3),
                            segments=info["n_segments"], launches_per_solve=info["n_launches_fwd"] +
                            info["n_launches_bwd"] + 3, graph=not args.no_graph, autotune=args.autotune),
-               tflops=round(flops / sec / 1e12, 4), log_z=float(lz[0]), roofline=roof, kernels=kernels)
+               tflops=round(flops / sec / 1e12, 4), log_z=float(lz[0]), roofline=roof, kernels=kernels,
+               step_ms=step_stats(plan.marginals, np))
     if not args.no_cpu_baseline:
         import oracle
         lv = oracle.build_leaves(net)
@@ -157,6 +171,7 @@ def bench_bn500x512(args, T, W, np, sync):
     sec, (lz, m) = timed(lambda: plan.marginals(ev, batch=B), args.steps, args.warmup,
                          lambda: (plan.sync(), sync()))
     roof, kernels, flops = roofline(plan, 1, "bn500x512", evidence=ev, batch=B)
+    steps = step_stats(lambda: plan.marginals(ev, batch=B), np)
     # the plain FP32 per-instance form: one instance per call, no batching
     one = T.Plan(T.Network(net), semirings=T.SUM_PRODUCT, evidence_mode=T.EVIDENCE_INDICATOR, max_batch=1,
                  use_graph=not args.no_graph)
@@ -180,7 +195,7 @@ def bench_bn500x512(args, T, W, np, sync):
                            wave_nodes=info["n_wave"], interleaved_nodes=info["n_interleaved"],
                            batch_layout="interleaved" if info["batch_stride"] else "instance_major",
                            graph=not args.no_graph, autotune=args.autotune),
-               tflops=round(flops / sec / 1e12, 4), roofline=roof, kernels=kernels,
+               tflops=round(flops / sec / 1e12, 4), roofline=roof, kernels=kernels, step_ms=steps,
                per_instance_fp32=dict(value=round(n1 / sec1, 2), unit="instance-solves/s",
                                       max_log_z_diff_vs_batched=float(np.abs(lz1 - lz[:4]).max())))
     if lp_plan is not None:
@@ -333,6 +348,7 @@ def bench_tropical_gemm(args, T, W, np, sync):
     plan = T.Plan(T.Network(net), semirings=T.MAX_PLUS, use_graph=not args.no_graph)
     info = plan.info()
     sec, (lp, x) = timed(lambda: plan.map(), args.steps, args.warmup, lambda: (plan.sync(), sync()))
+    steps = step_stats(plan.map, np)
     prof = plan.profile(2, reps=3)
     kind_of = {v: k for k, v in KIND_NAMES.items()}
     avg_ms, fl_launch, by_launch, n_launch = plan.profile_kind(2, kind_of["contract_tropical_dense"], reps=5)
@@ -348,7 +364,7 @@ def bench_tropical_gemm(args, T, W, np, sync):
                config=dict(workload="three-factor network, 4 x 729 x 729 x 729 dense max-plus product + readout",
                            seed=0, n_vars=int(net.n_vars), tree_sc_log2=round(info["sc"], 3),
                            tree_tc_log2=round(info["tc"], 3), graph=not args.no_graph),
-               log_p=float(lp[0]), roofline=roof, kernels=kernels)
+               log_p=float(lp[0]), roofline=roof, kernels=kernels, step_ms=steps)
     if not args.no_cpu_baseline:
         import oracle
         pairs, _ = plan.tree()
@@ -380,7 +396,8 @@ def bench_map(args, T, W, np, sync, which):
     out = dict(value=round(1.0 / sec, 3), unit="MAP solves/s", ms_per_step=round(sec * 1e3, 4), dtype="f32",
                config=dict(workload=wl, seed=0, n_vars=int(net.n_vars), tree_sc_log2=round(info["sc"], 3),
                            tree_tc_log2=round(info["tc"], 3), graph=not args.no_graph),
-               tflops=round(flops / sec / 1e12, 4), log_p=float(lp[0]), roofline=roof, kernels=kernels)
+               tflops=round(flops / sec / 1e12, 4), log_p=float(lp[0]), roofline=roof, kernels=kernels,
+               step_ms=step_stats(lambda: plan.map(evb), np))
     if not args.no_cpu_baseline:
         import oracle
         pairs, _ = plan.tree()
