@@ -96,8 +96,50 @@ def roofline(plan, task, workload, evidence=None, batch=1, kernel=None):
                     frac=round(mfma_frac, 4), traffic=traffic)
     roof.update(kernel=dom_name, launches_per_solve=n_launch, avg_launch_us=round(avg_ms * 1e3, 3),
                 bytes_per_launch=round(by_launch), flops_per_launch=round(fl_launch))
+    if roof["bound"] == "hbm":
+        roof["copy_ref"] = copy_reference(by_launch)
     kernels = {k: dict(n=v["n"], ms=round(v["ms"], 4)) for k, v in agg.items()}
     return roof, kernels, flops_task
+
+
+def copy_reference(nbytes, reps=50):
+    """What one launch moving the same bytes reaches: a plain device copy of
+    nbytes / 2 bytes (read once, written once), launched back to back like the
+    kernel kinds (one graph of `reps` copies, replayed between two events on
+    the same stream).  "hbm":
+    each launch copies another pair of slices of a 1 GiB pool (source and
+    destination out of the caches); "cached": one pair of buffers every time
+    (both stay in the last-level cache, as a pass's freshly written carriers
+    may)."""
+    import torch
+    n = max(1, int(nbytes // 8))
+    slots = max(2, (1 << 28) // n)  # 1 GiB of floats per pool
+    src = torch.ones(slots * n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    out = {}
+    for name, rot in (("hbm", True), ("cached", False)):
+        views = [((r % slots) * n if rot else 0) for r in range(reps)]
+        pairs = [(dst[k:k + n], src[k:k + n]) for k in views]
+        for d, c in pairs[:5]:
+            d.copy_(c)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()  # the copies replay back to back, free of host overhead
+        with torch.cuda.graph(g):
+            for d, c in pairs:
+                d.copy_(c)
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / reps * 1e3
+        del g
+        out[name] = dict(us=round(us, 3), frac=round(8 * n / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4))
+    del src, dst
+    out["what"] = "plain device copy of the launch's byte count (half read, half written), one launch each"
+    return out
 
 
 def timed(fn, steps, warmup, sync):
