@@ -308,8 +308,11 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
     return op;
   }
   // very few outputs, each a long sum: workgroups reduce chunks of the
-  // summed index cooperatively (more outputs go to the wave form below)
-  if (n_out * (uint64_t)op.nb <= 64 && a.nS >= 256) {
+  // summed index cooperatively (more outputs, or sums of fewer than 8192
+  // entries, go to the wave form below: one wavefront per output takes at
+  // most 128 entries per lane there, cheaper than the split form's two
+  // launches of their own)
+  if (n_out * (uint64_t)op.nb <= 64 && a.nS >= 8192) {
     op.split = true;
     // about 1024 workgroups in total, each reducing at least 1K summed entries
     uint32_t want = std::max<uint32_t>(1, 1024u / (uint32_t)op.nb);
