@@ -344,10 +344,13 @@ static Op make_op(tn_plan_t *p, int semi, int X, int Y, int Z, int I) {
     if (Y >= 0) {
       const Labels Bl = inter(R, LY), Ml = minus(R, LY);
       const int64_t nB = numel(Bl, card), nM = numel(Ml, card);
-      // eligible for any summed set (sum-product) or >= 8 entries (max-plus);
-      // the rules below take it for >= 8 entries or none (sum-product), the
-      // autotuner may take it for 2..7 as well
-      const bool s_ok = semi == SEMI_SUM ? true : a.nS >= 8;
+      // eligible for any summed set (sum-product), or for max-plus (the
+      // tiles then run on the vector ALUs) from 8 entries and 2^17
+      // candidates over all instances: smaller max-plus products go to the
+      // forms of the grouped stage launch instead of a dense launch of their
+      // own (on the 300-variable network's tree 8 of its 17 dense launches
+      // shared a stage with a grouped one)
+      const bool s_ok = semi == SEMI_SUM ? true : a.nS >= 8 && (uint64_t)op.nb * n_out * a.nS >= (1u << 17);
       const bool dense_ok =
           nM >= 16 && a.nC >= 8 && s_ok &&
           nB * ((nM + kGemmTile - 1) / kGemmTile) * (((int64_t)a.nC + kGemmTile - 1) / kGemmTile) < (1LL << 31);
