@@ -530,7 +530,7 @@ def test_map_bn300_bit_exact(T):
     assert abs(oracle.log_joint(bn, x2[0]) - lp2[0]) <= 1e-3 * max(1.0, abs(v64))
 
 
-@pytest.mark.parametrize("seed", [0, 4])
+@pytest.mark.parametrize("seed", [2, 4])
 def test_map_dense_tropical_bit_exact(T, seed):
     """Trees with dense max-plus nodes (64 x 64 tiles on the vector ALUs):
     value and assignment bit for bit against the oracle's FP32 emulation on
