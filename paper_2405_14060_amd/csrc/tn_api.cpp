@@ -491,8 +491,10 @@ static void build_leaves(tn_plan_t *p, const tn_net *net) {
 }
 
 // gather map of factor f restricted to its unobserved variables (sorted),
-// and (var, stride) pairs of its observed variables, strides in load order
-static void factor_gather(tn_plan_t *p, const tn_net *net, int f, const std::vector<char> &fixed,
+// and (var, stride) pairs of its observed variables, strides in load order;
+// true when the map is the identity (the unobserved variables trail the
+// scope in sorted order), so that the leaf is a contiguous copy
+static bool factor_gather(tn_plan_t *p, const tn_net *net, int f, const std::vector<char> &fixed,
                           int32_t &gmap_off, int32_t &obs_b, int32_t &obs_e) {
   const auto &sc = net->scope[f];
   std::vector<int64_t> st(sc.size());
@@ -531,6 +533,9 @@ static void factor_gather(tn_plan_t *p, const tn_net *net, int f, const std::vec
       p->obs.push_back((int32_t)st[i]);
     }
   obs_e = (int32_t)(p->obs.size() / 2);
+  for (int64_t i = 0; i < n; ++i)
+    if (p->gmap[gmap_off + i] != i) return false;
+  return true;
 }
 
 // Forward ops of a tree whose leaf tensors exist: creates node tensors.
@@ -2404,7 +2409,7 @@ static void make_plan(tn_plan_t *p, const tn_net *net, const tn_plan_opts *o) {
     d.size = (int32_t)numel(p->leaf_lab[i], p->card);
     if (d.kind == 0) {
       const int f = p->leaf_factor[i];
-      factor_gather(p, net, f, fixed, d.gmap, d.obs_begin, d.obs_end);
+      d.ident = factor_gather(p, net, f, fixed, d.gmap, d.obs_begin, d.obs_end) ? 1 : 0;
       d.src = net->val_off[f];
     }
     // batched: indicator vectors, and under batched sliced evidence every
@@ -3353,7 +3358,7 @@ static void build_mmap(tn_plan_t *p, const tn_net *net) {
       d.kind = 0;
       d.var = -1;
       d.size = (int32_t)numel(l, p->card);
-      factor_gather(p, net, fs[i], fixed, d.gmap, d.obs_begin, d.obs_end);
+      d.ident = factor_gather(p, net, fs[i], fixed, d.gmap, d.obs_begin, d.obs_end) ? 1 : 0;
       d.src = net->val_off[fs[i]];
       d.dst = tid;
       d.slot = tid;
@@ -3396,7 +3401,7 @@ static void build_mmap(tn_plan_t *p, const tn_net *net) {
     LeafDesc d{};
     d.kind = 0;
     d.size = (int32_t)numel(l, p->card);
-    factor_gather(p, net, f, p->is_obs, d.gmap, d.obs_begin, d.obs_end);
+    d.ident = factor_gather(p, net, f, p->is_obs, d.gmap, d.obs_begin, d.obs_end) ? 1 : 0;
     d.src = net->val_off[f];
     d.dst = tid;
     d.slot = -1;

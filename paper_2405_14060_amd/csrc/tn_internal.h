@@ -358,6 +358,7 @@ struct LeafDesc {
   int32_t maxdom;    // 1: log domain (zero = -inf, one = 0)
   int32_t nsub;      // workgroups preparing the leaf (> 1: a large leaf, each
                      // workgroup's maximum in its own sub-slot)
+  int32_t ident;     // 1: the gather map is the identity (element i at src + base + i)
 };
 
 static constexpr int kPrepBig = 16;  // leaves per launch prepared by several workgroups

@@ -3164,6 +3164,8 @@ void launch_dseg_bwd(const DSegArgs &a, const DSegArgs *b, void *stream) {
 // leaf preparation: evidence slicing (gather), indicator vectors, maxima;
 // extra blocks clear the maxima of the tensors produced in this solve
 // --------------------------------------------------------------------------
+static constexpr int kPrepBatch = 8;  // loads in flight per thread in a leaf's gather
+
 __global__ __launch_bounds__(kBlock) void k_prepare(PrepareArgs a) {
   const int b = blockIdx.y;
   const int n_lb = a.n_leaves + a.big_blk0[a.n_big];  // workgroups of leaves
@@ -3199,10 +3201,18 @@ __global__ __launch_bounds__(kBlock) void k_prepare(PrepareArgs a) {
         base += (int64_t)a.evidence[(int64_t)bi * a.n_vars + a.obs[2 * o]] * a.obs[2 * o + 1];
       const float *src = a.arena + d.src + base;
       m = 0.f;
-      for (int i = 0; i < d.size; ++i) {
-        const float v = src[a.gmap[d.gmap + i]];
-        dst[i * es] = v;
-        m = fmaxf(m, fabsf(v));
+      if (d.ident) {
+        for (int i = 0; i < d.size; ++i) {
+          const float v = src[i];
+          dst[i * es] = v;
+          m = fmaxf(m, fabsf(v));
+        }
+      } else {
+        for (int i = 0; i < d.size; ++i) {
+          const float v = src[a.gmap[d.gmap + i]];
+          dst[i * es] = v;
+          m = fmaxf(m, fabsf(v));
+        }
       }
     } else if (d.kind == 1) {
       const float one = d.maxdom ? 0.f : 1.f;
@@ -3229,9 +3239,27 @@ __global__ __launch_bounds__(kBlock) void k_prepare(PrepareArgs a) {
     int64_t base = 0;
     for (int o = d.obs_begin; o < d.obs_end; ++o)
       base += (int64_t)a.evidence[(int64_t)row * a.n_vars + a.obs[2 * o]] * a.obs[2 * o + 1];
-    const float *src = a.arena + d.src + base;
-    for (int i = i0; i < d.size; i += istep) {
-      const float v = src[a.gmap[d.gmap + i]];
+    const float *__restrict__ src = a.arena + d.src + base;
+    const int32_t *__restrict__ gm = a.gmap + d.gmap;
+    // a large leaf has at most kMaxSubSlots workgroups (one maximum each), so
+    // every thread keeps kPrepBatch loads in flight: the map entries first
+    // (none for an identity map), then the values, then the stores
+    int i = i0;
+    for (; i + (kPrepBatch - 1) * istep < d.size; i += kPrepBatch * istep) {
+      int32_t o[kPrepBatch];
+#pragma unroll
+      for (int k = 0; k < kPrepBatch; ++k) o[k] = d.ident ? i + k * istep : gm[i + k * istep];
+      float v[kPrepBatch];
+#pragma unroll
+      for (int k = 0; k < kPrepBatch; ++k) v[k] = src[o[k]];
+#pragma unroll
+      for (int k = 0; k < kPrepBatch; ++k) {
+        dst[i + k * istep] = v[k];
+        lmax = fmaxf(lmax, fabsf(v[k]));
+      }
+    }
+    for (; i < d.size; i += istep) {
+      const float v = src[d.ident ? i : gm[i]];
       dst[i] = v;
       lmax = fmaxf(lmax, fabsf(v));
     }
